@@ -1,0 +1,239 @@
+"""ctypes wrapper of the FP64 CPU oracle (kgdb_oracle.c).
+
+TEST INFRASTRUCTURE ONLY: imported by the test suite, the smoke check and the
+benchmark's CPU-baseline leg.  The GPU product path never imports this module.
+"""
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "kgdb_oracle.c")
+_LIB = os.path.join(_HERE, "libkgdb_oracle.so")
+
+STREAM_WALK, STREAM_VEL, STREAM_LANGEVIN, STREAM_DB, STREAM_WARMUP = 1, 2, 3, 4, 5
+TF_PHANTOM, TF_NOFORCE = 1, 2
+
+
+def build(force=False):
+    """Compile the oracle with gcc (plain -O2, no fast-math, no FMA contraction)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        cmd = ["gcc", "-O2", "-std=gnu11", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
+               "-shared", "-o", _LIB + ".tmp", _SRC, "-lm"]
+        subprocess.check_call(cmd)
+        os.replace(_LIB + ".tmp", _LIB)
+    return _LIB
+
+
+class Params(C.Structure):
+    _fields_ = [
+        ("M", C.c_int32), ("N", C.c_int32),
+        ("rho", C.c_double), ("kappa", C.c_double), ("n_exp", C.c_double),
+        ("k_fene", C.c_double), ("R0", C.c_double), ("T", C.c_double),
+        ("gamma", C.c_double), ("dt", C.c_double), ("db_rmax", C.c_double),
+        ("db_rate", C.c_double),
+        ("proposal", C.c_int32), ("precision", C.c_int32),
+        ("warmup_steps", C.c_int32),
+        ("warmup_dt0", C.c_double), ("warmup_max_disp", C.c_double),
+        ("warmup_fcap", C.c_double), ("fene_floor", C.c_double),
+        ("seed", C.c_uint64), ("melt_id", C.c_int32), ("test_flags", C.c_uint32),
+        ("r_cell", C.c_double),
+    ]
+
+
+class Stats(C.Structure):
+    _fields_ = [
+        ("attempts", C.c_int64), ("no_candidate", C.c_int64), ("accepted", C.c_int64),
+        ("reverse_impossible", C.c_int64), ("sum_ncand", C.c_int64),
+        ("sum_dE_accepted", C.c_double), ("ncand_end", C.c_int64),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+DEFAULTS = dict(M=20, N=50, rho=0.85, kappa=1.5, n_exp=2.0, k_fene=0.0, R0=1.5, T=1.0,
+                gamma=1.0, dt=0.01, db_rmax=1.3, db_rate=1e-3, proposal=0, precision=0,
+                warmup_steps=1000, warmup_dt0=0.001, warmup_max_disp=0.05, warmup_fcap=10.0,
+                fene_floor=0.02, seed=1,
+                melt_id=0, test_flags=0, r_cell=0.0)
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        L = C.CDLL(_LIB)
+        P = C.c_void_p
+        dp = np.ctypeslib.ndpointer(np.float64, flags="C")
+        ip = np.ctypeslib.ndpointer(np.int32, flags="C")
+        up = np.ctypeslib.ndpointer(np.uint64, flags="C")
+        L.kgdbref_last_error.restype = C.c_char_p
+        L.kgdbref_philox.argtypes = [up, up, up]
+        L.kgdbref_normals.argtypes = [C.c_uint64] * 5 + [dp]
+        for f in ("kgdbref_mie",):
+            getattr(L, f).restype = C.c_double
+            getattr(L, f).argtypes = [C.c_double] * 3
+        for f in ("kgdbref_mlj", "kgdbref_pair_u", "kgdbref_pair_f"):
+            getattr(L, f).restype = C.c_double
+            getattr(L, f).argtypes = [C.c_double] * 2
+        L.kgdbref_kn.restype = C.c_double
+        L.kgdbref_kn.argtypes = [C.c_double] * 3
+        for f in ("kgdbref_fene_u", "kgdbref_fene_f"):
+            getattr(L, f).restype = C.c_double
+            getattr(L, f).argtypes = [C.c_double] * 4
+        L.kgdbref_create.restype = P
+        L.kgdbref_create.argtypes = [C.POINTER(Params)]
+        L.kgdbref_create_empty.restype = P
+        L.kgdbref_create_empty.argtypes = [C.POINTER(Params)]
+        L.kgdbref_destroy.argtypes = [P]
+        L.kgdbref_box.restype = C.c_double
+        L.kgdbref_box.argtypes = [P]
+        L.kgdbref_kfene.restype = C.c_double
+        L.kgdbref_kfene.argtypes = [P]
+        L.kgdbref_get_state.argtypes = [P, P, P, P, P, P, P]
+        L.kgdbref_set_state.argtypes = [P, P, P, P, P, P]
+        L.kgdbref_forces.argtypes = [P, C.c_int32, P, P, P]
+        L.kgdbref_md_steps.argtypes = [P, C.c_int64]
+        L.kgdbref_cell_list.argtypes = [P, C.c_double, C.POINTER(C.c_int32), P, P, C.c_int64]
+        L.kgdbref_candidates.argtypes = [P, C.c_int32, P, C.c_int64, C.POINTER(C.c_int64)]
+        L.kgdbref_db_sweep.argtypes = [P, C.c_int64, C.c_int32, C.POINTER(Stats)]
+        L.kgdbref_move_dE.restype = C.c_double
+        L.kgdbref_move_dE.argtypes = [P] + [C.c_int32] * 5
+        L.kgdbref_apply_move.argtypes = [P] + [C.c_int32] * 5
+        L.kgdbref_observables.argtypes = [P, P, P, P]
+        L.kgdbref_energy.argtypes = [P, P]
+        L.kgdbref_fit_ellK.argtypes = [dp, C.c_int32, C.c_double, C.POINTER(C.c_double)]
+        _lib = L
+    return _lib
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def _check(rc):
+    if rc != 0:
+        raise RuntimeError(f"oracle error {rc}: {lib().kgdbref_last_error().decode()}")
+
+
+def philox(ctr, key):
+    out = np.zeros(4, np.uint64)
+    lib().kgdbref_philox(np.asarray(ctr, np.uint64), np.asarray(key, np.uint64), out)
+    return out
+
+
+def normals(seed, melt, i_lo, i_hi, stream):
+    z = np.zeros(4)
+    lib().kgdbref_normals(seed, melt, i_lo, i_hi, stream, z)
+    return z
+
+
+def mie(n, m, r): return lib().kgdbref_mie(n, m, r)
+def mlj(n, r): return lib().kgdbref_mlj(n, r)
+def pair_u(n, r): return lib().kgdbref_pair_u(n, r)
+def pair_f(n, r): return lib().kgdbref_pair_f(n, r)
+def kn(n, l0=0.960897, R0=1.5): return lib().kgdbref_kn(n, l0, R0)
+def fene_u(k, R0, r, amin=0.0): return lib().kgdbref_fene_u(k, R0, r, amin)
+def fene_f(k, R0, r, amin=0.0): return lib().kgdbref_fene_f(k, R0, r, amin)
+
+
+def fit_ellK(r2n, N, l0):
+    out = C.c_double()
+    _check(lib().kgdbref_fit_ellK(np.ascontiguousarray(r2n, np.float64), N, l0, C.byref(out)))
+    return out.value
+
+
+def make_params(**kw):
+    d = dict(DEFAULTS)
+    d.update(kw)
+    return Params(**d)
+
+
+class Melt:
+    """One melt held by the oracle."""
+
+    def __init__(self, empty=False, **kw):
+        self.p = make_params(**kw)
+        L = lib()
+        h = (L.kgdbref_create_empty if empty else L.kgdbref_create)(C.byref(self.p))
+        if not h:
+            raise RuntimeError("oracle init failed: " + L.kgdbref_last_error().decode())
+        self.h = h
+        self.M, self.N = self.p.M, self.p.N
+        self.Nm = self.M * self.N
+        self.L = L.kgdbref_box(h)
+        self.kfene = L.kgdbref_kfene(h)
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            lib().kgdbref_destroy(self.h)
+            self.h = None
+
+    def get_state(self):
+        x = np.zeros((3, self.Nm)); v = np.zeros((3, self.Nm))
+        fc = np.zeros((3, self.Nm)); fl = np.zeros((3, self.Nm))
+        ch = np.zeros(self.Nm, np.int32); cnt = np.zeros(4, np.uint64)
+        _check(lib().kgdbref_get_state(self.h, _ptr(x), _ptr(v), _ptr(fc), _ptr(fl), _ptr(ch), _ptr(cnt)))
+        return dict(x=x, v=v, fc=fc, fl=fl, chains=ch.reshape(self.M, self.N), counters=cnt)
+
+    def set_state(self, x=None, v=None, fl=None, chains=None, counters=None):
+        cv = lambda a, t: None if a is None else np.ascontiguousarray(a, t)
+        x, v, fl = cv(x, np.float64), cv(v, np.float64), cv(fl, np.float64)
+        ch, cnt = cv(chains, np.int32), cv(counters, np.uint64)
+        _check(lib().kgdbref_set_state(self.h, _ptr(x), _ptr(v), _ptr(fl), _ptr(ch), _ptr(cnt)))
+
+    def forces(self, brute=False):
+        F = np.zeros((3, self.Nm)); S = np.zeros(self.Nm); E = np.zeros(3)
+        _check(lib().kgdbref_forces(self.h, int(brute), _ptr(F), _ptr(S), _ptr(E)))
+        return F, S, E
+
+    def md_steps(self, n):
+        _check(lib().kgdbref_md_steps(self.h, n))
+
+    def cell_list(self, rcell=0.0):
+        nc = C.c_int32()
+        _check(lib().kgdbref_cell_list(self.h, rcell, C.byref(nc), None, None, 0))
+        start = np.zeros(nc.value ** 3 + 1, np.int32); srt = np.zeros(self.Nm, np.int32)
+        _check(lib().kgdbref_cell_list(self.h, rcell, C.byref(nc), _ptr(start), _ptr(srt), start.size))
+        return nc.value, start, srt
+
+    def candidates(self, brute=False, cap=1 << 20):
+        keys = np.zeros(cap, np.uint64); n = C.c_int64()
+        _check(lib().kgdbref_candidates(self.h, int(brute), _ptr(keys), cap, C.byref(n)))
+        return keys[: n.value].copy()
+
+    def db_sweep(self, K, brute=False):
+        st = Stats()
+        _check(lib().kgdbref_db_sweep(self.h, K, int(brute), C.byref(st)))
+        return st.as_dict()
+
+    def move_dE(self, A, i, B, j, var):
+        return lib().kgdbref_move_dE(self.h, A, i, B, j, var)
+
+    def apply_move(self, A, i, B, j, var):
+        _check(lib().kgdbref_apply_move(self.h, A, i, B, j, var))
+
+    def observables(self):
+        r2n = np.zeros(self.N - 1); lk = C.c_double(); mb = C.c_double()
+        _check(lib().kgdbref_observables(self.h, _ptr(r2n), C.byref(lk), C.byref(mb)))
+        return r2n, lk.value, mb.value
+
+    def energy(self):
+        e = np.zeros(4)
+        _check(lib().kgdbref_energy(self.h, _ptr(e)))
+        return e
+
+
+def key_decode(key, M, N):
+    """(A, i, B, j, variant) of a candidate key; i, j are 1-based bond indices."""
+    key = int(key)
+    Nb = N - 1
+    var = key & 1
+    q = key >> 1
+    hi, lo = divmod(q, M * Nb)
+    return hi // Nb, hi % Nb + 1, lo // Nb, lo % Nb + 1, var
