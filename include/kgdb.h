@@ -1,0 +1,162 @@
+/*
+ * kgdb — MI355X (gfx950) library for the hot path of Dietz & Hoy, "Facile equilibration of
+ * well-entangled semiflexible bead-spring polymer melts" (arXiv 2109.11001): Langevin
+ * molecular dynamics of semiflexible Kremer-Grest melts under the core-softened MLJ^n pair
+ * potential (Sec. II.A, Eqs. 5-6) with the FENE constant k_n of Eq. 9 and the angle term of
+ * Eq. 4, interleaved with double-bridging Monte Carlo moves (Fig. 1; Sec. II.B).
+ *
+ * Plain C ABI: host pointers and sizes only.  Every call returns 0 or a negative kgdb_err;
+ * kgdb_last_error() gives the message of the last failure on the calling thread.
+ * A handle holds a BATCH of independent melts advanced together (a single melt is a batch
+ * of one).  The library owns all device memory of a handle; host arrays passed in are
+ * caller-owned and copied.  Calls on one handle are not thread-safe.
+ * Units: eps = sigma = m = k_B = 1, time in tau_LJ (Sec. II.B).
+ */
+#ifndef KGDB_H
+#define KGDB_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum kgdb_err {
+  KGDB_OK = 0,
+  KGDB_E_PARAM = -1,     /* invalid parameters (n = 6 is singular in Eq. 5, M < 1, ...) */
+  KGDB_E_ALLOC = -2,     /* device or host allocation failed */
+  KGDB_E_HIP = -3,       /* a HIP runtime call failed */
+  KGDB_E_FENE = -4,      /* a bond left the FENE domain: r >= R0 (strict) or r >= 2 R0 (floored) */
+  KGDB_E_NONFINITE = -5, /* non-finite force, position or velocity */
+  KGDB_E_OVERFLOW = -6,  /* a fixed capacity (cell bucket, neighbour list, candidate list) was exceeded */
+  KGDB_E_STATE = -7      /* inconsistent state passed in (e.g. chain table not a permutation) */
+};
+
+/* proposal modes of the double-bridging attempt */
+#define KGDB_PROPOSAL_UNIFORM 0 /* uniform over the candidate set, exact Metropolis-Hastings */
+#define KGDB_PROPOSAL_LEARNED 1 /* reserved: learned proposal (rejected with KGDB_E_PARAM)   */
+#define KGDB_PROPOSAL_LITERAL 2 /* acceptance exp(-dE/T) only, as printed in Fig. 1         */
+
+/* force precision */
+#define KGDB_PREC_FP64 0  /* plain path: forces in FP64 */
+#define KGDB_PREC_MIXED 1 /* FP32 pair/bond/angle forces from cell-relative coordinates, FP64 state */
+
+/* test flags */
+#define KGDB_TF_PHANTOM 1u /* nonbonded pairs off; bonded pairs keep MLJ^n */
+#define KGDB_TF_NOFORCE 2u /* conservative forces off (free Langevin particles) */
+
+/* One melt: M chains of N beads in a cubic periodic box of side (M N / rho)^(1/3).
+   Field order is part of the ABI. */
+typedef struct {
+  int32_t M, N;           /* chains, beads per chain (M >= 1, N >= 2)                          */
+  double rho;             /* monomer density [sigma^-3]                                        */
+  double kappa;           /* angle stiffness of Eq. 4 [eps]                                    */
+  double n_exp;           /* repulsive exponent n of Eq. 6 (n > 0, n != 6)                     */
+  double k_fene;          /* <= 0: k_n from Eq. 9 with l0 = 0.960897; > 0: this value           */
+  double R0;              /* FENE range (1.5)                                                  */
+  double T, gamma, dt;    /* temperature, Langevin friction [1/tau], timestep [tau]            */
+  double db_rmax;         /* longest new bond a double-bridging move may create (1.3 sigma)    */
+  double db_rate;         /* attempts per monomer per tau (1e-3), used when a sweep size is < 0 */
+  int32_t proposal;       /* KGDB_PROPOSAL_*                                                   */
+  int32_t precision;      /* KGDB_PREC_*; must be equal for all melts of a batch              */
+  int32_t warmup_steps;   /* warm-up steps run by init (0 = none)                              */
+  double warmup_dt0;      /* first warm-up timestep; ramped geometrically to dt                */
+  double warmup_max_disp; /* per-step displacement cap during warm-up [sigma]                  */
+  double warmup_fcap;     /* pair-force cap at the first warm-up step, ramped to 100x          */
+  double fene_floor;      /* a_min of the floored FENE log (0 = strict singular form)          */
+  uint64_t seed;          /* Philox key word 0                                                 */
+  int32_t melt_id;        /* Philox key word 1                                                 */
+  uint32_t test_flags;    /* KGDB_TF_*                                                         */
+  double r_cell;          /* MD cell edge (<= 0: r_c = 2^(1/6)); must be >= r_c                */
+} kgdb_params;
+
+/* statistics of one melt's double-bridging sweep */
+typedef struct {
+  int64_t attempts;           /* attempts made                                          */
+  int64_t no_candidate;       /* attempts that found an empty candidate set            */
+  int64_t accepted;           /* accepted moves                                        */
+  int64_t reverse_impossible; /* proposals rejected because the reverse move is invalid */
+  int64_t sum_ncand;          /* sum over attempts with candidates of |C(x)|           */
+  double sum_dE_accepted;     /* sum of Delta E over accepted moves                    */
+  int64_t ncand_end;          /* |C| after the sweep                                   */
+} kgdb_db_stats;
+
+typedef struct kgdb_batch kgdb_batch;
+
+/* Create a batch of `count` melts from params[0..count-1] on `hip_stream` (a hipStream_t;
+   NULL = the library creates its own).  Each melt is initialised as seeded freely jointed
+   random walks with bond 0.97, Maxwell-Boltzmann velocities with the mean removed, and the
+   warm-up of Sec. II.B (small initial timestep, ramped).  Returns KGDB_E_PARAM for invalid
+   parameters, KGDB_E_FENE/NONFINITE if the warm-up fails.  *out is owned by the caller and
+   released by kgdb_destroy. */
+int kgdb_init_batch(const kgdb_params* params, int32_t count, void* hip_stream, kgdb_batch** out);
+/* kgdb_init_batch with count = 1 */
+int kgdb_init_melt(const kgdb_params* params, void* hip_stream, kgdb_batch** out);
+void kgdb_destroy(kgdb_batch* b);
+const char* kgdb_last_error(void);
+int32_t kgdb_batch_size(const kgdb_batch* b);
+
+/* Advance every melt by nsteps velocity-Verlet Langevin steps (Sec. II.B's MD).  Runs on the
+   batch's stream; device error flags are read once at the end (KGDB_E_FENE, _NONFINITE,
+   _OVERFLOW).  use_graph != 0 replays captured 100-step hipGraph chunks. */
+int kgdb_md_steps(kgdb_batch* b, int64_t nsteps, int32_t use_graph);
+
+/* One double-bridging sweep per melt (Fig. 1, Sec. II.B): n_attempts sequential attempts
+   (< 0: round(db_rate * N_mono * time since the last sweep)).  Positions and velocities are
+   untouched; the chain tables change.  stats[k] receives melt k's statistics (may be NULL). */
+int kgdb_db_sweep(kgdb_batch* b, int64_t n_attempts, kgdb_db_stats* stats);
+
+/* R^2(n)/n for n = 1..N-1 (r2_over_n has N-1 entries) of melt `melt`, its mean bond length,
+   and l_K from the least-squares fit of Eq. 14 over ceil(N/4) <= n <= floor(N/2) with l0 the
+   mean bond length.  Any output pointer may be NULL. */
+int kgdb_observables(kgdb_batch* b, int32_t melt, double* r2_over_n, double* ell_K, double* mean_bond);
+
+/* FP64 energies of melt `melt`: out = {U_pair (truncated MLJ^n over all pairs),
+   U_bond (FENE log part, Eqs. 3/10), U_ang (Eq. 4), kinetic} */
+int kgdb_energy(kgdb_batch* b, int32_t melt, double out[4]);
+
+/* State of melt `melt`.  x, v, fc, fl: component-major [3][M*N] doubles; chains: [M][N]
+   monomer ids; counters = {step, sweep, last_sweep_step, fc_valid}.  NULL skips a field.
+   set_state wraps x into the box, checks that chains is a permutation (KGDB_E_STATE), and
+   marks the conservative forces stale. */
+int kgdb_get_state(kgdb_batch* b, int32_t melt, double* x, double* v, double* fc, double* fl,
+                   int32_t* chains, uint64_t* counters);
+int kgdb_set_state(kgdb_batch* b, int32_t melt, const double* x, const double* v, const double* fl,
+                   const int32_t* chains, const uint64_t* counters);
+
+/* ---- test hooks (each synchronises the stream) ------------------------------------------ */
+/* Conservative forces at the current positions of melt `melt` in the batch's precision:
+   F [3][Nm], S [Nm] = sum of the magnitudes of the individual contributions on each bead,
+   E3 = {U_pair, U_bond, U_ang}.  NULL skips. */
+int kgdb_forces(kgdb_batch* b, int32_t melt, double* F, double* S, double* E3);
+/* Cell list of the current positions: nc per side, cell_start [nc^3+1], sorted ids [Nm]
+   (counting sort by cell, stable by monomer id).  start_cap = capacity of cell_start. */
+int kgdb_cell_list(kgdb_batch* b, int32_t melt, int32_t* nc, int32_t* cell_start,
+                   int32_t* sorted_ids, int64_t start_cap);
+/* Sorted double-bridging candidate keys of the current topology.  Key of (A, i, B, j, v),
+   A < B chain indices, i, j 1-based bond indices, v = 0 (i = j) or 1 (i + j = N):
+   ((A (N-1) + i - 1) M (N-1) + B (N-1) + j - 1) * 2 + v.  *n receives |C|. */
+int kgdb_candidates(kgdb_batch* b, int32_t melt, uint64_t* keys, int64_t cap, int64_t* n);
+/* For each key: Delta E of the move and |C(x')| after it, without committing. */
+int kgdb_db_probe(kgdb_batch* b, int32_t melt, const uint64_t* keys, int64_t nkeys, double* dE,
+                  int64_t* ncand_after);
+/* Time `reps` launches of the fused force/integrator kernel on the batch's stream with HIP
+   events (the state is advanced by reps steps); *avg_ms receives the mean duration. */
+int kgdb_time_force_kernel(kgdb_batch* b, int32_t reps, double* avg_ms);
+/* kgdb_db_sweep plus an on-device check, per attempt, that the incremental count of the
+   candidates touching the two chains equals a full recount (mismatch: KGDB_E_STATE). */
+int kgdb_db_sweep_checked(kgdb_batch* b, int64_t n_attempts, kgdb_db_stats* stats);
+/* Per-launch HIP-event timing of the fused force kernel and of the cell finalisation inside
+   kgdb_md_steps while enabled (graphs are not used meanwhile).  profile_read returns the
+   summed milliseconds and launch counts since the last read and resets them. */
+int kgdb_profile(kgdb_batch* b, int32_t enable);
+int kgdb_profile_read(kgdb_batch* b, double* force_ms, int64_t* force_n, double* fin_ms, int64_t* fin_n);
+/* geometry of melt `melt`: out = {L, MD cells per side, double-bridging cells per side,
+   FENE constant in use (k_n of Eq. 9 or the literal value)} */
+int kgdb_melt_geometry(const kgdb_batch* b, int32_t melt, double out[4]);
+/* total number of monomers and cells of the batch (for byte accounting) */
+int kgdb_batch_sizes(const kgdb_batch* b, int64_t* monomers, int64_t* cells);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* KGDB_H */

@@ -515,13 +515,14 @@ static void mb_velocities(melt_t *m) {
 
 static int warmup(melt_t *m) {
   int W = m->p.warmup_steps;
+  m->fc_valid = 0;
   for (int w = 0; w < W; w++) {
     /* geometric ramps: dt from warmup_dt0 to dt, pair-force cap from warmup_fcap to
-       100 x warmup_fcap (the cap changes F_c, so it is recomputed every step) */
+       100 x warmup_fcap; a step's opening kick reuses the force of the previous step's
+       closing kick (computed with that step's cap) */
     double t = (W == 1) ? 1.0 : (double)w / (double)(W - 1);
     double dtw = m->p.warmup_dt0 * pow(m->p.dt / m->p.warmup_dt0, t);
     m->fcap = m->p.warmup_fcap * pow(100.0, t);
-    m->fc_valid = 0;
     int rc = vv_step(m, dtw, m->p.warmup_max_disp, (uint64_t)w + 1, ST_WARMUP);
     if (rc) { m->fcap = 0; return rc; }
   }

@@ -1,0 +1,514 @@
+// Double-bridging Monte Carlo on gfx950 (Fig. 1 and Sec. II.B).
+//
+// A move exchanges bond i of chain A with bond j of chain B (A < B) so that both chains keep
+// N beads: P (i = j) reconnects (a_i, b_{i+1}) and (b_i, a_{i+1}); AP (i + j = N) reconnects
+// (a_i, b_j) and (a_{i+1}, b_{j+1}).  Both new bonds must be <= db_rmax.  The proposal is
+// uniform over the candidate set C(x) and is corrected by the Metropolis-Hastings factor
+// |C(x)| / |C(x')| (zero when the reverse move is not a candidate of x'); the paper-literal
+// mode keeps only exp(-dE/T).  Delta E is the change of the FENE log and angle terms at the
+// two junctions (the pair terms of Eq. 6 are unchanged by a move).
+//
+// Positions do not change during a sweep, so the set of monomer pairs within db_rmax is built
+// once per sweep; attempts then only look up topology.  One workgroup per melt runs the
+// sweep's attempts in order, holding the sorted candidate list in LDS.
+//
+// Built with -ffp-contract=off: distances that decide candidate membership are computed with
+// the same operation sequence as their definition.
+#include "kgdb_dev.h"
+#include "kgdb_kernels.h"
+#include "kgdb.h"
+
+namespace kgdb {
+
+constexpr int DB_BLOCK = 1024;
+constexpr int DB_MAXPT = 8;  // chain-table entries per thread in a commit: 2N <= 8192
+
+__device__ __forceinline__ double dist2(const double* __restrict__ x, int NP, double L, int u, int w) {
+  const double dx = min_image(x[w] - x[u], L);
+  const double dy = min_image(x[NP + w] - x[NP + u], L);
+  const double dz = min_image(x[2 * NP + w] - x[2 * NP + u], L);
+  return dx * dx + dy * dy + dz * dz;
+}
+
+// ---------------------------------------------------------------------------------------
+// grid of cells >= db_rmax, then the close-pair list of every monomer
+// ---------------------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_db_bin(const MeltDesc* __restrict__ md, const int* __restrict__ blk_melt,
+                                                const int* __restrict__ blk_base, int NP,
+                                                const double* __restrict__ x, int* __restrict__ cnt13,
+                                                int* __restrict__ bucket13, uint32_t* __restrict__ err) {
+  const int lb = xcd_remap(blockIdx.x, gridDim.x);
+  const int k = __builtin_amdgcn_readfirstlane(blk_melt[lb]);
+  const MeltDesc& d = md[k];
+  const int li = blk_base[lb] + (int)threadIdx.x;
+  if (li >= d.Nm) return;
+  const int g = d.off + li;
+  const int nc = d.nc13;
+  const int cx = cell_coord(x[g], d.cinv13, nc), cy = cell_coord(x[NP + g], d.cinv13, nc),
+            cz = cell_coord(x[2 * NP + g], d.cinv13, nc);
+  const int c = d.cell13_off + (cz * nc + cy) * nc + cx;
+  const int s = atomicAdd(&cnt13[c], 1);
+  if (s < DB_CELL_CAP) bucket13[c * DB_CELL_CAP + s] = g;
+  else atomicOr(&err[k], ERR_NBR_OVERFLOW);
+}
+
+__global__ __launch_bounds__(256) void k_db_nbr(const MeltDesc* __restrict__ md, const int* __restrict__ blk_melt,
+                                                const int* __restrict__ blk_base, int NP,
+                                                const double* __restrict__ x, const int* __restrict__ cnt13,
+                                                const int* __restrict__ bucket13, int* __restrict__ nnb,
+                                                int* __restrict__ nbr, uint32_t* __restrict__ err) {
+  const int lb = xcd_remap(blockIdx.x, gridDim.x);
+  const int k = __builtin_amdgcn_readfirstlane(blk_melt[lb]);
+  const MeltDesc& d = md[k];
+  const int li = blk_base[lb] + (int)threadIdx.x;
+  if (li >= d.Nm) return;
+  const int u = d.off + li;
+  const int nc = d.nc13;
+  const int cx = cell_coord(x[u], d.cinv13, nc), cy = cell_coord(x[NP + u], d.cinv13, nc),
+            cz = cell_coord(x[2 * NP + u], d.cinv13, nc);
+  // distinct neighbouring cells: 3 per side when nc >= 3, else every cell once
+  const int lo = nc >= 3 ? -1 : 0, hi = nc >= 3 ? 1 : nc - 1;
+  int cntu = 0;
+  for (int oz = lo; oz <= hi; ++oz)
+    for (int oy = lo; oy <= hi; ++oy)
+      for (int ox = lo; ox <= hi; ++ox) {
+        const int nx = (cx + ox + nc) % nc, ny = (cy + oy + nc) % nc, nz = (cz + oz + nc) % nc;
+        const int c = d.cell13_off + (nz * nc + ny) * nc + nx;
+        int n = cnt13[c];
+        n = n > DB_CELL_CAP ? DB_CELL_CAP : n;
+        for (int j = 0; j < n; ++j) {
+          const int w = bucket13[c * DB_CELL_CAP + j];
+          if (w == u) continue;
+          if (dist2(x, NP, d.L, u, w) <= d.rmax2) {
+            if (cntu < DB_NBR_CAP) nbr[(size_t)u * DB_NBR_CAP + cntu] = w;
+            ++cntu;
+          }
+        }
+      }
+  if (cntu > DB_NBR_CAP) { atomicOr(&err[k], ERR_NBR_OVERFLOW); cntu = DB_NBR_CAP; }
+  nnb[u] = cntu;
+}
+
+__device__ __forceinline__ uint64_t make_key(int M, int N, int A, int i, int B, int j, int var) {
+  const uint64_t Nb = (uint64_t)(N - 1);
+  return ((((uint64_t)A * Nb + (uint64_t)(i - 1)) * (uint64_t)M * Nb + (uint64_t)B * Nb + (uint64_t)(j - 1)) << 1) |
+         (uint64_t)var;
+}
+
+struct Move { int A, i, B, j, var; };
+
+__device__ __forceinline__ Move decode_key(uint64_t key, int M, int N) {
+  const uint64_t Nb = (uint64_t)(N - 1);
+  Move mv;
+  mv.var = (int)(key & 1ull);
+  const uint64_t q = key >> 1;
+  const uint64_t mn = (uint64_t)M * Nb;
+  const uint64_t hi = q / mn, lo = q - hi * mn;
+  mv.A = (int)(hi / Nb); mv.i = (int)(hi % Nb) + 1;
+  mv.B = (int)(lo / Nb); mv.j = (int)(lo % Nb) + 1;
+  return mv;
+}
+
+// topology view: old tables, optionally seen through a tentative move (var < 0: no move)
+struct Topo {
+  const int* chain;  // global ids at global chain-table index
+  const int* loc;    // local chain index of each global monomer
+  int off, N;
+  Move mv;
+  // monomer at chain X, 1-based position p, in the (tentative) topology
+  __device__ __forceinline__ int at(int X, int p) const {
+    if (mv.var >= 0 && (X == mv.A || X == mv.B)) {
+      if (mv.var == 0) {
+        if (p > mv.i) X = (X == mv.A) ? mv.B : mv.A;
+      } else if (X == mv.A) {
+        if (p > mv.i) { X = mv.B; p = mv.i + mv.j + 1 - p; }
+      } else {
+        if (p <= N - mv.i) { X = mv.A; p = N + 1 - p; }
+      }
+    }
+    return chain[off + X * N + p - 1];
+  }
+  // (chain, 1-based position) of monomer u in the (tentative) topology
+  __device__ __forceinline__ void where(int u, int& C, int& p) const {
+    const int l = loc[u];
+    C = l / N; p = l - C * N + 1;
+    if (mv.var < 0 || (C != mv.A && C != mv.B)) return;
+    if (mv.var == 0) {
+      if (p > mv.i) C = (C == mv.A) ? mv.B : mv.A;
+    } else if (C == mv.A) {
+      if (p > mv.i) { C = mv.B; p = N + 1 - p; }
+    } else {
+      if (p <= mv.j) { C = mv.A; p = mv.i + mv.j + 1 - p; }
+      else C = mv.B;
+    }
+  }
+};
+
+// Candidates whose "first" new bond is the close pair (u, w): (a_i, b_{i+1}) for P and
+// (a_i, b_j) for AP, a on the lower chain.  Calls emit(key) for each.
+template <typename Emit>
+__device__ __forceinline__ void first_bond_candidates(const Topo& T, const double* __restrict__ x, int NP, double L,
+                                                      double rmax2, int M, int u, int Cu, int pu, int w, int Cw,
+                                                      int pw, Emit emit) {
+  const int N = T.N;
+  if (Cu < Cw) {
+    const int i = pu;
+    if (i <= N - 1 && pw == i + 1 && dist2(x, NP, L, T.at(Cw, i), T.at(Cu, i + 1)) <= rmax2)
+      emit(make_key(M, N, Cu, i, Cw, i, 0));
+    if (i <= N - 1 && pw == N - i && dist2(x, NP, L, T.at(Cu, i + 1), T.at(Cw, pw + 1)) <= rmax2)
+      emit(make_key(M, N, Cu, i, Cw, pw, 1));
+  } else {
+    const int i = pw;
+    if (i <= N - 1 && pu == i + 1 && dist2(x, NP, L, T.at(Cu, i), T.at(Cw, i + 1)) <= rmax2)
+      emit(make_key(M, N, Cw, i, Cu, i, 0));
+    if (i <= N - 1 && pu == N - i && dist2(x, NP, L, T.at(Cw, i + 1), T.at(Cu, pu + 1)) <= rmax2)
+      emit(make_key(M, N, Cw, i, Cu, pu, 1));
+  }
+}
+
+// full candidate list: each monomer u on the lower chain of a close pair
+__global__ __launch_bounds__(256) void k_db_cands(const MeltDesc* __restrict__ md, const int* __restrict__ blk_melt,
+                                                  const int* __restrict__ blk_base, DbArgs a) {
+  const int lb = xcd_remap(blockIdx.x, gridDim.x);
+  const int k = __builtin_amdgcn_readfirstlane(blk_melt[lb]);
+  const MeltDesc& d = md[k];
+  const int li = blk_base[lb] + (int)threadIdx.x;
+  if (li >= d.Nm) return;
+  const int u = d.off + li;
+  Topo T{a.chain, a.loc, d.off, d.N, {0, 0, 0, 0, -1}};
+  int Cu, pu;
+  T.where(u, Cu, pu);
+  const int nn = a.nnb[u];
+  for (int q = 0; q < nn; ++q) {
+    const int w = a.nbr[(size_t)u * DB_NBR_CAP + q];
+    int Cw, pw;
+    T.where(w, Cw, pw);
+    if (Cu >= Cw) continue;
+    first_bond_candidates(T, a.x, a.NP, d.L, d.rmax2, d.M, u, Cu, pu, w, Cw, pw, [&](uint64_t key) {
+      const int s = atomicAdd(&a.ncand[k], 1);
+      if (s < DB_CAND_CAP) a.cand[(size_t)k * DB_CAND_CAP + s] = key;
+      else atomicOr(&a.err[k], ERR_CAND_OVERFLOW);
+    });
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+// energies of the junctions (FENE log part and angles that a move can change)
+// ---------------------------------------------------------------------------------------
+__device__ double bond_u(const MeltDesc& d, const double* __restrict__ x, int NP, int u, int w) {
+  const double r = sqrt(dist2(x, NP, d.L, u, w));
+  const double R0 = sqrt(d.R0sq);
+  const bool broken = d.amin > 0 ? !(r < 2.0 * R0) : !(r < R0);
+  if (broken) return INFINITY;
+  const double a = 1.0 - (r / R0) * (r / R0);
+  if (d.amin > 0 && a < d.amin) return -0.5 * d.kfene * R0 * R0 * (log(d.amin) + (a - d.amin) / d.amin);
+  return -0.5 * d.kfene * R0 * R0 * log(a);
+}
+
+__device__ double angle_u(const MeltDesc& d, const double* __restrict__ x, int NP, int p, int q, int s) {
+  const double L = d.L;
+  const double b1x = min_image(x[q] - x[p], L), b1y = min_image(x[NP + q] - x[NP + p], L),
+               b1z = min_image(x[2 * NP + q] - x[2 * NP + p], L);
+  const double b2x = min_image(x[s] - x[q], L), b2y = min_image(x[NP + s] - x[NP + q], L),
+               b2z = min_image(x[2 * NP + s] - x[2 * NP + q], L);
+  const double l1 = sqrt(b1x * b1x + b1y * b1y + b1z * b1z);
+  const double l2 = sqrt(b2x * b2x + b2y * b2y + b2z * b2z);
+  return d.kappa * (1.0 - (b1x * b2x + b1y * b2y + b1z * b2z) / (l1 * l2));
+}
+
+// bond kb (1-based, between kb and kb+1) of chain X plus the angles at vertices kb, kb+1
+__device__ double junction_energy(const MeltDesc& d, const Topo& T, const double* __restrict__ x, int NP, int X,
+                                  int kb) {
+  const int N = d.N;
+  double e = bond_u(d, x, NP, T.at(X, kb), T.at(X, kb + 1));
+  for (int v = kb; v <= kb + 1; ++v)
+    if (v >= 2 && v <= N - 1) e += angle_u(d, x, NP, T.at(X, v - 1), T.at(X, v), T.at(X, v + 1));
+  return e;
+}
+
+__device__ double move_dE(const MeltDesc& d, const int* chain, const int* loc, const double* x, int NP,
+                          const Move& mv) {
+  Topo To{chain, loc, d.off, d.N, {mv.A, mv.i, mv.B, mv.j, -1}};
+  Topo Tn{chain, loc, d.off, d.N, mv};
+  const double e_old = junction_energy(d, To, x, NP, mv.A, mv.i) + junction_energy(d, To, x, NP, mv.B, mv.j);
+  const double e_new = junction_energy(d, Tn, x, NP, mv.A, mv.i) + junction_energy(d, Tn, x, NP, mv.B, mv.j);
+  return e_new - e_old;
+}
+
+// Candidates involving chain A or B of topology T (each once): scan the monomers of both
+// chains over their close pairs.  Block-cooperative; returns the count to every thread via
+// *s_count (LDS); emits keys into s_new (capacity DB_NEW_CAP) when s_new != nullptr.
+__device__ void count_touching(const MeltDesc& d, const Topo& T, const DbArgs& a, int A, int B, int* s_count,
+                               uint64_t* s_new, uint32_t* s_err) {
+  const int N = d.N;
+  int local = 0;
+  for (int idx = threadIdx.x; idx < 2 * N; idx += blockDim.x) {
+    const int X = idx < N ? A : B;
+    const int p = (idx < N ? idx : idx - N) + 1;
+    const int u = T.at(X, p);
+    const int nn = a.nnb[u];
+    for (int q = 0; q < nn; ++q) {
+      const int w = a.nbr[(size_t)u * DB_NBR_CAP + q];
+      int Cw, pw;
+      T.where(w, Cw, pw);
+      if (Cw == X) continue;
+      if (X == B && Cw == A) continue;  // counted from chain A's side
+      first_bond_candidates(T, a.x, a.NP, d.L, d.rmax2, d.M, u, X, p, w, Cw, pw, [&](uint64_t key) {
+        ++local;
+        if (s_new) {
+          const int s = atomicAdd(&s_count[1], 1);
+          if (s < DB_NEW_CAP) s_new[s] = key;
+          else atomicOr(s_err, ERR_CAND_OVERFLOW);
+        }
+      });
+    }
+  }
+  if (local) atomicAdd(&s_count[0], local);
+}
+
+__device__ __forceinline__ bool touches(uint64_t key, int M, int N, int A, int B) {
+  const Move m = decode_key(key, M, N);
+  return m.A == A || m.A == B || m.B == A || m.B == B;
+}
+
+// exclusive prefix sum over the block (blockDim = DB_BLOCK); s_tmp holds DB_BLOCK/64 ints
+__device__ int block_exclusive_scan(int v, int* s_tmp, int* s_total) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  int incl = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int t = __shfl_up(incl, o, 64);
+    if (lane >= o) incl += t;
+  }
+  if (lane == 63) s_tmp[wv] = incl;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int acc = 0;
+    for (int q = 0; q < (int)(blockDim.x >> 6); ++q) { const int t = s_tmp[q]; s_tmp[q] = acc; acc += t; }
+    *s_total = acc;
+  }
+  __syncthreads();
+  const int r = s_tmp[wv] + incl - v;
+  __syncthreads();
+  return r;
+}
+
+// ---------------------------------------------------------------------------------------
+// The sweep: one workgroup per melt, attempts in order.
+// ---------------------------------------------------------------------------------------
+__global__ __launch_bounds__(DB_BLOCK) void k_db_sweep(DbArgs a) {
+  __shared__ uint64_t s_keys[2 * DB_CAND_CAP];  // [0, CAP): the sorted list; [CAP, 2CAP): scratch
+  __shared__ uint64_t s_new[DB_NEW_CAP];
+  __shared__ int s_tmp[DB_BLOCK / 64];
+  __shared__ int s_cnt[4];
+  __shared__ int s_total;
+  __shared__ uint32_t s_err;
+  __shared__ Move s_mv;
+  __shared__ int s_accept;
+  __shared__ double s_dE;
+  __shared__ double s_u;
+
+  const int k = blockIdx.x;
+  const MeltDesc& d = a.md[k];
+  const int M = d.M, N = d.N;
+  kgdb_db_stats* st = (kgdb_db_stats*)a.stats + k;
+  if (threadIdx.x == 0) {
+    st->attempts = st->no_candidate = st->accepted = st->reverse_impossible = st->sum_ncand = 0;
+    st->sum_dE_accepted = 0.0;
+    st->ncand_end = 0;
+    s_err = 0;
+  }
+  int n = a.ncand[k];
+  if (n > DB_CAND_CAP || a.err[k] != 0) {  // a build overflow was latched: no attempts
+    if (threadIdx.x == 0) st->ncand_end = n;
+    return;
+  }
+  // sort the list (bitonic over the next power of two, padded with the largest key)
+  int P = 1;
+  while (P < n) P <<= 1;
+  for (int t = threadIdx.x; t < P; t += blockDim.x) s_keys[t] = t < n ? a.cand[(size_t)k * DB_CAND_CAP + t] : ~0ull;
+  __syncthreads();
+  for (int size = 2; size <= P; size <<= 1)
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int t = threadIdx.x; t < P; t += blockDim.x) {
+        const int o = t ^ stride;
+        if (o > t) {
+          const bool up = (t & size) == 0;
+          const uint64_t x0 = s_keys[t], x1 = s_keys[o];
+          if ((x0 > x1) == up) { s_keys[t] = x1; s_keys[o] = x0; }
+        }
+      }
+      __syncthreads();
+    }
+
+  const int64_t K = a.nattempt[k];
+  const uint64_t sweep = a.sweep_ctr[k];
+  for (int64_t att = 0; att < K; ++att) {
+    if (n == 0) {
+      if (threadIdx.x == 0) { st->attempts++; st->no_candidate++; }
+      continue;
+    }
+    if (threadIdx.x == 0) {
+      const U64x4 w = rng_draw(d, (uint64_t)att, sweep, ST_DB);
+      const uint64_t m = rng_choice(w.w[0], (uint64_t)n);
+      s_mv = decode_key(s_keys[m], M, N);
+      s_u = u01(w.w[1]);
+      s_cnt[0] = s_cnt[1] = s_cnt[2] = s_cnt[3] = 0;
+    }
+    __syncthreads();
+    const Move mv = s_mv;
+    // candidates involving A or B now: from the list
+    int mine = 0;
+    for (int t = threadIdx.x; t < n; t += blockDim.x) mine += touches(s_keys[t], M, N, mv.A, mv.B) ? 1 : 0;
+    if (mine) atomicAdd(&s_cnt[2], mine);
+    // ... and after the move: scanned, keys kept for a commit
+    Topo Tn{a.chain, a.loc, d.off, N, mv};
+    count_touching(d, Tn, a, mv.A, mv.B, s_cnt, s_new, &s_err);
+    if (a.debug) {
+      Topo To{a.chain, a.loc, d.off, N, {mv.A, mv.i, mv.B, mv.j, -1}};
+      count_touching(d, To, a, mv.A, mv.B, s_cnt + 3, nullptr, &s_err);
+    }
+    if (threadIdx.x == 0) s_dE = move_dE(d, a.chain, a.loc, a.x, a.NP, mv);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const int old_ab = s_cnt[2], new_ab = s_cnt[0];
+      const int n_new = n - old_ab + new_ab;
+      if (a.debug && s_cnt[3] != old_ab) s_err |= ERR_DB_MISMATCH;
+      const double dE = s_dE;
+      double ratio;
+      if (d.proposal == KGDB_PROPOSAL_LITERAL) {
+        ratio = exp(-dE / d.T);
+      } else {
+        const Topo To{a.chain, a.loc, d.off, N, {mv.A, mv.i, mv.B, mv.j, -1}};
+        const bool rev_ok = dist2(a.x, a.NP, d.L, To.at(mv.A, mv.i), To.at(mv.A, mv.i + 1)) <= d.rmax2 &&
+                            dist2(a.x, a.NP, d.L, To.at(mv.B, mv.j), To.at(mv.B, mv.j + 1)) <= d.rmax2;
+        if (!rev_ok) { st->reverse_impossible++; ratio = 0.0; }
+        else ratio = exp(-dE / d.T) * (double)n / (double)n_new;
+      }
+      st->attempts++;
+      st->sum_ncand += n;
+      // capacities of the merge: kept keys sit below the sorted new keys in the scratch half
+      const int acc = (s_u < ratio) && (s_cnt[1] <= DB_NEW_CAP) && (n_new <= DB_CAND_CAP) &&
+                      (n - old_ab <= DB_CAND_CAP - DB_NEW_CAP);
+      if ((s_u < ratio) && !acc) s_err |= ERR_CAND_OVERFLOW;
+      if (acc) { st->accepted++; st->sum_dE_accepted += dE; }
+      s_accept = acc;
+    }
+    __syncthreads();
+    if (!s_accept) continue;
+
+    // ---- commit: new rows of chains A and B (read through the move, then written)
+    {
+      const Topo Tm{a.chain, a.loc, d.off, N, mv};
+      int vals[DB_MAXPT];
+#pragma unroll
+      for (int q = 0; q < DB_MAXPT; ++q) {
+        const int idx = threadIdx.x + q * DB_BLOCK;
+        if (idx < 2 * N) {
+          const int X = idx < N ? mv.A : mv.B;
+          vals[q] = Tm.at(X, (idx < N ? idx : idx - N) + 1);
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < DB_MAXPT; ++q) {
+        const int idx = threadIdx.x + q * DB_BLOCK;
+        if (idx < 2 * N) {
+          const int X = idx < N ? mv.A : mv.B;
+          const int p0 = idx < N ? idx : idx - N;
+          a.chain[d.off + X * N + p0] = vals[q];
+          a.loc[vals[q]] = X * N + p0;
+        }
+      }
+    }
+    // ---- list update: drop keys touching A or B (order kept), merge the new ones
+    {
+      const int nn = s_cnt[1] < DB_NEW_CAP ? s_cnt[1] : DB_NEW_CAP;
+      // sort the (few) new keys by rank: keys are distinct
+      uint64_t* s_scr = s_keys + DB_CAND_CAP;
+      for (int t = threadIdx.x; t < nn; t += blockDim.x) {
+        const uint64_t key = s_new[t];
+        int r = 0;
+        for (int q = 0; q < nn; ++q) r += s_new[q] < key ? 1 : 0;
+        s_scr[DB_CAND_CAP - DB_NEW_CAP + r] = key;  // sorted new keys at the top of the scratch half
+      }
+      // compact the kept keys into the bottom of the scratch half, in order
+      const int per = (n + DB_BLOCK - 1) / DB_BLOCK;  // <= 3
+      const int t0 = threadIdx.x * per;
+      int keep = 0;
+      for (int q = 0; q < per; ++q)
+        if (t0 + q < n && !touches(s_keys[t0 + q], M, N, mv.A, mv.B)) ++keep;
+      const int pos0 = block_exclusive_scan(keep, s_tmp, &s_total);
+      const int nk = s_total;
+      int pos = pos0;
+      for (int q = 0; q < per; ++q)
+        if (t0 + q < n && !touches(s_keys[t0 + q], M, N, mv.A, mv.B)) s_scr[pos++] = s_keys[t0 + q];
+      __syncthreads();
+      const uint64_t* s_ns = s_scr + (DB_CAND_CAP - DB_NEW_CAP);
+      // merge: kept key at r goes to r + #(new < key); new key at q to q + #(kept < key)
+      for (int t = threadIdx.x; t < nk; t += blockDim.x) {
+        const uint64_t key = s_scr[t];
+        int lo = 0, hi = nn;
+        while (lo < hi) { const int mid = (lo + hi) >> 1; if (s_ns[mid] < key) lo = mid + 1; else hi = mid; }
+        s_keys[t + lo] = key;
+      }
+      for (int t = threadIdx.x; t < nn; t += blockDim.x) {
+        const uint64_t key = s_ns[t];
+        int lo = 0, hi = nk;
+        while (lo < hi) { const int mid = (lo + hi) >> 1; if (s_scr[mid] < key) lo = mid + 1; else hi = mid; }
+        s_keys[t + lo] = key;
+      }
+      n = nk + nn;
+      __syncthreads();
+    }
+  }
+  if (threadIdx.x == 0) {
+    st->ncand_end = n;
+    if (s_err) atomicOr(&a.err[k], s_err);
+    a.ncand[k] = n;
+  }
+  for (int t = threadIdx.x; t < n; t += blockDim.x) a.cand[(size_t)k * DB_CAND_CAP + t] = s_keys[t];
+}
+
+// test hook: Delta E and |C(x')| for given keys, without committing (one block per key)
+__global__ __launch_bounds__(DB_BLOCK) void k_db_probe(DbArgs a, int k, const uint64_t* keys, double* dE,
+                                                       int64_t* nafter) {
+  __shared__ int s_cnt[4];
+  __shared__ uint32_t s_err;
+  const MeltDesc& d = a.md[k];
+  const Move mv = decode_key(keys[blockIdx.x], d.M, d.N);
+  if (threadIdx.x == 0) { s_cnt[0] = s_cnt[1] = s_cnt[2] = s_cnt[3] = 0; s_err = 0; }
+  __syncthreads();
+  const int n = a.ncand[k] < DB_CAND_CAP ? a.ncand[k] : DB_CAND_CAP;
+  int mine = 0;
+  for (int t = threadIdx.x; t < n; t += blockDim.x)
+    mine += touches(a.cand[(size_t)k * DB_CAND_CAP + t], d.M, d.N, mv.A, mv.B) ? 1 : 0;
+  if (mine) atomicAdd(&s_cnt[2], mine);
+  Topo Tn{a.chain, a.loc, d.off, d.N, mv};
+  count_touching(d, Tn, a, mv.A, mv.B, s_cnt, nullptr, &s_err);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    nafter[blockIdx.x] = (int64_t)n - s_cnt[2] + s_cnt[0];
+    dE[blockIdx.x] = move_dE(d, a.chain, a.loc, a.x, a.NP, mv);
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+void launch_db_build(const DbArgs& a, const BlockMap& pm, const BlockMap& cm13, hipStream_t s) {
+  hipLaunchKernelGGL(k_db_bin, dim3(pm.nblk), dim3(256), 0, s, a.md, pm.melt, pm.base, a.NP, a.x, a.cnt13,
+                     a.bucket13, a.err);
+  hipLaunchKernelGGL(k_db_nbr, dim3(pm.nblk), dim3(256), 0, s, a.md, pm.melt, pm.base, a.NP, a.x, a.cnt13,
+                     a.bucket13, a.nnb, a.nbr, a.err);
+  hipLaunchKernelGGL(k_db_cands, dim3(pm.nblk), dim3(256), 0, s, a.md, pm.melt, pm.base, a);
+}
+
+void launch_db_sweep(const DbArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_db_sweep, dim3(a.nm), dim3(DB_BLOCK), 0, s, a);
+}
+
+void launch_db_probe(const DbArgs& a, int melt, const uint64_t* keys, int nkeys, double* dE, int64_t* nafter,
+                     hipStream_t s) {
+  if (nkeys > 0) hipLaunchKernelGGL(k_db_probe, dim3(nkeys), dim3(DB_BLOCK), 0, s, a, melt, keys, dE, nafter);
+}
+
+}  // namespace kgdb

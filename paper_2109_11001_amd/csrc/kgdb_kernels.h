@@ -1,0 +1,98 @@
+// Host-visible launch interfaces of the kgdb kernels (one translation unit per module).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace kgdb {
+
+struct MeltDesc;
+
+// logical block -> (melt, first local index) for kernels over monomers or cells
+struct BlockMap {
+  const int* melt = nullptr;
+  const int* base = nullptr;
+  int nblk = 0;
+};
+
+// fused force kernel modes
+enum : int {
+  F_OPEN = 1,    // opening half kick + drift + wrap + binning of the new position
+  F_CLOSE = 2,   // Langevin force of the step + closing half kick
+  F_STORE = 4,   // store v, F_c, F_L at an integer time (end of a run of steps)
+  F_WARM = 8,    // warm-up: ramped dt, displacement cap, pair-force cap, warm-up noise stream
+  F_DIAG = 16,   // forces only: F_c, per-bead magnitude sums and energies (test hooks)
+  F_EXACT = 32,  // pair distances from the FP64 master positions (with F_DIAG, R = double)
+};
+
+struct ForceArgs {
+  const MeltDesc* md;
+  const int* blk_melt;
+  const int* blk_base;
+  int NP;
+  const double* x;  // current positions [3][NP]
+  double* xn;       // next positions [3][NP]
+  double* v;
+  double* fc;
+  double* fl;
+  int* cell_of;
+  const int* cnt;        // bucket occupancy of the current positions
+  const void* spos;      // cell-relative coordinates of the current positions
+  int* cnt_next;         // occupancy of the next positions (zeroed)
+  int* bucket;           // bucket ids: sorted ones of the current cells are read only with F_EXACT
+  const int* chain;      // chain tables: global monomer id at (melt, chain, position)
+  const int* loc;        // chain * N + position of each monomer (local to its melt)
+  const uint64_t* step_base;
+  uint32_t* err;
+  double* outS;
+  double* outE;
+  double t_close, t_open;  // warm-up ramp coordinates in [0, 1]
+  uint32_t s_off;          // Langevin counter offset of this closing kick
+};
+
+void launch_bin(const MeltDesc* md, const BlockMap& pm, int NP, const double* x, int* cell_of, int* cnt,
+                int* bucket, uint32_t* err, hipStream_t s);
+void launch_finalize(int prec, const MeltDesc* md, const BlockMap& cm, int NP, const double* x, const int* cnt,
+                     int* bucket, void* spos, int* cnt_clear, hipStream_t s);
+void launch_force(int prec, int mode, const ForceArgs& a, int nblk, hipStream_t s);
+void launch_advance(uint64_t* step_base, int nm, uint64_t n, hipStream_t s);
+void launch_fill_i32(int* p, int n, int v, hipStream_t s);
+size_t spos_bytes(int prec);
+
+// ---- init and observables (kgdb_obs.hip)
+void launch_random_walks(const MeltDesc* md, int nm, int max_M, int NP, double* x, int* chain, int* loc,
+                         hipStream_t s);
+void launch_velocities(const MeltDesc* md, const BlockMap& pm, int NP, double* v, hipStream_t s);
+void launch_remove_mean(const MeltDesc* md, int nm, int NP, double* v, hipStream_t s);
+void launch_reduce_melt(const MeltDesc* md, int nm, int NP, const double* outE, const double* v,
+                        double* out4, hipStream_t s);
+void launch_prefix(const MeltDesc* md, int k, int M, int NP, const double* x, const int* chain, double* spre,
+                   double* blen, hipStream_t s);
+void launch_r2(const MeltDesc* md, int k, int M, int N, const double* spre, double* part, double* r2sum,
+               hipStream_t s);
+
+// ---- double bridging (kgdb_db.hip)
+struct DbArgs {
+  const MeltDesc* md;
+  int nm;
+  int NP;
+  const double* x;
+  int* chain;
+  int* loc;
+  int* cnt13;      // [NC13] occupancy of the db grid
+  int* bucket13;   // [NC13 * DB_CELL_CAP]
+  int* nnb;        // [NP] close-neighbour counts
+  int* nbr;        // [NP * DB_NBR_CAP] close neighbours (global ids)
+  uint64_t* cand;  // [nm * DB_CAND_CAP] candidate keys per melt
+  int* ncand;      // [nm]
+  uint32_t* err;
+  const uint64_t* sweep_ctr;  // per melt sweep index (Philox counter word 1)
+  const int64_t* nattempt;    // per melt attempts of this sweep
+  void* stats;                // per melt kgdb_db_stats
+  int debug;                  // recount the old topology and compare with the list
+};
+void launch_db_build(const DbArgs& a, const BlockMap& pm, const BlockMap& cm13, hipStream_t s);
+void launch_db_sweep(const DbArgs& a, hipStream_t s);
+void launch_db_probe(const DbArgs& a, int melt, const uint64_t* keys, int nkeys, double* dE, int64_t* nafter,
+                     hipStream_t s);
+
+}  // namespace kgdb

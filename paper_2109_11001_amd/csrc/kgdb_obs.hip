@@ -1,0 +1,163 @@
+// Initial states, deterministic per-melt reductions and the R^2(n)/n observable (gfx950).
+#include "kgdb_dev.h"
+#include "kgdb_kernels.h"
+
+namespace kgdb {
+
+// Seeded freely jointed random walks: bond 0.97 sigma along isotropic unit vectors
+// u = (sqrt(1-z^2) cos phi, sqrt(1-z^2) sin phi, z), z uniform in [-1,1), phi in [0, 2 pi),
+// uniform start points; accumulated unwrapped in chain order, then wrapped.  One thread
+// per chain (blockIdx.y = melt).  Monomer ids start as chain * N + position.
+__global__ void k_random_walks(const MeltDesc* __restrict__ md, int NP, double* __restrict__ x,
+                               int* __restrict__ chain, int* __restrict__ loc) {
+  const MeltDesc& d = md[blockIdx.y];
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= d.M) return;
+  const int N = d.N;
+  U64x4 w = rng_draw(d, (uint64_t)c * N, 0, ST_WALK);
+  double px = u01(w.w[0]) * d.L, py = u01(w.w[1]) * d.L, pz = u01(w.w[2]) * d.L;
+  for (int p = 0; p < N; ++p) {
+    if (p > 0) {
+      w = rng_draw(d, (uint64_t)c * N + p, 0, ST_WALK);
+      const double z = 2.0 * u01(w.w[0]) - 1.0;
+      const double ph = 6.283185307179586 * u01(w.w[1]);
+      const double st = sqrt(1.0 - z * z);
+      px = px + 0.97 * (st * cos(ph));
+      py = py + 0.97 * (st * sin(ph));
+      pz = pz + 0.97 * z;
+    }
+    const int li = c * N + p, g = d.off + li;
+    x[g] = wrap_box(px, d.L);
+    x[NP + g] = wrap_box(py, d.L);
+    x[2 * NP + g] = wrap_box(pz, d.L);
+    chain[g] = g;
+    loc[g] = li;
+  }
+}
+
+// Maxwell-Boltzmann velocities at T (mean removed by k_remove_mean)
+__global__ __launch_bounds__(256) void k_velocities(const MeltDesc* __restrict__ md, const int* __restrict__ blk_melt,
+                                                    const int* __restrict__ blk_base, int NP, double* __restrict__ v) {
+  const int lb = xcd_remap(blockIdx.x, gridDim.x);
+  const int k = __builtin_amdgcn_readfirstlane(blk_melt[lb]);
+  const MeltDesc& d = md[k];
+  const int li = blk_base[lb] + (int)threadIdx.x;
+  if (li >= d.Nm) return;
+  const int g = d.off + li;
+  const U64x4 w = rng_draw(d, (uint64_t)li, 0, ST_VEL);
+  double z0, z1, z2, z3;
+  gauss2(w.w[0], w.w[1], z0, z1);
+  gauss2(w.w[2], w.w[3], z2, z3);
+  const double s = sqrt(d.T);
+  v[g] = s * z0; v[NP + g] = s * z1; v[2 * NP + g] = s * z2;
+}
+
+// fixed-order block sum (strided partial sums, then a tree): deterministic
+template <int NT>
+__device__ double block_sum(double v, double* s) {
+  s[threadIdx.x] = v;
+  __syncthreads();
+  for (int o = NT / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) s[threadIdx.x] += s[threadIdx.x + o];
+    __syncthreads();
+  }
+  const double r = s[0];
+  __syncthreads();
+  return r;
+}
+
+__global__ __launch_bounds__(256) void k_remove_mean(const MeltDesc* __restrict__ md, int NP, double* __restrict__ v) {
+  __shared__ double s[256];
+  const MeltDesc& d = md[blockIdx.x];
+  for (int c = 0; c < 3; ++c) {
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < d.Nm; i += 256) acc += v[c * NP + d.off + i];
+    const double mean = block_sum<256>(acc, s) / d.Nm;
+    for (int i = threadIdx.x; i < d.Nm; i += 256) v[c * NP + d.off + i] -= mean;
+  }
+}
+
+// per melt: {U_pair, U_bond, U_ang, K} from per-bead energies and velocities
+__global__ __launch_bounds__(256) void k_reduce_melt(const MeltDesc* __restrict__ md, int NP,
+                                                     const double* __restrict__ outE, const double* __restrict__ v,
+                                                     double* __restrict__ out4) {
+  __shared__ double s[256];
+  const MeltDesc& d = md[blockIdx.x];
+  for (int c = 0; c < 4; ++c) {
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < d.Nm; i += 256) {
+      const int g = d.off + i;
+      if (c < 3) acc += outE[c * NP + g];
+      else acc += 0.5 * (v[g] * v[g] + v[NP + g] * v[NP + g] + v[2 * NP + g] * v[2 * NP + g]);
+    }
+    const double r = block_sum<256>(acc, s);
+    if (threadIdx.x == 0) out4[4 * blockIdx.x + c] = r;
+  }
+}
+
+// Per chain of melt k: prefix sums s_p of minimum-image bond vectors (FP64) and the sum of
+// its bond lengths.  spre is [M*N][3] local to the melt.
+__global__ void k_prefix(const MeltDesc* __restrict__ md, int k, int NP, const double* __restrict__ x,
+                         const int* __restrict__ chain, double* __restrict__ spre, double* __restrict__ blen) {
+  const MeltDesc& d = md[k];
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= d.M) return;
+  const int N = d.N;
+  const int* row = chain + d.off + c * N;
+  double sx = 0, sy = 0, sz = 0, bl = 0;
+  spre[3 * (c * N)] = 0; spre[3 * (c * N) + 1] = 0; spre[3 * (c * N) + 2] = 0;
+  for (int p = 1; p < N; ++p) {
+    const int a = row[p - 1], b = row[p];
+    const double dx = min_image(x[b] - x[a], d.L), dy = min_image(x[NP + b] - x[NP + a], d.L),
+                 dz = min_image(x[2 * NP + b] - x[2 * NP + a], d.L);
+    sx += dx; sy += dy; sz += dz;
+    bl += sqrt(dx * dx + dy * dy + dz * dz);
+    spre[3 * (c * N + p)] = sx; spre[3 * (c * N + p) + 1] = sy; spre[3 * (c * N + p) + 2] = sz;
+  }
+  blen[c] = bl;
+}
+
+// block per chemical distance n (1..N-1): sum over chains and i of |s_{i+n} - s_i|^2
+__global__ __launch_bounds__(256) void k_r2(int M, int N, const double* __restrict__ spre, double* __restrict__ r2sum) {
+  __shared__ double s[256];
+  const int n = blockIdx.x + 1;
+  double acc = 0.0;
+  const int per = N - n;
+  const long total = (long)M * per;
+  for (long t = threadIdx.x; t < total; t += 256) {
+    const int c = (int)(t / per), i = (int)(t - (long)c * per);
+    const double* a = spre + 3 * ((long)c * N + i);
+    const double* b = spre + 3 * ((long)c * N + i + n);
+    const double dx = b[0] - a[0], dy = b[1] - a[1], dz = b[2] - a[2];
+    acc += dx * dx + dy * dy + dz * dz;
+  }
+  const double r = block_sum<256>(acc, s);
+  if (threadIdx.x == 0) r2sum[n - 1] = r;
+}
+
+// ---------------------------------------------------------------------------------------
+void launch_random_walks(const MeltDesc* md, int nm, int max_M, int NP, double* x, int* chain, int* loc,
+                         hipStream_t s) {
+  hipLaunchKernelGGL(k_random_walks, dim3((max_M + 63) / 64, nm), dim3(64), 0, s, md, NP, x, chain, loc);
+}
+void launch_velocities(const MeltDesc* md, const BlockMap& pm, int NP, double* v, hipStream_t s) {
+  hipLaunchKernelGGL(k_velocities, dim3(pm.nblk), dim3(256), 0, s, md, pm.melt, pm.base, NP, v);
+}
+void launch_remove_mean(const MeltDesc* md, int nm, int NP, double* v, hipStream_t s) {
+  hipLaunchKernelGGL(k_remove_mean, dim3(nm), dim3(256), 0, s, md, NP, v);
+}
+void launch_reduce_melt(const MeltDesc* md, int nm, int NP, const double* outE, const double* v, double* out4,
+                        hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce_melt, dim3(nm), dim3(256), 0, s, md, NP, outE, v, out4);
+}
+void launch_prefix(const MeltDesc* md, int k, int M, int NP, const double* x, const int* chain, double* spre,
+                   double* blen, hipStream_t s) {
+  hipLaunchKernelGGL(k_prefix, dim3((M + 63) / 64), dim3(64), 0, s, md, k, NP, x, chain, spre, blen);
+}
+void launch_r2(const MeltDesc* md, int k, int M, int N, const double* spre, double* part, double* r2sum,
+               hipStream_t s) {
+  (void)md; (void)k; (void)part;
+  if (N > 1) hipLaunchKernelGGL(k_r2, dim3(N - 1), dim3(256), 0, s, M, N, spre, r2sum);
+}
+
+}  // namespace kgdb

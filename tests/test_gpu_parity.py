@@ -1,0 +1,339 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle on identical inputs.
+
+Bars: bit-exact for cell lists, candidate lists, post-sweep topologies and sweep counts;
+1e-12 (relative to the per-bead force scale S_i) for FP64 forces and single steps;
+1e-5 of S_i for FP32 forces of the mixed path.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import oracle as o
+from tests import inputs
+
+pytestmark = pytest.mark.gpu
+
+kg = pytest.importorskip("paper_2109_11001_amd")
+
+
+def _gpu_available():
+    try:
+        import torch
+        return torch.cuda.is_available()
+    except Exception:
+        return False
+
+
+if not _gpu_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+
+def pair(**kw):
+    """An oracle melt and a GPU melt built from the same parameters (GPU init skipped)."""
+    om = o.Melt(**kw)
+    gkw = dict(kw)
+    gkw["warmup_steps"] = 0
+    gm = kg.Melt(**gkw)
+    transfer(om, gm)
+    return om, gm
+
+
+def transfer(om, gm, melt=0):
+    st = om.get_state()
+    gm.set_state(melt, x=st["x"], v=st["v"], fl=st["fl"], chains=st["chains"], counters=st["counters"])
+
+
+def mi_diff(a, b, L):
+    d = a - b
+    return d - L * np.rint(d / L)
+
+
+# ------------------------------------------------------------------------------- init
+@pytest.mark.parametrize("kw", [dict(M=20, N=50, seed=1), dict(M=7, N=33, seed=5, melt_id=3),
+                                dict(M=200, N=1000, seed=2, kappa=2.0)])
+def test_init_matches_oracle(kw):
+    om = o.Melt(warmup_steps=0, **kw)
+    gm = kg.Melt(warmup_steps=0, **kw)
+    so, sg = om.get_state(), gm.get_state()
+    assert gm.geom[0]["L"] == om.L
+    assert np.array_equal(so["chains"], sg["chains"])
+    assert np.max(np.abs(mi_diff(so["x"], sg["x"], om.L))) < 1e-11
+    assert np.max(np.abs(so["v"] - sg["v"])) < 1e-13
+
+
+def test_warmup_matches_oracle():
+    kw = dict(M=20, N=50, seed=3, warmup_steps=30)
+    om, gm = o.Melt(**kw), kg.Melt(**kw)
+    so, sg = om.get_state(), gm.get_state()
+    assert np.max(np.abs(mi_diff(so["x"], sg["x"], om.L))) < 1e-9
+    assert np.max(np.abs(so["v"] - sg["v"])) < 1e-7
+
+
+# -------------------------------------------------------------------------- cell lists
+@pytest.mark.parametrize("kw", [dict(M=20, N=50, seed=1), dict(M=7, N=33, seed=9),
+                                dict(M=200, N=1000, seed=1, warmup_steps=0),
+                                dict(M=20, N=50, seed=4, r_cell=1.6)])
+def test_cell_list_bit_exact(kw):
+    om, gm = pair(**kw)
+    nco, so, ido = om.cell_list(kw.get("r_cell", 0.0))
+    ncg, sg, idg = gm.cell_list()
+    assert nco == ncg
+    assert np.array_equal(so, sg)
+    assert np.array_equal(ido, idg)
+
+
+# ------------------------------------------------------------------------------ forces
+FORCE_CASES = [dict(n_exp=2.0, kappa=1.5), dict(n_exp=12.0, kappa=3.0), dict(n_exp=5.75, kappa=0.0),
+               dict(n_exp=6.5, kappa=2.5), dict(n_exp=2.0, kappa=1.5, k_fene=30.0),
+               dict(n_exp=5.0, kappa=1.5, test_flags=o.TF_PHANTOM)]
+
+
+def _force_err(Fo, So, Fg):
+    dF = np.sqrt(((Fo - Fg) ** 2).sum(0))
+    return np.max(dF / np.maximum(So, 1e-300))
+
+
+@pytest.mark.parametrize("case", FORCE_CASES)
+@pytest.mark.parametrize("size", [dict(M=20, N=50), dict(M=7, N=33)])
+def test_forces_fp64(case, size):
+    om, gm = pair(seed=11, warmup_steps=200, **size, **case)
+    Fo, So, Eo = om.forces()
+    Fg, Sg, Eg = gm.forces()
+    assert _force_err(Fo, So, Fg) < 1e-12
+    assert np.allclose(Sg, So, rtol=1e-12, atol=0)
+    assert np.allclose(Eg, Eo, rtol=1e-12, atol=1e-12)
+    eo, eg = om.energy(), gm.energy()
+    assert np.allclose(eg, eo, rtol=1e-12, atol=1e-12)
+
+
+@pytest.mark.parametrize("case", FORCE_CASES)
+def test_forces_mixed_precision(case):
+    om = o.Melt(M=20, N=50, seed=12, warmup_steps=200, **case)
+    gm = kg.Melt(M=20, N=50, seed=12, warmup_steps=0, precision=kg.PREC_MIXED, **case)
+    transfer(om, gm)
+    Fo, So, _ = om.forces()
+    Fg, _, _ = gm.forces()
+    assert _force_err(Fo, So, Fg) <= 1e-5
+    # energies stay FP64 in the mixed path
+    assert np.allclose(gm.energy(), om.energy(), rtol=1e-12, atol=1e-12)
+
+
+def test_forces_full_size_c1():
+    # the 200k-monomer workload (200 chains x 1000 beads, kappa = 2, n = 2), both precisions
+    om = o.Melt(M=200, N=1000, kappa=2.0, seed=1, warmup_steps=100)
+    Fo, So, _ = om.forces()
+    for prec, tol in ((kg.PREC_FP64, 1e-12), (kg.PREC_MIXED, 1e-5)):
+        gm = kg.Melt(M=200, N=1000, kappa=2.0, seed=1, warmup_steps=0, precision=prec)
+        transfer(om, gm)
+        Fg, _, _ = gm.forces()
+        assert _force_err(Fo, So, Fg) <= tol, prec
+        gm.close()
+
+
+# --------------------------------------------------------------------------- dynamics
+@pytest.mark.parametrize("nsteps", [1, 7, 50])
+def test_md_steps_fp64(nsteps):
+    om, gm = pair(M=20, N=50, seed=21, warmup_steps=300, kappa=1.5)
+    om.md_steps(nsteps)
+    gm.md_steps(nsteps, graph=False)
+    so, sg = om.get_state(), gm.get_state()
+    tol = 1e-12 * 10 ** (nsteps / 25)  # chaotic growth over short windows
+    assert np.max(np.abs(mi_diff(so["x"], sg["x"], om.L))) < tol
+    assert np.max(np.abs(so["v"] - sg["v"])) < 100 * tol
+    assert np.max(np.abs(so["fl"] - sg["fl"])) < 100 * tol
+    assert np.array_equal(so["counters"][:3], sg["counters"][:3])
+
+
+def test_md_steps_mixed_one_step():
+    om = o.Melt(M=20, N=50, seed=22, warmup_steps=300)
+    gm = kg.Melt(M=20, N=50, seed=22, warmup_steps=0, precision=kg.PREC_MIXED)
+    transfer(om, gm)
+    om.md_steps(1)
+    gm.md_steps(1)
+    so, sg = om.get_state(), gm.get_state()
+    # FP32 force error 1e-5 x S_i enters v through dt/2 and x through dt^2/2
+    assert np.max(np.abs(so["v"] - sg["v"])) < 1e-3
+    assert np.max(np.abs(mi_diff(so["x"], sg["x"], om.L))) < 1e-5
+
+
+def test_graph_equals_direct_and_is_deterministic():
+    kw = dict(M=20, N=50, seed=5, warmup_steps=100)
+    a, b, c = kg.Melt(**kw), kg.Melt(**kw), kg.Melt(**kw)
+    a.md_steps(250, graph=True)
+    b.md_steps(250, graph=False)
+    c.md_steps(250, graph=True)
+    sa, sb, sc = a.get_state(), b.get_state(), c.get_state()
+    for f in ("x", "v", "fl", "fc"):
+        assert np.array_equal(sa[f], sb[f]), f
+        assert np.array_equal(sa[f], sc[f]), f
+
+
+def test_nve_energy_conservation_gpu():
+    base = o.Melt(M=10, N=40, n_exp=8.0, kappa=1.0, seed=3, warmup_steps=500)
+    st = base.get_state()
+    errs = []
+    for dt in (0.002, 0.001):
+        gm = kg.Melt(M=10, N=40, n_exp=8.0, kappa=1.0, seed=3, gamma=0.0, dt=dt, warmup_steps=0)
+        gm.set_state(x=st["x"], v=st["v"], chains=st["chains"])
+        e0 = gm.energy().sum()
+        dev = []
+        for _ in range(20):
+            gm.md_steps(int(round(0.1 / dt)))
+            dev.append(gm.energy().sum() - e0)
+        errs.append(np.max(np.abs(dev)))
+    assert 2.8 < errs[0] / errs[1] < 5.5
+
+
+def test_langevin_equipartition_gpu():
+    gm = kg.Melt(M=20, N=50, test_flags=kg.TF_NOFORCE, warmup_steps=0, T=1.3, seed=9)
+    gm.md_steps(500)
+    acc = []
+    for _ in range(20):
+        gm.md_steps(150)
+        acc.append(gm.get_state()["v"].ravel())
+    assert np.var(np.concatenate(acc)) == pytest.approx(1.3, rel=0.03)
+
+
+# -------------------------------------------------------------------- double bridging
+@pytest.mark.parametrize("kw", [dict(M=20, N=50, seed=1), dict(M=30, N=24, seed=2),
+                                dict(M=31, N=25, seed=3, kappa=0.0),
+                                dict(M=200, N=1000, seed=1, kappa=2.0, warmup_steps=100)])
+def test_candidates_bit_exact(kw):
+    om, gm = pair(**kw)
+    ko, kgk = om.candidates(), gm.candidates()
+    assert len(ko) > 0
+    assert np.array_equal(ko, kgk)
+
+
+def test_db_probe_matches_oracle():
+    om, gm = pair(M=30, N=24, seed=7, warmup_steps=200)
+    keys = om.candidates()
+    assert len(keys) >= 5
+    dEg, nag = gm.db_probe(keys)
+    for k, dg, ng in zip(keys, dEg, nag):
+        A, i, B, j, var = o.key_decode(k, 30, 24)
+        do = om.move_dE(A, i, B, j, var)
+        assert dg == pytest.approx(do, rel=1e-12, abs=1e-12)
+        ch = om.get_state()["chains"].copy()
+        om.apply_move(A, i, B, j, var)
+        n_after = len(om.candidates())
+        om.set_state(chains=ch)
+        assert ng == n_after
+
+
+@pytest.mark.parametrize("proposal", [0, 2])
+@pytest.mark.parametrize("kw", [dict(M=20, N=50, seed=1, kappa=1.5), dict(M=30, N=24, seed=2, kappa=0.5),
+                                dict(M=25, N=31, seed=8, kappa=3.0, n_exp=5.75)])
+def test_db_sweep_bit_exact(kw, proposal):
+    om, gm = pair(proposal=proposal, **kw)
+    for sweep in range(3):
+        so_stats = om.db_sweep(150)
+        sg_stats = gm.db_sweep(150, checked=True)[0]
+        for f in ("attempts", "no_candidate", "accepted", "reverse_impossible", "sum_ncand", "ncand_end"):
+            assert so_stats[f] == sg_stats[f], (sweep, f, so_stats, sg_stats)
+        assert sg_stats["sum_dE_accepted"] == pytest.approx(so_stats["sum_dE_accepted"], rel=1e-11, abs=1e-11)
+        assert np.array_equal(om.get_state()["chains"], gm.get_state()["chains"])
+    assert so_stats["accepted"] > 0
+
+
+def test_db_sweep_stiff_hard_core():
+    # kappa = 3, n = 12: moves are rarely accepted; decisions must still agree
+    om, gm = pair(M=25, N=31, seed=8, kappa=3.0, n_exp=12.0)
+    so = om.db_sweep(300)
+    sg = gm.db_sweep(300, checked=True)[0]
+    for f in ("attempts", "no_candidate", "accepted", "reverse_impossible", "sum_ncand", "ncand_end"):
+        assert so[f] == sg[f], f
+    assert np.array_equal(om.get_state()["chains"], gm.get_state()["chains"])
+
+
+def test_db_sweep_full_size_c1():
+    om, gm = pair(M=200, N=1000, seed=1, kappa=2.0, warmup_steps=100)
+    so = om.db_sweep(20)
+    sg = gm.db_sweep(20, checked=True)[0]
+    assert so["accepted"] == sg["accepted"] and so["ncand_end"] == sg["ncand_end"]
+    assert np.array_equal(om.get_state()["chains"], gm.get_state()["chains"])
+
+
+def test_md_after_sweep_parity():
+    # the sweep invalidates the bonded forces; the next step must recompute them
+    om, gm = pair(M=20, N=50, seed=31, warmup_steps=200)
+    om.db_sweep(100)
+    gm.db_sweep(100)
+    om.md_steps(5)
+    gm.md_steps(5)
+    so, sg = om.get_state(), gm.get_state()
+    assert np.max(np.abs(mi_diff(so["x"], sg["x"], om.L))) < 1e-11
+
+
+# --------------------------------------------------------------------- observables
+@pytest.mark.parametrize("kw", [dict(M=20, N=50, seed=1), dict(M=100, N=2000, seed=1, kappa=3.0, warmup_steps=0)])
+def test_observables_match_oracle(kw):
+    om, gm = pair(**kw)
+    ro, lko, mbo = om.observables()
+    rg, lkg, mbg = gm.observables()
+    # both sides sum M (N - n) non-negative FP64 terms per n in different orders: each sum is
+    # within (number of terms) x 2^-53 of the exact one, relative
+    M, N = kw["M"], kw["N"]
+    n = np.arange(1, N)
+    bound = 2 * M * (N - n) * 2.0 ** -53
+    assert np.all(np.abs(rg - ro) <= bound * ro)
+    assert abs(mbg - mbo) <= 2 * M * (N - 1) * 2.0 ** -53 * mbo
+    assert lkg == pytest.approx(lko, rel=1e-8)
+
+
+# --------------------------------------------------------------------------- batches
+def test_batch_equals_single_melts():
+    melts = [dict(M=20, N=50, seed=1, melt_id=0, kappa=0.0, warmup_steps=50),
+             dict(M=13, N=40, seed=1, melt_id=1, kappa=1.0, warmup_steps=50),
+             dict(M=9, N=70, seed=1, melt_id=2, kappa=2.5, warmup_steps=50)]
+    b = kg.Batch(melts)
+    singles = [kg.Melt(**m) for m in melts]
+    b.md_steps(230)
+    b.db_sweep(40)
+    b.md_steps(120)
+    for k, s in enumerate(singles):
+        s.md_steps(230)
+        s.db_sweep(40)
+        s.md_steps(120)
+        sb, ss = b.get_state(k), s.get_state()
+        for f in ("x", "v", "fl", "chains"):
+            assert np.array_equal(sb[f], ss[f]), (k, f)
+
+
+# ---------------------------------------------------------------------------- errors
+def test_invalid_params():
+    with pytest.raises(kg.KgdbError) as e:
+        kg.Melt(n_exp=6.0)
+    assert e.value.code == kg._lib.E_PARAM
+    with pytest.raises(kg.KgdbError):
+        kg.Melt(M=2, N=3, rho=0.85)  # box smaller than 3 cells
+
+
+def test_fene_and_nonfinite_errors():
+    om = o.Melt(M=20, N=50, seed=1, warmup_steps=100)
+    st = om.get_state()
+    gm = kg.Melt(M=20, N=50, seed=1, warmup_steps=0)
+    x = st["x"].copy()
+    ch = st["chains"]
+    x[:, ch[0, 1]] = x[:, ch[0, 0]] + np.array([3.2, 0.0, 0.0])  # bond beyond 2 R0
+    gm.set_state(x=x, v=st["v"], chains=ch)
+    with pytest.raises(kg.KgdbError) as e:
+        gm.md_steps(1)
+    assert e.value.code == kg._lib.E_FENE
+    x = st["x"].copy()
+    v = st["v"].copy()
+    v[0, 5] = np.nan
+    gm.set_state(x=x, v=v, chains=ch)
+    with pytest.raises(kg.KgdbError) as e:
+        gm.md_steps(1)
+    assert e.value.code == kg._lib.E_NONFINITE
+
+
+def test_bad_chain_table_rejected():
+    gm = kg.Melt(M=20, N=50, seed=1, warmup_steps=0)
+    ch = inputs.identity_chains(20, 50)
+    ch[0, 0] = ch[0, 1]
+    with pytest.raises(kg.KgdbError) as e:
+        gm.set_state(chains=ch)
+    assert e.value.code == kg._lib.E_STATE
