@@ -66,7 +66,9 @@ typedef struct {
   uint64_t seed;          /* Philox key word 0                                                 */
   int32_t melt_id;        /* Philox key word 1                                                 */
   uint32_t test_flags;    /* KGDB_TF_*                                                         */
-  double r_cell;          /* MD cell edge (<= 0: r_c = 2^(1/6)); must be >= r_c                */
+  double r_cell;          /* cell edge of the exported cell list and the warm-up (<= 0: r_c)   */
+  int32_t nl_every;       /* neighbour-list rebuild interval K in steps (<= 0: 5)               */
+  double nl_skin;         /* list skin (<= 0: 13.2 K dt sqrt(T), twice a 6.6-sigma drift)       */
 } kgdb_params;
 
 /* statistics of one melt's double-bridging sweep */
@@ -139,17 +141,27 @@ int kgdb_candidates(kgdb_batch* b, int32_t melt, uint64_t* keys, int64_t cap, in
 /* For each key: Delta E of the move and |C(x')| after it, without committing. */
 int kgdb_db_probe(kgdb_batch* b, int32_t melt, const uint64_t* keys, int64_t nkeys, double* dE,
                   int64_t* ncand_after);
-/* Time `reps` launches of the fused force/integrator kernel on the batch's stream with HIP
-   events (the state is advanced by reps steps); *avg_ms receives the mean duration. */
+/* Time `reps` launches of the production step kernel on the batch's stream with HIP events
+   (the state is advanced by reps + 1 steps); *avg_ms receives the mean duration. */
 int kgdb_time_force_kernel(kgdb_batch* b, int32_t reps, double* avg_ms);
 /* kgdb_db_sweep plus an on-device check, per attempt, that the incremental count of the
    candidates touching the two chains equals a full recount (mismatch: KGDB_E_STATE). */
 int kgdb_db_sweep_checked(kgdb_batch* b, int64_t n_attempts, kgdb_db_stats* stats);
-/* Per-launch HIP-event timing of the fused force kernel and of the cell finalisation inside
+/* Per-launch HIP-event timing of the step kernel and of the neighbour-list rebuilds inside
    kgdb_md_steps while enabled (graphs are not used meanwhile).  profile_read returns the
-   summed milliseconds and launch counts since the last read and resets them. */
+   summed milliseconds of step kernels and of rebuilds (fin_ms), with their counts, since
+   the last read and resets them. */
 int kgdb_profile(kgdb_batch* b, int32_t enable);
 int kgdb_profile_read(kgdb_batch* b, double* force_ms, int64_t* force_n, double* fin_ms, int64_t* fin_n);
+/* Autotuner of the production step: the neighbour-list rebuild interval K (1, 2 or 5 steps;
+   the skin follows K).  nl_every > 0 sets it; nl_every == 0 times each usable K over `reps`
+   steps (<= 0: 20) on the current state with HIP events, keeps the fastest, and restores the
+   state.  *chosen (may be NULL) receives K (0: the box is too small for lists and steps run
+   on the r_c cell grid); ms_per_variant (may be NULL, 3 entries) the mean time per step of
+   K = 1, 2, 5 (0 when unusable). */
+int kgdb_autotune(kgdb_batch* b, int32_t nl_every, int32_t reps, int32_t* chosen, double* ms_per_variant);
+/* neighbour lists: out = {K, skin, mean list length, rollbacks so far} */
+int kgdb_nl_info(kgdb_batch* b, double out[4]);
 /* geometry of melt `melt`: out = {L, MD cells per side, double-bridging cells per side,
    FENE constant in use (k_n of Eq. 9 or the literal value)} */
 int kgdb_melt_geometry(const kgdb_batch* b, int32_t melt, double out[4]);

@@ -14,7 +14,8 @@ from ._lib import (PREC_FP64, PREC_MIXED, PROPOSAL_LITERAL, PROPOSAL_UNIFORM, TF
 DEFAULTS = dict(M=20, N=50, rho=0.85, kappa=1.5, n_exp=2.0, k_fene=0.0, R0=1.5, T=1.0,
                 gamma=1.0, dt=0.01, db_rmax=1.3, db_rate=1e-3, proposal=PROPOSAL_UNIFORM,
                 precision=PREC_FP64, warmup_steps=1000, warmup_dt0=0.001, warmup_max_disp=0.05,
-                warmup_fcap=10.0, fene_floor=0.02, seed=1, melt_id=0, test_flags=0, r_cell=0.0)
+                warmup_fcap=10.0, fene_floor=0.02, seed=1, melt_id=0, test_flags=0, r_cell=0.0,
+                nl_every=0, nl_skin=0.0)
 
 # the n values of the paper's schedule, Eq. (11)
 XI = (2.0, 3.0, 4.0, 5.0, 5.75, 6.5, 7.0, 8.0, 9.0, 10.0, 11.0, 12.0)
@@ -56,9 +57,13 @@ class Batch:
             self.geom.append(dict(L=g[0], nc=int(g[1]), nc13=int(g[2]), k_fene=g[3]))
 
     def close(self):
-        if getattr(self, "_h", None):
-            load().kgdb_destroy(self._h)
+        h = getattr(self, "_h", None)
+        if h:
             self._h = None
+            try:
+                load().kgdb_destroy(h)
+            except Exception:  # interpreter shutdown
+                pass
 
     def __del__(self):
         self.close()
@@ -139,6 +144,17 @@ class Batch:
         fm, fn, nm_, nn = C.c_double(), C.c_int64(), C.c_double(), C.c_int64()
         check(load().kgdb_profile_read(self._h, C.byref(fm), C.byref(fn), C.byref(nm_), C.byref(nn)))
         return dict(force_ms=fm.value, force_n=fn.value, finalize_ms=nm_.value, finalize_n=nn.value)
+
+    def autotune(self, nl_every=0, reps=20):
+        """Pick (0) or set the neighbour-list rebuild interval; returns (K, ms per step for K=1,2,5)."""
+        ch = C.c_int32(); ms = np.zeros(3)
+        check(load().kgdb_autotune(self._h, int(nl_every), int(reps), C.byref(ch), ptr(ms)))
+        return ch.value, dict(zip((1, 2, 5), ms))
+
+    def nl_info(self):
+        out = np.zeros(4)
+        check(load().kgdb_nl_info(self._h, ptr(out)))
+        return dict(K=int(out[0]), skin=out[1], mean_list=out[2], rollbacks=int(out[3]))
 
     def sizes(self):
         a, b = C.c_int64(), C.c_int64()

@@ -34,7 +34,7 @@ class Params(C.Structure):
         ("warmup_dt0", C.c_double), ("warmup_max_disp", C.c_double), ("warmup_fcap", C.c_double),
         ("fene_floor", C.c_double),
         ("seed", C.c_uint64), ("melt_id", C.c_int32), ("test_flags", C.c_uint32),
-        ("r_cell", C.c_double),
+        ("r_cell", C.c_double), ("nl_every", C.c_int32), ("nl_skin", C.c_double),
     ]
 
 
@@ -55,7 +55,7 @@ EXPORTS = [
     "kgdb_md_steps", "kgdb_db_sweep", "kgdb_observables", "kgdb_energy", "kgdb_get_state",
     "kgdb_set_state", "kgdb_forces", "kgdb_cell_list", "kgdb_candidates", "kgdb_db_probe",
     "kgdb_time_force_kernel", "kgdb_db_sweep_checked", "kgdb_profile", "kgdb_profile_read",
-    "kgdb_melt_geometry", "kgdb_batch_sizes",
+    "kgdb_melt_geometry", "kgdb_batch_sizes", "kgdb_autotune", "kgdb_nl_info",
 ]
 
 _lib = None
@@ -95,6 +95,8 @@ def load():
     L.kgdb_profile_read.argtypes = [P, P, P, P, P]
     L.kgdb_melt_geometry.argtypes = [P, i32, P]
     L.kgdb_batch_sizes.argtypes = [P, P, P]
+    L.kgdb_autotune.argtypes = [P, i32, i32, P, P]
+    L.kgdb_nl_info.argtypes = [P, P]
     for f in EXPORTS:
         if f not in ("kgdb_destroy", "kgdb_last_error", "kgdb_batch_size"):
             getattr(L, f).restype = C.c_int

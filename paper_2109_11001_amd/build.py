@@ -19,6 +19,7 @@ COMMON = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-
 # contraction; the force kernel keeps contraction for speed
 SOURCES = {
     "kgdb_md.hip": [],
+    "kgdb_nl.hip": [],
     "kgdb_db.hip": ["-ffp-contract=off"],
     "kgdb_obs.hip": ["-ffp-contract=off"],
     "kgdb_api.hip": ["-ffp-contract=off"],

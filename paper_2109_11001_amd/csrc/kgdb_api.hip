@@ -3,6 +3,7 @@
 // test hooks.  Kernels live in kgdb_md.hip, kgdb_db.hip and kgdb_obs.hip.
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -45,7 +46,9 @@ struct kgdb_batch {
   // device
   MeltDesc* d_md = nullptr;
   int* d_blk = nullptr;  // block maps, concatenated
-  BlockMap pm, cm;
+  BlockMap pm, cm;       // monomers (256 per block), cells (256/FIN_LANES per block)
+  BlockMap fm[4];        // force kernel: 256/G monomers per block for G = 1, 2, 4, 8
+  int lanes = FORCE_LANES_DEFAULT;  // lanes per monomer in the cell-grid force kernel
   double* d_x[2] = {nullptr, nullptr};
   int cur = 0;
   double *d_v = nullptr, *d_fc = nullptr, *d_fl = nullptr, *d_diagF = nullptr, *d_S = nullptr, *d_E = nullptr;
@@ -54,6 +57,29 @@ struct kgdb_batch {
   int* d_bucket = nullptr;
   void* d_spos = nullptr;
   int *d_chain = nullptr, *d_loc = nullptr;
+  int* d_mono = nullptr;  // monomer id (local) held in each storage slot
+  int *d_perm = nullptr, *d_inv = nullptr, *d_start = nullptr, *d_tmpi = nullptr;
+  double* d_tmp3 = nullptr;
+  bool reorder = true;    // renumber slots in cell order after each run of MD steps
+  // neighbour lists (production steps)
+  int NCL = 0;                     // list-grid cells (sized for the finest grid among the K choices)
+  int nl_k = 5;                    // rebuild interval in use
+  int nl_ki = 2;                   // its index in NL_KS
+  std::vector<MeltDesc> Dk[3];     // descriptors for each rebuild interval of NL_KS
+  BlockMap lm[3];                  // list-grid cell blocks for each K
+  int* d_cntl[2] = {nullptr, nullptr};
+  int cl = 0;                      // list-grid occupancy buffer the next rebuild fills
+  int* d_bucketl = nullptr;
+  void* d_rel[2] = {nullptr, nullptr};
+  float4* d_relb = nullptr;
+  int* d_refc = nullptr;
+  uint32_t* d_nlist = nullptr;
+  int* d_nlen = nullptr;
+  double* d_save = nullptr;        // chunk-start state for the rollback
+  uint64_t* d_save_step = nullptr;
+  hipGraphExec_t ngexec[3][2][2] = {};  // [K][x parity][occupancy parity]
+  int64_t nl_rollbacks = 0;
+  bool rebuild_pending = false;    // profiling: a rebuild was timed for the next step
   uint64_t* d_step = nullptr;
   uint32_t* d_err = nullptr;
   double* d_out4 = nullptr;
@@ -114,6 +140,26 @@ static int check_params(const kgdb_params& p) {
   return 0;
 }
 
+// rebuild intervals the runtime chooses from (each divides the 100-step graph chunk with an
+// even number of rebuilds, so the occupancy buffers' parity returns after a chunk)
+static const int NL_KS[3] = {1, 2, 5};
+
+static double nl_skin_for(const kgdb_params& p, int K) {
+  // twice a 6.6-sigma ballistic drift over K steps at temperature T, unless given
+  return p.nl_skin > 0 ? p.nl_skin : 13.2 * K * p.dt * std::sqrt(p.T > 0 ? p.T : 1.0);
+}
+
+static void set_list_geometry(MeltDesc& d, const kgdb_params& p, int K) {
+  const double rc = std::pow(2.0, 1.0 / 6.0);
+  const double skin = nl_skin_for(p, K);
+  const double rl = rc + skin;
+  d.ncl = std::max(1, (int)std::floor(d.L / rl));
+  d.cinvl = (double)d.ncl / d.L;
+  d.hl = d.L / d.ncl;
+  d.rlist2 = rl * rl;
+  d.half_skin2 = 0.25 * skin * skin;
+}
+
 static MeltDesc make_desc(const kgdb_params& p) {
   MeltDesc d;
   std::memset(&d, 0, sizeof d);
@@ -142,6 +188,9 @@ static MeltDesc make_desc(const kgdb_params& p) {
   d.T = p.T; d.gamma = p.gamma; d.dt = p.dt;
   d.warm_dt0 = p.warmup_dt0; d.warm_cap = p.warmup_max_disp; d.warm_fcap = p.warmup_fcap;
   d.rmax2 = p.db_rmax * p.db_rmax;
+  d.invN = 1.0 / d.N;
+  d.lang_amp = std::sqrt(2.0 * p.gamma * p.T / p.dt);
+  set_list_geometry(d, p, p.nl_every > 0 ? p.nl_every : 5);
   d.seed = p.seed;
   d.melt_id = (uint64_t)(int64_t)p.melt_id;
   d.test_flags = p.test_flags;
@@ -158,12 +207,16 @@ static double host_wrap(double x, double L) {
 // ---------------------------------------------------------------------------------------
 // step machinery
 // ---------------------------------------------------------------------------------------
+static int lane_index(int lanes) { return lanes == 1 ? 0 : lanes == 2 ? 1 : lanes == 4 ? 2 : 3; }
+static int force_blocks(const kgdb_batch* b) { return b->fm[lane_index(b->lanes)].nblk; }
+
 static ForceArgs force_args(kgdb_batch* b) {
   ForceArgs a;
   std::memset(&a, 0, sizeof a);
   a.md = b->d_md;
-  a.blk_melt = b->pm.melt;
-  a.blk_base = b->pm.base;
+  const BlockMap& fm = b->fm[lane_index(b->lanes)];
+  a.blk_melt = fm.melt;
+  a.blk_base = fm.base;
   a.NP = b->NP;
   a.x = b->d_x[b->cur];
   a.xn = b->d_x[1 - b->cur];
@@ -177,6 +230,7 @@ static ForceArgs force_args(kgdb_batch* b) {
   a.bucket = b->d_bucket;
   a.chain = b->d_chain;
   a.loc = b->d_loc;
+  a.mono = b->d_mono;
   a.step_base = b->d_step;
   a.err = b->d_err;
   a.outS = b->d_S;
@@ -209,7 +263,7 @@ static int do_step(kgdb_batch* b, int mode, uint32_t s_off, double t_close, doub
     if (b->ev_used == PROF_EVENTS) CHK(prof_flush(b));
     HIPCHK(hipEventRecord(b->ev[4 * b->ev_used], b->s));
   }
-  launch_force(b->prec, mode, a, b->pm.nblk, b->s);
+  launch_force(b->prec, mode, b->lanes, a, force_blocks(b), b->s);
   if (prof) HIPCHK(hipEventRecord(b->ev[4 * b->ev_used + 1], b->s));
   if (mode & F_OPEN) {
     b->cur = 1 - b->cur;
@@ -275,8 +329,200 @@ static int capture_chunk(kgdb_batch* b, int parity) {
   return 0;
 }
 
+// Renumber the storage slots of every melt in cell order (cells of melt k cover exactly the
+// slots of melt k), from the occupancy and buckets of the last list rebuild.
+static int reorder_storage(kgdb_batch* b) {
+  const int NP = b->NP;
+  launch_perm_cells(b->d_cntl[1 - b->cl], b->d_bucketl, NL_CELL_CAP, b->NCL, b->d_start, b->d_perm, b->d_inv, b->s);
+  launch_gather_f64x3(b->d_x[1 - b->cur], b->d_x[b->cur], b->d_perm, NP, b->s);
+  double* f3[3] = {b->d_v, b->d_fc, b->d_fl};
+  for (double* f : f3) {
+    launch_gather_f64x3(b->d_tmp3, f, b->d_perm, NP, b->s);
+    HIPCHK(hipMemcpyAsync(f, b->d_tmp3, sizeof(double) * 3 * (size_t)NP, hipMemcpyDeviceToDevice, b->s));
+  }
+  int* i1[2] = {b->d_loc, b->d_mono};
+  for (int* f : i1) {
+    launch_gather_i32(b->d_tmpi, f, b->d_perm, NP, b->s);
+    HIPCHK(hipMemcpyAsync(f, b->d_tmpi, sizeof(int) * (size_t)NP, hipMemcpyDeviceToDevice, b->s));
+  }
+  launch_remap_i32(b->d_chain, b->d_inv, NP, b->s);
+  HIPCHK(hipGetLastError());
+  b->cur = 1 - b->cur;
+  b->cells_valid = false;
+  return 0;
+}
+
+static NlArgs nl_args(kgdb_batch* b) {
+  NlArgs a;
+  std::memset(&a, 0, sizeof a);
+  a.md = b->d_md;
+  a.pblk_melt = b->pm.melt;
+  a.pblk_base = b->pm.base;
+  a.cblk_melt = b->lm[b->nl_ki].melt;
+  a.cblk_base = b->lm[b->nl_ki].base;
+  a.NP = b->NP;
+  a.x = b->d_x[b->cur];
+  a.xn = b->d_x[1 - b->cur];
+  a.v = b->d_v;
+  a.fc = b->d_fc;
+  a.fl = b->d_fl;
+  a.cnt = b->d_cntl[b->cl];
+  a.cnt_clear = b->d_cntl[1 - b->cl];
+  a.bucket = b->d_bucketl;
+  a.rel_cur = b->d_rel[b->cur];
+  a.rel_next = b->d_rel[1 - b->cur];
+  a.relb = b->d_relb;
+  a.refc = b->d_refc;
+  a.nlist = b->d_nlist;
+  a.nlen = b->d_nlen;
+  a.chain = b->d_chain;
+  a.loc = b->d_loc;
+  a.mono = b->d_mono;
+  a.step_base = b->d_step;
+  a.err = b->d_err;
+  return a;
+}
+
+static int nl_rebuild(kgdb_batch* b, bool capture) {
+  const bool prof = b->prof && !capture;
+  if (prof) {
+    if (b->ev_used == PROF_EVENTS) CHK(prof_flush(b));
+    HIPCHK(hipEventRecord(b->ev[4 * b->ev_used + 2], b->s));
+  }
+  launch_nl_rebuild(b->prec, nl_args(b), b->pm.nblk, b->lm[b->nl_ki].nblk, b->s);
+  if (prof) HIPCHK(hipEventRecord(b->ev[4 * b->ev_used + 3], b->s));
+  b->cl = 1 - b->cl;
+  b->rebuild_pending = prof;
+  return 0;
+}
+
+static int nl_step(kgdb_batch* b, int mode, uint32_t s_off, bool capture) {
+  NlArgs a = nl_args(b);
+  a.s_off = s_off;
+  const bool prof = b->prof && !capture && (mode & F_OPEN);
+  if (prof) {
+    if (!b->rebuild_pending) {  // no rebuild before this step: empty rebuild interval
+      if (b->ev_used == PROF_EVENTS) CHK(prof_flush(b));
+      HIPCHK(hipEventRecord(b->ev[4 * b->ev_used + 2], b->s));
+      HIPCHK(hipEventRecord(b->ev[4 * b->ev_used + 3], b->s));
+    }
+    HIPCHK(hipEventRecord(b->ev[4 * b->ev_used], b->s));
+  }
+  launch_nl_step(b->prec, mode, a, b->pm.nblk, b->s);
+  if (prof) {
+    HIPCHK(hipEventRecord(b->ev[4 * b->ev_used + 1], b->s));
+    b->ev_used++;
+    b->rebuild_pending = false;
+  }
+  if (mode & F_OPEN) b->cur = 1 - b->cur;
+  if (!capture) HIPCHK(hipGetLastError());
+  return 0;
+}
+
+static int capture_nl_chunk(kgdb_batch* b, hipGraphExec_t* out) {
+  hipGraph_t g = nullptr;
+  HIPCHK(hipStreamBeginCapture(b->s, hipStreamCaptureModeThreadLocal));
+  int rc = 0;
+  for (int j = 1; j <= GCHUNK && !rc; ++j) {
+    if (j % b->nl_k == 0) rc = nl_rebuild(b, true);
+    if (!rc) rc = nl_step(b, F_CLOSE | F_OPEN, (uint32_t)j, true);
+  }
+  launch_advance(b->d_step, b->nm, GCHUNK, b->s);
+  hipError_t e = hipStreamEndCapture(b->s, &g);
+  if (rc) return rc;
+  if (e != hipSuccess) return fail(KGDB_E_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+  e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+  hipGraphDestroy(g);
+  if (e != hipSuccess) return fail(KGDB_E_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+  return 0;
+}
+
+// one pass of n steps with rebuilds every nl_k steps (before the forces at step s, s % K == 0)
+static int nl_pass(kgdb_batch* b, int64_t n, bool graph) {
+  const int K = b->nl_k;
+  CHK(nl_rebuild(b, false));
+  CHK(nl_step(b, F_OPEN, 0, false));
+  int64_t s = 1;
+  if (graph && !b->prof && GCHUNK % K == 0) {
+    while (n - s >= GCHUNK) {
+      hipGraphExec_t& ge = b->ngexec[b->nl_ki][b->cur][b->cl];
+      if (!ge) CHK(capture_nl_chunk(b, &ge));  // capture flips parities GCHUNK times: net no change
+      HIPCHK(hipGraphLaunch(ge, b->s));
+      s += GCHUNK;
+    }
+  }
+  const int64_t s0 = s;
+  for (; s < n; ++s) {
+    if (s % K == 0) CHK(nl_rebuild(b, false));
+    CHK(nl_step(b, F_CLOSE | F_OPEN, (uint32_t)(s - s0 + 1), false));
+  }
+  if (n - s0 > 0) launch_advance(b->d_step, b->nm, (uint64_t)(n - s0), b->s);
+  if (n % K == 0) CHK(nl_rebuild(b, false));
+  CHK(nl_step(b, F_CLOSE | F_STORE, 1, false));
+  launch_advance(b->d_step, b->nm, 1, b->s);
+  HIPCHK(hipGetLastError());
+  return 0;
+}
+
+static int save_state(kgdb_batch* b, bool back) {
+  const size_t n3 = 3 * (size_t)b->NP;
+  double* f[4] = {b->d_x[b->cur], b->d_v, b->d_fc, b->d_fl};
+  for (int q = 0; q < 4; ++q)
+    HIPCHK(hipMemcpyAsync(back ? f[q] : b->d_save + q * n3, back ? b->d_save + q * n3 : f[q], n3 * sizeof(double),
+                          hipMemcpyDeviceToDevice, b->s));
+  HIPCHK(hipMemcpyAsync(back ? b->d_step : b->d_save_step, back ? b->d_save_step : b->d_step,
+                        b->nm * sizeof(uint64_t), hipMemcpyDeviceToDevice, b->s));
+  return 0;
+}
+
+// Switch the rebuild interval (and with it the list grid).  A rebuild clears the other
+// occupancy buffer only over its own grid's cells, so both buffers are zeroed here in full.
+static int set_nl_interval(kgdb_batch* b, int ki) {
+  b->nl_ki = ki;
+  b->nl_k = NL_KS[ki];
+  b->D = b->Dk[ki];
+  HIPCHK(hipMemcpyAsync(b->d_md, b->D.data(), sizeof(MeltDesc) * b->nm, hipMemcpyHostToDevice, b->s));
+  HIPCHK(hipMemsetAsync(b->d_cntl[0], 0, sizeof(int) * (size_t)b->NCL, b->s));
+  HIPCHK(hipMemsetAsync(b->d_cntl[1], 0, sizeof(int) * (size_t)b->NCL, b->s));
+  return 0;
+}
+
+static int run_steps_cells(kgdb_batch* b, int64_t n, bool graph);
+
 static int run_steps(kgdb_batch* b, int64_t n, bool graph) {
   if (n <= 0) return 0;
+  if (b->nl_ki < 0) return run_steps_cells(b, n, graph);
+  const int cur0 = b->cur;
+  CHK(save_state(b, false));
+  for (;;) {
+    CHK(nl_pass(b, n, graph));
+    if (b->prof) CHK(prof_flush(b));
+    HIPCHK(hipMemcpyAsync(b->h_err, b->d_err, sizeof(uint32_t) * b->nm, hipMemcpyDeviceToHost, b->s));
+    HIPCHK(hipStreamSynchronize(b->s));
+    uint32_t all = 0;
+    for (int k = 0; k < b->nm; ++k) all |= b->h_err[k];
+    if (!(all & ERR_NLIST_STALE) || b->nl_k == 1) break;
+    // a monomer outran the skin: redo the pass with more frequent rebuilds
+    HIPCHK(hipMemsetAsync(b->d_err, 0, sizeof(uint32_t) * b->nm, b->s));
+    b->cur = cur0;
+    CHK(save_state(b, true));
+    CHK(set_nl_interval(b, b->nl_ki - 1));
+    b->nl_rollbacks++;
+  }
+  if (b->nl_k == 1) {  // staleness cannot matter when every force evaluation follows a rebuild
+    for (int k = 0; k < b->nm; ++k) b->h_err[k] &= ~ERR_NLIST_STALE;
+    HIPCHK(hipMemcpyAsync(b->d_err, b->h_err, sizeof(uint32_t) * b->nm, hipMemcpyHostToDevice, b->s));
+  }
+  for (int k = 0; k < b->nm; ++k) b->step[k] += (uint64_t)n;
+  b->fc_valid = true;
+  b->cells_valid = false;
+  CHK(check_errors(b));
+  if (b->reorder) CHK(reorder_storage(b));
+  return 0;
+}
+
+// stepping on the r_c cell grid (used when the box is too small for a list grid of >= 3 cells)
+static int run_steps_cells(kgdb_batch* b, int64_t n, bool graph) {
   CHK(ensure_cells(b));
   CHK(do_step(b, F_OPEN, 0, 0, 0, false));
   int64_t rem = n - 1;
@@ -323,6 +569,10 @@ void kgdb_destroy(kgdb_batch* b) {
   if (b->s) hipStreamSynchronize(b->s);
   for (int p = 0; p < 2; ++p)
     if (b->gexec[p]) hipGraphExecDestroy(b->gexec[p]);
+  for (auto& a1 : b->ngexec)
+    for (auto& a2 : a1)
+      for (auto& ge : a2)
+        if (ge) hipGraphExecDestroy(ge);
   for (auto e : b->ev) hipEventDestroy(e);
   for (void* q : b->allocs) hipFree(q);
   if (b->h_err) hipHostFree(b->h_err);
@@ -331,26 +581,40 @@ void kgdb_destroy(kgdb_batch* b) {
 }
 
 static int build_block_maps(kgdb_batch* b) {
-  std::vector<int> pmelt, pbase, cmelt, cbase;
-  for (int k = 0; k < b->nm; ++k) {
-    for (int i = 0; i < b->D[k].Nm; i += 256) { pmelt.push_back(k); pbase.push_back(i); }
-    const int ncell = b->D[k].nc * b->D[k].nc * b->D[k].nc;
-    for (int i = 0; i < ncell; i += 256) { cmelt.push_back(k); cbase.push_back(i); }
-  }
-  const size_t tot = pmelt.size() * 2 + cmelt.size() * 2;
-  CHK(dalloc(b, &b->d_blk, tot));
+  // per melt: blocks of `per` items; each map is (melt index, first local item) per block
   std::vector<int> all;
-  all.insert(all.end(), pmelt.begin(), pmelt.end());
-  all.insert(all.end(), pbase.begin(), pbase.end());
-  all.insert(all.end(), cmelt.begin(), cmelt.end());
-  all.insert(all.end(), cbase.begin(), cbase.end());
+  std::vector<std::pair<size_t, size_t>> spans;  // (offset of melt[], number of blocks)
+  auto add_map = [&](int per, bool cells) {
+    std::vector<int> melt, base;
+    for (int k = 0; k < b->nm; ++k) {
+      const int n = cells ? b->D[k].nc * b->D[k].nc * b->D[k].nc : b->D[k].Nm;
+      for (int i = 0; i < n; i += per) { melt.push_back(k); base.push_back(i); }
+    }
+    spans.push_back({all.size(), melt.size()});
+    all.insert(all.end(), melt.begin(), melt.end());
+    all.insert(all.end(), base.begin(), base.end());
+  };
+  add_map(256, false);
+  add_map(256 / FIN_LANES, true);
+  for (int G : {1, 2, 4, 8}) add_map(256 / G, false);
+  for (int q = 0; q < 3; ++q) {  // list-grid cells for each rebuild interval
+    std::vector<int> melt, base;
+    for (int k = 0; k < b->nm; ++k) {
+      const int n = b->Dk[q][k].ncl * b->Dk[q][k].ncl * b->Dk[q][k].ncl;
+      for (int i = 0; i < n; i += 256) { melt.push_back(k); base.push_back(i); }
+    }
+    spans.push_back({all.size(), melt.size()});
+    all.insert(all.end(), melt.begin(), melt.end());
+    all.insert(all.end(), base.begin(), base.end());
+  }
+  CHK(dalloc(b, &b->d_blk, all.size()));
   HIPCHK(hipMemcpy(b->d_blk, all.data(), all.size() * sizeof(int), hipMemcpyHostToDevice));
-  b->pm.melt = b->d_blk;
-  b->pm.base = b->d_blk + pmelt.size();
-  b->pm.nblk = (int)pmelt.size();
-  b->cm.melt = b->d_blk + 2 * pmelt.size();
-  b->cm.base = b->d_blk + 2 * pmelt.size() + cmelt.size();
-  b->cm.nblk = (int)cmelt.size();
+  BlockMap* maps[9] = {&b->pm, &b->cm, &b->fm[0], &b->fm[1], &b->fm[2], &b->fm[3], &b->lm[0], &b->lm[1], &b->lm[2]};
+  for (int m = 0; m < 9; ++m) {
+    maps[m]->melt = b->d_blk + spans[m].first;
+    maps[m]->base = b->d_blk + spans[m].first + spans[m].second;
+    maps[m]->nblk = (int)spans[m].second;
+  }
   return 0;
 }
 
@@ -387,6 +651,39 @@ static int init_impl(const kgdb_params* params, int32_t count, void* stream, kgd
     return fail(KGDB_E_PARAM, "batch too large for 32-bit indexing");
   }
   b->NP = (int)NP; b->NC = (int)NC; b->NC13 = (int)NC13;
+  // list-grid geometry for each rebuild interval; pick the requested or the largest usable
+  {
+    int64_t ncl_max = 0;
+    bool usable[3];
+    for (int q = 0; q < 3; ++q) {
+      b->Dk[q] = b->D;
+      int64_t off = 0;
+      usable[q] = true;
+      for (int k = 0; k < count; ++k) {
+        set_list_geometry(b->Dk[q][k], params[k], NL_KS[q]);
+        b->Dk[q][k].celll_off = (int)off;
+        off += (int64_t)b->Dk[q][k].ncl * b->Dk[q][k].ncl * b->Dk[q][k].ncl;
+        if (b->Dk[q][k].ncl < 3 || b->Dk[q][k].ncl > 1023) usable[q] = false;
+      }
+      ncl_max = std::max(ncl_max, off);
+    }
+    if (ncl_max * NL_CELL_CAP >= (1ll << 31)) { delete b; return fail(KGDB_E_PARAM, "list grid too large"); }
+    b->NCL = (int)ncl_max;
+    int want = params[0].nl_every;
+    for (int k = 1; k < count; ++k)
+      if (params[k].nl_every != want) { delete b; return fail(KGDB_E_PARAM, "nl_every differs within the batch"); }
+    int ki = -1;
+    if (want > 0) {
+      for (int q = 0; q < 3; ++q) if (NL_KS[q] == want) ki = q;
+      if (ki < 0) { delete b; return fail(KGDB_E_PARAM, "nl_every must be 1, 2 or 5"); }
+      while (ki >= 0 && !usable[ki]) --ki;
+    } else {
+      ki = 2;
+      while (ki >= 0 && !usable[ki]) --ki;
+    }
+    b->nl_ki = ki;  // -1: stepping on the r_c grid
+    if (ki >= 0) { b->nl_k = NL_KS[ki]; b->D = b->Dk[ki]; }
+  }
   int rc = 0;
   auto step = [&](int r) { if (!rc) rc = r; };
   if (stream) b->s = (hipStream_t)stream;
@@ -415,6 +712,26 @@ static int init_impl(const kgdb_params* params, int32_t count, void* stream, kgd
   }
   step(dalloc(b, &b->d_chain, np));
   step(dalloc(b, &b->d_loc, np));
+  step(dalloc(b, &b->d_mono, np));
+  step(dalloc(b, &b->d_perm, np));
+  step(dalloc(b, &b->d_inv, np));
+  step(dalloc(b, &b->d_tmpi, np));
+  step(dalloc(b, &b->d_tmp3, 3 * np));
+  step(dalloc(b, &b->d_start, (size_t)std::max<int64_t>(NC, b->NCL) + 1));
+  step(dalloc(b, &b->d_cntl[0], (size_t)b->NCL));
+  step(dalloc(b, &b->d_cntl[1], (size_t)b->NCL));
+  step(dalloc(b, &b->d_bucketl, (size_t)b->NCL * NL_CELL_CAP));
+  for (int q = 0; q < 2 && !rc; ++q) {
+    void* r = nullptr;
+    if (hipMalloc(&r, np * rel_bytes(b->prec)) != hipSuccess) rc = fail(KGDB_E_ALLOC, "hipMalloc rel");
+    else { b->allocs.push_back(r); b->d_rel[q] = r; }
+  }
+  step(dalloc(b, &b->d_relb, np));
+  step(dalloc(b, &b->d_refc, np));
+  step(dalloc(b, &b->d_nlist, np * NL_CAP));
+  step(dalloc(b, &b->d_nlen, np));
+  step(dalloc(b, &b->d_save, 12 * np));
+  step(dalloc(b, &b->d_save_step, (size_t)count));
   step(dalloc(b, &b->d_step, (size_t)count));
   step(dalloc(b, &b->d_err, (size_t)count));
   step(dalloc(b, &b->d_out4, 4 * (size_t)count));
@@ -434,6 +751,10 @@ static int init_impl(const kgdb_params* params, int32_t count, void* stream, kgd
     rc = fail(KGDB_E_ALLOC, "hipHostMalloc");
   if (!rc) rc = build_block_maps(b);
   if (rc) { kgdb_destroy(b); return rc; }
+  if (const char* e = std::getenv("KGDB_FORCE_LANES")) {
+    const int l = std::atoi(e);
+    if (l == 1 || l == 2 || l == 4 || l == 8) b->lanes = l;
+  }
   b->step.assign(count, 0);
   b->sweep.assign(count, 0);
   b->last_sweep.assign(count, 0);
@@ -446,7 +767,15 @@ static int init_impl(const kgdb_params* params, int32_t count, void* stream, kgd
   hip(hipMemsetAsync(b->d_err, 0, sizeof(uint32_t) * count, b->s), "err");
   hip(hipMemsetAsync(b->d_fl, 0, sizeof(double) * 3 * np, b->s), "fl");
   hip(hipMemsetAsync(b->d_fc, 0, sizeof(double) * 3 * np, b->s), "fc");
+  hip(hipMemsetAsync(b->d_cntl[0], 0, sizeof(int) * (size_t)b->NCL, b->s), "cntl");
+  hip(hipMemsetAsync(b->d_cntl[1], 0, sizeof(int) * (size_t)b->NCL, b->s), "cntl");
   if (rc) { kgdb_destroy(b); return rc; }
+  {
+    std::vector<int> mono(np);
+    for (int k = 0; k < count; ++k)
+      for (int i = 0; i < b->D[k].Nm; ++i) mono[b->D[k].off + i] = i;
+    hip(hipMemcpy(b->d_mono, mono.data(), sizeof(int) * np, hipMemcpyHostToDevice), "mono");
+  }
   launch_random_walks(b->d_md, count, b->max_M, b->NP, b->d_x[0], b->d_chain, b->d_loc, b->s);
   launch_velocities(b->d_md, b->pm, b->NP, b->d_v, b->s);
   launch_remove_mean(b->d_md, count, b->NP, b->d_v, b->s);
@@ -479,22 +808,39 @@ static int check_melt(const kgdb_batch* b, int32_t melt) {
   return 0;
 }
 
+// storage slot -> monomer id (local) of melt `melt`
+static int melt_mono(kgdb_batch* b, int32_t melt, std::vector<int>& mono) {
+  const MeltDesc& d = b->D[melt];
+  mono.resize(d.Nm);
+  HIPCHK(hipMemcpy(mono.data(), b->d_mono + d.off, sizeof(int) * d.Nm, hipMemcpyDeviceToHost));
+  return 0;
+}
+
+// copy a [3][NP] slot-ordered device array of melt `melt` to a [3][Nm] id-ordered host array
+static int download_by_id(kgdb_batch* b, int32_t melt, const double* dev, double* out, const std::vector<int>& mono) {
+  const MeltDesc& d = b->D[melt];
+  std::vector<double> tmp(d.Nm);
+  for (int c = 0; c < 3; ++c) {
+    HIPCHK(hipMemcpy(tmp.data(), dev + (size_t)c * b->NP + d.off, sizeof(double) * d.Nm, hipMemcpyDeviceToHost));
+    for (int s = 0; s < d.Nm; ++s) out[(size_t)c * d.Nm + mono[s]] = tmp[s];
+  }
+  return 0;
+}
+
 int kgdb_get_state(kgdb_batch* b, int32_t melt, double* x, double* v, double* fc, double* fl, int32_t* chains,
                    uint64_t* counters) {
   CHK(check_melt(b, melt));
   const MeltDesc& d = b->D[melt];
-  const size_t nb = sizeof(double) * d.Nm;
   HIPCHK(hipStreamSynchronize(b->s));
-  for (int c = 0; c < 3; ++c) {
-    const size_t o = (size_t)c * b->NP + d.off;
-    if (x) HIPCHK(hipMemcpy(x + (size_t)c * d.Nm, b->d_x[b->cur] + o, nb, hipMemcpyDeviceToHost));
-    if (v) HIPCHK(hipMemcpy(v + (size_t)c * d.Nm, b->d_v + o, nb, hipMemcpyDeviceToHost));
-    if (fc) HIPCHK(hipMemcpy(fc + (size_t)c * d.Nm, b->d_fc + o, nb, hipMemcpyDeviceToHost));
-    if (fl) HIPCHK(hipMemcpy(fl + (size_t)c * d.Nm, b->d_fl + o, nb, hipMemcpyDeviceToHost));
-  }
+  std::vector<int> mono;
+  CHK(melt_mono(b, melt, mono));
+  if (x) CHK(download_by_id(b, melt, b->d_x[b->cur], x, mono));
+  if (v) CHK(download_by_id(b, melt, b->d_v, v, mono));
+  if (fc) CHK(download_by_id(b, melt, b->d_fc, fc, mono));
+  if (fl) CHK(download_by_id(b, melt, b->d_fl, fl, mono));
   if (chains) {
     HIPCHK(hipMemcpy(chains, b->d_chain + d.off, sizeof(int) * d.Nm, hipMemcpyDeviceToHost));
-    for (int i = 0; i < d.Nm; ++i) chains[i] -= d.off;
+    for (int i = 0; i < d.Nm; ++i) chains[i] = mono[chains[i] - d.off];
   }
   if (counters) {
     counters[0] = b->step[melt];
@@ -505,6 +851,8 @@ int kgdb_get_state(kgdb_batch* b, int32_t melt, double* x, double* v, double* fc
   return 0;
 }
 
+// Writes melt `melt` in monomer-id storage order (slot = id); fields not given are
+// carried over into that order.
 int kgdb_set_state(kgdb_batch* b, int32_t melt, const double* x, const double* v, const double* fl,
                    const int32_t* chains, const uint64_t* counters) {
   CHK(check_melt(b, melt));
@@ -516,21 +864,35 @@ int kgdb_set_state(kgdb_batch* b, int32_t melt, const double* x, const double* v
       if (chains[i] < 0 || chains[i] >= d.Nm || seen[chains[i]]) return fail(KGDB_E_STATE, "chain table is not a permutation");
       seen[chains[i]] = 1;
     }
-    std::vector<int> g(d.Nm), loc(d.Nm);
-    for (int i = 0; i < d.Nm; ++i) { g[i] = chains[i] + d.off; loc[chains[i]] = i; }
-    HIPCHK(hipMemcpy(b->d_chain + d.off, g.data(), sizeof(int) * d.Nm, hipMemcpyHostToDevice));
-    HIPCHK(hipMemcpy(b->d_loc + d.off, loc.data(), sizeof(int) * d.Nm, hipMemcpyHostToDevice));
   }
+  // current state in id order, overwritten by the given fields
+  std::vector<int> mono;
+  CHK(melt_mono(b, melt, mono));
+  const size_t n3 = 3 * (size_t)d.Nm;
+  std::vector<double> hx(n3), hv(n3), hfc(n3), hfl(n3);
+  std::vector<int> ch(d.Nm);
+  CHK(download_by_id(b, melt, b->d_x[b->cur], hx.data(), mono));
+  CHK(download_by_id(b, melt, b->d_v, hv.data(), mono));
+  CHK(download_by_id(b, melt, b->d_fc, hfc.data(), mono));
+  CHK(download_by_id(b, melt, b->d_fl, hfl.data(), mono));
+  HIPCHK(hipMemcpy(ch.data(), b->d_chain + d.off, sizeof(int) * d.Nm, hipMemcpyDeviceToHost));
+  for (int i = 0; i < d.Nm; ++i) ch[i] = mono[ch[i] - d.off];
+  if (chains) std::memcpy(ch.data(), chains, sizeof(int) * d.Nm);
+  if (x) for (size_t i = 0; i < n3; ++i) hx[i] = host_wrap(x[i], d.L);
+  if (v) std::memcpy(hv.data(), v, sizeof(double) * n3);
+  if (fl) std::memcpy(hfl.data(), fl, sizeof(double) * n3);
+  std::vector<int> g(d.Nm), loc(d.Nm), id(d.Nm);
+  for (int i = 0; i < d.Nm; ++i) { g[i] = ch[i] + d.off; loc[ch[i]] = i; id[i] = i; }
+  HIPCHK(hipMemcpy(b->d_chain + d.off, g.data(), sizeof(int) * d.Nm, hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(b->d_loc + d.off, loc.data(), sizeof(int) * d.Nm, hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(b->d_mono + d.off, id.data(), sizeof(int) * d.Nm, hipMemcpyHostToDevice));
   const size_t nb = sizeof(double) * d.Nm;
-  std::vector<double> tmp(d.Nm);
   for (int c = 0; c < 3; ++c) {
-    const size_t o = (size_t)c * b->NP + d.off;
-    if (x) {
-      for (int i = 0; i < d.Nm; ++i) tmp[i] = host_wrap(x[(size_t)c * d.Nm + i], d.L);
-      HIPCHK(hipMemcpy(b->d_x[b->cur] + o, tmp.data(), nb, hipMemcpyHostToDevice));
-    }
-    if (v) HIPCHK(hipMemcpy(b->d_v + o, v + (size_t)c * d.Nm, nb, hipMemcpyHostToDevice));
-    if (fl) HIPCHK(hipMemcpy(b->d_fl + o, fl + (size_t)c * d.Nm, nb, hipMemcpyHostToDevice));
+    const size_t o = (size_t)c * b->NP + d.off, h = (size_t)c * d.Nm;
+    HIPCHK(hipMemcpy(b->d_x[b->cur] + o, hx.data() + h, nb, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(b->d_v + o, hv.data() + h, nb, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(b->d_fc + o, hfc.data() + h, nb, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(b->d_fl + o, hfl.data() + h, nb, hipMemcpyHostToDevice));
   }
   if (counters) {
     b->step[melt] = counters[0];
@@ -549,15 +911,19 @@ int kgdb_forces(kgdb_batch* b, int32_t melt, double* F, double* S, double* E3) {
   CHK(ensure_cells(b));
   ForceArgs a = force_args(b);
   a.fc = b->d_diagF;
-  launch_force(b->prec, F_DIAG, a, b->pm.nblk, b->s);
+  launch_force(b->prec, F_DIAG, b->lanes, a, force_blocks(b), b->s);
   launch_reduce_melt(b->d_md, b->nm, b->NP, b->d_E, b->d_v, b->d_out4, b->s);
   HIPCHK(hipGetLastError());
   CHK(check_errors(b));
   const MeltDesc& d = b->D[melt];
-  for (int c = 0; c < 3 && F; ++c)
-    HIPCHK(hipMemcpy(F + (size_t)c * d.Nm, b->d_diagF + (size_t)c * b->NP + d.off, sizeof(double) * d.Nm,
-                     hipMemcpyDeviceToHost));
-  if (S) HIPCHK(hipMemcpy(S, b->d_S + d.off, sizeof(double) * d.Nm, hipMemcpyDeviceToHost));
+  std::vector<int> mono;
+  CHK(melt_mono(b, melt, mono));
+  if (F) CHK(download_by_id(b, melt, b->d_diagF, F, mono));
+  if (S) {
+    std::vector<double> tmp(d.Nm);
+    HIPCHK(hipMemcpy(tmp.data(), b->d_S + d.off, sizeof(double) * d.Nm, hipMemcpyDeviceToHost));
+    for (int s2 = 0; s2 < d.Nm; ++s2) S[mono[s2]] = tmp[s2];
+  }
   if (E3) {
     double o4[4];
     HIPCHK(hipMemcpy(o4, b->d_out4 + 4 * melt, sizeof o4, hipMemcpyDeviceToHost));
@@ -571,7 +937,7 @@ int kgdb_energy(kgdb_batch* b, int32_t melt, double out[4]) {
   CHK(ensure_cells(b));
   ForceArgs a = force_args(b);
   a.fc = b->d_diagF;
-  launch_force(0, F_DIAG | F_EXACT, a, b->pm.nblk, b->s);  // FP64 from the master positions
+  launch_force(0, F_DIAG | F_EXACT, b->lanes, a, force_blocks(b), b->s);  // FP64 from the master positions
   launch_reduce_melt(b->d_md, b->nm, b->NP, b->d_E, b->d_v, b->d_out4, b->s);
   HIPCHK(hipGetLastError());
   CHK(check_errors(b));
@@ -593,11 +959,18 @@ int kgdb_cell_list(kgdb_batch* b, int32_t melt, int32_t* nc, int32_t* cell_start
   HIPCHK(hipMemcpy(cnt.data(), b->d_cnt[b->cur] + d.cell_off, sizeof(int) * ncell, hipMemcpyDeviceToHost));
   HIPCHK(hipMemcpy(bucket.data(), b->d_bucket + (size_t)d.cell_off * CELL_CAP, sizeof(int) * bucket.size(),
                    hipMemcpyDeviceToHost));
+  std::vector<int> mono;
+  CHK(melt_mono(b, melt, mono));
   int pos = 0;
   for (int c = 0; c < ncell; ++c) {
     if (cell_start) cell_start[c] = pos;
-    for (int j = 0; j < cnt[c]; ++j, ++pos)
-      if (sorted_ids) sorted_ids[pos] = bucket[(size_t)c * CELL_CAP + j] - d.off;
+    const int n = cnt[c];
+    if (sorted_ids) {
+      // buckets hold storage slots; the exported list holds monomer ids, ascending per cell
+      for (int j = 0; j < n; ++j) sorted_ids[pos + j] = mono[bucket[(size_t)c * CELL_CAP + j] - d.off];
+      std::sort(sorted_ids + pos, sorted_ids + pos + n);
+    }
+    pos += n;
   }
   if (cell_start) cell_start[ncell] = pos;
   return 0;
@@ -834,6 +1207,104 @@ int kgdb_profile_read(kgdb_batch* b, double* force_ms, int64_t* force_n, double*
   if (fin_n) *fin_n = b->prof_fin_n;
   b->prof_force_ms = b->prof_fin_ms = 0;
   b->prof_force_n = b->prof_fin_n = 0;
+  return 0;
+}
+
+static void drop_graphs(kgdb_batch* b) {
+  for (int p = 0; p < 2; ++p)
+    if (b->gexec[p]) { hipGraphExecDestroy(b->gexec[p]); b->gexec[p] = nullptr; }
+}
+
+// Neighbour-list rebuild interval K: nl_every > 0 sets it (1, 2 or 5); nl_every == 0 times
+// each usable interval over `reps` steps with HIP events (step kernel + rebuilds) and keeps
+// the fastest.  The state is restored afterwards, so tuning does not advance the run.
+int kgdb_autotune(kgdb_batch* b, int32_t nl_every, int32_t reps, int32_t* chosen, double* ms_per_variant) {
+  if (!b) return fail(KGDB_E_PARAM, "bad handle");
+  if (b->nl_ki < 0) {  // box too small for a list grid: nothing to tune
+    if (chosen) *chosen = 0;
+    return 0;
+  }
+  auto usable = [&](int q) {
+    for (int k = 0; k < b->nm; ++k)
+      if (b->Dk[q][k].ncl < 3) return false;
+    return true;
+  };
+  if (nl_every > 0) {
+    int q = -1;
+    for (int i = 0; i < 3; ++i) if (NL_KS[i] == nl_every) q = i;
+    if (q < 0 || !usable(q)) return fail(KGDB_E_PARAM, "nl_every must be a usable 1, 2 or 5");
+    CHK(set_nl_interval(b, q));
+    if (chosen) *chosen = b->nl_k;
+    return 0;
+  }
+  if (reps < 1) reps = 20;
+  if (b->ev.empty()) {
+    b->ev.resize(4 * PROF_EVENTS);
+    for (auto& e : b->ev) HIPCHK(hipEventCreate(&e));
+  }
+  const size_t n3 = 3 * (size_t)b->NP;
+  double* sx = nullptr;
+  uint64_t* sst = nullptr;
+  HIPCHK(hipMalloc(&sx, 4 * n3 * sizeof(double)));
+  HIPCHK(hipMalloc(&sst, b->nm * sizeof(uint64_t)));
+  auto copy_state = [&](bool back) {
+    double* f[4] = {b->d_x[b->cur], b->d_v, b->d_fc, b->d_fl};
+    for (int q = 0; q < 4; ++q)
+      (void)hipMemcpyAsync(back ? f[q] : sx + q * n3, back ? sx + q * n3 : f[q], n3 * sizeof(double),
+                           hipMemcpyDeviceToDevice, b->s);
+    (void)hipMemcpyAsync(back ? b->d_step : sst, back ? sst : b->d_step, b->nm * sizeof(uint64_t),
+                         hipMemcpyDeviceToDevice, b->s);
+  };
+  const bool was_reorder = b->reorder, was_fc = b->fc_valid, was_prof = b->prof;
+  const int was_cur = b->cur;
+  const std::vector<uint64_t> was_step = b->step;
+  b->reorder = false;
+  copy_state(false);
+  double best = INFINITY;
+  int best_q = b->nl_ki, rc = 0;
+  for (int q = 0; q < 3 && !rc; ++q) {
+    if (ms_per_variant) ms_per_variant[q] = 0;
+    if (!usable(q)) continue;
+    rc = set_nl_interval(b, q);
+    if (rc) break;
+    b->prof = true;
+    b->prof_force_ms = b->prof_fin_ms = 0;
+    b->prof_force_n = b->prof_fin_n = 0;
+    rc = run_steps(b, reps, false);
+    b->prof = was_prof;
+    const double ms = b->prof_force_n ? (b->prof_force_ms + b->prof_fin_ms) / b->prof_force_n : INFINITY;
+    if (ms_per_variant) ms_per_variant[q] = ms;
+    if (!rc && b->nl_ki == q && ms < best) { best = ms; best_q = q; }  // a rollback disqualifies
+    b->cur = was_cur;
+    copy_state(true);
+    b->step = was_step;
+    b->cells_valid = false;
+    b->fc_valid = was_fc;
+  }
+  (void)hipStreamSynchronize(b->s);
+  (void)hipFree(sx);
+  (void)hipFree(sst);
+  b->reorder = was_reorder;
+  b->prof_force_ms = b->prof_fin_ms = 0;
+  b->prof_force_n = b->prof_fin_n = 0;
+  CHK(set_nl_interval(b, best_q));
+  if (chosen) *chosen = b->nl_k;
+  return rc;
+}
+
+// neighbour-list state: out = {rebuild interval K, skin, mean list length, rollbacks so far}
+int kgdb_nl_info(kgdb_batch* b, double out[4]) {
+  if (!b || !out) return fail(KGDB_E_PARAM, "bad arguments");
+  if (b->nl_ki < 0) { out[0] = out[1] = out[2] = 0; out[3] = 0; return 0; }
+  std::vector<int> len(b->NP);
+  HIPCHK(hipStreamSynchronize(b->s));
+  HIPCHK(hipMemcpy(len.data(), b->d_nlen, sizeof(int) * b->NP, hipMemcpyDeviceToHost));
+  double sum = 0;
+  for (int v : len) sum += v;
+  out[0] = b->nl_k;
+  out[1] = nl_skin_for(b->P[0], b->nl_k);
+  out[2] = sum / b->NP;
+  out[3] = (double)b->nl_rollbacks;
   return 0;
 }
 

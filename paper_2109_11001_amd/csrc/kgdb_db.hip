@@ -242,7 +242,9 @@ __device__ void count_touching(const MeltDesc& d, const Topo& T, const DbArgs& a
                                uint64_t* s_new, uint32_t* s_err) {
   const int N = d.N;
   int local = 0;
-  for (int idx = threadIdx.x; idx < 2 * N; idx += blockDim.x) {
+  // the last wavefront computes Delta E meanwhile and takes no part in the scan
+  const int nscan = (int)blockDim.x - 64;
+  for (int idx = threadIdx.x; idx < 2 * N && (int)threadIdx.x < nscan; idx += nscan) {
     const int X = idx < N ? A : B;
     const int p = (idx < N ? idx : idx - N) + 1;
     const int u = T.at(X, p);
@@ -305,6 +307,8 @@ __global__ __launch_bounds__(DB_BLOCK) void k_db_sweep(DbArgs a) {
   __shared__ uint32_t s_err;
   __shared__ Move s_mv;
   __shared__ int s_accept;
+  __shared__ int s_rev;
+  __shared__ int s_phase;
   __shared__ double s_dE;
   __shared__ double s_u;
 
@@ -357,36 +361,62 @@ __global__ __launch_bounds__(DB_BLOCK) void k_db_sweep(DbArgs a) {
     }
     __syncthreads();
     const Move mv = s_mv;
-    // candidates involving A or B now: from the list
+    // candidates involving A or B now (from the list); Delta E and the reverse-move test on
+    // the last wavefront meanwhile
     int mine = 0;
     for (int t = threadIdx.x; t < n; t += blockDim.x) mine += touches(s_keys[t], M, N, mv.A, mv.B) ? 1 : 0;
     if (mine) atomicAdd(&s_cnt[2], mine);
-    // ... and after the move: scanned, keys kept for a commit
-    Topo Tn{a.chain, a.loc, d.off, N, mv};
-    count_touching(d, Tn, a, mv.A, mv.B, s_cnt, s_new, &s_err);
-    if (a.debug) {
+    if (threadIdx.x >= blockDim.x - 64) {
+      // one junction per lane: old A, old B, new A, new B; summed in that order
+      const int l = threadIdx.x - (blockDim.x - 64);
+      double e = 0.0;
+      if (l < 4) {
+        const Topo T{a.chain, a.loc, d.off, N, l < 2 ? Move{mv.A, mv.i, mv.B, mv.j, -1} : mv};
+        e = (l & 1) ? junction_energy(d, T, a.x, a.NP, mv.B, mv.j) : junction_energy(d, T, a.x, a.NP, mv.A, mv.i);
+      } else if (l == 4) {
+        const Topo To{a.chain, a.loc, d.off, N, {mv.A, mv.i, mv.B, mv.j, -1}};
+        s_rev = dist2(a.x, a.NP, d.L, To.at(mv.A, mv.i), To.at(mv.A, mv.i + 1)) <= d.rmax2 &&
+                dist2(a.x, a.NP, d.L, To.at(mv.B, mv.j), To.at(mv.B, mv.j + 1)) <= d.rmax2;
+      }
+      const double e1 = __shfl(e, 1, 64), e2 = __shfl(e, 2, 64), e3 = __shfl(e, 3, 64);
+      if (l == 0) s_dE = (e2 + e3) - (e + e1);
+    } else if (a.debug) {
       Topo To{a.chain, a.loc, d.off, N, {mv.A, mv.i, mv.B, mv.j, -1}};
       count_touching(d, To, a, mv.A, mv.B, s_cnt + 3, nullptr, &s_err);
     }
-    if (threadIdx.x == 0) s_dE = move_dE(d, a.chain, a.loc, a.x, a.NP, mv);
+    __syncthreads();
+    // Decide what can be decided without |C(x')|.  The reverse move is a candidate of x'
+    // whenever it is allowed, so |C(x')| >= |C| - |C_AB(x)| + 1 bounds the Hastings ratio
+    // from above; a draw above that bound rejects exactly as the full ratio would.
+    if (threadIdx.x == 0) {
+      const int old_ab = s_cnt[2];
+      if (a.debug && s_cnt[3] != old_ab) s_err |= ERR_DB_MISMATCH;
+      const double dE = s_dE;
+      st->attempts++;
+      st->sum_ncand += n;
+      int phase = 1;  // 0 reject, 1 count, 2 accept (count only for the commit)
+      if (d.proposal == KGDB_PROPOSAL_LITERAL) {
+        phase = (s_u < exp(-dE / d.T)) ? 2 : 0;
+      } else if (!s_rev) {
+        st->reverse_impossible++;
+        phase = 0;
+      } else if (!(s_u < exp(-dE / d.T) * (double)n / (double)(n - old_ab + 1))) {
+        phase = 0;
+      }
+      s_phase = phase;
+    }
+    __syncthreads();
+    if (s_phase == 0) continue;
+    {
+      Topo Tn{a.chain, a.loc, d.off, N, mv};
+      if ((int)threadIdx.x < (int)blockDim.x - 64) count_touching(d, Tn, a, mv.A, mv.B, s_cnt, s_new, &s_err);
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
       const int old_ab = s_cnt[2], new_ab = s_cnt[0];
       const int n_new = n - old_ab + new_ab;
-      if (a.debug && s_cnt[3] != old_ab) s_err |= ERR_DB_MISMATCH;
       const double dE = s_dE;
-      double ratio;
-      if (d.proposal == KGDB_PROPOSAL_LITERAL) {
-        ratio = exp(-dE / d.T);
-      } else {
-        const Topo To{a.chain, a.loc, d.off, N, {mv.A, mv.i, mv.B, mv.j, -1}};
-        const bool rev_ok = dist2(a.x, a.NP, d.L, To.at(mv.A, mv.i), To.at(mv.A, mv.i + 1)) <= d.rmax2 &&
-                            dist2(a.x, a.NP, d.L, To.at(mv.B, mv.j), To.at(mv.B, mv.j + 1)) <= d.rmax2;
-        if (!rev_ok) { st->reverse_impossible++; ratio = 0.0; }
-        else ratio = exp(-dE / d.T) * (double)n / (double)n_new;
-      }
-      st->attempts++;
-      st->sum_ncand += n;
+      const double ratio = (s_phase == 2) ? 2.0 : exp(-dE / d.T) * (double)n / (double)n_new;
       // capacities of the merge: kept keys sit below the sorted new keys in the scratch half
       const int acc = (s_u < ratio) && (s_cnt[1] <= DB_NEW_CAP) && (n_new <= DB_CAND_CAP) &&
                       (n - old_ab <= DB_CAND_CAP - DB_NEW_CAP);

@@ -13,6 +13,8 @@ constexpr int DB_CELL_CAP = 64;   // monomers per cell of the double-bridging gr
 constexpr int DB_NBR_CAP = 64;    // monomers within db_rmax of one monomer
 constexpr int DB_CAND_CAP = 3072; // candidate keys per melt (held in LDS during a sweep)
 constexpr int DB_NEW_CAP = 1024;  // candidates touching the two chains of one move
+constexpr int NL_CELL_CAP = 32;   // monomers per cell of the neighbour-list grid
+constexpr int NL_CAP = 64;        // neighbour-list entries per monomer
 
 // device error bits (per melt)
 enum : uint32_t {
@@ -22,6 +24,8 @@ enum : uint32_t {
   ERR_NBR_OVERFLOW = 8u,
   ERR_CAND_OVERFLOW = 16u,
   ERR_DB_MISMATCH = 32u,
+  ERR_NLIST_OVERFLOW = 64u,
+  ERR_NLIST_STALE = 128u,  // a monomer moved more than skin/2 since the last list rebuild
 };
 
 // Philox counter word 2: the random-number stream
@@ -47,6 +51,12 @@ struct MeltDesc {
   double T, gamma, dt;
   double warm_dt0, warm_cap, warm_fcap;
   double rmax2;              // (db_rmax)^2
+  // neighbour lists: grid of cells >= r_list = r_c + skin
+  int celll_off, ncl;        // first global cell, cells per side
+  double cinvl, hl;          // ncl / L, L / ncl
+  double rlist2, half_skin2; // r_list^2, (skin / 2)^2
+  double invN;               // 1 / N
+  double lang_amp;           // sqrt(2 gamma T / dt)
   uint64_t seed, melt_id;    // Philox key
   uint32_t test_flags;
   int pad;
@@ -81,10 +91,12 @@ __device__ __forceinline__ double u01(uint64_t r) { return (double)(r >> 11) * 0
 __device__ __forceinline__ double u01_open0(uint64_t r) { return (double)((r >> 11) + 1) * 0x1.0p-53; }
 // Box-Muller: two normals from two words
 __device__ __forceinline__ void gauss2(uint64_t a, uint64_t b, double& z0, double& z1) {
+  // cos(2 pi u), sin(2 pi u) through sincospi(2u): no range reduction of a rounded 2 pi u
   double rad = sqrt(-2.0 * log(u01_open0(a)));
-  double ph = 6.283185307179586 * u01(b);
-  z0 = rad * cos(ph);
-  z1 = rad * sin(ph);
+  double sn, cs;
+  sincospi(2.0 * u01(b), &sn, &cs);
+  z0 = rad * cs;
+  z1 = rad * sn;
 }
 // exact integer in [0,K): high word of r*K
 __device__ __forceinline__ uint64_t rng_choice(uint64_t r, uint64_t K) { return __umul64hi(r, K); }

@@ -7,6 +7,11 @@ namespace kgdb {
 
 struct MeltDesc;
 
+// lanes that cooperate on one cell in the cell finalisation (blocks of 256 threads); the
+// fused force kernel is built for 1, 2, 4 or 8 lanes per monomer (chosen at run time)
+constexpr int FIN_LANES = 4;
+constexpr int FORCE_LANES_DEFAULT = 4;
+
 // logical block -> (melt, first local index) for kernels over monomers or cells
 struct BlockMap {
   const int* melt = nullptr;
@@ -41,6 +46,7 @@ struct ForceArgs {
   int* bucket;           // bucket ids: sorted ones of the current cells are read only with F_EXACT
   const int* chain;      // chain tables: global monomer id at (melt, chain, position)
   const int* loc;        // chain * N + position of each monomer (local to its melt)
+  const int* mono;       // monomer id (local to its melt) held in each storage slot
   const uint64_t* step_base;
   uint32_t* err;
   double* outS;
@@ -53,10 +59,49 @@ void launch_bin(const MeltDesc* md, const BlockMap& pm, int NP, const double* x,
                 int* bucket, uint32_t* err, hipStream_t s);
 void launch_finalize(int prec, const MeltDesc* md, const BlockMap& cm, int NP, const double* x, const int* cnt,
                      int* bucket, void* spos, int* cnt_clear, hipStream_t s);
-void launch_force(int prec, int mode, const ForceArgs& a, int nblk, hipStream_t s);
+void launch_force(int prec, int mode, int lanes, const ForceArgs& a, int nblk, hipStream_t s);
 void launch_advance(uint64_t* step_base, int nm, uint64_t n, hipStream_t s);
 void launch_fill_i32(int* p, int n, int v, hipStream_t s);
 size_t spos_bytes(int prec);
+// renumbering of storage slots in cell order: perm[new] = old, inv[old] = new
+void launch_perm_cells(const int* cnt, const int* bucket, int cap, int NC, int* start, int* perm, int* inv,
+                       hipStream_t s);
+void launch_gather_f64x3(double* dst, const double* src, const int* perm, int NP, hipStream_t s);
+void launch_gather_i32(int* dst, const int* src, const int* perm, int NP, hipStream_t s);
+void launch_remap_i32(int* a, const int* inv, int NP, hipStream_t s);
+
+// ---- neighbour-list MD step (kgdb_nl.hip)
+struct NlArgs {
+  const MeltDesc* md;
+  const int* pblk_melt;  // monomer blocks (256 per block)
+  const int* pblk_base;
+  const int* cblk_melt;  // list-grid cell blocks (256 per block)
+  const int* cblk_base;
+  int NP;
+  const double* x;
+  double* xn;
+  double* v;
+  double* fc;
+  double* fl;
+  int* cnt;        // list-grid occupancy being filled
+  int* cnt_clear;  // the other occupancy buffer (cleared by the rebuild)
+  int* bucket;
+  void* rel_cur;   // reference-cell-relative positions (force precision, 4 per monomer)
+  void* rel_next;
+  float4* relb;    // relative positions at the last rebuild
+  int* refc;       // packed reference cell of each monomer
+  uint32_t* nlist; // [NL_CAP][NP]: (slot << 5) | cell-offset code
+  int* nlen;
+  const int* chain;
+  const int* loc;
+  const int* mono;
+  const uint64_t* step_base;
+  uint32_t* err;
+  uint32_t s_off;
+};
+void launch_nl_rebuild(int prec, const NlArgs& a, int pblk, int cblk, hipStream_t s);
+void launch_nl_step(int prec, int mode, const NlArgs& a, int pblk, hipStream_t s);
+size_t rel_bytes(int prec);
 
 // ---- init and observables (kgdb_obs.hip)
 void launch_random_walks(const MeltDesc* md, int nm, int max_M, int NP, double* x, int* chain, int* loc,

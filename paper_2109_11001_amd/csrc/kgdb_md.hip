@@ -42,34 +42,22 @@ __global__ __launch_bounds__(256) void k_bin(const MeltDesc* __restrict__ md,
 }
 
 // ---------------------------------------------------------------------------------------
-// Per cell: order the bucket by monomer id (rank by counting: ids are unique), write the
-// cell-relative coordinates x - c h in the force precision, and clear the other count
-// buffer for the next binning.
+// Per cell (FIN_LANES lanes per cell): order the bucket by monomer id (rank by counting:
+// ids are unique), write the cell-relative coordinates x - c h in the force precision, and
+// clear the other occupancy buffer for the next binning.  The bucket's first 8 ids are
+// loaded without waiting for the occupancy (they lie inside the bucket either way).
 // ---------------------------------------------------------------------------------------
-// rank-by-counting sort of one bucket held in registers (CAPT = compile-time bound)
-template <typename R, int CAPT>
-__device__ __forceinline__ void finalize_cell(int n, int base, int NP, const double* __restrict__ x, double ox,
-                                              double oy, double oz, int* __restrict__ bucket,
-                                              SPos<R>* __restrict__ spos) {
-  int ids[CAPT];
-#pragma unroll
-  for (int j = 0; j < CAPT; ++j) ids[j] = (j < n) ? bucket[base + j] : 0x7fffffff;
-#pragma unroll
-  for (int j = 0; j < CAPT; ++j) {
-    if (j < n) {
-      int r = 0;
-#pragma unroll
-      for (int m = 0; m < CAPT; ++m) r += (ids[m] < ids[j]) ? 1 : 0;
-      const int id = ids[j];
-      bucket[base + r] = id;
-      SPos<R> p;
-      p.x = (R)(x[id] - ox);
-      p.y = (R)(x[NP + id] - oy);
-      p.z = (R)(x[2 * NP + id] - oz);
-      p.id = id;
-      spos[base + r] = p;
-    }
-  }
+template <typename R>
+__device__ __forceinline__ void put_record(int id, int slot, int NP, const double* __restrict__ x, double ox,
+                                           double oy, double oz, int* __restrict__ bucket,
+                                           SPos<R>* __restrict__ spos) {
+  bucket[slot] = id;
+  SPos<R> p;
+  p.x = (R)(x[id] - ox);
+  p.y = (R)(x[NP + id] - oy);
+  p.z = (R)(x[2 * NP + id] - oz);
+  p.id = id;
+  spos[slot] = p;
 }
 
 template <typename R>
@@ -83,18 +71,50 @@ __global__ __launch_bounds__(256) void k_finalize(const MeltDesc* __restrict__ m
   const int k = __builtin_amdgcn_readfirstlane(blk_melt[lb]);
   const MeltDesc& d = md[k];
   const int nc = d.nc;
-  const int lc = blk_base[lb] + (int)threadIdx.x;
+  const int sub = threadIdx.x & (FIN_LANES - 1);
+  const int lc = blk_base[lb] + (int)(threadIdx.x / FIN_LANES);
   if (lc >= nc * nc * nc) return;
   const int c = d.cell_off + lc;
-  cnt_clear[c] = 0;
+  const int base = c * CELL_CAP;
+  int ids[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) ids[j] = bucket[base + j];
   int n = cnt[c];
+  if (sub == 0) cnt_clear[c] = 0;
   if (n > CELL_CAP) n = CELL_CAP;
   if (n == 0) return;
-  const int base = c * CELL_CAP;
   const int cx = lc % nc, cy = (lc / nc) % nc, cz = lc / (nc * nc);
   const double ox = cx * d.h, oy = cy * d.h, oz = cz * d.h;
-  if (n <= 8) finalize_cell<R, 8>(n, base, NP, x, ox, oy, oz, bucket, spos);
-  else finalize_cell<R, CELL_CAP>(n, base, NP, x, ox, oy, oz, bucket, spos);
+  if (n <= 8) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+      if (j >= n) ids[j] = 0x7fffffff;
+    // every rank depends on all ids, so all loads complete before any lane stores
+#pragma unroll
+    for (int j = sub; j < 8; j += FIN_LANES) {
+      if (j < n) {
+        int r = 0;
+#pragma unroll
+        for (int m = 0; m < 8; ++m) r += (ids[m] < ids[j]) ? 1 : 0;
+        put_record<R>(ids[j], base + r, NP, x, ox, oy, oz, bucket, spos);
+      }
+    }
+  } else if (sub == 0) {
+    int all[CELL_CAP];
+#pragma unroll
+    for (int j = 0; j < CELL_CAP; ++j) all[j] = (j < n) ? bucket[base + j] : 0x7fffffff;
+    int rk[CELL_CAP];
+#pragma unroll
+    for (int j = 0; j < CELL_CAP; ++j) {
+      int r = 0;
+#pragma unroll
+      for (int m = 0; m < CELL_CAP; ++m) r += (all[m] < all[j]) ? 1 : 0;
+      rk[j] = r;
+    }
+#pragma unroll
+    for (int j = 0; j < CELL_CAP; ++j)
+      if (j < n) put_record<R>(all[j], base + rk[j], NP, x, ox, oy, oz, bucket, spos);
+  }
 }
 
 template <typename R> struct V3 { R x, y, z; };
@@ -108,20 +128,39 @@ __device__ __forceinline__ R pair_coef(R r2, R pa, R pb, int nh, R n_half, R& sn
   return (pa * sn - pb * s6) * s2;
 }
 
+template <int G, typename T>
+__device__ __forceinline__ T group_sum(T v) {
+#pragma unroll
+  for (int o = G / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, G);
+  return v;
+}
+
 // ---------------------------------------------------------------------------------------
-// Fused force + integrator kernel; one thread per monomer (monomer-id order, which is
-// chain order: consecutive threads are spatially close).
+// Fused force + integrator kernel.  G lanes per monomer; storage is kept in cell order, so
+// consecutive monomers are spatial neighbours and each XCD's share of the grid is a compact
+// slab of the box:
+//   * each lane takes every G-th of the 27 stencil cells, loading their occupancies and
+//     first records in one round (the records' addresses do not depend on the
+//     occupancy), then any further records;
+//   * the chain neighbours p-2, p-1, p+1, p+2 are fetched meanwhile, spread over the lanes;
+//   * the pair force is summed across the group, lane 0 adds bond and angle forces and
+//     integrates.
 // ---------------------------------------------------------------------------------------
-template <typename R, int MODE>
+template <typename R, int MODE, int G>
 __global__ __launch_bounds__(256) void k_force(ForceArgs a) {
+  constexpr int CPL = (27 + G - 1) / G;  // stencil cells per lane
+  constexpr int NPL = (4 + G - 1) / G;   // chain neighbours fetched per lane
   const int lb = xcd_remap(blockIdx.x, gridDim.x);
   const int k = __builtin_amdgcn_readfirstlane(a.blk_melt[lb]);
   const MeltDesc& d = a.md[k];
-  const int li = a.blk_base[lb] + (int)threadIdx.x;
-  if (li >= d.Nm) return;
+  const int sub = G > 1 ? (int)(threadIdx.x & (G - 1)) : 0;
+  const int li0 = a.blk_base[lb] + (int)(threadIdx.x / G);
+  const bool valid = li0 < d.Nm;
+  if (G == 1 && !valid) return;
+  const int li = valid ? li0 : d.Nm - 1;  // padding lanes mirror the last monomer, write nothing
   const int NP = a.NP;
   const int g = d.off + li;
-  const double L = d.L;
+  const double L = d.L, invL = 1.0 / d.L;
   const double xg = a.x[g], yg = a.x[NP + g], zg = a.x[2 * NP + g];
   const SPos<R>* __restrict__ spos = (const SPos<R>*)a.spos;
 
@@ -133,6 +172,27 @@ __global__ __launch_bounds__(256) void k_force(ForceArgs a) {
     dt_close = d.warm_dt0 * pow(d.dt / d.warm_dt0, a.t_close);
     dt_open = d.warm_dt0 * pow(d.dt / d.warm_dt0, a.t_open);
   }
+  const bool forces_on = !(d.test_flags & TF_NOFORCE);
+  const int N = d.N;
+
+  // ---- chain neighbours (slots 0..3 = p-2, p-1, p+1, p+2), lane (q mod G) fetches slot q
+  const int lcp = a.loc[g];
+  const int c = lcp / N, p = lcp - c * N;
+  R nbx[NPL], nby[NPL], nbz[NPL];
+  bool nbh[NPL];
+#pragma unroll
+  for (int t = 0; t < NPL; ++t) {
+    const int q = sub + t * G;
+    const int qoff = q == 0 ? -2 : q == 1 ? -1 : q == 2 ? 1 : 2;
+    nbh[t] = forces_on && q < 4 && p + qoff >= 0 && p + qoff < N;
+    nbx[t] = nby[t] = nbz[t] = (R)0;
+    if (nbh[t]) {
+      const int j = a.chain[d.off + c * N + p + qoff];
+      double dx = a.x[j] - xg, dy = a.x[NP + j] - yg, dz = a.x[2 * NP + j] - zg;
+      dx -= L * rint(dx * invL); dy -= L * rint(dy * invL); dz -= L * rint(dz * invL);
+      nbx[t] = (R)dx; nby[t] = (R)dy; nbz[t] = (R)dz;
+    }
+  }
 
   V3<R> F = {(R)0, (R)0, (R)0};
   R Ssum = (R)0;
@@ -141,81 +201,100 @@ __global__ __launch_bounds__(256) void k_force(ForceArgs a) {
   const R pa = (R)d.pa, pb = (R)d.pb, rc2 = (R)d.rc2, n_half = (R)(0.5 * d.n_exp);
   const int nh = d.n_half_int;
 
-  if (!(d.test_flags & TF_NOFORCE)) {
-    // ---------------- nonbonded + bonded pairs: truncated MLJ^n over the 27 cells
-    if (!(d.test_flags & TF_PHANTOM)) {
-      const int nc = d.nc;
-      const int lc = a.cell_of[g] - d.cell_off;
-      const int cx = lc % nc, cy = (lc / nc) % nc, cz = lc / (nc * nc);
-      const R hR = (R)d.h;
-      const R rx = (R)(xg - cx * d.h), ry = (R)(yg - cy * d.h), rz = (R)(zg - cz * d.h);
-      for (int oz = -1; oz <= 1; ++oz) {
-        int nz = cz + oz; nz += (nz < 0) ? nc : 0; nz -= (nz >= nc) ? nc : 0;
-        const R shz = (R)oz * hR - rz;
-        for (int oy = -1; oy <= 1; ++oy) {
-          int ny = cy + oy; ny += (ny < 0) ? nc : 0; ny -= (ny >= nc) ? nc : 0;
-          const R shy = (R)oy * hR - ry;
+  auto pair_term = [&](R dx, R dy, R dz) {  // (dx, dy, dz) = x_j - x_i
+    const R r2 = dx * dx + dy * dy + dz * dz;
+    if (r2 < rc2) {
+      R sn, s6;
+      R coef = pair_coef<R>(r2, pa, pb, nh, n_half, sn, s6);
+      if (MODE & F_WARM) {
+        const R rr = sqrt(r2);
+        if (coef * rr > fcap) coef = fcap / rr;
+      }
+      F.x -= coef * dx; F.y -= coef * dy; F.z -= coef * dz;
+      if (MODE & F_DIAG) {
+        Ssum += fabs(coef) * sqrt(r2);
+        e_pair += 0.5 * ((double)d.ua * (double)sn - (double)d.ub * (double)s6 + 1.0);
+      }
+    }
+  };
+
+  // ---- pair forces over this lane's stencil cells
+  if (forces_on && !(d.test_flags & TF_PHANTOM)) {
+    const int nc = d.nc;
+    const int lc = a.cell_of[g] - d.cell_off;
+    const int cx = lc % nc, cy = (lc / nc) % nc, cz = lc / (nc * nc);
+    const R hR = (R)d.h;
+    const R rx = (R)(xg - cx * d.h), ry = (R)(yg - cy * d.h), rz = (R)(zg - cz * d.h);
+    int nb[CPL], cn[CPL];
+    SPos<R> r0[CPL];
 #pragma unroll
-          for (int ox = -1; ox <= 1; ++ox) {
-            int nx = cx + ox; nx += (nx < 0) ? nc : 0; nx -= (nx >= nc) ? nc : 0;
-            const R shx = (R)ox * hR - rx;
-            const int nb = d.cell_off + (nz * nc + ny) * nc + nx;
-            int n = a.cnt[nb];
-            n = n > CELL_CAP ? CELL_CAP : n;
-            const SPos<R>* cp = spos + nb * CELL_CAP;
-            for (int j = 0; j < n; ++j) {
-              R dx, dy, dz;  // x_j - x_i
-              if (MODE & F_EXACT) {
-                // FP64 minimum image from the master positions (energy reductions)
-                const int id = a.bucket[nb * CELL_CAP + j];
-                if (id == g) continue;
-                dx = (R)min_image(a.x[id] - xg, L);
-                dy = (R)min_image(a.x[NP + id] - yg, L);
-                dz = (R)min_image(a.x[2 * NP + id] - zg, L);
-              } else {
-                const SPos<R> p = cp[j];
-                if (p.id == g) continue;
-                dx = p.x + shx; dy = p.y + shy; dz = p.z + shz;
-              }
-              const R r2 = dx * dx + dy * dy + dz * dz;
-              if (r2 < rc2) {
-                R sn, s6;
-                R coef = pair_coef<R>(r2, pa, pb, nh, n_half, sn, s6);
-                if (MODE & F_WARM) {
-                  const R rr = sqrt(r2);
-                  if (coef * rr > fcap) coef = fcap / rr;
-                }
-                F.x -= coef * dx; F.y -= coef * dy; F.z -= coef * dz;
-                if (MODE & F_DIAG) {
-                  Ssum += fabs(coef) * sqrt(r2);
-                  e_pair += 0.5 * ((double)d.ua * (double)sn - (double)d.ub * (double)s6 + 1.0);
-                }
-              }
-            }
-          }
+    for (int q = 0; q < CPL; ++q) {
+      const int s = sub + q * G;
+      const int sc = s < 27 ? s : 13;  // unused slots point at the own cell, occupancy forced to 0
+      const int ox = sc % 3 - 1, oy = (sc / 3) % 3 - 1, oz = sc / 9 - 1;
+      int nx = cx + ox; nx += (nx < 0) ? nc : 0; nx -= (nx >= nc) ? nc : 0;
+      int ny = cy + oy; ny += (ny < 0) ? nc : 0; ny -= (ny >= nc) ? nc : 0;
+      int nz = cz + oz; nz += (nz < 0) ? nc : 0; nz -= (nz >= nc) ? nc : 0;
+      nb[q] = d.cell_off + (nz * nc + ny) * nc + nx;
+    }
+#pragma unroll
+    for (int q = 0; q < CPL; ++q) {
+      cn[q] = a.cnt[nb[q]];
+      if (!(MODE & F_EXACT)) r0[q] = spos[nb[q] * CELL_CAP];
+      if (sub + q * G >= 27) cn[q] = 0;
+    }
+#pragma unroll
+    for (int q = 0; q < CPL; ++q) {
+      const int s = sub + q * G;
+      const int sc = s < 27 ? s : 13;
+      const R shx = (R)(sc % 3 - 1) * hR - rx, shy = (R)((sc / 3) % 3 - 1) * hR - ry, shz = (R)(sc / 9 - 1) * hR - rz;
+      const int n = cn[q] > CELL_CAP ? CELL_CAP : cn[q];
+      for (int j = 0; j < n; ++j) {
+        if (MODE & F_EXACT) {
+          // FP64 minimum image from the master positions (energy reductions)
+          const int id = a.bucket[nb[q] * CELL_CAP + j];
+          if (id == g) continue;
+          pair_term((R)min_image(a.x[id] - xg, L), (R)min_image(a.x[NP + id] - yg, L),
+                    (R)min_image(a.x[2 * NP + id] - zg, L));
+        } else {
+          const SPos<R> r = (j == 0) ? r0[q] : spos[nb[q] * CELL_CAP + j];
+          if (r.id == g) continue;
+          pair_term(r.x + shx, r.y + shy, r.z + shz);
         }
       }
     }
+  }
 
-    // ---------------- bonded: FENE (Eqs. 3, 10) and angles (Eq. 4) along the chain
-    const int N = d.N;
-    const int lcp = a.loc[g];
-    const int c = lcp / N, p = lcp - c * N;
-    const int* __restrict__ crow = a.chain + d.off + c * N;
-    V3<R> P[5];
-    bool has[5];
+  // ---- sum over the lane group; gather the chain neighbours into lane 0
+  V3<R> P[5];
+  bool has[5];
+  P[2].x = P[2].y = P[2].z = (R)0;
+  has[2] = true;
+  if (G == 1) {
 #pragma unroll
-    for (int q = 0; q < 5; ++q) {
-      const int pp = p + q - 2;
-      has[q] = (pp >= 0 && pp < N);
-      P[q].x = P[q].y = P[q].z = (R)0;
-      if (q != 2 && has[q]) {
-        const int j = crow[pp];
-        P[q].x = (R)min_image(a.x[j] - xg, L);
-        P[q].y = (R)min_image(a.x[NP + j] - yg, L);
-        P[q].z = (R)min_image(a.x[2 * NP + j] - zg, L);
-      }
+    for (int q = 0; q < 4; ++q) {
+      const int sl = q < 2 ? q : q + 1;
+      P[sl].x = nbx[q]; P[sl].y = nby[q]; P[sl].z = nbz[q]; has[sl] = nbh[q];
     }
+  } else {
+    F.x = group_sum<G>(F.x); F.y = group_sum<G>(F.y); F.z = group_sum<G>(F.z);
+    if (MODE & F_DIAG) { Ssum = group_sum<G>(Ssum); e_pair = group_sum<G>(e_pair); }
+    const int g0 = (int)(threadIdx.x & ~(G - 1)) & 63;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int sl = q < 2 ? q : q + 1;
+      const int src = g0 + (q % G);
+      const int t = q / G;
+      P[sl].x = __shfl(nbx[t], src, 64);
+      P[sl].y = __shfl(nby[t], src, 64);
+      P[sl].z = __shfl(nbz[t], src, 64);
+      has[sl] = __shfl((int)nbh[t], src, 64) != 0;
+    }
+    if (sub != 0 || !valid) return;
+  }
+
+  // ---- bonded: FENE (Eqs. 3, 10) and angles (Eq. 4) along the chain
+  if (forces_on) {
     const R kf = (R)d.kfene, R0sq = (R)d.R0sq, amin = (R)d.amin;
 #pragma unroll
     for (int q = 1; q <= 3; q += 2) {
@@ -224,10 +303,9 @@ __global__ __launch_bounds__(256) void k_force(ForceArgs a) {
       const R r2 = b.x * b.x + b.y * b.y + b.z * b.z;
       const bool broken = (amin > (R)0) ? !(r2 < (R)4 * R0sq) : !(r2 < R0sq);
       if (broken) errbits |= ERR_FENE;
-      R am = (R)1 - r2 / R0sq;
+      const R am = (R)1 - r2 / R0sq;
       const bool floored = (amin > (R)0 && am < amin);
-      const R ae = floored ? amin : am;
-      const R cb = kf / ae;  // F_i = k (x_j - x_i) / a
+      const R cb = kf / (floored ? amin : am);  // F_i = k (x_j - x_i) / a
       F.x += cb * b.x; F.y += cb * b.y; F.z += cb * b.z;
       if (MODE & F_DIAG) {
         Ssum += fabs(cb) * sqrt(r2);
@@ -235,21 +313,7 @@ __global__ __launch_bounds__(256) void k_force(ForceArgs a) {
         const double ad = 1.0 - (double)r2 / d.R0sq;
         e_bond += 0.5 * (floored ? -hk * (log(d.amin) + (ad - d.amin) / d.amin) : -hk * log(ad));
       }
-      if (d.test_flags & TF_PHANTOM) {
-        if (r2 < rc2) {
-          R sn, s6;
-          R coef = pair_coef<R>(r2, pa, pb, nh, n_half, sn, s6);
-          if (MODE & F_WARM) {
-            const R rr = sqrt(r2);
-            if (coef * rr > fcap) coef = fcap / rr;
-          }
-          F.x -= coef * b.x; F.y -= coef * b.y; F.z -= coef * b.z;
-          if (MODE & F_DIAG) {
-            Ssum += fabs(coef) * sqrt(r2);
-            e_pair += 0.5 * ((double)d.ua * (double)sn - (double)d.ub * (double)s6 + 1.0);
-          }
-        }
-      }
+      if (d.test_flags & TF_PHANTOM) pair_term(b.x, b.y, b.z);
     }
     const R kap = (R)d.kappa;
     if (d.kappa != 0.0) {
@@ -267,9 +331,9 @@ __global__ __launch_bounds__(256) void k_force(ForceArgs a) {
         V3<R> g1 = {b2.x * inv12 - c1 * b1.x, b2.y * inv12 - c1 * b1.y, b2.z * inv12 - c1 * b1.z};
         V3<R> g2 = {b1.x * inv12 - c2 * b2.x, b1.y * inv12 - c2 * b2.y, b1.z * inv12 - c2 * b2.z};
         V3<R> f;
-        if (dv == 1) { f.x = -kap * g1.x; f.y = -kap * g1.y; f.z = -kap * g1.z; }        // g is the first bead
+        if (dv == 1) { f.x = -kap * g1.x; f.y = -kap * g1.y; f.z = -kap * g1.z; }  // first bead
         else if (dv == 0) { f.x = kap * (g1.x - g2.x); f.y = kap * (g1.y - g2.y); f.z = kap * (g1.z - g2.z); }
-        else { f.x = kap * g2.x; f.y = kap * g2.y; f.z = kap * g2.z; }                  // g is the last bead
+        else { f.x = kap * g2.x; f.y = kap * g2.y; f.z = kap * g2.z; }  // last bead
         F.x += f.x; F.y += f.y; F.z += f.z;
         if (MODE & F_DIAG) {
           Ssum += sqrt(f.x * f.x + f.y * f.y + f.z * f.z);
@@ -292,7 +356,8 @@ __global__ __launch_bounds__(256) void k_force(ForceArgs a) {
     if (MODE & F_CLOSE) {
       // Langevin force of this step, then the closing half kick
       const uint64_t idx = (MODE & F_WARM) ? (uint64_t)a.s_off : a.step_base[k] + (uint64_t)a.s_off;
-      const U64x4 w = rng_draw(d, (uint64_t)li, idx, (MODE & F_WARM) ? ST_WARMUP : ST_LANGEVIN);
+      // the noise is keyed by the monomer id, not by the storage slot
+      const U64x4 w = rng_draw(d, (uint64_t)a.mono[g], idx, (MODE & F_WARM) ? ST_WARMUP : ST_LANGEVIN);
       double z0, z1, z2, z3;
       gauss2(w.w[0], w.w[1], z0, z1);
       gauss2(w.w[2], w.w[3], z2, z3);
@@ -332,16 +397,81 @@ __global__ __launch_bounds__(256) void k_force(ForceArgs a) {
       a.xn[g] = nxp; a.xn[NP + g] = nyp; a.xn[2 * NP + g] = nzp;
       // bin the new position for the next step
       const int nc = d.nc;
-      int cx = cell_coord(nxp, d.cinv, nc), cy = cell_coord(nyp, d.cinv, nc), cz = cell_coord(nzp, d.cinv, nc);
-      if (!(isfinite(nxp) && isfinite(nyp) && isfinite(nzp))) cx = cy = cz = 0;
-      const int cn = d.cell_off + (cz * nc + cy) * nc + cx;
-      a.cell_of[g] = cn;
-      const int s = atomicAdd(&a.cnt_next[cn], 1);
-      if (s < CELL_CAP) a.bucket[cn * CELL_CAP + s] = g;
+      const int cx = cell_coord(nxp, d.cinv, nc), cy = cell_coord(nyp, d.cinv, nc), cz = cell_coord(nzp, d.cinv, nc);
+      const int cnw = d.cell_off + (cz * nc + cy) * nc + cx;
+      a.cell_of[g] = cnw;
+      const int s = atomicAdd(&a.cnt_next[cnw], 1);
+      if (s < CELL_CAP) a.bucket[cnw * CELL_CAP + s] = g;
       else errbits |= ERR_CELL_OVERFLOW;
     }
   }
   if (errbits) atomicOr(&a.err[k], errbits);
+}
+
+// ---------------------------------------------------------------------------------------
+// Spatial reordering of the per-monomer storage: slots are renumbered in cell order
+// (row-major cells, ascending old slot within a cell), so that consecutive threads and each
+// XCD's share of the grid touch a compact region of the box.
+// ---------------------------------------------------------------------------------------
+// exclusive scan of the bucket occupancies over all cells (one workgroup; once per reorder)
+__global__ __launch_bounds__(1024) void k_scan_cells(const int* __restrict__ cnt, int cap, int NC,
+                                                    int* __restrict__ start) {
+  __shared__ int s_part[1024];
+  const int t = threadIdx.x;
+  const int per = (NC + 1023) / 1024;
+  const int lo = t * per, hi = min(lo + per, NC);
+  int sum = 0;
+  for (int c = lo; c < hi; ++c) sum += min(cnt[c], cap);
+  s_part[t] = sum;
+  __syncthreads();
+  for (int o = 1; o < 1024; o <<= 1) {
+    const int v = t >= o ? s_part[t - o] : 0;
+    __syncthreads();
+    s_part[t] += v;
+    __syncthreads();
+  }
+  int run = s_part[t] - sum;
+  for (int c = lo; c < hi; ++c) {
+    start[c] = run;
+    run += min(cnt[c], cap);
+  }
+  if (t == 1023) start[NC] = s_part[1023];
+}
+
+// perm[new slot] = old slot, inv[old slot] = new slot
+__global__ __launch_bounds__(256) void k_perm_cells(const int* __restrict__ cnt, const int* __restrict__ bucket,
+                                                    int cap, const int* __restrict__ start, int NC,
+                                                    int* __restrict__ perm, int* __restrict__ inv) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= NC) return;
+  const int n = min(cnt[c], cap), s0 = start[c];
+  for (int j = 0; j < n; ++j) {
+    const int old = bucket[c * cap + j];
+    perm[s0 + j] = old;
+    inv[old] = s0 + j;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_gather_f64x3(double* __restrict__ dst, const double* __restrict__ src,
+                                                      const int* __restrict__ perm, int NP) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= NP) return;
+  const int o = perm[s];
+  dst[s] = src[o];
+  dst[NP + s] = src[NP + o];
+  dst[2 * NP + s] = src[2 * NP + o];
+}
+
+__global__ __launch_bounds__(256) void k_gather_i32(int* __restrict__ dst, const int* __restrict__ src,
+                                                    const int* __restrict__ perm, int NP) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s < NP) dst[s] = src[perm[s]];
+}
+
+// chain tables hold slots: map them through inv
+__global__ __launch_bounds__(256) void k_remap_i32(int* __restrict__ a, const int* __restrict__ inv, int NP) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s < NP) a[s] = inv[a[s]];
 }
 
 // per-melt step counters advance after a run of closing kicks
@@ -373,10 +503,10 @@ void launch_finalize(int prec, const MeltDesc* md, const BlockMap& cm, int NP, c
                        bucket, (SPos<double>*)spos, cnt_clear);
 }
 
-template <typename R>
-static void launch_force_t(int mode, const ForceArgs& a, int nblk, hipStream_t s) {
+template <typename R, int G>
+static void launch_force_g(int mode, const ForceArgs& a, int nblk, hipStream_t s) {
 #define KG_CASE(M) \
-  case M: hipLaunchKernelGGL((k_force<R, M>), dim3(nblk), dim3(256), 0, s, a); break;
+  case M: hipLaunchKernelGGL((k_force<R, M, G>), dim3(nblk), dim3(256), 0, s, a); break;
   switch (mode) {
     KG_CASE(F_OPEN)
     KG_CASE(F_CLOSE | F_OPEN)
@@ -391,9 +521,19 @@ static void launch_force_t(int mode, const ForceArgs& a, int nblk, hipStream_t s
 #undef KG_CASE
 }
 
-void launch_force(int prec, int mode, const ForceArgs& a, int nblk, hipStream_t s) {
-  if (prec) launch_force_t<float>(mode, a, nblk, s);
-  else launch_force_t<double>(mode, a, nblk, s);
+template <typename R>
+static void launch_force_t(int mode, int lanes, const ForceArgs& a, int nblk, hipStream_t s) {
+  switch (lanes) {
+    case 1: launch_force_g<R, 1>(mode, a, nblk, s); break;
+    case 2: launch_force_g<R, 2>(mode, a, nblk, s); break;
+    case 4: launch_force_g<R, 4>(mode, a, nblk, s); break;
+    default: launch_force_g<R, 8>(mode, a, nblk, s); break;
+  }
+}
+
+void launch_force(int prec, int mode, int lanes, const ForceArgs& a, int nblk, hipStream_t s) {
+  if (prec) launch_force_t<float>(mode, lanes, a, nblk, s);
+  else launch_force_t<double>(mode, lanes, a, nblk, s);
 }
 
 void launch_advance(uint64_t* step_base, int nm, uint64_t n, hipStream_t s) {
@@ -402,6 +542,21 @@ void launch_advance(uint64_t* step_base, int nm, uint64_t n, hipStream_t s) {
 
 void launch_fill_i32(int* p, int n, int v, hipStream_t s) {
   if (n > 0) hipLaunchKernelGGL(k_fill_i32, dim3((n + 255) / 256), dim3(256), 0, s, p, n, v);
+}
+
+void launch_perm_cells(const int* cnt, const int* bucket, int cap, int NC, int* start, int* perm, int* inv,
+                       hipStream_t s) {
+  hipLaunchKernelGGL(k_scan_cells, dim3(1), dim3(1024), 0, s, cnt, cap, NC, start);
+  hipLaunchKernelGGL(k_perm_cells, dim3((NC + 255) / 256), dim3(256), 0, s, cnt, bucket, cap, start, NC, perm, inv);
+}
+void launch_gather_f64x3(double* dst, const double* src, const int* perm, int NP, hipStream_t s) {
+  hipLaunchKernelGGL(k_gather_f64x3, dim3((NP + 255) / 256), dim3(256), 0, s, dst, src, perm, NP);
+}
+void launch_gather_i32(int* dst, const int* src, const int* perm, int NP, hipStream_t s) {
+  hipLaunchKernelGGL(k_gather_i32, dim3((NP + 255) / 256), dim3(256), 0, s, dst, src, perm, NP);
+}
+void launch_remap_i32(int* a, const int* inv, int NP, hipStream_t s) {
+  hipLaunchKernelGGL(k_remap_i32, dim3((NP + 255) / 256), dim3(256), 0, s, a, inv, NP);
 }
 
 size_t spos_bytes(int prec) { return prec ? sizeof(SPos<float>) : sizeof(SPos<double>); }

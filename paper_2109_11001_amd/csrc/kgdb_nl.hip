@@ -1,0 +1,381 @@
+// Production MD step on gfx950: Verlet neighbour lists rebuilt every K steps.
+//
+// Rebuild (every K steps): bin the monomers into a grid of cells of edge >= r_list = r_c + skin
+// (counting sort with id-ordered buckets), record for each monomer its reference cell and its
+// position relative to that cell's origin, and list the monomers within r_list in the 27
+// neighbouring cells together with the cell offset (a 5-bit code).  Lists are column-major
+// (entry k of monomer i at k * NP + i) so that a wavefront reads them coalesced.
+//
+// Step: one kernel per step; one thread per monomer runs the truncated MLJ^n pair force over
+// its list (displacements from reference-cell-relative coordinates, so FP32 keeps full
+// relative precision), the FENE and angle forces along its chain, and the Langevin
+// velocity-Verlet update.  It writes the new relative coordinates to the other buffer and
+// flags the run stale when a monomer has moved more than skin/2 since the rebuild (the host
+// then reruns the chunk with more frequent rebuilds).
+#include "kgdb_dev.h"
+#include "kgdb_kernels.h"
+
+namespace kgdb {
+
+template <typename R> struct Rel4;
+template <> struct Rel4<float> { float x, y, z, w; };
+template <> struct Rel4<double> { double x, y, z, w; };
+
+__device__ __forceinline__ int pack_cell(int cx, int cy, int cz) { return cx | (cy << 10) | (cz << 20); }
+
+// ---------------------------------------------------------------------------------------
+// rebuild 1: binning into the list grid
+// ---------------------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_nl_bin(NlArgs a) {
+  const int lb = xcd_remap(blockIdx.x, gridDim.x);
+  const int k = __builtin_amdgcn_readfirstlane(a.pblk_melt[lb]);
+  const MeltDesc& d = a.md[k];
+  const int li = a.pblk_base[lb] + (int)threadIdx.x;
+  if (li >= d.Nm) return;
+  const int g = d.off + li;
+  const int nc = d.ncl;
+  const int cx = cell_coord(a.x[g], d.cinvl, nc), cy = cell_coord(a.x[a.NP + g], d.cinvl, nc),
+            cz = cell_coord(a.x[2 * a.NP + g], d.cinvl, nc);
+  const int c = d.celll_off + (cz * nc + cy) * nc + cx;
+  const int s = atomicAdd(&a.cnt[c], 1);
+  if (s < NL_CELL_CAP) a.bucket[c * NL_CELL_CAP + s] = g;
+  else atomicOr(&a.err[k], ERR_CELL_OVERFLOW);
+}
+
+// ---------------------------------------------------------------------------------------
+// rebuild 2: per cell, order the bucket by slot and write each member's reference cell and
+// reference-relative position; clear the other occupancy buffer
+// ---------------------------------------------------------------------------------------
+// rank-by-counting sort of one bucket held in registers (CAPT = compile-time bound), then
+// each member's reference cell and reference-relative position
+template <typename R, int CAPT>
+__device__ __forceinline__ void nl_place(const NlArgs& a, Rel4<R>* rel, int base, int n, double ox, double oy,
+                                         double oz, int pc) {
+  int ids[CAPT];
+#pragma unroll
+  for (int j = 0; j < CAPT; ++j) ids[j] = (j < n) ? a.bucket[base + j] : 0x7fffffff;
+#pragma unroll
+  for (int j = 0; j < CAPT; ++j) {
+    if (j < n) {
+      int r = 0;
+#pragma unroll
+      for (int m = 0; m < CAPT; ++m) r += (ids[m] < ids[j]) ? 1 : 0;
+      const int id = ids[j];
+      a.bucket[base + r] = id;
+      Rel4<R> p;
+      p.x = (R)(a.x[id] - ox);
+      p.y = (R)(a.x[a.NP + id] - oy);
+      p.z = (R)(a.x[2 * a.NP + id] - oz);
+      p.w = (R)0;
+      rel[id] = p;
+      a.relb[id] = make_float4((float)p.x, (float)p.y, (float)p.z, 0.f);
+      a.refc[id] = pc;
+    }
+  }
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_nl_finalize(NlArgs a) {
+  const int lb = xcd_remap(blockIdx.x, gridDim.x);
+  const int k = __builtin_amdgcn_readfirstlane(a.cblk_melt[lb]);
+  const MeltDesc& d = a.md[k];
+  const int nc = d.ncl;
+  const int lc = a.cblk_base[lb] + (int)threadIdx.x;
+  if (lc >= nc * nc * nc) return;
+  const int c = d.celll_off + lc;
+  a.cnt_clear[c] = 0;
+  int n = a.cnt[c];
+  if (n > NL_CELL_CAP) n = NL_CELL_CAP;
+  if (n == 0) return;
+  const int base = c * NL_CELL_CAP;
+  const int cx = lc % nc, cy = (lc / nc) % nc, cz = lc / (nc * nc);
+  const double ox = cx * d.hl, oy = cy * d.hl, oz = cz * d.hl;
+  const int pc = pack_cell(cx, cy, cz);
+  Rel4<R>* rel = (Rel4<R>*)a.rel_cur;
+  if (n <= 8) nl_place<R, 8>(a, rel, base, n, ox, oy, oz, pc);
+  else nl_place<R, NL_CELL_CAP>(a, rel, base, n, ox, oy, oz, pc);
+}
+
+// ---------------------------------------------------------------------------------------
+// rebuild 3: neighbour lists (all monomers within r_list, bonded ones included: every pair
+// feels MLJ^n once)
+// ---------------------------------------------------------------------------------------
+template <typename R>
+__global__ __launch_bounds__(256) void k_nl_build(NlArgs a) {
+  const int lb = xcd_remap(blockIdx.x, gridDim.x);
+  const int k = __builtin_amdgcn_readfirstlane(a.pblk_melt[lb]);
+  const MeltDesc& d = a.md[k];
+  const int li = a.pblk_base[lb] + (int)threadIdx.x;
+  if (li >= d.Nm) return;
+  const int NP = a.NP;
+  const int g = d.off + li;
+  const Rel4<R>* __restrict__ rel = (const Rel4<R>*)a.rel_cur;
+  const Rel4<R> ri = rel[g];
+  const int pc = a.refc[g];
+  const int cx = pc & 1023, cy = (pc >> 10) & 1023, cz = pc >> 20;
+  const int nc = d.ncl;
+  const R hl = (R)d.hl, rl2 = (R)d.rlist2;
+  int cnt = 0;
+  int xs[3];
+#pragma unroll
+  for (int ox = -1; ox <= 1; ++ox) {
+    int nx = cx + ox; nx += (nx < 0) ? nc : 0; nx -= (nx >= nc) ? nc : 0;
+    xs[ox + 1] = nx;
+  }
+  // 9 rows of 3 cells; each row's members are walked as one flattened sequence, four at a
+  // time (independent id and position loads)
+  for (int oz = -1; oz <= 1; ++oz) {
+    int nz = cz + oz; nz += (nz < 0) ? nc : 0; nz -= (nz >= nc) ? nc : 0;
+    for (int oy = -1; oy <= 1; ++oy) {
+      int ny = cy + oy; ny += (ny < 0) ? nc : 0; ny -= (ny >= nc) ? nc : 0;
+      const int row = d.celll_off + (nz * nc + ny) * nc;
+      const int c0 = row + xs[0], c1 = row + xs[1], c2 = row + xs[2];
+      const int n0 = min(a.cnt[c0], NL_CELL_CAP), n1 = min(a.cnt[c1], NL_CELL_CAP), n2 = min(a.cnt[c2], NL_CELL_CAP);
+      const int tot = n0 + n1 + n2;
+      const R sy = (R)oy * hl - ri.y, sz = (R)oz * hl - ri.z;
+      const uint32_t code_yz = (uint32_t)(3 * (oy + 1) + 9 * (oz + 1));
+      for (int t0 = 0; t0 < tot; t0 += 4) {
+        int id[4], ox[4];
+        bool ok[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int t = t0 + u;
+          ok[u] = t < tot;
+          const int w = t < n0 ? 0 : (t < n0 + n1 ? 1 : 2);
+          const int cc = w == 0 ? c0 : (w == 1 ? c1 : c2);
+          const int j = t - (w == 0 ? 0 : (w == 1 ? n0 : n0 + n1));
+          ox[u] = w - 1;
+          id[u] = ok[u] ? a.bucket[cc * NL_CELL_CAP + j] : g;
+        }
+        Rel4<R> p[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) p[u] = rel[id[u]];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          if (!ok[u] || id[u] == g) continue;
+          const R dx = p[u].x + (R)ox[u] * hl - ri.x, dy = p[u].y + sy, dz = p[u].z + sz;
+          if (dx * dx + dy * dy + dz * dz < rl2) {
+            if (cnt < NL_CAP) a.nlist[(size_t)cnt * NP + g] = ((uint32_t)id[u] << 5) | (code_yz + (uint32_t)(ox[u] + 1));
+            ++cnt;
+          }
+        }
+      }
+    }
+  }
+  if (cnt > NL_CAP) { atomicOr(&a.err[k], ERR_NLIST_OVERFLOW); cnt = NL_CAP; }
+  a.nlen[g] = cnt;
+}
+
+template <typename R> struct W3 { R x, y, z; };
+
+// fast FP32 reciprocal and square root (about 1 ulp); exact IEEE forms in FP64
+__device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double frcp(double x) { return 1.0 / x; }
+__device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ double fsqrt(double x) { return sqrt(x); }
+
+// ---------------------------------------------------------------------------------------
+// the step: forces from the lists + chain, Langevin velocity Verlet
+// ---------------------------------------------------------------------------------------
+template <typename R, int MODE>
+__global__ __launch_bounds__(256) void k_nl_step(NlArgs a) {
+  const int lb = xcd_remap(blockIdx.x, gridDim.x);
+  const int k = __builtin_amdgcn_readfirstlane(a.pblk_melt[lb]);
+  const MeltDesc& d = a.md[k];
+  const int li = a.pblk_base[lb] + (int)threadIdx.x;
+  if (li >= d.Nm) return;
+  const int NP = a.NP;
+  const int g = d.off + li;
+  const double L = d.L, invL = 1.0 / d.L;
+  const double xg = a.x[g], yg = a.x[NP + g], zg = a.x[2 * NP + g];
+  const Rel4<R>* __restrict__ rel = (const Rel4<R>*)a.rel_cur;
+  const bool forces_on = !(d.test_flags & TF_NOFORCE);
+  uint32_t errbits = 0;
+
+  // chain neighbours p-2, p-1, p+1, p+2 (FP64 minimum image, then the force precision)
+  const int N = d.N;
+  const int lcp = a.loc[g];
+  const int c = (int)((double)lcp * d.invN), p0 = lcp - c * N;
+  const int cch = (p0 < 0) ? c - 1 : (p0 >= N ? c + 1 : c);  // guard the reciprocal's rounding
+  const int p = lcp - cch * N;
+  W3<R> P[5];
+  bool has[5];
+#pragma unroll
+  for (int q = 0; q < 5; ++q) {
+    const int pp = p + q - 2;
+    has[q] = (q == 2) || (forces_on && pp >= 0 && pp < N);
+    P[q].x = P[q].y = P[q].z = (R)0;
+    if (q != 2 && has[q]) {
+      const int j = a.chain[d.off + cch * N + pp];
+      double dx = a.x[j] - xg, dy = a.x[NP + j] - yg, dz = a.x[2 * NP + j] - zg;
+      dx -= L * rint(dx * invL); dy -= L * rint(dy * invL); dz -= L * rint(dz * invL);
+      P[q].x = (R)dx; P[q].y = (R)dy; P[q].z = (R)dz;
+    }
+  }
+
+  W3<R> F = {(R)0, (R)0, (R)0};
+  const R pa = (R)d.pa, pb = (R)d.pb, rc2 = (R)d.rc2, n_half = (R)(0.5 * d.n_exp);
+  const int nh = d.n_half_int;
+  auto pair_add = [&](R dx, R dy, R dz) {  // (dx, dy, dz) = x_j - x_i
+    const R r2 = dx * dx + dy * dy + dz * dz;
+    if (r2 < rc2) {
+      const R s2 = frcp(r2);
+      const R s6 = s2 * s2 * s2;
+      const R sn = pow_half<R>(s2, nh, n_half);
+      const R coef = (pa * sn - pb * s6) * s2;
+      F.x -= coef * dx; F.y -= coef * dy; F.z -= coef * dz;
+    }
+  };
+
+  if (forces_on && !(d.test_flags & TF_PHANTOM)) {
+    const Rel4<R> ri = rel[g];
+    const R hl = (R)d.hl;
+    const int n = a.nlen[g];
+    auto entry = [&](uint32_t e, const Rel4<R>& rj) {
+      const int code = (int)(e & 31u);
+      const int ox = code % 3 - 1, oy = (code / 3) % 3 - 1, oz = code / 9 - 1;
+      pair_add(rj.x + (R)ox * hl - ri.x, rj.y + (R)oy * hl - ri.y, rj.z + (R)oz * hl - ri.z);
+    };
+    int t = 0;
+    // four entries per round: their loads are independent, so the gathers overlap
+    for (; t + 4 <= n; t += 4) {
+      uint32_t e[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) e[u] = a.nlist[(size_t)(t + u) * NP + g];
+      Rel4<R> rj[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) rj[u] = rel[e[u] >> 5];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) entry(e[u], rj[u]);
+    }
+    for (; t < n; ++t) {
+      const uint32_t e = a.nlist[(size_t)t * NP + g];
+      entry(e, rel[e >> 5]);
+    }
+  }
+
+  if (forces_on) {
+    const R kf = (R)d.kfene, R0sq = (R)d.R0sq, amin = (R)d.amin, iR0sq = (R)(1.0 / d.R0sq);
+#pragma unroll
+    for (int q = 1; q <= 3; q += 2) {
+      if (!has[q]) continue;
+      const W3<R> b = P[q];
+      const R r2 = b.x * b.x + b.y * b.y + b.z * b.z;
+      const bool broken = (amin > (R)0) ? !(r2 < (R)4 * R0sq) : !(r2 < R0sq);
+      if (broken) errbits |= ERR_FENE;
+      const R am = (R)1 - r2 * iR0sq;
+      const R cb = kf * frcp((amin > (R)0 && am < amin) ? amin : am);  // F_i = k (x_j - x_i) / a
+      F.x += cb * b.x; F.y += cb * b.y; F.z += cb * b.z;
+      if (d.test_flags & TF_PHANTOM) pair_add(b.x, b.y, b.z);
+    }
+    const R kap = (R)d.kappa;
+    if (d.kappa != 0.0) {
+#pragma unroll
+      for (int dv = -1; dv <= 1; ++dv) {
+        const int iv = 2 + dv;
+        if (!(has[iv - 1] && has[iv] && has[iv + 1])) continue;
+        const W3<R> b1 = {P[iv].x - P[iv - 1].x, P[iv].y - P[iv - 1].y, P[iv].z - P[iv - 1].z};
+        const W3<R> b2 = {P[iv + 1].x - P[iv].x, P[iv + 1].y - P[iv].y, P[iv + 1].z - P[iv].z};
+        const R l1s = b1.x * b1.x + b1.y * b1.y + b1.z * b1.z;
+        const R l2s = b2.x * b2.x + b2.y * b2.y + b2.z * b2.z;
+        const R i1 = frcp(l1s), i2 = frcp(l2s);
+        const R inv12 = fsqrt(i1 * i2);
+        const R cs = (b1.x * b2.x + b1.y * b2.y + b1.z * b2.z) * inv12;
+        const R c1 = cs * i1, c2 = cs * i2;
+        const W3<R> g1 = {b2.x * inv12 - c1 * b1.x, b2.y * inv12 - c1 * b1.y, b2.z * inv12 - c1 * b1.z};
+        const W3<R> g2 = {b1.x * inv12 - c2 * b2.x, b1.y * inv12 - c2 * b2.y, b1.z * inv12 - c2 * b2.z};
+        if (dv == 1) { F.x -= kap * g1.x; F.y -= kap * g1.y; F.z -= kap * g1.z; }  // first bead
+        else if (dv == 0) { F.x += kap * (g1.x - g2.x); F.y += kap * (g1.y - g2.y); F.z += kap * (g1.z - g2.z); }
+        else { F.x += kap * g2.x; F.y += kap * g2.y; F.z += kap * g2.z; }  // last bead
+      }
+    }
+  }
+
+  const double Fx = (double)F.x, Fy = (double)F.y, Fz = (double)F.z;
+  if (!(isfinite(Fx) && isfinite(Fy) && isfinite(Fz))) errbits |= ERR_NONFINITE;
+  double vx = a.v[g], vy = a.v[NP + g], vz = a.v[2 * NP + g];
+  double fx, fy, fz;
+  const double dt = d.dt;
+  if (MODE & F_CLOSE) {
+    const uint64_t idx = a.step_base[k] + (uint64_t)a.s_off;
+    const U64x4 w = rng_draw(d, (uint64_t)a.mono[g], idx, ST_LANGEVIN);
+    double z0, z1, z2, z3;
+    gauss2(w.w[0], w.w[1], z0, z1);
+    gauss2(w.w[2], w.w[3], z2, z3);
+    const double amp = d.lang_amp;  // sqrt(2 gamma T / dt)
+    fx = -d.gamma * vx + amp * z0;
+    fy = -d.gamma * vy + amp * z1;
+    fz = -d.gamma * vz + amp * z2;
+    vx = vx + 0.5 * dt * (Fx + fx);
+    vy = vy + 0.5 * dt * (Fy + fy);
+    vz = vz + 0.5 * dt * (Fz + fz);
+  } else {
+    fx = a.fl[g]; fy = a.fl[NP + g]; fz = a.fl[2 * NP + g];
+  }
+  if (MODE & F_STORE) {
+    a.fc[g] = Fx; a.fc[NP + g] = Fy; a.fc[2 * NP + g] = Fz;
+    a.fl[g] = fx; a.fl[NP + g] = fy; a.fl[2 * NP + g] = fz;
+    a.v[g] = vx; a.v[NP + g] = vy; a.v[2 * NP + g] = vz;
+    if (!(isfinite(vx) && isfinite(vy) && isfinite(vz))) errbits |= ERR_NONFINITE;
+  }
+  if (MODE & F_OPEN) {
+    const double hx = vx + 0.5 * dt * (Fx + fx);
+    const double hy = vy + 0.5 * dt * (Fy + fy);
+    const double hz = vz + 0.5 * dt * (Fz + fz);
+    const double nxp = wrap_box(xg + dt * hx, L);
+    const double nyp = wrap_box(yg + dt * hy, L);
+    const double nzp = wrap_box(zg + dt * hz, L);
+    if (!(isfinite(nxp) && isfinite(nyp) && isfinite(nzp) && isfinite(hx) && isfinite(hy) && isfinite(hz)))
+      errbits |= ERR_NONFINITE;
+    a.v[g] = hx; a.v[NP + g] = hy; a.v[2 * NP + g] = hz;
+    a.xn[g] = nxp; a.xn[NP + g] = nyp; a.xn[2 * NP + g] = nzp;
+    // position relative to the reference cell (periodic image nearest to it)
+    const int pc = a.refc[g];
+    double rx = nxp - (pc & 1023) * d.hl, ry = nyp - ((pc >> 10) & 1023) * d.hl, rz = nzp - (pc >> 20) * d.hl;
+    rx -= L * rint(rx * invL); ry -= L * rint(ry * invL); rz -= L * rint(rz * invL);
+    Rel4<R> r;
+    r.x = (R)rx; r.y = (R)ry; r.z = (R)rz; r.w = (R)0;
+    ((Rel4<R>*)a.rel_next)[g] = r;
+    const float4 b = a.relb[g];
+    const float ex = (float)rx - b.x, ey = (float)ry - b.y, ez = (float)rz - b.z;
+    if (ex * ex + ey * ey + ez * ez > (float)d.half_skin2) errbits |= ERR_NLIST_STALE;
+  }
+  if (errbits) atomicOr(&a.err[k], errbits);
+}
+
+// ---------------------------------------------------------------------------------------
+void launch_nl_rebuild(int prec, const NlArgs& a, int pblk, int cblk, hipStream_t s) {
+  hipLaunchKernelGGL(k_nl_bin, dim3(pblk), dim3(256), 0, s, a);
+  if (prec) {
+    hipLaunchKernelGGL(k_nl_finalize<float>, dim3(cblk), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_nl_build<float>, dim3(pblk), dim3(256), 0, s, a);
+  } else {
+    hipLaunchKernelGGL(k_nl_finalize<double>, dim3(cblk), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_nl_build<double>, dim3(pblk), dim3(256), 0, s, a);
+  }
+}
+
+void launch_nl_step(int prec, int mode, const NlArgs& a, int pblk, hipStream_t s) {
+#define KG_CASE(R, M) \
+  case M: hipLaunchKernelGGL((k_nl_step<R, M>), dim3(pblk), dim3(256), 0, s, a); break;
+  if (prec) {
+    switch (mode) {
+      KG_CASE(float, F_OPEN)
+      KG_CASE(float, F_CLOSE | F_OPEN)
+      KG_CASE(float, F_CLOSE | F_STORE)
+      default: break;
+    }
+  } else {
+    switch (mode) {
+      KG_CASE(double, F_OPEN)
+      KG_CASE(double, F_CLOSE | F_OPEN)
+      KG_CASE(double, F_CLOSE | F_STORE)
+      default: break;
+    }
+  }
+#undef KG_CASE
+}
+
+size_t rel_bytes(int prec) { return prec ? sizeof(Rel4<float>) : sizeof(Rel4<double>); }
+
+}  // namespace kgdb

@@ -119,6 +119,44 @@ def test_forces_mixed_precision(case):
     assert np.allclose(gm.energy(), om.energy(), rtol=1e-12, atol=1e-12)
 
 
+@pytest.mark.parametrize("K", [1, 2, 5])
+@pytest.mark.parametrize("prec,tol", [(0, 1e-11), (1, 1e-5)])
+def test_md_every_rebuild_interval(K, prec, tol):
+    om = o.Melt(M=7, N=33, seed=13, warmup_steps=200, kappa=1.5)
+    gm = kg.Melt(M=7, N=33, seed=13, warmup_steps=0, kappa=1.5, precision=prec, nl_every=K)
+    transfer(om, gm)
+    assert gm.nl_info()["K"] == K
+    om.md_steps(12)
+    gm.md_steps(12)
+    so, sg = om.get_state(), gm.get_state()
+    assert np.max(np.abs(mi_diff(so["x"], sg["x"], om.L))) < tol
+    assert np.max(np.abs(so["v"] - sg["v"])) < (1e-9 if prec == 0 else 1e-3)
+
+
+def test_stale_lists_roll_back():
+    # a skin far too thin for 5-step rebuilds: the runtime must detect it, redo the steps
+    # with more frequent rebuilds, and still match the oracle
+    om = o.Melt(M=20, N=50, seed=17, warmup_steps=200)
+    gm = kg.Melt(M=20, N=50, seed=17, warmup_steps=0, nl_every=5, nl_skin=0.004)
+    transfer(om, gm)
+    om.md_steps(30)
+    gm.md_steps(30)
+    info = gm.nl_info()
+    assert info["rollbacks"] >= 1 and info["K"] < 5
+    d = mi_diff(om.get_state()["x"], gm.get_state()["x"], om.L)
+    assert np.max(np.abs(d)) < 1e-11
+
+
+def test_autotune_restores_state():
+    gm = kg.Melt(M=20, N=50, seed=3, warmup_steps=100)
+    before = gm.get_state()
+    chosen, ms = gm.autotune(0, reps=5)
+    assert chosen in (1, 2, 5) and all(v > 0 for v in ms.values())
+    after = gm.get_state()
+    for f in ("x", "v", "fl", "chains", "counters"):
+        assert np.array_equal(before[f], after[f]), f
+
+
 def test_forces_full_size_c1():
     # the 200k-monomer workload (200 chains x 1000 beads, kappa = 2, n = 2), both precisions
     om = o.Melt(M=200, N=1000, kappa=2.0, seed=1, warmup_steps=100)
