@@ -43,11 +43,13 @@ enum kgdb_err {
 /* test flags */
 #define KGDB_TF_PHANTOM 1u /* nonbonded pairs off; bonded pairs keep MLJ^n */
 #define KGDB_TF_NOFORCE 2u /* conservative forces off (free Langevin particles) */
+#define KGDB_TF_NL_GLOBAL 4u /* list build reads every neighbourhood from global memory (the path
+                                taken when one does not fit the LDS stage); results unchanged */
 
 /* One melt: M chains of N beads in a cubic periodic box of side (M N / rho)^(1/3).
    Field order is part of the ABI. */
 typedef struct {
-  int32_t M, N;           /* chains, beads per chain (M >= 1, N >= 2)                          */
+  int32_t M, N;           /* chains, beads per chain (1 <= M <= 8192, 2 <= N <= 4096)          */
   double rho;             /* monomer density [sigma^-3]                                        */
   double kappa;           /* angle stiffness of Eq. 4 [eps]                                    */
   double n_exp;           /* repulsive exponent n of Eq. 6 (n > 0, n != 6)                     */
@@ -87,8 +89,9 @@ typedef struct kgdb_batch kgdb_batch;
 /* Create a batch of `count` melts from params[0..count-1] on `hip_stream` (a hipStream_t;
    NULL = the library creates its own).  Each melt is initialised as seeded freely jointed
    random walks with bond 0.97, Maxwell-Boltzmann velocities with the mean removed, and the
-   warm-up of Sec. II.B (small initial timestep, ramped).  Returns KGDB_E_PARAM for invalid
-   parameters, KGDB_E_FENE/NONFINITE if the warm-up fails.  *out is owned by the caller and
+   warm-up of Sec. II.B (small initial timestep, ramped).  A batch holds fewer than 2^24
+   monomers in total.  Returns KGDB_E_PARAM for invalid parameters (or a batch too large),
+   KGDB_E_FENE/NONFINITE if the warm-up fails.  *out is owned by the caller and
    released by kgdb_destroy. */
 int kgdb_init_batch(const kgdb_params* params, int32_t count, void* hip_stream, kgdb_batch** out);
 /* kgdb_init_batch with count = 1 */

@@ -8,7 +8,7 @@ import ctypes as C
 
 import numpy as np
 
-from ._lib import (PREC_FP64, PREC_MIXED, PROPOSAL_LITERAL, PROPOSAL_UNIFORM, TF_NOFORCE,
+from ._lib import (PREC_FP64, PREC_MIXED, PROPOSAL_LITERAL, PROPOSAL_UNIFORM, TF_NL_GLOBAL, TF_NOFORCE,
                    TF_PHANTOM, DbStats, KgdbError, Params, check, load, ptr)
 
 DEFAULTS = dict(M=20, N=50, rho=0.85, kappa=1.5, n_exp=2.0, k_fene=0.0, R0=1.5, T=1.0,

@@ -14,7 +14,7 @@ LIB_PATH = os.path.join(HERE, "libkgdb.so")
 E_PARAM, E_ALLOC, E_HIP, E_FENE, E_NONFINITE, E_OVERFLOW, E_STATE = -1, -2, -3, -4, -5, -6, -7
 PROPOSAL_UNIFORM, PROPOSAL_LEARNED, PROPOSAL_LITERAL = 0, 1, 2
 PREC_FP64, PREC_MIXED = 0, 1
-TF_PHANTOM, TF_NOFORCE = 1, 2
+TF_PHANTOM, TF_NOFORCE, TF_NL_GLOBAL = 1, 2, 4
 
 
 class KgdbError(RuntimeError):

@@ -67,6 +67,8 @@ struct kgdb_batch {
   int nl_ki = 2;                   // its index in NL_KS
   std::vector<MeltDesc> Dk[3];     // descriptors for each rebuild interval of NL_KS
   BlockMap lm[3];                  // list-grid cell blocks for each K
+  BlockMap rm[3];                  // list-build blocks for each K
+  int stage_cap[3] = {0, 0, 0};    // list build: LDS-staged monomers per workgroup for each K
   int* d_cntl[2] = {nullptr, nullptr};
   int cl = 0;                      // list-grid occupancy buffer the next rebuild fills
   int* d_bucketl = nullptr;
@@ -126,6 +128,7 @@ static double fene_kn(double n, double l0, double R0) {
 static int check_params(const kgdb_params& p) {
   if (p.M < 1 || p.N < 2) return fail(KGDB_E_PARAM, "need M >= 1 and N >= 2");
   if (2 * p.N > 8 * 1024) return fail(KGDB_E_PARAM, "N > 4096 is not supported by the sweep kernel");
+  if (p.M > DB_MAX_CHAINS) return fail(KGDB_E_PARAM, "M > 8192 is not supported by the sweep kernel");
   if (!(p.rho > 0) || !(p.R0 > 0) || !(p.T >= 0) || !(p.dt > 0) || !(p.gamma >= 0))
     return fail(KGDB_E_PARAM, "rho, R0, dt must be > 0; T, gamma >= 0");
   if (!(p.n_exp > 0) || p.n_exp == 6.0) return fail(KGDB_E_PARAM, "n must be > 0 and != 6 (Eq. 5 is singular)");
@@ -158,6 +161,16 @@ static void set_list_geometry(MeltDesc& d, const kgdb_params& p, int K) {
   d.hl = d.L / d.ncl;
   d.rlist2 = rl * rl;
   d.half_skin2 = 0.25 * skin * skin;
+  // list-build blocks of about NLB_THREADS monomers: nl_S x nl_Sy cells, (nl_S + 2)(nl_Sy + 2) <= 198
+  const double occ = (double)d.Nm / ((double)d.ncl * d.ncl * d.ncl);
+  const double C = 0.94 * NLB_THREADS / std::max(occ, 1e-6);
+  int Sy = std::max(1, std::min((int)std::lround(std::sqrt(C / 6.0)), d.ncl));
+  int S = std::max(1, std::min((int)std::lround(C / Sy), std::min(64, d.ncl)));
+  while ((S + 2) * (Sy + 2) > 198) { if (Sy > 1) --Sy; else --S; }
+  d.nl_nseg = (d.ncl + S - 1) / S;
+  d.nl_S = (d.ncl + d.nl_nseg - 1) / d.nl_nseg;
+  d.nl_nyb = (d.ncl + Sy - 1) / Sy;
+  d.nl_Sy = (d.ncl + d.nl_nyb - 1) / d.nl_nyb;
 }
 
 static MeltDesc make_desc(const kgdb_params& p) {
@@ -360,6 +373,9 @@ static NlArgs nl_args(kgdb_batch* b) {
   a.pblk_base = b->pm.base;
   a.cblk_melt = b->lm[b->nl_ki].melt;
   a.cblk_base = b->lm[b->nl_ki].base;
+  a.rblk_melt = b->rm[b->nl_ki].melt;
+  a.rblk_base = b->rm[b->nl_ki].base;
+  a.stage_cap = b->stage_cap[b->nl_ki];
   a.NP = b->NP;
   a.x = b->d_x[b->cur];
   a.xn = b->d_x[1 - b->cur];
@@ -389,7 +405,7 @@ static int nl_rebuild(kgdb_batch* b, bool capture) {
     if (b->ev_used == PROF_EVENTS) CHK(prof_flush(b));
     HIPCHK(hipEventRecord(b->ev[4 * b->ev_used + 2], b->s));
   }
-  launch_nl_rebuild(b->prec, nl_args(b), b->pm.nblk, b->lm[b->nl_ki].nblk, b->s);
+  launch_nl_rebuild(b->prec, nl_args(b), b->pm.nblk, b->lm[b->nl_ki].nblk, b->rm[b->nl_ki].nblk, b->s);
   if (prof) HIPCHK(hipEventRecord(b->ev[4 * b->ev_used + 3], b->s));
   b->cl = 1 - b->cl;
   b->rebuild_pending = prof;
@@ -607,10 +623,22 @@ static int build_block_maps(kgdb_batch* b) {
     all.insert(all.end(), melt.begin(), melt.end());
     all.insert(all.end(), base.begin(), base.end());
   }
+  for (int q = 0; q < 3; ++q) {  // list-build row segments for each rebuild interval
+    std::vector<int> melt, base;
+    for (int k = 0; k < b->nm; ++k) {
+      const MeltDesc& d = b->Dk[q][k];
+      const int n = d.ncl * d.nl_nyb * d.nl_nseg;
+      for (int i = 0; i < n; ++i) { melt.push_back(k); base.push_back(i); }
+    }
+    spans.push_back({all.size(), melt.size()});
+    all.insert(all.end(), melt.begin(), melt.end());
+    all.insert(all.end(), base.begin(), base.end());
+  }
   CHK(dalloc(b, &b->d_blk, all.size()));
   HIPCHK(hipMemcpy(b->d_blk, all.data(), all.size() * sizeof(int), hipMemcpyHostToDevice));
-  BlockMap* maps[9] = {&b->pm, &b->cm, &b->fm[0], &b->fm[1], &b->fm[2], &b->fm[3], &b->lm[0], &b->lm[1], &b->lm[2]};
-  for (int m = 0; m < 9; ++m) {
+  BlockMap* maps[12] = {&b->pm,    &b->cm,    &b->fm[0], &b->fm[1], &b->fm[2], &b->fm[3],
+                        &b->lm[0], &b->lm[1], &b->lm[2], &b->rm[0], &b->rm[1], &b->rm[2]};
+  for (int m = 0; m < 12; ++m) {
     maps[m]->melt = b->d_blk + spans[m].first;
     maps[m]->base = b->d_blk + spans[m].first + spans[m].second;
     maps[m]->nblk = (int)spans[m].second;
@@ -646,9 +674,9 @@ static int init_impl(const kgdb_params* params, int32_t count, void* stream, kgd
     b->max_Nm = std::max(b->max_Nm, d.Nm);
     b->D.push_back(d);
   }
-  if (NP >= (1ll << 30) || NC * CELL_CAP >= (1ll << 31) || NC13 * DB_CELL_CAP >= (1ll << 31)) {
+  if (NP >= (1ll << 24) || NC * CELL_CAP >= (1ll << 31) || NC13 * DB_CELL_CAP >= (1ll << 31)) {
     delete b;
-    return fail(KGDB_E_PARAM, "batch too large for 32-bit indexing");
+    return fail(KGDB_E_PARAM, "batch too large (at most 2^24 monomers)");
   }
   b->NP = (int)NP; b->NC = (int)NC; b->NC13 = (int)NC13;
   // list-grid geometry for each rebuild interval; pick the requested or the largest usable
@@ -668,6 +696,19 @@ static int init_impl(const kgdb_params* params, int32_t count, void* stream, kgd
       ncl_max = std::max(ncl_max, off);
     }
     if (ncl_max * NL_CELL_CAP >= (1ll << 31)) { delete b; return fail(KGDB_E_PARAM, "list grid too large"); }
+    // LDS stage of the list build: 1.25 x the largest mean neighbourhood of a block (+ 64); a
+    // block whose neighbourhood does not fit reads it from global memory instead
+    for (int q = 0; q < 3; ++q) {
+      double mx = 0.0;
+      for (int k = 0; k < count; ++k) {
+        const MeltDesc& d = b->Dk[q][k];
+        const double occ = (double)d.Nm / ((double)d.ncl * d.ncl * d.ncl);
+        mx = std::max(mx, 3.0 * (d.nl_S + 2) * (d.nl_Sy + 2) * occ);
+      }
+      b->stage_cap[q] = std::min(b->prec ? 4032 : 2000, ((int)(1.25 * mx) + 64 + 63) / 64 * 64);  // <= 64 KB
+      for (int k = 0; k < count; ++k)
+        if (params[k].test_flags & TF_NL_GLOBAL) b->stage_cap[q] = 0;
+    }
     b->NCL = (int)ncl_max;
     int want = params[0].nl_every;
     for (int k = 1; k < count; ++k)
@@ -728,7 +769,7 @@ static int init_impl(const kgdb_params* params, int32_t count, void* stream, kgd
   }
   step(dalloc(b, &b->d_relb, np));
   step(dalloc(b, &b->d_refc, np));
-  step(dalloc(b, &b->d_nlist, np * NL_CAP));
+  step(dalloc(b, &b->d_nlist, (np + 63) / 64 * 64 * NL_CAP));  // whole 64-monomer tiles
   step(dalloc(b, &b->d_nlen, np));
   step(dalloc(b, &b->d_save, 12 * np));
   step(dalloc(b, &b->d_save_step, (size_t)count));

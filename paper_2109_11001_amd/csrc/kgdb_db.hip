@@ -10,7 +10,7 @@
 //
 // Positions do not change during a sweep, so the set of monomer pairs within db_rmax is built
 // once per sweep; attempts then only look up topology.  One workgroup per melt runs the
-// sweep's attempts in order, holding the sorted candidate list in LDS.
+// sweep, holding the sorted candidate list in LDS.
 //
 // Built with -ffp-contract=off: distances that decide candidate membership are computed with
 // the same operation sequence as their definition.
@@ -236,15 +236,14 @@ __device__ double move_dE(const MeltDesc& d, const int* chain, const int* loc, c
 }
 
 // Candidates involving chain A or B of topology T (each once): scan the monomers of both
-// chains over their close pairs.  Block-cooperative; returns the count to every thread via
-// *s_count (LDS); emits keys into s_new (capacity DB_NEW_CAP) when s_new != nullptr.
+// chains over their close pairs.  Block-cooperative; adds the count to *s_count (LDS) and,
+// when s_new != nullptr, emits the keys into s_new (capacity DB_NEW_CAP, fill count in
+// s_count[1]).
 __device__ void count_touching(const MeltDesc& d, const Topo& T, const DbArgs& a, int A, int B, int* s_count,
                                uint64_t* s_new, uint32_t* s_err) {
   const int N = d.N;
   int local = 0;
-  // the last wavefront computes Delta E meanwhile and takes no part in the scan
-  const int nscan = (int)blockDim.x - 64;
-  for (int idx = threadIdx.x; idx < 2 * N && (int)threadIdx.x < nscan; idx += nscan) {
+  for (int idx = threadIdx.x; idx < 2 * N; idx += blockDim.x) {
     const int X = idx < N ? A : B;
     const int p = (idx < N ? idx : idx - N) + 1;
     const int u = T.at(X, p);
@@ -266,11 +265,6 @@ __device__ void count_touching(const MeltDesc& d, const Topo& T, const DbArgs& a
     }
   }
   if (local) atomicAdd(&s_count[0], local);
-}
-
-__device__ __forceinline__ bool touches(uint64_t key, int M, int N, int A, int B) {
-  const Move m = decode_key(key, M, N);
-  return m.A == A || m.A == B || m.B == A || m.B == B;
 }
 
 // exclusive prefix sum over the block (blockDim = DB_BLOCK); s_tmp holds DB_BLOCK/64 ints
@@ -295,26 +289,66 @@ __device__ int block_exclusive_scan(int v, int* s_tmp, int* s_total) {
   return r;
 }
 
+// the two chains of a key packed as (A << 16) | B
+__device__ __forceinline__ uint32_t key_pair(uint64_t key, int M, int N) {
+  const Move m = decode_key(key, M, N);
+  return ((uint32_t)m.A << 16) | (uint32_t)m.B;
+}
+__device__ __forceinline__ bool pair_touches(uint32_t pr, int A, int B) {
+  const int pa = (int)(pr >> 16), pb = (int)(pr & 0xffffu);
+  return pa == A || pa == B || pb == A || pb == B;
+}
+__device__ __forceinline__ bool touches(uint64_t key, int M, int N, int A, int B) {
+  return pair_touches(key_pair(key, M, N), A, B);
+}
+
+// number of keys < v in the sorted s_keys[0, n), n <= 64 * 64, by one wavefront: a coarse pass
+// over every S-th key, then the S - 1 keys of the bracket it found
+__device__ __forceinline__ int wave_lower_bound(const uint64_t* s_keys, int n, uint64_t v, int lane) {
+  const int S = (n + 63) >> 6;
+  const int pc = lane * S;
+  const int c = __popcll(__ballot(pc < n && s_keys[pc] < v));
+  if (c == 0) return 0;
+  const int b0 = (c - 1) * S + 1, b1 = min(c * S, n);
+  const int pf = b0 + lane;
+  return b0 + __popcll(__ballot(lane < S - 1 && pf < b1 && s_keys[pf] < v));
+}
+
+// one attempt evaluated against the current state (list, chains, positions)
+struct AttemptEval {
+  Move mv;
+  int old_ab;  // |C_AB(x)|: current candidates touching chain A or B
+  int phase;   // 0 reject, 1 needs |C(x')|, 2 accepted by the paper-literal rule
+  int rev;     // both old bonds <= db_rmax (the reverse move is allowed)
+  double dE, u;
+};
+
 // ---------------------------------------------------------------------------------------
-// The sweep: one workgroup per melt, attempts in order.
+// The sweep: one workgroup per melt.  Attempts are a Markov chain, but an attempt that is
+// rejected leaves the state unchanged; so each round evaluates the next DB_WAVES attempts
+// against the current state at once (one wavefront each: its draw, Delta E, the reverse test
+// and |C_AB(x)| from per-chain key counts), then walks them in order.  Attempts up to the
+// first accepted one are final; the ones after it are evaluated again in the next round.
+// Only attempts that pass the early bound recount |C(x')| with the whole workgroup.
 // ---------------------------------------------------------------------------------------
+constexpr int DB_WAVES = DB_BLOCK / 64;
+
 __global__ __launch_bounds__(DB_BLOCK) void k_db_sweep(DbArgs a) {
   __shared__ uint64_t s_keys[2 * DB_CAND_CAP];  // [0, CAP): the sorted list; [CAP, 2CAP): scratch
+  __shared__ uint32_t s_pair[2 * DB_CAND_CAP];  // chain pairs of s_keys, same layout
   __shared__ uint64_t s_new[DB_NEW_CAP];
+  __shared__ int s_cc[DB_MAX_CHAINS];           // keys touching each chain
+  __shared__ AttemptEval s_ev[DB_WAVES];
   __shared__ int s_tmp[DB_BLOCK / 64];
   __shared__ int s_cnt[4];
   __shared__ int s_total;
   __shared__ uint32_t s_err;
-  __shared__ Move s_mv;
   __shared__ int s_accept;
-  __shared__ int s_rev;
-  __shared__ int s_phase;
-  __shared__ double s_dE;
-  __shared__ double s_u;
 
   const int k = blockIdx.x;
   const MeltDesc& d = a.md[k];
   const int M = d.M, N = d.N;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   kgdb_db_stats* st = (kgdb_db_stats*)a.stats + k;
   if (threadIdx.x == 0) {
     st->attempts = st->no_candidate = st->accepted = st->reverse_impossible = st->sum_ncand = 0;
@@ -331,6 +365,7 @@ __global__ __launch_bounds__(DB_BLOCK) void k_db_sweep(DbArgs a) {
   int P = 1;
   while (P < n) P <<= 1;
   for (int t = threadIdx.x; t < P; t += blockDim.x) s_keys[t] = t < n ? a.cand[(size_t)k * DB_CAND_CAP + t] : ~0ull;
+  for (int t = threadIdx.x; t < M; t += blockDim.x) s_cc[t] = 0;
   __syncthreads();
   for (int size = 2; size <= P; size <<= 1)
     for (int stride = size >> 1; stride > 0; stride >>= 1) {
@@ -344,153 +379,195 @@ __global__ __launch_bounds__(DB_BLOCK) void k_db_sweep(DbArgs a) {
       }
       __syncthreads();
     }
+  for (int t = threadIdx.x; t < n; t += blockDim.x) {
+    const uint32_t pr = key_pair(s_keys[t], M, N);
+    s_pair[t] = pr;
+    atomicAdd(&s_cc[pr >> 16], 1);
+    atomicAdd(&s_cc[pr & 0xffffu], 1);
+  }
+  __syncthreads();
 
   const int64_t K = a.nattempt[k];
   const uint64_t sweep = a.sweep_ctr[k];
-  for (int64_t att = 0; att < K; ++att) {
+  const uint64_t kstride = (uint64_t)(N - 1) * (uint64_t)M * (uint64_t)(N - 1) * 2u;  // key span of one first chain
+  int64_t att = 0;
+  while (att < K) {
     if (n == 0) {
-      if (threadIdx.x == 0) { st->attempts++; st->no_candidate++; }
-      continue;
+      if (threadIdx.x == 0) { st->attempts += K - att; st->no_candidate += K - att; }
+      break;
     }
-    if (threadIdx.x == 0) {
-      const U64x4 w = rng_draw(d, (uint64_t)att, sweep, ST_DB);
-      const uint64_t m = rng_choice(w.w[0], (uint64_t)n);
-      s_mv = decode_key(s_keys[m], M, N);
-      s_u = u01(w.w[1]);
-      s_cnt[0] = s_cnt[1] = s_cnt[2] = s_cnt[3] = 0;
-    }
-    __syncthreads();
-    const Move mv = s_mv;
-    // candidates involving A or B now (from the list); Delta E and the reverse-move test on
-    // the last wavefront meanwhile
-    int mine = 0;
-    for (int t = threadIdx.x; t < n; t += blockDim.x) mine += touches(s_keys[t], M, N, mv.A, mv.B) ? 1 : 0;
-    if (mine) atomicAdd(&s_cnt[2], mine);
-    if (threadIdx.x >= blockDim.x - 64) {
-      // one junction per lane: old A, old B, new A, new B; summed in that order
-      const int l = threadIdx.x - (blockDim.x - 64);
-      double e = 0.0;
-      if (l < 4) {
-        const Topo T{a.chain, a.loc, d.off, N, l < 2 ? Move{mv.A, mv.i, mv.B, mv.j, -1} : mv};
-        e = (l & 1) ? junction_energy(d, T, a.x, a.NP, mv.B, mv.j) : junction_energy(d, T, a.x, a.NP, mv.A, mv.i);
-      } else if (l == 4) {
-        const Topo To{a.chain, a.loc, d.off, N, {mv.A, mv.i, mv.B, mv.j, -1}};
-        s_rev = dist2(a.x, a.NP, d.L, To.at(mv.A, mv.i), To.at(mv.A, mv.i + 1)) <= d.rmax2 &&
-                dist2(a.x, a.NP, d.L, To.at(mv.B, mv.j), To.at(mv.B, mv.j + 1)) <= d.rmax2;
+    // ---- evaluate attempts att .. att + DB_WAVES - 1, wavefront wv taking att + wv
+    if (threadIdx.x == 0) s_cnt[0] = s_cnt[1] = s_cnt[2] = s_cnt[3] = 0;
+    if (att + wv < K) {
+      const U64x4 r = rng_draw(d, (uint64_t)(att + wv), sweep, ST_DB);
+      const Move mv = decode_key(s_keys[rng_choice(r.w[0], (uint64_t)n)], M, N);
+      // lanes 0-3: junction energies old A, old B, new A, new B (the old bond lengths also
+      // give the reverse-move test)
+      double e = 0.0, r2 = 0.0;
+      if (lane < 4) {
+        const Topo T{a.chain, a.loc, d.off, N, lane < 2 ? Move{mv.A, mv.i, mv.B, mv.j, -1} : mv};
+        const int X = (lane & 1) ? mv.B : mv.A, kb = (lane & 1) ? mv.j : mv.i;
+        r2 = dist2(a.x, a.NP, d.L, T.at(X, kb), T.at(X, kb + 1));
+        e = junction_energy(d, T, a.x, a.NP, X, kb);
       }
+      // keys with chain pair (A, B) lie among the keys whose first chain is A
+      const int lo = wave_lower_bound(s_keys, n, (uint64_t)mv.A * kstride, lane);
+      const int hi = wave_lower_bound(s_keys, n, (uint64_t)(mv.A + 1) * kstride, lane);
+      const uint32_t want = ((uint32_t)mv.A << 16) | (uint32_t)mv.B;
+      int both = 0;
+      for (int t = lo; t < hi; t += 64) both += __popcll(__ballot(t + lane < hi && s_pair[t + lane] == want));
       const double e1 = __shfl(e, 1, 64), e2 = __shfl(e, 2, 64), e3 = __shfl(e, 3, 64);
-      if (l == 0) s_dE = (e2 + e3) - (e + e1);
-    } else if (a.debug) {
-      Topo To{a.chain, a.loc, d.off, N, {mv.A, mv.i, mv.B, mv.j, -1}};
-      count_touching(d, To, a, mv.A, mv.B, s_cnt + 3, nullptr, &s_err);
-    }
-    __syncthreads();
-    // Decide what can be decided without |C(x')|.  The reverse move is a candidate of x'
-    // whenever it is allowed, so |C(x')| >= |C| - |C_AB(x)| + 1 bounds the Hastings ratio
-    // from above; a draw above that bound rejects exactly as the full ratio would.
-    if (threadIdx.x == 0) {
-      const int old_ab = s_cnt[2];
-      if (a.debug && s_cnt[3] != old_ab) s_err |= ERR_DB_MISMATCH;
-      const double dE = s_dE;
-      st->attempts++;
-      st->sum_ncand += n;
-      int phase = 1;  // 0 reject, 1 count, 2 accept (count only for the commit)
-      if (d.proposal == KGDB_PROPOSAL_LITERAL) {
-        phase = (s_u < exp(-dE / d.T)) ? 2 : 0;
-      } else if (!s_rev) {
-        st->reverse_impossible++;
-        phase = 0;
-      } else if (!(s_u < exp(-dE / d.T) * (double)n / (double)(n - old_ab + 1))) {
-        phase = 0;
+      const double r2b = __shfl(r2, 1, 64);
+      if (lane == 0) {
+        const double dE = (e2 + e3) - (e + e1);
+        const double u = u01(r.w[1]);
+        const int rev = r2 <= d.rmax2 && r2b <= d.rmax2;
+        const int old_ab = s_cc[mv.A] + s_cc[mv.B] - both;
+        // Decide what can be decided without |C(x')|.  The reverse move is a candidate of x'
+        // whenever it is allowed, so |C(x')| >= |C| - |C_AB(x)| + 1 bounds the Hastings ratio
+        // from above; a draw above that bound rejects exactly as the full ratio would.
+        int phase = 1;
+        if (d.proposal == KGDB_PROPOSAL_LITERAL) phase = (u < exp(-dE / d.T)) ? 2 : 0;
+        else if (!rev) phase = 0;
+        else if (!(u < exp(-dE / d.T) * (double)n / (double)(n - old_ab + 1))) phase = 0;
+        AttemptEval& ev = s_ev[wv];
+        ev.mv = mv; ev.old_ab = old_ab; ev.phase = phase; ev.rev = rev; ev.dE = dE; ev.u = u;
       }
-      s_phase = phase;
     }
     __syncthreads();
-    if (s_phase == 0) continue;
-    {
-      Topo Tn{a.chain, a.loc, d.off, N, mv};
-      if ((int)threadIdx.x < (int)blockDim.x - 64) count_touching(d, Tn, a, mv.A, mv.B, s_cnt, s_new, &s_err);
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      const int old_ab = s_cnt[2], new_ab = s_cnt[0];
-      const int n_new = n - old_ab + new_ab;
-      const double dE = s_dE;
-      const double ratio = (s_phase == 2) ? 2.0 : exp(-dE / d.T) * (double)n / (double)n_new;
-      // capacities of the merge: kept keys sit below the sorted new keys in the scratch half
-      const int acc = (s_u < ratio) && (s_cnt[1] <= DB_NEW_CAP) && (n_new <= DB_CAND_CAP) &&
-                      (n - old_ab <= DB_CAND_CAP - DB_NEW_CAP);
-      if ((s_u < ratio) && !acc) s_err |= ERR_CAND_OVERFLOW;
-      if (acc) { st->accepted++; st->sum_dE_accepted += dE; }
-      s_accept = acc;
-    }
-    __syncthreads();
-    if (!s_accept) continue;
+    // ---- walk the evaluated attempts in order
+    const int nev = (int)min((int64_t)DB_WAVES, K - att);
+    int used = nev;
+    for (int w = 0; w < nev; ++w) {
+      const Move mv = s_ev[w].mv;
+      const int phase = s_ev[w].phase, old_ab = s_ev[w].old_ab;
+      if (a.debug) {
+        Topo To{a.chain, a.loc, d.off, N, {mv.A, mv.i, mv.B, mv.j, -1}};
+        count_touching(d, To, a, mv.A, mv.B, s_cnt + 3, nullptr, &s_err);
+        __syncthreads();
+        if (threadIdx.x == 0) {
+          if (s_cnt[3] != old_ab) s_err |= ERR_DB_MISMATCH;
+          s_cnt[3] = 0;
+        }
+        __syncthreads();
+      }
+      if (threadIdx.x == 0) {
+        st->attempts++;
+        st->sum_ncand += n;
+        if (d.proposal != KGDB_PROPOSAL_LITERAL && !s_ev[w].rev) st->reverse_impossible++;
+      }
+      if (phase == 0) continue;
+      {
+        Topo Tn{a.chain, a.loc, d.off, N, mv};
+        count_touching(d, Tn, a, mv.A, mv.B, s_cnt, s_new, &s_err);
+      }
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        const int new_ab = s_cnt[0];
+        const int n_new = n - old_ab + new_ab;
+        const double dE = s_ev[w].dE, u = s_ev[w].u;
+        const double ratio = (phase == 2) ? 2.0 : exp(-dE / d.T) * (double)n / (double)n_new;
+        // capacities of the merge: kept keys sit below the sorted new keys in the scratch half
+        const int acc = (u < ratio) && (s_cnt[1] <= DB_NEW_CAP) && (n_new <= DB_CAND_CAP) &&
+                        (n - old_ab <= DB_CAND_CAP - DB_NEW_CAP);
+        if ((u < ratio) && !acc) s_err |= ERR_CAND_OVERFLOW;
+        if (acc) { st->accepted++; st->sum_dE_accepted += dE; }
+        s_accept = acc;
+      }
+      __syncthreads();
+      if (!s_accept) {
+        if (threadIdx.x == 0) s_cnt[0] = s_cnt[1] = 0;
+        __syncthreads();
+        continue;
+      }
 
-    // ---- commit: new rows of chains A and B (read through the move, then written)
-    {
-      const Topo Tm{a.chain, a.loc, d.off, N, mv};
-      int vals[DB_MAXPT];
+      // ---- commit: new rows of chains A and B (read through the move, then written)
+      {
+        const Topo Tm{a.chain, a.loc, d.off, N, mv};
+        int vals[DB_MAXPT];
 #pragma unroll
-      for (int q = 0; q < DB_MAXPT; ++q) {
-        const int idx = threadIdx.x + q * DB_BLOCK;
-        if (idx < 2 * N) {
-          const int X = idx < N ? mv.A : mv.B;
-          vals[q] = Tm.at(X, (idx < N ? idx : idx - N) + 1);
+        for (int q = 0; q < DB_MAXPT; ++q) {
+          const int idx = threadIdx.x + q * DB_BLOCK;
+          if (idx < 2 * N) {
+            const int X = idx < N ? mv.A : mv.B;
+            vals[q] = Tm.at(X, (idx < N ? idx : idx - N) + 1);
+          }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < DB_MAXPT; ++q) {
+          const int idx = threadIdx.x + q * DB_BLOCK;
+          if (idx < 2 * N) {
+            const int X = idx < N ? mv.A : mv.B;
+            const int p0 = idx < N ? idx : idx - N;
+            a.chain[d.off + X * N + p0] = vals[q];
+            a.loc[vals[q]] = X * N + p0;
+          }
         }
       }
-      __syncthreads();
-#pragma unroll
-      for (int q = 0; q < DB_MAXPT; ++q) {
-        const int idx = threadIdx.x + q * DB_BLOCK;
-        if (idx < 2 * N) {
-          const int X = idx < N ? mv.A : mv.B;
-          const int p0 = idx < N ? idx : idx - N;
-          a.chain[d.off + X * N + p0] = vals[q];
-          a.loc[vals[q]] = X * N + p0;
+      // ---- list update: drop keys touching A or B (order kept), merge the new ones; the
+      // per-chain counts follow
+      {
+        const int nn = s_cnt[1] < DB_NEW_CAP ? s_cnt[1] : DB_NEW_CAP;
+        uint64_t* s_scr = s_keys + DB_CAND_CAP;
+        uint32_t* s_pscr = s_pair + DB_CAND_CAP;
+        // sort the (few) new keys by rank: keys are distinct
+        for (int t = threadIdx.x; t < nn; t += blockDim.x) {
+          const uint64_t key = s_new[t];
+          int r = 0;
+          for (int q = 0; q < nn; ++q) r += s_new[q] < key ? 1 : 0;
+          const uint32_t pr = key_pair(key, M, N);
+          s_scr[DB_CAND_CAP - DB_NEW_CAP + r] = key;  // sorted new keys at the top of the scratch half
+          s_pscr[DB_CAND_CAP - DB_NEW_CAP + r] = pr;
+          atomicAdd(&s_cc[pr >> 16], 1);
+          atomicAdd(&s_cc[pr & 0xffffu], 1);
         }
+        // compact the kept keys into the bottom of the scratch half, in order
+        const int per = (n + DB_BLOCK - 1) / DB_BLOCK;  // <= 3
+        const int t0 = threadIdx.x * per;
+        int keep = 0;
+        for (int q = 0; q < per; ++q)
+          if (t0 + q < n && !pair_touches(s_pair[t0 + q], mv.A, mv.B)) ++keep;
+        const int pos0 = block_exclusive_scan(keep, s_tmp, &s_total);
+        const int nk = s_total;
+        int pos = pos0;
+        for (int q = 0; q < per; ++q) {
+          if (t0 + q >= n) break;
+          const uint32_t pr = s_pair[t0 + q];
+          if (!pair_touches(pr, mv.A, mv.B)) {
+            s_scr[pos] = s_keys[t0 + q];
+            s_pscr[pos++] = pr;
+          } else {
+            atomicSub(&s_cc[pr >> 16], 1);
+            atomicSub(&s_cc[pr & 0xffffu], 1);
+          }
+        }
+        __syncthreads();
+        const uint64_t* s_ns = s_scr + (DB_CAND_CAP - DB_NEW_CAP);
+        const uint32_t* s_nsp = s_pscr + (DB_CAND_CAP - DB_NEW_CAP);
+        // merge: kept key at r goes to r + #(new < key); new key at q to q + #(kept < key)
+        for (int t = threadIdx.x; t < nk; t += blockDim.x) {
+          const uint64_t key = s_scr[t];
+          int lo = 0, hi = nn;
+          while (lo < hi) { const int mid = (lo + hi) >> 1; if (s_ns[mid] < key) lo = mid + 1; else hi = mid; }
+          s_keys[t + lo] = key;
+          s_pair[t + lo] = s_pscr[t];
+        }
+        for (int t = threadIdx.x; t < nn; t += blockDim.x) {
+          const uint64_t key = s_ns[t];
+          int lo = 0, hi = nk;
+          while (lo < hi) { const int mid = (lo + hi) >> 1; if (s_scr[mid] < key) lo = mid + 1; else hi = mid; }
+          s_keys[t + lo] = key;
+          s_pair[t + lo] = s_nsp[t];
+        }
+        n = nk + nn;
+        __syncthreads();
       }
+      used = w + 1;  // attempts after an accepted one are evaluated again
+      break;
     }
-    // ---- list update: drop keys touching A or B (order kept), merge the new ones
-    {
-      const int nn = s_cnt[1] < DB_NEW_CAP ? s_cnt[1] : DB_NEW_CAP;
-      // sort the (few) new keys by rank: keys are distinct
-      uint64_t* s_scr = s_keys + DB_CAND_CAP;
-      for (int t = threadIdx.x; t < nn; t += blockDim.x) {
-        const uint64_t key = s_new[t];
-        int r = 0;
-        for (int q = 0; q < nn; ++q) r += s_new[q] < key ? 1 : 0;
-        s_scr[DB_CAND_CAP - DB_NEW_CAP + r] = key;  // sorted new keys at the top of the scratch half
-      }
-      // compact the kept keys into the bottom of the scratch half, in order
-      const int per = (n + DB_BLOCK - 1) / DB_BLOCK;  // <= 3
-      const int t0 = threadIdx.x * per;
-      int keep = 0;
-      for (int q = 0; q < per; ++q)
-        if (t0 + q < n && !touches(s_keys[t0 + q], M, N, mv.A, mv.B)) ++keep;
-      const int pos0 = block_exclusive_scan(keep, s_tmp, &s_total);
-      const int nk = s_total;
-      int pos = pos0;
-      for (int q = 0; q < per; ++q)
-        if (t0 + q < n && !touches(s_keys[t0 + q], M, N, mv.A, mv.B)) s_scr[pos++] = s_keys[t0 + q];
-      __syncthreads();
-      const uint64_t* s_ns = s_scr + (DB_CAND_CAP - DB_NEW_CAP);
-      // merge: kept key at r goes to r + #(new < key); new key at q to q + #(kept < key)
-      for (int t = threadIdx.x; t < nk; t += blockDim.x) {
-        const uint64_t key = s_scr[t];
-        int lo = 0, hi = nn;
-        while (lo < hi) { const int mid = (lo + hi) >> 1; if (s_ns[mid] < key) lo = mid + 1; else hi = mid; }
-        s_keys[t + lo] = key;
-      }
-      for (int t = threadIdx.x; t < nn; t += blockDim.x) {
-        const uint64_t key = s_ns[t];
-        int lo = 0, hi = nk;
-        while (lo < hi) { const int mid = (lo + hi) >> 1; if (s_scr[mid] < key) lo = mid + 1; else hi = mid; }
-        s_keys[t + lo] = key;
-      }
-      n = nk + nn;
-      __syncthreads();
-    }
+    att += used;
+    __syncthreads();  // s_ev and s_cnt are rewritten by the next round
   }
   if (threadIdx.x == 0) {
     st->ncand_end = n;

@@ -13,6 +13,8 @@ constexpr int DB_CELL_CAP = 64;   // monomers per cell of the double-bridging gr
 constexpr int DB_NBR_CAP = 64;    // monomers within db_rmax of one monomer
 constexpr int DB_CAND_CAP = 3072; // candidate keys per melt (held in LDS during a sweep)
 constexpr int DB_NEW_CAP = 1024;  // candidates touching the two chains of one move
+constexpr int DB_MAX_CHAINS = 8192; // chains per melt (per-chain key counts held in LDS during a sweep)
+constexpr int NLB_THREADS = 256;  // list-build workgroup: about this many home monomers per block
 constexpr int NL_CELL_CAP = 32;   // monomers per cell of the neighbour-list grid
 constexpr int NL_CAP = 64;        // neighbour-list entries per monomer
 
@@ -31,7 +33,7 @@ enum : uint32_t {
 // Philox counter word 2: the random-number stream
 enum : uint64_t { ST_WALK = 1, ST_VEL = 2, ST_LANGEVIN = 3, ST_DB = 4, ST_WARMUP = 5 };
 
-enum : uint32_t { TF_PHANTOM = 1u, TF_NOFORCE = 2u };
+enum : uint32_t { TF_PHANTOM = 1u, TF_NOFORCE = 2u, TF_NL_GLOBAL = 4u };
 
 // Per-melt constants, laid out for scalar loads (the melt index is uniform per workgroup).
 struct MeltDesc {
@@ -59,7 +61,9 @@ struct MeltDesc {
   double lang_amp;           // sqrt(2 gamma T / dt)
   uint64_t seed, melt_id;    // Philox key
   uint32_t test_flags;
-  int pad;
+  // list build: each workgroup takes a block of nl_S x nl_Sy cells of one z-plane of the list
+  // grid (nl_nseg blocks along x, nl_nyb along y) and stages its neighbourhood in LDS
+  int nl_S, nl_Sy, nl_nseg, nl_nyb;
 };
 
 // ---------------------------------------------------------------------------------------

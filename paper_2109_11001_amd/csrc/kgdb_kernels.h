@@ -77,6 +77,8 @@ struct NlArgs {
   const int* pblk_base;
   const int* cblk_melt;  // list-grid cell blocks (256 per block)
   const int* cblk_base;
+  const int* rblk_melt;  // list-build blocks: nl_S x nl_Sy cells of one z-plane each
+  const int* rblk_base;  // (z * nl_nyb + y block) * nl_nseg + x block
   int NP;
   const double* x;
   double* xn;
@@ -90,7 +92,7 @@ struct NlArgs {
   void* rel_next;
   float4* relb;    // relative positions at the last rebuild
   int* refc;       // packed reference cell of each monomer
-  uint32_t* nlist; // [NL_CAP][NP]: (slot << 5) | cell-offset code
+  uint32_t* nlist; // tiles of 64 monomers x NL_CAP entries: (slot << 5) | cell-offset code
   int* nlen;
   const int* chain;
   const int* loc;
@@ -98,8 +100,10 @@ struct NlArgs {
   const uint64_t* step_base;
   uint32_t* err;
   uint32_t s_off;
+  int stage_cap;   // list build: staged monomers per workgroup held in LDS
 };
-void launch_nl_rebuild(int prec, const NlArgs& a, int pblk, int cblk, hipStream_t s);
+size_t nl_stage_bytes(int prec, int cap);  // dynamic LDS of the list build
+void launch_nl_rebuild(int prec, const NlArgs& a, int pblk, int cblk, int rblk, hipStream_t s);
 void launch_nl_step(int prec, int mode, const NlArgs& a, int pblk, hipStream_t s);
 size_t rel_bytes(int prec);
 

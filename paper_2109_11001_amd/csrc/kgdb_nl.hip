@@ -3,8 +3,10 @@
 // Rebuild (every K steps): bin the monomers into a grid of cells of edge >= r_list = r_c + skin
 // (counting sort with id-ordered buckets), record for each monomer its reference cell and its
 // position relative to that cell's origin, and list the monomers within r_list in the 27
-// neighbouring cells together with the cell offset (a 5-bit code).  Lists are column-major
-// (entry k of monomer i at k * NP + i) so that a wavefront reads them coalesced.
+// neighbouring cells together with the cell offset (a 5-bit code), from neighbourhoods staged
+// in LDS one row segment at a time.  Lists are stored in tiles of 64 monomers: entries
+// 4q .. 4q + 3 of monomer i form one 16-byte word at ((i / 64) * NL_CAP / 4 + q) * 64 + i % 64,
+// so a wavefront of consecutive monomers reads (and the build writes) 1 KB runs.
 //
 // Step: one kernel per step; one thread per monomer runs the truncated MLJ^n pair force over
 // its list (displacements from reference-cell-relative coordinates, so FP32 keeps full
@@ -98,72 +100,188 @@ __global__ __launch_bounds__(256) void k_nl_finalize(NlArgs a) {
 
 // ---------------------------------------------------------------------------------------
 // rebuild 3: neighbour lists (all monomers within r_list, bonded ones included: every pair
-// feels MLJ^n once)
+// feels MLJ^n once).  One workgroup per block of nl_S x nl_Sy home cells in one z-plane of
+// the list grid: it stages the members of the (nl_S + 2) x (nl_Sy + 2) x 3 cells around the
+// block in LDS, then each thread lists one home monomer.  Candidates are visited row by row
+// (oz, then oy), the row's three cells in x order, each bucket in slot order.
 // ---------------------------------------------------------------------------------------
-template <typename R>
-__global__ __launch_bounds__(256) void k_nl_build(NlArgs a) {
-  const int lb = xcd_remap(blockIdx.x, gridDim.x);
-  const int k = __builtin_amdgcn_readfirstlane(a.pblk_melt[lb]);
-  const MeltDesc& d = a.md[k];
-  const int li = a.pblk_base[lb] + (int)threadIdx.x;
-  if (li >= d.Nm) return;
-  const int NP = a.NP;
-  const int g = d.off + li;
-  const Rel4<R>* __restrict__ rel = (const Rel4<R>*)a.rel_cur;
-  const Rel4<R> ri = rel[g];
-  const int pc = a.refc[g];
-  const int cx = pc & 1023, cy = (pc >> 10) & 1023, cz = pc >> 20;
-  const int nc = d.ncl;
-  const R hl = (R)d.hl, rl2 = (R)d.rlist2;
+constexpr int NLB_CELLS = 594;   // staged cells: 3 (nl_S + 2)(nl_Sy + 2) <= 594
+
+// A staged monomer: position in the block frame (origin at the corner of the first home cell,
+// so displacements need no per-cell offsets) and tag = (slot << 8) | (9 zz + 3 yy + i + 1) for
+// staged cell (x index i, y index yy, z index zz).  For a pair, the tag difference plus 13
+// is the 27-cell offset code of the list entry.
+template <typename R> struct alignas(16) Staged { R x, y, z; uint32_t tag; };
+
+// 16-byte word q of monomer i's list
+__device__ __forceinline__ size_t nl_word(int i, int q) {
+  return ((size_t)(i >> 6) * (NL_CAP / 4) + (size_t)q) * 64 + (size_t)(i & 63);
+}
+
+// The list of one home monomer (staged x index ih, y index yy); at(t, tmax) gives staged member
+// t, or any valid member when t > tmax.
+// Hits of a run of up to 32 candidates are collected as a bit mask first, then appended in
+// order, four entries per 16-byte store.
+template <typename R, typename At>
+__device__ __forceinline__ void nl_list_one(const NlArgs& a, int k, const Staged<R>& me, int ih, int yy, int W,
+                                            int WY, R rl2, const int* s_off, At at) {
+  uint4* __restrict__ out = (uint4*)a.nlist;
+  const int g = (int)(me.tag >> 8);
+  const uint32_t hv = (me.tag & 255u) - 13u;
+  uint4 acc = make_uint4(0, 0, 0, 0);  // the entries of the word being filled
   int cnt = 0;
-  int xs[3];
+  for (int zz = 0; zz < 3; ++zz) {
+    for (int dy = -1; dy <= 1; ++dy) {
+      const int c0 = (zz * WY + yy + dy) * W + ih - 1;  // cells c0 .. c0 + 2: x offsets -1, 0, +1
+      const int b = s_off[c0], e = s_off[c0 + 3];
+      for (int r0 = b; r0 < e; r0 += 32) {
+        const int re = min(e, r0 + 32);
+        uint32_t m = 0;
+        for (int t0 = r0; t0 < re; t0 += 4) {
+          // at() may read up to three entries past the run (masked below)
+          Staged<R> p[4];
 #pragma unroll
-  for (int ox = -1; ox <= 1; ++ox) {
-    int nx = cx + ox; nx += (nx < 0) ? nc : 0; nx -= (nx >= nc) ? nc : 0;
-    xs[ox + 1] = nx;
-  }
-  // 9 rows of 3 cells; each row's members are walked as one flattened sequence, four at a
-  // time (independent id and position loads)
-  for (int oz = -1; oz <= 1; ++oz) {
-    int nz = cz + oz; nz += (nz < 0) ? nc : 0; nz -= (nz >= nc) ? nc : 0;
-    for (int oy = -1; oy <= 1; ++oy) {
-      int ny = cy + oy; ny += (ny < 0) ? nc : 0; ny -= (ny >= nc) ? nc : 0;
-      const int row = d.celll_off + (nz * nc + ny) * nc;
-      const int c0 = row + xs[0], c1 = row + xs[1], c2 = row + xs[2];
-      const int n0 = min(a.cnt[c0], NL_CELL_CAP), n1 = min(a.cnt[c1], NL_CELL_CAP), n2 = min(a.cnt[c2], NL_CELL_CAP);
-      const int tot = n0 + n1 + n2;
-      const R sy = (R)oy * hl - ri.y, sz = (R)oz * hl - ri.z;
-      const uint32_t code_yz = (uint32_t)(3 * (oy + 1) + 9 * (oz + 1));
-      for (int t0 = 0; t0 < tot; t0 += 4) {
-        int id[4], ox[4];
-        bool ok[4];
+          for (int u = 0; u < 4; ++u) p[u] = at(t0 + u, re - 1);
+          uint32_t nib = 0;  // straight-line: no branches per candidate
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int t = t0 + u;
-          ok[u] = t < tot;
-          const int w = t < n0 ? 0 : (t < n0 + n1 ? 1 : 2);
-          const int cc = w == 0 ? c0 : (w == 1 ? c1 : c2);
-          const int j = t - (w == 0 ? 0 : (w == 1 ? n0 : n0 + n1));
-          ox[u] = w - 1;
-          id[u] = ok[u] ? a.bucket[cc * NL_CELL_CAP + j] : g;
-        }
-        Rel4<R> p[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) p[u] = rel[id[u]];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          if (!ok[u] || id[u] == g) continue;
-          const R dx = p[u].x + (R)ox[u] * hl - ri.x, dy = p[u].y + sy, dz = p[u].z + sz;
-          if (dx * dx + dy * dy + dz * dz < rl2) {
-            if (cnt < NL_CAP) a.nlist[(size_t)cnt * NP + g] = ((uint32_t)id[u] << 5) | (code_yz + (uint32_t)(ox[u] + 1));
-            ++cnt;
+          for (int u = 0; u < 4; ++u) {
+            const R dx = p[u].x - me.x, dy2 = p[u].y - me.y, dz = p[u].z - me.z;
+            nib |= (uint32_t)(dx * dx + dy2 * dy2 + dz * dz < rl2) << u;
           }
+          const int rem = re - t0;
+          nib &= rem >= 4 ? 15u : ((1u << rem) - 1u);
+          m |= nib << (t0 - r0);
+        }
+        while (m) {
+          const int bit = __builtin_ctz(m);
+          m &= m - 1;
+          const uint32_t tag = at(r0 + bit, r0 + bit).tag;
+          if (tag == me.tag) continue;  // the home monomer itself
+          // entry = (slot << 5) | (9 (oz + 1) + 3 (oy + 1) + ox + 1)
+          const uint32_t en = ((tag >> 3) & ~31u) | ((tag & 255u) - hv);
+          const int sl = cnt & 3;
+          acc.x = sl == 0 ? en : acc.x;
+          acc.y = sl == 1 ? en : acc.y;
+          acc.z = sl == 2 ? en : acc.z;
+          acc.w = sl == 3 ? en : acc.w;
+          if (sl == 3 && cnt < NL_CAP) out[nl_word(g, cnt >> 2)] = acc;
+          ++cnt;
         }
       }
     }
   }
+  if ((cnt & 3) && cnt < NL_CAP) out[nl_word(g, cnt >> 2)] = acc;  // the partial last word
   if (cnt > NL_CAP) { atomicOr(&a.err[k], ERR_NLIST_OVERFLOW); cnt = NL_CAP; }
   a.nlen[g] = cnt;
+}
+
+template <typename R>
+__global__ __launch_bounds__(NLB_THREADS) void k_nl_build(NlArgs a) {
+  // a.stage_cap staged members (+ 4 of padding for reads past a run) in dynamic LDS
+  extern __shared__ __align__(16) unsigned char s_dyn[];
+  Staged<R>* s_pos = (Staged<R>*)s_dyn;
+  __shared__ int s_off[NLB_CELLS + 1];  // staged cell -> first staged member
+  const int lb = xcd_remap(blockIdx.x, gridDim.x);
+  const int k = __builtin_amdgcn_readfirstlane(a.rblk_melt[lb]);
+  const MeltDesc& d = a.md[k];
+  const int nc = d.ncl, nseg = d.nl_nseg, nyb = d.nl_nyb, S = d.nl_S, Sy = d.nl_Sy;
+  const int W = S + 2, WY = Sy + 2;
+  int rb = a.rblk_base[lb];
+  const int seg = rb % nseg;
+  rb /= nseg;
+  const int yb = rb % nyb, cz = rb / nyb;
+  const int x0 = seg * S, nh = min(S, nc - x0);   // home cells x0 .. x0 + nh - 1
+  const int y0 = yb * Sy, nhy = min(Sy, nc - y0); // and rows y0 .. y0 + nhy - 1
+  const int ncell = 3 * WY * W;
+  const R hl = (R)d.hl;
+  const Rel4<R>* __restrict__ rel = (const Rel4<R>*)a.rel_cur;
+
+  // staged cell t = (zz WY + yy) W + i sits at x = x0 - 1 + i, y = y0 - 1 + yy, z = cz - 1 + zz
+  auto cell_of = [&](int t) {
+    const int row = t / W, i = t - row * W;
+    const int zz = row / WY, yy = row - zz * WY;
+    const int nz = (cz - 1 + zz + nc) % nc, ny = (y0 - 1 + yy + nc) % nc, nx = (x0 - 1 + i + nc) % nc;
+    return d.celll_off + (nz * nc + ny) * nc + nx;
+  };
+  for (int t = threadIdx.x; t < ncell; t += NLB_THREADS) s_off[t + 1] = min(a.cnt[cell_of(t)], NL_CELL_CAP);
+  __syncthreads();
+  if (threadIdx.x < 64) {  // inclusive scan of the counts by one wavefront
+    const int lane = threadIdx.x;
+    const int per = (ncell + 63) >> 6;
+    int sum = 0;
+    for (int q = 0; q < per; ++q) { const int t = lane * per + q; if (t < ncell) sum += s_off[t + 1]; }
+    int incl = sum;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) { const int v = __shfl_up(incl, o, 64); if (lane >= o) incl += v; }
+    int acc = incl - sum;
+    for (int q = 0; q < per; ++q) {
+      const int t = lane * per + q;
+      if (t < ncell) { acc += s_off[t + 1]; s_off[t + 1] = acc; }
+    }
+    if (lane == 0) s_off[0] = 0;
+  }
+  __syncthreads();
+  const int total = s_off[ncell];
+  const bool staged = total <= a.stage_cap;
+  // member t of the stage (or of the neighbourhood when it does not fit): its cell by
+  // bisection of s_off, then its slot, frame position and tag
+  auto member = [&](int t) -> Staged<R> {
+    int lo = 0, hi = ncell;
+    while (hi - lo > 1) { const int mid = (lo + hi) >> 1; if (s_off[mid] <= t) lo = mid; else hi = mid; }
+    const int id = a.bucket[cell_of(lo) * NL_CELL_CAP + (t - s_off[lo])];
+    const Rel4<R> p = rel[id];
+    const int row = lo / W, i = lo - row * W;
+    const int zz = row / WY, yy = row - zz * WY;
+    Staged<R> m;
+    m.x = p.x + (R)(i - 1) * hl;
+    m.y = p.y + (R)(yy - 1) * hl;
+    m.z = p.z + (R)(zz - 1) * hl;
+    m.tag = ((uint32_t)id << 8) | (uint32_t)(9 * zz + 3 * yy + i + 1);
+    return m;
+  };
+  if (staged) {
+    for (int t0 = threadIdx.x; t0 < total; t0 += 2 * NLB_THREADS) {
+      Staged<R> m[2];
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int t = t0 + u * NLB_THREADS;
+        if (t < total) m[u] = member(t);
+      }
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int t = t0 + u * NLB_THREADS;
+        if (t < total) s_pos[t] = m[u];
+      }
+    }
+  }
+  __syncthreads();
+
+  // home members: rows yy = 1 .. nhy of z index 1, cells i = 1 .. nh of each
+  int nhome = 0;
+  for (int yy = 1; yy <= nhy; ++yy) {
+    const int c = (WY + yy) * W + 1;
+    nhome += s_off[c + nh] - s_off[c];
+  }
+  // the bound carries a 1e-4 relative margin for the rounding of frame coordinates
+  const R rl2 = (R)(d.rlist2 * 1.0002);
+  for (int h = threadIdx.x; h < nhome; h += NLB_THREADS) {
+    int yy = 1, q = h;
+    for (;; ++yy) {
+      const int c = (WY + yy) * W + 1;
+      const int n = s_off[c + nh] - s_off[c];
+      if (q < n || yy == nhy) break;
+      q -= n;
+    }
+    const int c1 = (WY + yy) * W + 1;
+    const int t = s_off[c1] + q;
+    int lo = c1, hi = c1 + nh;
+    while (hi - lo > 1) { const int mid = (lo + hi) >> 1; if (s_off[mid] <= t) lo = mid; else hi = mid; }
+    const int ih = lo - (WY + yy) * W;
+    if (staged)
+      nl_list_one(a, k, s_pos[t], ih, yy, W, WY, rl2, s_off, [&](int u, int) { return s_pos[u]; });
+    else
+      nl_list_one(a, k, member(t), ih, yy, W, WY, rl2, s_off, [&](int u, int umax) { return member(min(u, umax)); });
+  }
 }
 
 template <typename R> struct W3 { R x, y, z; };
@@ -236,21 +354,17 @@ __global__ __launch_bounds__(256) void k_nl_step(NlArgs a) {
       const int ox = code % 3 - 1, oy = (code / 3) % 3 - 1, oz = code / 9 - 1;
       pair_add(rj.x + (R)ox * hl - ri.x, rj.y + (R)oy * hl - ri.y, rj.z + (R)oz * hl - ri.z);
     };
-    int t = 0;
-    // four entries per round: their loads are independent, so the gathers overlap
-    for (; t + 4 <= n; t += 4) {
-      uint32_t e[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) e[u] = a.nlist[(size_t)(t + u) * NP + g];
+    const uint4* __restrict__ words = (const uint4*)a.nlist;
+    // one 16-byte word (four entries) per round; the four gathers are independent
+    for (int t = 0; t < n; t += 4) {
+      const uint4 q = words[nl_word(g, t >> 2)];
+      const uint32_t e[4] = {q.x, q.y, q.z, q.w};
       Rel4<R> rj[4];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) rj[u] = rel[e[u] >> 5];
+      for (int u = 0; u < 4; ++u) rj[u] = rel[(t + u < n) ? (e[u] >> 5) : g];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) entry(e[u], rj[u]);
-    }
-    for (; t < n; ++t) {
-      const uint32_t e = a.nlist[(size_t)t * NP + g];
-      entry(e, rel[e >> 5]);
+      for (int u = 0; u < 4; ++u)
+        if (t + u < n) entry(e[u], rj[u]);
     }
   }
 
@@ -344,14 +458,18 @@ __global__ __launch_bounds__(256) void k_nl_step(NlArgs a) {
 }
 
 // ---------------------------------------------------------------------------------------
-void launch_nl_rebuild(int prec, const NlArgs& a, int pblk, int cblk, hipStream_t s) {
+size_t nl_stage_bytes(int prec, int cap) {
+  return (size_t)(cap + 4) * (prec ? sizeof(Staged<float>) : sizeof(Staged<double>));
+}
+
+void launch_nl_rebuild(int prec, const NlArgs& a, int pblk, int cblk, int rblk, hipStream_t s) {
   hipLaunchKernelGGL(k_nl_bin, dim3(pblk), dim3(256), 0, s, a);
   if (prec) {
     hipLaunchKernelGGL(k_nl_finalize<float>, dim3(cblk), dim3(256), 0, s, a);
-    hipLaunchKernelGGL(k_nl_build<float>, dim3(pblk), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_nl_build<float>, dim3(rblk), dim3(NLB_THREADS), nl_stage_bytes(1, a.stage_cap), s, a);
   } else {
     hipLaunchKernelGGL(k_nl_finalize<double>, dim3(cblk), dim3(256), 0, s, a);
-    hipLaunchKernelGGL(k_nl_build<double>, dim3(pblk), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_nl_build<double>, dim3(rblk), dim3(NLB_THREADS), nl_stage_bytes(0, a.stage_cap), s, a);
   }
 }
 

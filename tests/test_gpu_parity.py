@@ -207,6 +207,21 @@ def test_graph_equals_direct_and_is_deterministic():
         assert np.array_equal(sa[f], sc[f]), f
 
 
+@pytest.mark.parametrize("prec", [1, 0])
+def test_list_build_global_path_equals_lds_path(prec):
+    # the list build stages each neighbourhood in LDS and falls back to global reads when one
+    # does not fit; both paths must give the same lists, hence identical trajectories
+    kw = dict(M=40, N=100, seed=12, warmup_steps=200, precision=prec, nl_every=5)
+    a = kg.Melt(**kw)
+    b = kg.Melt(**dict(kw, test_flags=kg.TF_NL_GLOBAL))
+    a.md_steps(60, graph=False)
+    b.md_steps(60, graph=False)
+    sa, sb = a.get_state(), b.get_state()
+    for f in ("x", "v", "fc"):
+        assert np.array_equal(sa[f], sb[f]), f
+    assert a.nl_info()["mean_list"] == b.nl_info()["mean_list"]
+
+
 def test_nve_energy_conservation_gpu():
     base = o.Melt(M=10, N=40, n_exp=8.0, kappa=1.0, seed=3, warmup_steps=500)
     st = base.get_state()
