@@ -803,6 +803,14 @@ int kgdbref_apply_move(melt_t *m, int32_t A, int32_t i, int32_t B, int32_t j, in
   return OR_OK;
 }
 
+/* optional record of the attempts of uniform sweeps (training data of the learned
+   proposal): inputs of each proposed move at the topology it was proposed in, and whether
+   it was accepted */
+static float *g_log_feat;
+static int32_t *g_log_label;
+static int64_t g_log_cap, g_log_n;
+int kgdbref_features(melt_t *m, const uint64_t *keys, int64_t n, float *out);
+
 /* One double-bridging attempt (Fig. 1 with the exact Metropolis-Hastings correction
    for a proposal uniform over the current candidate set). */
 static int db_attempt(melt_t *m, uint64_t attempt, int brute, kgdbref_stats *st) {
@@ -817,6 +825,12 @@ static int db_attempt(melt_t *m, uint64_t attempt, int brute, kgdbref_stats *st)
   draw(m->p.seed, (uint64_t)m->p.melt_id, attempt, m->sweep, ST_DB, w);
   uint64_t key = keys[choice(w[0], (uint64_t)n)];
   free(keys);
+  int64_t log_at = -1;
+  if (g_log_feat && g_log_n < g_log_cap) { /* training record: inputs of the proposed move */
+    log_at = g_log_n++;
+    kgdbref_features(m, &key, 1, g_log_feat + log_at * 25);
+    g_log_label[log_at] = 0;
+  }
   int A, i, B, j, var;
   key_decode(m, key, &A, &i, &B, &j, &var);
   int32_t *nc = (int32_t *)malloc(sizeof(int32_t) * m->Nm);
@@ -841,6 +855,7 @@ static int db_attempt(melt_t *m, uint64_t attempt, int brute, kgdbref_stats *st)
     memcpy(m->chain, nc, sizeof(int32_t) * m->Nm);
     st->accepted++;
     st->sum_dE_accepted += dE;
+    if (log_at >= 0) g_log_label[log_at] = 1;
   }
   free(nc);
   return OR_OK;
@@ -861,6 +876,16 @@ int kgdbref_db_sweep(melt_t *m, int64_t K, int32_t brute, kgdbref_stats *st) {
   m->last_sweep_step = m->step;
   m->fc_valid = 0;
   return OR_OK;
+}
+
+/* a uniform sweep that records each attempt with candidates: feat [cap][25], label [cap] */
+int kgdbref_db_sweep_log(melt_t *m, int64_t K, int32_t brute, kgdbref_stats *st, float *feat, int32_t *label,
+                         int64_t cap, int64_t *nlog) {
+  g_log_feat = feat; g_log_label = label; g_log_cap = cap; g_log_n = 0;
+  int rc = kgdbref_db_sweep(m, K, brute, st);
+  *nlog = g_log_n;
+  g_log_feat = NULL; g_log_label = NULL; g_log_cap = 0; g_log_n = 0;
+  return rc;
 }
 
 /* ------------------------------------------------------------------------------------ */
@@ -930,4 +955,360 @@ int kgdbref_observables(melt_t *m, double *r2n, double *ellK, double *meanbond) 
   if (ellK) rc = kgdbref_fit_ellK(r2n, N, l0, ellK);
   free(s); free(acc);
   return rc;
+}
+
+/* ------------------------------------------------------------------------------------ */
+/* Learned double-bridging proposal (a project extension: the paper proposes uniformly  */
+/* over the candidate set).  A small network scores each candidate move from the local  */
+/* geometry of its two bonds; moves are proposed from a mixture of the softmax of the   */
+/* scores and the uniform proposal, and the Metropolis-Hastings ratio uses the forward  */
+/* probability of the move and the probability of the same (involutive) move from the   */
+/* new state, so the sampled distribution stays exp(-E/T).                              */
+/*                                                                                      */
+/* Network: 25 inputs -> 128 -> 128 -> 128 -> 1 logit, ReLU.  Quantisation (so that a   */
+/* matrix-core evaluation with FP32 accumulation is exact in any summation order):      */
+/*   weights  = code / 64, code = clamp(rint(64 w), -255, 255)                          */
+/*   inputs   = code / 64, code = clamp(rint(64 f), -255, 255)                          */
+/*   hidden   = code / 16, code = clamp(rint(16 max(z, 0)), 0, 255)                     */
+/*   z        = fl32(S + b) with S the exact dot product (|S| < 2^24 units) and b FP32  */
+/* Parameter vector (FP32): W1[128][25], b1[128], W2[128][128], b2[128], W3[128][128],  */
+/* b3[128], w4[128], b4.                                                                */
+/* ------------------------------------------------------------------------------------ */
+#define NN_IN 25
+#define NN_H 128
+#define NN_OFF_W1 0
+#define NN_OFF_B1 (NN_OFF_W1 + NN_H * NN_IN)
+#define NN_OFF_W2 (NN_OFF_B1 + NN_H)
+#define NN_OFF_B2 (NN_OFF_W2 + NN_H * NN_H)
+#define NN_OFF_W3 (NN_OFF_B2 + NN_H)
+#define NN_OFF_B3 (NN_OFF_W3 + NN_H * NN_H)
+#define NN_OFF_W4 (NN_OFF_B3 + NN_H)
+#define NN_OFF_B4 (NN_OFF_W4 + NN_H)
+#define NN_NPARAM (NN_OFF_B4 + 1)
+#define NN_LOGIT_CLAMP 40.0
+#define NN_HMAX (255.0f / 16.0f)
+
+int32_t kgdbref_mlp_nparam(void) { return NN_NPARAM; }
+
+static int nn_clamp255(double r, int lo) {
+  if (r > 255.0) return 255;
+  if (r < (double)lo) return lo;
+  return (int)r;
+}
+static int q_weight(float w) { return nn_clamp255(rint((double)w * 64.0), -255); }
+static int q_input(double f) { return nn_clamp255(rint(f * 64.0), -255); }
+static int q_hidden(float z) {
+  if (!(z > 0.0f)) return 0;
+  float t = z * 16.0f;
+  return nn_clamp255((double)rintf(t), 0);
+}
+
+/* Inputs of candidate `key` in topology `chain`.  The four beads around bond i of chain A
+   are (a_{i-1}, a_i, a_{i+1}, a_{i+2}); the four around bond j of chain B are ordered so
+   that the new bonds join inputs 1-5 and 2-6: (b_{j+2}, b_{j+1}, b_j, b_{j-1}) for P,
+   (b_{j-1}, b_j, b_{j+1}, b_{j+2}) for AP.  After the move the local chains read 0-1-5-4
+   and 3-2-6-7, before it 0-1-2-3 and 4-5-6-7, for both variants.  A position beyond a
+   chain end is replaced by the end bead.  Coordinates are minimum-image displacements
+   from bead 1 minus the mean of the four junction beads 1, 2, 5, 6; input 24 is kappa. */
+static void nn_features(const melt_t *m, const int32_t *chain, uint64_t key, double f[NN_IN]) {
+  int A, i, B, j, var;
+  key_decode(m, key, &A, &i, &B, &j, &var);
+  int N = m->N;
+  int pa[4] = {i - 1, i, i + 1, i + 2};
+  int pb[4];
+  if (var == 0) { pb[0] = j + 2; pb[1] = j + 1; pb[2] = j; pb[3] = j - 1; }
+  else { pb[0] = j - 1; pb[1] = j; pb[2] = j + 1; pb[3] = j + 2; }
+  int ids[8];
+  for (int k = 0; k < 4; k++) {
+    int p = pa[k] < 1 ? 1 : (pa[k] > N ? N : pa[k]);
+    int q = pb[k] < 1 ? 1 : (pb[k] > N ? N : pb[k]);
+    ids[k] = at(m, chain, A, p);
+    ids[4 + k] = at(m, chain, B, q);
+  }
+  double d[8][3];
+  for (int k = 0; k < 8; k++) disp(m, ids[1], ids[k], d[k]);
+  for (int c = 0; c < 3; c++) {
+    double cen = ((d[2][c] + d[5][c]) + d[6][c]) * 0.25; /* d[1] = 0 */
+    for (int k = 0; k < 8; k++) f[3 * k + c] = d[k][c] - cen;
+  }
+  f[24] = m->p.kappa;
+}
+
+/* exported: inputs (as FP32, the form they are logged in) of keys at the current topology */
+int kgdbref_features(melt_t *m, const uint64_t *keys, int64_t n, float *out) {
+  for (int64_t q = 0; q < n; q++) {
+    double f[NN_IN];
+    nn_features(m, m->chain, keys[q], f);
+    for (int k = 0; k < NN_IN; k++) out[q * NN_IN + k] = (float)f[k];
+  }
+  return OR_OK;
+}
+
+/* Quantised forward pass of one input vector (FP32 inputs, as logged).  Optionally
+   returns the pre-activations z[3][128] and hidden codes h[3][128].  Every dot product is
+   an exact integer sum. */
+static float nn_forward(const float *P, const float *x, float *z_out, int *h_out) {
+  int qin[NN_IN], h1[NN_H], h2[NN_H], h3[NN_H];
+  for (int k = 0; k < NN_IN; k++) qin[k] = q_input((double)x[k]);
+  for (int o = 0; o < NN_H; o++) {
+    int64_t S = 0;
+    for (int k = 0; k < NN_IN; k++) S += (int64_t)q_weight(P[NN_OFF_W1 + o * NN_IN + k]) * qin[k];
+    float z = (float)((double)S * 0x1.0p-12) + P[NN_OFF_B1 + o];
+    h1[o] = q_hidden(z);
+    if (z_out) z_out[o] = z;
+  }
+  for (int o = 0; o < NN_H; o++) {
+    int64_t S = 0;
+    for (int k = 0; k < NN_H; k++) S += (int64_t)q_weight(P[NN_OFF_W2 + o * NN_H + k]) * h1[k];
+    float z = (float)((double)S * 0x1.0p-10) + P[NN_OFF_B2 + o];
+    h2[o] = q_hidden(z);
+    if (z_out) z_out[NN_H + o] = z;
+  }
+  for (int o = 0; o < NN_H; o++) {
+    int64_t S = 0;
+    for (int k = 0; k < NN_H; k++) S += (int64_t)q_weight(P[NN_OFF_W3 + o * NN_H + k]) * h2[k];
+    float z = (float)((double)S * 0x1.0p-10) + P[NN_OFF_B3 + o];
+    h3[o] = q_hidden(z);
+    if (z_out) z_out[2 * NN_H + o] = z;
+  }
+  int64_t S = 0;
+  for (int k = 0; k < NN_H; k++) S += (int64_t)q_weight(P[NN_OFF_W4 + k]) * h3[k];
+  if (h_out)
+    for (int k = 0; k < NN_H; k++) { h_out[k] = h1[k]; h_out[NN_H + k] = h2[k]; h_out[2 * NN_H + k] = h3[k]; }
+  return (float)((double)S * 0x1.0p-10) + P[NN_OFF_B4];
+}
+
+/* exported: logits of n input vectors ([n][25] FP32) */
+int kgdbref_mlp_forward(const float *P, const float *x, int64_t n, float *logit) {
+  for (int64_t q = 0; q < n; q++) logit[q] = nn_forward(P, x + q * NN_IN, NULL, NULL);
+  return OR_OK;
+}
+
+/* exported: the quantised parameters as real values (weights code/64, biases unchanged) */
+void kgdbref_mlp_quantised(const float *P, double *out) {
+  for (int t = 0; t < NN_NPARAM; t++) {
+    int is_bias = (t >= NN_OFF_B1 && t < NN_OFF_W2) || (t >= NN_OFF_B2 && t < NN_OFF_W3) ||
+                  (t >= NN_OFF_B3 && t < NN_OFF_W4) || t == NN_OFF_B4;
+    out[t] = is_bias ? (double)P[t] : q_weight(P[t]) / 64.0;
+  }
+}
+
+static double softplus(double s) { return s > 0 ? s + log1p(exp(-s)) : log1p(exp(s)); }
+static double sigmoid(double s) { return s >= 0 ? 1.0 / (1.0 + exp(-s)) : exp(s) / (1.0 + exp(s)); }
+static int in_range(float z) { return z > 0.0f && z < NN_HMAX; }
+
+/* Mean binary cross-entropy of the logits against accept (1) / reject (0) labels and its
+   gradient by back-propagation with straight-through rounding: each rounding (weights and
+   hidden codes) passes the gradient unchanged; a clamped hidden unit (z <= 0 or
+   z >= 255/16) passes none.  FP64 throughout. */
+int kgdbref_mlp_grad(const float *P, const float *x, const int32_t *y, int64_t n, double *grad, double *loss) {
+  memset(grad, 0, sizeof(double) * NN_NPARAM);
+  double L = 0;
+  float z[3 * NN_H];
+  int h[3 * NN_H];
+  double g3[NN_H], g2[NN_H], g1[NN_H];
+  for (int64_t q = 0; q < n; q++) {
+    const float *xq = x + q * NN_IN;
+    double s = (double)nn_forward(P, xq, z, h);
+    L += softplus(s) - (double)y[q] * s;
+    double gs = (sigmoid(s) - (double)y[q]) / (double)n;
+    grad[NN_OFF_B4] += gs;
+    for (int k = 0; k < NN_H; k++) {
+      grad[NN_OFF_W4 + k] += gs * (h[2 * NN_H + k] / 16.0);
+      g3[k] = in_range(z[2 * NN_H + k]) ? gs * (q_weight(P[NN_OFF_W4 + k]) / 64.0) : 0.0;
+    }
+    for (int o = 0; o < NN_H; o++) {
+      grad[NN_OFF_B3 + o] += g3[o];
+      for (int k = 0; k < NN_H; k++) grad[NN_OFF_W3 + o * NN_H + k] += g3[o] * (h[NN_H + k] / 16.0);
+    }
+    for (int k = 0; k < NN_H; k++) {
+      double a = 0;
+      for (int o = 0; o < NN_H; o++) a += (q_weight(P[NN_OFF_W3 + o * NN_H + k]) / 64.0) * g3[o];
+      g2[k] = in_range(z[NN_H + k]) ? a : 0.0;
+    }
+    for (int o = 0; o < NN_H; o++) {
+      grad[NN_OFF_B2 + o] += g2[o];
+      for (int k = 0; k < NN_H; k++) grad[NN_OFF_W2 + o * NN_H + k] += g2[o] * (h[k] / 16.0);
+    }
+    for (int k = 0; k < NN_H; k++) {
+      double a = 0;
+      for (int o = 0; o < NN_H; o++) a += (q_weight(P[NN_OFF_W2 + o * NN_H + k]) / 64.0) * g2[o];
+      g1[k] = in_range(z[k]) ? a : 0.0;
+    }
+    for (int o = 0; o < NN_H; o++) {
+      grad[NN_OFF_B1 + o] += g1[o];
+      for (int k = 0; k < NN_IN; k++) grad[NN_OFF_W1 + o * NN_IN + k] += g1[o] * (q_input((double)xq[k]) / 64.0);
+    }
+  }
+  if (loss) *loss = L / (double)n;
+  return OR_OK;
+}
+
+/* Test surrogate of the straight-through gradient: the loss of a network whose rounding
+   offsets are frozen at parameters P0 (weights w -> w + (Q(w0) - w0); a hidden unit in
+   range at P0 -> z + (h(z0) - z0), out of range -> the constant h(z0)), evaluated in FP64
+   at parameters Pd without any rounding.  Its gradient at Pd = P0 is the straight-through
+   gradient, so finite differences of it check the back-propagation. */
+double kgdbref_mlp_surrogate_loss(const float *P0, const double *Pd, const float *x, const int32_t *y, int64_t n) {
+  double L = 0;
+  float z0[3 * NN_H];
+  int h0[3 * NN_H];
+  double a1[NN_H], a2[NN_H], a3[NN_H];
+#define WOFF(t) ((double)q_weight(P0[t]) / 64.0 - (double)P0[t])
+  for (int64_t q = 0; q < n; q++) {
+    const float *xq = x + q * NN_IN;
+    nn_forward(P0, xq, z0, h0);
+    for (int o = 0; o < NN_H; o++) {
+      double zz = Pd[NN_OFF_B1 + o];
+      for (int k = 0; k < NN_IN; k++)
+        zz += (Pd[NN_OFF_W1 + o * NN_IN + k] + WOFF(NN_OFF_W1 + o * NN_IN + k)) * (q_input((double)xq[k]) / 64.0);
+      a1[o] = in_range(z0[o]) ? zz + (h0[o] / 16.0 - (double)z0[o]) : h0[o] / 16.0;
+    }
+    for (int o = 0; o < NN_H; o++) {
+      double zz = Pd[NN_OFF_B2 + o];
+      for (int k = 0; k < NN_H; k++) zz += (Pd[NN_OFF_W2 + o * NN_H + k] + WOFF(NN_OFF_W2 + o * NN_H + k)) * a1[k];
+      a2[o] = in_range(z0[NN_H + o]) ? zz + (h0[NN_H + o] / 16.0 - (double)z0[NN_H + o]) : h0[NN_H + o] / 16.0;
+    }
+    for (int o = 0; o < NN_H; o++) {
+      double zz = Pd[NN_OFF_B3 + o];
+      for (int k = 0; k < NN_H; k++) zz += (Pd[NN_OFF_W3 + o * NN_H + k] + WOFF(NN_OFF_W3 + o * NN_H + k)) * a2[k];
+      a3[o] = in_range(z0[2 * NN_H + o]) ? zz + (h0[2 * NN_H + o] / 16.0 - (double)z0[2 * NN_H + o])
+                                         : h0[2 * NN_H + o] / 16.0;
+    }
+    double s = Pd[NN_OFF_B4];
+    for (int k = 0; k < NN_H; k++) s += (Pd[NN_OFF_W4 + k] + WOFF(NN_OFF_W4 + k)) * a3[k];
+    L += softplus(s) - (double)y[q] * s;
+  }
+#undef WOFF
+  return L / (double)n;
+}
+
+/* One Adam step (Kingma & Ba, 2015) on FP32 master parameters: m <- b1 m + (1-b1) g,
+   v <- b2 v + (1-b2) g^2, P <- P - lr mhat / (sqrt(vhat) + eps) with the bias corrections
+   of step t (1-based); weights (not biases) are then clamped to the representable range
+   +-255/64.  FP64 arithmetic; results returned in FP64. */
+void kgdbref_adam(const float *P, const float *m, const float *v, const double *g, int64_t t, double lr,
+                  double b1, double b2, double eps, double *P_out, double *m_out, double *v_out) {
+  double c1 = 1.0 - pow(b1, (double)t), c2 = 1.0 - pow(b2, (double)t);
+  for (int k = 0; k < NN_NPARAM; k++) {
+    double mm = b1 * m[k] + (1.0 - b1) * g[k];
+    double vv = b2 * v[k] + (1.0 - b2) * g[k] * g[k];
+    double p = (double)P[k] - lr * (mm / c1) / (sqrt(vv / c2) + eps);
+    int is_bias = (k >= NN_OFF_B1 && k < NN_OFF_W2) || (k >= NN_OFF_B2 && k < NN_OFF_W3) ||
+                  (k >= NN_OFF_B3 && k < NN_OFF_W4) || k == NN_OFF_B4;
+    if (!is_bias) { if (p > 255.0 / 64.0) p = 255.0 / 64.0; if (p < -255.0 / 64.0) p = -255.0 / 64.0; }
+    P_out[k] = p; m_out[k] = mm; v_out[k] = vv;
+  }
+}
+
+/* proposal weight of a logit (clamped so that exp stays finite) */
+static double nn_weight(float s) {
+  double d = (double)s;
+  if (d > NN_LOGIT_CLAMP) d = NN_LOGIT_CLAMP;
+  if (d < -NN_LOGIT_CLAMP) d = -NN_LOGIT_CLAMP;
+  return exp(d);
+}
+
+/* logits of all (sorted) candidates of topology `chain` */
+static void nn_score_all(const melt_t *m, const int32_t *chain, const float *P, const uint64_t *keys, int64_t n,
+                         double *w, double *Z) {
+  double acc = 0;
+  for (int64_t q = 0; q < n; q++) {
+    double f[NN_IN];
+    float xf[NN_IN];
+    nn_features(m, chain, keys[q], f);
+    for (int k = 0; k < NN_IN; k++) xf[k] = (float)f[k];
+    w[q] = nn_weight(nn_forward(P, xf, NULL, NULL));
+    acc += w[q];
+  }
+  *Z = acc;
+}
+
+/* exported for tests: proposal probabilities q(key | x) of the current candidate set */
+int kgdbref_learned_q(melt_t *m, const float *P, double mix, uint64_t *keys, double *q, int64_t cap, int64_t *n_out) {
+  int64_t n = count_or_list(m, m->chain, 0, NULL, 0);
+  *n_out = n;
+  if (n > cap) { set_err("buffer too small"); return OR_E_OVERFLOW; }
+  count_or_list(m, m->chain, 0, keys, n);
+  double *w = (double *)malloc(sizeof(double) * (n > 0 ? n : 1)), Z;
+  nn_score_all(m, m->chain, P, keys, n, w, &Z);
+  for (int64_t k = 0; k < n; k++) q[k] = (1.0 - mix) * w[k] / Z + mix / (double)n;
+  free(w);
+  return OR_OK;
+}
+
+/* One attempt with the learned proposal.  Random words of the attempt: w[0] picks the
+   move (uniform choice, or the softmax position u01(w[0]) Z), w[1] is the acceptance
+   uniform, w[2] selects the uniform component of the mixture (u01(w[2]) < mix). */
+static int db_attempt_learned(melt_t *m, uint64_t attempt, const float *P, double mix, kgdbref_stats *st) {
+  int64_t n = count_or_list(m, m->chain, 0, NULL, 0);
+  st->attempts++;
+  if (n == 0) { st->no_candidate++; return OR_OK; }
+  uint64_t *keys = (uint64_t *)malloc(sizeof(uint64_t) * n);
+  double *w = (double *)malloc(sizeof(double) * n), Z;
+  count_or_list(m, m->chain, 0, keys, n);
+  st->sum_ncand += n;
+  nn_score_all(m, m->chain, P, keys, n, w, &Z);
+  uint64_t r[4];
+  draw(m->p.seed, (uint64_t)m->p.melt_id, attempt, m->sweep, ST_DB, r);
+  int64_t idx;
+  if (u01(r[2]) < mix) idx = (int64_t)choice(r[0], (uint64_t)n);
+  else {
+    double t = u01(r[0]) * Z, cum = 0;
+    idx = n - 1;
+    for (int64_t k = 0; k < n; k++) {
+      cum += w[k];
+      if (cum > t) { idx = k; break; }
+    }
+  }
+  uint64_t key = keys[idx];
+  double qf = (1.0 - mix) * w[idx] / Z + mix / (double)n;
+  free(keys); free(w);
+  int A, i, B, j, var;
+  key_decode(m, key, &A, &i, &B, &j, &var);
+  int32_t *nc = (int32_t *)malloc(sizeof(int32_t) * m->Nm);
+  apply_move(m, m->chain, nc, A, i, B, j, var);
+  double dE = (junction_energy(m, nc, A, i) + junction_energy(m, nc, B, j)) -
+              (junction_energy(m, m->chain, A, i) + junction_energy(m, m->chain, B, j));
+  double ratio = 0.0;
+  int rev_ok = close_enough(m, at(m, m->chain, A, i), at(m, m->chain, A, i + 1)) &&
+               close_enough(m, at(m, m->chain, B, j), at(m, m->chain, B, j + 1));
+  if (!rev_ok) st->reverse_impossible++;
+  else {
+    int64_t n2 = count_or_list(m, nc, 0, NULL, 0);
+    uint64_t *k2 = (uint64_t *)malloc(sizeof(uint64_t) * n2);
+    double *w2 = (double *)malloc(sizeof(double) * n2), Z2;
+    count_or_list(m, nc, 0, k2, n2);
+    nn_score_all(m, nc, P, k2, n2, w2, &Z2);
+    double wr = 0;
+    for (int64_t k = 0; k < n2; k++)
+      if (k2[k] == key) wr = w2[k];
+    double qr = (1.0 - mix) * wr / Z2 + mix / (double)n2;
+    ratio = exp(-dE / m->p.T) * qr / qf;
+    free(k2); free(w2);
+  }
+  if (u01(r[1]) < ratio) {
+    memcpy(m->chain, nc, sizeof(int32_t) * m->Nm);
+    st->accepted++;
+    st->sum_dE_accepted += dE;
+  }
+  free(nc);
+  return OR_OK;
+}
+
+int kgdbref_db_sweep_learned(melt_t *m, int64_t K, const float *P, double mix, kgdbref_stats *st) {
+  memset(st, 0, sizeof *st);
+  if (K < 0) {
+    double t = (double)(m->step - m->last_sweep_step) * m->p.dt;
+    K = (int64_t)llround(m->p.db_rate * (double)m->Nm * t);
+  }
+  for (int64_t a = 0; a < K; a++) {
+    int rc = db_attempt_learned(m, (uint64_t)a, P, mix, st);
+    if (rc) return rc;
+  }
+  st->ncand_end = count_or_list(m, m->chain, 0, NULL, 0);
+  m->sweep++;
+  m->last_sweep_step = m->step;
+  m->fc_valid = 0;
+  return OR_OK;
 }

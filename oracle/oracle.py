@@ -108,6 +108,19 @@ def lib():
         L.kgdbref_observables.argtypes = [P, P, P, P]
         L.kgdbref_energy.argtypes = [P, P]
         L.kgdbref_fit_ellK.argtypes = [dp, C.c_int32, C.c_double, C.POINTER(C.c_double)]
+        # learned proposal
+        L.kgdbref_mlp_nparam.restype = C.c_int32
+        L.kgdbref_features.argtypes = [P, P, C.c_int64, P]
+        L.kgdbref_mlp_forward.argtypes = [P, P, C.c_int64, P]
+        L.kgdbref_mlp_quantised.argtypes = [P, P]
+        L.kgdbref_mlp_grad.argtypes = [P, P, P, C.c_int64, P, P]
+        L.kgdbref_mlp_surrogate_loss.restype = C.c_double
+        L.kgdbref_mlp_surrogate_loss.argtypes = [P, P, P, P, C.c_int64]
+        L.kgdbref_adam.argtypes = [P, P, P, P, C.c_int64, C.c_double, C.c_double, C.c_double, C.c_double, P, P, P]
+        L.kgdbref_learned_q.argtypes = [P, P, C.c_double, P, P, C.c_int64, C.POINTER(C.c_int64)]
+        L.kgdbref_db_sweep_learned.argtypes = [P, C.c_int64, P, C.c_double, C.POINTER(Stats)]
+        L.kgdbref_db_sweep_log.argtypes = [P, C.c_int64, C.c_int32, C.POINTER(Stats), P, P, C.c_int64,
+                                           C.POINTER(C.c_int64)]
         _lib = L
     return _lib
 
@@ -218,6 +231,31 @@ class Melt:
     def apply_move(self, A, i, B, j, var):
         _check(lib().kgdbref_apply_move(self.h, A, i, B, j, var))
 
+    def db_sweep_log(self, K, cap=1 << 16, brute=False):
+        """Uniform sweep that records (inputs, accepted) of every attempt with candidates."""
+        st = Stats()
+        feat = np.zeros((cap, NN_IN), np.float32); lab = np.zeros(cap, np.int32); n = C.c_int64()
+        _check(lib().kgdbref_db_sweep_log(self.h, K, int(brute), C.byref(st), _ptr(feat), _ptr(lab), cap, C.byref(n)))
+        return st.as_dict(), feat[: n.value].copy(), lab[: n.value].copy()
+
+    def db_sweep_learned(self, K, params, mix):
+        st = Stats()
+        P = np.ascontiguousarray(params, np.float32)
+        _check(lib().kgdbref_db_sweep_learned(self.h, K, _ptr(P), float(mix), C.byref(st)))
+        return st.as_dict()
+
+    def features(self, keys):
+        keys = np.ascontiguousarray(keys, np.uint64)
+        out = np.zeros((keys.size, NN_IN), np.float32)
+        _check(lib().kgdbref_features(self.h, _ptr(keys), keys.size, _ptr(out)))
+        return out
+
+    def learned_q(self, params, mix, cap=1 << 16):
+        keys = np.zeros(cap, np.uint64); q = np.zeros(cap); n = C.c_int64()
+        P = np.ascontiguousarray(params, np.float32)
+        _check(lib().kgdbref_learned_q(self.h, _ptr(P), float(mix), _ptr(keys), _ptr(q), cap, C.byref(n)))
+        return keys[: n.value].copy(), q[: n.value].copy()
+
     def observables(self):
         r2n = np.zeros(self.N - 1); lk = C.c_double(); mb = C.c_double()
         _check(lib().kgdbref_observables(self.h, _ptr(r2n), C.byref(lk), C.byref(mb)))
@@ -237,3 +275,60 @@ def key_decode(key, M, N):
     q = key >> 1
     hi, lo = divmod(q, M * Nb)
     return hi // Nb, hi % Nb + 1, lo // Nb, lo % Nb + 1, var
+
+
+# ---------------------------------------------------------------- learned proposal network
+NN_IN, NN_H = 25, 128
+NN_NPARAM = NN_H * NN_IN + NN_H + 2 * (NN_H * NN_H + NN_H) + NN_H + 1
+
+
+def nn_slices():
+    """Offsets of W1 [128][25], b1, W2 [128][128], b2, W3, b3, w4 [128], b4 in the parameter vector."""
+    sl, o = {}, 0
+    for name, size in (("W1", NN_H * NN_IN), ("b1", NN_H), ("W2", NN_H * NN_H), ("b2", NN_H),
+                       ("W3", NN_H * NN_H), ("b3", NN_H), ("w4", NN_H), ("b4", 1)):
+        sl[name] = slice(o, o + size)
+        o += size
+    assert o == NN_NPARAM
+    return sl
+
+
+def mlp_forward(params, x):
+    P = np.ascontiguousarray(params, np.float32)
+    x = np.ascontiguousarray(x, np.float32).reshape(-1, NN_IN)
+    out = np.zeros(x.shape[0], np.float32)
+    _check(lib().kgdbref_mlp_forward(_ptr(P), _ptr(x), x.shape[0], _ptr(out)))
+    return out
+
+
+def mlp_quantised(params):
+    P = np.ascontiguousarray(params, np.float32)
+    out = np.zeros(NN_NPARAM)
+    lib().kgdbref_mlp_quantised(_ptr(P), _ptr(out))
+    return out
+
+
+def mlp_grad(params, x, y):
+    P = np.ascontiguousarray(params, np.float32)
+    x = np.ascontiguousarray(x, np.float32).reshape(-1, NN_IN)
+    y = np.ascontiguousarray(y, np.int32)
+    g = np.zeros(NN_NPARAM); loss = np.zeros(1)
+    _check(lib().kgdbref_mlp_grad(_ptr(P), _ptr(x), _ptr(y), x.shape[0], _ptr(g), _ptr(loss)))
+    return g, float(loss[0])
+
+
+def mlp_surrogate_loss(params0, params, x, y):
+    P0 = np.ascontiguousarray(params0, np.float32)
+    Pd = np.ascontiguousarray(params, np.float64)
+    x = np.ascontiguousarray(x, np.float32).reshape(-1, NN_IN)
+    y = np.ascontiguousarray(y, np.int32)
+    return lib().kgdbref_mlp_surrogate_loss(_ptr(P0), _ptr(Pd), _ptr(x), _ptr(y), x.shape[0])
+
+
+def adam(params, m, v, g, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+    P = np.ascontiguousarray(params, np.float32)
+    m = np.ascontiguousarray(m, np.float32); v = np.ascontiguousarray(v, np.float32)
+    g = np.ascontiguousarray(g, np.float64)
+    Po, mo, vo = np.zeros(NN_NPARAM), np.zeros(NN_NPARAM), np.zeros(NN_NPARAM)
+    lib().kgdbref_adam(_ptr(P), _ptr(m), _ptr(v), _ptr(g), t, lr, b1, b2, eps, _ptr(Po), _ptr(mo), _ptr(vo))
+    return Po, mo, vo

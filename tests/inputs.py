@@ -35,3 +35,25 @@ def jitter(x, L, scale, seed):
     """Small seeded displacement of a configuration (kept in the box by the caller)."""
     rng = np.random.default_rng(seed + 15485863)
     return (x + rng.normal(0.0, scale, size=x.shape)) % L
+
+
+MLP_NPARAM = 128 * 25 + 128 + 2 * (128 * 128 + 128) + 128 + 1
+
+
+def random_mlp_params(seed, w_scale=0.25, b_scale=0.5):
+    """Seeded random parameter vector of the 25-128-128-128-1 proposal network (FP32)."""
+    rng = np.random.default_rng(seed + 32452843)
+    p = rng.normal(0.0, w_scale, size=MLP_NPARAM)
+    # biases (b1, b2, b3, b4) get their own scale
+    o = 0
+    for size, is_bias in ((128 * 25, 0), (128, 1), (128 * 128, 0), (128, 1), (128 * 128, 0), (128, 1),
+                          (128, 0), (1, 1)):
+        if is_bias:
+            p[o:o + size] = rng.normal(0.0, b_scale, size=size)
+        o += size
+    return p.astype(np.float32)
+
+
+def random_labels(n, seed, p=0.3):
+    rng = np.random.default_rng(seed + 49979687)
+    return (rng.uniform(size=n) < p).astype(np.int32)
