@@ -5,7 +5,8 @@
  * potential (Sec. II.A, Eqs. 5-6) with the FENE constant k_n of Eq. 9 and the angle term of
  * Eq. 4, interleaved with double-bridging Monte Carlo moves (Fig. 1; Sec. II.B).
  *
- * Plain C ABI: host pointers and sizes only.  Every call returns 0 or a negative kgdb_err;
+ * Plain C ABI: host pointers and sizes (device pointers only where a call says DEVICE).
+ * Every call returns 0 or a negative kgdb_err;
  * kgdb_last_error() gives the message of the last failure on the calling thread.
  * A handle holds a BATCH of independent melts advanced together (a single melt is a batch
  * of one).  The library owns all device memory of a handle; host arrays passed in are
@@ -33,7 +34,8 @@ enum kgdb_err {
 
 /* proposal modes of the double-bridging attempt */
 #define KGDB_PROPOSAL_UNIFORM 0 /* uniform over the candidate set, exact Metropolis-Hastings */
-#define KGDB_PROPOSAL_LEARNED 1 /* reserved: learned proposal (rejected with KGDB_E_PARAM)   */
+#define KGDB_PROPOSAL_LEARNED 1 /* learned proposal with exact Metropolis-Hastings correction
+                                   (a project extension; all melts of a batch or none)      */
 #define KGDB_PROPOSAL_LITERAL 2 /* acceptance exp(-dE/T) only, as printed in Fig. 1         */
 
 /* force precision */
@@ -170,6 +172,62 @@ int kgdb_nl_info(kgdb_batch* b, double out[4]);
 int kgdb_melt_geometry(const kgdb_batch* b, int32_t melt, double out[4]);
 /* total number of monomers and cells of the batch (for byte accounting) */
 int kgdb_batch_sizes(const kgdb_batch* b, int64_t* monomers, int64_t* cells);
+
+/* ---- learned double-bridging proposal (a project extension; the paper's Fig. 1 proposes
+   uniformly over the candidate set) ------------------------------------------------------
+   The network scores a candidate move from the geometry of its two bonds: 25 FP32 inputs
+   (8 beads x 3 minimum-image coordinates relative to the junction centre, then kappa) ->
+   128 -> 128 -> 128 -> 1 logit, ReLU.  Weights and inputs are rounded to codes c/64 and hidden
+   activations to c/16 (|c| <= 255), which makes the bf16 matrix-core evaluation with FP32
+   accumulation exact.  Parameter vector (FP32, KGDB_MLP_NPARAM entries, in this order):
+   W1[128][25], b1[128], W2[128][128], b2[128], W3[128][128], b3[128], w4[128], b4.
+   Moves are proposed from (1 - mix) w / Z + mix uniform over the candidate set, with weights
+   w = sigmoid(logit) (logit clamped to +-40) and Z their sum, and accepted with
+   min(1, exp(-dE/T) q(m|x') / q(m|x)); the reverse of a move is the same key.  A network
+   trained to classify acceptance makes w approach min(1, exp(-dE/T)), a locally balanced
+   proposal (Zanella, JASA 2020) whose Hastings ratio tends to Z(x)/Z(x'). */
+#define KGDB_MLP_NPARAM 36481
+int64_t kgdb_mlp_nparam(void);
+/* Quantise `params` (host, or device when params_on_device != 0) into the batch's proposal
+   network and set the uniform share mix in [0, 1].  Needed before a sweep of a batch whose
+   melts use KGDB_PROPOSAL_LEARNED; synchronises the stream. */
+int kgdb_set_proposal_net(kgdb_batch* b, const float* params, int32_t params_on_device, double mix);
+/* kgdb_db_sweep (uniform or paper-literal proposal) that records each attempt with
+   candidates, in order: feat (DEVICE, [count][cap][25] FP32) receives the network inputs of
+   the proposed move in the topology it was proposed in, label (DEVICE, [count][cap] int32)
+   1 if it was accepted else 0; n_logged (host, [count]) the records written per melt (at
+   most cap; later attempts are not recorded). */
+int kgdb_db_sweep_log(kgdb_batch* b, int64_t n_attempts, kgdb_db_stats* stats, float* feat, int32_t* label,
+                      int64_t cap, int64_t* n_logged);
+/* test hooks: network inputs of the given keys (host) at the current topology of melt
+   `melt` -> out (host, [nkeys][25]); sorted candidate keys and their logits under the
+   batch's network (host buffers of capacity cap; *n receives |C|) */
+int kgdb_features(kgdb_batch* b, int32_t melt, const uint64_t* keys, int64_t nkeys, float* out);
+int kgdb_candidate_logits(kgdb_batch* b, int32_t melt, uint64_t* keys, float* logits, int64_t cap, int64_t* n);
+
+/* Training of the network on logged attempts.  Stateless calls on caller-owned DEVICE
+   buffers, asynchronous on `stream` (a hipStream_t; NULL = the null stream).  ws is a
+   256-byte-aligned device workspace of at least kgdb_mlp_workspace_bytes(n) bytes that the
+   call overwrites.  feat [n][25] FP32, label [n] int32 (0/1), params/m/v [KGDB_MLP_NPARAM]
+   FP32. */
+int64_t kgdb_mlp_workspace_bytes(int64_t n);
+/* logits [n] of n input rows */
+int kgdb_mlp_forward(const float* params, const float* feat, int64_t n, float* logit, void* ws, int64_t ws_bytes,
+                     void* stream);
+/* mean binary cross-entropy of the logits against the labels (loss, device double; may be
+   NULL) and its gradient (grad, device [KGDB_MLP_NPARAM] doubles; may be NULL) by
+   back-propagation that passes each rounding unchanged and stops at hidden units cut by
+   the ReLU or saturated at 255/16 (straight-through) */
+int kgdb_mlp_grad(const float* params, const float* feat, const int32_t* label, int64_t n, double* grad,
+                  double* loss, void* ws, int64_t ws_bytes, void* stream);
+/* one Adam step (Kingma & Ba) of step number t >= 1 on the FP32 master parameters; weights
+   (not biases) are clamped to +-255/64 */
+int kgdb_mlp_adam(float* params, float* m, float* v, const double* grad, int64_t t, double lr, double b1, double b2,
+                  double eps, void* stream);
+/* kgdb_mlp_grad followed by kgdb_mlp_adam */
+int kgdb_mlp_train_step(float* params, float* m, float* v, const float* feat, const int32_t* label, int64_t n,
+                        int64_t t, double lr, double b1, double b2, double eps, void* ws, int64_t ws_bytes,
+                        double* loss, void* stream);
 
 #ifdef __cplusplus
 }

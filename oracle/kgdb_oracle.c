@@ -960,8 +960,9 @@ int kgdbref_observables(melt_t *m, double *r2n, double *ellK, double *meanbond) 
 /* ------------------------------------------------------------------------------------ */
 /* Learned double-bridging proposal (a project extension: the paper proposes uniformly  */
 /* over the candidate set).  A small network scores each candidate move from the local  */
-/* geometry of its two bonds; moves are proposed from a mixture of the softmax of the   */
-/* scores and the uniform proposal, and the Metropolis-Hastings ratio uses the forward  */
+/* geometry of its two bonds; moves are proposed from a mixture of the normalised       */
+/* weights sigmoid(score) and the uniform proposal (a softmax over log sigmoid(score)), */
+/* and the Metropolis-Hastings ratio uses the forward                                   */
 /* probability of the move and the probability of the same (involutive) move from the   */
 /* new state, so the sampled distribution stays exp(-E/T).                              */
 /*                                                                                      */
@@ -1201,12 +1202,16 @@ void kgdbref_adam(const float *P, const float *m, const float *v, const double *
   }
 }
 
-/* proposal weight of a logit (clamped so that exp stays finite) */
+/* Proposal weight of a logit: sigmoid(f), with f clamped to +-40 so that no weight is 0.
+   The network is trained as a classifier of acceptance, so sigmoid(f) estimates the
+   Metropolis acceptance min(1, exp(-dE/T)); that function g(t) = min(1, t) of the target
+   ratio t satisfies g(t) = t g(1/t), which makes the proposal locally balanced (Zanella,
+   J. Am. Stat. Assoc. 2020): the Hastings ratio then reduces to Z(x)/Z(x'). */
 static double nn_weight(float s) {
   double d = (double)s;
   if (d > NN_LOGIT_CLAMP) d = NN_LOGIT_CLAMP;
   if (d < -NN_LOGIT_CLAMP) d = -NN_LOGIT_CLAMP;
-  return exp(d);
+  return d >= 0 ? 1.0 / (1.0 + exp(-d)) : exp(d) / (1.0 + exp(d));
 }
 
 /* logits of all (sorted) candidates of topology `chain` */

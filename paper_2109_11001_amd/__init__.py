@@ -8,8 +8,10 @@ import ctypes as C
 
 import numpy as np
 
-from ._lib import (PREC_FP64, PREC_MIXED, PROPOSAL_LITERAL, PROPOSAL_UNIFORM, TF_NL_GLOBAL, TF_NOFORCE,
-                   TF_PHANTOM, DbStats, KgdbError, Params, check, load, ptr)
+from ._lib import (MLP_NPARAM, PREC_FP64, PREC_MIXED, PROPOSAL_LEARNED, PROPOSAL_LITERAL, PROPOSAL_UNIFORM,
+                   TF_NL_GLOBAL, TF_NOFORCE, TF_PHANTOM, DbStats, KgdbError, Params, check, load, ptr)
+
+NN_IN = 25
 
 DEFAULTS = dict(M=20, N=50, rho=0.85, kappa=1.5, n_exp=2.0, k_fene=0.0, R0=1.5, T=1.0,
                 gamma=1.0, dt=0.01, db_rmax=1.3, db_rate=1e-3, proposal=PROPOSAL_UNIFORM,
@@ -161,7 +163,116 @@ class Batch:
         check(load().kgdb_batch_sizes(self._h, C.byref(a), C.byref(b)))
         return a.value, b.value
 
+    # ---- learned proposal
+    def set_proposal_net(self, params, mix):
+        """Quantise FP32 parameters (numpy array or device tensor) into the batch's network."""
+        if hasattr(params, "data_ptr"):
+            check(load().kgdb_set_proposal_net(self._h, _dptr(params), 1, float(mix)))
+        else:
+            p = np.ascontiguousarray(params, np.float32)
+            check(load().kgdb_set_proposal_net(self._h, ptr(p), 0, float(mix)))
+
+    def db_sweep_log(self, n_attempts, cap):
+        """Uniform sweep recording each attempt: (stats, feat [nm][cap][25], label [nm][cap], n_logged)."""
+        import torch
+        feat = torch.zeros((self.nm, cap, NN_IN), dtype=torch.float32, device="cuda")
+        lab = torch.zeros((self.nm, cap), dtype=torch.int32, device="cuda")
+        st = (DbStats * self.nm)()
+        nl = np.zeros(self.nm, np.int64)
+        check(load().kgdb_db_sweep_log(self._h, int(n_attempts), st, _dptr(feat), _dptr(lab), int(cap), ptr(nl)))
+        return [s.as_dict() for s in st], feat, lab, nl
+
+    def features(self, keys, melt=0):
+        keys = np.ascontiguousarray(keys, np.uint64)
+        out = np.zeros((len(keys), NN_IN), np.float32)
+        check(load().kgdb_features(self._h, melt, ptr(keys), len(keys), ptr(out)))
+        return out
+
+    def candidate_logits(self, melt=0):
+        n = C.c_int64()
+        check(load().kgdb_candidate_logits(self._h, melt, None, None, 0, C.byref(n)))
+        keys = np.zeros(max(n.value, 1), np.uint64); lg = np.zeros(max(n.value, 1), np.float32)
+        check(load().kgdb_candidate_logits(self._h, melt, ptr(keys), ptr(lg), keys.size, C.byref(n)))
+        return keys[: n.value].copy(), lg[: n.value].copy()
+
 
 def Melt(stream=None, **kw):
     """A batch holding a single melt."""
     return Batch([kw], stream=stream)
+
+
+# ---------------------------------------------------------------- network training (device buffers)
+def _dptr(t):
+    assert t.is_cuda and t.is_contiguous()
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream_ptr(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(int(s.cuda_stream)) if s.cuda_stream else None
+
+
+def _workspace(n):
+    import torch
+    nb = int(load().kgdb_mlp_workspace_bytes(int(n)))
+    return torch.empty(nb + 256, dtype=torch.uint8, device="cuda"), nb
+
+
+def _aligned(ws):
+    p = ws.data_ptr()
+    return C.c_void_p((p + 255) & ~255)
+
+
+def mlp_forward(params, feat, stream=None):
+    """Logits of input rows feat [n][25] (device tensors)."""
+    import torch
+    n = feat.shape[0]
+    out = torch.empty(n, dtype=torch.float32, device="cuda")
+    ws, nb = _workspace(n)
+    check(load().kgdb_mlp_forward(_dptr(params), _dptr(feat), n, _dptr(out), _aligned(ws), nb, _stream_ptr(stream)))
+    return out
+
+
+def mlp_grad(params, feat, label, stream=None):
+    """(gradient [MLP_NPARAM] float64, mean BCE loss) on device."""
+    import torch
+    n = feat.shape[0]
+    g = torch.empty(MLP_NPARAM, dtype=torch.float64, device="cuda")
+    loss = torch.empty(1, dtype=torch.float64, device="cuda")
+    ws, nb = _workspace(n)
+    check(load().kgdb_mlp_grad(_dptr(params), _dptr(feat), _dptr(label), n, _dptr(g), _dptr(loss), _aligned(ws), nb,
+                               _stream_ptr(stream)))
+    return g, loss
+
+
+def mlp_adam(params, m, v, grad, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8, stream=None):
+    check(load().kgdb_mlp_adam(_dptr(params), _dptr(m), _dptr(v), _dptr(grad), int(t), lr, b1, b2, eps,
+                               _stream_ptr(stream)))
+
+
+class Trainer:
+    """FP32 master parameters, Adam moments and a workspace on the device."""
+
+    def __init__(self, params, max_batch, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8, stream=None):
+        import torch
+        self.params = torch.as_tensor(np.ascontiguousarray(params, np.float32)).cuda()
+        self.m = torch.zeros_like(self.params)
+        self.v = torch.zeros_like(self.params)
+        self.loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+        self.ws, self.nb = _workspace(max_batch)
+        self.max_batch = max_batch
+        self.t = 0
+        self.lr, self.b1, self.b2, self.eps = lr, b1, b2, eps
+        self.stream = stream
+
+    def step(self, feat, label):
+        """One Adam step on a batch (device tensors feat [n][25] float32, label [n] int32)."""
+        n = feat.shape[0]
+        if n > self.max_batch:
+            raise ValueError("batch larger than the workspace")
+        self.t += 1
+        check(load().kgdb_mlp_train_step(_dptr(self.params), _dptr(self.m), _dptr(self.v), _dptr(feat),
+                                         _dptr(label), n, self.t, self.lr, self.b1, self.b2, self.eps,
+                                         _aligned(self.ws), self.nb, _dptr(self.loss), _stream_ptr(self.stream)))
+        return self.loss

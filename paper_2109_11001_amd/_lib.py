@@ -56,7 +56,10 @@ EXPORTS = [
     "kgdb_set_state", "kgdb_forces", "kgdb_cell_list", "kgdb_candidates", "kgdb_db_probe",
     "kgdb_time_force_kernel", "kgdb_db_sweep_checked", "kgdb_profile", "kgdb_profile_read",
     "kgdb_melt_geometry", "kgdb_batch_sizes", "kgdb_autotune", "kgdb_nl_info",
+    "kgdb_mlp_nparam", "kgdb_set_proposal_net", "kgdb_db_sweep_log", "kgdb_features", "kgdb_candidate_logits",
+    "kgdb_mlp_workspace_bytes", "kgdb_mlp_forward", "kgdb_mlp_grad", "kgdb_mlp_adam", "kgdb_mlp_train_step",
 ]
+MLP_NPARAM = 36481
 
 _lib = None
 
@@ -97,9 +100,21 @@ def load():
     L.kgdb_batch_sizes.argtypes = [P, P, P]
     L.kgdb_autotune.argtypes = [P, i32, i32, P, P]
     L.kgdb_nl_info.argtypes = [P, P]
+    L.kgdb_mlp_nparam.argtypes = []
+    L.kgdb_set_proposal_net.argtypes = [P, P, i32, dbl]
+    L.kgdb_db_sweep_log.argtypes = [P, i64, P, P, P, i64, P]
+    L.kgdb_features.argtypes = [P, i32, P, i64, P]
+    L.kgdb_candidate_logits.argtypes = [P, i32, P, P, i64, P]
+    L.kgdb_mlp_workspace_bytes.argtypes = [i64]
+    L.kgdb_mlp_forward.argtypes = [P, P, i64, P, P, i64, P]
+    L.kgdb_mlp_grad.argtypes = [P, P, P, i64, P, P, P, i64, P]
+    L.kgdb_mlp_adam.argtypes = [P, P, P, P, i64, dbl, dbl, dbl, dbl, P]
+    L.kgdb_mlp_train_step.argtypes = [P, P, P, P, P, i64, i64, dbl, dbl, dbl, dbl, P, i64, P, P]
     for f in EXPORTS:
         if f not in ("kgdb_destroy", "kgdb_last_error", "kgdb_batch_size"):
             getattr(L, f).restype = C.c_int
+    L.kgdb_mlp_nparam.restype = i64
+    L.kgdb_mlp_workspace_bytes.restype = i64
     _lib = L
     return L
 

@@ -23,6 +23,7 @@ SOURCES = {
     "kgdb_db.hip": ["-ffp-contract=off"],
     "kgdb_obs.hip": ["-ffp-contract=off"],
     "kgdb_api.hip": ["-ffp-contract=off"],
+    "kgdb_mlp.hip": ["-ffp-contract=off"],
 }
 
 

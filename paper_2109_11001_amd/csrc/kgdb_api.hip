@@ -11,6 +11,7 @@
 #include "kgdb.h"
 #include "kgdb_dev.h"
 #include "kgdb_kernels.h"
+#include "kgdb_mlp_dev.h"
 
 using namespace kgdb;
 
@@ -90,6 +91,10 @@ struct kgdb_batch {
   int64_t *d_natt = nullptr, *d_probe_n = nullptr;
   double* d_probe_dE = nullptr;
   kgdb_db_stats* d_stats = nullptr;
+  NetQ* d_net = nullptr;     // quantised network of the learned proposal
+  bool has_net = false;
+  double mix = 0.0;          // uniform share of the learned proposal mixture
+  bool learned = false;      // the batch's melts use the learned proposal
   double *d_spre = nullptr, *d_blen = nullptr, *d_r2 = nullptr;
   std::vector<void*> allocs;
   // host mirrors
@@ -133,7 +138,7 @@ static int check_params(const kgdb_params& p) {
     return fail(KGDB_E_PARAM, "rho, R0, dt must be > 0; T, gamma >= 0");
   if (!(p.n_exp > 0) || p.n_exp == 6.0) return fail(KGDB_E_PARAM, "n must be > 0 and != 6 (Eq. 5 is singular)");
   if (!(p.db_rmax > 0)) return fail(KGDB_E_PARAM, "db_rmax must be > 0");
-  if (p.proposal != KGDB_PROPOSAL_UNIFORM && p.proposal != KGDB_PROPOSAL_LITERAL)
+  if (p.proposal != KGDB_PROPOSAL_UNIFORM && p.proposal != KGDB_PROPOSAL_LITERAL && p.proposal != KGDB_PROPOSAL_LEARNED)
     return fail(KGDB_E_PARAM, "unsupported proposal mode");
   if (p.precision != KGDB_PREC_FP64 && p.precision != KGDB_PREC_MIXED) return fail(KGDB_E_PARAM, "bad precision");
   if (p.warmup_steps < 0) return fail(KGDB_E_PARAM, "warmup_steps < 0");
@@ -653,6 +658,8 @@ static int init_impl(const kgdb_params* params, int32_t count, void* stream, kgd
   for (int k = 1; k < count; ++k) {
     if (params[k].precision != params[0].precision) return fail(KGDB_E_PARAM, "precision differs within the batch");
     if (params[k].warmup_steps != params[0].warmup_steps) return fail(KGDB_E_PARAM, "warmup_steps differs within the batch");
+    if ((params[k].proposal == KGDB_PROPOSAL_LEARNED) != (params[0].proposal == KGDB_PROPOSAL_LEARNED))
+      return fail(KGDB_E_PARAM, "the learned proposal must be used by all melts of a batch or by none");
   }
   kgdb_batch* b = new kgdb_batch();
   b->nm = count;
@@ -785,6 +792,12 @@ static int init_impl(const kgdb_params* params, int32_t count, void* stream, kgd
   step(dalloc(b, &b->d_sweep, (size_t)count));
   step(dalloc(b, &b->d_natt, (size_t)count));
   step(dalloc(b, &b->d_stats, (size_t)count));
+  {
+    char* q = nullptr;
+    step(dalloc(b, &q, netq_bytes()));
+    b->d_net = (NetQ*)q;
+  }
+  b->learned = params[0].proposal == KGDB_PROPOSAL_LEARNED;
   step(dalloc(b, &b->d_spre, 3 * (size_t)b->max_Nm));
   step(dalloc(b, &b->d_blen, (size_t)b->max_M));
   step(dalloc(b, &b->d_r2, (size_t)b->max_N));
@@ -1037,6 +1050,8 @@ static DbArgs db_args(kgdb_batch* b) {
   a.nattempt = b->d_natt;
   a.stats = b->d_stats;
   a.debug = 0;
+  a.net = b->d_net;
+  a.mix = b->mix;
   return a;
 }
 
@@ -1090,8 +1105,11 @@ int kgdb_db_probe(kgdb_batch* b, int32_t melt, const uint64_t* keys, int64_t nke
   return 0;
 }
 
-static int sweep_impl(kgdb_batch* b, int64_t n_attempts, kgdb_db_stats* stats, int debug) {
+static int sweep_impl(kgdb_batch* b, int64_t n_attempts, kgdb_db_stats* stats, int debug, float* log_feat = nullptr,
+                      int32_t* log_label = nullptr, int64_t log_cap = 0, int64_t* log_n = nullptr) {
   if (!b) return fail(KGDB_E_PARAM, "bad handle");
+  if (b->learned && !b->has_net) return fail(KGDB_E_STATE, "learned proposal without a network (kgdb_set_proposal_net)");
+  if (b->learned && (debug || log_feat)) return fail(KGDB_E_PARAM, "checked and logged sweeps use the uniform proposal");
   std::vector<int64_t> K(b->nm);
   for (int k = 0; k < b->nm; ++k) {
     if (n_attempts >= 0) K[k] = n_attempts;
@@ -1103,9 +1121,22 @@ static int sweep_impl(kgdb_batch* b, int64_t n_attempts, kgdb_db_stats* stats, i
   HIPCHK(hipMemcpyAsync(b->d_natt, K.data(), sizeof(int64_t) * b->nm, hipMemcpyHostToDevice, b->s));
   DbArgs a = db_args(b);
   a.debug = debug;
+  a.log_feat = log_feat;
+  a.log_label = log_label;
+  a.log_cap = log_cap;
+  int64_t* d_logn = nullptr;
+  if (log_feat) {
+    HIPCHK(hipMallocAsync((void**)&d_logn, sizeof(int64_t) * b->nm, b->s));
+    a.log_n = d_logn;
+  }
   CHK(db_build(b, a));
-  launch_db_sweep(a, b->s);
+  if (b->learned) launch_db_sweep_learned(a, b->s);
+  else launch_db_sweep(a, b->s);
   HIPCHK(hipGetLastError());
+  if (log_feat) {
+    HIPCHK(hipMemcpyAsync(log_n, d_logn, sizeof(int64_t) * b->nm, hipMemcpyDeviceToHost, b->s));
+    HIPCHK(hipFreeAsync(d_logn, b->s));
+  }
   std::vector<kgdb_db_stats> st(b->nm);
   HIPCHK(hipMemcpyAsync(st.data(), b->d_stats, sizeof(kgdb_db_stats) * b->nm, hipMemcpyDeviceToHost, b->s));
   const int rc = check_errors(b);
@@ -1364,4 +1395,138 @@ int kgdb_batch_sizes(const kgdb_batch* b, int64_t* monomers, int64_t* cells) {
   return 0;
 }
 
+
+// ---- learned proposal ------------------------------------------------------------------
+int kgdb_set_proposal_net(kgdb_batch* b, const float* params, int32_t params_on_device, double mix) {
+  if (!b || !params) return fail(KGDB_E_PARAM, "null argument");
+  if (!(mix >= 0.0 && mix <= 1.0)) return fail(KGDB_E_PARAM, "mix must lie in [0, 1]");
+  float* d_p = nullptr;
+  if (!params_on_device) {
+    HIPCHK(hipMallocAsync((void**)&d_p, sizeof(float) * NN_NPARAM, b->s));
+    HIPCHK(hipMemcpyAsync(d_p, params, sizeof(float) * NN_NPARAM, hipMemcpyHostToDevice, b->s));
+  }
+  launch_mlp_quant(d_p ? d_p : params, b->d_net, b->s);
+  HIPCHK(hipGetLastError());
+  if (d_p) HIPCHK(hipFreeAsync(d_p, b->s));
+  HIPCHK(hipStreamSynchronize(b->s));
+  b->has_net = true;
+  b->mix = mix;
+  return 0;
+}
+
+int kgdb_db_sweep_log(kgdb_batch* b, int64_t n_attempts, kgdb_db_stats* stats, float* feat, int32_t* label,
+                      int64_t cap, int64_t* n_logged) {
+  if (!b || !feat || !label || !n_logged || cap < 1) return fail(KGDB_E_PARAM, "null argument or capacity < 1");
+  return sweep_impl(b, n_attempts, stats, 0, feat, label, cap, n_logged);
+}
+
+int kgdb_features(kgdb_batch* b, int32_t melt, const uint64_t* keys, int64_t nkeys, float* out) {
+  CHK(check_melt(b, melt));
+  if (nkeys <= 0) return 0;
+  if (!keys || !out) return fail(KGDB_E_PARAM, "null argument");
+  const MeltDesc& d = b->D[melt];
+  const uint64_t kmax = (uint64_t)d.M * (d.N - 1) * d.M * (d.N - 1) * 2;
+  for (int64_t q = 0; q < nkeys; ++q)
+    if (keys[q] >= kmax) return fail(KGDB_E_PARAM, "key out of range");
+  uint64_t* d_k = nullptr;
+  float* d_f = nullptr;
+  HIPCHK(hipMallocAsync((void**)&d_k, sizeof(uint64_t) * nkeys, b->s));
+  HIPCHK(hipMallocAsync((void**)&d_f, sizeof(float) * NN_IN * nkeys, b->s));
+  HIPCHK(hipMemcpyAsync(d_k, keys, sizeof(uint64_t) * nkeys, hipMemcpyHostToDevice, b->s));
+  launch_db_features(db_args(b), melt, d_k, (int)nkeys, d_f, b->s);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipMemcpyAsync(out, d_f, sizeof(float) * NN_IN * nkeys, hipMemcpyDeviceToHost, b->s));
+  HIPCHK(hipFreeAsync(d_k, b->s));
+  HIPCHK(hipFreeAsync(d_f, b->s));
+  HIPCHK(hipStreamSynchronize(b->s));
+  return 0;
+}
+
+int kgdb_candidate_logits(kgdb_batch* b, int32_t melt, uint64_t* keys, float* logits, int64_t cap, int64_t* n) {
+  CHK(check_melt(b, melt));
+  if (!b->has_net) return fail(KGDB_E_STATE, "no proposal network set");
+  int64_t nk = 0;
+  CHK(kgdb_candidates(b, melt, nullptr, 0, &nk));
+  if (n) *n = nk;
+  if (!keys || !logits) return 0;
+  if (cap < nk) return fail(KGDB_E_PARAM, "buffer too small");
+  CHK(kgdb_candidates(b, melt, keys, cap, &nk));
+  if (nk == 0) return 0;
+  uint64_t* d_k = nullptr;
+  float *d_f = nullptr, *d_l = nullptr;
+  HIPCHK(hipMallocAsync((void**)&d_k, sizeof(uint64_t) * nk, b->s));
+  HIPCHK(hipMallocAsync((void**)&d_f, sizeof(float) * NN_IN * nk, b->s));
+  HIPCHK(hipMallocAsync((void**)&d_l, sizeof(float) * nk, b->s));
+  HIPCHK(hipMemcpyAsync(d_k, keys, sizeof(uint64_t) * nk, hipMemcpyHostToDevice, b->s));
+  launch_db_features(db_args(b), melt, d_k, (int)nk, d_f, b->s);
+  launch_mlp_forward(b->d_net, d_f, nk, d_l, nullptr, b->s);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipMemcpyAsync(logits, d_l, sizeof(float) * nk, hipMemcpyDeviceToHost, b->s));
+  HIPCHK(hipFreeAsync(d_k, b->s));
+  HIPCHK(hipFreeAsync(d_f, b->s));
+  HIPCHK(hipFreeAsync(d_l, b->s));
+  HIPCHK(hipStreamSynchronize(b->s));
+  return 0;
+}
+
+int64_t kgdb_mlp_nparam(void) { return NN_NPARAM; }
+
+int64_t kgdb_mlp_workspace_bytes(int64_t n) {
+  if (n < 0) return -1;
+  return (int64_t)mlp_work_layout(nullptr, n).bytes;
+}
+
+static int mlp_check_ws(int64_t n, void* ws, int64_t ws_bytes) {
+  if (n < 1) return fail(KGDB_E_PARAM, "need n >= 1");
+  if (!ws || ws_bytes < kgdb_mlp_workspace_bytes(n)) return fail(KGDB_E_PARAM, "workspace too small");
+  if ((uintptr_t)ws & 255) return fail(KGDB_E_PARAM, "workspace must be 256-byte aligned");
+  return 0;
+}
+
+int kgdb_mlp_forward(const float* params, const float* feat, int64_t n, float* logit, void* ws, int64_t ws_bytes,
+                     void* stream) {
+  if (!params || !feat || !logit) return fail(KGDB_E_PARAM, "null argument");
+  CHK(mlp_check_ws(n, ws, ws_bytes));
+  hipStream_t s = (hipStream_t)stream;
+  MlpWork w = mlp_work_layout(ws, n);
+  launch_mlp_quant(params, w.net, s);
+  launch_mlp_forward(w.net, feat, n, logit, nullptr, s);
+  HIPCHK(hipGetLastError());
+  return 0;
+}
+
+int kgdb_mlp_grad(const float* params, const float* feat, const int32_t* label, int64_t n, double* grad,
+                  double* loss, void* ws, int64_t ws_bytes, void* stream) {
+  if (!params || !feat || !label) return fail(KGDB_E_PARAM, "null argument");
+  CHK(mlp_check_ws(n, ws, ws_bytes));
+  hipStream_t s = (hipStream_t)stream;
+  MlpWork w = mlp_work_layout(ws, n);
+  launch_mlp_quant(params, w.net, s);
+  launch_mlp_forward(w.net, feat, n, w.logit, &w, s);
+  launch_mlp_grad(w, label, n, s);
+  if (grad) HIPCHK(hipMemcpyAsync(grad, w.grad, sizeof(double) * NN_NPARAM, hipMemcpyDeviceToDevice, s));
+  if (loss) HIPCHK(hipMemcpyAsync(loss, w.loss, sizeof(double), hipMemcpyDeviceToDevice, s));
+  HIPCHK(hipGetLastError());
+  return 0;
+}
+
+int kgdb_mlp_adam(float* params, float* m, float* v, const double* grad, int64_t t, double lr, double b1, double b2,
+                  double eps, void* stream) {
+  if (!params || !m || !v || !grad) return fail(KGDB_E_PARAM, "null argument");
+  if (t < 1 || !(lr > 0) || !(b1 >= 0 && b1 < 1) || !(b2 >= 0 && b2 < 1) || !(eps > 0))
+    return fail(KGDB_E_PARAM, "need t >= 1, lr > 0, 0 <= b1, b2 < 1, eps > 0");
+  const double c1 = 1.0 - std::pow(b1, (double)t), c2 = 1.0 - std::pow(b2, (double)t);
+  launch_mlp_adam(params, m, v, grad, c1, c2, lr, b1, b2, eps, (hipStream_t)stream);
+  HIPCHK(hipGetLastError());
+  return 0;
+}
+
+int kgdb_mlp_train_step(float* params, float* m, float* v, const float* feat, const int32_t* label, int64_t n,
+                        int64_t t, double lr, double b1, double b2, double eps, void* ws, int64_t ws_bytes,
+                        double* loss, void* stream) {
+  if (!params || !m || !v) return fail(KGDB_E_PARAM, "null argument");
+  CHK(kgdb_mlp_grad(params, feat, label, n, nullptr, loss, ws, ws_bytes, stream));
+  MlpWork w = mlp_work_layout(ws, n);
+  return kgdb_mlp_adam(params, m, v, w.grad, t, lr, b1, b2, eps, stream);
+}
 }  // extern "C"

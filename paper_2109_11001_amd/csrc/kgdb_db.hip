@@ -16,6 +16,7 @@
 // the same operation sequence as their definition.
 #include "kgdb_dev.h"
 #include "kgdb_kernels.h"
+#include "kgdb_mlp_dev.h"
 #include "kgdb.h"
 
 namespace kgdb {
@@ -166,6 +167,40 @@ __device__ __forceinline__ void first_bond_candidates(const Topo& T, const doubl
   }
 }
 
+// Inputs of the learned proposal for move mv in topology T: the beads a_{i-1}, a_i, a_{i+1},
+// a_{i+2} around bond i of chain A and four beads around bond j of chain B ordered so that the
+// new bonds join inputs 1-5 and 2-6 (b_{j+2}, b_{j+1}, b_j, b_{j-1} for P; b_{j-1}, b_j, b_{j+1},
+// b_{j+2} for AP); a position past a chain end takes the end bead.  Coordinates are
+// minimum-image displacements from bead 1 less the mean of the junction beads 1, 2, 5, 6;
+// input 24 is kappa.  FP64 arithmetic in a fixed order, rounded to FP32 at the end.
+__device__ void move_features(const MeltDesc& d, const Topo& T, const double* __restrict__ x, int NP, const Move& mv,
+                              float* f) {
+  const int N = d.N;
+  int ids[8];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    int p = mv.i - 1 + k;
+    int q = mv.var == 0 ? mv.j + 2 - k : mv.j - 1 + k;
+    p = p < 1 ? 1 : (p > N ? N : p);
+    q = q < 1 ? 1 : (q > N ? N : q);
+    ids[k] = T.at(mv.A, p);
+    ids[4 + k] = T.at(mv.B, q);
+  }
+  const double L = d.L;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const double* xc = x + (size_t)c * NP;
+    const double x1 = xc[ids[1]];
+    double dd[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) dd[k] = min_image(xc[ids[k]] - x1, L);
+    const double cen = ((dd[2] + dd[5]) + dd[6]) * 0.25;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) f[3 * k + c] = (float)(dd[k] - cen);
+  }
+  f[24] = (float)d.kappa;
+}
+
 // full candidate list: each monomer u on the lower chain of a close pair
 __global__ __launch_bounds__(256) void k_db_cands(const MeltDesc* __restrict__ md, const int* __restrict__ blk_melt,
                                                   const int* __restrict__ blk_base, DbArgs a) {
@@ -237,10 +272,10 @@ __device__ double move_dE(const MeltDesc& d, const int* chain, const int* loc, c
 
 // Candidates involving chain A or B of topology T (each once): scan the monomers of both
 // chains over their close pairs.  Block-cooperative; adds the count to *s_count (LDS) and,
-// when s_new != nullptr, emits the keys into s_new (capacity DB_NEW_CAP, fill count in
+// when s_new != nullptr, emits the keys into s_new (capacity new_cap, fill count in
 // s_count[1]).
 __device__ void count_touching(const MeltDesc& d, const Topo& T, const DbArgs& a, int A, int B, int* s_count,
-                               uint64_t* s_new, uint32_t* s_err) {
+                               uint64_t* s_new, uint32_t* s_err, int new_cap = DB_NEW_CAP) {
   const int N = d.N;
   int local = 0;
   for (int idx = threadIdx.x; idx < 2 * N; idx += blockDim.x) {
@@ -258,7 +293,7 @@ __device__ void count_touching(const MeltDesc& d, const Topo& T, const DbArgs& a
         ++local;
         if (s_new) {
           const int s = atomicAdd(&s_count[1], 1);
-          if (s < DB_NEW_CAP) s_new[s] = key;
+          if (s < new_cap) s_new[s] = key;
           else atomicOr(s_err, ERR_CAND_OVERFLOW);
         }
       });
@@ -344,6 +379,7 @@ __global__ __launch_bounds__(DB_BLOCK) void k_db_sweep(DbArgs a) {
   __shared__ int s_total;
   __shared__ uint32_t s_err;
   __shared__ int s_accept;
+  __shared__ int64_t s_logn, s_logat;  // training log: records written, record of this attempt
 
   const int k = blockIdx.x;
   const MeltDesc& d = a.md[k];
@@ -355,10 +391,14 @@ __global__ __launch_bounds__(DB_BLOCK) void k_db_sweep(DbArgs a) {
     st->sum_dE_accepted = 0.0;
     st->ncand_end = 0;
     s_err = 0;
+    s_logn = 0;
   }
   int n = a.ncand[k];
   if (n > DB_CAND_CAP || a.err[k] != 0) {  // a build overflow was latched: no attempts
-    if (threadIdx.x == 0) st->ncand_end = n;
+    if (threadIdx.x == 0) {
+      st->ncand_end = n;
+      if (a.log_n) a.log_n[k] = 0;
+    }
     return;
   }
   // sort the list (bitonic over the next power of two, padded with the largest key)
@@ -455,6 +495,17 @@ __global__ __launch_bounds__(DB_BLOCK) void k_db_sweep(DbArgs a) {
         st->attempts++;
         st->sum_ncand += n;
         if (d.proposal != KGDB_PROPOSAL_LITERAL && !s_ev[w].rev) st->reverse_impossible++;
+        // training record: inputs of the proposed move in the topology it was proposed in
+        s_logat = -1;
+        if (a.log_feat && s_logn < a.log_cap) {
+          s_logat = s_logn++;
+          const Topo To{a.chain, a.loc, d.off, N, {mv.A, mv.i, mv.B, mv.j, -1}};
+          float f[NN_IN];
+          move_features(d, To, a.x, a.NP, mv, f);
+          const size_t r = (size_t)k * a.log_cap + s_logat;
+          for (int q = 0; q < NN_IN; ++q) a.log_feat[r * NN_IN + q] = f[q];
+          a.log_label[r] = 0;
+        }
       }
       if (phase == 0) continue;
       {
@@ -472,6 +523,7 @@ __global__ __launch_bounds__(DB_BLOCK) void k_db_sweep(DbArgs a) {
                         (n - old_ab <= DB_CAND_CAP - DB_NEW_CAP);
         if ((u < ratio) && !acc) s_err |= ERR_CAND_OVERFLOW;
         if (acc) { st->accepted++; st->sum_dE_accepted += dE; }
+        if (acc && s_logat >= 0) a.log_label[(size_t)k * a.log_cap + s_logat] = 1;
         s_accept = acc;
       }
       __syncthreads();
@@ -573,6 +625,7 @@ __global__ __launch_bounds__(DB_BLOCK) void k_db_sweep(DbArgs a) {
     st->ncand_end = n;
     if (s_err) atomicOr(&a.err[k], s_err);
     a.ncand[k] = n;
+    if (a.log_n) a.log_n[k] = s_logn;
   }
   for (int t = threadIdx.x; t < n; t += blockDim.x) a.cand[(size_t)k * DB_CAND_CAP + t] = s_keys[t];
 }
@@ -601,6 +654,324 @@ __global__ __launch_bounds__(DB_BLOCK) void k_db_probe(DbArgs a, int k, const ui
 }
 
 // ---------------------------------------------------------------------------------------
+// Learned proposal.  A move is drawn from the mixture (1 - mix) w / Z + mix uniform over C(x),
+// w = sigmoid(f) of the network's logit f and Z the sum of w over C(x), and accepted with the
+// Metropolis-Hastings ratio exp(-dE/T) q(m | x') / q(m | x): the reverse of a move is the same
+// key, since the canonical layout makes every move an involution.  The weights live beside
+// the sorted list with their running sums; after a move only the candidates that touch its
+// two chains are scored again.  Random words of attempt t: w0 picks the move (uniform choice, or the
+// softmax position u01(w0) Z), w1 is the acceptance uniform, w2 < mix selects the uniform
+// component.
+// ---------------------------------------------------------------------------------------
+constexpr int LS_SORT = 4096;    // power-of-two sort buffer >= DB_CAND_CAP
+constexpr int LS_NEW_CAP = 512;  // candidates touching the two chains of one move
+
+struct LearnedAttempt {
+  Move mv;
+  uint64_t key;
+  double qf, dE, u;
+  int rev, acc;
+};
+
+// sum over the workgroup (fixed order: wavefront trees, then the wavefront totals in order)
+__device__ double block_sum_f64(double v, double* s_tmp, double* s_out) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  if (lane == 0) s_tmp[wv] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double acc = 0.0;
+    for (int q = 0; q < (int)(blockDim.x >> 6); ++q) acc += s_tmp[q];
+    *s_out = acc;
+  }
+  __syncthreads();
+  return *s_out;
+}
+
+// s_cum[t] = s_w[0] + ... + s_w[t] for t < n (n <= 3 * DB_BLOCK); returns the total
+__device__ double block_cumsum_f64(const double* s_w, double* s_cum, int n, double* s_tmp, double* s_out) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int per = (n + DB_BLOCK - 1) / DB_BLOCK;
+  const int t0 = threadIdx.x * per;
+  double loc = 0.0;
+  for (int q = 0; q < per; ++q)
+    if (t0 + q < n) loc += s_w[t0 + q];
+  double incl = loc;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const double t = __shfl_up(incl, o, 64);
+    if (lane >= o) incl += t;
+  }
+  if (lane == 63) s_tmp[wv] = incl;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double acc = 0.0;
+    for (int q = 0; q < (int)(blockDim.x >> 6); ++q) { const double t = s_tmp[q]; s_tmp[q] = acc; acc += t; }
+    *s_out = acc;
+  }
+  __syncthreads();
+  double run = s_tmp[wv] + (incl - loc);
+  for (int q = 0; q < per; ++q)
+    if (t0 + q < n) { run += s_w[t0 + q]; s_cum[t0 + q] = run; }
+  __syncthreads();
+  return *s_out;
+}
+
+// proposal weights of keys[0, n) in topology T, one 64-row network tile at a time
+__device__ void score_keys(const MeltDesc& d, const Topo& T, const DbArgs& a, const uint64_t* keys, int n,
+                           double* w, NetTile& t) {
+  for (int r0 = 0; r0 < n; r0 += NN_TILE) {
+    if (threadIdx.x < NN_TILE) {
+      const int r = r0 + threadIdx.x;
+      if (r < n) {
+        float f[NN_IN];
+        move_features(d, T, a.x, a.NP, decode_key(keys[r], d.M, d.N), f);
+        nn_set_input(t, threadIdx.x, f);
+      } else {
+        nn_zero_input(t, threadIdx.x);
+      }
+    }
+    nn_forward_tile<DB_BLOCK / 64>(t, a.net, nullptr);
+    if (threadIdx.x < NN_TILE && r0 + (int)threadIdx.x < n) w[r0 + threadIdx.x] = nn_weight(t.logit[threadIdx.x]);
+  }
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(DB_BLOCK) void k_db_sweep_learned(DbArgs a) {
+  __shared__ uint64_t s_keys[LS_SORT];     // sorted candidate keys [0, n)
+  __shared__ double s_w[DB_CAND_CAP];      // their proposal weights sigmoid(f)
+  __shared__ double s_cum[DB_CAND_CAP];    // running sums of s_w
+  __shared__ uint64_t s_new[LS_NEW_CAP];   // candidates touching A or B after the move
+  __shared__ double s_wn[LS_NEW_CAP];
+  __shared__ uint64_t s_ns[LS_NEW_CAP];    // the same, sorted
+  __shared__ double s_wns[LS_NEW_CAP];
+  __shared__ uint64_t s_rm[LS_NEW_CAP];    // current candidates touching A or B
+  __shared__ NetTile s_t;
+  __shared__ double s_dtmp[DB_BLOCK / 64];
+  __shared__ double s_dout;
+  __shared__ int s_tmp[DB_BLOCK / 64];
+  __shared__ int s_cnt[4];
+  __shared__ int s_total, s_nrm;
+  __shared__ uint32_t s_err;
+  __shared__ LearnedAttempt s_at;
+
+  const int k = blockIdx.x;
+  const MeltDesc& d = a.md[k];
+  const int M = d.M, N = d.N;
+  kgdb_db_stats* st = (kgdb_db_stats*)a.stats + k;
+  if (threadIdx.x == 0) {
+    st->attempts = st->no_candidate = st->accepted = st->reverse_impossible = st->sum_ncand = 0;
+    st->sum_dE_accepted = 0.0;
+    st->ncand_end = 0;
+    s_err = 0;
+  }
+  int n = a.ncand[k];
+  if (n > DB_CAND_CAP || a.err[k] != 0) {
+    if (threadIdx.x == 0) st->ncand_end = n;
+    return;
+  }
+  int P = 1;
+  while (P < n) P <<= 1;
+  for (int t = threadIdx.x; t < P; t += blockDim.x) s_keys[t] = t < n ? a.cand[(size_t)k * DB_CAND_CAP + t] : ~0ull;
+  __syncthreads();
+  for (int size = 2; size <= P; size <<= 1)
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int t = threadIdx.x; t < P; t += blockDim.x) {
+        const int o = t ^ stride;
+        if (o > t) {
+          const bool up = (t & size) == 0;
+          const uint64_t x0 = s_keys[t], x1 = s_keys[o];
+          if ((x0 > x1) == up) { s_keys[t] = x1; s_keys[o] = x0; }
+        }
+      }
+      __syncthreads();
+    }
+  const double mix = a.mix;
+  {
+    const Topo T{a.chain, a.loc, d.off, N, {0, 0, 0, 0, -1}};
+    score_keys(d, T, a, s_keys, n, s_w, s_t);
+  }
+  double Z = block_cumsum_f64(s_w, s_cum, n, s_dtmp, &s_dout);
+
+  const int64_t K = a.nattempt[k];
+  const uint64_t sweep = a.sweep_ctr[k];
+  for (int64_t att = 0; att < K; ++att) {
+    __syncthreads();  // every wavefront is done with the previous attempt's shared record
+    if (n == 0) {
+      if (threadIdx.x == 0) { st->attempts += K - att; st->no_candidate += K - att; }
+      break;
+    }
+    if (threadIdx.x == 0) {
+      const U64x4 r = rng_draw(d, (uint64_t)att, sweep, ST_DB);
+      int idx;
+      if (u01(r.w[2]) < mix) {
+        idx = (int)rng_choice(r.w[0], (uint64_t)n);
+      } else {
+        const double t = u01(r.w[0]) * Z;  // first position whose running sum exceeds t
+        int lo = 0, hi = n;
+        while (lo < hi) { const int mid = (lo + hi) >> 1; if (s_cum[mid] > t) hi = mid; else lo = mid + 1; }
+        idx = lo < n ? lo : n - 1;
+      }
+      LearnedAttempt& at = s_at;
+      at.key = s_keys[idx];
+      at.mv = decode_key(at.key, M, N);
+      const Move mv = at.mv;
+      at.qf = (1.0 - mix) * s_w[idx] / Z + mix / (double)n;
+      at.dE = move_dE(d, a.chain, a.loc, a.x, a.NP, mv);
+      at.u = u01(r.w[1]);
+      const Topo To{a.chain, a.loc, d.off, N, {mv.A, mv.i, mv.B, mv.j, -1}};
+      at.rev = dist2(a.x, a.NP, d.L, To.at(mv.A, mv.i), To.at(mv.A, mv.i + 1)) <= d.rmax2 &&
+               dist2(a.x, a.NP, d.L, To.at(mv.B, mv.j), To.at(mv.B, mv.j + 1)) <= d.rmax2;
+      at.acc = 0;
+      st->attempts++;
+      st->sum_ncand += n;
+      if (!at.rev) st->reverse_impossible++;
+      s_cnt[0] = s_cnt[1] = 0;
+      s_nrm = 0;
+    }
+    __syncthreads();
+    if (!s_at.rev) continue;
+    const Move mv = s_at.mv;
+    const Topo Tn{a.chain, a.loc, d.off, N, mv};
+    count_touching(d, Tn, a, mv.A, mv.B, s_cnt, s_new, &s_err, LS_NEW_CAP);
+    double kept = 0.0;
+    for (int t = threadIdx.x; t < n; t += blockDim.x) {
+      const uint64_t key = s_keys[t];
+      if (touches(key, M, N, mv.A, mv.B)) {
+        const int q = atomicAdd(&s_nrm, 1);
+        if (q < LS_NEW_CAP) s_rm[q] = key;
+      } else {
+        kept += s_w[t];
+      }
+    }
+    const double kept_sum = block_sum_f64(kept, s_dtmp, &s_dout);  // synchronises
+    const int nn = s_cnt[0], nrm = s_nrm;
+    if (nn > LS_NEW_CAP || nrm > LS_NEW_CAP) {
+      if (threadIdx.x == 0) s_err |= ERR_CAND_OVERFLOW;
+      __syncthreads();
+      continue;
+    }
+    score_keys(d, Tn, a, s_new, nn, s_wn, s_t);
+    if (threadIdx.x == 0) {
+      LearnedAttempt& at = s_at;
+      double Z2 = kept_sum, wr = -1.0;
+      for (int q = 0; q < nn; ++q) {
+        Z2 += s_wn[q];
+        if (s_new[q] == at.key) wr = s_wn[q];
+      }
+      const int n2 = n - nrm + nn;
+      if (wr < 0.0) {
+        s_err |= ERR_DB_MISMATCH;  // the reverse move must be a candidate of x'
+      } else {
+        const double qr = (1.0 - mix) * wr / Z2 + mix / (double)n2;
+        const double ratio = exp(-at.dE / d.T) * qr / at.qf;
+        at.acc = (at.u < ratio) && n2 <= DB_CAND_CAP;
+        if ((at.u < ratio) && !at.acc) s_err |= ERR_CAND_OVERFLOW;
+        if (at.acc) { st->accepted++; st->sum_dE_accepted += at.dE; }
+      }
+    }
+    __syncthreads();
+    if (!s_at.acc) continue;
+
+    // ---- commit: new rows of chains A and B
+    {
+      int vals[DB_MAXPT];
+#pragma unroll
+      for (int q = 0; q < DB_MAXPT; ++q) {
+        const int idx = threadIdx.x + q * DB_BLOCK;
+        if (idx < 2 * N) vals[q] = Tn.at(idx < N ? mv.A : mv.B, (idx < N ? idx : idx - N) + 1);
+      }
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < DB_MAXPT; ++q) {
+        const int idx = threadIdx.x + q * DB_BLOCK;
+        if (idx < 2 * N) {
+          const int X = idx < N ? mv.A : mv.B;
+          const int p0 = idx < N ? idx : idx - N;
+          a.chain[d.off + X * N + p0] = vals[q];
+          a.loc[vals[q]] = X * N + p0;
+        }
+      }
+    }
+    // ---- list update: keys touching A or B leave (order kept), the new ones merge in with
+    // their weights
+    {
+      for (int t = threadIdx.x; t < nn; t += blockDim.x) {
+        const uint64_t key = s_new[t];
+        int r = 0;
+        for (int q = 0; q < nn; ++q) r += s_new[q] < key ? 1 : 0;
+        s_ns[r] = key;
+        s_wns[r] = s_wn[t];
+      }
+      const int per = (n + DB_BLOCK - 1) / DB_BLOCK;  // <= 3
+      const int t0 = threadIdx.x * per;
+      uint64_t kk[3];
+      double kw[3];
+      int keep = 0, flags = 0;
+      for (int q = 0; q < per && q < 3; ++q) {
+        if (t0 + q < n) {
+          kk[q] = s_keys[t0 + q];
+          kw[q] = s_w[t0 + q];
+          if (!touches(kk[q], M, N, mv.A, mv.B)) { ++keep; flags |= 1 << q; }
+        }
+      }
+      const int pos0 = block_exclusive_scan(keep, s_tmp, &s_total);  // synchronises
+      const int nk = s_total;
+      // destination of new key t: t + #(kept keys below it)
+      int dnew = -1;
+      uint64_t knew = 0;
+      double wnew = 0.0;
+      if ((int)threadIdx.x < nn) {
+        knew = s_ns[threadIdx.x];
+        wnew = s_wns[threadIdx.x];
+        int lo = 0, hi = n;
+        while (lo < hi) { const int mid = (lo + hi) >> 1; if (s_keys[mid] < knew) lo = mid + 1; else hi = mid; }
+        int below_rm = 0;
+        for (int q = 0; q < nrm; ++q) below_rm += s_rm[q] < knew ? 1 : 0;
+        dnew = (int)threadIdx.x + lo - below_rm;
+      }
+      // destination of a kept key: its kept rank + #(new keys below it)
+      int dk[3];
+      int pos = pos0;
+      for (int q = 0; q < per && q < 3; ++q) {
+        dk[q] = -1;
+        if (flags & (1 << q)) {
+          int lo = 0, hi = nn;
+          while (lo < hi) { const int mid = (lo + hi) >> 1; if (s_ns[mid] < kk[q]) lo = mid + 1; else hi = mid; }
+          dk[q] = pos++ + lo;
+        }
+      }
+      __syncthreads();
+      for (int q = 0; q < per && q < 3; ++q)
+        if (dk[q] >= 0) { s_keys[dk[q]] = kk[q]; s_w[dk[q]] = kw[q]; }
+      if (dnew >= 0 && dnew < nk + nn) { s_keys[dnew] = knew; s_w[dnew] = wnew; }
+      n = nk + nn;
+      __syncthreads();
+    }
+    Z = block_cumsum_f64(s_w, s_cum, n, s_dtmp, &s_dout);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    st->ncand_end = n;
+    if (s_err) atomicOr(&a.err[k], s_err);
+    a.ncand[k] = n;
+  }
+  for (int t = threadIdx.x; t < n; t += blockDim.x) a.cand[(size_t)k * DB_CAND_CAP + t] = s_keys[t];
+}
+
+// test hook: inputs of the learned proposal for given keys at the current topology
+__global__ __launch_bounds__(256) void k_db_features(DbArgs a, int k, const uint64_t* keys, int nkeys, float* feat) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nkeys) return;
+  const MeltDesc& d = a.md[k];
+  const Topo T{a.chain, a.loc, d.off, d.N, {0, 0, 0, 0, -1}};
+  float f[NN_IN];
+  move_features(d, T, a.x, a.NP, decode_key(keys[t], d.M, d.N), f);
+  for (int q = 0; q < NN_IN; ++q) feat[(size_t)t * NN_IN + q] = f[q];
+}
+
+// ---------------------------------------------------------------------------------------
 void launch_db_build(const DbArgs& a, const BlockMap& pm, const BlockMap& cm13, hipStream_t s) {
   hipLaunchKernelGGL(k_db_bin, dim3(pm.nblk), dim3(256), 0, s, a.md, pm.melt, pm.base, a.NP, a.x, a.cnt13,
                      a.bucket13, a.err);
@@ -616,6 +987,14 @@ void launch_db_sweep(const DbArgs& a, hipStream_t s) {
 void launch_db_probe(const DbArgs& a, int melt, const uint64_t* keys, int nkeys, double* dE, int64_t* nafter,
                      hipStream_t s) {
   if (nkeys > 0) hipLaunchKernelGGL(k_db_probe, dim3(nkeys), dim3(DB_BLOCK), 0, s, a, melt, keys, dE, nafter);
+}
+
+void launch_db_sweep_learned(const DbArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_db_sweep_learned, dim3(a.nm), dim3(DB_BLOCK), 0, s, a);
+}
+
+void launch_db_features(const DbArgs& a, int melt, const uint64_t* keys, int nkeys, float* feat, hipStream_t s) {
+  if (nkeys > 0) hipLaunchKernelGGL(k_db_features, dim3((nkeys + 255) / 256), dim3(256), 0, s, a, melt, keys, nkeys, feat);
 }
 
 }  // namespace kgdb

@@ -6,6 +6,7 @@
 namespace kgdb {
 
 struct MeltDesc;
+struct NetQ;
 
 // lanes that cooperate on one cell in the cell finalisation (blocks of 256 threads); the
 // fused force kernel is built for 1, 2, 4 or 8 lanes per monomer (chosen at run time)
@@ -138,10 +139,46 @@ struct DbArgs {
   const int64_t* nattempt;    // per melt attempts of this sweep
   void* stats;                // per melt kgdb_db_stats
   int debug;                  // recount the old topology and compare with the list
+  // learned proposal: quantised network and the uniform share of the proposal mixture
+  const NetQ* net;
+  double mix;
+  // optional log of uniform sweeps: inputs [melt][cap][25] and accept labels [melt][cap]
+  float* log_feat;
+  int32_t* log_label;
+  int64_t log_cap;
+  int64_t* log_n;             // [nm] records written per melt
 };
 void launch_db_build(const DbArgs& a, const BlockMap& pm, const BlockMap& cm13, hipStream_t s);
 void launch_db_sweep(const DbArgs& a, hipStream_t s);
 void launch_db_probe(const DbArgs& a, int melt, const uint64_t* keys, int nkeys, double* dE, int64_t* nafter,
                      hipStream_t s);
+void launch_db_sweep_learned(const DbArgs& a, hipStream_t s);
+// inputs of the learned proposal for given keys of melt `melt` at its current topology
+void launch_db_features(const DbArgs& a, int melt, const uint64_t* keys, int nkeys, float* feat, hipStream_t s);
+
+// ---- network of the learned proposal (kgdb_mlp.hip)
+struct MlpWork {  // training workspace carved from one device buffer
+  NetQ* net;
+  int16_t* xq;
+  uint8_t* code;
+  uint8_t* mask;
+  float* logit;
+  double* gs;
+  double* g;
+  double* lossp;
+  double* part;
+  double* grad;
+  double* loss;
+  int nchunk;
+  size_t bytes;
+};
+MlpWork mlp_work_layout(void* base, int64_t n);  // base == nullptr: sizes only
+void launch_mlp_quant(const float* P, NetQ* q, hipStream_t s);
+void launch_mlp_forward(const NetQ* net, const float* feat, int64_t n, float* logit, const MlpWork* rec,
+                        hipStream_t s);
+void launch_mlp_grad(const MlpWork& w, const int32_t* label, int64_t n, hipStream_t s);
+void launch_mlp_adam(float* P, float* m, float* v, const double* g, double c1, double c2, double lr, double b1,
+                     double b2, double eps, hipStream_t s);
+size_t netq_bytes();
 
 }  // namespace kgdb

@@ -45,3 +45,11 @@ def test_params_struct_matches_header_fields():
     body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
     names = re.findall(r"\b([a-zA-Z_0-9]+)\s*[,;]", body)
     assert names == [f for f, _ in _lib.Params._fields_]
+
+
+def test_network_size_agrees_everywhere():
+    from oracle import oracle as o
+    from paper_2109_11001_amd import _lib
+    src = open(os.path.join(ROOT, "include", "kgdb.h")).read()
+    n_hdr = int(re.search(r"#define KGDB_MLP_NPARAM (\d+)", src).group(1))
+    assert n_hdr == _lib.MLP_NPARAM == o.NN_NPARAM == _lib.load().kgdb_mlp_nparam()

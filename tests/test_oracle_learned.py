@@ -200,8 +200,8 @@ def test_learned_q_is_the_mixture_of_softmax_and_uniform(melt):
     P = inputs.random_mlp_params(2, w_scale=0.4)
     keys, q = melt.learned_q(P, 0.2)
     assert np.array_equal(keys, melt.candidates())
-    s = o.mlp_forward(P, melt.features(keys)).astype(np.float64)
-    w = np.exp(np.clip(s, -40, 40))
+    s = np.clip(o.mlp_forward(P, melt.features(keys)).astype(np.float64), -40, 40)
+    w = 1.0 / (1.0 + np.exp(-s))
     assert np.allclose(q, 0.8 * w / w.sum() + 0.2 / len(keys), rtol=1e-12)
     assert q.sum() == pytest.approx(1.0, abs=1e-12)
     assert q.max() / q.min() > 2.0  # the network makes the proposal far from uniform
