@@ -9,9 +9,15 @@ steps).  The full 10^4-step run is 100 such steps.
 
 The project form (FP32 forces, FP64 state/energies/Delta E) gives `value`; the plain FP64 path is
 timed the same way on the same GPU and reported beside it.  The dominant kernel (the fused force
-+ integrator kernel) is timed with HIP events on the library's stream over a profiled run of the
-same workload; its algorithmic bytes per launch give the roofline figure.
++ integrator kernel) is timed with HIP events on the library's stream over a profiled pass of the
+same length as the timed region, run right after it (direct launches, since events cannot
+bracket single kernels inside a replayed graph); its algorithmic bytes per launch give the
+roofline figure.  The learned-proposal form runs on the same system at kappa = 2.5: a network is
+trained on the GPU from logged uniform sweeps (untimed set-up), then the same bench steps are
+timed with the learned and with the uniform proposal from one shared state.
 """
+import hashlib
+import re
 import argparse
 import json
 import os
@@ -27,6 +33,7 @@ HBM_PEAK_GBS = 8000.0
 WORKLOAD = dict(M=200, N=1000, rho=0.85, kappa=2.0, n_exp=2.0, k_fene=0.0, dt=0.01, gamma=1.0, T=1.0,
                 seed=1, warmup_steps=1000)
 MD_PER_STEP = 100
+LEARNED_KAPPA = 2.5
 
 
 def step_kernel_bytes(mixed, mean_list):
@@ -80,7 +87,7 @@ def run_gpu(kg, precision, steps, warmup, stream, profile_steps):
     # per-launch HIP-event timing of the fused force kernel (direct launches, same workload)
     if profile_steps > 0:
         b.profile(True)
-        for _ in range(max(1, profile_steps // MD_PER_STEP)):
+        for _ in range(max(1, profile_steps)):
             b.md_steps(MD_PER_STEP)
             b.db_sweep(K)
         prof = b.profile_read()
@@ -96,6 +103,100 @@ def run_gpu(kg, precision, steps, warmup, stream, profile_steps):
     out["monomers"] = nm
     b.close()
     return out
+
+
+def run_learned(kg, steps, warmup, stream, log_sweeps=20, log_attempts=2000, train_steps=300):
+    """Learned vs uniform proposal on the 200 x 1000 melt at kappa = 2.5 (mixed precision)."""
+    import torch
+    params = dict(WORKLOAD, precision=kg.PREC_MIXED, kappa=LEARNED_KAPPA)
+    # set-up (untimed): logged uniform sweeps with MD in between, then training on the GPU
+    t0 = time.perf_counter()
+    b = kg.Batch([params], stream=stream)
+    b.autotune(0, reps=20)
+    feats, labs = [], []
+    for _ in range(log_sweeps):
+        b.md_steps(MD_PER_STEP)
+        st, f, lab, nl = b.db_sweep_log(log_attempts, cap=log_attempts)
+        feats.append(f[0, : nl[0]].clone())
+        labs.append(lab[0, : nl[0]].clone())
+    x = torch.cat(feats)
+    y = torch.cat(labs)
+    from tests.inputs import random_mlp_params  # seeded initial weights (no method arithmetic)
+    tr = kg.Trainer(random_mlp_params(3, w_scale=0.1, b_scale=0.1), max_batch=len(y), lr=3e-3, stream=stream)
+    with torch.cuda.stream(stream):
+        first = float(tr.step(x, y).cpu()[0])
+        for _ in range(train_steps - 1):
+            loss = tr.step(x, y)
+        last = float(loss.cpu()[0])
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    state = b.get_state()
+    b.close()
+    out = {"kappa": LEARNED_KAPPA, "train_records": int(len(y)), "train_accept_rate": float(y.float().mean()),
+           "train_steps": train_steps, "loss_first": first, "loss_last": last, "setup_s": round(setup_s, 2)}
+    for name, prop in (("uniform", kg.PROPOSAL_UNIFORM), ("learned", kg.PROPOSAL_LEARNED)):
+        g = kg.Batch([dict(params, warmup_steps=0, proposal=prop)], stream=stream)
+        g.set_state(0, x=state["x"], v=state["v"], fl=state["fl"], chains=state["chains"],
+                    counters=state["counters"])
+        g.autotune(0, reps=20)
+        if prop == kg.PROPOSAL_LEARNED:
+            g.set_proposal_net(tr.params, 0.1)
+        for _ in range(warmup):
+            g.md_steps(MD_PER_STEP)
+            g.db_sweep(-1)
+        torch.cuda.synchronize()
+        acc = att = 0
+        t_db = 0.0
+        a0 = time.perf_counter()
+        for _ in range(steps):
+            g.md_steps(MD_PER_STEP)
+            c = time.perf_counter()
+            st = g.db_sweep(-1)[0]
+            t_db += time.perf_counter() - c
+            acc += st["accepted"]
+            att += st["attempts"] - st["no_candidate"]
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - a0
+        nm, _ = g.sizes()
+        out[name] = {"monomer_steps_per_s": nm * MD_PER_STEP * steps / wall, "db_accepted_per_s": acc / wall,
+                     "accept_rate": acc / max(att, 1), "db_accepted_per_sweep_s": acc / t_db if t_db > 0 else None,
+                     "db_s": round(t_db, 4), "attempts": att}
+        g.close()
+    out["accepted_per_s_gain"] = out["learned"]["db_accepted_per_s"] / max(out["uniform"]["db_accepted_per_s"], 1e-30)
+    return out
+
+
+def step_kernel_hash():
+    """sha256 of the step kernel's source (its body in kgdb_nl.hip plus kgdb_dev.h)."""
+    csrc = os.path.join(ROOT, "paper_2109_11001_amd", "csrc")
+    nl = open(os.path.join(csrc, "kgdb_nl.hip")).read()
+    dev = open(os.path.join(csrc, "kgdb_dev.h")).read()
+    m = re.search(r"__global__ __launch_bounds__\(256\) void k_nl_step\(NlArgs a\) \{.*?\n\}\n", nl, re.S)
+    return hashlib.sha256((m.group(0) + dev).encode()).hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per launch of the step kernel from the committed PMC summary, or None when the
+    kernel source has changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "pmc_k_nl_step_200k_mixed.md")
+    try:
+        text = open(path).read()
+        rec = json.loads(re.search(r"^traffic_json: (\{.*\})$", text, re.M).group(1))
+        sha = step_kernel_hash()
+    except (OSError, AttributeError, ValueError):
+        return None
+    return rec if rec.get("kernel_sha256") == sha else None
+
+
+def copy_calibration(mib=256, reps=5):
+    """A plain device copy of known size, for scaling the FETCH_SIZE / WRITE_SIZE counters."""
+    import torch
+    src = torch.ones(mib << 18, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(f"[bench] copy calibration: {reps} copies of {mib} MiB", file=sys.stderr, flush=True)
 
 
 def cpu_baseline(md_steps=15, db_attempts=8):
@@ -123,10 +224,16 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100, help="timed bench steps (100 MD steps + 1 sweep each)")
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--profile-steps", type=int, default=1000)
+    ap.add_argument("--profile-steps", type=int, default=-1,
+                    help="bench steps of the HIP-event-timed pass (default: as many as timed)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run plain copies of known size (for PMC byte counters)")
     args = ap.parse_args()
+    if args.profile_steps < 0:
+        args.profile_steps = args.steps
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); melts shard across GPUs without any "
               "exchange, so the per-GPU figure is the single-GPU one", file=sys.stderr)
@@ -136,6 +243,8 @@ def main():
     import paper_2109_11001_amd as kg
     torch.cuda.set_device(0)
     stream = torch.cuda.Stream()
+    if args.copy_calibration:
+        copy_calibration()
     print(f"[bench] mixed path: {args.warmup} warm-up + {args.steps} timed steps", file=sys.stderr, flush=True)
     mixed = run_gpu(kg, kg.PREC_MIXED, args.steps, args.warmup, stream, args.profile_steps)
     print(f"[bench] mixed done: {mixed['monomer_steps_per_s']:.3e} monomer-steps/s", file=sys.stderr, flush=True)
@@ -143,6 +252,12 @@ def main():
     if not args.no_fp64:
         fp64 = run_gpu(kg, kg.PREC_FP64, args.steps, args.warmup, stream, args.profile_steps)
         print(f"[bench] fp64 done: {fp64['monomer_steps_per_s']:.3e} monomer-steps/s", file=sys.stderr, flush=True)
+    learned = None
+    if not args.no_learned:
+        print("[bench] learned-proposal form (training, then learned vs uniform)", file=sys.stderr, flush=True)
+        learned = run_learned(kg, args.steps, args.warmup, stream)
+        print(f"[bench] learned done: accept rate {learned['learned']['accept_rate']:.3f} vs "
+              f"{learned['uniform']['accept_rate']:.3f}", file=sys.stderr, flush=True)
     cpu = None
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
@@ -153,9 +268,13 @@ def main():
         bpm = step_kernel_bytes(True, mixed["nl"]["mean_list"])
         bytes_launch = bpm * mixed["monomers"]
         achieved = bytes_launch / (mixed["force_kernel_ms"] * 1e-3) / 1e9
+        tr = measured_traffic()
         roof = {"bound": "hbm", "kernel": "k_nl_step<float, close|open> (list forces + bonded + Langevin VV)",
                 "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": tr["bytes_per_launch"] if tr else None,
+                "traffic_split": {k_: tr[k_] for k_ in ("fetch_bytes", "write_bytes", "scale")} if tr else None,
+                "algorithmic_bytes_per_launch": round(bytes_launch),
                 "bytes_per_monomer": round(bpm, 1), "avg_launch_ms": mixed["force_kernel_ms"],
                 "launches": mixed["force_launches_timed"], "neighbour_lists": mixed["nl"],
                 "autotune_ms_per_step_by_K": mixed["tune_ms"],
@@ -187,6 +306,8 @@ def main():
                              "db_accepted_per_s": fp64["db_accepted_per_s"],
                              "force_kernel_ms": fp64.get("force_kernel_ms")}
         line["speedup_vs_fp64_path"] = mixed["monomer_steps_per_s"] / fp64["monomer_steps_per_s"]
+    if learned:
+        line["learned_form"] = learned
     line["roofline"] = roof
     line["cpu_baseline"] = cpu
     print(json.dumps(line), flush=True)

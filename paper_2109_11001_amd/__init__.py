@@ -50,6 +50,7 @@ class Batch:
         h = C.c_void_p()
         check(L.kgdb_init_batch(arr, len(melts), _stream_handle(stream), C.byref(h)))
         self._h = h
+        self._stream = stream
         self.params = [dict(DEFAULTS, **m) for m in melts]
         self.nm = len(melts)
         self.geom = []
@@ -175,8 +176,14 @@ class Batch:
     def db_sweep_log(self, n_attempts, cap):
         """Uniform sweep recording each attempt: (stats, feat [nm][cap][25], label [nm][cap], n_logged)."""
         import torch
-        feat = torch.zeros((self.nm, cap, NN_IN), dtype=torch.float32, device="cuda")
-        lab = torch.zeros((self.nm, cap), dtype=torch.int32, device="cuda")
+        if self._stream is not None and hasattr(self._stream, "cuda_stream"):
+            with torch.cuda.stream(self._stream):  # buffers ordered on the library's stream
+                feat = torch.empty((self.nm, cap, NN_IN), dtype=torch.float32, device="cuda")
+                lab = torch.empty((self.nm, cap), dtype=torch.int32, device="cuda")
+        else:
+            feat = torch.empty((self.nm, cap, NN_IN), dtype=torch.float32, device="cuda")
+            lab = torch.empty((self.nm, cap), dtype=torch.int32, device="cuda")
+            torch.cuda.synchronize()  # the library's own stream is not ordered after torch's
         st = (DbStats * self.nm)()
         nl = np.zeros(self.nm, np.int64)
         check(load().kgdb_db_sweep_log(self._h, int(n_attempts), st, _dptr(feat), _dptr(lab), int(cap), ptr(nl)))
@@ -261,6 +268,7 @@ class Trainer:
         self.v = torch.zeros_like(self.params)
         self.loss = torch.zeros(1, dtype=torch.float64, device="cuda")
         self.ws, self.nb = _workspace(max_batch)
+        torch.cuda.synchronize()  # the buffers are used on `stream`
         self.max_batch = max_batch
         self.t = 0
         self.lr, self.b1, self.b2, self.eps = lr, b1, b2, eps

@@ -427,11 +427,10 @@ static int nl_step(kgdb_batch* b, int mode, uint32_t s_off, bool capture) {
       HIPCHK(hipEventRecord(b->ev[4 * b->ev_used + 2], b->s));
       HIPCHK(hipEventRecord(b->ev[4 * b->ev_used + 3], b->s));
     }
-    HIPCHK(hipEventRecord(b->ev[4 * b->ev_used], b->s));
   }
-  launch_nl_step(b->prec, mode, a, b->pm.nblk, b->s);
+  launch_nl_step(b->prec, mode, a, b->pm.nblk, b->s, prof ? b->ev[4 * b->ev_used] : nullptr,
+                 prof ? b->ev[4 * b->ev_used + 1] : nullptr);
   if (prof) {
-    HIPCHK(hipEventRecord(b->ev[4 * b->ev_used + 1], b->s));
     b->ev_used++;
     b->rebuild_pending = false;
   }

@@ -105,7 +105,9 @@ struct NlArgs {
 };
 size_t nl_stage_bytes(int prec, int cap);  // dynamic LDS of the list build
 void launch_nl_rebuild(int prec, const NlArgs& a, int pblk, int cblk, int rblk, hipStream_t s);
-void launch_nl_step(int prec, int mode, const NlArgs& a, int pblk, hipStream_t s);
+// ev0/ev1 (optional): events stamped at the kernel's own start and end
+void launch_nl_step(int prec, int mode, const NlArgs& a, int pblk, hipStream_t s, hipEvent_t ev0 = nullptr,
+                    hipEvent_t ev1 = nullptr);
 size_t rel_bytes(int prec);
 
 // ---- init and observables (kgdb_obs.hip)

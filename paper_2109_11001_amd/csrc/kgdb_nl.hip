@@ -14,6 +14,8 @@
 // velocity-Verlet update.  It writes the new relative coordinates to the other buffer and
 // flags the run stale when a monomer has moved more than skin/2 since the rebuild (the host
 // then reruns the chunk with more frequent rebuilds).
+#include <hip/hip_ext.h>
+
 #include "kgdb_dev.h"
 #include "kgdb_kernels.h"
 
@@ -473,9 +475,13 @@ void launch_nl_rebuild(int prec, const NlArgs& a, int pblk, int cblk, int rblk, 
   }
 }
 
-void launch_nl_step(int prec, int mode, const NlArgs& a, int pblk, hipStream_t s) {
-#define KG_CASE(R, M) \
-  case M: hipLaunchKernelGGL((k_nl_step<R, M>), dim3(pblk), dim3(256), 0, s, a); break;
+void launch_nl_step(int prec, int mode, const NlArgs& a, int pblk, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+  // with events: hipExtLaunchKernelGGL stamps them at the dispatch's own start and end
+#define KG_CASE(R, M)                                                                               \
+  case M:                                                                                           \
+    if (ev0) hipExtLaunchKernelGGL((k_nl_step<R, M>), dim3(pblk), dim3(256), 0, s, ev0, ev1, 0, a); \
+    else hipLaunchKernelGGL((k_nl_step<R, M>), dim3(pblk), dim3(256), 0, s, a);                    \
+    break;
   if (prec) {
     switch (mode) {
       KG_CASE(float, F_OPEN)
