@@ -171,7 +171,7 @@ def step_kernel_hash():
     csrc = os.path.join(ROOT, "paper_2109_11001_amd", "csrc")
     nl = open(os.path.join(csrc, "kgdb_nl.hip")).read()
     dev = open(os.path.join(csrc, "kgdb_dev.h")).read()
-    m = re.search(r"__global__ __launch_bounds__\(256\) void k_nl_step\(NlArgs a\) \{.*?\n\}\n", nl, re.S)
+    m = re.search(r"void k_nl_step\(NlArgs a\) \{.*?\n\}\n", nl, re.S)
     return hashlib.sha256((m.group(0) + dev).encode()).hexdigest()
 
 

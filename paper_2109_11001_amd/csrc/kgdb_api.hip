@@ -764,7 +764,10 @@ static int init_impl(const kgdb_params* params, int32_t count, void* stream, kgd
   step(dalloc(b, &b->d_inv, np));
   step(dalloc(b, &b->d_tmpi, np));
   step(dalloc(b, &b->d_tmp3, 3 * np));
-  step(dalloc(b, &b->d_start, (size_t)std::max<int64_t>(NC, b->NCL) + 1));
+  {  // cell starts [0, NC], then the scan's scratch: the total and one sum per 1024 cells
+    const int64_t nc_max = std::max<int64_t>(NC, b->NCL);
+    step(dalloc(b, &b->d_start, (size_t)(nc_max + 3 + (nc_max + 1023) / 1024)));
+  }
   step(dalloc(b, &b->d_cntl[0], (size_t)b->NCL));
   step(dalloc(b, &b->d_cntl[1], (size_t)b->NCL));
   step(dalloc(b, &b->d_bucketl, (size_t)b->NCL * NL_CELL_CAP));

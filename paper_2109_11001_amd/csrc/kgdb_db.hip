@@ -53,41 +53,58 @@ __global__ __launch_bounds__(256) void k_db_bin(const MeltDesc* __restrict__ md,
   else atomicOr(&err[k], ERR_NBR_OVERFLOW);
 }
 
+// Four lanes per monomer, each scanning every fourth of the 27 neighbouring cells; hits take
+// their place in the monomer's row through a counter in LDS (the order within a row is free:
+// every consumer sorts what it derives from it).
+constexpr int NBR_LANES = 4;
+
 __global__ __launch_bounds__(256) void k_db_nbr(const MeltDesc* __restrict__ md, const int* __restrict__ blk_melt,
                                                 const int* __restrict__ blk_base, int NP,
                                                 const double* __restrict__ x, const int* __restrict__ cnt13,
                                                 const int* __restrict__ bucket13, int* __restrict__ nnb,
                                                 int* __restrict__ nbr, uint32_t* __restrict__ err) {
+  __shared__ int s_n[256 / NBR_LANES];
+  // logical block lb covers monomers blk_base[lb / 4] + 64 (lb % 4) .. + 63 of melt blk_melt[lb / 4]
   const int lb = xcd_remap(blockIdx.x, gridDim.x);
-  const int k = __builtin_amdgcn_readfirstlane(blk_melt[lb]);
+  const int pb = lb >> 2;
+  const int k = __builtin_amdgcn_readfirstlane(blk_melt[pb]);
   const MeltDesc& d = md[k];
-  const int li = blk_base[lb] + (int)threadIdx.x;
-  if (li >= d.Nm) return;
-  const int u = d.off + li;
+  const int sub = threadIdx.x & (NBR_LANES - 1), m = threadIdx.x >> 2;
+  const int li = blk_base[pb] + (lb & 3) * 64 + m;
+  const bool valid = li < d.Nm;
+  const int u = d.off + (valid ? li : 0);
+  if (sub == 0) s_n[m] = 0;
+  __syncthreads();
   const int nc = d.nc13;
-  const int cx = cell_coord(x[u], d.cinv13, nc), cy = cell_coord(x[NP + u], d.cinv13, nc),
-            cz = cell_coord(x[2 * NP + u], d.cinv13, nc);
+  const double xu = x[u], yu = x[NP + u], zu = x[2 * NP + u];
+  const int cx = cell_coord(xu, d.cinv13, nc), cy = cell_coord(yu, d.cinv13, nc), cz = cell_coord(zu, d.cinv13, nc);
   // distinct neighbouring cells: 3 per side when nc >= 3, else every cell once
-  const int lo = nc >= 3 ? -1 : 0, hi = nc >= 3 ? 1 : nc - 1;
-  int cntu = 0;
-  for (int oz = lo; oz <= hi; ++oz)
-    for (int oy = lo; oy <= hi; ++oy)
-      for (int ox = lo; ox <= hi; ++ox) {
-        const int nx = (cx + ox + nc) % nc, ny = (cy + oy + nc) % nc, nz = (cz + oz + nc) % nc;
-        const int c = d.cell13_off + (nz * nc + ny) * nc + nx;
-        int n = cnt13[c];
-        n = n > DB_CELL_CAP ? DB_CELL_CAP : n;
-        for (int j = 0; j < n; ++j) {
-          const int w = bucket13[c * DB_CELL_CAP + j];
-          if (w == u) continue;
-          if (dist2(x, NP, d.L, u, w) <= d.rmax2) {
-            if (cntu < DB_NBR_CAP) nbr[(size_t)u * DB_NBR_CAP + cntu] = w;
-            ++cntu;
-          }
-        }
+  const int span = nc >= 3 ? 3 : nc, lo = nc >= 3 ? -1 : 0;
+  const int ncell = span * span * span;
+  for (int t = sub; t < ncell && valid; t += NBR_LANES) {
+    const int ox = t % span + lo, oy = (t / span) % span + lo, oz = t / (span * span) + lo;
+    const int nx = (cx + ox + nc) % nc, ny = (cy + oy + nc) % nc, nz = (cz + oz + nc) % nc;
+    const int c = d.cell13_off + (nz * nc + ny) * nc + nx;
+    int n = cnt13[c];
+    n = n > DB_CELL_CAP ? DB_CELL_CAP : n;
+    for (int j = 0; j < n; ++j) {
+      const int w = bucket13[c * DB_CELL_CAP + j];
+      if (w == u) continue;
+      const double dx = min_image(x[w] - xu, d.L);
+      const double dy = min_image(x[NP + w] - yu, d.L);
+      const double dz = min_image(x[2 * NP + w] - zu, d.L);
+      if (dx * dx + dy * dy + dz * dz <= d.rmax2) {
+        const int q = atomicAdd(&s_n[m], 1);
+        if (q < DB_NBR_CAP) nbr[(size_t)u * DB_NBR_CAP + q] = w;
       }
-  if (cntu > DB_NBR_CAP) { atomicOr(&err[k], ERR_NBR_OVERFLOW); cntu = DB_NBR_CAP; }
-  nnb[u] = cntu;
+    }
+  }
+  __syncthreads();
+  if (valid && sub == 0) {
+    const int total = s_n[m];
+    if (total > DB_NBR_CAP) atomicOr(&err[k], ERR_NBR_OVERFLOW);
+    nnb[u] = total > DB_NBR_CAP ? DB_NBR_CAP : total;
+  }
 }
 
 __device__ __forceinline__ uint64_t make_key(int M, int N, int A, int i, int B, int j, int var) {
@@ -278,25 +295,54 @@ __device__ void count_touching(const MeltDesc& d, const Topo& T, const DbArgs& a
                                uint64_t* s_new, uint32_t* s_err, int new_cap = DB_NEW_CAP) {
   const int N = d.N;
   int local = 0;
-  for (int idx = threadIdx.x; idx < 2 * N; idx += blockDim.x) {
-    const int X = idx < N ? A : B;
-    const int p = (idx < N ? idx : idx - N) + 1;
-    const int u = T.at(X, p);
-    const int nn = a.nnb[u];
-    for (int q = 0; q < nn; ++q) {
-      const int w = a.nbr[(size_t)u * DB_NBR_CAP + q];
-      int Cw, pw;
-      T.where(w, Cw, pw);
-      if (Cw == X) continue;
-      if (X == B && Cw == A) continue;  // counted from chain A's side
-      first_bond_candidates(T, a.x, a.NP, d.L, d.rmax2, d.M, u, X, p, w, Cw, pw, [&](uint64_t key) {
-        ++local;
-        if (s_new) {
-          const int s = atomicAdd(&s_count[1], 1);
-          if (s < new_cap) s_new[s] = key;
-          else atomicOr(s_err, ERR_CAND_OVERFLOW);
+  auto emit = [&](uint64_t key) {
+    ++local;
+    if (s_new) {
+      const int s = atomicAdd(&s_count[1], 1);
+      if (s < new_cap) s_new[s] = key;
+      else atomicOr(s_err, ERR_CAND_OVERFLOW);
+    }
+  };
+  // each thread takes two monomers per pass and requests their close-pair rows four entries
+  // (16 bytes) at a time, so the loads of both monomers are in flight together
+  for (int idx0 = threadIdx.x; idx0 < 2 * N; idx0 += 2 * blockDim.x) {
+    int X[2], p[2], u[2], nn[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int idx = idx0 + h * (int)blockDim.x;
+      const bool ok = idx < 2 * N;
+      X[h] = (idx < N) ? A : B;
+      p[h] = (idx < N ? idx : idx - N) + 1;
+      u[h] = ok ? T.at(X[h], p[h]) : -1;
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h) nn[h] = u[h] >= 0 ? a.nnb[u[h]] : 0;
+    const int nmax = nn[0] > nn[1] ? nn[0] : nn[1];
+    for (int q0 = 0; q0 < nmax; q0 += 4) {
+      int w[2][4];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        if (q0 < nn[h]) {
+          const int4 r = *(const int4*)(a.nbr + (size_t)u[h] * DB_NBR_CAP + q0);
+          w[h][0] = r.x; w[h][1] = r.y; w[h][2] = r.z; w[h][3] = r.w;
         }
-      });
+      }
+      int Cw[2][4], pw[2][4];
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          if (q0 + j < nn[h]) T.where(w[h][j], Cw[h][j], pw[h][j]);
+      // the candidate tests (rarely past the index conditions) run one pair at a time
+#pragma unroll 1
+      for (int hj = 0; hj < 8; ++hj) {
+        const int h = hj >> 2, j = hj & 3;
+        if (q0 + j >= nn[h]) continue;
+        const int Cj = Cw[h][j];
+        if (Cj == X[h]) continue;
+        if (X[h] == B && Cj == A) continue;  // counted from chain A's side
+        first_bond_candidates(T, a.x, a.NP, d.L, d.rmax2, d.M, u[h], X[h], p[h], w[h][j], Cj, pw[h][j], emit);
+      }
     }
   }
   if (local) atomicAdd(&s_count[0], local);
@@ -738,8 +784,51 @@ __device__ void score_keys(const MeltDesc& d, const Topo& T, const DbArgs& a, co
   __syncthreads();
 }
 
+// Inputs of move mv in topology T by lanes 0-7 of a wavefront (lane b: bead b), written as
+// input codes / 64 into x[0..NN_INP) (LDS).  Same arithmetic as move_features.
+__device__ void move_features_wave(const MeltDesc& d, const Topo& T, const double* __restrict__ x, int NP,
+                                   const Move& mv, __bf16* xrow) {
+  const int lane = threadIdx.x & 63;
+  const int N = d.N;
+  const int b = lane & 7;
+  int id;
+  if (b < 4) {
+    int p = mv.i - 1 + b;
+    p = p < 1 ? 1 : (p > N ? N : p);
+    id = T.at(mv.A, p);
+  } else {
+    int q = mv.var == 0 ? mv.j + 2 - (b - 4) : mv.j - 1 + (b - 4);
+    q = q < 1 ? 1 : (q > N ? N : q);
+    id = T.at(mv.B, q);
+  }
+  const int id1 = __shfl(id, 1, 64);
+  double dd[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) dd[c] = min_image(x[(size_t)c * NP + id] - x[(size_t)c * NP + id1], d.L);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const double d2 = __shfl(dd[c], 2, 64), d5 = __shfl(dd[c], 5, 64), d6 = __shfl(dd[c], 6, 64);
+    const double cen = ((d2 + d5) + d6) * 0.25;
+    if (lane < 8) xrow[3 * lane + c] = (__bf16)((float)q_input((float)(dd[c] - cen)) * 0.015625f);
+  }
+  if (lane == 0) xrow[24] = (__bf16)((float)q_input((float)d.kappa) * 0.015625f);
+  if (lane >= 25 && lane < NN_INP) xrow[lane] = (__bf16)0.0f;
+  __builtin_amdgcn_wave_barrier();
+}
+
+// one attempt evaluated by a wavefront against the current state
+struct LearnedEval {
+  Move mv;
+  uint64_t key;
+  double qf, dE, u, kept, wr;
+  int nrm, rev, phase;  // phase: 0 reject, 1 needs the full evaluation
+};
+
+constexpr int LS_WAVES = DB_BLOCK / 64;
+
 __global__ __launch_bounds__(DB_BLOCK) void k_db_sweep_learned(DbArgs a) {
   __shared__ uint64_t s_keys[LS_SORT];     // sorted candidate keys [0, n)
+  __shared__ uint32_t s_pair[DB_CAND_CAP]; // their chain pairs (A << 16) | B
   __shared__ double s_w[DB_CAND_CAP];      // their proposal weights sigmoid(f)
   __shared__ double s_cum[DB_CAND_CAP];    // running sums of s_w
   __shared__ uint64_t s_new[LS_NEW_CAP];   // candidates touching A or B after the move
@@ -747,18 +836,19 @@ __global__ __launch_bounds__(DB_BLOCK) void k_db_sweep_learned(DbArgs a) {
   __shared__ uint64_t s_ns[LS_NEW_CAP];    // the same, sorted
   __shared__ double s_wns[LS_NEW_CAP];
   __shared__ uint64_t s_rm[LS_NEW_CAP];    // current candidates touching A or B
-  __shared__ NetTile s_t;
+  __shared__ NetTile s_t;                  // network tile (its first rows double as per-wavefront rows)
+  __shared__ LearnedEval s_ev[LS_WAVES];
   __shared__ double s_dtmp[DB_BLOCK / 64];
   __shared__ double s_dout;
   __shared__ int s_tmp[DB_BLOCK / 64];
   __shared__ int s_cnt[4];
-  __shared__ int s_total, s_nrm;
+  __shared__ int s_total, s_nrm, s_accept;
   __shared__ uint32_t s_err;
-  __shared__ LearnedAttempt s_at;
 
   const int k = blockIdx.x;
   const MeltDesc& d = a.md[k];
   const int M = d.M, N = d.N;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   kgdb_db_stats* st = (kgdb_db_stats*)a.stats + k;
   if (threadIdx.x == 0) {
     st->attempts = st->no_candidate = st->accepted = st->reverse_impossible = st->sum_ncand = 0;
@@ -787,6 +877,7 @@ __global__ __launch_bounds__(DB_BLOCK) void k_db_sweep_learned(DbArgs a) {
       }
       __syncthreads();
     }
+  for (int t = threadIdx.x; t < n; t += blockDim.x) s_pair[t] = key_pair(s_keys[t], M, N);
   const double mix = a.mix;
   {
     const Topo T{a.chain, a.loc, d.off, N, {0, 0, 0, 0, -1}};
@@ -794,16 +885,21 @@ __global__ __launch_bounds__(DB_BLOCK) void k_db_sweep_learned(DbArgs a) {
   }
   double Z = block_cumsum_f64(s_w, s_cum, n, s_dtmp, &s_dout);
 
+  // per-wavefront rows of the single-row network pass, inside the tile's second buffer
+  __bf16* xrow = &s_t.a1[0][0] + (size_t)wv * (NN_SA0 + NN_SA);
+  __bf16* hrow = xrow + NN_SA0;
+
   const int64_t K = a.nattempt[k];
   const uint64_t sweep = a.sweep_ctr[k];
-  for (int64_t att = 0; att < K; ++att) {
-    __syncthreads();  // every wavefront is done with the previous attempt's shared record
+  int64_t att = 0;
+  while (att < K) {
     if (n == 0) {
       if (threadIdx.x == 0) { st->attempts += K - att; st->no_candidate += K - att; }
       break;
     }
-    if (threadIdx.x == 0) {
-      const U64x4 r = rng_draw(d, (uint64_t)att, sweep, ST_DB);
+    // ---- evaluate attempts att .. att + LS_WAVES - 1, wavefront wv taking att + wv
+    if (att + wv < K) {
+      const U64x4 r = rng_draw(d, (uint64_t)(att + wv), sweep, ST_DB);
       int idx;
       if (u01(r.w[2]) < mix) {
         idx = (int)rng_choice(r.w[0], (uint64_t)n);
@@ -813,143 +909,188 @@ __global__ __launch_bounds__(DB_BLOCK) void k_db_sweep_learned(DbArgs a) {
         while (lo < hi) { const int mid = (lo + hi) >> 1; if (s_cum[mid] > t) hi = mid; else lo = mid + 1; }
         idx = lo < n ? lo : n - 1;
       }
-      LearnedAttempt& at = s_at;
-      at.key = s_keys[idx];
-      at.mv = decode_key(at.key, M, N);
-      const Move mv = at.mv;
-      at.qf = (1.0 - mix) * s_w[idx] / Z + mix / (double)n;
-      at.dE = move_dE(d, a.chain, a.loc, a.x, a.NP, mv);
-      at.u = u01(r.w[1]);
-      const Topo To{a.chain, a.loc, d.off, N, {mv.A, mv.i, mv.B, mv.j, -1}};
-      at.rev = dist2(a.x, a.NP, d.L, To.at(mv.A, mv.i), To.at(mv.A, mv.i + 1)) <= d.rmax2 &&
-               dist2(a.x, a.NP, d.L, To.at(mv.B, mv.j), To.at(mv.B, mv.j + 1)) <= d.rmax2;
-      at.acc = 0;
-      st->attempts++;
-      st->sum_ncand += n;
-      if (!at.rev) st->reverse_impossible++;
-      s_cnt[0] = s_cnt[1] = 0;
-      s_nrm = 0;
-    }
-    __syncthreads();
-    if (!s_at.rev) continue;
-    const Move mv = s_at.mv;
-    const Topo Tn{a.chain, a.loc, d.off, N, mv};
-    count_touching(d, Tn, a, mv.A, mv.B, s_cnt, s_new, &s_err, LS_NEW_CAP);
-    double kept = 0.0;
-    for (int t = threadIdx.x; t < n; t += blockDim.x) {
-      const uint64_t key = s_keys[t];
-      if (touches(key, M, N, mv.A, mv.B)) {
-        const int q = atomicAdd(&s_nrm, 1);
-        if (q < LS_NEW_CAP) s_rm[q] = key;
-      } else {
-        kept += s_w[t];
+      const uint64_t key = s_keys[idx];
+      const Move mv = decode_key(key, M, N);
+      const double qf = (1.0 - mix) * s_w[idx] / Z + mix / (double)n;
+      // lanes 0-3: junction energies old A, old B, new A, new B (and the old bond lengths)
+      double e = 0.0, r2 = 0.0;
+      if (lane < 4) {
+        const Topo T{a.chain, a.loc, d.off, N, lane < 2 ? Move{mv.A, mv.i, mv.B, mv.j, -1} : mv};
+        const int X = (lane & 1) ? mv.B : mv.A, kb = (lane & 1) ? mv.j : mv.i;
+        r2 = dist2(a.x, a.NP, d.L, T.at(X, kb), T.at(X, kb + 1));
+        e = junction_energy(d, T, a.x, a.NP, X, kb);
+      }
+      // candidates touching A or B now, and the weight of the others
+      const uint32_t A = (uint32_t)mv.A, B = (uint32_t)mv.B;
+      int rmc = 0;
+      double kept = 0.0;
+      for (int t = lane; t < n; t += 64) {
+        const uint32_t pr = s_pair[t];
+        const uint32_t pa = pr >> 16, pb = pr & 0xffffu;
+        if (pa == A || pa == B || pb == A || pb == B) ++rmc;
+        else kept += s_w[t];
+      }
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) { rmc += __shfl_xor(rmc, o, 64); kept += __shfl_xor(kept, o, 64); }
+      const double e1 = __shfl(e, 1, 64), e2 = __shfl(e, 2, 64), e3 = __shfl(e, 3, 64);
+      const double r2a = __shfl(r2, 0, 64), r2b = __shfl(r2, 1, 64);
+      const double dE = (e2 + e3) - (__shfl(e, 0, 64) + e1);
+      const int rev = r2a <= d.rmax2 && r2b <= d.rmax2;
+      // the reverse move's weight at x' (the same key), from a single-row pass
+      double wr = 0.0;
+      if (rev) {
+        const Topo Tn{a.chain, a.loc, d.off, N, mv};
+        move_features_wave(d, Tn, a.x, a.NP, mv, xrow);
+        wr = nn_weight(nn_forward_row(a.net, xrow, hrow));
+      }
+      if (lane == 0) {
+        const double u = u01(r.w[1]);
+        // |C(x')| >= |C| - |C_AB(x)| + 1 and Z(x') >= (weights not touching A, B) + w_r since
+        // the reverse move is a candidate of x': an upper bound on the Hastings ratio.  A draw
+        // above it (with a margin far wider than any rounding of the sums) rejects exactly as
+        // the full ratio would.
+        int phase = 1;
+        if (!rev) phase = 0;
+        else {
+          const double qr_max = (1.0 - mix) * wr / (kept + wr) + mix / (double)(n - rmc + 1);
+          if (!(u < exp(-dE / d.T) * qr_max / qf * (1.0 + 1e-9))) phase = 0;
+        }
+        LearnedEval& ev = s_ev[wv];
+        ev.mv = mv; ev.key = key; ev.qf = qf; ev.dE = dE; ev.u = u; ev.kept = kept; ev.wr = wr;
+        ev.nrm = rmc; ev.rev = rev; ev.phase = phase;
       }
     }
-    const double kept_sum = block_sum_f64(kept, s_dtmp, &s_dout);  // synchronises
-    const int nn = s_cnt[0], nrm = s_nrm;
-    if (nn > LS_NEW_CAP || nrm > LS_NEW_CAP) {
-      if (threadIdx.x == 0) s_err |= ERR_CAND_OVERFLOW;
+    __syncthreads();
+    // ---- walk the evaluated attempts in order
+    const int nev = (int)min((int64_t)LS_WAVES, K - att);
+    int used = nev;
+    for (int w = 0; w < nev; ++w) {
+      if (threadIdx.x == 0) {
+        st->attempts++;
+        st->sum_ncand += n;
+        if (!s_ev[w].rev) st->reverse_impossible++;
+      }
+      if (s_ev[w].phase == 0) continue;
+      const Move mv = s_ev[w].mv;
+      const Topo Tn{a.chain, a.loc, d.off, N, mv};
+      if (threadIdx.x == 0) { s_cnt[0] = s_cnt[1] = 0; s_nrm = 0; }
       __syncthreads();
-      continue;
-    }
-    score_keys(d, Tn, a, s_new, nn, s_wn, s_t);
-    if (threadIdx.x == 0) {
-      LearnedAttempt& at = s_at;
-      double Z2 = kept_sum, wr = -1.0;
-      for (int q = 0; q < nn; ++q) {
-        Z2 += s_wn[q];
-        if (s_new[q] == at.key) wr = s_wn[q];
+      count_touching(d, Tn, a, mv.A, mv.B, s_cnt, s_new, &s_err, LS_NEW_CAP);
+      __syncthreads();
+      const int nn = s_cnt[0], nrm = s_ev[w].nrm;
+      if (nn > LS_NEW_CAP || nrm > LS_NEW_CAP) {
+        if (threadIdx.x == 0) s_err |= ERR_CAND_OVERFLOW;
+        __syncthreads();
+        continue;
       }
-      const int n2 = n - nrm + nn;
-      if (wr < 0.0) {
-        s_err |= ERR_DB_MISMATCH;  // the reverse move must be a candidate of x'
-      } else {
-        const double qr = (1.0 - mix) * wr / Z2 + mix / (double)n2;
-        const double ratio = exp(-at.dE / d.T) * qr / at.qf;
-        at.acc = (at.u < ratio) && n2 <= DB_CAND_CAP;
-        if ((at.u < ratio) && !at.acc) s_err |= ERR_CAND_OVERFLOW;
-        if (at.acc) { st->accepted++; st->sum_dE_accepted += at.dE; }
+      score_keys(d, Tn, a, s_new, nn, s_wn, s_t);  // synchronises
+      if (threadIdx.x == 0) {
+        const LearnedEval& ev = s_ev[w];
+        double Z2 = ev.kept, wr = -1.0;
+        for (int q = 0; q < nn; ++q) {
+          Z2 += s_wn[q];
+          if (s_new[q] == ev.key) wr = s_wn[q];
+        }
+        const int n2 = n - nrm + nn;
+        int acc = 0;
+        if (wr < 0.0) {
+          s_err |= ERR_DB_MISMATCH;  // the reverse move must be a candidate of x'
+        } else {
+          const double qr = (1.0 - mix) * wr / Z2 + mix / (double)n2;
+          const double ratio = exp(-ev.dE / d.T) * qr / ev.qf;
+          acc = (ev.u < ratio) && n2 <= DB_CAND_CAP;
+          if ((ev.u < ratio) && !acc) s_err |= ERR_CAND_OVERFLOW;
+          if (acc) { st->accepted++; st->sum_dE_accepted += ev.dE; }
+        }
+        s_accept = acc;
       }
-    }
-    __syncthreads();
-    if (!s_at.acc) continue;
+      __syncthreads();
+      if (!s_accept) continue;
 
-    // ---- commit: new rows of chains A and B
-    {
-      int vals[DB_MAXPT];
+      // ---- commit: new rows of chains A and B
+      {
+        int vals[DB_MAXPT];
 #pragma unroll
-      for (int q = 0; q < DB_MAXPT; ++q) {
-        const int idx = threadIdx.x + q * DB_BLOCK;
-        if (idx < 2 * N) vals[q] = Tn.at(idx < N ? mv.A : mv.B, (idx < N ? idx : idx - N) + 1);
-      }
-      __syncthreads();
+        for (int q = 0; q < DB_MAXPT; ++q) {
+          const int idx = threadIdx.x + q * DB_BLOCK;
+          if (idx < 2 * N) vals[q] = Tn.at(idx < N ? mv.A : mv.B, (idx < N ? idx : idx - N) + 1);
+        }
+        __syncthreads();
 #pragma unroll
-      for (int q = 0; q < DB_MAXPT; ++q) {
-        const int idx = threadIdx.x + q * DB_BLOCK;
-        if (idx < 2 * N) {
-          const int X = idx < N ? mv.A : mv.B;
-          const int p0 = idx < N ? idx : idx - N;
-          a.chain[d.off + X * N + p0] = vals[q];
-          a.loc[vals[q]] = X * N + p0;
+        for (int q = 0; q < DB_MAXPT; ++q) {
+          const int idx = threadIdx.x + q * DB_BLOCK;
+          if (idx < 2 * N) {
+            const int X = idx < N ? mv.A : mv.B;
+            const int p0 = idx < N ? idx : idx - N;
+            a.chain[d.off + X * N + p0] = vals[q];
+            a.loc[vals[q]] = X * N + p0;
+          }
         }
       }
+      // ---- list update: keys touching A or B leave (order kept), the new ones merge in with
+      // their weights and chain pairs
+      {
+        for (int t = threadIdx.x; t < nn; t += blockDim.x) {
+          const uint64_t key = s_new[t];
+          int r = 0;
+          for (int q = 0; q < nn; ++q) r += s_new[q] < key ? 1 : 0;
+          s_ns[r] = key;
+          s_wns[r] = s_wn[t];
+        }
+        const int per = (n + DB_BLOCK - 1) / DB_BLOCK;  // <= 3
+        const int t0 = threadIdx.x * per;
+        uint64_t kk[3];
+        double kw[3];
+        uint32_t kp[3];
+        int keep = 0, flags = 0;
+        for (int q = 0; q < per && q < 3; ++q) {
+          if (t0 + q < n) {
+            kk[q] = s_keys[t0 + q];
+            kw[q] = s_w[t0 + q];
+            kp[q] = s_pair[t0 + q];
+            if (!pair_touches(kp[q], mv.A, mv.B)) { ++keep; flags |= 1 << q; }
+            else s_rm[atomicAdd(&s_nrm, 1)] = kk[q];  // nrm <= LS_NEW_CAP was checked
+          }
+        }
+        const int pos0 = block_exclusive_scan(keep, s_tmp, &s_total);  // synchronises
+        const int nk = s_total;
+        // destination of new key t: t + #(kept keys below it)
+        int dnew = -1;
+        uint64_t knew = 0;
+        double wnew = 0.0;
+        if ((int)threadIdx.x < nn) {
+          knew = s_ns[threadIdx.x];
+          wnew = s_wns[threadIdx.x];
+          int lo = 0, hi = n;
+          while (lo < hi) { const int mid = (lo + hi) >> 1; if (s_keys[mid] < knew) lo = mid + 1; else hi = mid; }
+          int below_rm = 0;
+          for (int q = 0; q < nrm; ++q) below_rm += s_rm[q] < knew ? 1 : 0;
+          dnew = (int)threadIdx.x + lo - below_rm;
+        }
+        // destination of a kept key: its kept rank + #(new keys below it)
+        int dk[3];
+        int pos = pos0;
+        for (int q = 0; q < per && q < 3; ++q) {
+          dk[q] = -1;
+          if (flags & (1 << q)) {
+            int lo = 0, hi = nn;
+            while (lo < hi) { const int mid = (lo + hi) >> 1; if (s_ns[mid] < kk[q]) lo = mid + 1; else hi = mid; }
+            dk[q] = pos++ + lo;
+          }
+        }
+        __syncthreads();
+        for (int q = 0; q < per && q < 3; ++q)
+          if (dk[q] >= 0) { s_keys[dk[q]] = kk[q]; s_w[dk[q]] = kw[q]; s_pair[dk[q]] = kp[q]; }
+        if (dnew >= 0 && dnew < nk + nn) { s_keys[dnew] = knew; s_w[dnew] = wnew; s_pair[dnew] = key_pair(knew, M, N); }
+        n = nk + nn;
+        __syncthreads();
+      }
+      Z = block_cumsum_f64(s_w, s_cum, n, s_dtmp, &s_dout);
+      used = w + 1;  // attempts after an accepted one are evaluated again
+      break;
     }
-    // ---- list update: keys touching A or B leave (order kept), the new ones merge in with
-    // their weights
-    {
-      for (int t = threadIdx.x; t < nn; t += blockDim.x) {
-        const uint64_t key = s_new[t];
-        int r = 0;
-        for (int q = 0; q < nn; ++q) r += s_new[q] < key ? 1 : 0;
-        s_ns[r] = key;
-        s_wns[r] = s_wn[t];
-      }
-      const int per = (n + DB_BLOCK - 1) / DB_BLOCK;  // <= 3
-      const int t0 = threadIdx.x * per;
-      uint64_t kk[3];
-      double kw[3];
-      int keep = 0, flags = 0;
-      for (int q = 0; q < per && q < 3; ++q) {
-        if (t0 + q < n) {
-          kk[q] = s_keys[t0 + q];
-          kw[q] = s_w[t0 + q];
-          if (!touches(kk[q], M, N, mv.A, mv.B)) { ++keep; flags |= 1 << q; }
-        }
-      }
-      const int pos0 = block_exclusive_scan(keep, s_tmp, &s_total);  // synchronises
-      const int nk = s_total;
-      // destination of new key t: t + #(kept keys below it)
-      int dnew = -1;
-      uint64_t knew = 0;
-      double wnew = 0.0;
-      if ((int)threadIdx.x < nn) {
-        knew = s_ns[threadIdx.x];
-        wnew = s_wns[threadIdx.x];
-        int lo = 0, hi = n;
-        while (lo < hi) { const int mid = (lo + hi) >> 1; if (s_keys[mid] < knew) lo = mid + 1; else hi = mid; }
-        int below_rm = 0;
-        for (int q = 0; q < nrm; ++q) below_rm += s_rm[q] < knew ? 1 : 0;
-        dnew = (int)threadIdx.x + lo - below_rm;
-      }
-      // destination of a kept key: its kept rank + #(new keys below it)
-      int dk[3];
-      int pos = pos0;
-      for (int q = 0; q < per && q < 3; ++q) {
-        dk[q] = -1;
-        if (flags & (1 << q)) {
-          int lo = 0, hi = nn;
-          while (lo < hi) { const int mid = (lo + hi) >> 1; if (s_ns[mid] < kk[q]) lo = mid + 1; else hi = mid; }
-          dk[q] = pos++ + lo;
-        }
-      }
-      __syncthreads();
-      for (int q = 0; q < per && q < 3; ++q)
-        if (dk[q] >= 0) { s_keys[dk[q]] = kk[q]; s_w[dk[q]] = kw[q]; }
-      if (dnew >= 0 && dnew < nk + nn) { s_keys[dnew] = knew; s_w[dnew] = wnew; }
-      n = nk + nn;
-      __syncthreads();
-    }
-    Z = block_cumsum_f64(s_w, s_cum, n, s_dtmp, &s_dout);
+    att += used;
+    __syncthreads();  // s_ev and the per-wavefront rows are rewritten by the next round
   }
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -975,8 +1116,8 @@ __global__ __launch_bounds__(256) void k_db_features(DbArgs a, int k, const uint
 void launch_db_build(const DbArgs& a, const BlockMap& pm, const BlockMap& cm13, hipStream_t s) {
   hipLaunchKernelGGL(k_db_bin, dim3(pm.nblk), dim3(256), 0, s, a.md, pm.melt, pm.base, a.NP, a.x, a.cnt13,
                      a.bucket13, a.err);
-  hipLaunchKernelGGL(k_db_nbr, dim3(pm.nblk), dim3(256), 0, s, a.md, pm.melt, pm.base, a.NP, a.x, a.cnt13,
-                     a.bucket13, a.nnb, a.nbr, a.err);
+  hipLaunchKernelGGL(k_db_nbr, dim3(pm.nblk * NBR_LANES), dim3(256), 0, s, a.md, pm.melt, pm.base, a.NP, a.x,
+                     a.cnt13, a.bucket13, a.nnb, a.nbr, a.err);
   hipLaunchKernelGGL(k_db_cands, dim3(pm.nblk), dim3(256), 0, s, a.md, pm.melt, pm.base, a);
 }
 

@@ -163,4 +163,48 @@ __device__ void nn_forward_tile(NetTile& t, const NetQ* __restrict__ net, const 
   __syncthreads();
 }
 
+// One layer of a single input row by one wavefront (see nn_forward_row): the row is row 0 of
+// a 16-row A block whose other rows are zero.
+template <int K>
+__device__ __forceinline__ void nn_row_layer(const __bf16* in, __bf16* h, const __bf16* __restrict__ W,
+                                             const float* __restrict__ bias) {
+  const int lane = threadIdx.x & 63;
+  const int r16 = lane & 15, kq = lane >> 4;
+  const bf16x8 zero = {(__bf16)0.0f, (__bf16)0.0f, (__bf16)0.0f, (__bf16)0.0f,
+                       (__bf16)0.0f, (__bf16)0.0f, (__bf16)0.0f, (__bf16)0.0f};
+  bf16x8 av[K / 32];
+#pragma unroll
+  for (int q = 0; q < K / 32; ++q) av[q] = r16 == 0 ? *(const bf16x8*)(in + q * 32 + kq * 8) : zero;
+  // every A fragment is in registers before the first result overwrites h (in may be h)
+#pragma unroll 2
+  for (int ct = 0; ct < 8; ++ct) {
+    f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+    const __bf16* bp = W + (ct * 16 + r16) * K + kq * 8;
+#pragma unroll
+    for (int q = 0; q < K / 32; ++q)
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[q], *(const bf16x8*)(bp + q * 32), acc, 0, 0, 0);
+    if (lane < 16) {  // row 0 sits in lanes 0-15
+      const int col = ct * 16 + lane;
+      h[col] = (__bf16)((float)q_hidden(acc[0] + bias[col]) * 0.0625f);
+    }
+  }
+  __builtin_amdgcn_wave_barrier();
+}
+
+// One input row through the network by a single wavefront, on the same instruction as the
+// tile, so the logit is the one the tile gives (every sum is exact).  x: the row's input
+// codes / 64 ([NN_INP] bf16, LDS); h: one row of NN_H bf16 scratch (LDS).  Returns the
+// logit in every lane.
+__device__ __forceinline__ float nn_forward_row(const NetQ* __restrict__ net, const __bf16* x, __bf16* h) {
+  const int lane = threadIdx.x & 63;
+  nn_row_layer<NN_INP>(x, h, &net->W1[0][0], net->b1);
+  nn_row_layer<NN_H>(h, h, &net->W2[0][0], net->b2);
+  nn_row_layer<NN_H>(h, h, &net->W3[0][0], net->b3);
+  // output unit: every partial sum is exact, so the lane split does not change the result
+  float s = (float)h[lane] * net->w4[lane] + (float)h[lane + 64] * net->w4[lane + 64];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+  return s + net->b4;
+}
+
 }  // namespace kgdb

@@ -297,8 +297,9 @@ __device__ __forceinline__ double fsqrt(double x) { return sqrt(x); }
 // ---------------------------------------------------------------------------------------
 // the step: forces from the lists + chain, Langevin velocity Verlet
 // ---------------------------------------------------------------------------------------
+// at least three wavefronts per SIMD: a 200k-monomer melt gives about three per SIMD
 template <typename R, int MODE>
-__global__ __launch_bounds__(256) void k_nl_step(NlArgs a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_nl_step(NlArgs a) {
   const int lb = xcd_remap(blockIdx.x, gridDim.x);
   const int k = __builtin_amdgcn_readfirstlane(a.pblk_melt[lb]);
   const MeltDesc& d = a.md[k];
@@ -307,30 +308,65 @@ __global__ __launch_bounds__(256) void k_nl_step(NlArgs a) {
   const int NP = a.NP;
   const int g = d.off + li;
   const double L = d.L, invL = 1.0 / d.L;
-  const double xg = a.x[g], yg = a.x[NP + g], zg = a.x[2 * NP + g];
   const Rel4<R>* __restrict__ rel = (const Rel4<R>*)a.rel_cur;
   const bool forces_on = !(d.test_flags & TF_NOFORCE);
+  const bool pairs_on = forces_on && !(d.test_flags & TF_PHANTOM);
   uint32_t errbits = 0;
+
+  // independent loads first: the wavefront's memory requests overlap one another and the
+  // noise arithmetic below
+  const int lcp = a.loc[g];
+  const int n = pairs_on ? a.nlen[g] : 0;
+  const Rel4<R> ri = rel[g];
+  const double xg = a.x[g], yg = a.x[NP + g], zg = a.x[2 * NP + g];
+  double vx = a.v[g], vy = a.v[NP + g], vz = a.v[2 * NP + g];
+  const uint64_t mono = (MODE & F_CLOSE) ? (uint64_t)a.mono[g] : 0ull;
+  const uint4* __restrict__ words = (const uint4*)a.nlist;
+  // first chunk of the list: CH entries (CH / 4 16-byte words) and their CH gathers; FP64
+  // coordinates take twice the registers, so their chunks are half as long
+  constexpr int CH = sizeof(R) == 4 ? 8 : 4, CW = CH / 4;
+  uint4 wd[CW];
+#pragma unroll
+  for (int q = 0; q < CW; ++q) wd[q] = words[nl_word(g, q)];
 
   // chain neighbours p-2, p-1, p+1, p+2 (FP64 minimum image, then the force precision)
   const int N = d.N;
-  const int lcp = a.loc[g];
   const int c = (int)((double)lcp * d.invN), p0 = lcp - c * N;
   const int cch = (p0 < 0) ? c - 1 : (p0 >= N ? c + 1 : c);  // guard the reciprocal's rounding
   const int p = lcp - cch * N;
-  W3<R> P[5];
   bool has[5];
+  int pj[5];
 #pragma unroll
-  for (int q = 0; q < 5; ++q) {
+  for (int q = 0; q < 5; ++q) {  // unconditional loads of clamped positions: no branches between them
     const int pp = p + q - 2;
     has[q] = (q == 2) || (forces_on && pp >= 0 && pp < N);
-    P[q].x = P[q].y = P[q].z = (R)0;
-    if (q != 2 && has[q]) {
-      const int j = a.chain[d.off + cch * N + pp];
-      double dx = a.x[j] - xg, dy = a.x[NP + j] - yg, dz = a.x[2 * NP + j] - zg;
-      dx -= L * rint(dx * invL); dy -= L * rint(dy * invL); dz -= L * rint(dz * invL);
-      P[q].x = (R)dx; P[q].y = (R)dy; P[q].z = (R)dz;
-    }
+    const int j = a.chain[d.off + cch * N + min(max(pp, 0), N - 1)];
+    pj[q] = (q != 2 && has[q]) ? j : g;
+  }
+  double bx[5], by[5], bz[5];
+#pragma unroll
+  for (int q = 0; q < 5; ++q) { bx[q] = a.x[pj[q]]; by[q] = a.x[NP + pj[q]]; bz[q] = a.x[2 * NP + pj[q]]; }
+
+  uint32_t e[CH];
+  Rel4<R> rj[CH];
+#pragma unroll
+  for (int q = 0; q < CW; ++q) { e[4 * q] = wd[q].x; e[4 * q + 1] = wd[q].y; e[4 * q + 2] = wd[q].z; e[4 * q + 3] = wd[q].w; }
+#pragma unroll
+  for (int u = 0; u < CH; ++u) rj[u] = rel[(u < n) ? (e[u] >> 5) : g];
+
+  // Langevin noise of this closing kick (depends only on the monomer id and the step),
+  // computed while the gathers above are in flight: the empty asm pins the arithmetic here
+  // and the scheduling barriers keep the loads issued before it
+  double z0 = 0.0, z1 = 0.0, z2 = 0.0;
+  if (MODE & F_CLOSE) {
+    const uint64_t idx = a.step_base[k] + (uint64_t)a.s_off;
+    __builtin_amdgcn_sched_barrier(0);
+    const U64x4 w = rng_draw(d, mono, idx, ST_LANGEVIN);
+    double z3;
+    gauss2(w.w[0], w.w[1], z0, z1);
+    gauss2(w.w[2], w.w[3], z2, z3);
+    asm volatile("" : "+v"(z0), "+v"(z1), "+v"(z2));  // materialise the noise here
+    __builtin_amdgcn_sched_barrier(0);
   }
 
   W3<R> F = {(R)0, (R)0, (R)0};
@@ -346,27 +382,51 @@ __global__ __launch_bounds__(256) void k_nl_step(NlArgs a) {
       F.x -= coef * dx; F.y -= coef * dy; F.z -= coef * dz;
     }
   };
+  // list entries: the same force without a branch (lanes of a wavefront rarely agree on the
+  // cutoff test); r2 is clamped away from 0 for entries outside it, whose force is masked
+  auto pair_add_nb = [&](R dx, R dy, R dz) {
+    const R r2 = dx * dx + dy * dy + dz * dz;
+    const bool in = r2 < rc2;
+    const R s2 = frcp(in ? r2 : rc2);
+    const R s6 = s2 * s2 * s2;
+    const R sn = pow_half<R>(s2, nh, n_half);
+    const R coef = in ? (pa * sn - pb * s6) * s2 : (R)0;
+    F.x -= coef * dx; F.y -= coef * dy; F.z -= coef * dz;
+  };
+  const R hl = (R)d.hl;
+  auto entry = [&](uint32_t en, const Rel4<R>& r) {
+    const int code = (int)(en & 31u);
+    const int ox = code % 3 - 1, oy = (code / 3) % 3 - 1, oz = code / 9 - 1;
+    pair_add_nb(r.x + (R)ox * hl - ri.x, r.y + (R)oy * hl - ri.y, r.z + (R)oz * hl - ri.z);
+  };
 
-  if (forces_on && !(d.test_flags & TF_PHANTOM)) {
-    const Rel4<R> ri = rel[g];
-    const R hl = (R)d.hl;
-    const int n = a.nlen[g];
-    auto entry = [&](uint32_t e, const Rel4<R>& rj) {
-      const int code = (int)(e & 31u);
-      const int ox = code % 3 - 1, oy = (code / 3) % 3 - 1, oz = code / 9 - 1;
-      pair_add(rj.x + (R)ox * hl - ri.x, rj.y + (R)oy * hl - ri.y, rj.z + (R)oz * hl - ri.z);
-    };
-    const uint4* __restrict__ words = (const uint4*)a.nlist;
-    // one 16-byte word (four entries) per round; the four gathers are independent
-    for (int t = 0; t < n; t += 4) {
-      const uint4 q = words[nl_word(g, t >> 2)];
-      const uint32_t e[4] = {q.x, q.y, q.z, q.w};
-      Rel4<R> rj[4];
+  // list: chunk t holds entries t .. t + CH - 1; the next chunk's words are requested before
+  // the current chunk is evaluated
+  for (int t = 0; t < n; t += CH) {
+    const bool more = t + CH < n;
 #pragma unroll
-      for (int u = 0; u < 4; ++u) rj[u] = rel[(t + u < n) ? (e[u] >> 5) : g];
+    for (int q = 0; q < CW; ++q) wd[q] = more ? words[nl_word(g, (t >> 2) + CW + q)] : make_uint4(0, 0, 0, 0);
 #pragma unroll
-      for (int u = 0; u < 4; ++u)
-        if (t + u < n) entry(e[u], rj[u]);
+    for (int u = 0; u < CH; ++u)
+      if (t + u < n) entry(e[u], rj[u]);
+    if (more) {
+#pragma unroll
+      for (int q = 0; q < CW; ++q) {
+        e[4 * q] = wd[q].x; e[4 * q + 1] = wd[q].y; e[4 * q + 2] = wd[q].z; e[4 * q + 3] = wd[q].w;
+      }
+#pragma unroll
+      for (int u = 0; u < CH; ++u) rj[u] = rel[(t + CH + u < n) ? (e[u] >> 5) : g];
+    }
+  }
+
+  W3<R> P[5];
+#pragma unroll
+  for (int q = 0; q < 5; ++q) {
+    P[q].x = P[q].y = P[q].z = (R)0;
+    if (q != 2 && has[q]) {
+      double dx = bx[q] - xg, dy = by[q] - yg, dz = bz[q] - zg;
+      dx -= L * rint(dx * invL); dy -= L * rint(dy * invL); dz -= L * rint(dz * invL);
+      P[q].x = (R)dx; P[q].y = (R)dy; P[q].z = (R)dz;
     }
   }
 
@@ -409,15 +469,9 @@ __global__ __launch_bounds__(256) void k_nl_step(NlArgs a) {
 
   const double Fx = (double)F.x, Fy = (double)F.y, Fz = (double)F.z;
   if (!(isfinite(Fx) && isfinite(Fy) && isfinite(Fz))) errbits |= ERR_NONFINITE;
-  double vx = a.v[g], vy = a.v[NP + g], vz = a.v[2 * NP + g];
   double fx, fy, fz;
   const double dt = d.dt;
   if (MODE & F_CLOSE) {
-    const uint64_t idx = a.step_base[k] + (uint64_t)a.s_off;
-    const U64x4 w = rng_draw(d, (uint64_t)a.mono[g], idx, ST_LANGEVIN);
-    double z0, z1, z2, z3;
-    gauss2(w.w[0], w.w[1], z0, z1);
-    gauss2(w.w[2], w.w[3], z2, z3);
     const double amp = d.lang_amp;  // sqrt(2 gamma T / dt)
     fx = -d.gamma * vx + amp * z0;
     fy = -d.gamma * vy + amp * z1;
