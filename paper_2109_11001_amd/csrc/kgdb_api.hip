@@ -381,6 +381,10 @@ static NlArgs nl_args(kgdb_batch* b) {
   a.rblk_melt = b->rm[b->nl_ki].melt;
   a.rblk_base = b->rm[b->nl_ki].base;
   a.stage_cap = b->stage_cap[b->nl_ki];
+  a.nh_uniform = b->D[0].n_half_int;
+  for (const MeltDesc& d : b->D)
+    if (d.n_half_int != a.nh_uniform) a.nh_uniform = 0;
+  if (a.nh_uniform != 1 && a.nh_uniform != 6) a.nh_uniform = 0;
   a.NP = b->NP;
   a.x = b->d_x[b->cur];
   a.xn = b->d_x[1 - b->cur];

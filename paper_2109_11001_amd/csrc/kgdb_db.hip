@@ -348,6 +348,87 @@ __device__ void count_touching(const MeltDesc& d, const Topo& T, const DbArgs& a
   if (local) atomicAdd(&s_count[0], local);
 }
 
+// Candidates of x' = mv(x) that involve chain A or B, derived from the current sorted list
+// (keys, chain pairs) instead of a rescan of both chains' close pairs:
+// (1) a candidate of x with exactly one of A, B whose bond on that chain is not the move's
+//     junction bond maps one to one onto a candidate of x' with the same four beads.  Bonds
+//     carried over with a tail keep their index; in the reconnection of antiparallel bonds a
+//     carried-over piece is reversed, bond z becomes bond N - z and the variant flips (P at
+//     (z, l) with z = l has the new bonds of AP at (N - z, l), and conversely);
+// (2) candidates on the two new junction bonds with other chains: every such candidate has
+//     one new bond from the junction bond's first bead, so that bead's close pairs find them;
+// (3) candidates between A' and B' (pairs of bonds that may have shared a chain before) by
+//     direct enumeration of the P and AP bond pairs.
+// Block-cooperative; adds the count to s_count[0] and, when s_new != nullptr, emits the keys
+// into s_new (capacity new_cap, fill count in s_count[1]).
+__device__ void touching_after(const MeltDesc& d, const DbArgs& a, const Move& mv, const uint64_t* keys,
+                               const uint32_t* pairs, int n, int* s_count, uint64_t* s_new, uint32_t* s_err,
+                               int new_cap) {
+  const int M = d.M, N = d.N, A = mv.A, B = mv.B;
+  const Topo Tn{a.chain, a.loc, d.off, N, mv};
+  int local = 0;
+  auto emit = [&](uint64_t key) {
+    ++local;
+    if (s_new) {
+      const int s = atomicAdd(&s_count[1], 1);
+      if (s < new_cap) s_new[s] = key;
+      else atomicOr(s_err, ERR_CAND_OVERFLOW);
+    }
+  };
+  auto key_of = [&](int X, int xb, int Y, int yb, int v) {
+    return X < Y ? make_key(M, N, X, xb, Y, yb, v) : make_key(M, N, Y, yb, X, xb, v);
+  };
+  // (1) relabelled candidates
+  for (int t = threadIdx.x; t < n; t += blockDim.x) {
+    const uint32_t pr = pairs[t];
+    const int pa = (int)(pr >> 16), pb = (int)(pr & 0xffffu);
+    const bool ta = pa == A || pa == B, tb = pb == A || pb == B;
+    if (ta == tb) continue;  // neither chain, or both (those are enumerated in (3))
+    const Move c = decode_key(keys[t], M, N);
+    const int Z = ta ? c.A : c.B, zb = ta ? c.i : c.j, C = ta ? c.B : c.A, cb = ta ? c.j : c.i;
+    int Zn, k, flip = 0;
+    if (mv.var == 0) {  // tails beyond bond i exchanged
+      if (zb == mv.i) continue;
+      Zn = (zb < mv.i) ? Z : (Z == A ? B : A);
+      k = zb;
+    } else if (Z == A) {  // A' = a_1..a_i b_j..b_1, B' = a_N..a_{i+1} b_{j+1}..b_N
+      if (zb == mv.i) continue;
+      if (zb < mv.i) { Zn = A; k = zb; } else { Zn = B; k = N - zb; flip = 1; }
+    } else {
+      if (zb == mv.j) continue;
+      if (zb > mv.j) { Zn = B; k = zb; } else { Zn = A; k = N - zb; flip = 1; }
+    }
+    emit(key_of(Zn, k, C, cb, c.var ^ flip));
+  }
+  // (2) the junction bonds: bond i of A', bond j of B'
+  if (threadIdx.x < 2) {
+    const int X = threadIdx.x == 0 ? A : B;
+    const int kb = threadIdx.x == 0 ? mv.i : mv.j;
+    const int u = Tn.at(X, kb), u1 = Tn.at(X, kb + 1);
+    const int nn = a.nnb[u];
+    for (int q = 0; q < nn; ++q) {
+      const int w = a.nbr[(size_t)u * DB_NBR_CAP + q];
+      int Cw, pw;
+      Tn.where(w, Cw, pw);
+      if (Cw == A || Cw == B) continue;
+      if (pw == kb + 1 && dist2(a.x, a.NP, d.L, Tn.at(Cw, kb), u1) <= d.rmax2) emit(key_of(X, kb, Cw, kb, 0));
+      if (pw == N - kb && dist2(a.x, a.NP, d.L, u1, Tn.at(Cw, pw + 1)) <= d.rmax2) emit(key_of(X, kb, Cw, pw, 1));
+    }
+  }
+  // (3) A'-B' pairs: bond k of A' with bond k (P) or N - k (AP) of B'
+  for (int k = threadIdx.x + 1; k <= N - 1; k += blockDim.x) {
+    const int ak = Tn.at(A, k), ak1 = Tn.at(A, k + 1);
+    const int bk = Tn.at(B, k), bk1 = Tn.at(B, k + 1);
+    if (dist2(a.x, a.NP, d.L, ak, bk1) <= d.rmax2 && dist2(a.x, a.NP, d.L, bk, ak1) <= d.rmax2)
+      emit(make_key(M, N, A, k, B, k, 0));
+    const int l = N - k;
+    const int bl = Tn.at(B, l), bl1 = Tn.at(B, l + 1);
+    if (dist2(a.x, a.NP, d.L, ak, bl) <= d.rmax2 && dist2(a.x, a.NP, d.L, ak1, bl1) <= d.rmax2)
+      emit(make_key(M, N, A, k, B, l, 1));
+  }
+  if (local) atomicAdd(&s_count[0], local);
+}
+
 // exclusive prefix sum over the block (blockDim = DB_BLOCK); s_tmp holds DB_BLOCK/64 ints
 __device__ int block_exclusive_scan(int v, int* s_tmp, int* s_total) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -395,6 +476,30 @@ __device__ __forceinline__ int wave_lower_bound(const uint64_t* s_keys, int n, u
   return b0 + __popcll(__ballot(lane < S - 1 && pf < b1 && s_keys[pf] < v));
 }
 
+// Delta E and reverse-move validity of keys[0, n) in the current topology, four threads per
+// key (junction energies of old A, old B, new A, new B; the old bond lengths).  Same
+// arithmetic and order as an attempt's own evaluation.  Block-cooperative.
+__device__ void key_attributes(const MeltDesc& d, const DbArgs& a, const uint64_t* keys, int n, double* dE,
+                               uint8_t* rev) {
+  const int lane = threadIdx.x & 63;
+  for (int t = threadIdx.x; t < 4 * n; t += blockDim.x) {  // 4 n is a multiple of 4: groups stay whole
+    const int c = t >> 2, role = t & 3;
+    const Move mv = decode_key(keys[c], d.M, d.N);
+    const Topo T{a.chain, a.loc, d.off, d.N, role < 2 ? Move{mv.A, mv.i, mv.B, mv.j, -1} : mv};
+    const int X = (role & 1) ? mv.B : mv.A, kb = (role & 1) ? mv.j : mv.i;
+    const double r2 = dist2(a.x, a.NP, d.L, T.at(X, kb), T.at(X, kb + 1));
+    const double e = junction_energy(d, T, a.x, a.NP, X, kb);
+    const int g0 = lane & ~3;
+    const double e0 = __shfl(e, g0, 64), e1 = __shfl(e, g0 + 1, 64), e2 = __shfl(e, g0 + 2, 64),
+                 e3 = __shfl(e, g0 + 3, 64);
+    const double r2a = __shfl(r2, g0, 64), r2b = __shfl(r2, g0 + 1, 64);
+    if (role == 0) {
+      dE[c] = (e2 + e3) - (e0 + e1);
+      rev[c] = (r2a <= d.rmax2 && r2b <= d.rmax2) ? 1 : 0;
+    }
+  }
+}
+
 // one attempt evaluated against the current state (list, chains, positions)
 struct AttemptEval {
   Move mv;
@@ -419,6 +524,8 @@ __global__ __launch_bounds__(DB_BLOCK) void k_db_sweep(DbArgs a) {
   __shared__ uint32_t s_pair[2 * DB_CAND_CAP];  // chain pairs of s_keys, same layout
   __shared__ uint64_t s_new[DB_NEW_CAP];
   __shared__ int s_cc[DB_MAX_CHAINS];           // keys touching each chain
+  __shared__ double s_dE[DB_CAND_CAP];          // Delta E of each listed move
+  __shared__ uint8_t s_rev[DB_CAND_CAP];        // its reverse move is allowed
   __shared__ AttemptEval s_ev[DB_WAVES];
   __shared__ int s_tmp[DB_BLOCK / 64];
   __shared__ int s_cnt[4];
@@ -471,6 +578,7 @@ __global__ __launch_bounds__(DB_BLOCK) void k_db_sweep(DbArgs a) {
     atomicAdd(&s_cc[pr >> 16], 1);
     atomicAdd(&s_cc[pr & 0xffffu], 1);
   }
+  key_attributes(d, a, s_keys, n, s_dE, s_rev);
   __syncthreads();
 
   const int64_t K = a.nattempt[k];
@@ -486,28 +594,18 @@ __global__ __launch_bounds__(DB_BLOCK) void k_db_sweep(DbArgs a) {
     if (threadIdx.x == 0) s_cnt[0] = s_cnt[1] = s_cnt[2] = s_cnt[3] = 0;
     if (att + wv < K) {
       const U64x4 r = rng_draw(d, (uint64_t)(att + wv), sweep, ST_DB);
-      const Move mv = decode_key(s_keys[rng_choice(r.w[0], (uint64_t)n)], M, N);
-      // lanes 0-3: junction energies old A, old B, new A, new B (the old bond lengths also
-      // give the reverse-move test)
-      double e = 0.0, r2 = 0.0;
-      if (lane < 4) {
-        const Topo T{a.chain, a.loc, d.off, N, lane < 2 ? Move{mv.A, mv.i, mv.B, mv.j, -1} : mv};
-        const int X = (lane & 1) ? mv.B : mv.A, kb = (lane & 1) ? mv.j : mv.i;
-        r2 = dist2(a.x, a.NP, d.L, T.at(X, kb), T.at(X, kb + 1));
-        e = junction_energy(d, T, a.x, a.NP, X, kb);
-      }
+      const int idx = (int)rng_choice(r.w[0], (uint64_t)n);
+      const Move mv = decode_key(s_keys[idx], M, N);
       // keys with chain pair (A, B) lie among the keys whose first chain is A
       const int lo = wave_lower_bound(s_keys, n, (uint64_t)mv.A * kstride, lane);
       const int hi = wave_lower_bound(s_keys, n, (uint64_t)(mv.A + 1) * kstride, lane);
       const uint32_t want = ((uint32_t)mv.A << 16) | (uint32_t)mv.B;
       int both = 0;
       for (int t = lo; t < hi; t += 64) both += __popcll(__ballot(t + lane < hi && s_pair[t + lane] == want));
-      const double e1 = __shfl(e, 1, 64), e2 = __shfl(e, 2, 64), e3 = __shfl(e, 3, 64);
-      const double r2b = __shfl(r2, 1, 64);
       if (lane == 0) {
-        const double dE = (e2 + e3) - (e + e1);
+        const double dE = s_dE[idx];
         const double u = u01(r.w[1]);
-        const int rev = r2 <= d.rmax2 && r2b <= d.rmax2;
+        const int rev = s_rev[idx];
         const int old_ab = s_cc[mv.A] + s_cc[mv.B] - both;
         // Decide what can be decided without |C(x')|.  The reverse move is a candidate of x'
         // whenever it is allowed, so |C(x')| >= |C| - |C_AB(x)| + 1 bounds the Hastings ratio
@@ -554,11 +652,16 @@ __global__ __launch_bounds__(DB_BLOCK) void k_db_sweep(DbArgs a) {
         }
       }
       if (phase == 0) continue;
-      {
+      touching_after(d, a, mv, s_keys, s_pair, n, s_cnt, s_new, &s_err, DB_NEW_CAP);
+      if (a.debug) {  // the derived set has the size of a full rescan of both chains
         Topo Tn{a.chain, a.loc, d.off, N, mv};
-        count_touching(d, Tn, a, mv.A, mv.B, s_cnt, s_new, &s_err);
+        count_touching(d, Tn, a, mv.A, mv.B, s_cnt + 2, nullptr, &s_err);
       }
       __syncthreads();
+      if (a.debug && threadIdx.x == 0) {
+        if (s_cnt[2] != s_cnt[0]) s_err |= ERR_DB_MISMATCH;
+        s_cnt[2] = 0;
+      }
       if (threadIdx.x == 0) {
         const int new_ab = s_cnt[0];
         const int n_new = n - old_ab + new_ab;
@@ -659,6 +762,9 @@ __global__ __launch_bounds__(DB_BLOCK) void k_db_sweep(DbArgs a) {
           s_pair[t + lo] = s_nsp[t];
         }
         n = nk + nn;
+        __syncthreads();
+        // attributes of every listed move in the new topology (the chain rows written above)
+        key_attributes(d, a, s_keys, n, s_dE, s_rev);
         __syncthreads();
       }
       used = w + 1;  // attempts after an accepted one are evaluated again
@@ -975,7 +1081,7 @@ __global__ __launch_bounds__(DB_BLOCK) void k_db_sweep_learned(DbArgs a) {
       const Topo Tn{a.chain, a.loc, d.off, N, mv};
       if (threadIdx.x == 0) { s_cnt[0] = s_cnt[1] = 0; s_nrm = 0; }
       __syncthreads();
-      count_touching(d, Tn, a, mv.A, mv.B, s_cnt, s_new, &s_err, LS_NEW_CAP);
+      touching_after(d, a, mv, s_keys, s_pair, n, s_cnt, s_new, &s_err, LS_NEW_CAP);
       __syncthreads();
       const int nn = s_cnt[0], nrm = s_ev[w].nrm;
       if (nn > LS_NEW_CAP || nrm > LS_NEW_CAP) {

@@ -102,6 +102,7 @@ struct NlArgs {
   uint32_t* err;
   uint32_t s_off;
   int stage_cap;   // list build: staged monomers per workgroup held in LDS
+  int nh_uniform;  // n / 2 when every melt has n = 2 or n = 12 (the step kernel is built for those), else 0
 };
 size_t nl_stage_bytes(int prec, int cap);  // dynamic LDS of the list build
 void launch_nl_rebuild(int prec, const NlArgs& a, int pblk, int cblk, int rblk, hipStream_t s);

@@ -297,13 +297,27 @@ __device__ __forceinline__ double fsqrt(double x) { return sqrt(x); }
 // ---------------------------------------------------------------------------------------
 // the step: forces from the lists + chain, Langevin velocity Verlet
 // ---------------------------------------------------------------------------------------
-// at least three wavefronts per SIMD: a 200k-monomer melt gives about three per SIMD
-template <typename R, int MODE>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_nl_step(NlArgs a) {
+// NH > 0: the exponent n = 2 NH is fixed at compile time (the soft and the standard
+// potential); NH = 0 reads it from the melt.  At most 128 registers, so that four
+// wavefronts fit per SIMD: a 200k-monomer melt needs a little over three per SIMD, and a
+// second round of workgroups would double the kernel's duration.
+template <typename R, int MODE, int NH>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_nl_step(NlArgs a) {
   const int lb = xcd_remap(blockIdx.x, gridDim.x);
   const int k = __builtin_amdgcn_readfirstlane(a.pblk_melt[lb]);
   const MeltDesc& d = a.md[k];
   const int li = a.pblk_base[lb] + (int)threadIdx.x;
+  // displacement of each of the 27 neighbouring reference cells (list entries carry its code)
+  __shared__ Rel4<R> s_cell[27];
+  if (threadIdx.x < 27) {
+    const int code = (int)threadIdx.x;
+    const R hl = (R)d.hl;
+    s_cell[code].x = (R)(code % 3 - 1) * hl;
+    s_cell[code].y = (R)((code / 3) % 3 - 1) * hl;
+    s_cell[code].z = (R)(code / 9 - 1) * hl;
+    s_cell[code].w = (R)0;
+  }
+  __syncthreads();
   if (li >= d.Nm) return;
   const int NP = a.NP;
   const int g = d.off + li;
@@ -322,12 +336,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
   double vx = a.v[g], vy = a.v[NP + g], vz = a.v[2 * NP + g];
   const uint64_t mono = (MODE & F_CLOSE) ? (uint64_t)a.mono[g] : 0ull;
   const uint4* __restrict__ words = (const uint4*)a.nlist;
-  // first chunk of the list: CH entries (CH / 4 16-byte words) and their CH gathers; FP64
-  // coordinates take twice the registers, so their chunks are half as long
+  // first chunk of the list: CH0 entries (CH0 / 4 16-byte words) and their gathers, all
+  // requested before the noise arithmetic; later chunks have CH entries.  FP64 coordinates
+  // take twice the registers, so their chunks are half as long.
+  constexpr int CH0 = sizeof(R) == 4 ? 8 : 4, CW0 = CH0 / 4;
   constexpr int CH = sizeof(R) == 4 ? 8 : 4, CW = CH / 4;
-  uint4 wd[CW];
+  uint4 wd0[CW0];
 #pragma unroll
-  for (int q = 0; q < CW; ++q) wd[q] = words[nl_word(g, q)];
+  for (int q = 0; q < CW0; ++q) wd0[q] = words[nl_word(g, q)];
 
   // chain neighbours p-2, p-1, p+1, p+2 (FP64 minimum image, then the force precision)
   const int N = d.N;
@@ -347,12 +363,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
 #pragma unroll
   for (int q = 0; q < 5; ++q) { bx[q] = a.x[pj[q]]; by[q] = a.x[NP + pj[q]]; bz[q] = a.x[2 * NP + pj[q]]; }
 
-  uint32_t e[CH];
-  Rel4<R> rj[CH];
+  uint32_t e0[CH0];
+  Rel4<R> rj0[CH0];
 #pragma unroll
-  for (int q = 0; q < CW; ++q) { e[4 * q] = wd[q].x; e[4 * q + 1] = wd[q].y; e[4 * q + 2] = wd[q].z; e[4 * q + 3] = wd[q].w; }
+  for (int q = 0; q < CW0; ++q) {
+    e0[4 * q] = wd0[q].x; e0[4 * q + 1] = wd0[q].y; e0[4 * q + 2] = wd0[q].z; e0[4 * q + 3] = wd0[q].w;
+  }
 #pragma unroll
-  for (int u = 0; u < CH; ++u) rj[u] = rel[(u < n) ? (e[u] >> 5) : g];
+  for (int u = 0; u < CH0; ++u) rj0[u] = rel[(u < n) ? (e0[u] >> 5) : g];
 
   // Langevin noise of this closing kick (depends only on the monomer id and the step),
   // computed while the gathers above are in flight: the empty asm pins the arithmetic here
@@ -371,7 +389,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
 
   W3<R> F = {(R)0, (R)0, (R)0};
   const R pa = (R)d.pa, pb = (R)d.pb, rc2 = (R)d.rc2, n_half = (R)(0.5 * d.n_exp);
-  const int nh = d.n_half_int;
+  const int nh = NH > 0 ? NH : d.n_half_int;
   auto pair_add = [&](R dx, R dy, R dz) {  // (dx, dy, dz) = x_j - x_i
     const R r2 = dx * dx + dy * dy + dz * dz;
     if (r2 < rc2) {
@@ -393,30 +411,35 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     const R coef = in ? (pa * sn - pb * s6) * s2 : (R)0;
     F.x -= coef * dx; F.y -= coef * dy; F.z -= coef * dz;
   };
-  const R hl = (R)d.hl;
   auto entry = [&](uint32_t en, const Rel4<R>& r) {
-    const int code = (int)(en & 31u);
-    const int ox = code % 3 - 1, oy = (code / 3) % 3 - 1, oz = code / 9 - 1;
-    pair_add_nb(r.x + (R)ox * hl - ri.x, r.y + (R)oy * hl - ri.y, r.z + (R)oz * hl - ri.z);
+    const Rel4<R> o = s_cell[en & 31u];
+    pair_add_nb(r.x + o.x - ri.x, r.y + o.y - ri.y, r.z + o.z - ri.z);
   };
 
-  // list: chunk t holds entries t .. t + CH - 1; the next chunk's words are requested before
-  // the current chunk is evaluated
-  for (int t = 0; t < n; t += CH) {
-    const bool more = t + CH < n;
+  // list: the first chunk, then chunks t .. t + CH - 1 whose words are requested before the
+  // previous chunk is evaluated
+  uint4 wd[CW];
+  uint32_t e[CH];
+  Rel4<R> rj[CH];
+  bool more = CH0 < n;
 #pragma unroll
-    for (int q = 0; q < CW; ++q) wd[q] = more ? words[nl_word(g, (t >> 2) + CW + q)] : make_uint4(0, 0, 0, 0);
+  for (int q = 0; q < CW; ++q) wd[q] = more ? words[nl_word(g, CW0 + q)] : make_uint4(0, 0, 0, 0);
+#pragma unroll
+  for (int u = 0; u < CH0; ++u)
+    if (u < n) entry(e0[u], rj0[u]);
+  for (int t = CH0; t < n; t += CH) {
+#pragma unroll
+    for (int q = 0; q < CW; ++q) {
+      e[4 * q] = wd[q].x; e[4 * q + 1] = wd[q].y; e[4 * q + 2] = wd[q].z; e[4 * q + 3] = wd[q].w;
+    }
+#pragma unroll
+    for (int u = 0; u < CH; ++u) rj[u] = rel[(t + u < n) ? (e[u] >> 5) : g];
+    more = t + CH < n;
+#pragma unroll
+    for (int q = 0; q < CW; ++q) wd[q] = more ? words[nl_word(g, ((t + CH) >> 2) + q)] : make_uint4(0, 0, 0, 0);
 #pragma unroll
     for (int u = 0; u < CH; ++u)
       if (t + u < n) entry(e[u], rj[u]);
-    if (more) {
-#pragma unroll
-      for (int q = 0; q < CW; ++q) {
-        e[4 * q] = wd[q].x; e[4 * q + 1] = wd[q].y; e[4 * q + 2] = wd[q].z; e[4 * q + 3] = wd[q].w;
-      }
-#pragma unroll
-      for (int u = 0; u < CH; ++u) rj[u] = rel[(t + CH + u < n) ? (e[u] >> 5) : g];
-    }
   }
 
   W3<R> P[5];
@@ -529,13 +552,21 @@ void launch_nl_rebuild(int prec, const NlArgs& a, int pblk, int cblk, int rblk, 
   }
 }
 
-void launch_nl_step(int prec, int mode, const NlArgs& a, int pblk, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+template <typename R, int M>
+static void launch_step_nh(const NlArgs& a, int pblk, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
   // with events: hipExtLaunchKernelGGL stamps them at the dispatch's own start and end
-#define KG_CASE(R, M)                                                                               \
-  case M:                                                                                           \
-    if (ev0) hipExtLaunchKernelGGL((k_nl_step<R, M>), dim3(pblk), dim3(256), 0, s, ev0, ev1, 0, a); \
-    else hipLaunchKernelGGL((k_nl_step<R, M>), dim3(pblk), dim3(256), 0, s, a);                    \
-    break;
+  auto go = [&](auto kern) {
+    if (ev0) hipExtLaunchKernelGGL(kern, dim3(pblk), dim3(256), 0, s, ev0, ev1, 0, a);
+    else hipLaunchKernelGGL(kern, dim3(pblk), dim3(256), 0, s, a);
+  };
+  if (a.nh_uniform == 1) go(k_nl_step<R, M, 1>);
+  else if (a.nh_uniform == 6) go(k_nl_step<R, M, 6>);
+  else go(k_nl_step<R, M, 0>);
+}
+
+void launch_nl_step(int prec, int mode, const NlArgs& a, int pblk, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+#define KG_CASE(R, M) \
+  case M: launch_step_nh<R, M>(a, pblk, s, ev0, ev1); break;
   if (prec) {
     switch (mode) {
       KG_CASE(float, F_OPEN)
