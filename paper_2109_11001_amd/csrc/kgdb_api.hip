@@ -73,6 +73,8 @@ struct kgdb_batch {
   int* d_cntl[2] = {nullptr, nullptr};
   int cl = 0;                      // list-grid occupancy buffer the next rebuild fills
   int* d_bucketl = nullptr;
+  int* d_bucketl_raw = nullptr;    // list-grid buckets as filled by the binning
+  int* d_celll = nullptr;          // list-grid cell of each monomer
   void* d_rel[2] = {nullptr, nullptr};
   float4* d_relb = nullptr;
   int* d_refc = nullptr;
@@ -394,6 +396,10 @@ static NlArgs nl_args(kgdb_batch* b) {
   a.cnt = b->d_cntl[b->cl];
   a.cnt_clear = b->d_cntl[1 - b->cl];
   a.bucket = b->d_bucketl;
+  a.bucket_raw = b->d_bucketl_raw;
+  a.cell_l = b->d_celll;
+  a.ncl_total = 0;
+  for (const MeltDesc& d : b->D) a.ncl_total += d.ncl * d.ncl * d.ncl;
   a.rel_cur = b->d_rel[b->cur];
   a.rel_next = b->d_rel[1 - b->cur];
   a.relb = b->d_relb;
@@ -525,8 +531,9 @@ static int run_steps(kgdb_batch* b, int64_t n, bool graph) {
     HIPCHK(hipStreamSynchronize(b->s));
     uint32_t all = 0;
     for (int k = 0; k < b->nm; ++k) all |= b->h_err[k];
-    if (!(all & ERR_NLIST_STALE) || b->nl_k == 1) break;
-    // a monomer outran the skin: redo the pass with more frequent rebuilds
+    // a monomer outran the skin, or a list-grid bucket or a list overflowed (dense spots of
+    // an unrelaxed start): redo the pass with more frequent rebuilds on a finer grid
+    if (!(all & (ERR_NLIST_STALE | ERR_CELL_OVERFLOW | ERR_NLIST_OVERFLOW)) || b->nl_k == 1) break;
     HIPCHK(hipMemsetAsync(b->d_err, 0, sizeof(uint32_t) * b->nm, b->s));
     b->cur = cur0;
     CHK(save_state(b, true));
@@ -775,6 +782,8 @@ static int init_impl(const kgdb_params* params, int32_t count, void* stream, kgd
   step(dalloc(b, &b->d_cntl[0], (size_t)b->NCL));
   step(dalloc(b, &b->d_cntl[1], (size_t)b->NCL));
   step(dalloc(b, &b->d_bucketl, (size_t)b->NCL * NL_CELL_CAP));
+  step(dalloc(b, &b->d_bucketl_raw, (size_t)b->NCL * NL_CELL_CAP));
+  step(dalloc(b, &b->d_celll, (size_t)NP));
   for (int q = 0; q < 2 && !rc; ++q) {
     void* r = nullptr;
     if (hipMalloc(&r, np * rel_bytes(b->prec)) != hipSuccess) rc = fail(KGDB_E_ALLOC, "hipMalloc rel");

@@ -88,7 +88,10 @@ struct NlArgs {
   double* fl;
   int* cnt;        // list-grid occupancy being filled
   int* cnt_clear;  // the other occupancy buffer (cleared by the rebuild)
-  int* bucket;
+  int* bucket;      // list-grid buckets, ordered by slot
+  int* bucket_raw;  // the same as filled by the binning (any order)
+  int* cell_l;      // list-grid cell of each monomer
+  int ncl_total;    // list-grid cells of the batch (current rebuild interval)
   void* rel_cur;   // reference-cell-relative positions (force precision, 4 per monomer)
   void* rel_next;
   float4* relb;    // relative positions at the last rebuild

@@ -30,74 +30,76 @@ __device__ __forceinline__ int pack_cell(int cx, int cy, int cz) { return cx | (
 // ---------------------------------------------------------------------------------------
 // rebuild 1: binning into the list grid
 // ---------------------------------------------------------------------------------------
+// Monomers are stored in cell order from the previous rebuild, so a wavefront's lanes mostly
+// fall into a few cells: each run of lanes with the same cell takes its bucket slots with one
+// atomic (the order within a bucket is fixed by the finalisation).
 __global__ __launch_bounds__(256) void k_nl_bin(NlArgs a) {
+  const int lb = xcd_remap(blockIdx.x, gridDim.x);
+  const int k = __builtin_amdgcn_readfirstlane(a.pblk_melt[lb]);
+  const MeltDesc& d = a.md[k];
+  const int li = a.pblk_base[lb] + (int)threadIdx.x;
+  const bool valid = li < d.Nm;
+  const int g = d.off + (valid ? li : 0);
+  const int nc = d.ncl;
+  int c = -1;
+  if (valid) {
+    const int cx = cell_coord(a.x[g], d.cinvl, nc), cy = cell_coord(a.x[a.NP + g], d.cinvl, nc),
+              cz = cell_coord(a.x[2 * a.NP + g], d.cinvl, nc);
+    c = d.celll_off + (cz * nc + cy) * nc + cx;
+    a.cell_l[g] = c;
+  }
+  const int lane = threadIdx.x & 63;
+  const int prev = __shfl_up(c, 1, 64);
+  const uint64_t heads = __ballot(lane == 0 || prev != c);
+  const uint64_t upto = (2ull << lane) - 1ull;  // lanes 0 .. lane (all 64 for lane 63)
+  const int hl = 63 - __builtin_clzll(heads & upto);
+  int base = 0;
+  if (hl == lane && c >= 0) {
+    const uint64_t after = heads & ~upto;
+    const int next = after ? __builtin_ctzll(after) : 64;
+    base = atomicAdd(&a.cnt[c], next - lane);
+  }
+  base = __shfl(base, hl, 64);
+  if (c < 0) return;
+  const int s = base + (lane - hl);
+  if (s < NL_CELL_CAP) a.bucket_raw[c * NL_CELL_CAP + s] = g;
+  else atomicOr(&a.err[k], ERR_CELL_OVERFLOW);
+}
+
+// ---------------------------------------------------------------------------------------
+// rebuild 2: one thread per monomer: its rank by slot within its cell's bucket (buckets end up
+// ordered by slot), its reference cell and reference-relative position; the other occupancy
+// buffer is cleared over the current grid
+// ---------------------------------------------------------------------------------------
+template <typename R>
+__global__ __launch_bounds__(256) void k_nl_finalize(NlArgs a) {
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < a.ncl_total; t += gridDim.x * blockDim.x)
+    a.cnt_clear[t] = 0;
   const int lb = xcd_remap(blockIdx.x, gridDim.x);
   const int k = __builtin_amdgcn_readfirstlane(a.pblk_melt[lb]);
   const MeltDesc& d = a.md[k];
   const int li = a.pblk_base[lb] + (int)threadIdx.x;
   if (li >= d.Nm) return;
   const int g = d.off + li;
-  const int nc = d.ncl;
-  const int cx = cell_coord(a.x[g], d.cinvl, nc), cy = cell_coord(a.x[a.NP + g], d.cinvl, nc),
-            cz = cell_coord(a.x[2 * a.NP + g], d.cinvl, nc);
-  const int c = d.celll_off + (cz * nc + cy) * nc + cx;
-  const int s = atomicAdd(&a.cnt[c], 1);
-  if (s < NL_CELL_CAP) a.bucket[c * NL_CELL_CAP + s] = g;
-  else atomicOr(&a.err[k], ERR_CELL_OVERFLOW);
-}
-
-// ---------------------------------------------------------------------------------------
-// rebuild 2: per cell, order the bucket by slot and write each member's reference cell and
-// reference-relative position; clear the other occupancy buffer
-// ---------------------------------------------------------------------------------------
-// rank-by-counting sort of one bucket held in registers (CAPT = compile-time bound), then
-// each member's reference cell and reference-relative position
-template <typename R, int CAPT>
-__device__ __forceinline__ void nl_place(const NlArgs& a, Rel4<R>* rel, int base, int n, double ox, double oy,
-                                         double oz, int pc) {
-  int ids[CAPT];
-#pragma unroll
-  for (int j = 0; j < CAPT; ++j) ids[j] = (j < n) ? a.bucket[base + j] : 0x7fffffff;
-#pragma unroll
-  for (int j = 0; j < CAPT; ++j) {
-    if (j < n) {
-      int r = 0;
-#pragma unroll
-      for (int m = 0; m < CAPT; ++m) r += (ids[m] < ids[j]) ? 1 : 0;
-      const int id = ids[j];
-      a.bucket[base + r] = id;
-      Rel4<R> p;
-      p.x = (R)(a.x[id] - ox);
-      p.y = (R)(a.x[a.NP + id] - oy);
-      p.z = (R)(a.x[2 * a.NP + id] - oz);
-      p.w = (R)0;
-      rel[id] = p;
-      a.relb[id] = make_float4((float)p.x, (float)p.y, (float)p.z, 0.f);
-      a.refc[id] = pc;
-    }
-  }
-}
-
-template <typename R>
-__global__ __launch_bounds__(256) void k_nl_finalize(NlArgs a) {
-  const int lb = xcd_remap(blockIdx.x, gridDim.x);
-  const int k = __builtin_amdgcn_readfirstlane(a.cblk_melt[lb]);
-  const MeltDesc& d = a.md[k];
-  const int nc = d.ncl;
-  const int lc = a.cblk_base[lb] + (int)threadIdx.x;
-  if (lc >= nc * nc * nc) return;
-  const int c = d.celll_off + lc;
-  a.cnt_clear[c] = 0;
-  int n = a.cnt[c];
-  if (n > NL_CELL_CAP) n = NL_CELL_CAP;
-  if (n == 0) return;
+  const int c = a.cell_l[g];
+  const int n = min(a.cnt[c], NL_CELL_CAP);
   const int base = c * NL_CELL_CAP;
+  int r = 0;
+  for (int j0 = 0; j0 < n; j0 += 4) {
+    const int4 q = *(const int4*)(a.bucket_raw + base + j0);
+    r += (q.x < g) + (j0 + 1 < n && q.y < g) + (j0 + 2 < n && q.z < g) + (j0 + 3 < n && q.w < g);
+  }
+  if (r < NL_CELL_CAP) a.bucket[base + r] = g;
+  const int nc = d.ncl, lc = c - d.celll_off;
   const int cx = lc % nc, cy = (lc / nc) % nc, cz = lc / (nc * nc);
-  const double ox = cx * d.hl, oy = cy * d.hl, oz = cz * d.hl;
-  const int pc = pack_cell(cx, cy, cz);
-  Rel4<R>* rel = (Rel4<R>*)a.rel_cur;
-  if (n <= 8) nl_place<R, 8>(a, rel, base, n, ox, oy, oz, pc);
-  else nl_place<R, NL_CELL_CAP>(a, rel, base, n, ox, oy, oz, pc);
+  Rel4<R> p;
+  p.x = (R)(a.x[g] - cx * d.hl);
+  p.y = (R)(a.x[a.NP + g] - cy * d.hl);
+  p.z = (R)(a.x[2 * a.NP + g] - cz * d.hl);
+  p.w = (R)0;
+  ((Rel4<R>*)a.rel_cur)[g] = p;
+  a.relb[g] = make_float4((float)p.x, (float)p.y, (float)p.z, 0.f);
+  a.refc[g] = pack_cell(cx, cy, cz);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -544,10 +546,10 @@ size_t nl_stage_bytes(int prec, int cap) {
 void launch_nl_rebuild(int prec, const NlArgs& a, int pblk, int cblk, int rblk, hipStream_t s) {
   hipLaunchKernelGGL(k_nl_bin, dim3(pblk), dim3(256), 0, s, a);
   if (prec) {
-    hipLaunchKernelGGL(k_nl_finalize<float>, dim3(cblk), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_nl_finalize<float>, dim3(pblk), dim3(256), 0, s, a);
     hipLaunchKernelGGL(k_nl_build<float>, dim3(rblk), dim3(NLB_THREADS), nl_stage_bytes(1, a.stage_cap), s, a);
   } else {
-    hipLaunchKernelGGL(k_nl_finalize<double>, dim3(cblk), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_nl_finalize<double>, dim3(pblk), dim3(256), 0, s, a);
     hipLaunchKernelGGL(k_nl_build<double>, dim3(rblk), dim3(NLB_THREADS), nl_stage_bytes(0, a.stage_cap), s, a);
   }
 }
