@@ -84,6 +84,8 @@ struct kgdb_batch {
   uint64_t* d_save_step = nullptr;
   hipGraphExec_t ngexec[3][2][2] = {};  // [K][x parity][occupancy parity]
   int64_t nl_rollbacks = 0;
+  int nl_ki_target = 2;            // interval chosen by the caller or the autotuner
+  int nl_clean = 0;                // passes without a rollback since the interval was lowered
   bool rebuild_pending = false;    // profiling: a rebuild was timed for the next step
   uint64_t* d_step = nullptr;
   uint32_t* d_err = nullptr;
@@ -153,6 +155,7 @@ static int check_params(const kgdb_params& p) {
 // rebuild intervals the runtime chooses from (each divides the 100-step graph chunk with an
 // even number of rebuilds, so the occupancy buffers' parity returns after a chunk)
 static const int NL_KS[3] = {1, 2, 5};
+static const int NL_CLEAN_PASSES = 4;  // clean passes before a lowered rebuild interval is raised again
 
 static double nl_skin_for(const kgdb_params& p, int K) {
   // twice a 6.6-sigma ballistic drift over K steps at temperature T, unless given
@@ -209,6 +212,8 @@ static MeltDesc make_desc(const kgdb_params& p) {
   d.warm_dt0 = p.warmup_dt0; d.warm_cap = p.warmup_max_disp; d.warm_fcap = p.warmup_fcap;
   d.rmax2 = p.db_rmax * p.db_rmax;
   d.invN = 1.0 / d.N;
+  d.inv_mnb = 1.0 / ((double)d.M * (double)(d.N - 1));
+  d.inv_nb = 1.0 / (double)(d.N - 1);
   d.lang_amp = std::sqrt(2.0 * p.gamma * p.T / p.dt);
   set_list_geometry(d, p, p.nl_every > 0 ? p.nl_every : 5);
   d.seed = p.seed;
@@ -539,6 +544,7 @@ static int run_steps(kgdb_batch* b, int64_t n, bool graph) {
     CHK(save_state(b, true));
     CHK(set_nl_interval(b, b->nl_ki - 1));
     b->nl_rollbacks++;
+    b->nl_clean = -1;
   }
   if (b->nl_k == 1) {  // staleness cannot matter when every force evaluation follows a rebuild
     for (int k = 0; k < b->nm; ++k) b->h_err[k] &= ~ERR_NLIST_STALE;
@@ -549,6 +555,12 @@ static int run_steps(kgdb_batch* b, int64_t n, bool graph) {
   b->cells_valid = false;
   CHK(check_errors(b));
   if (b->reorder) CHK(reorder_storage(b));
+  // A rollback answers one fast monomer, usually a rare event: after NL_CLEAN_PASSES clean
+  // passes the next pass tries the next longer interval again, up to the chosen one.
+  if (b->nl_ki < b->nl_ki_target && ++b->nl_clean >= NL_CLEAN_PASSES) {
+    CHK(set_nl_interval(b, b->nl_ki + 1));
+    b->nl_clean = 0;
+  }
   return 0;
 }
 
@@ -739,7 +751,7 @@ static int init_impl(const kgdb_params* params, int32_t count, void* stream, kgd
       ki = 2;
       while (ki >= 0 && !usable[ki]) --ki;
     }
-    b->nl_ki = ki;  // -1: stepping on the r_c grid
+    b->nl_ki = b->nl_ki_target = ki;  // -1: stepping on the r_c grid
     if (ki >= 0) { b->nl_k = NL_KS[ki]; b->D = b->Dk[ki]; }
   }
   int rc = 0;
@@ -1321,6 +1333,8 @@ int kgdb_autotune(kgdb_batch* b, int32_t nl_every, int32_t reps, int32_t* chosen
     for (int i = 0; i < 3; ++i) if (NL_KS[i] == nl_every) q = i;
     if (q < 0 || !usable(q)) return fail(KGDB_E_PARAM, "nl_every must be a usable 1, 2 or 5");
     CHK(set_nl_interval(b, q));
+    b->nl_ki_target = q;
+    b->nl_clean = 0;
     if (chosen) *chosen = b->nl_k;
     return 0;
   }
@@ -1354,6 +1368,8 @@ int kgdb_autotune(kgdb_batch* b, int32_t nl_every, int32_t reps, int32_t* chosen
     if (!usable(q)) continue;
     rc = set_nl_interval(b, q);
     if (rc) break;
+    b->nl_ki_target = q;
+    b->nl_clean = 0;
     b->prof = true;
     b->prof_force_ms = b->prof_fin_ms = 0;
     b->prof_force_n = b->prof_fin_n = 0;
@@ -1375,6 +1391,8 @@ int kgdb_autotune(kgdb_batch* b, int32_t nl_every, int32_t reps, int32_t* chosen
   b->prof_force_ms = b->prof_fin_ms = 0;
   b->prof_force_n = b->prof_fin_n = 0;
   CHK(set_nl_interval(b, best_q));
+  b->nl_ki_target = best_q;
+  b->nl_clean = 0;
   if (chosen) *chosen = b->nl_k;
   return rc;
 }

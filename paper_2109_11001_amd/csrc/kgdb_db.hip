@@ -21,8 +21,10 @@
 
 namespace kgdb {
 
-constexpr int DB_BLOCK = 1024;
-constexpr int DB_MAXPT = 8;  // chain-table entries per thread in a commit: 2N <= 8192
+// 512 threads: eight wavefronts of at most 256 registers each, so the sweep loop runs without spills
+constexpr int DB_BLOCK = 512;
+constexpr int DB_KPT = (DB_CAND_CAP + DB_BLOCK - 1) / DB_BLOCK;  // listed keys per thread in a merge
+constexpr int DB_NPT = (DB_NEW_CAP + DB_BLOCK - 1) / DB_BLOCK;   // new keys per thread in a merge
 
 __device__ __forceinline__ double dist2(const double* __restrict__ x, int NP, double L, int u, int w) {
   const double dx = min_image(x[w] - x[u], L);
@@ -115,15 +117,28 @@ __device__ __forceinline__ uint64_t make_key(int M, int N, int A, int i, int B, 
 
 struct Move { int A, i, B, j, var; };
 
-__device__ __forceinline__ Move decode_key(uint64_t key, int M, int N) {
-  const uint64_t Nb = (uint64_t)(N - 1);
+// floor(q / m) and q mod m for q < 2^50: the FP64 product q (1/m) is within 1/4 of q / m, so
+// its truncation is off by at most one, which the remainder's sign and size correct
+__device__ __forceinline__ uint32_t udiv_recip(uint64_t q, uint32_t m, double inv, uint32_t& rem) {
+  uint64_t h = (uint64_t)((double)q * inv);
+  int64_t r = (int64_t)(q - h * (uint64_t)m);
+  if (r < 0) { --h; r += m; }
+  else if (r >= (int64_t)m) { ++h; r -= m; }
+  rem = (uint32_t)r;
+  return (uint32_t)h;
+}
+
+// key = 2 ((A (N-1) + i - 1) M (N-1) + B (N-1) + j - 1) + var: keys sort by (A, i, B, j, var)
+__device__ __forceinline__ Move decode_key(uint64_t key, const MeltDesc& d) {
+  const uint32_t Nb = (uint32_t)(d.N - 1);
   Move mv;
   mv.var = (int)(key & 1ull);
-  const uint64_t q = key >> 1;
-  const uint64_t mn = (uint64_t)M * Nb;
-  const uint64_t hi = q / mn, lo = q - hi * mn;
-  mv.A = (int)(hi / Nb); mv.i = (int)(hi % Nb) + 1;
-  mv.B = (int)(lo / Nb); mv.j = (int)(lo % Nb) + 1;
+  uint32_t lo, ri, rj;
+  const uint32_t hi = udiv_recip(key >> 1, (uint32_t)d.M * Nb, d.inv_mnb, lo);
+  mv.A = (int)udiv_recip(hi, Nb, d.inv_nb, ri);
+  mv.B = (int)udiv_recip(lo, Nb, d.inv_nb, rj);
+  mv.i = (int)ri + 1;
+  mv.j = (int)rj + 1;
   return mv;
 }
 
@@ -161,6 +176,24 @@ struct Topo {
     }
   }
 };
+
+// Apply move mv to the chain tables.  A move exchanges table entries in pairs: (A, p) with
+// (B, p) for P and (A, p) with (B, N + 1 - p) for AP, p = i + 1 .. N (the view of Topo::at).
+// Each thread swaps whole pairs, so no entry is read after another thread wrote it.
+// Block-cooperative; readers need a barrier afterwards.
+__device__ __forceinline__ void commit_move(int off, int N, int* __restrict__ chain, int* __restrict__ loc,
+                                            const Move& mv) {
+  for (int t = threadIdx.x; t < N - mv.i; t += blockDim.x) {
+    const int p = mv.i + 1 + t;
+    const int q = mv.var == 0 ? p : N + 1 - p;
+    const int la = mv.A * N + p - 1, lb = mv.B * N + q - 1;
+    const int va = chain[off + la], vb = chain[off + lb];
+    chain[off + la] = vb;
+    chain[off + lb] = va;
+    loc[vb] = la;
+    loc[va] = lb;
+  }
+}
 
 // Candidates whose "first" new bond is the close pair (u, w): (a_i, b_{i+1}) for P and
 // (a_i, b_j) for AP, a on the lower chain.  Calls emit(key) for each.
@@ -384,7 +417,7 @@ __device__ void touching_after(const MeltDesc& d, const DbArgs& a, const Move& m
     const int pa = (int)(pr >> 16), pb = (int)(pr & 0xffffu);
     const bool ta = pa == A || pa == B, tb = pb == A || pb == B;
     if (ta == tb) continue;  // neither chain, or both (those are enumerated in (3))
-    const Move c = decode_key(keys[t], M, N);
+    const Move c = decode_key(keys[t], d);
     const int Z = ta ? c.A : c.B, zb = ta ? c.i : c.j, C = ta ? c.B : c.A, cb = ta ? c.j : c.i;
     int Zn, k, flip = 0;
     if (mv.var == 0) {  // tails beyond bond i exchanged
@@ -400,13 +433,15 @@ __device__ void touching_after(const MeltDesc& d, const DbArgs& a, const Move& m
     }
     emit(key_of(Zn, k, C, cb, c.var ^ flip));
   }
-  // (2) the junction bonds: bond i of A', bond j of B'
-  if (threadIdx.x < 2) {
-    const int X = threadIdx.x == 0 ? A : B;
-    const int kb = threadIdx.x == 0 ? mv.i : mv.j;
+  // (2) the junction bonds: bond i of A' (wavefront 0), bond j of B' (wavefront 1), one close
+  // pair of the bond's first bead per lane
+  if (threadIdx.x < 128) {
+    const bool second = threadIdx.x >= 64;
+    const int X = second ? B : A;
+    const int kb = second ? mv.j : mv.i;
     const int u = Tn.at(X, kb), u1 = Tn.at(X, kb + 1);
     const int nn = a.nnb[u];
-    for (int q = 0; q < nn; ++q) {
+    for (int q = threadIdx.x & 63; q < nn; q += 64) {
       const int w = a.nbr[(size_t)u * DB_NBR_CAP + q];
       int Cw, pw;
       Tn.where(w, Cw, pw);
@@ -452,16 +487,16 @@ __device__ int block_exclusive_scan(int v, int* s_tmp, int* s_total) {
 }
 
 // the two chains of a key packed as (A << 16) | B
-__device__ __forceinline__ uint32_t key_pair(uint64_t key, int M, int N) {
-  const Move m = decode_key(key, M, N);
+__device__ __forceinline__ uint32_t key_pair(uint64_t key, const MeltDesc& d) {
+  const Move m = decode_key(key, d);
   return ((uint32_t)m.A << 16) | (uint32_t)m.B;
 }
 __device__ __forceinline__ bool pair_touches(uint32_t pr, int A, int B) {
   const int pa = (int)(pr >> 16), pb = (int)(pr & 0xffffu);
   return pa == A || pa == B || pb == A || pb == B;
 }
-__device__ __forceinline__ bool touches(uint64_t key, int M, int N, int A, int B) {
-  return pair_touches(key_pair(key, M, N), A, B);
+__device__ __forceinline__ bool touches(uint64_t key, const MeltDesc& d, int A, int B) {
+  return pair_touches(key_pair(key, d), A, B);
 }
 
 // number of keys < v in the sorted s_keys[0, n), n <= 64 * 64, by one wavefront: a coarse pass
@@ -484,7 +519,7 @@ __device__ void key_attributes(const MeltDesc& d, const DbArgs& a, const uint64_
   const int lane = threadIdx.x & 63;
   for (int t = threadIdx.x; t < 4 * n; t += blockDim.x) {  // 4 n is a multiple of 4: groups stay whole
     const int c = t >> 2, role = t & 3;
-    const Move mv = decode_key(keys[c], d.M, d.N);
+    const Move mv = decode_key(keys[c], d);
     const Topo T{a.chain, a.loc, d.off, d.N, role < 2 ? Move{mv.A, mv.i, mv.B, mv.j, -1} : mv};
     const int X = (role & 1) ? mv.B : mv.A, kb = (role & 1) ? mv.j : mv.i;
     const double r2 = dist2(a.x, a.NP, d.L, T.at(X, kb), T.at(X, kb + 1));
@@ -519,17 +554,22 @@ struct AttemptEval {
 // ---------------------------------------------------------------------------------------
 constexpr int DB_WAVES = DB_BLOCK / 64;
 
+template <bool DBG>
 __global__ __launch_bounds__(DB_BLOCK) void k_db_sweep(DbArgs a) {
   __shared__ uint64_t s_keys[2 * DB_CAND_CAP];  // [0, CAP): the sorted list; [CAP, 2CAP): scratch
-  __shared__ uint32_t s_pair[2 * DB_CAND_CAP];  // chain pairs of s_keys, same layout
+  __shared__ uint32_t s_pair[DB_CAND_CAP];      // chain pairs of s_keys
   __shared__ uint64_t s_new[DB_NEW_CAP];
   __shared__ int s_cc[DB_MAX_CHAINS];           // keys touching each chain
   __shared__ double s_dE[DB_CAND_CAP];          // Delta E of each listed move
   __shared__ uint8_t s_rev[DB_CAND_CAP];        // its reverse move is allowed
+  __shared__ double s_ndE[DB_NEW_CAP];          // the same for the keys a commit adds
+  __shared__ uint8_t s_nrev[DB_NEW_CAP];
   __shared__ AttemptEval s_ev[DB_WAVES];
+  __shared__ uint64_t s_rw[DB_BLOCK];           // draws of attempts c0 .. c0 + DB_BLOCK - 1: choice word,
+  __shared__ double s_ru[DB_BLOCK];             // and acceptance uniform
   __shared__ int s_tmp[DB_BLOCK / 64];
   __shared__ int s_cnt[4];
-  __shared__ int s_total;
+  __shared__ int s_total, s_nrm;
   __shared__ uint32_t s_err;
   __shared__ int s_accept;
   __shared__ int64_t s_logn, s_logat;  // training log: records written, record of this attempt
@@ -539,16 +579,20 @@ __global__ __launch_bounds__(DB_BLOCK) void k_db_sweep(DbArgs a) {
   const int M = d.M, N = d.N;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   kgdb_db_stats* st = (kgdb_db_stats*)a.stats + k;
+  // statistics, kept by thread 0 in LDS and stored at the end
+  __shared__ int64_t n_att, n_nocand, n_acc, n_norev, sum_nc;
+  __shared__ double sum_dE;
   if (threadIdx.x == 0) {
-    st->attempts = st->no_candidate = st->accepted = st->reverse_impossible = st->sum_ncand = 0;
-    st->sum_dE_accepted = 0.0;
-    st->ncand_end = 0;
     s_err = 0;
     s_logn = 0;
+    n_att = n_nocand = n_acc = n_norev = sum_nc = 0;
+    sum_dE = 0.0;
   }
   int n = a.ncand[k];
   if (n > DB_CAND_CAP || a.err[k] != 0) {  // a build overflow was latched: no attempts
     if (threadIdx.x == 0) {
+      st->attempts = st->no_candidate = st->accepted = st->reverse_impossible = st->sum_ncand = 0;
+      st->sum_dE_accepted = 0.0;
       st->ncand_end = n;
       if (a.log_n) a.log_n[k] = 0;
     }
@@ -573,7 +617,7 @@ __global__ __launch_bounds__(DB_BLOCK) void k_db_sweep(DbArgs a) {
       __syncthreads();
     }
   for (int t = threadIdx.x; t < n; t += blockDim.x) {
-    const uint32_t pr = key_pair(s_keys[t], M, N);
+    const uint32_t pr = key_pair(s_keys[t], d);
     s_pair[t] = pr;
     atomicAdd(&s_cc[pr >> 16], 1);
     atomicAdd(&s_cc[pr & 0xffffu], 1);
@@ -584,18 +628,31 @@ __global__ __launch_bounds__(DB_BLOCK) void k_db_sweep(DbArgs a) {
   const int64_t K = a.nattempt[k];
   const uint64_t sweep = a.sweep_ctr[k];
   const uint64_t kstride = (uint64_t)(N - 1) * (uint64_t)M * (uint64_t)(N - 1) * 2u;  // key span of one first chain
-  int64_t att = 0;
+  const double T = d.T;
+  const int literal = d.proposal == KGDB_PROPOSAL_LITERAL;
+  int64_t att = 0, c0 = -(int64_t)DB_BLOCK;
   while (att < K) {
+    // the draws depend on the attempt index only: one thread per attempt, a chunk at a time
+    if (att + DB_WAVES > c0 + DB_BLOCK) {
+      c0 = att;
+      const U64x4 r = rng_draw(d, (uint64_t)(c0 + threadIdx.x), sweep, ST_DB);
+      s_rw[threadIdx.x] = r.w[0];
+      s_ru[threadIdx.x] = u01(r.w[1]);
+      __syncthreads();
+    }
     if (n == 0) {
-      if (threadIdx.x == 0) { st->attempts += K - att; st->no_candidate += K - att; }
+      if (threadIdx.x == 0) {
+        n_att += K - att;
+        n_nocand += K - att;
+      }
       break;
     }
     // ---- evaluate attempts att .. att + DB_WAVES - 1, wavefront wv taking att + wv
     if (threadIdx.x == 0) s_cnt[0] = s_cnt[1] = s_cnt[2] = s_cnt[3] = 0;
     if (att + wv < K) {
-      const U64x4 r = rng_draw(d, (uint64_t)(att + wv), sweep, ST_DB);
-      const int idx = (int)rng_choice(r.w[0], (uint64_t)n);
-      const Move mv = decode_key(s_keys[idx], M, N);
+      const int ci = (int)(att - c0) + wv;
+      const int idx = (int)rng_choice(s_rw[ci], (uint64_t)n);
+      const Move mv = decode_key(s_keys[idx], d);
       // keys with chain pair (A, B) lie among the keys whose first chain is A
       const int lo = wave_lower_bound(s_keys, n, (uint64_t)mv.A * kstride, lane);
       const int hi = wave_lower_bound(s_keys, n, (uint64_t)(mv.A + 1) * kstride, lane);
@@ -604,16 +661,16 @@ __global__ __launch_bounds__(DB_BLOCK) void k_db_sweep(DbArgs a) {
       for (int t = lo; t < hi; t += 64) both += __popcll(__ballot(t + lane < hi && s_pair[t + lane] == want));
       if (lane == 0) {
         const double dE = s_dE[idx];
-        const double u = u01(r.w[1]);
+        const double u = s_ru[ci];
         const int rev = s_rev[idx];
         const int old_ab = s_cc[mv.A] + s_cc[mv.B] - both;
         // Decide what can be decided without |C(x')|.  The reverse move is a candidate of x'
         // whenever it is allowed, so |C(x')| >= |C| - |C_AB(x)| + 1 bounds the Hastings ratio
         // from above; a draw above that bound rejects exactly as the full ratio would.
         int phase = 1;
-        if (d.proposal == KGDB_PROPOSAL_LITERAL) phase = (u < exp(-dE / d.T)) ? 2 : 0;
+        if (literal) phase = (u < exp(-dE / T)) ? 2 : 0;
         else if (!rev) phase = 0;
-        else if (!(u < exp(-dE / d.T) * (double)n / (double)(n - old_ab + 1))) phase = 0;
+        else if (!(u < exp(-dE / T) * (double)n / (double)(n - old_ab + 1))) phase = 0;
         AttemptEval& ev = s_ev[wv];
         ev.mv = mv; ev.old_ab = old_ab; ev.phase = phase; ev.rev = rev; ev.dE = dE; ev.u = u;
       }
@@ -625,7 +682,7 @@ __global__ __launch_bounds__(DB_BLOCK) void k_db_sweep(DbArgs a) {
     for (int w = 0; w < nev; ++w) {
       const Move mv = s_ev[w].mv;
       const int phase = s_ev[w].phase, old_ab = s_ev[w].old_ab;
-      if (a.debug) {
+      if constexpr (DBG) {
         Topo To{a.chain, a.loc, d.off, N, {mv.A, mv.i, mv.B, mv.j, -1}};
         count_touching(d, To, a, mv.A, mv.B, s_cnt + 3, nullptr, &s_err);
         __syncthreads();
@@ -636,9 +693,9 @@ __global__ __launch_bounds__(DB_BLOCK) void k_db_sweep(DbArgs a) {
         __syncthreads();
       }
       if (threadIdx.x == 0) {
-        st->attempts++;
-        st->sum_ncand += n;
-        if (d.proposal != KGDB_PROPOSAL_LITERAL && !s_ev[w].rev) st->reverse_impossible++;
+        n_att++;
+        sum_nc += n;
+        if (!literal && !s_ev[w].rev) n_norev++;
         // training record: inputs of the proposed move in the topology it was proposed in
         s_logat = -1;
         if (a.log_feat && s_logn < a.log_cap) {
@@ -653,12 +710,12 @@ __global__ __launch_bounds__(DB_BLOCK) void k_db_sweep(DbArgs a) {
       }
       if (phase == 0) continue;
       touching_after(d, a, mv, s_keys, s_pair, n, s_cnt, s_new, &s_err, DB_NEW_CAP);
-      if (a.debug) {  // the derived set has the size of a full rescan of both chains
+      if constexpr (DBG) {  // the derived set has the size of a full rescan of both chains
         Topo Tn{a.chain, a.loc, d.off, N, mv};
         count_touching(d, Tn, a, mv.A, mv.B, s_cnt + 2, nullptr, &s_err);
       }
       __syncthreads();
-      if (a.debug && threadIdx.x == 0) {
+      if (DBG && threadIdx.x == 0) {
         if (s_cnt[2] != s_cnt[0]) s_err |= ERR_DB_MISMATCH;
         s_cnt[2] = 0;
       }
@@ -666,14 +723,15 @@ __global__ __launch_bounds__(DB_BLOCK) void k_db_sweep(DbArgs a) {
         const int new_ab = s_cnt[0];
         const int n_new = n - old_ab + new_ab;
         const double dE = s_ev[w].dE, u = s_ev[w].u;
-        const double ratio = (phase == 2) ? 2.0 : exp(-dE / d.T) * (double)n / (double)n_new;
-        // capacities of the merge: kept keys sit below the sorted new keys in the scratch half
+        const double ratio = (phase == 2) ? 2.0 : exp(-dE / T) * (double)n / (double)n_new;
+        // capacities of the merge: new keys and leaving keys share the scratch half
         const int acc = (u < ratio) && (s_cnt[1] <= DB_NEW_CAP) && (n_new <= DB_CAND_CAP) &&
-                        (n - old_ab <= DB_CAND_CAP - DB_NEW_CAP);
+                        (old_ab <= DB_CAND_CAP - DB_NEW_CAP);
         if ((u < ratio) && !acc) s_err |= ERR_CAND_OVERFLOW;
-        if (acc) { st->accepted++; st->sum_dE_accepted += dE; }
+        if (acc) { n_acc++; sum_dE += dE; }
         if (acc && s_logat >= 0) a.log_label[(size_t)k * a.log_cap + s_logat] = 1;
         s_accept = acc;
+        s_nrm = 0;
       }
       __syncthreads();
       if (!s_accept) {
@@ -682,89 +740,105 @@ __global__ __launch_bounds__(DB_BLOCK) void k_db_sweep(DbArgs a) {
         continue;
       }
 
-      // ---- commit: new rows of chains A and B (read through the move, then written)
+      // ---- commit: the new rows of chains A and B
+      commit_move(d.off, N, a.chain, a.loc, mv);
+      // ---- list update: keys touching A or B leave (order kept), the new ones merge in.  A
+      // move changes only the junctions of chains A and B, so the Delta E and reverse test of
+      // every other listed move carry over; only the new keys are evaluated.
       {
-        const Topo Tm{a.chain, a.loc, d.off, N, mv};
-        int vals[DB_MAXPT];
-#pragma unroll
-        for (int q = 0; q < DB_MAXPT; ++q) {
-          const int idx = threadIdx.x + q * DB_BLOCK;
-          if (idx < 2 * N) {
-            const int X = idx < N ? mv.A : mv.B;
-            vals[q] = Tm.at(X, (idx < N ? idx : idx - N) + 1);
-          }
-        }
-        __syncthreads();
-#pragma unroll
-        for (int q = 0; q < DB_MAXPT; ++q) {
-          const int idx = threadIdx.x + q * DB_BLOCK;
-          if (idx < 2 * N) {
-            const int X = idx < N ? mv.A : mv.B;
-            const int p0 = idx < N ? idx : idx - N;
-            a.chain[d.off + X * N + p0] = vals[q];
-            a.loc[vals[q]] = X * N + p0;
-          }
-        }
-      }
-      // ---- list update: drop keys touching A or B (order kept), merge the new ones; the
-      // per-chain counts follow
-      {
-        const int nn = s_cnt[1] < DB_NEW_CAP ? s_cnt[1] : DB_NEW_CAP;
-        uint64_t* s_scr = s_keys + DB_CAND_CAP;
-        uint32_t* s_pscr = s_pair + DB_CAND_CAP;
-        // sort the (few) new keys by rank: keys are distinct
+        const int nn = s_cnt[1];                          // <= DB_NEW_CAP = DB_BLOCK
+        uint64_t* s_ns = s_keys + DB_CAND_CAP;            // the new keys, sorted
+        uint64_t* s_rm = s_keys + DB_CAND_CAP + DB_NEW_CAP;  // the leaving keys
         for (int t = threadIdx.x; t < nn; t += blockDim.x) {
           const uint64_t key = s_new[t];
           int r = 0;
           for (int q = 0; q < nn; ++q) r += s_new[q] < key ? 1 : 0;
-          const uint32_t pr = key_pair(key, M, N);
-          s_scr[DB_CAND_CAP - DB_NEW_CAP + r] = key;  // sorted new keys at the top of the scratch half
-          s_pscr[DB_CAND_CAP - DB_NEW_CAP + r] = pr;
+          s_ns[r] = key;
+          const uint32_t pr = key_pair(key, d);
           atomicAdd(&s_cc[pr >> 16], 1);
           atomicAdd(&s_cc[pr & 0xffffu], 1);
         }
-        // compact the kept keys into the bottom of the scratch half, in order
-        const int per = (n + DB_BLOCK - 1) / DB_BLOCK;  // <= 3
+        const int per = (n + DB_BLOCK - 1) / DB_BLOCK;  // <= DB_KPT
         const int t0 = threadIdx.x * per;
-        int keep = 0;
-        for (int q = 0; q < per; ++q)
-          if (t0 + q < n && !pair_touches(s_pair[t0 + q], mv.A, mv.B)) ++keep;
-        const int pos0 = block_exclusive_scan(keep, s_tmp, &s_total);
-        const int nk = s_total;
-        int pos = pos0;
-        for (int q = 0; q < per; ++q) {
-          if (t0 + q >= n) break;
-          const uint32_t pr = s_pair[t0 + q];
-          if (!pair_touches(pr, mv.A, mv.B)) {
-            s_scr[pos] = s_keys[t0 + q];
-            s_pscr[pos++] = pr;
-          } else {
-            atomicSub(&s_cc[pr >> 16], 1);
-            atomicSub(&s_cc[pr & 0xffffu], 1);
+        uint64_t kk[DB_KPT];
+        uint32_t kp[DB_KPT];
+        double kd[DB_KPT];
+        uint8_t kr[DB_KPT];
+        int keep = 0, flags = 0;
+#pragma unroll
+        for (int q = 0; q < DB_KPT; ++q) {
+          if (q < per && t0 + q < n) {
+            kk[q] = s_keys[t0 + q];
+            kp[q] = s_pair[t0 + q];
+            kd[q] = s_dE[t0 + q];
+            kr[q] = s_rev[t0 + q];
+            if (!pair_touches(kp[q], mv.A, mv.B)) {
+              ++keep;
+              flags |= 1 << q;
+            } else {
+              const int slot = atomicAdd(&s_nrm, 1);  // < old_ab <= DB_CAND_CAP - DB_NEW_CAP
+              if (slot < DB_CAND_CAP - DB_NEW_CAP) s_rm[slot] = kk[q];
+              atomicSub(&s_cc[kp[q] >> 16], 1);
+              atomicSub(&s_cc[kp[q] & 0xffffu], 1);
+            }
           }
         }
-        __syncthreads();
-        const uint64_t* s_ns = s_scr + (DB_CAND_CAP - DB_NEW_CAP);
-        const uint32_t* s_nsp = s_pscr + (DB_CAND_CAP - DB_NEW_CAP);
-        // merge: kept key at r goes to r + #(new < key); new key at q to q + #(kept < key)
-        for (int t = threadIdx.x; t < nk; t += blockDim.x) {
-          const uint64_t key = s_scr[t];
-          int lo = 0, hi = nn;
-          while (lo < hi) { const int mid = (lo + hi) >> 1; if (s_ns[mid] < key) lo = mid + 1; else hi = mid; }
-          s_keys[t + lo] = key;
-          s_pair[t + lo] = s_pscr[t];
+        const int pos0 = block_exclusive_scan(keep, s_tmp, &s_total);  // synchronises
+        const int nk = s_total, nrm = s_nrm;
+        // attributes of the new keys in the committed topology (chain rows written above)
+        key_attributes(d, a, s_ns, nn, s_ndE, s_nrev);
+        // destination of new key t: t + #(kept keys below it)
+        int dnew[DB_NPT];
+#pragma unroll
+        for (int q = 0; q < DB_NPT; ++q) {
+          const int t = (int)threadIdx.x + q * DB_BLOCK;
+          dnew[q] = -1;
+          if (t < nn) {
+            const uint64_t knew = s_ns[t];
+            int lo = 0, hi = n;
+            while (lo < hi) { const int mid = (lo + hi) >> 1; if (s_keys[mid] < knew) lo = mid + 1; else hi = mid; }
+            int below_rm = 0;
+            for (int r = 0; r < nrm; ++r) below_rm += s_rm[r] < knew ? 1 : 0;
+            dnew[q] = t + lo - below_rm;
+          }
         }
-        for (int t = threadIdx.x; t < nn; t += blockDim.x) {
-          const uint64_t key = s_ns[t];
-          int lo = 0, hi = nk;
-          while (lo < hi) { const int mid = (lo + hi) >> 1; if (s_scr[mid] < key) lo = mid + 1; else hi = mid; }
-          s_keys[t + lo] = key;
-          s_pair[t + lo] = s_nsp[t];
+        // destination of a kept key: its kept rank + #(new keys below it)
+        int dk[DB_KPT];
+        int pos = pos0;
+#pragma unroll
+        for (int q = 0; q < DB_KPT; ++q) {
+          dk[q] = -1;
+          if (flags & (1 << q)) {
+            int lo = 0, hi = nn;
+            while (lo < hi) { const int mid = (lo + hi) >> 1; if (s_ns[mid] < kk[q]) lo = mid + 1; else hi = mid; }
+            dk[q] = pos++ + lo;
+          }
+        }
+        __syncthreads();  // every read of the old list and of s_ndE's producers is done
+#pragma unroll
+        for (int q = 0; q < DB_KPT; ++q)
+          if (dk[q] >= 0) { s_keys[dk[q]] = kk[q]; s_pair[dk[q]] = kp[q]; s_dE[dk[q]] = kd[q]; s_rev[dk[q]] = kr[q]; }
+#pragma unroll
+        for (int q = 0; q < DB_NPT; ++q) {
+          if (dnew[q] >= 0) {
+            const int t = (int)threadIdx.x + q * DB_BLOCK;
+            const uint64_t knew = s_ns[t];
+            s_keys[dnew[q]] = knew;
+            s_pair[dnew[q]] = key_pair(knew, d);
+            s_dE[dnew[q]] = s_ndE[t];
+            s_rev[dnew[q]] = s_nrev[t];
+          }
         }
         n = nk + nn;
         __syncthreads();
-        // attributes of every listed move in the new topology (the chain rows written above)
-        key_attributes(d, a, s_keys, n, s_dE, s_rev);
+      }
+      if constexpr (DBG) {  // the carried attributes equal a full evaluation in the new topology
+        double* s_chk = (double*)(s_keys + DB_CAND_CAP);  // scratch half: n <= DB_CAND_CAP doubles
+        uint8_t* s_chr = (uint8_t*)s_new;                 // DB_NEW_CAP * 8 >= DB_CAND_CAP bytes
+        key_attributes(d, a, s_keys, n, s_chk, s_chr);
+        __syncthreads();
+        for (int t = threadIdx.x; t < n; t += blockDim.x)
+          if (s_chk[t] != s_dE[t] || s_chr[t] != s_rev[t]) atomicOr(&s_err, ERR_DB_MISMATCH);
         __syncthreads();
       }
       used = w + 1;  // attempts after an accepted one are evaluated again
@@ -773,7 +847,14 @@ __global__ __launch_bounds__(DB_BLOCK) void k_db_sweep(DbArgs a) {
     att += used;
     __syncthreads();  // s_ev and s_cnt are rewritten by the next round
   }
+  __syncthreads();
   if (threadIdx.x == 0) {
+    st->attempts = n_att;
+    st->no_candidate = n_nocand;
+    st->accepted = n_acc;
+    st->reverse_impossible = n_norev;
+    st->sum_ncand = sum_nc;
+    st->sum_dE_accepted = sum_dE;
     st->ncand_end = n;
     if (s_err) atomicOr(&a.err[k], s_err);
     a.ncand[k] = n;
@@ -788,13 +869,13 @@ __global__ __launch_bounds__(DB_BLOCK) void k_db_probe(DbArgs a, int k, const ui
   __shared__ int s_cnt[4];
   __shared__ uint32_t s_err;
   const MeltDesc& d = a.md[k];
-  const Move mv = decode_key(keys[blockIdx.x], d.M, d.N);
+  const Move mv = decode_key(keys[blockIdx.x], d);
   if (threadIdx.x == 0) { s_cnt[0] = s_cnt[1] = s_cnt[2] = s_cnt[3] = 0; s_err = 0; }
   __syncthreads();
   const int n = a.ncand[k] < DB_CAND_CAP ? a.ncand[k] : DB_CAND_CAP;
   int mine = 0;
   for (int t = threadIdx.x; t < n; t += blockDim.x)
-    mine += touches(a.cand[(size_t)k * DB_CAND_CAP + t], d.M, d.N, mv.A, mv.B) ? 1 : 0;
+    mine += touches(a.cand[(size_t)k * DB_CAND_CAP + t], d, mv.A, mv.B) ? 1 : 0;
   if (mine) atomicAdd(&s_cnt[2], mine);
   Topo Tn{a.chain, a.loc, d.off, d.N, mv};
   count_touching(d, Tn, a, mv.A, mv.B, s_cnt, nullptr, &s_err);
@@ -817,6 +898,7 @@ __global__ __launch_bounds__(DB_BLOCK) void k_db_probe(DbArgs a, int k, const ui
 // ---------------------------------------------------------------------------------------
 constexpr int LS_SORT = 4096;    // power-of-two sort buffer >= DB_CAND_CAP
 constexpr int LS_NEW_CAP = 512;  // candidates touching the two chains of one move
+static_assert(LS_NEW_CAP <= DB_BLOCK, "one new key per thread in the learned merge");
 
 struct LearnedAttempt {
   Move mv;
@@ -841,7 +923,7 @@ __device__ double block_sum_f64(double v, double* s_tmp, double* s_out) {
   return *s_out;
 }
 
-// s_cum[t] = s_w[0] + ... + s_w[t] for t < n (n <= 3 * DB_BLOCK); returns the total
+// s_cum[t] = s_w[0] + ... + s_w[t] for t < n (n <= DB_KPT * DB_BLOCK); returns the total
 __device__ double block_cumsum_f64(const double* s_w, double* s_cum, int n, double* s_tmp, double* s_out) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int per = (n + DB_BLOCK - 1) / DB_BLOCK;
@@ -878,7 +960,7 @@ __device__ void score_keys(const MeltDesc& d, const Topo& T, const DbArgs& a, co
       const int r = r0 + threadIdx.x;
       if (r < n) {
         float f[NN_IN];
-        move_features(d, T, a.x, a.NP, decode_key(keys[r], d.M, d.N), f);
+        move_features(d, T, a.x, a.NP, decode_key(keys[r], d), f);
         nn_set_input(t, threadIdx.x, f);
       } else {
         nn_zero_input(t, threadIdx.x);
@@ -983,7 +1065,7 @@ __global__ __launch_bounds__(DB_BLOCK) void k_db_sweep_learned(DbArgs a) {
       }
       __syncthreads();
     }
-  for (int t = threadIdx.x; t < n; t += blockDim.x) s_pair[t] = key_pair(s_keys[t], M, N);
+  for (int t = threadIdx.x; t < n; t += blockDim.x) s_pair[t] = key_pair(s_keys[t], d);
   const double mix = a.mix;
   {
     const Topo T{a.chain, a.loc, d.off, N, {0, 0, 0, 0, -1}};
@@ -1016,7 +1098,7 @@ __global__ __launch_bounds__(DB_BLOCK) void k_db_sweep_learned(DbArgs a) {
         idx = lo < n ? lo : n - 1;
       }
       const uint64_t key = s_keys[idx];
-      const Move mv = decode_key(key, M, N);
+      const Move mv = decode_key(key, d);
       const double qf = (1.0 - mix) * s_w[idx] / Z + mix / (double)n;
       // lanes 0-3: junction energies old A, old B, new A, new B (and the old bond lengths)
       double e = 0.0, r2 = 0.0;
@@ -1113,26 +1195,8 @@ __global__ __launch_bounds__(DB_BLOCK) void k_db_sweep_learned(DbArgs a) {
       __syncthreads();
       if (!s_accept) continue;
 
-      // ---- commit: new rows of chains A and B
-      {
-        int vals[DB_MAXPT];
-#pragma unroll
-        for (int q = 0; q < DB_MAXPT; ++q) {
-          const int idx = threadIdx.x + q * DB_BLOCK;
-          if (idx < 2 * N) vals[q] = Tn.at(idx < N ? mv.A : mv.B, (idx < N ? idx : idx - N) + 1);
-        }
-        __syncthreads();
-#pragma unroll
-        for (int q = 0; q < DB_MAXPT; ++q) {
-          const int idx = threadIdx.x + q * DB_BLOCK;
-          if (idx < 2 * N) {
-            const int X = idx < N ? mv.A : mv.B;
-            const int p0 = idx < N ? idx : idx - N;
-            a.chain[d.off + X * N + p0] = vals[q];
-            a.loc[vals[q]] = X * N + p0;
-          }
-        }
-      }
+      // ---- commit: the new rows of chains A and B
+      commit_move(d.off, N, a.chain, a.loc, mv);
       // ---- list update: keys touching A or B leave (order kept), the new ones merge in with
       // their weights and chain pairs
       {
@@ -1143,13 +1207,15 @@ __global__ __launch_bounds__(DB_BLOCK) void k_db_sweep_learned(DbArgs a) {
           s_ns[r] = key;
           s_wns[r] = s_wn[t];
         }
-        const int per = (n + DB_BLOCK - 1) / DB_BLOCK;  // <= 3
+        const int per = (n + DB_BLOCK - 1) / DB_BLOCK;  // <= DB_KPT
         const int t0 = threadIdx.x * per;
-        uint64_t kk[3];
-        double kw[3];
-        uint32_t kp[3];
+        uint64_t kk[DB_KPT];
+        double kw[DB_KPT];
+        uint32_t kp[DB_KPT];
         int keep = 0, flags = 0;
-        for (int q = 0; q < per && q < 3; ++q) {
+#pragma unroll
+        for (int q = 0; q < DB_KPT; ++q) {
+          if (q >= per) break;
           if (t0 + q < n) {
             kk[q] = s_keys[t0 + q];
             kw[q] = s_w[t0 + q];
@@ -1174,9 +1240,10 @@ __global__ __launch_bounds__(DB_BLOCK) void k_db_sweep_learned(DbArgs a) {
           dnew = (int)threadIdx.x + lo - below_rm;
         }
         // destination of a kept key: its kept rank + #(new keys below it)
-        int dk[3];
+        int dk[DB_KPT];
         int pos = pos0;
-        for (int q = 0; q < per && q < 3; ++q) {
+#pragma unroll
+        for (int q = 0; q < DB_KPT; ++q) {
           dk[q] = -1;
           if (flags & (1 << q)) {
             int lo = 0, hi = nn;
@@ -1185,9 +1252,10 @@ __global__ __launch_bounds__(DB_BLOCK) void k_db_sweep_learned(DbArgs a) {
           }
         }
         __syncthreads();
-        for (int q = 0; q < per && q < 3; ++q)
+#pragma unroll
+        for (int q = 0; q < DB_KPT; ++q)
           if (dk[q] >= 0) { s_keys[dk[q]] = kk[q]; s_w[dk[q]] = kw[q]; s_pair[dk[q]] = kp[q]; }
-        if (dnew >= 0 && dnew < nk + nn) { s_keys[dnew] = knew; s_w[dnew] = wnew; s_pair[dnew] = key_pair(knew, M, N); }
+        if (dnew >= 0 && dnew < nk + nn) { s_keys[dnew] = knew; s_w[dnew] = wnew; s_pair[dnew] = key_pair(knew, d); }
         n = nk + nn;
         __syncthreads();
       }
@@ -1214,7 +1282,7 @@ __global__ __launch_bounds__(256) void k_db_features(DbArgs a, int k, const uint
   const MeltDesc& d = a.md[k];
   const Topo T{a.chain, a.loc, d.off, d.N, {0, 0, 0, 0, -1}};
   float f[NN_IN];
-  move_features(d, T, a.x, a.NP, decode_key(keys[t], d.M, d.N), f);
+  move_features(d, T, a.x, a.NP, decode_key(keys[t], d), f);
   for (int q = 0; q < NN_IN; ++q) feat[(size_t)t * NN_IN + q] = f[q];
 }
 
@@ -1228,7 +1296,8 @@ void launch_db_build(const DbArgs& a, const BlockMap& pm, const BlockMap& cm13, 
 }
 
 void launch_db_sweep(const DbArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(k_db_sweep, dim3(a.nm), dim3(DB_BLOCK), 0, s, a);
+  if (a.debug) hipLaunchKernelGGL(k_db_sweep<true>, dim3(a.nm), dim3(DB_BLOCK), 0, s, a);
+  else hipLaunchKernelGGL(k_db_sweep<false>, dim3(a.nm), dim3(DB_BLOCK), 0, s, a);
 }
 
 void launch_db_probe(const DbArgs& a, int melt, const uint64_t* keys, int nkeys, double* dE, int64_t* nafter,

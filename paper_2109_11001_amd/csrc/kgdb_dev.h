@@ -58,6 +58,7 @@ struct MeltDesc {
   double cinvl, hl;          // ncl / L, L / ncl
   double rlist2, half_skin2; // r_list^2, (skin / 2)^2
   double invN;               // 1 / N
+  double inv_mnb, inv_nb;    // 1 / (M (N - 1)), 1 / (N - 1): double-bridging key decoding
   double lang_amp;           // sqrt(2 gamma T / dt)
   uint64_t seed, melt_id;    // Philox key
   uint32_t test_flags;

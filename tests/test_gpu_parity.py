@@ -147,6 +147,22 @@ def test_stale_lists_roll_back():
     assert np.max(np.abs(d)) < 1e-11
 
 
+def test_lowered_interval_is_retried():
+    # with the same too-thin skin, K = 1 is clean: after four clean passes the runtime tries a
+    # longer interval again, which rolls back again; the trajectory still matches the oracle
+    om = o.Melt(M=20, N=50, seed=17, warmup_steps=200)
+    gm = kg.Melt(M=20, N=50, seed=17, warmup_steps=0, nl_every=5, nl_skin=0.004)
+    transfer(om, gm)
+    counts = []
+    for _ in range(6):
+        om.md_steps(10)
+        gm.md_steps(10)
+        counts.append(gm.nl_info()["rollbacks"])
+    assert counts[4] == counts[0] and counts[5] > counts[4], counts
+    d = mi_diff(om.get_state()["x"], gm.get_state()["x"], om.L)
+    assert np.max(np.abs(d)) < 1e-11
+
+
 def test_autotune_restores_state():
     gm = kg.Melt(M=20, N=50, seed=3, warmup_steps=100)
     before = gm.get_state()
