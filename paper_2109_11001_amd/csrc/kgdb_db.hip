@@ -564,6 +564,7 @@ __global__ __launch_bounds__(DB_BLOCK) void k_db_sweep(DbArgs a) {
   __shared__ uint8_t s_rev[DB_CAND_CAP];        // its reverse move is allowed
   __shared__ double s_ndE[DB_NEW_CAP];          // the same for the keys a commit adds
   __shared__ uint8_t s_nrev[DB_NEW_CAP];
+  __shared__ int s_dst[DB_NEW_CAP];             // their places in the merged list
   __shared__ AttemptEval s_ev[DB_WAVES];
   __shared__ uint64_t s_rw[DB_BLOCK];           // draws of attempts c0 .. c0 + DB_BLOCK - 1: choice word,
   __shared__ double s_ru[DB_BLOCK];             // and acceptance uniform
@@ -746,18 +747,9 @@ __global__ __launch_bounds__(DB_BLOCK) void k_db_sweep(DbArgs a) {
       // move changes only the junctions of chains A and B, so the Delta E and reverse test of
       // every other listed move carry over; only the new keys are evaluated.
       {
-        const int nn = s_cnt[1];                          // <= DB_NEW_CAP = DB_BLOCK
-        uint64_t* s_ns = s_keys + DB_CAND_CAP;            // the new keys, sorted
-        uint64_t* s_rm = s_keys + DB_CAND_CAP + DB_NEW_CAP;  // the leaving keys
-        for (int t = threadIdx.x; t < nn; t += blockDim.x) {
-          const uint64_t key = s_new[t];
-          int r = 0;
-          for (int q = 0; q < nn; ++q) r += s_new[q] < key ? 1 : 0;
-          s_ns[r] = key;
-          const uint32_t pr = key_pair(key, d);
-          atomicAdd(&s_cc[pr >> 16], 1);
-          atomicAdd(&s_cc[pr & 0xffffu], 1);
-        }
+        const int nn = s_cnt[1];                             // <= DB_NEW_CAP
+        uint64_t* s_ns = s_keys + DB_CAND_CAP;               // the new keys, sorted
+        uint64_t* s_rm = s_keys + DB_CAND_CAP + DB_NEW_CAP;  // the leaving keys (any order)
         const int per = (n + DB_BLOCK - 1) / DB_BLOCK;  // <= DB_KPT
         const int t0 = threadIdx.x * per;
         uint64_t kk[DB_KPT];
@@ -785,23 +777,25 @@ __global__ __launch_bounds__(DB_BLOCK) void k_db_sweep(DbArgs a) {
         }
         const int pos0 = block_exclusive_scan(keep, s_tmp, &s_total);  // synchronises
         const int nk = s_total, nrm = s_nrm;
-        // attributes of the new keys in the committed topology (chain rows written above)
-        key_attributes(d, a, s_ns, nn, s_ndE, s_nrev);
-        // destination of new key t: t + #(kept keys below it)
-        int dnew[DB_NPT];
-#pragma unroll
-        for (int q = 0; q < DB_NPT; ++q) {
-          const int t = (int)threadIdx.x + q * DB_BLOCK;
-          dnew[q] = -1;
-          if (t < nn) {
-            const uint64_t knew = s_ns[t];
-            int lo = 0, hi = n;
-            while (lo < hi) { const int mid = (lo + hi) >> 1; if (s_keys[mid] < knew) lo = mid + 1; else hi = mid; }
-            int below_rm = 0;
-            for (int r = 0; r < nrm; ++r) below_rm += s_rm[r] < knew ? 1 : 0;
-            dnew[q] = t + lo - below_rm;
+        // attributes of the new keys (in s_new order) in the committed topology
+        key_attributes(d, a, s_new, nn, s_ndE, s_nrev);
+        // one wavefront per new key: its rank r among the new keys and its destination
+        // r + #(kept keys below it) = r + #(listed keys below it) - #(leaving keys below it)
+        for (int t = wv; t < nn; t += DB_WAVES) {
+          const uint64_t key = s_new[t];
+          int r = 0, brm = 0;
+          for (int q0 = 0; q0 < nn; q0 += 64) r += __popcll(__ballot(q0 + lane < nn && s_new[q0 + lane] < key));
+          for (int q0 = 0; q0 < nrm; q0 += 64) brm += __popcll(__ballot(q0 + lane < nrm && s_rm[q0 + lane] < key));
+          const int lo = wave_lower_bound(s_keys, n, key, lane);
+          if (lane == 0) {
+            s_ns[r] = key;
+            s_dst[t] = r + lo - brm;
+            const uint32_t pr = key_pair(key, d);
+            atomicAdd(&s_cc[pr >> 16], 1);
+            atomicAdd(&s_cc[pr & 0xffffu], 1);
           }
         }
+        __syncthreads();
         // destination of a kept key: its kept rank + #(new keys below it)
         int dk[DB_KPT];
         int pos = pos0;
@@ -814,20 +808,17 @@ __global__ __launch_bounds__(DB_BLOCK) void k_db_sweep(DbArgs a) {
             dk[q] = pos++ + lo;
           }
         }
-        __syncthreads();  // every read of the old list and of s_ndE's producers is done
+        __syncthreads();  // every read of the old list is done
 #pragma unroll
         for (int q = 0; q < DB_KPT; ++q)
           if (dk[q] >= 0) { s_keys[dk[q]] = kk[q]; s_pair[dk[q]] = kp[q]; s_dE[dk[q]] = kd[q]; s_rev[dk[q]] = kr[q]; }
-#pragma unroll
-        for (int q = 0; q < DB_NPT; ++q) {
-          if (dnew[q] >= 0) {
-            const int t = (int)threadIdx.x + q * DB_BLOCK;
-            const uint64_t knew = s_ns[t];
-            s_keys[dnew[q]] = knew;
-            s_pair[dnew[q]] = key_pair(knew, d);
-            s_dE[dnew[q]] = s_ndE[t];
-            s_rev[dnew[q]] = s_nrev[t];
-          }
+        for (int t = threadIdx.x; t < nn; t += blockDim.x) {
+          const int dd = s_dst[t];
+          const uint64_t key = s_new[t];
+          s_keys[dd] = key;
+          s_pair[dd] = key_pair(key, d);
+          s_dE[dd] = s_ndE[t];
+          s_rev[dd] = s_nrev[t];
         }
         n = nk + nn;
         __syncthreads();

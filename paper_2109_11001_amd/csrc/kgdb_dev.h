@@ -103,6 +103,22 @@ __device__ __forceinline__ void gauss2(uint64_t a, uint64_t b, double& z0, doubl
   z0 = rad * cs;
   z1 = rad * sn;
 }
+// The same transform in FP32 for the mixed-precision path (FP32 forces): the hardware log2 and
+// sine / cosine (argument in revolutions, so 2 pi u needs no range reduction) on the same
+// 53-bit uniforms; |error| of a normal is a few 1e-7, far below the FP32 force rounding.
+__device__ __forceinline__ void gauss2_f32(uint64_t a, uint64_t b, double& z0, double& z1) {
+  const float u = (float)u01_open0(a);  // (0, 1]: log2 u >= -53
+  const float rad = __builtin_amdgcn_sqrtf(-1.38629436f * __builtin_amdgcn_logf(u));  // -2 ln u
+  const float t = (float)u01(b);        // [0, 1)
+  z0 = (double)(rad * __builtin_amdgcn_cosf(t));
+  z1 = (double)(rad * __builtin_amdgcn_sinf(t));
+}
+// Langevin noise at the force precision R
+template <typename R>
+__device__ __forceinline__ void gauss2_r(uint64_t a, uint64_t b, double& z0, double& z1) {
+  if constexpr (sizeof(R) == 4) gauss2_f32(a, b, z0, z1);
+  else gauss2(a, b, z0, z1);
+}
 // exact integer in [0,K): high word of r*K
 __device__ __forceinline__ uint64_t rng_choice(uint64_t r, uint64_t K) { return __umul64hi(r, K); }
 

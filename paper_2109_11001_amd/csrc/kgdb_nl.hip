@@ -122,54 +122,86 @@ __device__ __forceinline__ size_t nl_word(int i, int q) {
   return ((size_t)(i >> 6) * (NL_CAP / 4) + (size_t)q) * 64 + (size_t)(i & 63);
 }
 
-// The list of one home monomer (staged x index ih, y index yy); at(t, tmax) gives staged member
-// t, or any valid member when t > tmax.
-// Hits of a run of up to 32 candidates are collected as a bit mask first, then appended in
-// order, four entries per 16-byte store.
+// The list of one home monomer (staged index tme, staged x index ih, y index yy); at(t, tmax)
+// gives staged member t, or any valid member when t > tmax.
+//
+// The neighbourhood is the 3 x 3 rows (z index zz, y offset dy) of three cells along x.  A row,
+// or a side cell of it, whose nearest point is farther than r_list plus a margin (far above
+// the rounding of frame coordinates) holds no member within r_list and is skipped: the list is
+// the same.  Hits of a run of up to 32 members are collected as a bit mask first (the home
+// monomer's own bit cleared), then appended in order, four entries per 16-byte store.
 template <typename R, typename At>
-__device__ __forceinline__ void nl_list_one(const NlArgs& a, int k, const Staged<R>& me, int ih, int yy, int W,
-                                            int WY, R rl2, const int* s_off, At at) {
+__device__ __forceinline__ void nl_list_one(const NlArgs& a, int k, const Staged<R>& me, int tme, int ih, int yy,
+                                            int W, int WY, R hl, R rl2, R rskip2, const int* s_off, At at) {
   uint4* __restrict__ out = (uint4*)a.nlist;
   const int g = (int)(me.tag >> 8);
   const uint32_t hv = (me.tag & 255u) - 13u;
   uint4 acc = make_uint4(0, 0, 0, 0);  // the entries of the word being filled
   int cnt = 0;
+  auto put = [&](uint32_t tag) {  // entry = (slot << 5) | (9 (oz + 1) + 3 (oy + 1) + ox + 1)
+    const uint32_t en = ((tag >> 3) & ~31u) | ((tag & 255u) - hv);
+    const int sl = cnt & 3;
+    acc.x = sl == 0 ? en : acc.x;
+    acc.y = sl == 1 ? en : acc.y;
+    acc.z = sl == 2 ? en : acc.z;
+    acc.w = sl == 3 ? en : acc.w;
+    if (sl == 3 && cnt < NL_CAP) out[nl_word(g, cnt >> 2)] = acc;
+    ++cnt;
+  };
+  auto hits = [&](int r0, int re) {  // hit mask of members r0 .. re - 1 (re - r0 <= 32)
+    uint32_t m = 0;
+    for (int t0 = r0; t0 < re; t0 += 4) {
+      // at() may read up to three entries past the run (masked below)
+      Staged<R> p[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) p[u] = at(t0 + u, re - 1);
+      uint32_t nib = 0;  // straight-line: no branches per candidate
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const R dx = p[u].x - me.x, dy = p[u].y - me.y, dz = p[u].z - me.z;
+        nib |= (uint32_t)(dx * dx + dy * dy + dz * dz < rl2) << u;
+      }
+      const int rem = re - t0;
+      nib &= rem >= 4 ? 15u : ((1u << rem) - 1u);
+      m |= nib << (t0 - r0);
+    }
+    return m;
+  };
+  // distances from the home monomer to the faces of its cell (frame origin: low corner of the
+  // first home cell, which has x index 1)
+  const R cx0 = (R)(ih - 1) * hl, cy0 = (R)(yy - 1) * hl;
+  const R dxl = me.x - cx0, dxr = cx0 + hl - me.x;
+  const R dyl = me.y - cy0, dyr = cy0 + hl - me.y;
+  const R dzl = me.z, dzr = hl - me.z;
   for (int zz = 0; zz < 3; ++zz) {
+    const R ez = zz == 0 ? dzl : (zz == 2 ? dzr : (R)0);
     for (int dy = -1; dy <= 1; ++dy) {
+      const R ey = dy < 0 ? dyl : (dy > 0 ? dyr : (R)0);
+      const R e2 = ey * ey + ez * ez;
       const int c0 = (zz * WY + yy + dy) * W + ih - 1;  // cells c0 .. c0 + 2: x offsets -1, 0, +1
-      const int b = s_off[c0], e = s_off[c0 + 3];
-      for (int r0 = b; r0 < e; r0 += 32) {
-        const int re = min(e, r0 + 32);
-        uint32_t m = 0;
-        for (int t0 = r0; t0 < re; t0 += 4) {
-          // at() may read up to three entries past the run (masked below)
-          Staged<R> p[4];
-#pragma unroll
-          for (int u = 0; u < 4; ++u) p[u] = at(t0 + u, re - 1);
-          uint32_t nib = 0;  // straight-line: no branches per candidate
-#pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            const R dx = p[u].x - me.x, dy2 = p[u].y - me.y, dz = p[u].z - me.z;
-            nib |= (uint32_t)(dx * dx + dy2 * dy2 + dz * dz < rl2) << u;
-          }
-          const int rem = re - t0;
-          nib &= rem >= 4 ? 15u : ((1u << rem) - 1u);
-          m |= nib << (t0 - r0);
-        }
-        while (m) {
-          const int bit = __builtin_ctz(m);
-          m &= m - 1;
+      int b = s_off[c0], e = s_off[c0 + 3];
+      if (e2 > rskip2) {
+        e = b;
+      } else {
+        if (dxl * dxl + e2 > rskip2) b = s_off[c0 + 1];
+        if (dxr * dxr + e2 > rskip2) e = s_off[c0 + 2];
+      }
+      const int re = min(e, b + 32);
+      uint32_t m = hits(b, re);
+      const int sb = tme - b;  // the home monomer itself
+      if (sb >= 0 && sb < 32) m &= ~(1u << sb);
+      while (m) {
+        const int bit = __builtin_ctz(m);
+        m &= m - 1;
+        put(at(b + bit, b + bit).tag);
+      }
+      for (int r0 = re; r0 < e; r0 += 32) {  // members past the first 32 of a run
+        uint32_t m2 = hits(r0, min(e, r0 + 32));
+        while (m2) {
+          const int bit = __builtin_ctz(m2);
+          m2 &= m2 - 1;
           const uint32_t tag = at(r0 + bit, r0 + bit).tag;
-          if (tag == me.tag) continue;  // the home monomer itself
-          // entry = (slot << 5) | (9 (oz + 1) + 3 (oy + 1) + ox + 1)
-          const uint32_t en = ((tag >> 3) & ~31u) | ((tag & 255u) - hv);
-          const int sl = cnt & 3;
-          acc.x = sl == 0 ? en : acc.x;
-          acc.y = sl == 1 ? en : acc.y;
-          acc.z = sl == 2 ? en : acc.z;
-          acc.w = sl == 3 ? en : acc.w;
-          if (sl == 3 && cnt < NL_CAP) out[nl_word(g, cnt >> 2)] = acc;
-          ++cnt;
+          if (tag != me.tag) put(tag);
         }
       }
     }
@@ -266,8 +298,11 @@ __global__ __launch_bounds__(NLB_THREADS) void k_nl_build(NlArgs a) {
     const int c = (WY + yy) * W + 1;
     nhome += s_off[c + nh] - s_off[c];
   }
-  // the bound carries a 1e-4 relative margin for the rounding of frame coordinates
+  // the bound carries a 1e-4 relative margin for the rounding of frame coordinates; rows and
+  // cells are skipped only beyond r_list + 1e-3
   const R rl2 = (R)(d.rlist2 * 1.0002);
+  const double rsk = sqrt(d.rlist2) + 1e-3;
+  const R rskip2 = (R)(rsk * rsk);
   for (int h = threadIdx.x; h < nhome; h += NLB_THREADS) {
     int yy = 1, q = h;
     for (;; ++yy) {
@@ -282,9 +317,11 @@ __global__ __launch_bounds__(NLB_THREADS) void k_nl_build(NlArgs a) {
     while (hi - lo > 1) { const int mid = (lo + hi) >> 1; if (s_off[mid] <= t) lo = mid; else hi = mid; }
     const int ih = lo - (WY + yy) * W;
     if (staged)
-      nl_list_one(a, k, s_pos[t], ih, yy, W, WY, rl2, s_off, [&](int u, int) { return s_pos[u]; });
+      nl_list_one(a, k, s_pos[t], t, ih, yy, W, WY, hl, rl2, rskip2, s_off,
+                  [&](int u, int) { return s_pos[u]; });
     else
-      nl_list_one(a, k, member(t), ih, yy, W, WY, rl2, s_off, [&](int u, int umax) { return member(min(u, umax)); });
+      nl_list_one(a, k, member(t), t, ih, yy, W, WY, hl, rl2, rskip2, s_off,
+                  [&](int u, int umax) { return member(min(u, umax)); });
   }
 }
 
@@ -383,8 +420,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
     __builtin_amdgcn_sched_barrier(0);
     const U64x4 w = rng_draw(d, mono, idx, ST_LANGEVIN);
     double z3;
-    gauss2(w.w[0], w.w[1], z0, z1);
-    gauss2(w.w[2], w.w[3], z2, z3);
+    gauss2_r<R>(w.w[0], w.w[1], z0, z1);
+    gauss2_r<R>(w.w[2], w.w[3], z2, z3);
     asm volatile("" : "+v"(z0), "+v"(z1), "+v"(z2));  // materialise the noise here
     __builtin_amdgcn_sched_barrier(0);
   }

@@ -211,6 +211,23 @@ def test_md_steps_mixed_one_step():
     assert np.max(np.abs(mi_diff(so["x"], sg["x"], om.L))) < 1e-5
 
 
+def test_mixed_noise_is_the_fp64_noise_in_fp32():
+    # with the forces off, one step of the two precisions from the same state differs only in
+    # the transform of the same uniforms into normals: FP32 (hardware log2, sine and cosine of
+    # revolutions) against FP64 Box-Muller
+    kw = dict(M=20, N=50, seed=31, warmup_steps=0, test_flags=kg.TF_NOFORCE)
+    a = kg.Melt(precision=kg.PREC_FP64, **kw)
+    b = kg.Melt(precision=kg.PREC_MIXED, **kw)
+    st = a.get_state()
+    b.set_state(0, x=st["x"], v=st["v"], fl=st["fl"], chains=st["chains"], counters=st["counters"])
+    a.md_steps(1, graph=False)
+    b.md_steps(1, graph=False)
+    sa, sb = a.get_state(), b.get_state()
+    assert np.array_equal(sa["x"], sb["x"])
+    dz = np.abs(sa["v"] - sb["v"]) / (0.5 * 0.01 * np.sqrt(2.0 * 1.0 * 1.0 / 0.01))  # |delta z|
+    assert 0 < np.max(dz) < 1e-5, np.max(dz)
+
+
 def test_graph_equals_direct_and_is_deterministic():
     kw = dict(M=20, N=50, seed=5, warmup_steps=100)
     a, b, c = kg.Melt(**kw), kg.Melt(**kw), kg.Melt(**kw)
