@@ -133,6 +133,23 @@ def test_md_every_rebuild_interval(K, prec, tol):
     assert np.max(np.abs(so["v"] - sg["v"])) < (1e-9 if prec == 0 else 1e-3)
 
 
+def test_md_steps_full_size_c1():
+    # the 200k-monomer workload (200 chains x 1000 beads, kappa = 2, n = 2) through the
+    # production step as the bench runs it (Verlet lists, graphs)
+    om = o.Melt(M=200, N=1000, kappa=2.0, seed=1, warmup_steps=100)
+    st = om.get_state()
+    om.md_steps(2)
+    so = om.get_state()
+    for prec, tx, tv in ((kg.PREC_FP64, 1e-11, 1e-9), (kg.PREC_MIXED, 1e-5, 1e-3)):
+        gm = kg.Melt(M=200, N=1000, kappa=2.0, seed=1, warmup_steps=0, precision=prec)
+        gm.set_state(0, x=st["x"], v=st["v"], fl=st["fl"], chains=st["chains"], counters=st["counters"])
+        gm.md_steps(2)
+        sg = gm.get_state()
+        assert np.max(np.abs(mi_diff(so["x"], sg["x"], om.L))) < tx, prec
+        assert np.max(np.abs(so["v"] - sg["v"])) < tv, prec
+        gm.close()
+
+
 def test_stale_lists_roll_back():
     # a skin far too thin for 5-step rebuilds: the runtime must detect it, redo the steps
     # with more frequent rebuilds, and still match the oracle
