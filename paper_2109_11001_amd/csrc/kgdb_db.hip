@@ -1004,6 +1004,7 @@ struct LearnedEval {
 };
 
 constexpr int LS_WAVES = DB_BLOCK / 64;
+static_assert(LS_WAVES <= 16, "the reverse weights of a round take one 16-row pass");
 
 __global__ __launch_bounds__(DB_BLOCK) void k_db_sweep_learned(DbArgs a) {
   __shared__ uint64_t s_keys[LS_SORT];     // sorted candidate keys [0, n)
@@ -1029,15 +1030,21 @@ __global__ __launch_bounds__(DB_BLOCK) void k_db_sweep_learned(DbArgs a) {
   const int M = d.M, N = d.N;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   kgdb_db_stats* st = (kgdb_db_stats*)a.stats + k;
+  // statistics, kept by thread 0 in LDS and stored at the end
+  __shared__ int64_t n_att, n_nocand, n_acc, n_norev, sum_nc;
+  __shared__ double sum_dE;
   if (threadIdx.x == 0) {
-    st->attempts = st->no_candidate = st->accepted = st->reverse_impossible = st->sum_ncand = 0;
-    st->sum_dE_accepted = 0.0;
-    st->ncand_end = 0;
     s_err = 0;
+    n_att = n_nocand = n_acc = n_norev = sum_nc = 0;
+    sum_dE = 0.0;
   }
   int n = a.ncand[k];
   if (n > DB_CAND_CAP || a.err[k] != 0) {
-    if (threadIdx.x == 0) st->ncand_end = n;
+    if (threadIdx.x == 0) {
+      st->attempts = st->no_candidate = st->accepted = st->reverse_impossible = st->sum_ncand = 0;
+      st->sum_dE_accepted = 0.0;
+      st->ncand_end = n;
+    }
     return;
   }
   int P = 1;
@@ -1064,16 +1071,12 @@ __global__ __launch_bounds__(DB_BLOCK) void k_db_sweep_learned(DbArgs a) {
   }
   double Z = block_cumsum_f64(s_w, s_cum, n, s_dtmp, &s_dout);
 
-  // per-wavefront rows of the single-row network pass, inside the tile's second buffer
-  __bf16* xrow = &s_t.a1[0][0] + (size_t)wv * (NN_SA0 + NN_SA);
-  __bf16* hrow = xrow + NN_SA0;
-
   const int64_t K = a.nattempt[k];
   const uint64_t sweep = a.sweep_ctr[k];
   int64_t att = 0;
   while (att < K) {
     if (n == 0) {
-      if (threadIdx.x == 0) { st->attempts += K - att; st->no_candidate += K - att; }
+      if (threadIdx.x == 0) { n_att += K - att; n_nocand += K - att; }
       break;
     }
     // ---- evaluate attempts att .. att + LS_WAVES - 1, wavefront wv taking att + wv
@@ -1115,29 +1118,35 @@ __global__ __launch_bounds__(DB_BLOCK) void k_db_sweep_learned(DbArgs a) {
       const double r2a = __shfl(r2, 0, 64), r2b = __shfl(r2, 1, 64);
       const double dE = (e2 + e3) - (__shfl(e, 0, 64) + e1);
       const int rev = r2a <= d.rmax2 && r2b <= d.rmax2;
-      // the reverse move's weight at x' (the same key), from a single-row pass
-      double wr = 0.0;
+      // inputs of the reverse move (the same key) at x', row wv of the tile
       if (rev) {
         const Topo Tn{a.chain, a.loc, d.off, N, mv};
-        move_features_wave(d, Tn, a.x, a.NP, mv, xrow);
-        wr = nn_weight(nn_forward_row(a.net, xrow, hrow));
+        move_features_wave(d, Tn, a.x, a.NP, mv, &s_t.a0[wv][0]);
       }
       if (lane == 0) {
-        const double u = u01(r.w[1]);
-        // |C(x')| >= |C| - |C_AB(x)| + 1 and Z(x') >= (weights not touching A, B) + w_r since
-        // the reverse move is a candidate of x': an upper bound on the Hastings ratio.  A draw
-        // above it (with a margin far wider than any rounding of the sums) rejects exactly as
-        // the full ratio would.
-        int phase = 1;
-        if (!rev) phase = 0;
-        else {
-          const double qr_max = (1.0 - mix) * wr / (kept + wr) + mix / (double)(n - rmc + 1);
-          if (!(u < exp(-dE / d.T) * qr_max / qf * (1.0 + 1e-9))) phase = 0;
-        }
         LearnedEval& ev = s_ev[wv];
-        ev.mv = mv; ev.key = key; ev.qf = qf; ev.dE = dE; ev.u = u; ev.kept = kept; ev.wr = wr;
-        ev.nrm = rmc; ev.rev = rev; ev.phase = phase;
+        ev.mv = mv; ev.key = key; ev.qf = qf; ev.dE = dE; ev.u = u01(r.w[1]); ev.kept = kept;
+        ev.nrm = rmc; ev.rev = rev;
       }
+    }
+    // the reverse weights of the round's attempts: one 16-row pass of the tile (the rows of
+    // attempts without an allowed reverse move are not used)
+    nn_forward_tile<LS_WAVES, 1>(s_t, a.net, nullptr);  // synchronises
+    if (att + wv < K && lane == 0) {
+      LearnedEval& ev = s_ev[wv];
+      const double wr = ev.rev ? nn_weight(s_t.logit[wv]) : 0.0;
+      // |C(x')| >= |C| - |C_AB(x)| + 1 and Z(x') >= (weights not touching A, B) + w_r since
+      // the reverse move is a candidate of x': an upper bound on the Hastings ratio.  A draw
+      // above it (with a margin far wider than any rounding of the sums) rejects exactly as
+      // the full ratio would.
+      int phase = 1;
+      if (!ev.rev) phase = 0;
+      else {
+        const double qr_max = (1.0 - mix) * wr / (ev.kept + wr) + mix / (double)(n - ev.nrm + 1);
+        if (!(ev.u < exp(-ev.dE / d.T) * qr_max / ev.qf * (1.0 + 1e-9))) phase = 0;
+      }
+      ev.wr = wr;
+      ev.phase = phase;
     }
     __syncthreads();
     // ---- walk the evaluated attempts in order
@@ -1145,9 +1154,9 @@ __global__ __launch_bounds__(DB_BLOCK) void k_db_sweep_learned(DbArgs a) {
     int used = nev;
     for (int w = 0; w < nev; ++w) {
       if (threadIdx.x == 0) {
-        st->attempts++;
-        st->sum_ncand += n;
-        if (!s_ev[w].rev) st->reverse_impossible++;
+        n_att++;
+        sum_nc += n;
+        if (!s_ev[w].rev) n_norev++;
       }
       if (s_ev[w].phase == 0) continue;
       const Move mv = s_ev[w].mv;
@@ -1179,7 +1188,7 @@ __global__ __launch_bounds__(DB_BLOCK) void k_db_sweep_learned(DbArgs a) {
           const double ratio = exp(-ev.dE / d.T) * qr / ev.qf;
           acc = (ev.u < ratio) && n2 <= DB_CAND_CAP;
           if ((ev.u < ratio) && !acc) s_err |= ERR_CAND_OVERFLOW;
-          if (acc) { st->accepted++; st->sum_dE_accepted += ev.dE; }
+          if (acc) { n_acc++; sum_dE += ev.dE; }
         }
         s_accept = acc;
       }
@@ -1259,6 +1268,12 @@ __global__ __launch_bounds__(DB_BLOCK) void k_db_sweep_learned(DbArgs a) {
   }
   __syncthreads();
   if (threadIdx.x == 0) {
+    st->attempts = n_att;
+    st->no_candidate = n_nocand;
+    st->accepted = n_acc;
+    st->reverse_impossible = n_norev;
+    st->sum_ncand = sum_nc;
+    st->sum_dE_accepted = sum_dE;
     st->ncand_end = n;
     if (s_err) atomicOr(&a.err[k], s_err);
     a.ncand[k] = n;

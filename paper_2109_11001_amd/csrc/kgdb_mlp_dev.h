@@ -102,109 +102,74 @@ struct NetRecord {
   int nrow;
 };
 
-// One hidden layer over the 64 rows of a tile: 4 x 8 output blocks of 16 x 16 on
-// v_mfma_f32_16x16x32_bf16, shared round-robin by the workgroup's NW wavefronts.  Operand
-// layout of the instruction (wave64): lane l supplies row l%16 of A and column l%16 of B,
-// each with the 8 consecutive k of block l/16; it receives rows 4(l/16)..4(l/16)+3 of
-// column l%16 of the result.
-template <int K, int NW>
+// One hidden layer over the first 16 RB rows of a tile: RB x 8 output blocks of 16 x 16 on
+// v_mfma_f32_16x16x32_bf16.  Wavefront wv of NW owns the output column blocks wv, wv + NW, ...:
+// the weight fragments of a column block are loaded once and serve all of its row blocks.
+// Operand layout of the instruction (wave64): lane l supplies row l%16 of A and column l%16 of
+// B, each with the 8 consecutive k of block l/16; it receives rows 4(l/16)..4(l/16)+3 of column
+// l%16 of the result.
+template <int K, int NW, int RB>
 __device__ __forceinline__ void nn_layer(const __bf16* __restrict__ in, int in_stride, __bf16* __restrict__ out,
                                          const __bf16* __restrict__ W, const float* __restrict__ bias,
                                          const NetRecord* rec, int layer) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int r16 = lane & 15, kq = lane >> 4;
-  for (int t = wv; t < 32; t += NW) {
-    const int rt = t >> 3, ct = t & 7;
-    f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
-    const __bf16* ap = in + (rt * 16 + r16) * in_stride + kq * 8;
+  for (int ct = wv; ct < 8; ct += NW) {
+    bf16x8 bw[K / 32];
     const __bf16* bp = W + (ct * 16 + r16) * K + kq * 8;
 #pragma unroll
-    for (int kk = 0; kk < K; kk += 32) {
-      const bf16x8 av = *(const bf16x8*)(ap + kk);
-      const bf16x8 bv = *(const bf16x8*)(bp + kk);
-      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc, 0, 0, 0);
-    }
+    for (int kk = 0; kk < K / 32; ++kk) bw[kk] = *(const bf16x8*)(bp + kk * 32);
     const int col = ct * 16 + r16;
     const float bb = bias[col];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int row = rt * 16 + kq * 4 + i;
-      const float z = acc[i] + bb;
-      const int c = q_hidden(z);
-      out[row * NN_SA + col] = (__bf16)((float)c * 0.0625f);
-      if (rec && row < rec->nrow) {
-        const size_t o = ((size_t)row * 3 + layer) * NN_H + col;
-        rec->code[o] = (uint8_t)c;
-        rec->mask[o] = nn_in_range(z) ? 1 : 0;
+    for (int rt = 0; rt < RB; ++rt) {
+      f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+      const __bf16* ap = in + (rt * 16 + r16) * in_stride + kq * 8;
+#pragma unroll
+      for (int kk = 0; kk < K / 32; ++kk)
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(*(const bf16x8*)(ap + kk * 32), bw[kk], acc, 0, 0, 0);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int row = rt * 16 + kq * 4 + i;
+        const float z = acc[i] + bb;
+        const int c = q_hidden(z);
+        out[row * NN_SA + col] = (__bf16)((float)c * 0.0625f);
+        if (rec && row < rec->nrow) {
+          const size_t o = ((size_t)row * 3 + layer) * NN_H + col;
+          rec->code[o] = (uint8_t)c;
+          rec->mask[o] = nn_in_range(z) ? 1 : 0;
+        }
       }
     }
   }
 }
 
-// Logits of the tile's 64 rows (inputs already in t.a0) into t.logit.  Block-cooperative:
+// Logits of the first 16 RB rows of the tile (inputs already in t.a0) into t.logit; the other
+// rows are left alone (each output row depends on its own input row only).  Block-cooperative:
 // every thread of the workgroup (NW wavefronts) must call it.
-template <int NW>
+template <int NW, int RB = 4>
 __device__ void nn_forward_tile(NetTile& t, const NetQ* __restrict__ net, const NetRecord* rec) {
   __syncthreads();
-  nn_layer<NN_INP, NW>(&t.a0[0][0], NN_SA0, &t.a1[0][0], &net->W1[0][0], net->b1, rec, 0);
+  nn_layer<NN_INP, NW, RB>(&t.a0[0][0], NN_SA0, &t.a1[0][0], &net->W1[0][0], net->b1, rec, 0);
   __syncthreads();
-  nn_layer<NN_H, NW>(&t.a1[0][0], NN_SA, &t.a2[0][0], &net->W2[0][0], net->b2, rec, 1);
+  nn_layer<NN_H, NW, RB>(&t.a1[0][0], NN_SA, &t.a2[0][0], &net->W2[0][0], net->b2, rec, 1);
   __syncthreads();
-  nn_layer<NN_H, NW>(&t.a2[0][0], NN_SA, &t.a1[0][0], &net->W3[0][0], net->b3, rec, 2);
+  nn_layer<NN_H, NW, RB>(&t.a2[0][0], NN_SA, &t.a1[0][0], &net->W3[0][0], net->b3, rec, 2);
   __syncthreads();
-  // output unit: products (c/16)(c'/64) and all their partial sums are exact in FP32
-  if (threadIdx.x < NN_TILE) {
-    const int r = threadIdx.x;
+  // output unit: products (c/16)(c'/64) and all their partial sums are exact in FP32, so the
+  // TPR lanes of a row may split its 128 products and add their partial sums in any order
+  constexpr int TPR = (NW * 64) / (16 * RB);
+  static_assert(TPR >= 1 && TPR <= 64 && (TPR & (TPR - 1)) == 0, "lanes per output row");
+  {
+    const int r = threadIdx.x / TPR, j = threadIdx.x % TPR;
     float s = 0.0f;
-#pragma unroll 8
-    for (int k = 0; k < NN_H; ++k) s += (float)t.a1[r][k] * net->w4[k];
-    t.logit[r] = s + net->b4;
+#pragma unroll
+    for (int k = j * (NN_H / TPR); k < (j + 1) * (NN_H / TPR); ++k) s += (float)t.a1[r][k] * net->w4[k];
+#pragma unroll
+    for (int o = TPR / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+    if (j == 0) t.logit[r] = s + net->b4;
   }
   __syncthreads();
-}
-
-// One layer of a single input row by one wavefront (see nn_forward_row): the row is row 0 of
-// a 16-row A block whose other rows are zero.
-template <int K>
-__device__ __forceinline__ void nn_row_layer(const __bf16* in, __bf16* h, const __bf16* __restrict__ W,
-                                             const float* __restrict__ bias) {
-  const int lane = threadIdx.x & 63;
-  const int r16 = lane & 15, kq = lane >> 4;
-  const bf16x8 zero = {(__bf16)0.0f, (__bf16)0.0f, (__bf16)0.0f, (__bf16)0.0f,
-                       (__bf16)0.0f, (__bf16)0.0f, (__bf16)0.0f, (__bf16)0.0f};
-  bf16x8 av[K / 32];
-#pragma unroll
-  for (int q = 0; q < K / 32; ++q) av[q] = r16 == 0 ? *(const bf16x8*)(in + q * 32 + kq * 8) : zero;
-  // every A fragment is in registers before the first result overwrites h (in may be h)
-#pragma unroll 2
-  for (int ct = 0; ct < 8; ++ct) {
-    f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
-    const __bf16* bp = W + (ct * 16 + r16) * K + kq * 8;
-#pragma unroll
-    for (int q = 0; q < K / 32; ++q)
-      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[q], *(const bf16x8*)(bp + q * 32), acc, 0, 0, 0);
-    if (lane < 16) {  // row 0 sits in lanes 0-15
-      const int col = ct * 16 + lane;
-      h[col] = (__bf16)((float)q_hidden(acc[0] + bias[col]) * 0.0625f);
-    }
-  }
-  __builtin_amdgcn_wave_barrier();
-}
-
-// One input row through the network by a single wavefront, on the same instruction as the
-// tile, so the logit is the one the tile gives (every sum is exact).  x: the row's input
-// codes / 64 ([NN_INP] bf16, LDS); h: one row of NN_H bf16 scratch (LDS).  Returns the
-// logit in every lane.
-__device__ __forceinline__ float nn_forward_row(const NetQ* __restrict__ net, const __bf16* x, __bf16* h) {
-  const int lane = threadIdx.x & 63;
-  nn_row_layer<NN_INP>(x, h, &net->W1[0][0], net->b1);
-  nn_row_layer<NN_H>(h, h, &net->W2[0][0], net->b2);
-  nn_row_layer<NN_H>(h, h, &net->W3[0][0], net->b3);
-  // output unit: every partial sum is exact, so the lane split does not change the result
-  float s = (float)h[lane] * net->w4[lane] + (float)h[lane + 64] * net->w4[lane + 64];
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
-  return s + net->b4;
 }
 
 }  // namespace kgdb
