@@ -419,18 +419,24 @@ static NlArgs nl_args(kgdb_batch* b) {
   return a;
 }
 
-static int nl_rebuild(kgdb_batch* b, bool capture) {
+// fused: the step before binned the positions (F_BIN), so the rebuild starts at the ranking
+static int nl_rebuild(kgdb_batch* b, bool capture, bool fused = true) {
   const bool prof = b->prof && !capture;
   if (prof) {
     if (b->ev_used == PROF_EVENTS) CHK(prof_flush(b));
     HIPCHK(hipEventRecord(b->ev[4 * b->ev_used + 2], b->s));
   }
-  launch_nl_rebuild(b->prec, nl_args(b), b->pm.nblk, b->lm[b->nl_ki].nblk, b->rm[b->nl_ki].nblk, b->s);
+  launch_nl_rebuild(b->prec, nl_args(b), b->pm.nblk, b->lm[b->nl_ki].nblk, b->rm[b->nl_ki].nblk, !fused, b->s);
   if (prof) HIPCHK(hipEventRecord(b->ev[4 * b->ev_used + 3], b->s));
   b->cl = 1 - b->cl;
   b->rebuild_pending = prof;
   return 0;
 }
+
+// Step s of a pass (s = 0 opens it) is followed by a list rebuild exactly when (s + 1) % K == 0
+// (graph chunks hold a multiple of K steps, so the rule holds inside them): such a step bins
+// the new positions itself and the rebuild starts at the ranking.
+static int bin_flag(const kgdb_batch* b, int64_t s) { return (s + 1) % b->nl_k == 0 ? F_BIN : 0; }
 
 static int nl_step(kgdb_batch* b, int mode, uint32_t s_off, bool capture) {
   NlArgs a = nl_args(b);
@@ -460,7 +466,7 @@ static int capture_nl_chunk(kgdb_batch* b, hipGraphExec_t* out) {
   int rc = 0;
   for (int j = 1; j <= GCHUNK && !rc; ++j) {
     if (j % b->nl_k == 0) rc = nl_rebuild(b, true);
-    if (!rc) rc = nl_step(b, F_CLOSE | F_OPEN, (uint32_t)j, true);
+    if (!rc) rc = nl_step(b, F_CLOSE | F_OPEN | bin_flag(b, j), (uint32_t)j, true);
   }
   launch_advance(b->d_step, b->nm, GCHUNK, b->s);
   hipError_t e = hipStreamEndCapture(b->s, &g);
@@ -475,8 +481,8 @@ static int capture_nl_chunk(kgdb_batch* b, hipGraphExec_t* out) {
 // one pass of n steps with rebuilds every nl_k steps (before the forces at step s, s % K == 0)
 static int nl_pass(kgdb_batch* b, int64_t n, bool graph) {
   const int K = b->nl_k;
-  CHK(nl_rebuild(b, false));
-  CHK(nl_step(b, F_OPEN, 0, false));
+  CHK(nl_rebuild(b, false, false));
+  CHK(nl_step(b, F_OPEN | bin_flag(b, 0), 0, false));
   int64_t s = 1;
   if (graph && !b->prof && GCHUNK % K == 0) {
     while (n - s >= GCHUNK) {
@@ -489,7 +495,7 @@ static int nl_pass(kgdb_batch* b, int64_t n, bool graph) {
   const int64_t s0 = s;
   for (; s < n; ++s) {
     if (s % K == 0) CHK(nl_rebuild(b, false));
-    CHK(nl_step(b, F_CLOSE | F_OPEN, (uint32_t)(s - s0 + 1), false));
+    CHK(nl_step(b, F_CLOSE | F_OPEN | bin_flag(b, s), (uint32_t)(s - s0 + 1), false));
   }
   if (n - s0 > 0) launch_advance(b->d_step, b->nm, (uint64_t)(n - s0), b->s);
   if (n % K == 0) CHK(nl_rebuild(b, false));

@@ -28,6 +28,7 @@ enum : int {
   F_WARM = 8,    // warm-up: ramped dt, displacement cap, pair-force cap, warm-up noise stream
   F_DIAG = 16,   // forces only: F_c, per-bead magnitude sums and energies (test hooks)
   F_EXACT = 32,  // pair distances from the FP64 master positions (with F_DIAG, R = double)
+  F_BIN = 64,    // list step: also bin the new position for the list rebuild that follows
 };
 
 struct ForceArgs {
@@ -108,7 +109,8 @@ struct NlArgs {
   int nh_uniform;  // n / 2 when every melt has n = 2 or n = 12 (the step kernel is built for those), else 0
 };
 size_t nl_stage_bytes(int prec, int cap);  // dynamic LDS of the list build
-void launch_nl_rebuild(int prec, const NlArgs& a, int pblk, int cblk, int rblk, hipStream_t s);
+// bin = false: the positions were binned by the step before (F_BIN)
+void launch_nl_rebuild(int prec, const NlArgs& a, int pblk, int cblk, int rblk, bool bin, hipStream_t s);
 // ev0/ev1 (optional): events stamped at the kernel's own start and end
 void launch_nl_step(int prec, int mode, const NlArgs& a, int pblk, hipStream_t s, hipEvent_t ev0 = nullptr,
                     hipEvent_t ev1 = nullptr);

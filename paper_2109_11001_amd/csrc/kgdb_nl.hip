@@ -32,30 +32,19 @@ __device__ __forceinline__ int pack_cell(int cx, int cy, int cz) { return cx | (
 // ---------------------------------------------------------------------------------------
 // Monomers are stored in cell order from the previous rebuild, so a wavefront's lanes mostly
 // fall into a few cells: each run of lanes with the same cell takes its bucket slots with one
-// atomic (the order within a bucket is fixed by the finalisation).
-__global__ __launch_bounds__(256) void k_nl_bin(NlArgs a) {
-  const int lb = xcd_remap(blockIdx.x, gridDim.x);
-  const int k = __builtin_amdgcn_readfirstlane(a.pblk_melt[lb]);
-  const MeltDesc& d = a.md[k];
-  const int li = a.pblk_base[lb] + (int)threadIdx.x;
-  const bool valid = li < d.Nm;
-  const int g = d.off + (valid ? li : 0);
-  const int nc = d.ncl;
-  int c = -1;
-  if (valid) {
-    const int cx = cell_coord(a.x[g], d.cinvl, nc), cy = cell_coord(a.x[a.NP + g], d.cinvl, nc),
-              cz = cell_coord(a.x[2 * a.NP + g], d.cinvl, nc);
-    c = d.celll_off + (cz * nc + cy) * nc + cx;
-    a.cell_l[g] = c;
-  }
+// atomic (the order within a bucket is fixed by the finalisation).  Inactive lanes end runs,
+// so the step kernel (whose last wavefront of a melt may have left lanes) bins the same way.
+__device__ __forceinline__ void nl_bin_wave(const NlArgs& a, int k, int g, int c) {
   const int lane = threadIdx.x & 63;
   const int prev = __shfl_up(c, 1, 64);
-  const uint64_t heads = __ballot(lane == 0 || prev != c);
-  const uint64_t upto = (2ull << lane) - 1ull;  // lanes 0 .. lane (all 64 for lane 63)
+  const uint64_t active = __ballot(1);
+  const bool prev_on = lane > 0 && ((active >> (lane - 1)) & 1ull);
+  const uint64_t heads = __ballot(!prev_on || prev != c);  // first lane of each run
+  const uint64_t upto = (2ull << lane) - 1ull;             // lanes 0 .. lane (all 64 for lane 63)
   const int hl = 63 - __builtin_clzll(heads & upto);
   int base = 0;
   if (hl == lane && c >= 0) {
-    const uint64_t after = heads & ~upto;
+    const uint64_t after = (heads | ~active) & ~upto;
     const int next = after ? __builtin_ctzll(after) : 64;
     base = atomicAdd(&a.cnt[c], next - lane);
   }
@@ -64,6 +53,27 @@ __global__ __launch_bounds__(256) void k_nl_bin(NlArgs a) {
   const int s = base + (lane - hl);
   if (s < NL_CELL_CAP) a.bucket_raw[c * NL_CELL_CAP + s] = g;
   else atomicOr(&a.err[k], ERR_CELL_OVERFLOW);
+}
+
+// the list-grid cell of a position
+__device__ __forceinline__ int nl_cell(const MeltDesc& d, double x, double y, double z) {
+  const int nc = d.ncl;
+  return d.celll_off + (cell_coord(z, d.cinvl, nc) * nc + cell_coord(y, d.cinvl, nc)) * nc + cell_coord(x, d.cinvl, nc);
+}
+
+__global__ __launch_bounds__(256) void k_nl_bin(NlArgs a) {
+  const int lb = xcd_remap(blockIdx.x, gridDim.x);
+  const int k = __builtin_amdgcn_readfirstlane(a.pblk_melt[lb]);
+  const MeltDesc& d = a.md[k];
+  const int li = a.pblk_base[lb] + (int)threadIdx.x;
+  const bool valid = li < d.Nm;
+  const int g = d.off + (valid ? li : 0);
+  int c = -1;
+  if (valid) {
+    c = nl_cell(d, a.x[g], a.x[a.NP + g], a.x[2 * a.NP + g]);
+    a.cell_l[g] = c;
+  }
+  nl_bin_wave(a, k, g, c);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -561,6 +571,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
       errbits |= ERR_NONFINITE;
     a.v[g] = hx; a.v[NP + g] = hy; a.v[2 * NP + g] = hz;
     a.xn[g] = nxp; a.xn[NP + g] = nyp; a.xn[2 * NP + g] = nzp;
+    if (MODE & F_BIN) {  // the list rebuild that follows takes the new positions binned here
+      const int cl = nl_cell(d, nxp, nyp, nzp);
+      a.cell_l[g] = cl;
+      nl_bin_wave(a, k, g, cl);
+    }
     // position relative to the reference cell (periodic image nearest to it)
     const int pc = a.refc[g];
     double rx = nxp - (pc & 1023) * d.hl, ry = nyp - ((pc >> 10) & 1023) * d.hl, rz = nzp - (pc >> 20) * d.hl;
@@ -580,8 +595,8 @@ size_t nl_stage_bytes(int prec, int cap) {
   return (size_t)(cap + 4) * (prec ? sizeof(Staged<float>) : sizeof(Staged<double>));
 }
 
-void launch_nl_rebuild(int prec, const NlArgs& a, int pblk, int cblk, int rblk, hipStream_t s) {
-  hipLaunchKernelGGL(k_nl_bin, dim3(pblk), dim3(256), 0, s, a);
+void launch_nl_rebuild(int prec, const NlArgs& a, int pblk, int cblk, int rblk, bool bin, hipStream_t s) {
+  if (bin) hipLaunchKernelGGL(k_nl_bin, dim3(pblk), dim3(256), 0, s, a);
   if (prec) {
     hipLaunchKernelGGL(k_nl_finalize<float>, dim3(pblk), dim3(256), 0, s, a);
     hipLaunchKernelGGL(k_nl_build<float>, dim3(rblk), dim3(NLB_THREADS), nl_stage_bytes(1, a.stage_cap), s, a);
@@ -609,14 +624,18 @@ void launch_nl_step(int prec, int mode, const NlArgs& a, int pblk, hipStream_t s
   if (prec) {
     switch (mode) {
       KG_CASE(float, F_OPEN)
+      KG_CASE(float, F_OPEN | F_BIN)
       KG_CASE(float, F_CLOSE | F_OPEN)
+      KG_CASE(float, F_CLOSE | F_OPEN | F_BIN)
       KG_CASE(float, F_CLOSE | F_STORE)
       default: break;
     }
   } else {
     switch (mode) {
       KG_CASE(double, F_OPEN)
+      KG_CASE(double, F_OPEN | F_BIN)
       KG_CASE(double, F_CLOSE | F_OPEN)
+      KG_CASE(double, F_CLOSE | F_OPEN | F_BIN)
       KG_CASE(double, F_CLOSE | F_STORE)
       default: break;
     }
