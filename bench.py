@@ -36,18 +36,20 @@ MD_PER_STEP = 100
 LEARNED_KAPPA = 2.5
 
 
-def step_kernel_bytes(mixed, mean_list):
-    """Algorithmic bytes per monomer of one step-kernel launch (close + open).
+def step_kernel_bytes(mixed, mean_list, K):
+    """Algorithmic bytes per monomer of one step-kernel launch (close + open), averaged over the
+    K steps of a rebuild interval.
 
     reads: position x (24), velocity v_half (24), own reference-relative position (16 mixed /
     32 FP64), its value at the last rebuild (16), reference cell (4), chain-table position (4),
     its chain-table entry (4), monomer id (4), list length (4) and list entries (4 each).
-    writes: new x (24), new v_half (24), new relative position (16 / 32).  Neighbours' relative
-    positions and bonded partners' positions are re-reads served from cache.
+    writes: new x (24), new v_half (24), new relative position (16 / 32); on the step before a
+    rebuild also the list-grid cell (4) and bucket entry (4).  Neighbours' relative positions
+    and bonded partners' positions are re-reads served from cache.
     """
     rel = 16 if mixed else 32
     reads = 24 + 24 + rel + 16 + 4 + 4 + 4 + 4 + 4 + 4 * mean_list
-    writes = 24 + 24 + rel
+    writes = 24 + 24 + rel + 8.0 / K
     return reads + writes
 
 
@@ -265,7 +267,7 @@ def main():
 
     roof = None
     if "force_kernel_ms" in mixed:
-        bpm = step_kernel_bytes(True, mixed["nl"]["mean_list"])
+        bpm = step_kernel_bytes(True, mixed["nl"]["mean_list"], mixed["nl"]["K"])
         bytes_launch = bpm * mixed["monomers"]
         achieved = bytes_launch / (mixed["force_kernel_ms"] * 1e-3) / 1e9
         tr = measured_traffic()

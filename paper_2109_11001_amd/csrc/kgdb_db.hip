@@ -280,8 +280,9 @@ __global__ __launch_bounds__(256) void k_db_cands(const MeltDesc* __restrict__ m
 // ---------------------------------------------------------------------------------------
 // energies of the junctions (FENE log part and angles that a move can change)
 // ---------------------------------------------------------------------------------------
-__device__ double bond_u(const MeltDesc& d, const double* __restrict__ x, int NP, int u, int w) {
-  const double r = sqrt(dist2(x, NP, d.L, u, w));
+// FENE log term of a bond of squared (minimum-image) length r2
+__device__ double bond_u_r2(const MeltDesc& d, double r2) {
+  const double r = sqrt(r2);
   const double R0 = sqrt(d.R0sq);
   const bool broken = d.amin > 0 ? !(r < 2.0 * R0) : !(r < R0);
   if (broken) return INFINITY;
@@ -289,16 +290,43 @@ __device__ double bond_u(const MeltDesc& d, const double* __restrict__ x, int NP
   if (d.amin > 0 && a < d.amin) return -0.5 * d.kfene * R0 * R0 * (log(d.amin) + (a - d.amin) / d.amin);
   return -0.5 * d.kfene * R0 * R0 * log(a);
 }
+__device__ double bond_u(const MeltDesc& d, const double* __restrict__ x, int NP, int u, int w) {
+  return bond_u_r2(d, dist2(x, NP, d.L, u, w));
+}
 
+// bending term of the bond vectors b1 = q - p, b2 = s - q (minimum image)
+__device__ double angle_u_b(const MeltDesc& d, double b1x, double b1y, double b1z, double b2x, double b2y,
+                            double b2z) {
+  const double l1 = sqrt(b1x * b1x + b1y * b1y + b1z * b1z);
+  const double l2 = sqrt(b2x * b2x + b2y * b2y + b2z * b2z);
+  return d.kappa * (1.0 - (b1x * b2x + b1y * b2y + b1z * b2z) / (l1 * l2));
+}
 __device__ double angle_u(const MeltDesc& d, const double* __restrict__ x, int NP, int p, int q, int s) {
   const double L = d.L;
   const double b1x = min_image(x[q] - x[p], L), b1y = min_image(x[NP + q] - x[NP + p], L),
                b1z = min_image(x[2 * NP + q] - x[2 * NP + p], L);
   const double b2x = min_image(x[s] - x[q], L), b2y = min_image(x[NP + s] - x[NP + q], L),
                b2z = min_image(x[2 * NP + s] - x[2 * NP + q], L);
-  const double l1 = sqrt(b1x * b1x + b1y * b1y + b1z * b1z);
-  const double l2 = sqrt(b2x * b2x + b2y * b2y + b2z * b2z);
-  return d.kappa * (1.0 - (b1x * b2x + b1y * b2y + b1z * b2z) / (l1 * l2));
+  return angle_u_b(d, b1x, b1y, b1z, b2x, b2y, b2z);
+}
+
+// The same from the positions of beads kb - 1 .. kb + 2 (px[o], py[o], pz[o], o = 0 .. 3; those
+// past a chain end unused), with the same operations; also returns the bond's squared length.
+__device__ double junction_energy_pos(const MeltDesc& d, const double* px, const double* py, const double* pz,
+                                      int kb, double& r2) {
+  const double L = d.L;
+  double bx[3], by[3], bz[3];  // bond vectors o -> o + 1
+#pragma unroll
+  for (int o = 0; o < 3; ++o) {
+    bx[o] = min_image(px[o + 1] - px[o], L);
+    by[o] = min_image(py[o + 1] - py[o], L);
+    bz[o] = min_image(pz[o + 1] - pz[o], L);
+  }
+  r2 = bx[1] * bx[1] + by[1] * by[1] + bz[1] * bz[1];
+  double e = bond_u_r2(d, r2);
+  if (kb >= 2) e += angle_u_b(d, bx[0], by[0], bz[0], bx[1], by[1], bz[1]);
+  if (kb + 1 <= d.N - 1) e += angle_u_b(d, bx[1], by[1], bz[1], bx[2], by[2], bz[2]);
+  return e;
 }
 
 // bond kb (1-based, between kb and kb+1) of chain X plus the angles at vertices kb, kb+1
@@ -963,27 +991,26 @@ __device__ void score_keys(const MeltDesc& d, const Topo& T, const DbArgs& a, co
   __syncthreads();
 }
 
-// Inputs of move mv in topology T by lanes 0-7 of a wavefront (lane b: bead b), written as
-// input codes / 64 into x[0..NN_INP) (LDS).  Same arithmetic as move_features.
-__device__ void move_features_wave(const MeltDesc& d, const Topo& T, const double* __restrict__ x, int NP,
-                                   const Move& mv, __bf16* xrow) {
-  const int lane = threadIdx.x & 63;
-  const int N = d.N;
-  const int b = lane & 7;
-  int id;
+// Bead b (0-7) of the learned proposal's inputs for move mv in topology T (see move_features).
+__device__ __forceinline__ int feature_bead(const Topo& T, const Move& mv, int N, int b) {
   if (b < 4) {
     int p = mv.i - 1 + b;
     p = p < 1 ? 1 : (p > N ? N : p);
-    id = T.at(mv.A, p);
-  } else {
-    int q = mv.var == 0 ? mv.j + 2 - (b - 4) : mv.j - 1 + (b - 4);
-    q = q < 1 ? 1 : (q > N ? N : q);
-    id = T.at(mv.B, q);
+    return T.at(mv.A, p);
   }
-  const int id1 = __shfl(id, 1, 64);
+  int q = mv.var == 0 ? mv.j + 2 - (b - 4) : mv.j - 1 + (b - 4);
+  q = q < 1 ? 1 : (q > N ? N : q);
+  return T.at(mv.B, q);
+}
+
+// Inputs from the positions of the eight beads held by lanes 0-7 of a wavefront (lane b: bead
+// b), written as input codes / 64 into x[0..NN_INP) (LDS).  Same arithmetic as move_features.
+__device__ void move_features_gathered(const MeltDesc& d, double px, double py, double pz, __bf16* xrow) {
+  const int lane = threadIdx.x & 63;
+  const double p[3] = {px, py, pz};
   double dd[3];
 #pragma unroll
-  for (int c = 0; c < 3; ++c) dd[c] = min_image(x[(size_t)c * NP + id] - x[(size_t)c * NP + id1], d.L);
+  for (int c = 0; c < 3; ++c) dd[c] = min_image(p[c] - __shfl(p[c], 1, 64), d.L);
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
     const double d2 = __shfl(dd[c], 2, 64), d5 = __shfl(dd[c], 5, 64), d6 = __shfl(dd[c], 6, 64);
@@ -1094,15 +1121,24 @@ __global__ __launch_bounds__(DB_BLOCK) void k_db_sweep_learned(DbArgs a) {
       const uint64_t key = s_keys[idx];
       const Move mv = decode_key(key, d);
       const double qf = (1.0 - mix) * s_w[idx] / Z + mix / (double)n;
-      // lanes 0-3: junction energies old A, old B, new A, new B (and the old bond lengths)
-      double e = 0.0, r2 = 0.0;
-      if (lane < 4) {
-        const Topo T{a.chain, a.loc, d.off, N, lane < 2 ? Move{mv.A, mv.i, mv.B, mv.j, -1} : mv};
-        const int X = (lane & 1) ? mv.B : mv.A, kb = (lane & 1) ? mv.j : mv.i;
-        r2 = dist2(a.x, a.NP, d.L, T.at(X, kb), T.at(X, kb + 1));
-        e = junction_energy(d, T, a.x, a.NP, X, kb);
+      // One gather for every bead the attempt needs, a bead per lane: lanes 0-7 the network's
+      // inputs at x' (the reverse move's), lanes 8-23 beads kb - 1 .. kb + 2 of the junctions
+      // of old A, old B (at x) and new A, new B (at x').
+      const Topo Tn{a.chain, a.loc, d.off, N, mv};
+      int bid = -1;
+      if (lane < 8) {
+        bid = feature_bead(Tn, mv, N, lane);
+      } else if (lane < 24) {
+        const int j = (lane - 8) >> 2, o = (lane - 8) & 3;
+        const Topo T{a.chain, a.loc, d.off, N, j < 2 ? Move{mv.A, mv.i, mv.B, mv.j, -1} : mv};
+        const int X = (j & 1) ? mv.B : mv.A, kb = (j & 1) ? mv.j : mv.i;
+        const int pp = kb - 1 + o;
+        if (pp >= 1 && pp <= N) bid = T.at(X, pp);
       }
-      // candidates touching A or B now, and the weight of the others
+      double bx = 0.0, by = 0.0, bz = 0.0;
+      if (bid >= 0) { bx = a.x[bid]; by = a.x[a.NP + bid]; bz = a.x[2 * a.NP + bid]; }
+      // candidates touching A or B now, and the weight of the others (while the loads are in
+      // flight)
       const uint32_t A = (uint32_t)mv.A, B = (uint32_t)mv.B;
       int rmc = 0;
       double kept = 0.0;
@@ -1114,15 +1150,21 @@ __global__ __launch_bounds__(DB_BLOCK) void k_db_sweep_learned(DbArgs a) {
       }
 #pragma unroll
       for (int o = 32; o > 0; o >>= 1) { rmc += __shfl_xor(rmc, o, 64); kept += __shfl_xor(kept, o, 64); }
+      // lanes 0-3: junction energies old A, old B, new A, new B from the gathered beads
+      double jx[4], jy[4], jz[4];
+#pragma unroll
+      for (int o = 0; o < 4; ++o) {
+        const int src = 8 + 4 * (lane & 3) + o;
+        jx[o] = __shfl(bx, src, 64); jy[o] = __shfl(by, src, 64); jz[o] = __shfl(bz, src, 64);
+      }
+      double r2 = 0.0;
+      const double e = junction_energy_pos(d, jx, jy, jz, (lane & 1) ? mv.j : mv.i, r2);
       const double e1 = __shfl(e, 1, 64), e2 = __shfl(e, 2, 64), e3 = __shfl(e, 3, 64);
       const double r2a = __shfl(r2, 0, 64), r2b = __shfl(r2, 1, 64);
       const double dE = (e2 + e3) - (__shfl(e, 0, 64) + e1);
       const int rev = r2a <= d.rmax2 && r2b <= d.rmax2;
       // inputs of the reverse move (the same key) at x', row wv of the tile
-      if (rev) {
-        const Topo Tn{a.chain, a.loc, d.off, N, mv};
-        move_features_wave(d, Tn, a.x, a.NP, mv, &s_t.a0[wv][0]);
-      }
+      if (rev) move_features_gathered(d, bx, by, bz, &s_t.a0[wv][0]);
       if (lane == 0) {
         LearnedEval& ev = s_ev[wv];
         ev.mv = mv; ev.key = key; ev.qf = qf; ev.dE = dE; ev.u = u01(r.w[1]); ev.kept = kept;
