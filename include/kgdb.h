@@ -104,7 +104,11 @@ int32_t kgdb_batch_size(const kgdb_batch* b);
 
 /* Advance every melt by nsteps velocity-Verlet Langevin steps (Sec. II.B's MD).  Runs on the
    batch's stream; device error flags are read once at the end (KGDB_E_FENE, _NONFINITE,
-   _OVERFLOW).  use_graph != 0 replays captured 100-step hipGraph chunks. */
+   _OVERFLOW).  use_graph != 0 replays captured 100-step hipGraph chunks.  A call whose
+   neighbour lists went stale (a monomer moved more than skin/2 since their rebuild) or
+   overflowed is redone from its start with the next shorter rebuild interval; after four
+   calls without such a redo the interval steps back up towards the chosen one.  The
+   trajectory is the same either way (to rounding). */
 int kgdb_md_steps(kgdb_batch* b, int64_t nsteps, int32_t use_graph);
 
 /* One double-bridging sweep per melt (Fig. 1, Sec. II.B): n_attempts sequential attempts
