@@ -85,6 +85,13 @@ struct kgdb_batch {
   hipGraphExec_t ngexec[3][2][2] = {};  // [K][x parity][occupancy parity]
   int64_t nl_rollbacks = 0;
   int nl_ki_target = 2;            // interval chosen by the caller or the autotuner
+  // lists built ahead (beside a double-bridging sweep) for the next run of steps: valid while
+  // the positions version and the interval are those they were built at
+  uint64_t xver = 0;               // bumped whenever positions or storage slots may change
+  uint64_t lists_ver = ~0ull;
+  int lists_ki = -1;
+  hipStream_t s2 = nullptr;        // side stream of that rebuild (default priority)
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   int nl_clean = 0;                // passes without a rollback since the interval was lowered
   bool rebuild_pending = false;    // profiling: a rebuild was timed for the next step
   uint64_t* d_step = nullptr;
@@ -420,13 +427,14 @@ static NlArgs nl_args(kgdb_batch* b) {
 }
 
 // fused: the step before binned the positions (F_BIN), so the rebuild starts at the ranking
-static int nl_rebuild(kgdb_batch* b, bool capture, bool fused = true) {
-  const bool prof = b->prof && !capture;
+static int nl_rebuild(kgdb_batch* b, bool capture, bool fused = true, hipStream_t on = nullptr) {
+  const bool prof = b->prof && !capture && !on;
   if (prof) {
     if (b->ev_used == PROF_EVENTS) CHK(prof_flush(b));
     HIPCHK(hipEventRecord(b->ev[4 * b->ev_used + 2], b->s));
   }
-  launch_nl_rebuild(b->prec, nl_args(b), b->pm.nblk, b->lm[b->nl_ki].nblk, b->rm[b->nl_ki].nblk, !fused, b->s);
+  launch_nl_rebuild(b->prec, nl_args(b), b->pm.nblk, b->lm[b->nl_ki].nblk, b->rm[b->nl_ki].nblk, !fused,
+                    on ? on : b->s);
   if (prof) HIPCHK(hipEventRecord(b->ev[4 * b->ev_used + 3], b->s));
   b->cl = 1 - b->cl;
   b->rebuild_pending = prof;
@@ -481,7 +489,8 @@ static int capture_nl_chunk(kgdb_batch* b, hipGraphExec_t* out) {
 // one pass of n steps with rebuilds every nl_k steps (before the forces at step s, s % K == 0)
 static int nl_pass(kgdb_batch* b, int64_t n, bool graph) {
   const int K = b->nl_k;
-  CHK(nl_rebuild(b, false, false));
+  if (b->lists_ver == b->xver && b->lists_ki == b->nl_ki && !b->prof) b->lists_ver = ~0ull;  // built ahead
+  else CHK(nl_rebuild(b, false, false));
   CHK(nl_step(b, F_OPEN | bin_flag(b, 0), 0, false));
   int64_t s = 1;
   if (graph && !b->prof && GCHUNK % K == 0) {
@@ -519,6 +528,7 @@ static int save_state(kgdb_batch* b, bool back) {
 // Switch the rebuild interval (and with it the list grid).  A rebuild clears the other
 // occupancy buffer only over its own grid's cells, so both buffers are zeroed here in full.
 static int set_nl_interval(kgdb_batch* b, int ki) {
+  b->lists_ver = ~0ull;  // lists built ahead rely on the occupancy buffers cleared here
   b->nl_ki = ki;
   b->nl_k = NL_KS[ki];
   b->D = b->Dk[ki];
@@ -561,6 +571,7 @@ static int run_steps(kgdb_batch* b, int64_t n, bool graph) {
   b->cells_valid = false;
   CHK(check_errors(b));
   if (b->reorder) CHK(reorder_storage(b));
+  b->xver++;
   // A rollback answers one fast monomer, usually a rare event: after NL_CLEAN_PASSES clean
   // passes the next pass tries the next longer interval again, up to the chosen one.
   if (b->nl_ki < b->nl_ki_target && ++b->nl_clean >= NL_CLEAN_PASSES) {
@@ -591,6 +602,7 @@ static int run_steps_cells(kgdb_batch* b, int64_t n, bool graph) {
   if (b->prof) CHK(prof_flush(b));
   for (int k = 0; k < b->nm; ++k) b->step[k] += (uint64_t)n;
   b->fc_valid = true;
+  b->xver++;
   return check_errors(b);
 }
 
@@ -623,6 +635,9 @@ void kgdb_destroy(kgdb_batch* b) {
       for (auto& ge : a2)
         if (ge) hipGraphExecDestroy(ge);
   for (auto e : b->ev) hipEventDestroy(e);
+  if (b->ev_fork) hipEventDestroy(b->ev_fork);
+  if (b->ev_join) hipEventDestroy(b->ev_join);
+  if (b->s2) hipStreamDestroy(b->s2);
   for (void* q : b->allocs) hipFree(q);
   if (b->h_err) hipHostFree(b->h_err);
   if (b->own_stream && b->s) hipStreamDestroy(b->s);
@@ -990,6 +1005,7 @@ int kgdb_set_state(kgdb_batch* b, int32_t melt, const double* x, const double* v
   }
   b->cells_valid = false;
   b->fc_valid = false;
+  b->xver++;
   return 0;
 }
 
@@ -1163,8 +1179,28 @@ static int sweep_impl(kgdb_batch* b, int64_t n_attempts, kgdb_db_stats* stats, i
     a.log_n = d_logn;
   }
   CHK(db_build(b, a));
+  // The sweep runs one workgroup per melt; the list rebuild that opens the next run of steps
+  // depends on positions and slots only, which a sweep leaves alone, so it runs beside the
+  // sweep on a second stream (not while profiling, to keep the timed rebuilds on one stream).
+  const bool ahead = b->nl_ki >= 0 && !b->prof;
+  if (ahead) {
+    if (!b->s2) {
+      HIPCHK(hipStreamCreateWithFlags(&b->s2, hipStreamNonBlocking));
+      HIPCHK(hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming));
+      HIPCHK(hipEventCreateWithFlags(&b->ev_join, hipEventDisableTiming));
+    }
+    HIPCHK(hipEventRecord(b->ev_fork, b->s));
+    HIPCHK(hipStreamWaitEvent(b->s2, b->ev_fork, 0));
+  }
   if (b->learned) launch_db_sweep_learned(a, b->s);
   else launch_db_sweep(a, b->s);
+  if (ahead) {
+    CHK(nl_rebuild(b, false, false, b->s2));
+    HIPCHK(hipEventRecord(b->ev_join, b->s2));
+    HIPCHK(hipStreamWaitEvent(b->s, b->ev_join, 0));
+    b->lists_ver = b->xver;
+    b->lists_ki = b->nl_ki;
+  }
   HIPCHK(hipGetLastError());
   if (log_feat) {
     HIPCHK(hipMemcpyAsync(log_n, d_logn, sizeof(int64_t) * b->nm, hipMemcpyDeviceToHost, b->s));
@@ -1397,6 +1433,7 @@ int kgdb_autotune(kgdb_batch* b, int32_t nl_every, int32_t reps, int32_t* chosen
   b->prof_force_ms = b->prof_fin_ms = 0;
   b->prof_force_n = b->prof_fin_n = 0;
   CHK(set_nl_interval(b, best_q));
+  b->xver++;
   b->nl_ki_target = best_q;
   b->nl_clean = 0;
   if (chosen) *chosen = b->nl_k;

@@ -358,6 +358,25 @@ def test_db_sweep_full_size_c1():
     assert np.array_equal(om.get_state()["chains"], gm.get_state()["chains"])
 
 
+def test_lists_built_beside_the_sweep():
+    # after a sweep the next run of steps starts from lists rebuilt beside the sweep (second
+    # stream); with profiling on they are rebuilt at the start of the run instead.  The lists
+    # are the same, so the trajectories agree bit for bit.
+    kw = dict(M=20, N=50, seed=8, warmup_steps=100, kappa=1.5)
+    a, b = kg.Melt(**kw), kg.Melt(**kw)
+    b.profile(True)
+    for m in (a, b):
+        m.md_steps(20, graph=False)
+        m.db_sweep(50)
+        m.md_steps(20, graph=False)
+        m.db_sweep(50)
+        m.md_steps(7, graph=False)
+    b.profile(False)
+    sa, sb = a.get_state(), b.get_state()
+    for f in ("x", "v", "fl", "chains"):
+        assert np.array_equal(sa[f], sb[f]), f
+
+
 def test_md_after_sweep_parity():
     # the sweep invalidates the bonded forces; the next step must recompute them
     om, gm = pair(M=20, N=50, seed=31, warmup_steps=200)
