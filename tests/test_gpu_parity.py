@@ -377,6 +377,24 @@ def test_lists_built_beside_the_sweep():
         assert np.array_equal(sa[f], sb[f]), f
 
 
+def test_sweeps_with_rolled_back_lists_match_oracle():
+    # lists built beside each sweep meet runs that roll back to shorter intervals (too thin a
+    # skin): every switch must drop them, and the trajectory still follows the oracle
+    om = o.Melt(M=20, N=50, seed=19, warmup_steps=200)
+    gm = kg.Melt(M=20, N=50, seed=19, warmup_steps=0, nl_every=5, nl_skin=0.004)
+    transfer(om, gm)
+    for _ in range(3):
+        om.md_steps(10)
+        gm.md_steps(10)
+        so = om.db_sweep(40)
+        sg = gm.db_sweep(40)[0]
+        assert so["accepted"] == sg["accepted"]
+    assert gm.nl_info()["rollbacks"] >= 1
+    d = mi_diff(om.get_state()["x"], gm.get_state()["x"], om.L)
+    assert np.max(np.abs(d)) < 1e-10
+    assert np.array_equal(om.get_state()["chains"], gm.get_state()["chains"])
+
+
 def test_md_after_sweep_parity():
     # the sweep invalidates the bonded forces; the next step must recompute them
     om, gm = pair(M=20, N=50, seed=31, warmup_steps=200)
