@@ -107,6 +107,52 @@ def run_gpu(kg, precision, steps, warmup, stream, profile_steps):
     return out
 
 
+def run_size(kg, monomers, md_steps, stream, precision):
+    """Step kernel on one melt of `monomers` monomers (N = 1000 beads per chain, or 2000 where
+    that would exceed the 8192 chains a melt may hold; rho = 0.85, the workload's potentials):
+    `md_steps` MD steps timed end to end, then as many again with the step kernel timed by
+    events.  From 1M monomers up the per-step state no longer fits the 256 MB last-level cache,
+    so the roofline figure is then set by HBM.  MD only: the sweep's candidate list (at most
+    3072 keys per melt) does not hold the ~2.6 keys per chain of melts this large."""
+    import torch
+    N = WORKLOAD["N"]
+    while monomers // N > 8192:
+        N *= 2
+    params = dict(WORKLOAD, M=monomers // N, N=N, precision=precision)
+    t0 = time.perf_counter()
+    b = kg.Batch([params], stream=stream)
+    torch.cuda.synchronize()
+    t_init = time.perf_counter() - t0
+    nm, _ = b.sizes()
+    K, tune_ms = b.autotune(0, reps=10)
+    b.md_steps(MD_PER_STEP)
+    torch.cuda.synchronize()
+    chunks = max(1, md_steps // MD_PER_STEP)  # calls of MD_PER_STEP steps, as in a bench step
+    t0 = time.perf_counter()
+    for _ in range(chunks):
+        b.md_steps(MD_PER_STEP)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    b.profile(True)
+    for _ in range(chunks):
+        b.md_steps(MD_PER_STEP)
+    prof = b.profile_read()
+    b.profile(False)
+    nl = b.nl_info()
+    b.close()
+    ms = prof["force_ms"] / max(prof["force_n"], 1)
+    bpm = step_kernel_bytes(precision == kg.PREC_MIXED, nl["mean_list"], nl["K"])
+    achieved = bpm * nm / (ms * 1e-3) / 1e9
+    return {"monomers": nm, "chains": nm // N, "beads_per_chain": N, "md_steps": chunks * MD_PER_STEP,
+            "monomer_steps_per_s": nm * chunks * MD_PER_STEP / wall, "avg_launch_ms": ms,
+            "launches": prof["force_n"], "rebuild_ms_per_step": prof["finalize_ms"] / max(prof["force_n"], 1),
+            "bytes_per_monomer": round(bpm, 1), "achieved_GBs": round(achieved, 1),
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "K": nl["K"], "mean_list": nl["mean_list"],
+            "rollbacks": nl["rollbacks"], "skin": round(nl["skin"], 4),
+            "autotune_ms_per_step_by_K": {str(k_): round(v_, 5) for k_, v_ in tune_ms.items()},
+            "init_s": round(t_init, 2)}
+
+
 def run_learned(kg, steps, warmup, stream, log_sweeps=20, log_attempts=2000, train_steps=300):
     """Learned vs uniform proposal on the 200 x 1000 melt at kappa = 2.5 (mixed precision)."""
     import torch
@@ -233,6 +279,11 @@ def main():
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run plain copies of known size (for PMC byte counters)")
+    ap.add_argument("--size-sweep", default="",
+                    help="comma-separated monomer counts (e.g. 1000000,4000000,16000000): also time the "
+                         "step kernel on single melts of these sizes (N = 1000), mixed path, MD only")
+    ap.add_argument("--size-sweep-steps", type=int, default=500)
+    ap.add_argument("--no-main", action="store_true", help="skip the workload runs (with --size-sweep)")
     args = ap.parse_args()
     if args.profile_steps < 0:
         args.profile_steps = args.steps
@@ -247,6 +298,15 @@ def main():
     stream = torch.cuda.Stream()
     if args.copy_calibration:
         copy_calibration()
+    sweep = []
+    for nm_ in [int(v) for v in args.size_sweep.split(",") if v.strip()]:
+        print(f"[bench] size sweep: {nm_} monomers, {args.size_sweep_steps} MD steps", file=sys.stderr, flush=True)
+        sweep.append(run_size(kg, nm_, args.size_sweep_steps, stream, kg.PREC_MIXED))
+        print(f"[bench] size sweep {nm_}: {sweep[-1]['avg_launch_ms'] * 1e3:.1f} us per step launch, "
+              f"frac {sweep[-1]['frac']}", file=sys.stderr, flush=True)
+    if args.no_main:
+        print(json.dumps({"size_sweep": sweep}), flush=True)
+        return
     print(f"[bench] mixed path: {args.warmup} warm-up + {args.steps} timed steps", file=sys.stderr, flush=True)
     mixed = run_gpu(kg, kg.PREC_MIXED, args.steps, args.warmup, stream, args.profile_steps)
     print(f"[bench] mixed done: {mixed['monomer_steps_per_s']:.3e} monomer-steps/s", file=sys.stderr, flush=True)
@@ -310,6 +370,8 @@ def main():
         line["speedup_vs_fp64_path"] = mixed["monomer_steps_per_s"] / fp64["monomer_steps_per_s"]
     if learned:
         line["learned_form"] = learned
+    if sweep:
+        line["size_sweep"] = sweep
     line["roofline"] = roof
     line["cpu_baseline"] = cpu
     print(json.dumps(line), flush=True)

@@ -72,7 +72,9 @@ typedef struct {
   uint32_t test_flags;    /* KGDB_TF_*                                                         */
   double r_cell;          /* cell edge of the exported cell list and the warm-up (<= 0: r_c)   */
   int32_t nl_every;       /* neighbour-list rebuild interval K in steps (<= 0: 5)               */
-  double nl_skin;         /* list skin (<= 0: 13.2 K dt sqrt(T), twice a 6.6-sigma drift)       */
+  double nl_skin;         /* list skin (<= 0: 2 u K dt sqrt(T), twice the drift at speed u sqrt(T);
+                             u = 6.6 up to 200,000 monomers in the batch, growing so that
+                             nm u exp(-u^2/2) stays fixed beyond: 7.25 at 16M)                   */
 } kgdb_params;
 
 /* statistics of one melt's double-bridging sweep */

@@ -164,14 +164,26 @@ static int check_params(const kgdb_params& p) {
 static const int NL_KS[3] = {1, 2, 5};
 static const int NL_CLEAN_PASSES = 4;  // clean passes before a lowered rebuild interval is raised again
 
-static double nl_skin_for(const kgdb_params& p, int K) {
-  // twice a 6.6-sigma ballistic drift over K steps at temperature T, unless given
-  return p.nl_skin > 0 ? p.nl_skin : 13.2 * K * p.dt * std::sqrt(p.T > 0 ? p.T : 1.0);
+// Speed, in units of sqrt(T), that the fastest of nm monomers exceeds about as rarely as the
+// fastest of 200,000 exceeds 6.6: the Maxwell tail gives P(|v| > u) ~ u exp(-u^2 / 2), so
+// nm P stays fixed when u^2 / 2 - ln u grows by ln(nm / 200000).  Never below 6.6.
+static double nl_skin_sigmas(double nm) {
+  const double u0 = 6.6, target = 0.5 * u0 * u0 - std::log(u0) + std::log(std::max(nm, 1.0) / 200000.0);
+  double u = u0;
+  if (target <= 0.5 * u0 * u0 - std::log(u0)) return u0;
+  for (int it = 0; it < 50; ++it) u -= (0.5 * u * u - std::log(u) - target) / (u - 1.0 / u);  // Newton
+  return u;
 }
 
-static void set_list_geometry(MeltDesc& d, const kgdb_params& p, int K) {
+static double nl_skin_for(const kgdb_params& p, int K, double nm_total) {
+  // twice the ballistic drift over K steps of a monomer at that speed (batch-wide: a stale list
+  // anywhere redoes the whole pass), unless given
+  return p.nl_skin > 0 ? p.nl_skin : 2.0 * nl_skin_sigmas(nm_total) * K * p.dt * std::sqrt(p.T > 0 ? p.T : 1.0);
+}
+
+static void set_list_geometry(MeltDesc& d, const kgdb_params& p, int K, double nm_total) {
   const double rc = std::pow(2.0, 1.0 / 6.0);
-  const double skin = nl_skin_for(p, K);
+  const double skin = nl_skin_for(p, K, nm_total);
   const double rl = rc + skin;
   d.ncl = std::max(1, (int)std::floor(d.L / rl));
   d.cinvl = (double)d.ncl / d.L;
@@ -222,7 +234,7 @@ static MeltDesc make_desc(const kgdb_params& p) {
   d.inv_mnb = 1.0 / ((double)d.M * (double)(d.N - 1));
   d.inv_nb = 1.0 / (double)(d.N - 1);
   d.lang_amp = std::sqrt(2.0 * p.gamma * p.T / p.dt);
-  set_list_geometry(d, p, p.nl_every > 0 ? p.nl_every : 5);
+  set_list_geometry(d, p, p.nl_every > 0 ? p.nl_every : 5, (double)d.Nm);
   d.seed = p.seed;
   d.melt_id = (uint64_t)(int64_t)p.melt_id;
   d.test_flags = p.test_flags;
@@ -738,7 +750,7 @@ static int init_impl(const kgdb_params* params, int32_t count, void* stream, kgd
       int64_t off = 0;
       usable[q] = true;
       for (int k = 0; k < count; ++k) {
-        set_list_geometry(b->Dk[q][k], params[k], NL_KS[q]);
+        set_list_geometry(b->Dk[q][k], params[k], NL_KS[q], (double)NP);
         b->Dk[q][k].celll_off = (int)off;
         off += (int64_t)b->Dk[q][k].ncl * b->Dk[q][k].ncl * b->Dk[q][k].ncl;
         if (b->Dk[q][k].ncl < 3 || b->Dk[q][k].ncl > 1023) usable[q] = false;
@@ -1450,7 +1462,7 @@ int kgdb_nl_info(kgdb_batch* b, double out[4]) {
   double sum = 0;
   for (int v : len) sum += v;
   out[0] = b->nl_k;
-  out[1] = nl_skin_for(b->P[0], b->nl_k);
+  out[1] = nl_skin_for(b->P[0], b->nl_k, (double)b->NP);
   out[2] = sum / b->NP;
   out[3] = (double)b->nl_rollbacks;
   return 0;
