@@ -124,7 +124,9 @@ def run_size(kg, monomers, md_steps, stream, precision):
     torch.cuda.synchronize()
     t_init = time.perf_counter() - t0
     nm, _ = b.sizes()
-    K, tune_ms = b.autotune(0, reps=10)
+    for _ in range(2):  # past the first calls after the warm-up, whose list builds run slower
+        b.md_steps(MD_PER_STEP)
+    K, tune_ms = b.autotune(0, reps=20)
     b.md_steps(MD_PER_STEP)
     torch.cuda.synchronize()
     chunks = max(1, md_steps // MD_PER_STEP)  # calls of MD_PER_STEP steps, as in a bench step
@@ -247,8 +249,9 @@ def copy_calibration(mib=256, reps=5):
     print(f"[bench] copy calibration: {reps} copies of {mib} MiB", file=sys.stderr, flush=True)
 
 
-def cpu_baseline(md_steps=15, db_attempts=8):
-    """The FP64 CPU oracle (single thread) on a bounded sample of the same workload."""
+def cpu_baseline(md_steps=15, db_attempts=8, stream=None):
+    """The FP64 CPU oracle (single thread) on a bounded sample of the same workload; then, from
+    the state it reached, the GPU path's error against it per result (untimed)."""
     from oracle import oracle as o
     m = o.Melt(**dict(WORKLOAD, warmup_steps=60))  # untimed setup: a shortened warm-up
     t0 = time.perf_counter()
@@ -261,10 +264,50 @@ def cpu_baseline(md_steps=15, db_attempts=8):
     nm = WORKLOAD["M"] * WORKLOAD["N"]
     K = round(1e-3 * nm * MD_PER_STEP * WORKLOAD["dt"])
     chunk = MD_PER_STEP * t_step + K * t_att
-    return {"value": nm * MD_PER_STEP / chunk, "unit": "monomer-timesteps/s", "cores": 1, "kind": "oracle",
-            "sample": f"200k-monomer workload melt: {md_steps} MD steps ({t_step:.3f} s each) and "
-                      f"{db_attempts} DB attempts ({t_att:.3f} s each), scaled to one bench step of "
-                      f"{MD_PER_STEP} MD steps + {K} attempts; single-threaded FP64 C oracle"}
+    out = {"value": nm * MD_PER_STEP / chunk, "unit": "monomer-timesteps/s", "cores": 1, "kind": "oracle",
+           "sample": f"200k-monomer workload melt: {md_steps} MD steps ({t_step:.3f} s each) and "
+                     f"{db_attempts} DB attempts ({t_att:.3f} s each), scaled to one bench step of "
+                     f"{MD_PER_STEP} MD steps + {K} attempts; single-threaded FP64 C oracle"}
+    out["gpu_error_vs_oracle"] = oracle_errors(m, stream)
+    return out
+
+
+def oracle_errors(m, stream, attempts=20):
+    """The GPU path against the oracle melt `m` (200k-monomer workload), both from its current
+    state: a double-bridging sweep (decisions and topology must be identical), forces relative
+    to S_i (the sum of the magnitudes of the contributions on bead i), one MD step, energies
+    and R^2(n)/n."""
+    import numpy as np
+    import paper_2109_11001_amd as kg
+    st = m.get_state()
+    so = m.db_sweep(attempts)
+    Fo, So, _ = m.forces()
+    eo = m.energy()
+    r2o, _, _ = m.observables()
+    m.md_steps(1)
+    xo = m.get_state()["x"]
+    L = m.L
+    res = {"workload": "200k-monomer workload melt after the oracle's timed sample",
+           "db_attempts": attempts, "db_accepted": so["accepted"]}
+    for name, prec in (("fp64", kg.PREC_FP64), ("mixed", kg.PREC_MIXED)):
+        g = kg.Batch([dict(WORKLOAD, warmup_steps=0, precision=prec)], stream=stream)
+        g.set_state(0, x=st["x"], v=st["v"], fl=st["fl"], chains=st["chains"], counters=st["counters"])
+        sg = g.db_sweep(attempts)[0]
+        same = (sg["accepted"] == so["accepted"] and sg["attempts"] == so["attempts"]
+                and np.array_equal(g.get_state()["chains"], m.get_state()["chains"]))
+        Fg, _, _ = g.forces()
+        eg = g.energy()
+        r2g, _, _ = g.observables()
+        g.md_steps(1)
+        d = g.get_state()["x"] - xo
+        d -= L * np.rint(d / L)
+        g.close()
+        res[name] = {"db_sweep_identical": bool(same),
+                     "force_max_err_over_S": float(np.max(np.sqrt(((Fg - Fo) ** 2).sum(0)) / So)),
+                     "x_after_1_step_max_abs": float(np.max(np.abs(d))),
+                     "energy_max_rel": float(np.max(np.abs(eg - eo) / np.maximum(np.abs(eo), 1e-300))),
+                     "r2n_max_rel": float(np.max(np.abs(r2g - r2o) / r2o))}
+    return res
 
 
 def main():
@@ -323,7 +366,7 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
-        cpu = cpu_baseline()
+        cpu = cpu_baseline(stream=stream)
 
     roof = None
     if "force_kernel_ms" in mixed:
