@@ -155,14 +155,10 @@ def run_size(kg, monomers, md_steps, stream, precision):
             "init_s": round(t_init, 2)}
 
 
-def run_learned(kg, steps, warmup, stream, log_sweeps=20, log_attempts=2000, train_steps=300):
-    """Learned vs uniform proposal on the 200 x 1000 melt at kappa = 2.5 (mixed precision)."""
+def train_proposal(kg, b, stream, log_sweeps, log_attempts, train_steps):
+    """Log `log_sweeps` uniform sweeps of `log_attempts` attempts (100 MD steps before each) on
+    melt 0 of batch `b`, then train a network on them on the GPU (full-batch Adam)."""
     import torch
-    params = dict(WORKLOAD, precision=kg.PREC_MIXED, kappa=LEARNED_KAPPA)
-    # set-up (untimed): logged uniform sweeps with MD in between, then training on the GPU
-    t0 = time.perf_counter()
-    b = kg.Batch([params], stream=stream)
-    b.autotune(0, reps=20)
     feats, labs = [], []
     for _ in range(log_sweeps):
         b.md_steps(MD_PER_STEP)
@@ -179,6 +175,18 @@ def run_learned(kg, steps, warmup, stream, log_sweeps=20, log_attempts=2000, tra
             loss = tr.step(x, y)
         last = float(loss.cpu()[0])
     torch.cuda.synchronize()
+    return tr, first, last, y
+
+
+def run_learned(kg, steps, warmup, stream, log_sweeps=20, log_attempts=2000, train_steps=300):
+    """Learned vs uniform proposal on the 200 x 1000 melt at kappa = 2.5 (mixed precision)."""
+    import torch
+    params = dict(WORKLOAD, precision=kg.PREC_MIXED, kappa=LEARNED_KAPPA)
+    # set-up (untimed): logged uniform sweeps with MD in between, then training on the GPU
+    t0 = time.perf_counter()
+    b = kg.Batch([params], stream=stream)
+    b.autotune(0, reps=20)
+    tr, first, last, y = train_proposal(kg, b, stream, log_sweeps, log_attempts, train_steps)
     setup_s = time.perf_counter() - t0
     state = b.get_state()
     b.close()
@@ -213,6 +221,106 @@ def run_learned(kg, steps, warmup, stream, log_sweeps=20, log_attempts=2000, tra
                      "db_s": round(t_db, 4), "attempts": att}
         g.close()
     out["accepted_per_s_gain"] = out["learned"]["db_accepted_per_s"] / max(out["uniform"]["db_accepted_per_s"], 1e-30)
+    return out
+
+
+EQ_SYSTEM = dict(M=2000, N=25, kappa=2.0)  # 50,000 monomers: short chains equilibrate within a run
+
+
+def _steps_to_within(times, samples, ref, tol):
+    """First sample time from which the mean of the samples over the second half of the elapsed
+    run, (t/2, t], stays within `tol` (relative) of `ref` for every n; None if it never does."""
+    import numpy as np
+    t = np.asarray(times, float)
+    S = np.asarray(samples)
+    dev = []
+    for k in range(len(t)):
+        w = (t > t[k] / 2) & (t <= t[k])
+        dev.append(float(np.max(np.abs(S[w].mean(0) - ref) / ref)))
+    bad = [k for k, d in enumerate(dev) if d > tol]
+    first = (bad[-1] + 1) if bad else 0
+    return (None if first >= len(t) else first), dev
+
+
+def run_equilibration(kg, stream, steps, ref_steps, every=1000, tol=0.02, batch_melts=4):
+    """Time to equilibrium of R^2(n)/n for each form, from one shared warmed-up start.
+
+    The reference is the plain FP64 path with the uniform proposal, its R^2(n)/n averaged over
+    the second half of a run of `ref_steps` steps.  Each form (plain FP64, mixed precision, a
+    batch of `batch_melts` melts with their own random streams, the learned proposal) then runs
+    `steps` steps from the start, one sweep at the paper's rate every 100 steps, R^2(n)/n read
+    every `every` steps; a form has equilibrated once the mean over the second half of its run
+    so far stays within `tol` of the reference for every n (the reference run itself counts as
+    the FP64 form).  Wall-clock times include the sweeps and the readings."""
+    import numpy as np
+    import torch
+    base = dict(WORKLOAD, **EQ_SYSTEM)
+    g = kg.Batch([dict(base, precision=kg.PREC_FP64)], stream=stream)
+    S0 = g.get_state()
+    g.close()
+
+    def start(form):
+        melts = batch_melts if form == "batched" else 1
+        prec = kg.PREC_FP64 if form == "fp64" else kg.PREC_MIXED
+        prop = kg.PROPOSAL_LEARNED if form == "learned" else kg.PROPOSAL_UNIFORM
+        b = kg.Batch([dict(base, warmup_steps=0, precision=prec, proposal=prop, melt_id=i) for i in range(melts)],
+                     stream=stream)
+        for i in range(melts):
+            b.set_state(i, x=S0["x"], v=S0["v"], fl=S0["fl"], chains=S0["chains"], counters=S0["counters"])
+        return b, melts
+
+    def run(form, nsteps, net=None):
+        b, melts = start(form)
+        if net is not None:
+            b.set_proposal_net(net, 0.1)
+        b.autotune(0, reps=20)
+        times, walls, samples = [], [], []
+        acc = att = 0
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s = 0
+        while s < nsteps:
+            for _ in range(every // MD_PER_STEP):
+                b.md_steps(MD_PER_STEP)
+                for st in b.db_sweep(-1):
+                    acc += st["accepted"]
+                    att += st["attempts"] - st["no_candidate"]
+            s += every
+            samples.append(np.mean([b.observables(i)[0] for i in range(melts)], axis=0))
+            times.append(s)
+            walls.append(time.perf_counter() - t0)
+        b.close()
+        return dict(times=times, walls=walls, samples=samples, accepted=acc, attempts=att, melts=melts)
+
+    out = {"system": f"{EQ_SYSTEM['M']} chains x {EQ_SYSTEM['N']} beads, kappa {EQ_SYSTEM['kappa']}, n 2, "
+                     "rho 0.85, dt 0.01, gamma 1", "tolerance": tol, "reading_every_steps": every,
+           "forms": {}}
+    runs = {"fp64": run("fp64", ref_steps)}
+    r = runs["fp64"]
+    half = np.asarray(r["times"]) > ref_steps / 2
+    ref = np.asarray(r["samples"])[half].mean(0)
+    out["reference"] = {"steps": ref_steps, "r2n_first": float(ref[0]), "r2n_last": float(ref[-1]),
+                        "r2n_max": float(ref.max())}
+    # learned proposal: a network trained on logged uniform sweeps of a copy of the start
+    b, _ = start("fp64")
+    t0 = time.perf_counter()
+    tr, first, last, y = train_proposal(kg, b, stream, 10, 2000, 300)
+    out["learned_training"] = {"records": int(len(y)), "loss_first": first, "loss_last": last,
+                               "setup_s": round(time.perf_counter() - t0, 2)}
+    b.close()
+    runs["mixed"] = run("mixed", steps)
+    runs["batched"] = run("batched", steps)
+    runs["learned"] = run("learned", steps, net=tr.params)
+    for form, r in runs.items():
+        k, dev = _steps_to_within(r["times"], r["samples"], ref, tol)
+        out["forms"][form] = {
+            "melts": r["melts"], "steps": r["times"][-1], "wall_s": round(r["walls"][-1], 3),
+            "us_per_md_step": round(1e6 * r["walls"][-1] / r["times"][-1], 2),
+            "steps_to_tol": r["times"][k] if k is not None else None,
+            "tau_to_tol": r["times"][k] * WORKLOAD["dt"] if k is not None else None,
+            "wall_s_to_tol": round(r["walls"][k], 3) if k is not None else None,
+            "max_dev_end": round(dev[-1], 5), "max_dev_start": round(dev[0], 4),
+            "accepted": r["accepted"], "accept_rate": r["accepted"] / max(r["attempts"], 1)}
     return out
 
 
@@ -326,7 +434,11 @@ def main():
                     help="comma-separated monomer counts (e.g. 1000000,4000000,16000000): also time the "
                          "step kernel on single melts of these sizes (N = 1000), mixed path, MD only")
     ap.add_argument("--size-sweep-steps", type=int, default=500)
-    ap.add_argument("--no-main", action="store_true", help="skip the workload runs (with --size-sweep)")
+    ap.add_argument("--no-main", action="store_true", help="skip the workload runs (with --size-sweep or --equilibration)")
+    ap.add_argument("--equilibration", type=int, default=0, metavar="STEPS",
+                    help="time to equilibrium of R^2(n)/n for each form on a 2000 x 25 melt, STEPS steps each")
+    ap.add_argument("--equilibration-ref", type=int, default=0, metavar="STEPS",
+                    help="length of the plain FP64 reference run (default: 2 x --equilibration)")
     args = ap.parse_args()
     if args.profile_steps < 0:
         args.profile_steps = args.steps
@@ -347,8 +459,13 @@ def main():
         sweep.append(run_size(kg, nm_, args.size_sweep_steps, stream, kg.PREC_MIXED))
         print(f"[bench] size sweep {nm_}: {sweep[-1]['avg_launch_ms'] * 1e3:.1f} us per step launch, "
               f"frac {sweep[-1]['frac']}", file=sys.stderr, flush=True)
+    eq = None
+    if args.equilibration > 0:
+        print(f"[bench] equilibration: {args.equilibration} steps per form", file=sys.stderr, flush=True)
+        eq = run_equilibration(kg, stream, args.equilibration, args.equilibration_ref or 2 * args.equilibration)
+        print("[bench] equilibration done", file=sys.stderr, flush=True)
     if args.no_main:
-        print(json.dumps({"size_sweep": sweep}), flush=True)
+        print(json.dumps({"size_sweep": sweep, "equilibration": eq}), flush=True)
         return
     print(f"[bench] mixed path: {args.warmup} warm-up + {args.steps} timed steps", file=sys.stderr, flush=True)
     mixed = run_gpu(kg, kg.PREC_MIXED, args.steps, args.warmup, stream, args.profile_steps)
@@ -415,6 +532,8 @@ def main():
         line["learned_form"] = learned
     if sweep:
         line["size_sweep"] = sweep
+    if eq:
+        line["equilibration"] = eq
     line["roofline"] = roof
     line["cpu_baseline"] = cpu
     print(json.dumps(line), flush=True)
