@@ -150,6 +150,36 @@ def test_md_steps_full_size_c1():
         gm.close()
 
 
+def test_md_steps_large_batch():
+    # five copies of the warmed 200k-monomer workload melt in one batch of 1M monomers, each
+    # with its own random stream (melt_id); the list skin follows the batch's monomer count
+    om = o.Melt(M=200, N=1000, kappa=2.0, seed=1, warmup_steps=100)
+    st = om.get_state()
+    nb = 5
+    base = dict(M=200, N=1000, kappa=2.0, seed=1, warmup_steps=0, precision=kg.PREC_FP64)
+    gm = kg.Batch([dict(base, melt_id=i) for i in range(nb)])
+    for i in range(nb):
+        gm.set_state(i, x=st["x"], v=st["v"], fl=st["fl"], chains=st["chains"], counters=st["counters"])
+    # speed u (units of sqrt(T)) exceeded by the fastest of nm monomers as rarely as 6.6 by the
+    # fastest of 200,000: u^2/2 - ln u grows by ln(nm / 200000); skin = twice the drift over K
+    target = 0.5 * 6.6 ** 2 - math.log(6.6) + math.log(nb * 200000 / 200000)
+    lo, hi = 6.6, 10.0
+    for _ in range(100):
+        mid = 0.5 * (lo + hi)
+        lo, hi = (mid, hi) if 0.5 * mid * mid - math.log(mid) < target else (lo, mid)
+    info = gm.nl_info()
+    assert abs(info["skin"] - 2.0 * lo * info["K"] * 0.01) < 1e-9, info
+    gm.md_steps(2)
+    for i in range(nb):
+        oi = o.Melt(M=200, N=1000, kappa=2.0, seed=1, melt_id=i, warmup_steps=0)
+        oi.set_state(x=st["x"], v=st["v"], fl=st["fl"], chains=st["chains"], counters=st["counters"])
+        oi.md_steps(2)
+        so, sg = oi.get_state(), gm.get_state(i)
+        assert np.max(np.abs(mi_diff(so["x"], sg["x"], om.L))) < 1e-11, i
+        assert np.max(np.abs(so["v"] - sg["v"])) < 1e-9, i
+    gm.close()
+
+
 def test_stale_lists_roll_back():
     # a skin far too thin for 5-step rebuilds: the runtime must detect it, redo the steps
     # with more frequent rebuilds, and still match the oracle
