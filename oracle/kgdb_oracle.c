@@ -573,6 +573,21 @@ int kgdbref_get_state(melt_t *m, double *x, double *v, double *fc, double *fl, i
   if (counters) { counters[0] = m->step; counters[1] = m->sweep; counters[2] = m->last_sweep_step; counters[3] = (uint64_t)m->fc_valid; }
   return OR_OK;
 }
+/* The stages of the protocol of Sec. II.B change the exponent n of Eqs. 5-6 and, with it, the
+   FENE constant of Eq. 9 (a literal k when k_fene > 0).  The conservative forces of the new
+   potential are computed before the next kick. */
+int kgdbref_set_potential(melt_t *m, double n_exp, double k_fene) {
+  if (!(n_exp > 0) || n_exp == 6.0) {
+    set_err("n must be > 0 and != 6");
+    return OR_E_PARAM;
+  }
+  m->p.n_exp = n_exp;
+  m->p.k_fene = k_fene;
+  m->kn = k_fene > 0 ? k_fene : kgdbref_kn(n_exp, 0.960897, m->p.R0);
+  m->fc_valid = 0;
+  return OR_OK;
+}
+
 /* chains must be a permutation of ids with every chain of length N; positions are wrapped */
 int kgdbref_set_state(melt_t *m, const double *x, const double *v, const double *fl,
                       const int32_t *chains, const uint64_t *counters) {

@@ -99,6 +99,7 @@ def lib():
         L.kgdbref_set_state.argtypes = [P, P, P, P, P, P]
         L.kgdbref_forces.argtypes = [P, C.c_int32, P, P, P]
         L.kgdbref_md_steps.argtypes = [P, C.c_int64]
+        L.kgdbref_set_potential.argtypes = [P, C.c_double, C.c_double]
         L.kgdbref_cell_list.argtypes = [P, C.c_double, C.POINTER(C.c_int32), P, P, C.c_int64]
         L.kgdbref_candidates.argtypes = [P, C.c_int32, P, C.c_int64, C.POINTER(C.c_int64)]
         L.kgdbref_db_sweep.argtypes = [P, C.c_int64, C.c_int32, C.POINTER(Stats)]
@@ -207,6 +208,9 @@ class Melt:
 
     def md_steps(self, n):
         _check(lib().kgdbref_md_steps(self.h, n))
+
+    def set_potential(self, n_exp, k_fene=0.0):
+        _check(lib().kgdbref_set_potential(self.h, float(n_exp), float(k_fene)))
 
     def cell_list(self, rcell=0.0):
         nc = C.c_int32()
