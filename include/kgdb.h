@@ -118,6 +118,42 @@ int kgdb_md_steps(kgdb_batch* b, int64_t nsteps, int32_t use_graph);
    untouched; the chain tables change.  stats[k] receives melt k's statistics (may be NULL). */
 int kgdb_db_sweep(kgdb_batch* b, int64_t n_attempts, kgdb_db_stats* stats);
 
+/* ---- the n-ramp protocol (Sec. II.B) ---- */
+
+/* Set the exponent n of the pair potential (Eqs. 5-6) of melt `melt` (-1: every melt) and its
+   FENE constant (k_fene <= 0: k_n of Eq. 9 for this n; > 0: that value).  Positions,
+   velocities, topology and neighbour lists are kept; the conservative forces are recomputed
+   before the next kick.  Waits for the batch's pending work.  KGDB_E_PARAM for n <= 0 or
+   n = 6 (Eq. 5 is singular) or a bad melt index. */
+int kgdb_set_potential(kgdb_batch* b, int32_t melt, double n_exp, double k_fene);
+
+/* Stage plan of the protocol for chains of N beads at stiffness kappa (host only, no device
+   work): stage i runs n = n_values[i], the set of Eq. 11 in increasing order, for steps[i]
+   timesteps of dt (round(tau_i / dt)).  The total is tau_eq of Eq. 18, from tau_fix of
+   Eq. 16 (prefactor f, e.g. 46.3354, and the fit a = 1.6, b = 0.77 of Eq. 15) and
+   tau_e = N_e(kappa)^2 l_K(kappa)/l_0 (the simplified Eq. 17, N_e = 77 exp(-kappa/1.1) + 9.4,
+   l_K from Eq. 12).  kappa < 2.5: the last 2 tau_e at n = 12 and the rest over the other
+   eleven n in proportion to n^(-1/2) (Eq. 19); kappa >= 2.5: all twelve in proportion to
+   n^(-1/2) (Eq. 20).  n_values and steps hold 12 entries; taus (may be NULL) receives
+   {tau_fix, tau_e, tau_eq, scheme 1 or 2}.  Returns the number of stages (12), or
+   KGDB_E_PARAM for kappa < 0, N < 2, dt <= 0 or f <= 0 (no message is set). */
+int kgdb_protocol_schedule(double kappa, int32_t N, double dt, double f, double* n_values, int64_t* steps,
+                           double* taus);
+
+typedef struct {
+  double n_exp;                                   /* exponent of the stage                   */
+  int64_t steps, attempts, no_candidate, accepted; /* MD steps run; sweep totals over the melts */
+  double wall_ms;                                  /* host wall-clock of the stage             */
+} kgdb_stage_stats;
+
+/* Run the stages in order on every melt: kgdb_set_potential(n_values[i], Eq. 9), then
+   steps[i] MD steps in calls of sweep_every steps, each followed by one double-bridging sweep
+   at the attempt rate (db_rate, Sec. II.B); sweep_every <= 0 runs the stage without sweeps
+   (core softening only).  out (may be NULL) holds nstages entries.  Stops at the first error
+   and returns it (the stages before it have run). */
+int kgdb_run_protocol(kgdb_batch* b, const double* n_values, const int64_t* steps, int32_t nstages,
+                      int64_t sweep_every, kgdb_stage_stats* out);
+
 /* R^2(n)/n for n = 1..N-1 (r2_over_n has N-1 entries) of melt `melt`, its mean bond length,
    and l_K from the least-squares fit of Eq. 14 over ceil(N/4) <= n <= floor(N/2) with l0 the
    mean bond length.  Any output pointer may be NULL. */

@@ -9,7 +9,7 @@ import ctypes as C
 import numpy as np
 
 from ._lib import (MLP_NPARAM, PREC_FP64, PREC_MIXED, PROPOSAL_LEARNED, PROPOSAL_LITERAL, PROPOSAL_UNIFORM,
-                   TF_NL_GLOBAL, TF_NOFORCE, TF_PHANTOM, DbStats, KgdbError, Params, check, load, ptr)
+                   TF_NL_GLOBAL, TF_NOFORCE, TF_PHANTOM, DbStats, KgdbError, Params, StageStats, check, load, ptr)
 
 NN_IN = 25
 
@@ -21,6 +21,21 @@ DEFAULTS = dict(M=20, N=50, rho=0.85, kappa=1.5, n_exp=2.0, k_fene=0.0, R0=1.5, 
 
 # the n values of the paper's schedule, Eq. (11)
 XI = (2.0, 3.0, 4.0, 5.0, 5.75, 6.5, 7.0, 8.0, 9.0, 10.0, 11.0, 12.0)
+# the prefactor of Eq. (16) that brings the kappa = 5.5, N = 400 run to 10^8 steps of 0.008 tau
+F0 = 46.3354
+
+
+def protocol_schedule(kappa, N, dt=0.01, f=F0):
+    """Stage plan of the n-ramp protocol (Sec. II.B, Eqs. 11-12, 16-20), from the library:
+    dict(n=[12 exponents], steps=[12 step counts], tau_fix, tau_e, tau_eq, scheme)."""
+    n = np.zeros(12)
+    steps = np.zeros(12, np.int64)
+    taus = np.zeros(4)
+    rc = load().kgdb_protocol_schedule(float(kappa), int(N), float(dt), float(f), ptr(n), ptr(steps), ptr(taus))
+    if rc < 0:
+        raise KgdbError(rc, "invalid schedule arguments")
+    return dict(n=n[:rc].tolist(), steps=steps[:rc].tolist(), tau_fix=taus[0], tau_e=taus[1], tau_eq=taus[2],
+                scheme=int(taus[3]))
 
 
 def make_params(**kw):
@@ -163,6 +178,22 @@ class Batch:
         a, b = C.c_int64(), C.c_int64()
         check(load().kgdb_batch_sizes(self._h, C.byref(a), C.byref(b)))
         return a.value, b.value
+
+    # ---- n-ramp protocol
+    def set_potential(self, n_exp, k_fene=0.0, melt=-1):
+        """Exponent n of Eqs. 5-6 and FENE constant (<= 0: Eq. 9) of one melt, or of all (-1)."""
+        check(load().kgdb_set_potential(self._h, int(melt), float(n_exp), float(k_fene)))
+
+    def run_protocol(self, n_values, steps, sweep_every=100):
+        """Run the stages (n_values[i] for steps[i] MD steps, a sweep every sweep_every steps;
+        <= 0: no sweeps) in the library; returns one statistics dict per stage."""
+        n = np.ascontiguousarray(n_values, np.float64)
+        st = np.ascontiguousarray(steps, np.int64)
+        if n.shape != st.shape:
+            raise ValueError("n_values and steps differ in length")
+        out = (StageStats * max(len(n), 1))()
+        check(load().kgdb_run_protocol(self._h, ptr(n), ptr(st), len(n), int(sweep_every), out))
+        return [out[i].as_dict() for i in range(len(n))]
 
     # ---- learned proposal
     def set_proposal_net(self, params, mix):

@@ -49,6 +49,16 @@ class DbStats(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class StageStats(C.Structure):
+    _fields_ = [
+        ("n_exp", C.c_double), ("steps", C.c_int64), ("attempts", C.c_int64), ("no_candidate", C.c_int64),
+        ("accepted", C.c_int64), ("wall_ms", C.c_double),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 # every symbol include/kgdb.h declares
 EXPORTS = [
     "kgdb_init_batch", "kgdb_init_melt", "kgdb_destroy", "kgdb_last_error", "kgdb_batch_size",
@@ -58,6 +68,7 @@ EXPORTS = [
     "kgdb_melt_geometry", "kgdb_batch_sizes", "kgdb_autotune", "kgdb_nl_info",
     "kgdb_mlp_nparam", "kgdb_set_proposal_net", "kgdb_db_sweep_log", "kgdb_features", "kgdb_candidate_logits",
     "kgdb_mlp_workspace_bytes", "kgdb_mlp_forward", "kgdb_mlp_grad", "kgdb_mlp_adam", "kgdb_mlp_train_step",
+    "kgdb_set_potential", "kgdb_protocol_schedule", "kgdb_run_protocol",
 ]
 MLP_NPARAM = 36481
 
@@ -110,6 +121,9 @@ def load():
     L.kgdb_mlp_grad.argtypes = [P, P, P, i64, P, P, P, i64, P]
     L.kgdb_mlp_adam.argtypes = [P, P, P, P, i64, dbl, dbl, dbl, dbl, P]
     L.kgdb_mlp_train_step.argtypes = [P, P, P, P, P, i64, i64, dbl, dbl, dbl, dbl, P, i64, P, P]
+    L.kgdb_set_potential.argtypes = [P, i32, dbl, dbl]
+    L.kgdb_protocol_schedule.argtypes = [dbl, i32, dbl, dbl, P, P, P]
+    L.kgdb_run_protocol.argtypes = [P, P, P, i32, i64, P]
     for f in EXPORTS:
         if f not in ("kgdb_destroy", "kgdb_last_error", "kgdb_batch_size"):
             getattr(L, f).restype = C.c_int

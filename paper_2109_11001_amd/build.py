@@ -24,6 +24,7 @@ SOURCES = {
     "kgdb_obs.hip": ["-ffp-contract=off"],
     "kgdb_api.hip": ["-ffp-contract=off"],
     "kgdb_mlp.hip": ["-ffp-contract=off"],
+    "kgdb_protocol.cpp": ["-ffp-contract=off"],
 }
 
 

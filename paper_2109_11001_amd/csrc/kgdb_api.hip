@@ -141,6 +141,19 @@ static double fene_kn(double n, double l0, double R0) {
   return num / ((n - 6.0) * R0 * R0 * l0 * l0);
 }
 
+// the constants of the pair potential MLJ^n (Eqs. 5-6) and of the FENE bond (Eq. 9, unless
+// k_fene > 0) for the exponent p.n_exp
+static void set_potential_desc(MeltDesc& d, const kgdb_params& p) {
+  const double n = p.n_exp;
+  d.n_exp = n;
+  d.pa = 6.0 * n * std::pow(2.0, n / 6.0) / (n - 6.0);
+  d.pb = 12.0 * n / (n - 6.0);
+  d.ua = 6.0 * std::pow(2.0, n / 6.0) / (n - 6.0);
+  d.ub = 2.0 * n / (n - 6.0);
+  d.n_half_int = (n == std::floor(n) && ((long)n % 2 == 0)) ? (int)(n / 2) : -1;
+  d.kfene = p.k_fene > 0 ? p.k_fene : fene_kn(n, 0.960897, p.R0);
+}
+
 static int check_params(const kgdb_params& p) {
   if (p.M < 1 || p.N < 2) return fail(KGDB_E_PARAM, "need M >= 1 and N >= 2");
   if (2 * p.N > 8 * 1024) return fail(KGDB_E_PARAM, "N > 4096 is not supported by the sweep kernel");
@@ -214,16 +227,9 @@ static MeltDesc make_desc(const kgdb_params& p) {
   d.h = d.L / d.nc;
   d.nc13 = std::max(1, (int)std::floor(d.L / p.db_rmax));
   d.cinv13 = (double)d.nc13 / d.L;
-  const double n = p.n_exp;
-  d.n_exp = n;
-  d.pa = 6.0 * n * std::pow(2.0, n / 6.0) / (n - 6.0);
-  d.pb = 12.0 * n / (n - 6.0);
-  d.ua = 6.0 * std::pow(2.0, n / 6.0) / (n - 6.0);
-  d.ub = 2.0 * n / (n - 6.0);
+  set_potential_desc(d, p);
   d.rc2 = rc * rc;
-  d.n_half_int = (n == std::floor(n) && ((long)n % 2 == 0)) ? (int)(n / 2) : -1;
   d.proposal = p.proposal;
-  d.kfene = p.k_fene > 0 ? p.k_fene : fene_kn(n, 0.960897, p.R0);
   d.R0sq = p.R0 * p.R0;
   d.amin = p.fene_floor > 0 ? p.fene_floor : 0.0;
   d.kappa = p.kappa;
@@ -915,6 +921,31 @@ int32_t kgdb_batch_size(const kgdb_batch* b) { return b ? b->nm : 0; }
 int kgdb_md_steps(kgdb_batch* b, int64_t nsteps, int32_t use_graph) {
   if (!b || nsteps < 0) return fail(KGDB_E_PARAM, "bad handle or step count");
   return run_steps(b, nsteps, use_graph != 0);
+}
+
+int kgdb_set_potential(kgdb_batch* b, int32_t melt, double n_exp, double k_fene) {
+  if (!b || melt < -1 || melt >= b->nm) return fail(KGDB_E_PARAM, "bad handle or melt index");
+  if (!(n_exp > 0) || n_exp == 6.0) return fail(KGDB_E_PARAM, "n must be > 0 and != 6 (Eq. 5 is singular)");
+  // work in flight (either stream) reads the melt table being replaced
+  HIPCHK(hipStreamSynchronize(b->s));
+  if (b->s2) HIPCHK(hipStreamSynchronize(b->s2));
+  for (int k = 0; k < b->nm; ++k) {
+    if (melt >= 0 && k != melt) continue;
+    b->P[k].n_exp = n_exp;
+    b->P[k].k_fene = k_fene;
+    set_potential_desc(b->D[k], b->P[k]);
+    for (auto& Dq : b->Dk) set_potential_desc(Dq[k], b->P[k]);
+  }
+  HIPCHK(hipMemcpyAsync(b->d_md, b->D.data(), sizeof(MeltDesc) * b->nm, hipMemcpyHostToDevice, b->s));
+  // captured runs of steps hold the step kernel built for the old exponent
+  for (auto& ge : b->gexec)
+    if (ge) { HIPCHK(hipGraphExecDestroy(ge)); ge = nullptr; }
+  for (auto& a1 : b->ngexec)
+    for (auto& a2 : a1)
+      for (auto& ge : a2)
+        if (ge) { HIPCHK(hipGraphExecDestroy(ge)); ge = nullptr; }
+  b->fc_valid = false;
+  return 0;
 }
 
 static int check_melt(const kgdb_batch* b, int32_t melt) {
