@@ -17,6 +17,7 @@ trained on the GPU from logged uniform sweeps (untimed set-up), then the same be
 timed with the learned and with the uniform proposal from one shared state.
 """
 import hashlib
+import math
 import re
 import argparse
 import json
@@ -324,6 +325,44 @@ def run_equilibration(kg, stream, steps, ref_steps, every=1000, tol=0.02, batch_
     return out
 
 
+PAPER_SYSTEM = dict(M=1000, N=400, dt=0.008)  # the paper's melts: 1000 chains of 400 beads, dt = tau / 125
+
+
+def run_protocol_bench(kg, stream, kappa, steps_per_stage, sweep_every=100):
+    """The n-ramp protocol (Sec. II.B) on the paper's own melt size at stiffness kappa: every
+    stage of the plan (Eqs. 11, 16-20) runs `steps_per_stage` steps with a sweep at the paper's
+    attempt rate every `sweep_every` steps, timed per stage; the full plan's wall-clock is
+    projected from those rates.  Also the swap success rate per exponent, beside the paper's
+    fit of it (Fig. 3 caption: a' exp(-b' kappa - d' n - e' n^2)), as a trend check."""
+    import torch
+    params = dict(WORKLOAD, **PAPER_SYSTEM, kappa=kappa, precision=kg.PREC_MIXED)
+    t0 = time.perf_counter()
+    b = kg.Batch([params], stream=stream)
+    b.md_steps(MD_PER_STEP)
+    b.autotune(0, reps=20)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    plan = kg.protocol_schedule(kappa, PAPER_SYSTEM["N"], dt=PAPER_SYSTEM["dt"])
+    st = b.run_protocol(plan["n"], [steps_per_stage] * len(plan["n"]), sweep_every=sweep_every)
+    nm, _ = b.sizes()
+    b.close()
+    stages, proj = [], 0.0
+    for i, s_ in enumerate(st):
+        ms = s_["wall_ms"] / max(s_["steps"], 1)
+        tried = s_["attempts"] - s_["no_candidate"]
+        n = plan["n"][i]
+        fit = 1.24 * math.exp(-0.77 * kappa - 0.24 * n - 0.015 * n * n)
+        stages.append({"n": n, "plan_steps": plan["steps"][i], "ms_per_step": round(ms, 5),
+                       "monomer_steps_per_s": nm / (ms * 1e-3), "accepted": s_["accepted"], "attempts": tried,
+                       "success_rate": s_["accepted"] / max(tried, 1), "paper_fit_success_rate": round(fit, 5)})
+        proj += plan["steps"][i] * ms * 1e-3
+    return {"system": f"{PAPER_SYSTEM['M']} chains x {PAPER_SYSTEM['N']} beads, kappa {kappa}, rho 0.85, "
+                      f"dt {PAPER_SYSTEM['dt']}, mixed precision", "monomers": nm,
+            "plan": {"steps_total": int(sum(plan["steps"])), "tau_eq": plan["tau_eq"], "scheme": plan["scheme"]},
+            "steps_per_stage_timed": steps_per_stage, "sweep_every": sweep_every, "setup_s": round(setup_s, 2),
+            "stages": stages, "projected_full_protocol_s": round(proj, 1)}
+
+
 def step_kernel_hash():
     """sha256 of the step kernel's source (its body in kgdb_nl.hip plus kgdb_dev.h)."""
     csrc = os.path.join(ROOT, "paper_2109_11001_amd", "csrc")
@@ -435,6 +474,10 @@ def main():
                          "step kernel on single melts of these sizes (N = 1000), mixed path, MD only")
     ap.add_argument("--size-sweep-steps", type=int, default=500)
     ap.add_argument("--no-main", action="store_true", help="skip the workload runs (with --size-sweep or --equilibration)")
+    ap.add_argument("--protocol", type=int, default=0, metavar="STEPS",
+                    help="time every stage of the n-ramp protocol for STEPS steps on the paper's 1000 x 400 "
+                         "melt and project the full run")
+    ap.add_argument("--protocol-kappa", default="2.0,5.5")
     ap.add_argument("--equilibration", type=int, default=0, metavar="STEPS",
                     help="time to equilibrium of R^2(n)/n for each form on a 2000 x 25 melt, STEPS steps each")
     ap.add_argument("--equilibration-ref", type=int, default=0, metavar="STEPS",
@@ -464,8 +507,14 @@ def main():
         print(f"[bench] equilibration: {args.equilibration} steps per form", file=sys.stderr, flush=True)
         eq = run_equilibration(kg, stream, args.equilibration, args.equilibration_ref or 2 * args.equilibration)
         print("[bench] equilibration done", file=sys.stderr, flush=True)
+    prot = []
+    for kap in [float(v) for v in args.protocol_kappa.split(",") if v.strip()] if args.protocol > 0 else []:
+        print(f"[bench] protocol: kappa {kap}, {args.protocol} steps per stage", file=sys.stderr, flush=True)
+        prot.append(run_protocol_bench(kg, stream, kap, args.protocol))
+        print(f"[bench] protocol kappa {kap}: projected {prot[-1]['projected_full_protocol_s']} s for "
+              f"{prot[-1]['plan']['steps_total']} steps", file=sys.stderr, flush=True)
     if args.no_main:
-        print(json.dumps({"size_sweep": sweep, "equilibration": eq}), flush=True)
+        print(json.dumps({"size_sweep": sweep, "equilibration": eq, "protocol": prot}), flush=True)
         return
     print(f"[bench] mixed path: {args.warmup} warm-up + {args.steps} timed steps", file=sys.stderr, flush=True)
     mixed = run_gpu(kg, kg.PREC_MIXED, args.steps, args.warmup, stream, args.profile_steps)
@@ -534,6 +583,8 @@ def main():
         line["size_sweep"] = sweep
     if eq:
         line["equilibration"] = eq
+    if prot:
+        line["protocol"] = prot
     line["roofline"] = roof
     line["cpu_baseline"] = cpu
     print(json.dumps(line), flush=True)
