@@ -163,6 +163,9 @@ typedef struct {
   int32_t melt_id;
   uint32_t test_flags;
   double r_cell;
+  int32_t init_mode;  /* 0: freely jointed random walks; 1: freely rotating chains (Sec. II.B) */
+  int32_t init_tries; /* states drawn at most (<= 0: 1000) */
+  double init_tol;    /* accepted relative l_K deviation (<= 0: 0.02) */
 } kgdbref_params;
 
 typedef struct {
@@ -181,6 +184,8 @@ typedef struct {
   uint64_t step, sweep;
   uint64_t last_sweep_step;
   int fc_valid;
+  int init_drawn;   /* initial states drawn */
+  double init_ellK; /* l_K fitted to the accepted freely rotating state */
   double fcap; /* pair-force cap, > 0 only during warm-up */
   int32_t *scratch_i;
 } melt_t;
@@ -200,7 +205,7 @@ static void disp(const melt_t *m, int i, int j, double d[3]) {
 
 static int check_params(const kgdbref_params *p) {
   if (p->M < 1 || p->N < 2 || !(p->rho > 0) || !(p->R0 > 0) || !(p->T >= 0) || !(p->dt > 0) ||
-      p->n_exp == 6.0 || !(p->n_exp > 0)) {
+      p->n_exp == 6.0 || !(p->n_exp > 0) || p->init_mode < 0 || p->init_mode > 1) {
     set_err("invalid parameters");
     return OR_E_PARAM;
   }
@@ -497,6 +502,65 @@ static void random_walks(melt_t *m) {
     for (int p = 0; p < N; p++) m->chain[c * N + p] = c * N + p;
 }
 
+/* Eq. 12: l_K / l_0 at T = eps.  The first (Flory) term is 0/0 at kappa = 0, where its
+   limit is 1. */
+static double eq12_kuhn_over_l0(double kappa) {
+  double flory = 1.0;
+  if (kappa > 0.0) {
+    double x = 2.0 * kappa;
+    flory = (x + exp(-x) - 1.0) / (1.0 - exp(-x) * (x + 1.0));
+  }
+  return flory + 0.77 * (tanh(-0.03 * kappa * kappa - 0.41 * kappa + 0.16) + 1.0);
+}
+
+/* Freely rotating chains (Sec. II.B).  A freely rotating chain whose successive bond vectors
+   make the angle theta has l_K / l_0 = (1 + cos theta) / (1 - cos theta), so the chains meant
+   by Eq. 13 (whose printed argument exceeds 1) have cos theta* = (C - 1) / (C + 1) with
+   C = l_K / l_0 from Eq. 12.  Chain c: start and first bond as in random_walks (isotropic),
+   bond length l0 = 0.960897; bond p >= 2 turns the previous bond u by theta* about the
+   azimuth phi = 2 pi u01, measured from e1 = (a x u) / |a x u| towards e2 = u x e1, where a
+   is the coordinate axis with the smallest |u component| (the first on ties).  State t uses
+   Philox counter word 1 = t. */
+static void fr_chains(melt_t *m, uint64_t t) {
+  int N = m->N, Nm = m->Nm;
+  uint64_t seed = m->p.seed, mid = (uint64_t)m->p.melt_id;
+  double C = eq12_kuhn_over_l0(m->p.kappa);
+  double ct = (C - 1.0) / (C + 1.0), st = sqrt(1.0 - ct * ct), l0 = 0.960897;
+  for (int c = 0; c < m->M; c++) {
+    uint64_t w[4];
+    draw(seed, mid, (uint64_t)c * N, t, ST_WALK, w);
+    double pos[3] = {u01(w[0]) * m->L, u01(w[1]) * m->L, u01(w[2]) * m->L};
+    double u[3] = {0.0, 0.0, 1.0};
+    for (int p = 0; p < N; p++) {
+      if (p == 1) {
+        draw(seed, mid, (uint64_t)c * N + p, t, ST_WALK, w);
+        double z = 2.0 * u01(w[0]) - 1.0, ph = 2.0 * M_PI * u01(w[1]), sz = sqrt(1.0 - z * z);
+        u[0] = sz * cos(ph); u[1] = sz * sin(ph); u[2] = z;
+      } else if (p > 1) {
+        draw(seed, mid, (uint64_t)c * N + p, t, ST_WALK, w);
+        double ph = 2.0 * M_PI * u01(w[0]);
+        int ax = 0; /* axis least aligned with u */
+        if (fabs(u[1]) < fabs(u[ax])) ax = 1;
+        if (fabs(u[2]) < fabs(u[ax])) ax = 2;
+        double a[3] = {0.0, 0.0, 0.0};
+        a[ax] = 1.0;
+        double e1[3] = {a[1] * u[2] - a[2] * u[1], a[2] * u[0] - a[0] * u[2], a[0] * u[1] - a[1] * u[0]};
+        double n1 = sqrt(e1[0] * e1[0] + e1[1] * e1[1] + e1[2] * e1[2]);
+        for (int k = 0; k < 3; k++) e1[k] /= n1;
+        double e2[3] = {u[1] * e1[2] - u[2] * e1[1], u[2] * e1[0] - u[0] * e1[2], u[0] * e1[1] - u[1] * e1[0]};
+        double nu[3];
+        for (int k = 0; k < 3; k++) nu[k] = ct * u[k] + st * (cos(ph) * e1[k] + sin(ph) * e2[k]);
+        double nn = sqrt(nu[0] * nu[0] + nu[1] * nu[1] + nu[2] * nu[2]);
+        for (int k = 0; k < 3; k++) u[k] = nu[k] / nn;
+      }
+      if (p > 0)
+        for (int k = 0; k < 3; k++) pos[k] = pos[k] + l0 * u[k];
+      int id = c * N + p;
+      for (int k = 0; k < 3; k++) m->x[k * Nm + id] = wrap(pos[k], m->L);
+    }
+  }
+}
+
 static void mb_velocities(melt_t *m) {
   int Nm = m->Nm;
   double sT = sqrt(m->p.T);
@@ -549,16 +613,42 @@ static melt_t *alloc_melt(const kgdbref_params *p) {
   return m;
 }
 
+int kgdbref_observables(melt_t *m, double *r2n, double *ellK, double *meanbond);
+
 /* full init; returns NULL on error (message via kgdbref_last_error) */
 melt_t *kgdbref_create(const kgdbref_params *p) {
   if (check_params(p)) return NULL;
   melt_t *m = alloc_melt(p);
   if (!m) { set_err("allocation failed"); return NULL; }
   random_walks(m);
+  m->init_drawn = 1;
+  m->init_ellK = 0.0;
+  if (p->init_mode == 1) {
+    /* draw states until the l_K fitted by Eq. 14 lies within init_tol of l_0 times Eq. 12 */
+    int tries = p->init_tries > 0 ? p->init_tries : 1000;
+    double tol = p->init_tol > 0 ? p->init_tol : 0.02;
+    double *r2n = (double *)malloc(sizeof(double) * (size_t)(m->N > 1 ? m->N - 1 : 1));
+    int ok = 0;
+    for (int t = 0; t < tries && !ok; t++) {
+      double lk = 0.0, l0 = 0.0;
+      fr_chains(m, (uint64_t)t);
+      kgdbref_observables(m, r2n, &lk, &l0);
+      m->init_drawn = t + 1;
+      if (fabs(lk / (l0 * eq12_kuhn_over_l0(p->kappa)) - 1.0) <= tol) { ok = 1; m->init_ellK = lk; }
+    }
+    free(r2n);
+    if (!ok) { set_err("no freely rotating state passed the l_K test"); kgdbref_destroy(m); return NULL; }
+  }
   mb_velocities(m);
   if (warmup(m)) { kgdbref_destroy(m); return NULL; }
   m->step = 0; m->sweep = 0; m->last_sweep_step = 0;
   return m;
+}
+
+/* out = {init_mode, states drawn, l_K fitted to the accepted freely rotating state} */
+int kgdbref_init_info(const melt_t *m, double *out) {
+  out[0] = m->p.init_mode; out[1] = m->init_drawn; out[2] = m->init_ellK;
+  return OR_OK;
 }
 
 /* state I/O; counters = {step, sweep, last_sweep_step, fc_valid} */

@@ -40,6 +40,7 @@ class Params(C.Structure):
         ("warmup_fcap", C.c_double), ("fene_floor", C.c_double),
         ("seed", C.c_uint64), ("melt_id", C.c_int32), ("test_flags", C.c_uint32),
         ("r_cell", C.c_double),
+        ("init_mode", C.c_int32), ("init_tries", C.c_int32), ("init_tol", C.c_double),
     ]
 
 
@@ -58,7 +59,7 @@ DEFAULTS = dict(M=20, N=50, rho=0.85, kappa=1.5, n_exp=2.0, k_fene=0.0, R0=1.5, 
                 gamma=1.0, dt=0.01, db_rmax=1.3, db_rate=1e-3, proposal=0, precision=0,
                 warmup_steps=1000, warmup_dt0=0.001, warmup_max_disp=0.05, warmup_fcap=10.0,
                 fene_floor=0.02, seed=1,
-                melt_id=0, test_flags=0, r_cell=0.0)
+                melt_id=0, test_flags=0, r_cell=0.0, init_mode=0, init_tries=0, init_tol=0.0)
 
 _lib = None
 
@@ -100,6 +101,7 @@ def lib():
         L.kgdbref_forces.argtypes = [P, C.c_int32, P, P, P]
         L.kgdbref_md_steps.argtypes = [P, C.c_int64]
         L.kgdbref_set_potential.argtypes = [P, C.c_double, C.c_double]
+        L.kgdbref_init_info.argtypes = [P, dp]
         L.kgdbref_cell_list.argtypes = [P, C.c_double, C.POINTER(C.c_int32), P, P, C.c_int64]
         L.kgdbref_candidates.argtypes = [P, C.c_int32, P, C.c_int64, C.POINTER(C.c_int64)]
         L.kgdbref_db_sweep.argtypes = [P, C.c_int64, C.c_int32, C.POINTER(Stats)]
@@ -208,6 +210,12 @@ class Melt:
 
     def md_steps(self, n):
         _check(lib().kgdbref_md_steps(self.h, n))
+
+    def init_info(self):
+        """(init mode, states drawn, l_K fitted to the accepted freely rotating state)."""
+        out = np.zeros(3)
+        _check(lib().kgdbref_init_info(self.h, out))
+        return int(out[0]), int(out[1]), out[2]
 
     def set_potential(self, n_exp, k_fene=0.0):
         _check(lib().kgdbref_set_potential(self.h, float(n_exp), float(k_fene)))
