@@ -75,7 +75,14 @@ typedef struct {
   double nl_skin;         /* list skin (<= 0: 2 u K dt sqrt(T), twice the drift at speed u sqrt(T);
                              u = 6.6 up to 200,000 monomers in the batch, growing so that
                              nm u exp(-u^2/2) stays fixed beyond: 7.25 at 16M)                   */
+  int32_t init_mode;      /* KGDB_INIT_RANDOM_WALK (0) or KGDB_INIT_FREELY_ROTATING (1)         */
+  int32_t init_tries;     /* freely rotating starts: states drawn at most (<= 0: 1000)          */
+  double init_tol;        /* freely rotating starts: accepted l_K deviation (<= 0: 0.02)        */
 } kgdb_params;
+
+/* initial chain conformations */
+#define KGDB_INIT_RANDOM_WALK 0      /* freely jointed walks, bond 0.97 sigma                     */
+#define KGDB_INIT_FREELY_ROTATING 1  /* freely rotating chains of Sec. II.B (Eqs. 12-14)          */
 
 /* statistics of one melt's double-bridging sweep */
 typedef struct {
@@ -92,8 +99,15 @@ typedef struct kgdb_batch kgdb_batch;
 
 /* Create a batch of `count` melts from params[0..count-1] on `hip_stream` (a hipStream_t;
    NULL = the library creates its own).  Each melt is initialised as seeded freely jointed
-   random walks with bond 0.97, Maxwell-Boltzmann velocities with the mean removed, and the
-   warm-up of Sec. II.B (small initial timestep, ramped).  A batch holds fewer than 2^24
+   random walks with bond 0.97 or, with KGDB_INIT_FREELY_ROTATING, as the freely rotating
+   chains of Sec. II.B: bonds of l0 = 0.960897, each at angle theta* to the one before it
+   (cos theta* = (C - 1)/(C + 1), C = l_K/l_0 of Eq. 12: Eq. 13 read for the angle between
+   successive bond vectors, as printed its argument exceeds 1) about a uniform azimuth; a
+   state whose l_K fitted by Eq. 14 (over ceil(N/4) <= n <= floor(N/2), l_0 the mean bond)
+   deviates from C l_0 by more than init_tol is drawn again (the t-th state from Philox
+   counter word 1 = t), at most init_tries times (KGDB_E_STATE if none passes).  Then
+   Maxwell-Boltzmann velocities with the mean removed, and the warm-up of Sec. II.B (small
+   initial timestep, ramped).  A batch holds fewer than 2^24
    monomers in total.  Returns KGDB_E_PARAM for invalid parameters (or a batch too large),
    KGDB_E_FENE/NONFINITE if the warm-up fails.  *out is owned by the caller and
    released by kgdb_destroy. */
@@ -212,6 +226,9 @@ int kgdb_nl_info(kgdb_batch* b, double out[4]);
 /* geometry of melt `melt`: out = {L, MD cells per side, double-bridging cells per side,
    FENE constant in use (k_n of Eq. 9 or the literal value)} */
 int kgdb_melt_geometry(const kgdb_batch* b, int32_t melt, double out[4]);
+/* initial state of melt `melt`: out = {init_mode, states drawn (1 for random walks), l_K fitted
+   to the accepted freely rotating state (0 for random walks)} */
+int kgdb_init_info(const kgdb_batch* b, int32_t melt, double out[3]);
 /* total number of monomers and cells of the batch (for byte accounting) */
 int kgdb_batch_sizes(const kgdb_batch* b, int64_t* monomers, int64_t* cells);
 

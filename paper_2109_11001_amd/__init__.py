@@ -8,8 +8,9 @@ import ctypes as C
 
 import numpy as np
 
-from ._lib import (MLP_NPARAM, PREC_FP64, PREC_MIXED, PROPOSAL_LEARNED, PROPOSAL_LITERAL, PROPOSAL_UNIFORM,
-                   TF_NL_GLOBAL, TF_NOFORCE, TF_PHANTOM, DbStats, KgdbError, Params, StageStats, check, load, ptr)
+from ._lib import (INIT_FREELY_ROTATING, INIT_RANDOM_WALK, MLP_NPARAM, PREC_FP64, PREC_MIXED, PROPOSAL_LEARNED,
+                   PROPOSAL_LITERAL, PROPOSAL_UNIFORM, TF_NL_GLOBAL, TF_NOFORCE, TF_PHANTOM, DbStats, KgdbError,
+                   Params, StageStats, check, load, ptr)
 
 NN_IN = 25
 
@@ -17,7 +18,7 @@ DEFAULTS = dict(M=20, N=50, rho=0.85, kappa=1.5, n_exp=2.0, k_fene=0.0, R0=1.5, 
                 gamma=1.0, dt=0.01, db_rmax=1.3, db_rate=1e-3, proposal=PROPOSAL_UNIFORM,
                 precision=PREC_FP64, warmup_steps=1000, warmup_dt0=0.001, warmup_max_disp=0.05,
                 warmup_fcap=10.0, fene_floor=0.02, seed=1, melt_id=0, test_flags=0, r_cell=0.0,
-                nl_every=0, nl_skin=0.0)
+                nl_every=0, nl_skin=0.0, init_mode=INIT_RANDOM_WALK, init_tries=0, init_tol=0.0)
 
 # the n values of the paper's schedule, Eq. (11)
 XI = (2.0, 3.0, 4.0, 5.0, 5.75, 6.5, 7.0, 8.0, 9.0, 10.0, 11.0, 12.0)
@@ -173,6 +174,12 @@ class Batch:
         out = np.zeros(4)
         check(load().kgdb_nl_info(self._h, ptr(out)))
         return dict(K=int(out[0]), skin=out[1], mean_list=out[2], rollbacks=int(out[3]))
+
+    def init_info(self, melt=0):
+        """(init mode, states drawn, l_K fitted to the accepted freely rotating state)."""
+        out = np.zeros(3)
+        check(load().kgdb_init_info(self._h, int(melt), ptr(out)))
+        return int(out[0]), int(out[1]), out[2]
 
     def sizes(self):
         a, b = C.c_int64(), C.c_int64()

@@ -14,6 +14,7 @@ LIB_PATH = os.path.join(HERE, "libkgdb.so")
 E_PARAM, E_ALLOC, E_HIP, E_FENE, E_NONFINITE, E_OVERFLOW, E_STATE = -1, -2, -3, -4, -5, -6, -7
 PROPOSAL_UNIFORM, PROPOSAL_LEARNED, PROPOSAL_LITERAL = 0, 1, 2
 PREC_FP64, PREC_MIXED = 0, 1
+INIT_RANDOM_WALK, INIT_FREELY_ROTATING = 0, 1
 TF_PHANTOM, TF_NOFORCE, TF_NL_GLOBAL = 1, 2, 4
 
 
@@ -35,6 +36,7 @@ class Params(C.Structure):
         ("fene_floor", C.c_double),
         ("seed", C.c_uint64), ("melt_id", C.c_int32), ("test_flags", C.c_uint32),
         ("r_cell", C.c_double), ("nl_every", C.c_int32), ("nl_skin", C.c_double),
+        ("init_mode", C.c_int32), ("init_tries", C.c_int32), ("init_tol", C.c_double),
     ]
 
 
@@ -68,7 +70,7 @@ EXPORTS = [
     "kgdb_melt_geometry", "kgdb_batch_sizes", "kgdb_autotune", "kgdb_nl_info",
     "kgdb_mlp_nparam", "kgdb_set_proposal_net", "kgdb_db_sweep_log", "kgdb_features", "kgdb_candidate_logits",
     "kgdb_mlp_workspace_bytes", "kgdb_mlp_forward", "kgdb_mlp_grad", "kgdb_mlp_adam", "kgdb_mlp_train_step",
-    "kgdb_set_potential", "kgdb_protocol_schedule", "kgdb_run_protocol",
+    "kgdb_set_potential", "kgdb_protocol_schedule", "kgdb_run_protocol", "kgdb_init_info",
 ]
 MLP_NPARAM = 36481
 
@@ -122,6 +124,7 @@ def load():
     L.kgdb_mlp_adam.argtypes = [P, P, P, P, i64, dbl, dbl, dbl, dbl, P]
     L.kgdb_mlp_train_step.argtypes = [P, P, P, P, P, i64, i64, dbl, dbl, dbl, dbl, P, i64, P, P]
     L.kgdb_set_potential.argtypes = [P, i32, dbl, dbl]
+    L.kgdb_init_info.argtypes = [P, i32, P]
     L.kgdb_protocol_schedule.argtypes = [dbl, i32, dbl, dbl, P, P, P]
     L.kgdb_run_protocol.argtypes = [P, P, P, i32, i64, P]
     for f in EXPORTS:

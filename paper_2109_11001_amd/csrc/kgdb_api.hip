@@ -39,6 +39,8 @@ constexpr int PROF_EVENTS = 256; // event pairs per profiling batch
 struct kgdb_batch {
   int nm = 0;
   std::vector<kgdb_params> P;
+  std::vector<int> init_drawn;      // initial states drawn per melt
+  std::vector<double> init_ellK;    // l_K fitted to the accepted freely rotating state
   std::vector<MeltDesc> D;
   int prec = 0;
   hipStream_t s = nullptr;
@@ -166,6 +168,8 @@ static int check_params(const kgdb_params& p) {
     return fail(KGDB_E_PARAM, "unsupported proposal mode");
   if (p.precision != KGDB_PREC_FP64 && p.precision != KGDB_PREC_MIXED) return fail(KGDB_E_PARAM, "bad precision");
   if (p.warmup_steps < 0) return fail(KGDB_E_PARAM, "warmup_steps < 0");
+  if (p.init_mode != KGDB_INIT_RANDOM_WALK && p.init_mode != KGDB_INIT_FREELY_ROTATING)
+    return fail(KGDB_E_PARAM, "unknown init_mode");
   if (p.warmup_steps > 0 && (!(p.warmup_dt0 > 0) || !(p.warmup_max_disp > 0) || !(p.warmup_fcap > 0)))
     return fail(KGDB_E_PARAM, "warm-up needs dt0, max_disp and fcap > 0");
   if ((int64_t)p.M * p.N > (int64_t)1 << 28) return fail(KGDB_E_PARAM, "melt too large");
@@ -243,6 +247,9 @@ static MeltDesc make_desc(const kgdb_params& p) {
   set_list_geometry(d, p, p.nl_every > 0 ? p.nl_every : 5, (double)d.Nm);
   d.seed = p.seed;
   d.melt_id = (uint64_t)(int64_t)p.melt_id;
+  d.init_mode = p.init_mode;
+  const double C = kuhn_over_l0(p.kappa);  // freely rotating chains: l_K / l_0 = (1 + cos) / (1 - cos)
+  d.fr_cos = (C - 1.0) / (C + 1.0);
   d.test_flags = p.test_flags;
   return d;
 }
@@ -712,6 +719,134 @@ static int build_block_maps(kgdb_batch* b) {
   return 0;
 }
 
+// l_K from Eq. 14 by least squares: log-grid bracket, then Brent's parabolic/golden search
+static double wlc_model(double n, double l0, double lk) {
+  return lk * (1.0 - lk / (2.0 * n * l0) * (1.0 - std::exp(-2.0 * n * l0 / lk)));
+}
+static double fit_sse(const std::vector<double>& r2n, int N, double l0, double lk) {
+  const int lo = (N + 3) / 4, hi = N / 2;
+  double s = 0.0;
+  for (int n = lo; n <= hi; ++n) {
+    const double e = r2n[n - 1] / l0 - wlc_model(n, l0, lk);
+    s += e * e;
+  }
+  return s;
+}
+static double fit_ellK(const std::vector<double>& r2n, int N, double l0) {
+  if (N < 4) return NAN;
+  auto f = [&](double u) { return fit_sse(r2n, N, l0, std::exp(u)); };
+  const double A = std::log(0.05), B = std::log(1e4);
+  const int G = 256;
+  int best = 0;
+  double fb = INFINITY;
+  for (int g = 0; g <= G; ++g) {
+    const double v = f(A + (B - A) * g / G);
+    if (v < fb) { fb = v; best = g; }
+  }
+  double a = A + (B - A) * std::max(best - 1, 0) / G, bb = A + (B - A) * std::min(best + 1, G) / G;
+  // Brent minimisation on [a, bb]
+  const double cg = 0.3819660112501051;
+  double x = a + cg * (bb - a), w = x, v = x, fx = f(x), fw = fx, fv = fx, dd = 0.0, e = 0.0;
+  for (int it = 0; it < 200; ++it) {
+    const double xm = 0.5 * (a + bb), tol1 = 1e-14 * std::fabs(x) + 1e-16, tol2 = 2.0 * tol1;
+    if (std::fabs(x - xm) <= tol2 - 0.5 * (bb - a)) break;
+    bool golden = true;
+    if (std::fabs(e) > tol1) {
+      double r = (x - w) * (fx - fv), q = (x - v) * (fx - fw), p = (x - v) * q - (x - w) * r;
+      q = 2.0 * (q - r);
+      if (q > 0) p = -p;
+      q = std::fabs(q);
+      const double etemp = e;
+      e = dd;
+      if (!(std::fabs(p) >= std::fabs(0.5 * q * etemp) || p <= q * (a - x) || p >= q * (bb - x))) {
+        dd = p / q;
+        const double u = x + dd;
+        if (u - a < tol2 || bb - u < tol2) dd = (xm - x >= 0) ? tol1 : -tol1;
+        golden = false;
+      }
+    }
+    if (golden) {
+      e = (x >= xm) ? a - x : bb - x;
+      dd = cg * e;
+    }
+    const double u = std::fabs(dd) >= tol1 ? x + dd : x + (dd >= 0 ? tol1 : -tol1);
+    const double fu = f(u);
+    if (fu <= fx) {
+      if (u >= x) a = x; else bb = x;
+      v = w; fv = fw; w = x; fw = fx; x = u; fx = fu;
+    } else {
+      if (u < x) a = u; else bb = u;
+      if (fu <= fw || w == x) { v = w; fv = fw; w = u; fw = fu; }
+      else if (fu <= fv || v == x || v == w) { v = u; fv = fu; }
+    }
+  }
+  return std::exp(x);
+}
+
+// R^2(n)/n, mean bond length and the l_K fit of Eq. 14 of melt `melt` at the current state
+static int melt_observables(kgdb_batch* b, int32_t melt, double* r2_over_n, double* ell_K, double* mean_bond) {
+  const MeltDesc& d = b->D[melt];
+  launch_prefix(b->d_md, melt, d.M, b->NP, b->d_x[b->cur], b->d_chain, b->d_spre, b->d_blen, b->s);
+  launch_r2(b->d_md, melt, d.M, d.N, b->d_spre, nullptr, b->d_r2, b->s);
+  HIPCHK(hipGetLastError());
+  std::vector<double> r2(std::max(d.N - 1, 1)), bl(d.M);
+  HIPCHK(hipMemcpyAsync(r2.data(), b->d_r2, sizeof(double) * (d.N - 1), hipMemcpyDeviceToHost, b->s));
+  HIPCHK(hipMemcpyAsync(bl.data(), b->d_blen, sizeof(double) * d.M, hipMemcpyDeviceToHost, b->s));
+  HIPCHK(hipStreamSynchronize(b->s));
+  std::vector<double> r2n(d.N - 1);
+  for (int n = 1; n < d.N; ++n) r2n[n - 1] = r2[n - 1] / ((double)d.M * (double)(d.N - n)) / (double)n;
+  double bs = 0.0;
+  for (int c = 0; c < d.M; ++c) bs += bl[c];
+  const double l0 = bs / ((double)d.M * (d.N - 1));
+  if (r2_over_n) std::memcpy(r2_over_n, r2n.data(), sizeof(double) * (d.N - 1));
+  if (mean_bond) *mean_bond = l0;
+  if (ell_K) *ell_K = fit_ellK(r2n, d.N, l0);
+  return 0;
+}
+
+// Freely rotating starts (Sec. II.B): draw state t = 0, 1, ... of every such melt until its
+// l_K fitted by Eq. 14 lies within init_tol of l_0 times Eq. 12, at most init_tries states.
+static int init_freely_rotating(kgdb_batch* b) {
+  std::vector<int> tries(b->nm, -1);
+  int pending = 0;
+  for (int k = 0; k < b->nm; ++k)
+    if (b->P[k].init_mode == KGDB_INIT_FREELY_ROTATING) { tries[k] = 0; ++pending; }
+  if (!pending) return 0;
+  int* d_tries = nullptr;
+  HIPCHK(hipMalloc(&d_tries, sizeof(int) * b->nm));
+  int rc = 0;
+  while (pending && !rc) {
+    if (hipMemcpy(d_tries, tries.data(), sizeof(int) * b->nm, hipMemcpyHostToDevice) != hipSuccess) {
+      rc = fail(KGDB_E_HIP, "copy of the state indices failed");
+      break;
+    }
+    launch_fr_chains(b->d_md, b->nm, b->max_M, b->NP, b->d_x[0], d_tries, b->s);
+    if (hipGetLastError() != hipSuccess) { rc = fail(KGDB_E_HIP, "freely rotating chains kernel"); break; }
+    for (int k = 0; k < b->nm && !rc; ++k) {
+      if (tries[k] < 0) continue;
+      const kgdb_params& p = b->P[k];
+      double lk = 0.0, l0 = 0.0;
+      rc = melt_observables(b, k, nullptr, &lk, &l0);
+      if (rc) break;
+      const double tol = p.init_tol > 0 ? p.init_tol : 0.02;
+      const int max_tries = p.init_tries > 0 ? p.init_tries : 1000;
+      b->init_drawn[k] = tries[k] + 1;
+      if (std::fabs(lk / (l0 * kuhn_over_l0(p.kappa)) - 1.0) <= tol) {
+        b->init_ellK[k] = lk;
+        tries[k] = -1;
+        --pending;
+      } else if (tries[k] + 1 >= max_tries) {
+        rc = fail(KGDB_E_STATE, "no freely rotating state of melt " + std::to_string(k) + " passed the l_K test in " +
+                                    std::to_string(max_tries) + " draws");
+      } else {
+        ++tries[k];
+      }
+    }
+  }
+  hipFree(d_tries);
+  return rc;
+}
+
 static int init_impl(const kgdb_params* params, int32_t count, void* stream, kgdb_batch** out) {
   if (!params || !out || count < 1) return fail(KGDB_E_PARAM, "null argument or empty batch");
   *out = nullptr;
@@ -897,10 +1032,14 @@ static int init_impl(const kgdb_params* params, int32_t count, void* stream, kgd
     hip(hipMemcpy(b->d_mono, mono.data(), sizeof(int) * np, hipMemcpyHostToDevice), "mono");
   }
   launch_random_walks(b->d_md, count, b->max_M, b->NP, b->d_x[0], b->d_chain, b->d_loc, b->s);
+  b->cur = 0;
+  b->init_drawn.assign(count, 1);
+  b->init_ellK.assign(count, 0.0);
+  if (!rc) rc = init_freely_rotating(b);
+  if (rc) { std::string m = g_err; kgdb_destroy(b); g_err = m; return rc; }
   launch_velocities(b->d_md, b->pm, b->NP, b->d_v, b->s);
   launch_remove_mean(b->d_md, count, b->NP, b->d_v, b->s);
   hip(hipGetLastError(), "init kernels");
-  b->cur = 0;
   b->cells_valid = false;
   if (!rc) rc = warmup(b);
   if (rc) { std::string m = g_err; kgdb_destroy(b); g_err = m; return rc; }
@@ -1269,88 +1408,18 @@ int kgdb_db_sweep_checked(kgdb_batch* b, int64_t n_attempts, kgdb_db_stats* stat
   return sweep_impl(b, n_attempts, stats, 1);
 }
 
-// l_K from Eq. 14 by least squares: log-grid bracket, then Brent's parabolic/golden search
-static double wlc_model(double n, double l0, double lk) {
-  return lk * (1.0 - lk / (2.0 * n * l0) * (1.0 - std::exp(-2.0 * n * l0 / lk)));
-}
-static double fit_sse(const std::vector<double>& r2n, int N, double l0, double lk) {
-  const int lo = (N + 3) / 4, hi = N / 2;
-  double s = 0.0;
-  for (int n = lo; n <= hi; ++n) {
-    const double e = r2n[n - 1] / l0 - wlc_model(n, l0, lk);
-    s += e * e;
-  }
-  return s;
-}
-static double fit_ellK(const std::vector<double>& r2n, int N, double l0) {
-  if (N < 4) return NAN;
-  auto f = [&](double u) { return fit_sse(r2n, N, l0, std::exp(u)); };
-  const double A = std::log(0.05), B = std::log(1e4);
-  const int G = 256;
-  int best = 0;
-  double fb = INFINITY;
-  for (int g = 0; g <= G; ++g) {
-    const double v = f(A + (B - A) * g / G);
-    if (v < fb) { fb = v; best = g; }
-  }
-  double a = A + (B - A) * std::max(best - 1, 0) / G, bb = A + (B - A) * std::min(best + 1, G) / G;
-  // Brent minimisation on [a, bb]
-  const double cg = 0.3819660112501051;
-  double x = a + cg * (bb - a), w = x, v = x, fx = f(x), fw = fx, fv = fx, dd = 0.0, e = 0.0;
-  for (int it = 0; it < 200; ++it) {
-    const double xm = 0.5 * (a + bb), tol1 = 1e-14 * std::fabs(x) + 1e-16, tol2 = 2.0 * tol1;
-    if (std::fabs(x - xm) <= tol2 - 0.5 * (bb - a)) break;
-    bool golden = true;
-    if (std::fabs(e) > tol1) {
-      double r = (x - w) * (fx - fv), q = (x - v) * (fx - fw), p = (x - v) * q - (x - w) * r;
-      q = 2.0 * (q - r);
-      if (q > 0) p = -p;
-      q = std::fabs(q);
-      const double etemp = e;
-      e = dd;
-      if (!(std::fabs(p) >= std::fabs(0.5 * q * etemp) || p <= q * (a - x) || p >= q * (bb - x))) {
-        dd = p / q;
-        const double u = x + dd;
-        if (u - a < tol2 || bb - u < tol2) dd = (xm - x >= 0) ? tol1 : -tol1;
-        golden = false;
-      }
-    }
-    if (golden) {
-      e = (x >= xm) ? a - x : bb - x;
-      dd = cg * e;
-    }
-    const double u = std::fabs(dd) >= tol1 ? x + dd : x + (dd >= 0 ? tol1 : -tol1);
-    const double fu = f(u);
-    if (fu <= fx) {
-      if (u >= x) a = x; else bb = x;
-      v = w; fv = fw; w = x; fw = fx; x = u; fx = fu;
-    } else {
-      if (u < x) a = u; else bb = u;
-      if (fu <= fw || w == x) { v = w; fv = fw; w = u; fw = fu; }
-      else if (fu <= fv || v == x || v == w) { v = u; fv = fu; }
-    }
-  }
-  return std::exp(x);
-}
 
 int kgdb_observables(kgdb_batch* b, int32_t melt, double* r2_over_n, double* ell_K, double* mean_bond) {
   CHK(check_melt(b, melt));
-  const MeltDesc& d = b->D[melt];
-  launch_prefix(b->d_md, melt, d.M, b->NP, b->d_x[b->cur], b->d_chain, b->d_spre, b->d_blen, b->s);
-  launch_r2(b->d_md, melt, d.M, d.N, b->d_spre, nullptr, b->d_r2, b->s);
-  HIPCHK(hipGetLastError());
-  std::vector<double> r2(std::max(d.N - 1, 1)), bl(d.M);
-  HIPCHK(hipMemcpyAsync(r2.data(), b->d_r2, sizeof(double) * (d.N - 1), hipMemcpyDeviceToHost, b->s));
-  HIPCHK(hipMemcpyAsync(bl.data(), b->d_blen, sizeof(double) * d.M, hipMemcpyDeviceToHost, b->s));
-  HIPCHK(hipStreamSynchronize(b->s));
-  std::vector<double> r2n(d.N - 1);
-  for (int n = 1; n < d.N; ++n) r2n[n - 1] = r2[n - 1] / ((double)d.M * (double)(d.N - n)) / (double)n;
-  double bs = 0.0;
-  for (int c = 0; c < d.M; ++c) bs += bl[c];
-  const double l0 = bs / ((double)d.M * (d.N - 1));
-  if (r2_over_n) std::memcpy(r2_over_n, r2n.data(), sizeof(double) * (d.N - 1));
-  if (mean_bond) *mean_bond = l0;
-  if (ell_K) *ell_K = fit_ellK(r2n, d.N, l0);
+  return melt_observables(b, melt, r2_over_n, ell_K, mean_bond);
+}
+
+int kgdb_init_info(const kgdb_batch* b, int32_t melt, double out[3]) {
+  CHK(check_melt(b, melt));
+  if (!out) return fail(KGDB_E_PARAM, "null argument");
+  out[0] = b->P[melt].init_mode;
+  out[1] = b->init_drawn[melt];
+  out[2] = b->init_ellK[melt];
   return 0;
 }
 

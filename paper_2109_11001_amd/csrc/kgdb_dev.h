@@ -65,6 +65,9 @@ struct MeltDesc {
   // list build: each workgroup takes a block of nl_S x nl_Sy cells of one z-plane of the list
   // grid (nl_nseg blocks along x, nl_nyb along y) and stages its neighbourhood in LDS
   int nl_S, nl_Sy, nl_nseg, nl_nyb;
+  // initial state: KGDB_INIT_* and, for freely rotating chains, cos theta* (Eqs. 12-13)
+  int init_mode;
+  double fr_cos;
 };
 
 // ---------------------------------------------------------------------------------------

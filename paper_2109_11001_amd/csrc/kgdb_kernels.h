@@ -119,6 +119,8 @@ size_t rel_bytes(int prec);
 // ---- init and observables (kgdb_obs.hip)
 void launch_random_walks(const MeltDesc* md, int nm, int max_M, int NP, double* x, int* chain, int* loc,
                          hipStream_t s);
+void launch_fr_chains(const MeltDesc* md, int nm, int max_M, int NP, double* x, const int* tries, hipStream_t s);
+double kuhn_over_l0(double kappa);  // Eq. 12
 void launch_velocities(const MeltDesc* md, const BlockMap& pm, int NP, double* v, hipStream_t s);
 void launch_remove_mean(const MeltDesc* md, int nm, int NP, double* v, hipStream_t s);
 void launch_reduce_melt(const MeltDesc* md, int nm, int NP, const double* outE, const double* v,

@@ -35,6 +35,57 @@ __global__ void k_random_walks(const MeltDesc* __restrict__ md, int NP, double* 
   }
 }
 
+// Freely rotating chains (Sec. II.B): the first bond isotropic, each later bond at angle
+// theta* to the one before it (cos theta* = d.fr_cos) about a uniform azimuth phi measured in
+// the frame e1 = (a x u)/|a x u|, e2 = u x e1, a the coordinate axis least aligned with the
+// previous bond u (the first of them on ties); bond length l0 = 0.960897.  State t of melt k
+// (tries[k] = t; < 0 skips the melt) draws from Philox counter word 1 = t.  The chain table
+// of k_random_walks is kept.
+__global__ void k_fr_chains(const MeltDesc* __restrict__ md, int NP, double* __restrict__ x,
+                            const int* __restrict__ tries) {
+  const int k = blockIdx.y;
+  const MeltDesc& d = md[k];
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (tries[k] < 0 || c >= d.M) return;
+  const int N = d.N;
+  const uint64_t t = (uint64_t)tries[k];
+  const double l0 = 0.960897, ct = d.fr_cos, st = sqrt(1.0 - ct * ct);
+  U64x4 w = rng_draw(d, (uint64_t)c * N, t, ST_WALK);
+  double px = u01(w.w[0]) * d.L, py = u01(w.w[1]) * d.L, pz = u01(w.w[2]) * d.L;
+  double ux = 0.0, uy = 0.0, uz = 1.0;
+  for (int p = 0; p < N; ++p) {
+    if (p == 1) {
+      w = rng_draw(d, (uint64_t)c * N + p, t, ST_WALK);
+      const double z = 2.0 * u01(w.w[0]) - 1.0;
+      const double ph = 6.283185307179586 * u01(w.w[1]);
+      const double s = sqrt(1.0 - z * z);
+      ux = s * cos(ph); uy = s * sin(ph); uz = z;
+    } else if (p > 1) {
+      w = rng_draw(d, (uint64_t)c * N + p, t, ST_WALK);
+      const double ph = 6.283185307179586 * u01(w.w[0]);
+      const double ax = fabs(ux), ay = fabs(uy), az = fabs(uz);
+      double vx, vy, vz;  // a x u
+      if (ax <= ay && ax <= az) { vx = 0.0; vy = -uz; vz = uy; }
+      else if (ay <= az) { vx = uz; vy = 0.0; vz = -ux; }
+      else { vx = -uy; vy = ux; vz = 0.0; }
+      const double vn = sqrt(vx * vx + vy * vy + vz * vz);
+      const double e1x = vx / vn, e1y = vy / vn, e1z = vz / vn;
+      const double e2x = uy * e1z - uz * e1y, e2y = uz * e1x - ux * e1z, e2z = ux * e1y - uy * e1x;
+      const double cp = cos(ph), sp = sin(ph);
+      const double nx = ct * ux + st * (cp * e1x + sp * e2x);
+      const double ny = ct * uy + st * (cp * e1y + sp * e2y);
+      const double nz = ct * uz + st * (cp * e1z + sp * e2z);
+      const double nn = sqrt(nx * nx + ny * ny + nz * nz);
+      ux = nx / nn; uy = ny / nn; uz = nz / nn;
+    }
+    if (p > 0) { px = px + l0 * ux; py = py + l0 * uy; pz = pz + l0 * uz; }
+    const int g = d.off + c * N + p;
+    x[g] = wrap_box(px, d.L);
+    x[NP + g] = wrap_box(py, d.L);
+    x[2 * NP + g] = wrap_box(pz, d.L);
+  }
+}
+
 // Maxwell-Boltzmann velocities at T (mean removed by k_remove_mean)
 __global__ __launch_bounds__(256) void k_velocities(const MeltDesc* __restrict__ md, const int* __restrict__ blk_melt,
                                                     const int* __restrict__ blk_base, int NP, double* __restrict__ v) {
@@ -139,6 +190,9 @@ __global__ __launch_bounds__(256) void k_r2(int M, int N, const double* __restri
 void launch_random_walks(const MeltDesc* md, int nm, int max_M, int NP, double* x, int* chain, int* loc,
                          hipStream_t s) {
   hipLaunchKernelGGL(k_random_walks, dim3((max_M + 63) / 64, nm), dim3(64), 0, s, md, NP, x, chain, loc);
+}
+void launch_fr_chains(const MeltDesc* md, int nm, int max_M, int NP, double* x, const int* tries, hipStream_t s) {
+  hipLaunchKernelGGL(k_fr_chains, dim3((max_M + 63) / 64, nm), dim3(64), 0, s, md, NP, x, tries);
 }
 void launch_velocities(const MeltDesc* md, const BlockMap& pm, int NP, double* v, hipStream_t s) {
   hipLaunchKernelGGL(k_velocities, dim3(pm.nblk), dim3(256), 0, s, md, pm.melt, pm.base, NP, v);

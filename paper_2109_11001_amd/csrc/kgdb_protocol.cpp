@@ -9,9 +9,7 @@
 
 #include "kgdb.h"
 
-namespace {
-
-const double XI[12] = {2.0, 3.0, 4.0, 5.0, 5.75, 6.5, 7.0, 8.0, 9.0, 10.0, 11.0, 12.0};  // Eq. 11
+namespace kgdb {
 
 // Eq. 12: l_K / l_0 at T = eps (Flory term plus the empirical melt correction).  The Flory
 // term is 0/0 at kappa = 0; its series there is 1 + 2 kappa / 3 + O(kappa^2).
@@ -26,6 +24,12 @@ double kuhn_over_l0(double kappa) {
   return flory + 0.77 * (std::tanh(-0.03 * kappa * kappa - 0.41 * kappa + 0.16) + 1.0);
 }
 
+}  // namespace kgdb
+
+namespace {
+
+const double XI[12] = {2.0, 3.0, 4.0, 5.0, 5.75, 6.5, 7.0, 8.0, 9.0, 10.0, 11.0, 12.0};  // Eq. 11
+
 }  // namespace
 
 extern "C" {
@@ -37,7 +41,7 @@ int kgdb_protocol_schedule(double kappa, int32_t N, double dt, double f, double*
   const double a = 1.6, b = 0.77;
   const double tau_fix = f * N / a * std::exp(b * kappa);                     // Eq. 16
   const double ne = 77.0 * std::exp(-kappa / 1.1) + 9.4;                      // initial N_e estimate
-  const double tau_e = ne * ne * kuhn_over_l0(kappa);                         // Eq. 17, O(1) prefactor dropped
+  const double tau_e = ne * ne * kgdb::kuhn_over_l0(kappa);                         // Eq. 17, O(1) prefactor dropped
   const double tau_eq = std::fmax(std::fmax(2.0 * tau_e, tau_fix), 200.0 * N);  // Eq. 18
   double tau[12];
   int scheme;
