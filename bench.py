@@ -252,7 +252,9 @@ def run_equilibration(kg, stream, steps, ref_steps, every=1000, tol=0.02, batch_
     `steps` steps from the start, one sweep at the paper's rate every 100 steps, R^2(n)/n read
     every `every` steps; a form has equilibrated once the mean over the second half of its run
     so far stays within `tol` of the reference for every n (the reference run itself counts as
-    the FP64 form).  Wall-clock times include the sweeps and the readings."""
+    the FP64 form).  Wall-clock times include the sweeps and the readings.  One more form,
+    mixed precision from freely rotating chains (Sec. II.B) instead of the shared random-walk
+    start, measures what the better initial state saves."""
     import numpy as np
     import torch
     base = dict(WORKLOAD, **EQ_SYSTEM)
@@ -264,6 +266,8 @@ def run_equilibration(kg, stream, steps, ref_steps, every=1000, tol=0.02, batch_
         melts = batch_melts if form == "batched" else 1
         prec = kg.PREC_FP64 if form == "fp64" else kg.PREC_MIXED
         prop = kg.PROPOSAL_LEARNED if form == "learned" else kg.PROPOSAL_UNIFORM
+        if form == "mixed_fr":  # its own start: freely rotating chains (Sec. II.B), then the warm-up
+            return kg.Batch([dict(base, precision=prec, init_mode=kg.INIT_FREELY_ROTATING)], stream=stream), 1
         b = kg.Batch([dict(base, warmup_steps=0, precision=prec, proposal=prop, melt_id=i) for i in range(melts)],
                      stream=stream)
         for i in range(melts):
@@ -312,6 +316,7 @@ def run_equilibration(kg, stream, steps, ref_steps, every=1000, tol=0.02, batch_
     runs["mixed"] = run("mixed", steps)
     runs["batched"] = run("batched", steps)
     runs["learned"] = run("learned", steps, net=tr.params)
+    runs["mixed_fr"] = run("mixed_fr", steps)
     for form, r in runs.items():
         k, dev = _steps_to_within(r["times"], r["samples"], ref, tol)
         out["forms"][form] = {
