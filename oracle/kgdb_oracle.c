@@ -180,6 +180,7 @@ typedef struct {
   int M, N, Nm;
   double L, kn, rc;
   double *x, *v, *fc, *fl; /* [3*Nm], component-major: x[d*Nm + i] */
+  double *du;              /* [3*Nm] displacement since the last reset, never wrapped */
   int32_t *chain;          /* chain[c*N + p]: monomer id at chain c, position p (0-based) */
   uint64_t step, sweep;
   uint64_t last_sweep_step;
@@ -214,7 +215,7 @@ static int check_params(const kgdbref_params *p) {
 
 void kgdbref_destroy(melt_t *m) {
   if (!m) return;
-  free(m->x); free(m->v); free(m->fc); free(m->fl); free(m->chain); free(m->scratch_i);
+  free(m->x); free(m->v); free(m->fc); free(m->fl); free(m->du); free(m->chain); free(m->scratch_i);
   free(m);
 }
 
@@ -441,6 +442,7 @@ static int vv_step(melt_t *m, double dt, double cap, uint64_t noise_index, uint6
     for (int k = 0; k < 3; k++) {
       m->v[k * Nm + i] = vh[k]; /* holds v_half until the closing kick */
       m->x[k * Nm + i] = wrap(m->x[k * Nm + i] + dt * vh[k], m->L);
+      m->du[k * Nm + i] += dt * vh[k];
     }
   }
   int rc = compute_forces(m, 0, m->fc, NULL, NULL);
@@ -608,8 +610,9 @@ static melt_t *alloc_melt(const kgdbref_params *p) {
   m->v = (double *)calloc(n3, sizeof(double));
   m->fc = (double *)calloc(n3, sizeof(double));
   m->fl = (double *)calloc(n3, sizeof(double));
+  m->du = (double *)calloc(n3, sizeof(double));
   m->chain = (int32_t *)malloc(sizeof(int32_t) * m->Nm);
-  if (!m->x || !m->v || !m->fc || !m->fl || !m->chain) { kgdbref_destroy(m); return NULL; }
+  if (!m->x || !m->v || !m->fc || !m->fl || !m->du || !m->chain) { kgdbref_destroy(m); return NULL; }
   return m;
 }
 
@@ -642,6 +645,7 @@ melt_t *kgdbref_create(const kgdbref_params *p) {
   mb_velocities(m);
   if (warmup(m)) { kgdbref_destroy(m); return NULL; }
   m->step = 0; m->sweep = 0; m->last_sweep_step = 0;
+  memset(m->du, 0, sizeof(double) * 3 * (size_t)m->Nm);
   return m;
 }
 
@@ -696,6 +700,7 @@ int kgdbref_set_state(melt_t *m, const double *x, const double *v, const double 
   if (fl) memcpy(m->fl, fl, n3 * sizeof(double));
   if (counters) { m->step = counters[0]; m->sweep = counters[1]; m->last_sweep_step = counters[2]; }
   m->fc_valid = 0;
+  memset(m->du, 0, sizeof(double) * 3 * (size_t)m->Nm); /* displacements count from the new state */
   return OR_OK;
 }
 
@@ -1060,6 +1065,57 @@ int kgdbref_observables(melt_t *m, double *r2n, double *ellK, double *meanbond) 
   if (ellK) rc = kgdbref_fit_ellK(r2n, N, l0, ellK);
   free(s); free(acc);
   return rc;
+}
+
+/* Structure observables of the appendices (App. A: g(r) and S(q); App. B: monomer MSD). */
+
+/* Histogram of the minimum-image distances of all ordered pairs i != j: counts[b] is the
+   number with b dr <= r < (b + 1) dr, dr = r_max / nbins (r_max <= L / 2).  g(r) follows by
+   dividing by N_m rho (4 pi / 3) ((b + 1)^3 - b^3) dr^3. */
+int kgdbref_pair_hist(melt_t *m, double r_max, int32_t nbins, uint64_t *counts) {
+  if (!(r_max > 0) || r_max > 0.5 * m->L || nbins < 1) { set_err("need 0 < r_max <= L/2, nbins >= 1"); return OR_E_PARAM; }
+  double dr = r_max / nbins;
+  memset(counts, 0, sizeof(uint64_t) * (size_t)nbins);
+  for (int i = 0; i < m->Nm; i++)
+    for (int j = 0; j < m->Nm; j++) {
+      if (i == j) continue;
+      double d[3];
+      disp(m, i, j, d);
+      double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+      if (r < r_max) {
+        int b = (int)(r / dr);
+        if (b < nbins) counts[b]++;
+      }
+    }
+  return OR_OK;
+}
+
+/* S(q) = |sum_j exp(i q . x_j)|^2 / N_m for the box's reciprocal-lattice vectors
+   q = (2 pi / L) (n_x, n_y, n_z), given as integer triples nvec[3 q + c]. */
+int kgdbref_structure_factor(melt_t *m, const int32_t *nvec, int64_t nq, double *S) {
+  int Nm = m->Nm;
+  for (int64_t q = 0; q < nq; q++) {
+    double k[3];
+    for (int c = 0; c < 3; c++) k[c] = 2.0 * M_PI / m->L * (double)nvec[3 * q + c];
+    double cs = 0.0, sn = 0.0;
+    for (int j = 0; j < Nm; j++) {
+      double ph = k[0] * m->x[j] + k[1] * m->x[Nm + j] + k[2] * m->x[2 * Nm + j];
+      cs += cos(ph);
+      sn += sin(ph);
+    }
+    S[q] = (cs * cs + sn * sn) / Nm;
+  }
+  return OR_OK;
+}
+
+/* Mean squared displacement of the monomers since the last reset (the drift of every step
+   accumulated without wrapping). */
+void kgdbref_msd_reset(melt_t *m) { memset(m->du, 0, sizeof(double) * 3 * (size_t)m->Nm); }
+double kgdbref_msd(const melt_t *m) {
+  double s = 0.0;
+  for (int i = 0; i < m->Nm; i++)
+    for (int c = 0; c < 3; c++) s += m->du[c * m->Nm + i] * m->du[c * m->Nm + i];
+  return s / m->Nm;
 }
 
 /* ------------------------------------------------------------------------------------ */

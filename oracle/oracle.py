@@ -102,6 +102,12 @@ def lib():
         L.kgdbref_md_steps.argtypes = [P, C.c_int64]
         L.kgdbref_set_potential.argtypes = [P, C.c_double, C.c_double]
         L.kgdbref_init_info.argtypes = [P, dp]
+        L.kgdbref_pair_hist.argtypes = [P, C.c_double, C.c_int32, up]
+        L.kgdbref_structure_factor.argtypes = [P, ip, C.c_int64, dp]
+        L.kgdbref_msd_reset.argtypes = [P]
+        L.kgdbref_msd_reset.restype = None
+        L.kgdbref_msd.argtypes = [P]
+        L.kgdbref_msd.restype = C.c_double
         L.kgdbref_cell_list.argtypes = [P, C.c_double, C.POINTER(C.c_int32), P, P, C.c_int64]
         L.kgdbref_candidates.argtypes = [P, C.c_int32, P, C.c_int64, C.POINTER(C.c_int64)]
         L.kgdbref_db_sweep.argtypes = [P, C.c_int64, C.c_int32, C.POINTER(Stats)]
@@ -210,6 +216,25 @@ class Melt:
 
     def md_steps(self, n):
         _check(lib().kgdbref_md_steps(self.h, n))
+
+    def pair_hist(self, r_max, nbins):
+        """Ordered-pair counts of minimum-image distances in nbins bins over [0, r_max)."""
+        out = np.zeros(nbins, np.uint64)
+        _check(lib().kgdbref_pair_hist(self.h, float(r_max), int(nbins), out))
+        return out
+
+    def structure_factor(self, nvec):
+        """S(q) for reciprocal-lattice vectors q = 2 pi n / L (n: [nq][3] integers)."""
+        n = np.ascontiguousarray(nvec, np.int32).reshape(-1, 3)
+        out = np.zeros(len(n))
+        _check(lib().kgdbref_structure_factor(self.h, n.ravel(), len(n), out))
+        return out
+
+    def msd_reset(self):
+        lib().kgdbref_msd_reset(self.h)
+
+    def msd(self):
+        return lib().kgdbref_msd(self.h)
 
     def init_info(self):
         """(init mode, states drawn, l_K fitted to the accepted freely rotating state)."""
