@@ -226,6 +226,29 @@ int kgdb_nl_info(kgdb_batch* b, double out[4]);
 /* geometry of melt `melt`: out = {L, MD cells per side, double-bridging cells per side,
    FENE constant in use (k_n of Eq. 9 or the literal value)} */
 int kgdb_melt_geometry(const kgdb_batch* b, int32_t melt, double out[4]);
+/* ---- structure observables (App. A: g(r), S(q); App. B: monomer MSD) ---- */
+
+/* Pair correlation of melt `melt` at the current positions: counts[b] (may be NULL) = number
+   of ordered pairs i != j whose minimum-image distance r satisfies b dr <= r < (b + 1) dr,
+   dr = r_max / nbins, bonded pairs included; g[b] (may be NULL) = counts[b] /
+   (N_m rho (4 pi / 3) ((b + 1)^3 - b^3) dr^3).  KGDB_E_PARAM unless 0 < r_max <= L/2,
+   1 <= nbins <= 8192 and the MD cells within r_max span less than the box. */
+int kgdb_pair_correlation(kgdb_batch* b, int32_t melt, double r_max, int32_t nbins, uint64_t* counts, double* g);
+
+/* Static structure factor of melt `melt`: S[q] = |sum_j exp(i k . x_j)|^2 / N_m for the box's
+   reciprocal-lattice vectors k = (2 pi / L) (nvec[3q], nvec[3q + 1], nvec[3q + 2]),
+   q < nq (caller-owned host arrays). */
+int kgdb_structure_factor(kgdb_batch* b, int32_t melt, const int32_t* nvec, int64_t nq, double* S);
+
+/* Monomer mean squared displacement.  kgdb_msd_reset starts tracking every melt from its
+   current positions (the first call allocates 48 bytes per monomer); each kgdb_md_steps call
+   then adds the minimum-image displacement since the previous call (a call must move no
+   monomer by L/2: runs of up to some thousand steps), and kgdb_set_state restarts the melt
+   it sets.  kgdb_msd gives the mean over melt `melt`'s monomers of the squared displacement
+   since the reset; KGDB_E_STATE before any reset. */
+int kgdb_msd_reset(kgdb_batch* b);
+int kgdb_msd(kgdb_batch* b, int32_t melt, double* msd);
+
 /* initial state of melt `melt`: out = {init_mode, states drawn (1 for random walks), l_K fitted
    to the accepted freely rotating state (0 for random walks)} */
 int kgdb_init_info(const kgdb_batch* b, int32_t melt, double out[3]);

@@ -175,6 +175,29 @@ class Batch:
         check(load().kgdb_nl_info(self._h, ptr(out)))
         return dict(K=int(out[0]), skin=out[1], mean_list=out[2], rollbacks=int(out[3]))
 
+    # ---- structure observables
+    def pair_correlation(self, r_max, nbins, melt=0):
+        """(ordered-pair counts, g(r)) in nbins bins over [0, r_max)."""
+        counts = np.zeros(nbins, np.uint64)
+        g = np.zeros(nbins)
+        check(load().kgdb_pair_correlation(self._h, int(melt), float(r_max), int(nbins), ptr(counts), ptr(g)))
+        return counts, g
+
+    def structure_factor(self, nvec, melt=0):
+        """S(q) for reciprocal-lattice vectors q = 2 pi n / L (n: [nq][3] integers)."""
+        n = np.ascontiguousarray(nvec, np.int32).reshape(-1, 3)
+        out = np.zeros(len(n))
+        check(load().kgdb_structure_factor(self._h, int(melt), ptr(n), len(n), ptr(out)))
+        return out
+
+    def msd_reset(self):
+        check(load().kgdb_msd_reset(self._h))
+
+    def msd(self, melt=0):
+        v = C.c_double()
+        check(load().kgdb_msd(self._h, int(melt), C.byref(v)))
+        return v.value
+
     def init_info(self, melt=0):
         """(init mode, states drawn, l_K fitted to the accepted freely rotating state)."""
         out = np.zeros(3)

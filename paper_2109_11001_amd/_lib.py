@@ -71,6 +71,7 @@ EXPORTS = [
     "kgdb_mlp_nparam", "kgdb_set_proposal_net", "kgdb_db_sweep_log", "kgdb_features", "kgdb_candidate_logits",
     "kgdb_mlp_workspace_bytes", "kgdb_mlp_forward", "kgdb_mlp_grad", "kgdb_mlp_adam", "kgdb_mlp_train_step",
     "kgdb_set_potential", "kgdb_protocol_schedule", "kgdb_run_protocol", "kgdb_init_info",
+    "kgdb_pair_correlation", "kgdb_structure_factor", "kgdb_msd_reset", "kgdb_msd",
 ]
 MLP_NPARAM = 36481
 
@@ -125,6 +126,10 @@ def load():
     L.kgdb_mlp_train_step.argtypes = [P, P, P, P, P, i64, i64, dbl, dbl, dbl, dbl, P, i64, P, P]
     L.kgdb_set_potential.argtypes = [P, i32, dbl, dbl]
     L.kgdb_init_info.argtypes = [P, i32, P]
+    L.kgdb_pair_correlation.argtypes = [P, i32, dbl, i32, P, P]
+    L.kgdb_structure_factor.argtypes = [P, i32, P, i64, P]
+    L.kgdb_msd_reset.argtypes = [P]
+    L.kgdb_msd.argtypes = [P, i32, P]
     L.kgdb_protocol_schedule.argtypes = [dbl, i32, dbl, dbl, P, P, P]
     L.kgdb_run_protocol.argtypes = [P, P, P, i32, i64, P]
     for f in EXPORTS:

@@ -39,6 +39,12 @@ constexpr int PROF_EVENTS = 256; // event pairs per profiling batch
 struct kgdb_batch {
   int nm = 0;
   std::vector<kgdb_params> P;
+  // mean squared displacement: per monomer id, the last position and the accumulated
+  // minimum-image displacement (allocated by the first kgdb_msd_reset)
+  double* d_msd_last = nullptr;
+  double* d_msd_acc = nullptr;
+  double* d_msd_out = nullptr;
+  bool msd_on = false;
   std::vector<int> init_drawn;      // initial states drawn per melt
   std::vector<double> init_ellK;    // l_K fitted to the accepted freely rotating state
   std::vector<MeltDesc> D;
@@ -595,6 +601,8 @@ static int run_steps(kgdb_batch* b, int64_t n, bool graph) {
   b->fc_valid = true;
   b->cells_valid = false;
   CHK(check_errors(b));
+  if (b->msd_on)  // a run of steps moves a monomer far less than L / 2
+    launch_msd_track(b->d_md, b->pm, b->NP, b->d_x[b->cur], b->d_mono, b->d_msd_last, b->d_msd_acc, 0, -1, b->s);
   if (b->reorder) CHK(reorder_storage(b));
   b->xver++;
   // A rollback answers one fast monomer, usually a rare event: after NL_CLEAN_PASSES clean
@@ -1188,6 +1196,8 @@ int kgdb_set_state(kgdb_batch* b, int32_t melt, const double* x, const double* v
   b->cells_valid = false;
   b->fc_valid = false;
   b->xver++;
+  if (b->msd_on)  // displacements count from the new state
+    launch_msd_track(b->d_md, b->pm, b->NP, b->d_x[b->cur], b->d_mono, b->d_msd_last, b->d_msd_acc, 1, melt, b->s);
   return 0;
 }
 
@@ -1414,6 +1424,81 @@ int kgdb_observables(kgdb_batch* b, int32_t melt, double* r2_over_n, double* ell
   return melt_observables(b, melt, r2_over_n, ell_K, mean_bond);
 }
 
+int kgdb_pair_correlation(kgdb_batch* b, int32_t melt, double r_max, int32_t nbins, uint64_t* counts, double* g) {
+  CHK(check_melt(b, melt));
+  const MeltDesc& d = b->D[melt];
+  if (!(r_max > 0) || r_max > 0.5 * d.L || nbins < 1 || nbins > 8192)
+    return fail(KGDB_E_PARAM, "need 0 < r_max <= L/2 and 1 <= nbins <= 8192");
+  const int R = (int)std::ceil(r_max / d.h);
+  if (2 * R + 1 > d.nc) return fail(KGDB_E_PARAM, "r_max reaches past half the box's cells");
+  CHK(ensure_cells(b));
+  unsigned long long* dh = nullptr;
+  HIPCHK(hipMallocAsync((void**)&dh, sizeof(unsigned long long) * nbins, b->s));
+  launch_fill_i32((int*)dh, 2 * nbins, 0, b->s);
+  launch_pair_hist(b->d_md, melt, d.Nm, b->NP, b->d_x[b->cur], b->d_cell_of, b->d_cnt[b->cur], b->d_bucket, r_max,
+                   nbins, R, dh, b->s);
+  std::vector<unsigned long long> h(nbins);
+  const hipError_t e1 = hipGetLastError();
+  const hipError_t e2 = hipMemcpyAsync(h.data(), dh, sizeof(unsigned long long) * nbins, hipMemcpyDeviceToHost, b->s);
+  const hipError_t e3 = hipFreeAsync(dh, b->s);
+  HIPCHK(hipStreamSynchronize(b->s));
+  if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) return fail(KGDB_E_HIP, "pair histogram");
+  CHK(check_errors(b));
+  // g(r) at bin b: pairs / (N_m rho (4 pi / 3) ((b + 1)^3 - b^3) dr^3), rho = N_m / L^3
+  const double dr = r_max / nbins, rho = d.Nm / (d.L * d.L * d.L);
+  for (int q = 0; q < nbins; ++q) {
+    if (counts) counts[q] = h[q];
+    if (g) {
+      const double shell = 4.0 * 3.141592653589793 / 3.0 * (std::pow(q + 1.0, 3) - std::pow((double)q, 3)) * dr * dr * dr;
+      g[q] = (double)h[q] / (d.Nm * rho * shell);
+    }
+  }
+  return 0;
+}
+
+int kgdb_structure_factor(kgdb_batch* b, int32_t melt, const int32_t* nvec, int64_t nq, double* S) {
+  CHK(check_melt(b, melt));
+  if (nq < 0 || (nq > 0 && (!nvec || !S)) || nq > (1 << 24)) return fail(KGDB_E_PARAM, "bad q list");
+  if (nq == 0) return 0;
+  int* dn = nullptr;
+  double* dS = nullptr;
+  HIPCHK(hipMallocAsync((void**)&dn, sizeof(int) * 3 * nq, b->s));
+  HIPCHK(hipMallocAsync((void**)&dS, sizeof(double) * nq, b->s));
+  HIPCHK(hipMemcpyAsync(dn, nvec, sizeof(int) * 3 * nq, hipMemcpyHostToDevice, b->s));
+  launch_structure_factor(b->d_md, melt, b->NP, b->d_x[b->cur], dn, nq, dS, b->s);
+  const hipError_t e1 = hipGetLastError();
+  const hipError_t e2 = hipMemcpyAsync(S, dS, sizeof(double) * nq, hipMemcpyDeviceToHost, b->s);
+  (void)hipFreeAsync(dn, b->s);
+  (void)hipFreeAsync(dS, b->s);
+  HIPCHK(hipStreamSynchronize(b->s));
+  if (e1 != hipSuccess || e2 != hipSuccess) return fail(KGDB_E_HIP, "structure factor");
+  return 0;
+}
+
+int kgdb_msd_reset(kgdb_batch* b) {
+  if (!b) return fail(KGDB_E_PARAM, "bad handle");
+  if (!b->d_msd_last) {
+    CHK(dalloc(b, &b->d_msd_last, 3 * (size_t)b->NP));
+    CHK(dalloc(b, &b->d_msd_acc, 3 * (size_t)b->NP));
+    CHK(dalloc(b, &b->d_msd_out, 1));
+  }
+  launch_msd_track(b->d_md, b->pm, b->NP, b->d_x[b->cur], b->d_mono, b->d_msd_last, b->d_msd_acc, 1, -1, b->s);
+  HIPCHK(hipGetLastError());
+  b->msd_on = true;
+  return 0;
+}
+
+int kgdb_msd(kgdb_batch* b, int32_t melt, double* msd) {
+  CHK(check_melt(b, melt));
+  if (!msd) return fail(KGDB_E_PARAM, "null argument");
+  if (!b->msd_on) return fail(KGDB_E_STATE, "displacements are not tracked: call kgdb_msd_reset first");
+  launch_msd_reduce(b->d_md, melt, b->NP, b->d_msd_acc, b->d_msd_out, b->s);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipMemcpyAsync(msd, b->d_msd_out, sizeof(double), hipMemcpyDeviceToHost, b->s));
+  HIPCHK(hipStreamSynchronize(b->s));
+  return 0;
+}
+
 int kgdb_init_info(const kgdb_batch* b, int32_t melt, double out[3]) {
   CHK(check_melt(b, melt));
   if (!out) return fail(KGDB_E_PARAM, "null argument");
@@ -1510,10 +1595,11 @@ int kgdb_autotune(kgdb_batch* b, int32_t nl_every, int32_t reps, int32_t* chosen
     (void)hipMemcpyAsync(back ? b->d_step : sst, back ? sst : b->d_step, b->nm * sizeof(uint64_t),
                          hipMemcpyDeviceToDevice, b->s);
   };
-  const bool was_reorder = b->reorder, was_fc = b->fc_valid, was_prof = b->prof;
+  const bool was_reorder = b->reorder, was_fc = b->fc_valid, was_prof = b->prof, was_msd = b->msd_on;
   const int was_cur = b->cur;
   const std::vector<uint64_t> was_step = b->step;
   b->reorder = false;
+  b->msd_on = false;  // the trial steps are undone
   copy_state(false);
   double best = INFINITY;
   int best_q = b->nl_ki, rc = 0;
@@ -1542,6 +1628,7 @@ int kgdb_autotune(kgdb_batch* b, int32_t nl_every, int32_t reps, int32_t* chosen
   (void)hipFree(sx);
   (void)hipFree(sst);
   b->reorder = was_reorder;
+  b->msd_on = was_msd;
   b->prof_force_ms = b->prof_fin_ms = 0;
   b->prof_force_n = b->prof_fin_n = 0;
   CHK(set_nl_interval(b, best_q));

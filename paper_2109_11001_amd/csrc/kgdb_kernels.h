@@ -121,6 +121,14 @@ void launch_random_walks(const MeltDesc* md, int nm, int max_M, int NP, double* 
                          hipStream_t s);
 void launch_fr_chains(const MeltDesc* md, int nm, int max_M, int NP, double* x, const int* tries, hipStream_t s);
 double kuhn_over_l0(double kappa);  // Eq. 12
+void launch_pair_hist(const MeltDesc* md, int k, int Nm, int NP, const double* x, const int* cell_of,
+                      const int* cnt, const int* bucket, double r_max, int nbins, int R, unsigned long long* hist,
+                      hipStream_t s);
+void launch_structure_factor(const MeltDesc* md, int k, int NP, const double* x, const int* nvec, int64_t nq,
+                             double* S, hipStream_t s);
+void launch_msd_track(const MeltDesc* md, const BlockMap& pm, int NP, const double* x, const int* mono, double* last,
+                      double* acc, int reset, int only, hipStream_t s);
+void launch_msd_reduce(const MeltDesc* md, int k, int NP, const double* acc, double* out, hipStream_t s);
 void launch_velocities(const MeltDesc* md, const BlockMap& pm, int NP, double* v, hipStream_t s);
 void launch_remove_mean(const MeltDesc* md, int nm, int NP, double* v, hipStream_t s);
 void launch_reduce_melt(const MeltDesc* md, int nm, int NP, const double* outE, const double* v,

@@ -187,6 +187,130 @@ __global__ __launch_bounds__(256) void k_r2(int M, int N, const double* __restri
 }
 
 // ---------------------------------------------------------------------------------------
+// Structure observables of the appendices: g(r) (App. A) from a histogram of pair distances,
+// S(q) (App. A) on the box's reciprocal lattice, and the monomer mean squared displacement
+// (App. B) from displacements accumulated between runs of steps.
+// ---------------------------------------------------------------------------------------
+
+// Ordered pairs i != j of melt k with minimum-image distance r < r_max, counted into bins of
+// width r_max / nbins; j runs over the MD cells within R of i's cell (2 R + 1 <= nc, so each
+// cell is visited once).  Counts are integers, so the histogram is exact.
+__global__ __launch_bounds__(256) void k_pair_hist(const MeltDesc* __restrict__ md, int k, int NP,
+                                                   const double* __restrict__ x, const int* __restrict__ cell_of,
+                                                   const int* __restrict__ cnt, const int* __restrict__ bucket,
+                                                   double r_max, int nbins, int R,
+                                                   unsigned long long* __restrict__ hist) {
+  extern __shared__ unsigned int s_hist[];
+  for (int b = threadIdx.x; b < nbins; b += blockDim.x) s_hist[b] = 0;
+  __syncthreads();
+  const MeltDesc& d = md[k];
+  const int li = blockIdx.x * blockDim.x + threadIdx.x;
+  if (li < d.Nm) {
+    const int g = d.off + li;
+    const int nc = d.nc, lc = cell_of[g] - d.cell_off;
+    const int cx = lc % nc, cy = (lc / nc) % nc, cz = lc / (nc * nc);
+    const double xi = x[g], yi = x[NP + g], zi = x[2 * NP + g];
+    const double dr = r_max / nbins;
+    for (int oz = -R; oz <= R; ++oz)
+      for (int oy = -R; oy <= R; ++oy)
+        for (int ox = -R; ox <= R; ++ox) {
+          const int c = d.cell_off + ((((cz + oz) % nc + nc) % nc * nc + ((cy + oy) % nc + nc) % nc) * nc +
+                                      ((cx + ox) % nc + nc) % nc);
+          const int n = min(cnt[c], CELL_CAP);
+          for (int s = 0; s < n; ++s) {
+            const int j = bucket[c * CELL_CAP + s];
+            if (j == g) continue;
+            const double ddx = min_image(x[j] - xi, d.L), ddy = min_image(x[NP + j] - yi, d.L),
+                         ddz = min_image(x[2 * NP + j] - zi, d.L);
+            const double r = sqrt(ddx * ddx + ddy * ddy + ddz * ddz);
+            if (r < r_max) {
+              const int b = (int)(r / dr);
+              if (b < nbins) atomicAdd(&s_hist[b], 1u);
+            }
+          }
+        }
+  }
+  __syncthreads();
+  for (int b = threadIdx.x; b < nbins; b += blockDim.x)
+    if (s_hist[b]) atomicAdd(&hist[b], (unsigned long long)s_hist[b]);
+}
+
+// S(q) = |sum_j exp(i q . x_j)|^2 / N_m for q = (2 pi / L) nvec[3 q ..], one workgroup per q
+__global__ __launch_bounds__(256) void k_structure_factor(const MeltDesc* __restrict__ md, int k, int NP,
+                                                          const double* __restrict__ x,
+                                                          const int* __restrict__ nvec, double* __restrict__ S) {
+  __shared__ double s[256];
+  const MeltDesc& d = md[k];
+  const int q = blockIdx.x;
+  const double f = 2.0 * 3.141592653589793 / d.L;
+  const double kx = f * nvec[3 * q], ky = f * nvec[3 * q + 1], kz = f * nvec[3 * q + 2];
+  double cs = 0.0, sn = 0.0;
+  for (int li = threadIdx.x; li < d.Nm; li += blockDim.x) {
+    const int g = d.off + li;
+    const double ph = kx * x[g] + ky * x[NP + g] + kz * x[2 * NP + g];
+    cs += cos(ph);
+    sn += sin(ph);
+  }
+  cs = block_sum<256>(cs, s);
+  sn = block_sum<256>(sn, s);
+  if (threadIdx.x == 0) S[q] = (cs * cs + sn * sn) / d.Nm;
+}
+
+// displacement tracking by monomer id: reset (last = x, acc = 0) or update (acc += the
+// minimum-image step since last, last = x) for melt `only` (< 0: every melt)
+__global__ __launch_bounds__(256) void k_msd_track(const MeltDesc* __restrict__ md, const int* __restrict__ blk_melt,
+                                                   const int* __restrict__ blk_base, int NP,
+                                                   const double* __restrict__ x, const int* __restrict__ mono,
+                                                   double* __restrict__ last, double* __restrict__ acc, int reset,
+                                                   int only) {
+  const int k = blk_melt[blockIdx.x];
+  if (only >= 0 && k != only) return;
+  const MeltDesc& d = md[k];
+  const int li = blk_base[blockIdx.x] + (int)threadIdx.x;
+  if (li >= d.Nm) return;
+  const int g = d.off + li, id = d.off + mono[g];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const double xn = x[(size_t)c * NP + g];
+    if (reset) acc[(size_t)c * NP + id] = 0.0;
+    else acc[(size_t)c * NP + id] += min_image(xn - last[(size_t)c * NP + id], d.L);
+    last[(size_t)c * NP + id] = xn;
+  }
+}
+
+// mean over melt k's monomers of |acc|^2 (fixed-order block sum)
+__global__ __launch_bounds__(256) void k_msd_reduce(const MeltDesc* __restrict__ md, int k, int NP,
+                                                    const double* __restrict__ acc, double* __restrict__ out) {
+  __shared__ double s[256];
+  const MeltDesc& d = md[k];
+  double v = 0.0;
+  for (int li = threadIdx.x; li < d.Nm; li += blockDim.x) {
+    const int id = d.off + li;
+    for (int c = 0; c < 3; ++c) v += acc[(size_t)c * NP + id] * acc[(size_t)c * NP + id];
+  }
+  v = block_sum<256>(v, s);
+  if (threadIdx.x == 0) out[0] = v / d.Nm;
+}
+
+void launch_pair_hist(const MeltDesc* md, int k, int Nm, int NP, const double* x, const int* cell_of,
+                      const int* cnt, const int* bucket, double r_max, int nbins, int R, unsigned long long* hist,
+                      hipStream_t s) {
+  hipLaunchKernelGGL(k_pair_hist, dim3((Nm + 255) / 256), dim3(256), sizeof(unsigned int) * nbins, s, md, k, NP, x,
+                     cell_of, cnt, bucket, r_max, nbins, R, hist);
+}
+void launch_structure_factor(const MeltDesc* md, int k, int NP, const double* x, const int* nvec, int64_t nq,
+                             double* S, hipStream_t s) {
+  if (nq > 0) hipLaunchKernelGGL(k_structure_factor, dim3((unsigned)nq), dim3(256), 0, s, md, k, NP, x, nvec, S);
+}
+void launch_msd_track(const MeltDesc* md, const BlockMap& pm, int NP, const double* x, const int* mono, double* last,
+                      double* acc, int reset, int only, hipStream_t s) {
+  hipLaunchKernelGGL(k_msd_track, dim3(pm.nblk), dim3(256), 0, s, md, pm.melt, pm.base, NP, x, mono, last, acc,
+                     reset, only);
+}
+void launch_msd_reduce(const MeltDesc* md, int k, int NP, const double* acc, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_msd_reduce, dim3(1), dim3(256), 0, s, md, k, NP, acc, out);
+}
+
 void launch_random_walks(const MeltDesc* md, int nm, int max_M, int NP, double* x, int* chain, int* loc,
                          hipStream_t s) {
   hipLaunchKernelGGL(k_random_walks, dim3((max_M + 63) / 64, nm), dim3(64), 0, s, md, NP, x, chain, loc);

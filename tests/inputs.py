@@ -57,3 +57,20 @@ def random_mlp_params(seed, w_scale=0.25, b_scale=0.5):
 def random_labels(n, seed, p=0.3):
     rng = np.random.default_rng(seed + 49979687)
     return (rng.uniform(size=n) < p).astype(np.int32)
+
+
+def qvectors(L, q_max, nbins, per_bin, seed=0):
+    """Reciprocal-lattice vectors n (q = 2 pi n / L) spread over nbins shells of |q| < q_max:
+    per shell, up to per_bin seeded random directions and magnitudes rounded to the lattice
+    (duplicates and q = 0 dropped).  Returns an int32 array [nq][3]."""
+    rng = np.random.default_rng(seed)
+    dq = q_max / nbins
+    out = set()
+    for b in range(nbins):
+        for _ in range(per_bin):
+            v = rng.normal(size=3)
+            v *= (b + rng.random()) * dq / np.linalg.norm(v)
+            n = tuple(int(t) for t in np.rint(v * L / (2 * np.pi)))
+            if n != (0, 0, 0):
+                out.add(n)
+    return np.array(sorted(out), np.int32).reshape(-1, 3)
