@@ -18,6 +18,8 @@ timed with the learned and with the uniform proposal from one shared state.
 """
 import hashlib
 import math
+
+import numpy as np
 import re
 import argparse
 import json
@@ -348,7 +350,36 @@ def run_protocol_bench(kg, stream, kappa, steps_per_stage, sweep_every=100):
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     plan = kg.protocol_schedule(kappa, PAPER_SYSTEM["N"], dt=PAPER_SYSTEM["dt"])
-    st = b.run_protocol(plan["n"], [steps_per_stage] * len(plan["n"]), sweep_every=sweep_every)
+    # structure at the end of each stage (App. A): g(r) to 3 sigma and S(q) on ~5,000
+    # reciprocal-lattice vectors up to 12 / sigma, averaged in shells of 0.1 / sigma (the peak
+    # from the three-shell running mean)
+    from tests.inputs import qvectors  # seeded choice of lattice vectors (no method arithmetic)
+    L = b.geom[0]["L"]
+    nsh = 120
+    qv = qvectors(L, 12.0, nsh, 48, seed=1)
+    qmag = 2 * math.pi / L * np.linalg.norm(qv, axis=1)
+    edges = np.linspace(0.0, 12.0, nsh + 1)
+    st, structure, t_obs = [], [], []
+    for n, _ in zip(plan["n"], plan["steps"]):
+        st += b.run_protocol([n], [steps_per_stage], sweep_every=sweep_every)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, g = b.pair_correlation(3.0, 150)
+        t1 = time.perf_counter()
+        S = b.structure_factor(qv)
+        t2 = time.perf_counter()
+        t_obs.append((t1 - t0, t2 - t1))
+        idx = np.digitize(qmag, edges) - 1
+        Sb = np.array([S[idx == i].mean() if np.any(idx == i) else np.nan for i in range(nsh)])
+        qc = 0.5 * (edges[1:] + edges[:-1])
+        sm = np.convolve(np.nan_to_num(Sb, nan=0.0), np.ones(3) / 3, mode="same")
+        win = (qc > 4.0) & (qc < 10.0)
+        structure.append({"n": n, "S_peak_q": round(float(qc[win][np.argmax(sm[win])]), 2),
+                          "S_peak": round(float(np.max(sm[win])), 3),
+                          "S_q_below_1p5": round(float(np.nanmean(S[qmag < 1.5])), 4),
+                          "S_q_5_to_8": round(float(np.mean(S[(qmag > 5) & (qmag < 8)])), 4),
+                          "S_q_above_8": round(float(np.mean(S[qmag > 8])), 4),
+                          "g_peak_r": float((np.argmax(g) + 0.5) * 3.0 / 150), "g_peak": round(float(np.max(g)), 3)})
     nm, _ = b.sizes()
     b.close()
     stages, proj = [], 0.0
@@ -365,7 +396,9 @@ def run_protocol_bench(kg, stream, kappa, steps_per_stage, sweep_every=100):
                       f"dt {PAPER_SYSTEM['dt']}, mixed precision", "monomers": nm,
             "plan": {"steps_total": int(sum(plan["steps"])), "tau_eq": plan["tau_eq"], "scheme": plan["scheme"]},
             "steps_per_stage_timed": steps_per_stage, "sweep_every": sweep_every, "setup_s": round(setup_s, 2),
-            "stages": stages, "projected_full_protocol_s": round(proj, 1)}
+            "stages": stages, "projected_full_protocol_s": round(proj, 1), "structure": structure,
+            "q_vectors": int(len(qv)), "g_r_ms": round(1e3 * float(np.median([t[0] for t in t_obs])), 2),
+            "S_q_ms": round(1e3 * float(np.median([t[1] for t in t_obs])), 2)}
 
 
 def step_kernel_hash():
