@@ -380,6 +380,9 @@ def run_protocol_bench(kg, stream, kappa, steps_per_stage, sweep_every=100):
                           "S_q_5_to_8": round(float(np.mean(S[(qmag > 5) & (qmag < 8)])), 4),
                           "S_q_above_8": round(float(np.mean(S[qmag > 8])), 4),
                           "g_peak_r": float((np.argmax(g) + 0.5) * 3.0 / 150), "g_peak": round(float(np.max(g)), 3)})
+    # the swap rate of n = 12 alone (denominator of the speedup), from a longer n = 12 run
+    tail = b.run_protocol([plan["n"][-1]], [10 * steps_per_stage], sweep_every=sweep_every)[0]
+    s12 = tail["accepted"] / max(tail["attempts"] - tail["no_candidate"], 1)
     nm, _ = b.sizes()
     b.close()
     stages, proj = [], 0.0
@@ -392,7 +395,15 @@ def run_protocol_bench(kg, stream, kappa, steps_per_stage, sweep_every=100):
                        "monomer_steps_per_s": nm / (ms * 1e-3), "accepted": s_["accepted"], "attempts": tried,
                        "success_rate": s_["accepted"] / max(tried, 1), "paper_fit_success_rate": round(fit, 5)})
         proj += plan["steps"][i] * ms * 1e-3
-    return {"system": f"{PAPER_SYSTEM['M']} chains x {PAPER_SYSTEM['N']} beads, kappa {kappa}, rho 0.85, "
+    # Table I analogue, projected over the full plan from the measured rates: swaps per monomer
+    # (attempt rate x stage time x success rate, summed) and the speedup R over n = 12-only
+    # double bridging of the same length (the sum over stages of tau_i S_i over tau_eq S_12)
+    dtp = PAPER_SYSTEM["dt"]
+    swaps = sum(1e-3 * ps * dtp * stg["success_rate"] for ps, stg in zip(plan["steps"], stages))
+    R = sum(ps * stg["success_rate"] for ps, stg in zip(plan["steps"], stages)) / max(sum(plan["steps"]) * s12, 1e-300)
+    return {"table1_projection": {"swaps_per_monomer": round(swaps, 2), "R": round(R, 1),
+                                  "success_rate_n12": s12, "n12_attempts": tail["attempts"] - tail["no_candidate"]},
+            "system": f"{PAPER_SYSTEM['M']} chains x {PAPER_SYSTEM['N']} beads, kappa {kappa}, rho 0.85, "
                       f"dt {PAPER_SYSTEM['dt']}, mixed precision", "monomers": nm,
             "plan": {"steps_total": int(sum(plan["steps"])), "tau_eq": plan["tau_eq"], "scheme": plan["scheme"]},
             "steps_per_stage_timed": steps_per_stage, "sweep_every": sweep_every, "setup_s": round(setup_s, 2),
