@@ -69,10 +69,13 @@ class Batch:
         self._stream = stream
         self.params = [dict(DEFAULTS, **m) for m in melts]
         self.nm = len(melts)
+        self._read_geometry()
+
+    def _read_geometry(self):
         self.geom = []
         for k in range(self.nm):
             g = np.zeros(4)
-            check(L.kgdb_melt_geometry(h, k, ptr(g)))
+            check(load().kgdb_melt_geometry(self._h, k, ptr(g)))
             self.geom.append(dict(L=g[0], nc=int(g[1]), nc13=int(g[2]), k_fene=g[3]))
 
     def close(self):
@@ -213,6 +216,9 @@ class Batch:
     def set_potential(self, n_exp, k_fene=0.0, melt=-1):
         """Exponent n of Eqs. 5-6 and FENE constant (<= 0: Eq. 9) of one melt, or of all (-1)."""
         check(load().kgdb_set_potential(self._h, int(melt), float(n_exp), float(k_fene)))
+        for k in ([melt] if melt >= 0 else range(self.nm)):
+            self.params[k].update(n_exp=float(n_exp), k_fene=float(k_fene))
+        self._read_geometry()
 
     def run_protocol(self, n_values, steps, sweep_every=100):
         """Run the stages (n_values[i] for steps[i] MD steps, a sweep every sweep_every steps;
@@ -222,7 +228,9 @@ class Batch:
         if n.shape != st.shape:
             raise ValueError("n_values and steps differ in length")
         out = (StageStats * max(len(n), 1))()
-        check(load().kgdb_run_protocol(self._h, ptr(n), ptr(st), len(n), int(sweep_every), out))
+        rc = load().kgdb_run_protocol(self._h, ptr(n), ptr(st), len(n), int(sweep_every), out)
+        self._read_geometry()
+        check(rc)
         return [out[i].as_dict() for i in range(len(n))]
 
     # ---- learned proposal

@@ -111,3 +111,24 @@ def test_run_protocol_without_sweeps_is_plain_md():
     assert np.array_equal(sa["x"], sb["x"]) and np.array_equal(sa["chains"], sb["chains"])
     a.close()
     b.close()
+
+
+def test_set_potential_of_one_melt_in_a_batch():
+    # only the named melt changes its exponent; the other keeps its forces bit for bit
+    kw0 = dict(M=20, N=50, kappa=1.5, n_exp=12.0, seed=8)
+    kw1 = dict(M=15, N=40, kappa=0.5, n_exp=12.0, seed=9, melt_id=1)
+    o0, o1 = o.Melt(warmup_steps=100, **kw0), o.Melt(warmup_steps=100, **kw1)
+    gm = kg.Batch([dict(kw0, warmup_steps=0), dict(kw1, warmup_steps=0)])
+    for k, om in enumerate((o0, o1)):
+        st = om.get_state()
+        gm.set_state(k, x=st["x"], v=st["v"], fl=st["fl"], chains=st["chains"], counters=st["counters"])
+    F0, _, _ = gm.forces(0)
+    gm.set_potential(7.0, melt=1)
+    o1.set_potential(7.0)
+    F0b, _, _ = gm.forces(0)
+    assert np.array_equal(F0, F0b)
+    Fo, So, _ = o1.forces()
+    Fg, _, _ = gm.forces(1)
+    assert np.max(np.sqrt(((Fo - Fg) ** 2).sum(0)) / So) < 1e-12
+    assert gm.geom[1]["k_fene"] == pytest.approx(o.kn(7.0), rel=1e-12)
+    gm.close()
