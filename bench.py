@@ -335,6 +335,13 @@ def run_equilibration(kg, stream, steps, ref_steps, every=1000, tol=0.02, batch_
 PAPER_SYSTEM = dict(M=1000, N=400, dt=0.008)  # the paper's melts: 1000 chains of 400 beads, dt = tau / 125
 
 
+def kg_kuhn(kappa):
+    """l_K / l_0 of Eq. 12 (for the report only)."""
+    x = 2.0 * kappa
+    flory = 1.0 if kappa == 0 else (x + math.exp(-x) - 1.0) / (1.0 - math.exp(-x) * (x + 1.0))
+    return flory + 0.77 * (math.tanh(-0.03 * kappa ** 2 - 0.41 * kappa + 0.16) + 1.0)
+
+
 def run_protocol_bench(kg, stream, kappa, steps_per_stage, sweep_every=100):
     """The n-ramp protocol (Sec. II.B) on the paper's own melt size at stiffness kappa: every
     stage of the plan (Eqs. 11, 16-20) runs `steps_per_stage` steps with a sweep at the paper's
@@ -359,9 +366,25 @@ def run_protocol_bench(kg, stream, kappa, steps_per_stage, sweep_every=100):
     qv = qvectors(L, 12.0, nsh, 48, seed=1)
     qmag = 2 * math.pi / L * np.linalg.norm(qv, axis=1)
     edges = np.linspace(0.0, 12.0, nsh + 1)
+    full = steps_per_stage <= 0  # the whole plan, stage by stage
     st, structure, t_obs = [], [], []
-    for n, _ in zip(plan["n"], plan["steps"]):
-        st += b.run_protocol([n], [steps_per_stage], sweep_every=sweep_every)
+    t_run = time.perf_counter()
+    for n, plan_steps in zip(plan["n"], plan["steps"]):
+        todo = plan_steps if full else steps_per_stage
+        acc = None
+        while todo > 0:  # calls of at most 250,000 steps, each reported
+            c = min(todo, 250000)
+            r = b.run_protocol([n], [c], sweep_every=sweep_every)[0]
+            if acc is None:
+                acc = r
+            else:
+                for f_ in ("steps", "attempts", "no_candidate", "accepted", "wall_ms"):
+                    acc[f_] += r[f_]
+            todo -= c
+            if full:
+                print(f"[bench] protocol kappa {kappa}: n = {n}, {acc['steps']} of {plan_steps} steps, "
+                      f"{acc['accepted']} swaps", file=sys.stderr, flush=True)
+        st.append(acc)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         _, g = b.pair_correlation(3.0, 150)
@@ -380,8 +403,10 @@ def run_protocol_bench(kg, stream, kappa, steps_per_stage, sweep_every=100):
                           "S_q_5_to_8": round(float(np.mean(S[(qmag > 5) & (qmag < 8)])), 4),
                           "S_q_above_8": round(float(np.mean(S[qmag > 8])), 4),
                           "g_peak_r": float((np.argmax(g) + 0.5) * 3.0 / 150), "g_peak": round(float(np.max(g)), 3)})
+    run_s = time.perf_counter() - t_run
+    lk_end = b.observables()[1]
     # the swap rate of n = 12 alone (denominator of the speedup), from a longer n = 12 run
-    tail = b.run_protocol([plan["n"][-1]], [10 * steps_per_stage], sweep_every=sweep_every)[0]
+    tail = b.run_protocol([plan["n"][-1]], [10 * (steps_per_stage if not full else 1000)], sweep_every=sweep_every)[0]
     s12 = tail["accepted"] / max(tail["attempts"] - tail["no_candidate"], 1)
     nm, _ = b.sizes()
     b.close()
@@ -401,7 +426,13 @@ def run_protocol_bench(kg, stream, kappa, steps_per_stage, sweep_every=100):
     dtp = PAPER_SYSTEM["dt"]
     swaps = sum(1e-3 * ps * dtp * stg["success_rate"] for ps, stg in zip(plan["steps"], stages))
     R = sum(ps * stg["success_rate"] for ps, stg in zip(plan["steps"], stages)) / max(sum(plan["steps"]) * s12, 1e-300)
-    return {"table1_projection": {"swaps_per_monomer": round(swaps, 2), "R": round(R, 1),
+    out_full = None
+    if full:
+        out_full = {"wall_s": round(run_s, 1), "steps": int(sum(x["steps"] for x in st)),
+                    "swaps_per_monomer": round(sum(x["accepted"] for x in st) / nm, 3),
+                    "ell_K_end": lk_end, "ell_K_eq12": 0.960897 * kg_kuhn(kappa)}
+    return {"full_run": out_full,
+            "table1_projection": {"swaps_per_monomer": round(swaps, 2), "R": round(R, 1),
                                   "success_rate_n12": s12, "n12_attempts": tail["attempts"] - tail["no_candidate"]},
             "system": f"{PAPER_SYSTEM['M']} chains x {PAPER_SYSTEM['N']} beads, kappa {kappa}, rho 0.85, "
                       f"dt {PAPER_SYSTEM['dt']}, mixed precision", "monomers": nm,
@@ -527,6 +558,8 @@ def main():
                     help="time every stage of the n-ramp protocol for STEPS steps on the paper's 1000 x 400 "
                          "melt and project the full run")
     ap.add_argument("--protocol-kappa", default="2.0,5.5")
+    ap.add_argument("--protocol-full", type=float, default=None, metavar="KAPPA",
+                    help="run the whole plan (10^7 steps for kappa < 2.5) on the 1000 x 400 melt at KAPPA")
     ap.add_argument("--equilibration", type=int, default=0, metavar="STEPS",
                     help="time to equilibrium of R^2(n)/n for each form on a 2000 x 25 melt, STEPS steps each")
     ap.add_argument("--equilibration-ref", type=int, default=0, metavar="STEPS",
@@ -562,6 +595,9 @@ def main():
         prot.append(run_protocol_bench(kg, stream, kap, args.protocol))
         print(f"[bench] protocol kappa {kap}: projected {prot[-1]['projected_full_protocol_s']} s for "
               f"{prot[-1]['plan']['steps_total']} steps", file=sys.stderr, flush=True)
+    if args.protocol_full is not None:
+        print(f"[bench] full protocol run: kappa {args.protocol_full}", file=sys.stderr, flush=True)
+        prot.append(run_protocol_bench(kg, stream, args.protocol_full, 0))
     if args.no_main:
         print(json.dumps({"size_sweep": sweep, "equilibration": eq, "protocol": prot}), flush=True)
         return
