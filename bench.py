@@ -476,6 +476,19 @@ def copy_calibration(mib=256, reps=5):
     print(f"[bench] copy calibration: {reps} copies of {mib} MiB", file=sys.stderr, flush=True)
 
 
+def host_cpu():
+    """Model name and logical CPU count of the host the oracle ran on."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return f"{model} ({os.cpu_count()} logical CPUs visible)"
+
+
 def cpu_baseline(md_steps=15, db_attempts=8, stream=None):
     """The FP64 CPU oracle (single thread) on a bounded sample of the same workload; then, from
     the state it reached, the GPU path's error against it per result (untimed)."""
@@ -492,6 +505,7 @@ def cpu_baseline(md_steps=15, db_attempts=8, stream=None):
     K = round(1e-3 * nm * MD_PER_STEP * WORKLOAD["dt"])
     chunk = MD_PER_STEP * t_step + K * t_att
     out = {"value": nm * MD_PER_STEP / chunk, "unit": "monomer-timesteps/s", "cores": 1, "kind": "oracle",
+           "host_cpu": host_cpu(),
            "sample": f"200k-monomer workload melt: {md_steps} MD steps ({t_step:.3f} s each) and "
                      f"{db_attempts} DB attempts ({t_att:.3f} s each), scaled to one bench step of "
                      f"{MD_PER_STEP} MD steps + {K} attempts; single-threaded FP64 C oracle"}
