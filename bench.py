@@ -335,6 +335,56 @@ def run_equilibration(kg, stream, steps, ref_steps, every=1000, tol=0.02, batch_
 PAPER_SYSTEM = dict(M=1000, N=400, dt=0.008)  # the paper's melts: 1000 chains of 400 beads, dt = tau / 125
 
 
+BATCH_KAPPAS = (0.0, 0.5, 1.0, 1.5, 2.0, 2.5)
+BATCH_SHAPES = ((225, 100), (125, 200), (75, 400), (50, 800))  # (chains, beads): 22.5k-40k monomers
+
+
+def run_batch(kg, stream, steps, warmup, single_steps=10):
+    """24 uneven melts (every kappa of BATCH_KAPPAS with every shape of BATCH_SHAPES, 705,000
+    monomers) advanced as one batch: bench steps of 100 MD steps and one sweep per melt at the
+    attempt rate.  The same melts are then run one batch of one at a time for `single_steps`
+    bench steps each, for the gain of batching."""
+    import torch
+    melts = [dict(WORKLOAD, M=M, N=N, kappa=kap, melt_id=i, precision=kg.PREC_MIXED)
+             for i, (kap, (M, N)) in enumerate((k_, s_) for k_ in BATCH_KAPPAS for s_ in BATCH_SHAPES)]
+    t0 = time.perf_counter()
+    b = kg.Batch(melts, stream=stream)
+    K, _ = b.autotune(0, reps=20)
+    setup_s = time.perf_counter() - t0
+    nm, _ = b.sizes()
+    for _ in range(warmup):
+        b.md_steps(MD_PER_STEP)
+        b.db_sweep(-1)
+    torch.cuda.synchronize()
+    acc = 0
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        b.md_steps(MD_PER_STEP)
+        acc += sum(x["accepted"] for x in b.db_sweep(-1))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    b.close()
+    seq = 0.0
+    for m in melts:
+        g = kg.Batch([m], stream=stream)
+        g.autotune(0, reps=20)
+        g.md_steps(MD_PER_STEP)
+        g.db_sweep(-1)
+        torch.cuda.synchronize()
+        a0 = time.perf_counter()
+        for _ in range(single_steps):
+            g.md_steps(MD_PER_STEP)
+            g.db_sweep(-1)
+        torch.cuda.synchronize()
+        seq += (time.perf_counter() - a0) / single_steps
+        g.close()
+    return {"melts": len(melts), "monomers": nm, "rebuild_interval": K, "setup_s": round(setup_s, 2),
+            "ms_per_bench_step": round(1e3 * wall / steps, 3), "monomer_steps_per_s": nm * MD_PER_STEP * steps / wall,
+            "db_accepted_per_s": acc / wall,
+            "one_at_a_time_ms_per_bench_step": round(1e3 * seq, 3),
+            "batching_gain": round(seq / (wall / steps), 2)}
+
+
 def kg_kuhn(kappa):
     """l_K / l_0 of Eq. 12 (for the report only)."""
     x = 2.0 * kappa
@@ -568,6 +618,8 @@ def main():
                          "step kernel on single melts of these sizes (N = 1000), mixed path, MD only")
     ap.add_argument("--size-sweep-steps", type=int, default=500)
     ap.add_argument("--no-main", action="store_true", help="skip the workload runs (with --size-sweep or --equilibration)")
+    ap.add_argument("--batch", action="store_true",
+                    help="24 uneven melts (kappa 0-2.5, N 100-800, 705k monomers) as one batch vs one at a time")
     ap.add_argument("--protocol", type=int, default=0, metavar="STEPS",
                     help="time every stage of the n-ramp protocol for STEPS steps on the paper's 1000 x 400 "
                          "melt and project the full run")
@@ -609,11 +661,17 @@ def main():
         prot.append(run_protocol_bench(kg, stream, kap, args.protocol))
         print(f"[bench] protocol kappa {kap}: projected {prot[-1]['projected_full_protocol_s']} s for "
               f"{prot[-1]['plan']['steps_total']} steps", file=sys.stderr, flush=True)
+    bat = None
+    if args.batch:
+        print("[bench] batch of 24 melts", file=sys.stderr, flush=True)
+        bat = run_batch(kg, stream, args.steps, args.warmup)
+        print(f"[bench] batch: {bat['monomer_steps_per_s']:.3e} monomer-steps/s, gain {bat['batching_gain']}",
+              file=sys.stderr, flush=True)
     if args.protocol_full is not None:
         print(f"[bench] full protocol run: kappa {args.protocol_full}", file=sys.stderr, flush=True)
         prot.append(run_protocol_bench(kg, stream, args.protocol_full, 0))
     if args.no_main:
-        print(json.dumps({"size_sweep": sweep, "equilibration": eq, "protocol": prot}), flush=True)
+        print(json.dumps({"size_sweep": sweep, "equilibration": eq, "protocol": prot, "batch": bat}), flush=True)
         return
     print(f"[bench] mixed path: {args.warmup} warm-up + {args.steps} timed steps", file=sys.stderr, flush=True)
     mixed = run_gpu(kg, kg.PREC_MIXED, args.steps, args.warmup, stream, args.profile_steps)
@@ -684,6 +742,8 @@ def main():
         line["equilibration"] = eq
     if prot:
         line["protocol"] = prot
+    if bat:
+        line["batch"] = bat
     line["roofline"] = roof
     line["cpu_baseline"] = cpu
     print(json.dumps(line), flush=True)
