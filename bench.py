@@ -560,7 +560,34 @@ def cpu_baseline(md_steps=15, db_attempts=8, stream=None):
                      f"{db_attempts} DB attempts ({t_att:.3f} s each), scaled to one bench step of "
                      f"{MD_PER_STEP} MD steps + {K} attempts; single-threaded FP64 C oracle"}
     out["gpu_error_vs_oracle"] = oracle_errors(m, stream)
+    # the small workload (20 chains x 50 beads) in full on both sides
+    import torch
+    import paper_2109_11001_amd as kg
+    t_or, _ = small_run(lambda: o.Melt(**SMALL_WORKLOAD))
+    torch.cuda.synchronize()
+    t_gpu, g = small_run(lambda: kg.Batch([dict(WORKLOAD, **SMALL_WORKLOAD, precision=kg.PREC_FP64)], stream=stream))
+    torch.cuda.synchronize()
+    t_gpu = max(t_gpu, 1e-9)
+    g.close()
+    out["small_workload_full"] = {"workload": "20 chains x 50 beads, kappa 1.5, n 2: init with 1000 warm-up steps, "
+                                              "2000 MD steps, 20 sweeps of 1 attempt",
+                                  "oracle_s": round(t_or, 3), "gpu_fp64_s": round(t_gpu, 4)}
     return out
+
+
+SMALL_WORKLOAD = dict(M=20, N=50, kappa=1.5, n_exp=2.0, seed=1)  # 1000 monomers, L = 10.56 sigma
+
+
+def small_run(make, steps=2000, sweeps=20):
+    """The small workload in full: init with warm-up, then `steps` MD steps with a sweep of one
+    attempt every steps / sweeps steps.  `make` builds the melt (GPU binding or oracle)."""
+    t0 = time.perf_counter()
+    m = make()
+    every = steps // sweeps
+    for _ in range(sweeps):
+        m.md_steps(every)
+        m.db_sweep(1)
+    return time.perf_counter() - t0, m
 
 
 def oracle_errors(m, stream, attempts=20):
