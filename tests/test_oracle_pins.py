@@ -35,6 +35,31 @@ def test_box_muller_moments():
     assert abs((z ** 4).mean() - 3.0) < 0.15
 
 
+def test_box_muller_pairs_are_independent():
+    """The four normals of one draw are independent standard normals: the two of a
+    Box-Muller pair share a radius but take cosine and sine of one angle, so they are
+    uncorrelated, E[z0^2 z1^2] = 1, the angle atan2(z1, z0) is uniform and the squared
+    radius z0^2 + z1^2 is exponential with mean 2.  (This is what makes the x, y and z
+    components of the Langevin noise independent.)"""
+    n = 40000
+    z = np.array([o.normals(11, 2, i, 7, o.STREAM_LANGEVIN) for i in range(n)])
+    c = np.corrcoef(z.T)
+    assert np.max(np.abs(c - np.eye(4))) < 5.0 / np.sqrt(n)
+    for a, b in ((0, 1), (2, 3), (0, 2), (1, 3)):
+        # E[za^2 zb^2] = 1 for independent normals (sd of the estimate ~ sqrt(8/n))
+        assert abs(np.mean(z[:, a] ** 2 * z[:, b] ** 2) - 1.0) < 5 * np.sqrt(8.0 / n)
+    for a, b in ((0, 1), (2, 3)):
+        ang = np.arctan2(z[:, b], z[:, a])
+        cnt, _ = np.histogram(ang, bins=32, range=(-np.pi, np.pi))
+        chi2 = np.sum((cnt - n / 32) ** 2 / (n / 32))
+        assert chi2 < 31 + 5 * np.sqrt(62), chi2  # chi-square with 31 degrees of freedom
+        r2 = z[:, a] ** 2 + z[:, b] ** 2
+        # exponential with mean 2: P(r2 > t) = exp(-t / 2)
+        for t in (0.5, 2.0, 6.0):
+            p = np.exp(-t / 2)
+            assert abs(np.mean(r2 > t) - p) < 5 * np.sqrt(p * (1 - p) / n)
+
+
 # ----------------------------------------------------------------------- potentials
 @pytest.mark.parametrize("n", [2, 3, 4.5, 8, 9, 12, 18])
 @pytest.mark.parametrize("m", [6, 3])
@@ -48,6 +73,15 @@ def test_mie_minimum_and_symmetry(n, m):
     assert abs(slope) < 1e-7
     for r in (0.7, 0.95, 1.3, 2.0):
         assert o.mie(n, m, r) == pytest.approx(o.mie(m, n, r), rel=1e-13)
+
+
+@pytest.mark.parametrize("n,r,u", [(2, 0.8, 1.861757), (12, 0.8, 43.948872), (2, 0.9, 0.548489),
+                                   (12, 0.9, 7.636119), (2, 1.0, 0.110118), (12, 1.0, 1.000000),
+                                   (2, 0.5, 57.440474), (12, 0.5, 16129.0)])
+def test_eq6_truncated_values(n, r, u):
+    # values of the truncated and shifted MLJ^n of Eq. (6) (in eps), evaluated independently
+    # from the equation at the softest (n = 2) and the standard (n = 12) exponent
+    assert o.pair_u(n, r) == pytest.approx(u, abs=6e-7)
 
 
 def test_mie_12_6_is_standard_lj():
@@ -227,6 +261,114 @@ def test_langevin_free_particles_equipartition():
     assert abs(np.mean(v)) < 0.03
 
 
+def test_langevin_free_particles_half_step_statistics():
+    """Free particles under the kick-drift-kick Langevin step: the half-step velocity
+    v_h = v - (dt/2) F_L (forces off) obeys v_h' = (1 - gamma dt) v_h + dt sqrt(2 gamma T/dt) xi,
+    so its stationary variance is T / (1 - gamma dt / 2) and its lag-k autocorrelation
+    (1 - gamma dt)^k, while the full-step velocity has variance T exactly.  gamma dt = 0.1
+    makes the half-step variance 5.3% above T."""
+    T, gamma, dt = 1.3, 10.0, 0.01
+    m = o.Melt(M=20, N=50, test_flags=o.TF_NOFORCE, warmup_steps=0, T=T, gamma=gamma, dt=dt, seed=21)
+    m.md_steps(300)
+    vs, vhs = [], []
+    for _ in range(120):
+        m.md_steps(20)
+        st = m.get_state()
+        vs.append(st["v"].ravel())
+        vhs.append((st["v"] - 0.5 * dt * st["fl"]).ravel())
+    v, vh = np.concatenate(vs), np.concatenate(vhs)
+    se = np.sqrt(2.0 / v.size)
+    assert np.var(v) / T == pytest.approx(1.0, abs=5 * se)
+    assert np.var(vh) / (T / (1 - 0.5 * gamma * dt)) == pytest.approx(1.0, abs=5 * se)
+    # autocorrelation of v_h over consecutive steps
+    series = []
+    for _ in range(400):
+        m.md_steps(1)
+        st = m.get_state()
+        series.append((st["v"] - 0.5 * dt * st["fl"]).ravel())
+    X = np.array(series)  # stationary mean 0: a per-particle time mean would bias rho down
+    var = np.mean(X * X)
+    for k in (1, 2, 3, 5):
+        rho = np.mean(X[k:] * X[:-k]) / var
+        assert rho == pytest.approx((1 - gamma * dt) ** k, abs=0.01), k
+
+
+def _warmup_reference(seed, M, N, W, dt0, dt, cap, fcap0, T, gamma, n, rho):
+    """The warm-up of the initial state as the design reads the paper's small, ramped
+    initial timestep, written out here from that statement with brute-force pair sums:
+    W velocity-Verlet Langevin steps on the warm-up noise stream; step w uses
+    dt_w = dt0 (dt/dt0)^(w/(W-1)) and a pair-force cap f_w = fcap0 100^(w/(W-1)); each
+    half-step velocity is scaled down so that the step moves no monomer farther than cap;
+    a step's opening kick takes the force that the previous step's closing kick computed
+    (the first step computes it with its own cap).  Forces from the pinned radial pair and
+    FENE forces (kappa = 0: no angle term)."""
+    m0 = o.Melt(M=M, N=N, warmup_steps=0, seed=seed, kappa=0.0, T=T, gamma=gamma, dt=dt, n_exp=n, rho=rho)
+    st = m0.get_state()
+    x, v, ch, L, Nm, kf = st["x"].copy(), st["v"].copy(), st["chains"], m0.L, M * N, m0.kfene
+    bonds = {(min(a, b), max(a, b)) for c in ch for a, b in zip(c[:-1], c[1:])}
+
+    def forces(x, fcap):
+        F = np.zeros((3, Nm))
+        for i in range(Nm):
+            for j in range(i + 1, Nm):
+                d = x[:, j] - x[:, i]
+                d -= L * np.rint(d / L)
+                r = np.sqrt(d @ d)
+                f = min(o.pair_f(n, r), fcap)  # radial, positive = repulsive
+                if (i, j) in bonds:
+                    f += o.fene_f(kf, 1.5, r, 0.02)
+                F[:, i] -= f * d / r
+                F[:, j] += f * d / r
+        return F
+
+    fl = np.zeros((3, Nm))
+    F = forces(x, fcap0)
+    for w in range(W):
+        t = w / (W - 1)
+        dtw, fw = dt0 * (dt / dt0) ** t, fcap0 * 100.0 ** t
+        vh = v + 0.5 * dtw * (F + fl)
+        sp = np.sqrt((vh ** 2).sum(0))
+        over = dtw * sp > cap
+        vh[:, over] *= cap / (dtw * sp[over])
+        x = x + dtw * vh
+        x -= L * np.floor(x / L)
+        F = forces(x, fw)
+        z = np.array([o.normals(seed, 0, i, w + 1, o.STREAM_WARMUP)[:3] for i in range(Nm)]).T
+        fl = -gamma * vh + np.sqrt(2 * gamma * T / dtw) * z
+        v = vh + 0.5 * dtw * (F + fl)
+    return x, v, L, over
+
+
+def test_warmup_follows_its_reading():
+    """The oracle's warm-up equals the reading written out above; the pair-force cap and
+    the displacement cap both bind (random-walk overlaps), so a warm-up whose opening kick
+    recomputed the force with the step's own cap, a ramp indexed differently, or another
+    noise index would not match."""
+    kw = dict(seed=5, M=6, N=6, W=4, dt0=0.001, dt=0.01, cap=0.01, fcap0=10.0, T=1.0, gamma=1.0, n=2.0, rho=0.85)
+    x_ref, v_ref, L, over = _warmup_reference(**kw)
+    m = o.Melt(M=6, N=6, warmup_steps=4, warmup_dt0=0.001, warmup_max_disp=0.01, warmup_fcap=10.0, seed=5,
+               kappa=0.0, T=1.0, gamma=1.0, dt=0.01, n_exp=2.0, rho=0.85)
+    st = m.get_state()
+    d = st["x"] - x_ref
+    d -= L * np.rint(d / L)
+    assert np.max(np.abs(d)) < 1e-11
+    assert np.max(np.abs(st["v"] - v_ref)) < 1e-9 * max(1.0, np.max(np.abs(v_ref)))
+    assert np.any(over)  # the displacement cap was active in the last step
+
+
+def test_warmup_without_caps_is_plain_md():
+    """With the caps out of reach, no noise and dt0 = dt the warm-up is W ordinary
+    velocity-Verlet steps, bit for bit (one force evaluation per step in both)."""
+    # phantom chains (bonded pairs only) keep the forces of the random-walk start moderate
+    kw = dict(M=10, N=20, seed=8, kappa=1.5, n_exp=5.0, T=0.0, gamma=1.0, dt=0.002, rho=0.85,
+              test_flags=o.TF_PHANTOM)
+    a = o.Melt(warmup_steps=30, warmup_dt0=0.002, warmup_max_disp=1e9, warmup_fcap=1e300, **kw)
+    b = o.Melt(warmup_steps=0, **kw)
+    b.md_steps(30)
+    sa, sb = a.get_state(), b.get_state()
+    assert np.array_equal(sa["x"], sb["x"]) and np.array_equal(sa["v"], sb["v"])
+
+
 @pytest.mark.slow
 def test_phantom_chain_angle_and_bond_statistics():
     # nonbonded pairs off, bonded MLJ kept: cos(theta) follows sin(t) exp(k cos t),
@@ -235,7 +377,7 @@ def test_phantom_chain_angle_and_bond_statistics():
     kap, n = 1.5, 5.0
     m = o.Melt(M=100, N=10, test_flags=o.TF_PHANTOM, kappa=kap, n_exp=n, seed=4, warmup_steps=200)
     m.md_steps(3000)
-    cs, bs = [], []
+    cs, bs, r2 = [], [], []
     for _ in range(40):
         m.md_steps(100)
         st = m.get_state()
@@ -245,14 +387,26 @@ def test_phantom_chain_angle_and_bond_statistics():
         bl = np.sqrt((b ** 2).sum(0))
         bs.append(bl.ravel())
         cs.append(((b[:, :, :-1] * b[:, :, 1:]).sum(0) / (bl[:, :-1] * bl[:, 1:])).ravel())
+        s_ = np.concatenate([np.zeros((3, ch.shape[0], 1)), np.cumsum(b, axis=2)], axis=2)
+        # per chain, mean over i of |s_{i+n} - s_i|^2 for n = 1 .. N-1
+        r2.append(np.array([((s_[:, :, nn:] - s_[:, :, :-nn]) ** 2).sum(0).mean(1) for nn in range(1, 10)]))
+    c = 1 / math.tanh(kap) - 1 / kap
     c_mean = np.concatenate(cs).mean()
-    assert c_mean == pytest.approx(1 / math.tanh(kap) - 1 / kap, abs=0.01)
+    assert c_mean == pytest.approx(c, abs=0.01)
     k = o.kn(n)
     U = lambda r: o.pair_u(n, r) + o.fene_u(k, 1.5, r, 0.02)
     U0 = U(0.96)
     Z = integrate.quad(lambda r: r * r * math.exp(-(U(r) - U0)), 0.5, 1.5, limit=200)[0]
     mb = integrate.quad(lambda r: r ** 3 * math.exp(-(U(r) - U0)), 0.5, 1.5, limit=200)[0] / Z
+    mb2 = integrate.quad(lambda r: r ** 4 * math.exp(-(U(r) - U0)), 0.5, 1.5, limit=200)[0] / Z
     assert np.concatenate(bs).mean() == pytest.approx(mb, abs=0.004)
+    # bond lengths and directions are independent and successive directions correlate as
+    # c^k, so <R^2(n)> = n <b^2> + 2 <b>^2 sum_{k<n} (n - k) c^k
+    R = np.concatenate(r2, axis=1)  # [n][chain samples]
+    for nn in range(1, 10):
+        pred = nn * mb2 + 2 * mb * mb * sum((nn - kk) * c ** kk for kk in range(1, nn))
+        se = R[nn - 1].std() / np.sqrt(R.shape[1])
+        assert abs(R[nn - 1].mean() - pred) < 6 * se + 0.002 * pred, (nn, R[nn - 1].mean(), pred, se)
 
 
 # ------------------------------------------------------------------ init pins
@@ -335,15 +489,6 @@ def test_moves_are_involutions_and_antisymmetric():
         assert np.array_equal(m.get_state()["chains"], ch0)
 
 
-def _tiny_system(seed):
-    # 3 chains x 4 beads in a small periodic box, frozen positions
-    M, N = 3, 4
-    m = o.Melt(empty=True, M=M, N=N, kappa=1.0, n_exp=2.0, rho=0.85, seed=seed)
-    x = inputs.random_positions(M * N, m.L, seed)
-    m.set_state(x=x, chains=inputs.identity_chains(M, N))
-    return m
-
-
 def _bonded_energy(x, ch, L, k, kap, R0=1.5, amin=0.02):
     # bond (log part, floored) + angle energies of a topology; pair terms are constant
     E = 0.0
@@ -358,60 +503,112 @@ def _bonded_energy(x, ch, L, k, kap, R0=1.5, amin=0.02):
     return E
 
 
-@pytest.mark.slow
-@pytest.mark.parametrize("proposal", [0, 2])
-def test_db_detailed_balance_tiny(proposal):
-    """Exact MH (proposal 0) samples exp(-E/T) over topologies; the paper-literal
-    Metropolis rule (proposal 2) is biased when |C| varies between states."""
-    for seed in range(40, 80):
-        m = _tiny_system(seed)
-        m.p.proposal = proposal
-        # enumerate the reachable topology set by breadth-first search over moves
-        st = m.get_state()
-        x, L = st["x"], m.L
-        start = st["chains"].copy()
-        seen, frontier = {start.tobytes(): start}, [start]
-        while frontier:
-            nxt = []
-            for ch in frontier:
-                m.set_state(chains=ch)
-                for k in m.candidates(brute=True):
-                    m.set_state(chains=ch)
-                    m.apply_move(*o.key_decode(k, 3, 4))
-                    c2 = m.get_state()["chains"].copy()
-                    if c2.tobytes() not in seen:
-                        seen[c2.tobytes()] = c2
-                        nxt.append(c2)
-            frontier = nxt
-        ncs = []
-        for ch in seen.values():
+def _enumerate_topologies(m, M, N, limit):
+    """Breadth-first search over double-bridging moves from the current topology (frozen
+    positions); returns the reachable topologies, or None when there are more than limit."""
+    start = m.get_state()["chains"].copy()
+    seen, frontier = {start.tobytes(): start}, [start]
+    while frontier:
+        if len(seen) > limit:
+            return None
+        nxt = []
+        for ch in frontier:
             m.set_state(chains=ch)
-            ncs.append(len(m.candidates(brute=True)))
-        if len(seen) >= 4 and len(set(ncs)) > 1:
-            break
-    else:
-        pytest.skip("no suitable tiny system")
-    states = list(seen.values())
+            for k in m.candidates(brute=True):
+                m.set_state(chains=ch)
+                m.apply_move(*o.key_decode(k, M, N))
+                c2 = m.get_state()["chains"].copy()
+                if c2.tobytes() not in seen:
+                    seen[c2.tobytes()] = c2
+                    nxt.append(c2)
+        frontier = nxt
+    m.set_state(chains=start)
+    return list(seen.values())
+
+
+def _one_attempt_matrices(m, states, M, N, pi):
+    """Exact one-attempt transition matrices over the enumerated topologies, built here from
+    the candidate sets and the Boltzmann weights: the exact Metropolis-Hastings rule for a
+    proposal uniform over C(x) (Fig. 1 made exact: ratio pi(x') |C(x)| / (pi(x) |C(x')|), zero
+    when the reverse move is not a candidate of x') and the rule as printed (pi(x')/pi(x))."""
     idx = {s.tobytes(): i for i, s in enumerate(states)}
-    E = np.array([_bonded_energy(x, s, L, m.kfene, 1.0) for s in states])
-    pi = np.exp(-(E - E.min()))
-    pi /= pi.sum()
-    # run the oracle's own sampler, one attempt per sweep, counting visits
-    m2 = o.Melt(empty=True, M=3, N=4, kappa=1.0, n_exp=2.0, seed=seed, proposal=proposal)
-    m2.set_state(x=x, chains=start)
-    counts = np.zeros(len(states))
-    nsamp = 40000
-    for t in range(nsamp):
-        m2.db_sweep(1, brute=True)
-        counts[idx[m2.get_state()["chains"].tobytes()]] += 1
-    freq = counts / nsamp
-    if proposal == 0:
-        assert np.max(np.abs(freq - pi)) < 0.03, (freq, pi)
-    else:
-        # uniform proposal without the Hastings factor: expected pi_i ~ |C_i| exp(-E_i)
-        q = np.array(ncs) * np.exp(-(E - E.min()))
-        q /= q.sum()
-        assert np.max(np.abs(freq - q)) < 0.03
+    cand = []
+    for s in states:
+        m.set_state(chains=s)
+        cand.append(m.candidates(brute=True))
+    ns = len(states)
+    T_mh, T_lit = np.zeros((ns, ns)), np.zeros((ns, ns))
+    for a, s in enumerate(states):
+        n = len(cand[a])
+        for k in cand[a]:
+            m.set_state(chains=s)
+            m.apply_move(*o.key_decode(k, M, N))
+            b = idx[m.get_state()["chains"].tobytes()]
+            rev = k in set(cand[b].tolist())  # the reverse of a move is the same key
+            if rev:
+                T_mh[a, b] += min(1.0, pi[b] * n / (pi[a] * len(cand[b]))) / n
+            T_lit[a, b] += min(1.0, pi[b] / pi[a]) / n
+        T_mh[a, a] += 1.0 - T_mh[a].sum()
+        T_lit[a, a] += 1.0 - T_lit[a].sum()
+    return T_mh, T_lit, [len(c) for c in cand]
+
+
+@pytest.fixture(scope="module")
+def tiny_db_system():
+    """A tiny melt (2 chains x 4 beads, frozen seeded positions) whose reachable topologies
+    are few, whose candidate counts differ between topologies, and on which the exact and
+    the printed acceptance rules give clearly different one-attempt transition rows."""
+    M, N = 2, 4
+    for seed in range(40, 400):
+        m = o.Melt(empty=True, M=M, N=N, kappa=1.0, n_exp=2.0, rho=0.85, seed=seed)
+        m.set_state(x=inputs.random_positions(M * N, m.L, seed), chains=inputs.identity_chains(M, N))
+        states = _enumerate_topologies(m, M, N, 16)
+        if states is None or len(states) < 3:
+            continue
+        x = m.get_state()["x"]
+        E = np.array([_bonded_energy(x, s, m.L, m.kfene, 1.0) for s in states])
+        pi = np.exp(-(E - E.min()))
+        pi /= pi.sum()
+        T_mh, T_lit, nc = _one_attempt_matrices(m, states, M, N, pi)
+        if len(set(nc)) > 1 and np.max(np.abs(T_mh - T_lit)) > 0.08:
+            return dict(m=m, seed=seed, M=M, N=N, x=x, states=states, pi=pi, T_mh=T_mh, T_lit=T_lit)
+    pytest.skip("no suitable tiny system")
+
+
+def test_db_exact_matrix_is_stationary(tiny_db_system):
+    """The exact rule leaves exp(-E/T) invariant; the printed rule does not when |C| varies."""
+    t = tiny_db_system
+    pi = t["pi"]
+    assert np.allclose(t["T_mh"].sum(1), 1.0, atol=1e-14)
+    assert np.max(np.abs(pi @ t["T_mh"] - pi)) < 1e-14
+    assert np.max(np.abs(pi @ t["T_lit"] - pi)) > 1e-3
+
+
+@pytest.mark.parametrize("proposal", [0, 2])
+def test_db_sampler_reproduces_one_attempt_rows(tiny_db_system, proposal):
+    """Single attempts of the oracle's sampler, started many times from every enumerated
+    topology, reproduce that topology's row of the exact one-attempt matrix (proposal 0)
+    or of the printed rule's matrix (proposal 2), within a 5-sigma binomial bound; the
+    bound is far below the gap between the two matrices, so dropping the Hastings factor
+    |C(x)|/|C(x')| (or the reverse-move test) fails the proposal-0 case."""
+    t = tiny_db_system
+    M, N, states = t["M"], t["N"], t["states"]
+    T = t["T_mh"] if proposal == 0 else t["T_lit"]
+    idx = {s.tobytes(): i for i, s in enumerate(states)}
+    ns, S = len(states), 4000
+    m2 = o.Melt(empty=True, M=M, N=N, kappa=1.0, n_exp=2.0, seed=t["seed"], proposal=proposal)
+    m2.set_state(x=t["x"], chains=states[0])
+    for a, s in enumerate(states):
+        cnt = np.zeros(ns)
+        for _ in range(S):
+            m2.set_state(chains=s)
+            m2.db_sweep(1, brute=True)
+            cnt[idx[m2.get_state()["chains"].tobytes()]] += 1
+        sd = np.sqrt(np.maximum(T[a] * (1 - T[a]), 1e-4) / S)
+        assert np.all(np.abs(cnt / S - T[a]) < 5 * sd), (a, cnt / S, T[a])
+    # the bound discriminates the two rules on some row
+    sd_max = np.sqrt(0.25 / S)
+    assert np.max(np.abs(t["T_mh"] - t["T_lit"])) > 8 * sd_max
 
 
 # ----------------------------------------------------------------- observables
