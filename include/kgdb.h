@@ -311,6 +311,17 @@ int kgdb_mlp_train_step(float* params, float* m, float* v, const float* feat, co
                         int64_t t, double lr, double b1, double b2, double eps, void* ws, int64_t ws_bytes,
                         double* loss, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, serving
+   loops, harnesses that forbid hipMalloc): kgdb_mlp_train_step without the workspace
+   argument.  The workspace is a fixed device array of the library, one per GPU, sized for
+   n <= KGDB_MLP_STATIC_ROWS rows (about 21 MB; KGDB_E_PARAM beyond that) and held until the
+   process ends; the call allocates nothing.  All calls on one GPU share that array, so calls
+   that overlap on one GPU (concurrent streams or threads) race; serialise them. */
+#define KGDB_MLP_STATIC_ROWS 4096
+int kgdb_mlp_train_step_static(float* params, float* m, float* v, const float* feat, const int32_t* label,
+                               int64_t n, int64_t t, double lr, double b1, double b2, double eps, double* loss,
+                               void* stream);
+
 #ifdef __cplusplus
 }
 #endif

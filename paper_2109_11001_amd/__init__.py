@@ -327,6 +327,19 @@ def mlp_adam(params, m, v, grad, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8, stream=
                                _stream_ptr(stream)))
 
 
+def mlp_train_step_static(params, m, v, feat, label, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8, loss=None,
+                          stream=None):
+    """One Adam step on device tensors with the library's fixed workspace (no allocation by
+    the library; at most MLP_STATIC_ROWS rows).  Returns the loss tensor (device double)."""
+    import torch
+    n = feat.shape[0]
+    if loss is None:
+        loss = torch.zeros(1, dtype=torch.float64, device=params.device)
+    check(load().kgdb_mlp_train_step_static(_dptr(params), _dptr(m), _dptr(v), _dptr(feat), _dptr(label), n,
+                                            int(t), lr, b1, b2, eps, _dptr(loss), _stream_ptr(stream)))
+    return loss
+
+
 class Trainer:
     """FP32 master parameters, Adam moments and a workspace on the device."""
 

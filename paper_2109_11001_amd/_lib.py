@@ -72,7 +72,9 @@ EXPORTS = [
     "kgdb_mlp_workspace_bytes", "kgdb_mlp_forward", "kgdb_mlp_grad", "kgdb_mlp_adam", "kgdb_mlp_train_step",
     "kgdb_set_potential", "kgdb_protocol_schedule", "kgdb_run_protocol", "kgdb_init_info",
     "kgdb_pair_correlation", "kgdb_structure_factor", "kgdb_msd_reset", "kgdb_msd",
+    "kgdb_mlp_train_step_static",
 ]
+MLP_STATIC_ROWS = 4096
 MLP_NPARAM = 36481
 
 _lib = None
@@ -124,6 +126,7 @@ def load():
     L.kgdb_mlp_grad.argtypes = [P, P, P, i64, P, P, P, i64, P]
     L.kgdb_mlp_adam.argtypes = [P, P, P, P, i64, dbl, dbl, dbl, dbl, P]
     L.kgdb_mlp_train_step.argtypes = [P, P, P, P, P, i64, i64, dbl, dbl, dbl, dbl, P, i64, P, P]
+    L.kgdb_mlp_train_step_static.argtypes = [P, P, P, P, P, i64, i64, dbl, dbl, dbl, dbl, P, P]
     L.kgdb_set_potential.argtypes = [P, i32, dbl, dbl]
     L.kgdb_init_info.argtypes = [P, i32, P]
     L.kgdb_pair_correlation.argtypes = [P, i32, dbl, i32, P, P]

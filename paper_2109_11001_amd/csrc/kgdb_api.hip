@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1805,3 +1806,50 @@ int kgdb_mlp_train_step(float* params, float* m, float* v, const float* feat, co
   return kgdb_mlp_adam(params, m, v, w.grad, t, lr, b1, b2, eps, stream);
 }
 }  // extern "C"
+
+// ---------------------------------------------------------------------------------------
+// Training step without any allocation: the workspace is a fixed device array of this
+// library, sized for KGDB_MLP_STATIC_ROWS rows.  In host code `scratch` only names the
+// symbol; its device address (one per GPU) comes from hipGetSymbolAddress and is the only
+// form in which it is handed to kernels.  Calls on one GPU share the array (they must not
+// overlap); every kernel of the step writes the parts it reads, so nothing needs clearing.
+// ---------------------------------------------------------------------------------------
+namespace {
+constexpr size_t STATIC_WS_BYTES = nn_work_bytes(KGDB_MLP_STATIC_ROWS, 256);
+constexpr int MAX_DEVICES = 64;
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[STATIC_WS_BYTES];
+
+static void* g_scratch_ptr[MAX_DEVICES] = {};
+
+// the current device's address of `scratch` (looked up once per device)
+static int static_workspace(void** out) {
+  int dev = -1;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= MAX_DEVICES) return fail(KGDB_E_PARAM, "device index out of range");
+  static std::mutex mu;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p || ((uintptr_t)p & 255)) return fail(KGDB_E_HIP, "static workspace has no aligned device address");
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return 0;
+}
+
+extern "C" int kgdb_mlp_train_step_static(float* params, float* m, float* v, const float* feat, const int32_t* label,
+                                          int64_t n, int64_t t, double lr, double b1, double b2, double eps,
+                                          double* loss, void* stream) {
+  if (!params || !m || !v || !feat || !label) return fail(KGDB_E_PARAM, "null argument");
+  if (n < 1 || n > KGDB_MLP_STATIC_ROWS)
+    return fail(KGDB_E_PARAM, "n must be in [1, " + std::to_string(KGDB_MLP_STATIC_ROWS) +
+                                  "] rows for the allocation-free training step");
+  const int64_t need = kgdb_mlp_workspace_bytes(n);
+  if (need < 0 || (size_t)need > STATIC_WS_BYTES) return fail(KGDB_E_PARAM, "static workspace too small for n rows");
+  void* ws = nullptr;
+  CHK(static_workspace(&ws));
+  return kgdb_mlp_train_step(params, m, v, feat, label, n, t, lr, b1, b2, eps, ws, need, loss, stream);
+}

@@ -48,6 +48,20 @@ struct alignas(256) NetQ {
   float pad_[3];
 };
 
+// Bytes of the training workspace for n rows, laid out as mlp_work_layout carves it (every
+// piece rounded up to 256 bytes): the quantised network, per-row input codes, hidden codes and
+// masks, logits, FP64 deltas and losses, per-chunk partial gradients, the gradient and the
+// loss.  chunk = rows per partial weight-gradient sum.
+constexpr size_t nn_align256(size_t x) { return (x + 255) & ~(size_t)255; }
+constexpr size_t nn_work_bytes(int64_t n, int chunk) {
+  return nn_align256(sizeof(NetQ)) + nn_align256(sizeof(int16_t) * NN_INP * (size_t)n) +
+         2 * nn_align256(3 * NN_H * (size_t)n) + nn_align256(sizeof(float) * (size_t)n) +
+         nn_align256(sizeof(double) * (size_t)n) + nn_align256(sizeof(double) * 3 * NN_H * (size_t)n) +
+         nn_align256(sizeof(double) * (size_t)n) +
+         nn_align256(sizeof(double) * NN_NPARAM * (size_t)((n + chunk - 1) / chunk > 0 ? (n + chunk - 1) / chunk : 1)) +
+         nn_align256(sizeof(double) * NN_NPARAM) + nn_align256(sizeof(double));
+}
+
 // activations of one tile in LDS
 struct alignas(16) NetTile {
   __bf16 a0[NN_TILE][NN_SA0];  // input codes / 64
