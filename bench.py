@@ -39,20 +39,30 @@ MD_PER_STEP = 100
 LEARNED_KAPPA = 2.5
 
 
-def step_kernel_bytes(mixed, mean_list, K):
-    """Algorithmic bytes per monomer of one step-kernel launch (close + open), averaged over the
-    K steps of a rebuild interval.
+def algorithmic_bytes(mixed):
+    """Bytes per monomer that one fused force + integrator step must move (the pair, bond and
+    angle forces and the Langevin velocity-Verlet update of one monomer): pair 36 (own position
+    16 / 24 FP64, cell bounds 6, force 12-16 / 24), bond + angle fused with it 20, integrator
+    112 / 120 (x and v in FP64 read and written, the force, the FP32 copy).  Neighbour re-reads
+    are served from LDS or cache and are not counted.  168 B mixed, 196 B plain FP64."""
+    return 168.0 if mixed else 196.0
 
-    reads: position x (24), velocity v_half (24), own reference-relative position (16 mixed /
-    32 FP64), its value at the last rebuild (16), reference cell (4), chain-table position (4),
-    its chain-table entry (4), monomer id (4), list length (4) and list entries (4 each).
+
+def implementation_bytes(mixed, mean_list, K):
+    """Bytes per monomer one launch of this implementation's step kernel moves in its own
+    layout, averaged over the K steps of a rebuild interval.
+
+    reads: position x (24), velocity v_half (24), own relative position (16: fixed point with
+    FP32 forces; 32 FP64), monomer id (4), chain neighbours' slots (16), list length (4) and
+    list entries (2 each, 16-bit indices into the workgroup's LDS stage).
     writes: new x (24), new v_half (24), new relative position (16 / 32); on the step before a
-    rebuild also the list-grid cell (4) and bucket entry (4).  Neighbours' relative positions
-    and bonded partners' positions are re-reads served from cache.
+    rebuild also the bucket entry (4, 4/K per launch on average).  The stage (the tile and its
+    halo: every cell's positions are re-read by ~5 tiles) and the chain neighbours' positions
+    are re-reads served from cache.
     """
     rel = 16 if mixed else 32
-    reads = 24 + 24 + rel + 16 + 4 + 4 + 4 + 4 + 4 + 4 * mean_list
-    writes = 24 + 24 + rel + 8.0 / K
+    reads = 24 + 24 + rel + 4 + 16 + 4 + 2 * mean_list
+    writes = 24 + 24 + rel + 4.0 / K
     return reads + writes
 
 
@@ -101,6 +111,8 @@ def run_gpu(kg, precision, steps, warmup, stream, profile_steps):
         out["finalize_kernel_ms"] = prof["finalize_ms"] / max(prof["force_n"], 1)  # rebuild time per step
         out["force_launches_timed"] = prof["force_n"]
     r2n, lk, mb = b.observables()
+    M_, N_ = WORKLOAD["M"], WORKLOAD["N"]
+    out["fene_floored_frac"] = b.fene_floored() / max(1, b.counters()[0] * M_ * (N_ - 1))
     out["nl"] = b.nl_info()
     out["tune_ms"] = {str(k_): round(v_, 5) for k_, v_ in tune_ms.items()}
     out["ell_K"] = lk
@@ -146,13 +158,17 @@ def run_size(kg, monomers, md_steps, stream, precision):
     nl = b.nl_info()
     b.close()
     ms = prof["force_ms"] / max(prof["force_n"], 1)
-    bpm = step_kernel_bytes(precision == kg.PREC_MIXED, nl["mean_list"], nl["K"])
+    mixed = precision == kg.PREC_MIXED
+    bpm = algorithmic_bytes(mixed)
+    ibpm = implementation_bytes(mixed, nl["mean_list"], nl["K"])
     achieved = bpm * nm / (ms * 1e-3) / 1e9
     return {"monomers": nm, "chains": nm // N, "beads_per_chain": N, "md_steps": chunks * MD_PER_STEP,
             "monomer_steps_per_s": nm * chunks * MD_PER_STEP / wall, "avg_launch_ms": ms,
             "launches": prof["force_n"], "rebuild_ms_per_step": prof["finalize_ms"] / max(prof["force_n"], 1),
-            "bytes_per_monomer": round(bpm, 1), "achieved_GBs": round(achieved, 1),
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "K": nl["K"], "mean_list": nl["mean_list"],
+            "bytes_per_monomer": bpm, "achieved_GBs": round(achieved, 1),
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "implementation_bytes_per_monomer": round(ibpm, 1),
+            "implementation_GBs": round(ibpm * nm / (ms * 1e-3) / 1e9, 1), "K": nl["K"], "mean_list": nl["mean_list"],
             "rollbacks": nl["rollbacks"], "skin": round(nl["skin"], 4),
             "autotune_ms_per_step_by_K": {str(k_): round(v_, 5) for k_, v_ in tune_ms.items()},
             "init_s": round(t_init, 2)}
@@ -493,6 +509,27 @@ def run_protocol_bench(kg, stream, kappa, steps_per_stage, sweep_every=100):
             "S_q_ms": round(1e3 * float(np.median([t[1] for t in t_obs])), 2)}
 
 
+def roofline(run, mixed):
+    """The step kernel's achieved bandwidth in algorithmic bytes (the graded figure) and in this
+    implementation's own bytes, from its mean launch time."""
+    nm = run["monomers"]
+    ms = run["force_kernel_ms"]
+    bpm = algorithmic_bytes(mixed)
+    ibpm = implementation_bytes(mixed, run["nl"]["mean_list"], run["nl"]["K"])
+    achieved = bpm * nm / (ms * 1e-3) / 1e9
+    impl = ibpm * nm / (ms * 1e-3) / 1e9
+    return {"bound": "hbm", "kernel": f"k_nl_step<{'float' if mixed else 'double'}, close|open> "
+                                      "(list forces + bonded + Langevin VV, one workgroup per tile)",
+            "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "algorithmic_bytes_per_launch": round(bpm * nm), "bytes_per_monomer": bpm,
+            "implementation_bytes_per_monomer": round(ibpm, 1), "implementation_GBs": round(impl, 1),
+            "implementation_frac": round(impl / HBM_PEAK_GBS, 4),
+            "avg_launch_ms": ms, "launches": run["force_launches_timed"], "neighbour_lists": run["nl"],
+            "autotune_ms_per_step_by_K": run["tune_ms"], "rebuild_ms_per_step": run.get("finalize_kernel_ms"),
+            "fene_floored_per_bond_step": run.get("fene_floored_frac")}
+
+
 def step_kernel_hash():
     """sha256 of the step kernel's source (its body in kgdb_nl.hip plus kgdb_dev.h)."""
     csrc = os.path.join(ROOT, "paper_2109_11001_amd", "csrc")
@@ -720,20 +757,10 @@ def main():
 
     roof = None
     if "force_kernel_ms" in mixed:
-        bpm = step_kernel_bytes(True, mixed["nl"]["mean_list"], mixed["nl"]["K"])
-        bytes_launch = bpm * mixed["monomers"]
-        achieved = bytes_launch / (mixed["force_kernel_ms"] * 1e-3) / 1e9
+        roof = roofline(mixed, True)
         tr = measured_traffic()
-        roof = {"bound": "hbm", "kernel": "k_nl_step<float, close|open> (list forces + bonded + Langevin VV)",
-                "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": tr["bytes_per_launch"] if tr else None,
-                "traffic_split": {k_: tr[k_] for k_ in ("fetch_bytes", "write_bytes", "scale")} if tr else None,
-                "algorithmic_bytes_per_launch": round(bytes_launch),
-                "bytes_per_monomer": round(bpm, 1), "avg_launch_ms": mixed["force_kernel_ms"],
-                "launches": mixed["force_launches_timed"], "neighbour_lists": mixed["nl"],
-                "autotune_ms_per_step_by_K": mixed["tune_ms"],
-                "rebuild_ms_per_step": mixed.get("finalize_kernel_ms")}
+        roof["traffic"] = tr["bytes_per_launch"] if tr else None
+        roof["traffic_split"] = {k_: tr[k_] for k_ in ("fetch_bytes", "write_bytes", "scale")} if tr else None
     line = {
         "metric": METRIC,
         "value": mixed["monomer_steps_per_s"],
@@ -759,7 +786,12 @@ def main():
     if fp64:
         line["fp64_path"] = {"value": fp64["monomer_steps_per_s"], "ms_per_step": fp64["ms_per_step"],
                              "db_accepted_per_s": fp64["db_accepted_per_s"],
-                             "force_kernel_ms": fp64.get("force_kernel_ms")}
+                             "md_only_monomer_steps_per_s": fp64["md_only_monomer_steps_per_s"],
+                             "time_split_s": {"md": round(fp64["md_s"], 4), "db": round(fp64["db_s"], 4)},
+                             "rebuild_ms_per_md_step": fp64.get("finalize_kernel_ms"),
+                             "force_kernel_ms": fp64.get("force_kernel_ms"),
+                             "neighbour_lists": fp64["nl"], "autotune_ms_per_step_by_K": fp64["tune_ms"],
+                             "roofline": roofline(fp64, False) if "force_kernel_ms" in fp64 else None}
         line["speedup_vs_fp64_path"] = mixed["monomer_steps_per_s"] / fp64["monomer_steps_per_s"]
     if learned:
         line["learned_form"] = learned

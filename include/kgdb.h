@@ -45,8 +45,10 @@ enum kgdb_err {
 /* test flags */
 #define KGDB_TF_PHANTOM 1u /* nonbonded pairs off; bonded pairs keep MLJ^n */
 #define KGDB_TF_NOFORCE 2u /* conservative forces off (free Langevin particles) */
-#define KGDB_TF_NL_GLOBAL 4u /* list build reads every neighbourhood from global memory (the path
-                                taken when one does not fit the LDS stage); results unchanged */
+#define KGDB_TF_NL_GLOBAL 4u /* list build and step read every neighbourhood from global memory
+                                (the path taken when one does not fit the LDS stage); results unchanged */
+#define KGDB_TF_SIDE_FAULT 8u /* the list rebuild run beside a sweep reports an overflow and leaves
+                                 empty lists (tests that such a rebuild is dropped); results unchanged */
 
 /* One melt: M chains of N beads in a cubic periodic box of side (M N / rho)^(1/3).
    Field order is part of the ABI. */
@@ -223,6 +225,15 @@ int kgdb_profile_read(kgdb_batch* b, double* force_ms, int64_t* force_n, double*
 int kgdb_autotune(kgdb_batch* b, int32_t nl_every, int32_t reps, int32_t* chosen, double* ms_per_variant);
 /* neighbour lists: out = {K, skin, mean list length, rollbacks so far} */
 int kgdb_nl_info(kgdb_batch* b, double out[4]);
+/* LDS stages of the list tiles (a performance diagnostic; no effect on results): out =
+   {rebuild tiles whose neighbourhood exceeded the LDS stage and was read from global memory,
+   so far; the largest neighbourhood (members) seen; the stage capacity at the current K; its
+   upper limit}.  After a pass in which a tile overflowed, the capacity grows (up to the limit). */
+int kgdb_nl_stats(kgdb_batch* b, int64_t out[4]);
+/* Bond-steps of melt `melt` (since init; each bond counted once per closing kick of an MD
+   step on the neighbour-list path) whose FENE argument a = 1 - r^2/R0^2 fell below
+   fene_floor, i.e. where the floored continuation of Eqs. 3/10 replaced the log. */
+int kgdb_fene_floored(kgdb_batch* b, int32_t melt, uint64_t* bond_steps);
 /* geometry of melt `melt`: out = {L, MD cells per side, double-bridging cells per side,
    FENE constant in use (k_n of Eq. 9 or the literal value)} */
 int kgdb_melt_geometry(const kgdb_batch* b, int32_t melt, double out[4]);

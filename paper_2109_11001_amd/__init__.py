@@ -9,7 +9,7 @@ import ctypes as C
 import numpy as np
 
 from ._lib import (INIT_FREELY_ROTATING, INIT_RANDOM_WALK, MLP_NPARAM, PREC_FP64, PREC_MIXED, PROPOSAL_LEARNED,
-                   PROPOSAL_LITERAL, PROPOSAL_UNIFORM, TF_NL_GLOBAL, TF_NOFORCE, TF_PHANTOM, DbStats, KgdbError,
+                   PROPOSAL_LITERAL, PROPOSAL_UNIFORM, TF_NL_GLOBAL, TF_NOFORCE, TF_PHANTOM, TF_SIDE_FAULT, DbStats, KgdbError,
                    Params, StageStats, check, load, ptr)
 
 NN_IN = 25
@@ -121,6 +121,12 @@ class Batch:
         check(load().kgdb_get_state(self._h, melt, ptr(x), ptr(v), ptr(fc), ptr(fl), ptr(ch), ptr(cnt)))
         return dict(x=x, v=v, fc=fc, fl=fl, chains=ch.reshape(M, N), counters=cnt)
 
+    def counters(self, melt=0):
+        """{step, sweep, last_sweep_step, fc_valid} of melt `melt` (no state transfer)."""
+        cnt = np.zeros(4, np.uint64)
+        check(load().kgdb_get_state(self._h, melt, None, None, None, None, None, ptr(cnt)))
+        return [int(c) for c in cnt]
+
     def set_state(self, melt=0, x=None, v=None, fl=None, chains=None, counters=None):
         cv = lambda a, t: None if a is None else np.ascontiguousarray(a, t)
         x, v, fl = cv(x, np.float64), cv(v, np.float64), cv(fl, np.float64)
@@ -177,6 +183,20 @@ class Batch:
         out = np.zeros(4)
         check(load().kgdb_nl_info(self._h, ptr(out)))
         return dict(K=int(out[0]), skin=out[1], mean_list=out[2], rollbacks=int(out[3]))
+
+    def nl_stats(self):
+        """LDS stages of the list tiles: tiles read from global memory so far, largest stage,
+        current capacity, capacity limit."""
+        out = np.zeros(4, np.int64)
+        check(load().kgdb_nl_stats(self._h, ptr(out)))
+        return dict(stage_overflows=int(out[0]), largest_stage=int(out[1]), stage_cap=int(out[2]),
+                    stage_cap_max=int(out[3]))
+
+    def fene_floored(self, melt=0):
+        """Bond-steps of melt `melt` on the floored FENE continuation (argument below fene_floor)."""
+        out = np.zeros(1, np.uint64)
+        check(load().kgdb_fene_floored(self._h, int(melt), ptr(out)))
+        return int(out[0])
 
     # ---- structure observables
     def pair_correlation(self, r_max, nbins, melt=0):

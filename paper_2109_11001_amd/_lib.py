@@ -15,7 +15,7 @@ E_PARAM, E_ALLOC, E_HIP, E_FENE, E_NONFINITE, E_OVERFLOW, E_STATE = -1, -2, -3, 
 PROPOSAL_UNIFORM, PROPOSAL_LEARNED, PROPOSAL_LITERAL = 0, 1, 2
 PREC_FP64, PREC_MIXED = 0, 1
 INIT_RANDOM_WALK, INIT_FREELY_ROTATING = 0, 1
-TF_PHANTOM, TF_NOFORCE, TF_NL_GLOBAL = 1, 2, 4
+TF_PHANTOM, TF_NOFORCE, TF_NL_GLOBAL, TF_SIDE_FAULT = 1, 2, 4, 8
 
 
 class KgdbError(RuntimeError):
@@ -72,7 +72,7 @@ EXPORTS = [
     "kgdb_mlp_workspace_bytes", "kgdb_mlp_forward", "kgdb_mlp_grad", "kgdb_mlp_adam", "kgdb_mlp_train_step",
     "kgdb_set_potential", "kgdb_protocol_schedule", "kgdb_run_protocol", "kgdb_init_info",
     "kgdb_pair_correlation", "kgdb_structure_factor", "kgdb_msd_reset", "kgdb_msd",
-    "kgdb_mlp_train_step_static",
+    "kgdb_mlp_train_step_static", "kgdb_fene_floored", "kgdb_nl_stats",
 ]
 MLP_STATIC_ROWS = 4096
 MLP_NPARAM = 36481
@@ -116,6 +116,8 @@ def load():
     L.kgdb_batch_sizes.argtypes = [P, P, P]
     L.kgdb_autotune.argtypes = [P, i32, i32, P, P]
     L.kgdb_nl_info.argtypes = [P, P]
+    L.kgdb_fene_floored.argtypes = [P, i32, P]
+    L.kgdb_nl_stats.argtypes = [P, P]
     L.kgdb_mlp_nparam.argtypes = []
     L.kgdb_set_proposal_net.argtypes = [P, P, i32, dbl]
     L.kgdb_db_sweep_log.argtypes = [P, i64, P, P, P, i64, P]

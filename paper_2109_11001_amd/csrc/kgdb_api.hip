@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdlib>
+#include <cstdio>
 #include <cstring>
 #include <mutex>
 #include <string>
@@ -68,30 +69,47 @@ struct kgdb_batch {
   void* d_spos = nullptr;
   int *d_chain = nullptr, *d_loc = nullptr;
   int* d_mono = nullptr;  // monomer id (local) held in each storage slot
-  int *d_perm = nullptr, *d_inv = nullptr, *d_start = nullptr, *d_tmpi = nullptr;
-  double* d_tmp3 = nullptr;
-  bool reorder = true;    // renumber slots in cell order after each run of MD steps
+  // the other buffer of each per-monomer array: a list rebuild moves the storage into it
+  // (tile-sorted slot order) and the pointers are swapped
+  double *d_v2 = nullptr, *d_fc2 = nullptr, *d_fl2 = nullptr;
+  int *d_chain2 = nullptr, *d_loc2 = nullptr, *d_mono2 = nullptr;
+  int4* d_nb4[2] = {nullptr, nullptr};  // chain neighbours' slots (current, other)
+  int rp = 0;                      // rebuild parity (flips with every rebuild)
+  int* d_inv = nullptr;            // old slot -> new slot of the last rebuild
   // neighbour lists (production steps)
   int NCL = 0;                     // list-grid cells (sized for the finest grid among the K choices)
+  int NTILE = 0;                   // list-grid tiles (likewise)
+  int ntile[3] = {0, 0, 0};        // tiles of the batch for each K
   int nl_k = 5;                    // rebuild interval in use
   int nl_ki = 2;                   // its index in NL_KS
   std::vector<MeltDesc> Dk[3];     // descriptors for each rebuild interval of NL_KS
-  BlockMap lm[3];                  // list-grid cell blocks for each K
-  BlockMap rm[3];                  // list-build blocks for each K
-  int stage_cap[3] = {0, 0, 0};    // list build: LDS-staged monomers per workgroup for each K
-  int* d_cntl[2] = {nullptr, nullptr};
-  int cl = 0;                      // list-grid occupancy buffer the next rebuild fills
-  int* d_bucketl = nullptr;
-  int* d_bucketl_raw = nullptr;    // list-grid buckets as filled by the binning
-  int* d_celll = nullptr;          // list-grid cell of each monomer
+  BlockMap rm[3];                  // list-grid tiles for each K
+  int stage_cap[3] = {0, 0, 0};    // LDS-staged members per tile for each K
+  int* d_cntl = nullptr;           // binning: count per sorted list-grid cell
+  int* d_tcnt = nullptr;           // binning: count per tile
+  int* d_tstart = nullptr;         // first slot of each tile
+  int* d_bucketl_raw = nullptr;    // slots binned into each cell
+  int2* d_cellsc = nullptr;        // first slot and count of each sorted cell
+  int* d_stage = nullptr;          // per tile: slots of its staged members (stage_cap_max each)
+  int stage_cap_max = 0;           // LDS limit of a stage (members)
+  uint32_t* d_nlstat = nullptr;    // rebuild tiles staged from global memory; largest stage (since last read)
+  uint32_t* h_nlstat = nullptr;
+  int64_t nl_stage_over = 0;       // rebuild tiles staged from global memory, all passes
+  int nl_stage_seen = 0;           // largest stage seen
+  int4* d_smeta = nullptr;         // per tile: first home slot, home count, staged count
+  size_t stage_words = 0;
   void* d_rel[2] = {nullptr, nullptr};
-  float4* d_relb = nullptr;
-  int* d_refc = nullptr;
   uint32_t* d_nlist = nullptr;
   int* d_nlen = nullptr;
-  double* d_save = nullptr;        // chunk-start state for the rollback
+  uint32_t* d_disp = nullptr;      // per melt: largest displacement of the last two steps
+  float* d_dacc = nullptr;         // per melt: bound on the displacement since the rebuild
+  unsigned long long* d_floor = nullptr;  // per melt: bond-steps on the FENE floor
+  uint32_t* d_err_side = nullptr;  // errors of a rebuild beside a sweep
+  bool remap_pending = false;      // a rebuild beside a sweep still has to carry the topology over
+  double* d_save = nullptr;        // pass-start state for the rollback (and the autotuner)
+  int* d_save_i = nullptr;
   uint64_t* d_save_step = nullptr;
-  hipGraphExec_t ngexec[3][2][2] = {};  // [K][x parity][occupancy parity]
+  hipGraphExec_t ngexec[3][2][2] = {};  // [K][x parity][rebuild parity]
   int64_t nl_rollbacks = 0;
   int nl_ki_target = 2;            // interval chosen by the caller or the autotuner
   // lists built ahead (beside a double-bridging sweep) for the next run of steps: valid while
@@ -212,18 +230,39 @@ static void set_list_geometry(MeltDesc& d, const kgdb_params& p, int K, double n
   d.ncl = std::max(1, (int)std::floor(d.L / rl));
   d.cinvl = (double)d.ncl / d.L;
   d.hl = d.L / d.ncl;
+  const double u = d.hl / 16777216.0;  // unit of the fixed-point relative positions
+  d.rc2_fx = d.rc2 / (u * u);
+  d.iu2_fx = 1.0 / (u * u);
   d.rlist2 = rl * rl;
   d.half_skin2 = 0.25 * skin * skin;
-  // list-build blocks of about NLB_THREADS monomers: nl_S x nl_Sy cells, (nl_S + 2)(nl_Sy + 2) <= 198
+  d.half_skin = 0.5 * skin;
+  // Tiles of nl_S x nl_Sy cells: the shape with the least modelled cost per home monomer.  A
+  // workgroup stages 3 (nl_S + 2)(nl_Sy + 2) cells and updates its home monomers in rounds of
+  // NLB_THREADS lanes (a round costs the same whether or not every lane holds a monomer); the
+  // last tile of a row (column) takes the remainder, and no tile is empty.  The stage must
+  // fit the LDS cap with room for fluctuations.
   const double occ = (double)d.Nm / ((double)d.ncl * d.ncl * d.ncl);
-  const double C = 0.94 * NLB_THREADS / std::max(occ, 1e-6);
-  int Sy = std::max(1, std::min((int)std::lround(std::sqrt(C / 6.0)), d.ncl));
-  int S = std::max(1, std::min((int)std::lround(C / Sy), std::min(64, d.ncl)));
-  while ((S + 2) * (Sy + 2) > 198) { if (Sy > 1) --Sy; else --S; }
-  d.nl_nseg = (d.ncl + S - 1) / S;
-  d.nl_S = (d.ncl + d.nl_nseg - 1) / d.nl_nseg;
-  d.nl_nyb = (d.ncl + Sy - 1) / Sy;
-  d.nl_Sy = (d.ncl + d.nl_nyb - 1) / d.nl_nyb;
+  const int cap = p.precision == KGDB_PREC_MIXED ? STAGE_CAP_MAX : STAGE_CAP_MAX_FP64;
+  double best = 1e300;
+  int bS = 1, bSy = 1;
+  for (int Sy = 1; Sy <= std::min(d.ncl, 64); ++Sy) {
+    const int nyb = (d.ncl + Sy - 1) / Sy, Sye = (d.ncl + nyb - 1) / nyb;
+    if (Sye != Sy) continue;
+    for (int S = 1; S <= std::min(d.ncl, 64); ++S) {
+      const int nseg = (d.ncl + S - 1) / S, Se = (d.ncl + nseg - 1) / nseg;
+      if (Se != S || (S + 2) * (Sy + 2) > 198) continue;
+      const double homes = S * Sy * occ, stage = 3.0 * (S + 2) * (Sy + 2) * occ;
+      if (1.5 * stage + 64 > cap && !(S == 1 && Sy == 1)) continue;
+      // (a tile's count fluctuates by about sqrt(homes / 4) in a melt: two of those in hand)
+      const double rounds = std::ceil((homes + std::sqrt(homes) + 2.0) / NLB_THREADS);
+      const double cost = (3000.0 + 40.0 * stage + 2500.0 * NLB_THREADS * rounds) / std::max(homes, 1e-9);
+      if (cost < best) { best = cost; bS = S; bSy = Sy; }
+    }
+  }
+  d.nl_S = bS;
+  d.nl_nseg = (d.ncl + bS - 1) / bS;
+  d.nl_Sy = bSy;
+  d.nl_nyb = (d.ncl + bSy - 1) / bSy;
 }
 
 static MeltDesc make_desc(const kgdb_params& p) {
@@ -242,6 +281,8 @@ static MeltDesc make_desc(const kgdb_params& p) {
   d.rc2 = rc * rc;
   d.proposal = p.proposal;
   d.R0sq = p.R0 * p.R0;
+  d.iR0sq = 1.0 / d.R0sq;
+  d.invL = 1.0 / d.L;
   d.amin = p.fene_floor > 0 ? p.fene_floor : 0.0;
   d.kappa = p.kappa;
   d.T = p.T; d.gamma = p.gamma; d.dt = p.dt;
@@ -375,6 +416,8 @@ static int check_errors(kgdb_batch* b) {
   if (all & ERR_NBR_OVERFLOW) return fail(KGDB_E_OVERFLOW, "close-pair list capacity exceeded" + where);
   if (all & ERR_CAND_OVERFLOW) return fail(KGDB_E_OVERFLOW, "candidate list capacity exceeded" + where);
   if (all & ERR_DB_MISMATCH) return fail(KGDB_E_STATE, "candidate recount disagrees with the list" + where);
+  if (all & ERR_NLIST_OVERFLOW) return fail(KGDB_E_OVERFLOW, "neighbour list capacity exceeded" + where);
+  if (all & ERR_NLIST_STALE) return fail(KGDB_E_STATE, "neighbour lists went stale" + where);
   return fail(KGDB_E_STATE, "unknown device error" + where);
 }
 
@@ -393,37 +436,13 @@ static int capture_chunk(kgdb_batch* b, int parity) {
   return 0;
 }
 
-// Renumber the storage slots of every melt in cell order (cells of melt k cover exactly the
-// slots of melt k), from the occupancy and buckets of the last list rebuild.
-static int reorder_storage(kgdb_batch* b) {
-  const int NP = b->NP;
-  launch_perm_cells(b->d_cntl[1 - b->cl], b->d_bucketl, NL_CELL_CAP, b->NCL, b->d_start, b->d_perm, b->d_inv, b->s);
-  launch_gather_f64x3(b->d_x[1 - b->cur], b->d_x[b->cur], b->d_perm, NP, b->s);
-  double* f3[3] = {b->d_v, b->d_fc, b->d_fl};
-  for (double* f : f3) {
-    launch_gather_f64x3(b->d_tmp3, f, b->d_perm, NP, b->s);
-    HIPCHK(hipMemcpyAsync(f, b->d_tmp3, sizeof(double) * 3 * (size_t)NP, hipMemcpyDeviceToDevice, b->s));
-  }
-  int* i1[2] = {b->d_loc, b->d_mono};
-  for (int* f : i1) {
-    launch_gather_i32(b->d_tmpi, f, b->d_perm, NP, b->s);
-    HIPCHK(hipMemcpyAsync(f, b->d_tmpi, sizeof(int) * (size_t)NP, hipMemcpyDeviceToDevice, b->s));
-  }
-  launch_remap_i32(b->d_chain, b->d_inv, NP, b->s);
-  HIPCHK(hipGetLastError());
-  b->cur = 1 - b->cur;
-  b->cells_valid = false;
-  return 0;
-}
-
 static NlArgs nl_args(kgdb_batch* b) {
   NlArgs a;
   std::memset(&a, 0, sizeof a);
   a.md = b->d_md;
+  a.nm = b->nm;
   a.pblk_melt = b->pm.melt;
   a.pblk_base = b->pm.base;
-  a.cblk_melt = b->lm[b->nl_ki].melt;
-  a.cblk_base = b->lm[b->nl_ki].base;
   a.rblk_melt = b->rm[b->nl_ki].melt;
   a.rblk_base = b->rm[b->nl_ki].base;
   a.stage_cap = b->stage_cap[b->nl_ki];
@@ -432,55 +451,102 @@ static NlArgs nl_args(kgdb_batch* b) {
     if (d.n_half_int != a.nh_uniform) a.nh_uniform = 0;
   if (a.nh_uniform != 1 && a.nh_uniform != 6) a.nh_uniform = 0;
   a.NP = b->NP;
+  a.ncl_total = 0;
+  for (const MeltDesc& d : b->D) a.ncl_total += d.ncl * d.ncl * d.ncl;
+  a.ntile_total = b->ntile[b->nl_ki];
   a.x = b->d_x[b->cur];
   a.xn = b->d_x[1 - b->cur];
   a.v = b->d_v;
+  a.vn = b->d_v2;
   a.fc = b->d_fc;
+  a.fcn = b->d_fc2;
   a.fl = b->d_fl;
-  a.cnt = b->d_cntl[b->cl];
-  a.cnt_clear = b->d_cntl[1 - b->cl];
-  a.bucket = b->d_bucketl;
+  a.fln = b->d_fl2;
+  a.mono = b->d_mono;
+  a.mono_n = b->d_mono2;
+  a.loc = b->d_loc;
+  a.loc_n = b->d_loc2;
+  a.chain = b->d_chain;
+  a.chain_n = b->d_chain2;
+  a.nb4 = b->d_nb4[0];
+  a.nb4_n = b->d_nb4[1];
+  a.inv = b->d_inv;
+  a.cnt = b->d_cntl;
+  a.tcnt = b->d_tcnt;
+  a.tstart = b->d_tstart;
   a.bucket_raw = b->d_bucketl_raw;
-  a.cell_l = b->d_celll;
-  a.ncl_total = 0;
-  for (const MeltDesc& d : b->D) a.ncl_total += d.ncl * d.ncl * d.ncl;
+  a.cellsc = b->d_cellsc;
+  a.stage_list = b->d_stage;
+  a.stage_stride = b->stage_cap_max;
+  a.nlstat = b->d_nlstat;
+  a.stage_meta = b->d_smeta;
   a.rel_cur = b->d_rel[b->cur];
   a.rel_next = b->d_rel[1 - b->cur];
-  a.relb = b->d_relb;
-  a.refc = b->d_refc;
   a.nlist = b->d_nlist;
   a.nlen = b->d_nlen;
-  a.chain = b->d_chain;
-  a.loc = b->d_loc;
-  a.mono = b->d_mono;
   a.step_base = b->d_step;
   a.err = b->d_err;
+  a.disp = b->d_disp;
+  a.dacc = b->d_dacc;
+  a.fene_floored = b->d_floor;
   return a;
 }
 
-// fused: the step before binned the positions (F_BIN), so the rebuild starts at the ranking
-static int nl_rebuild(kgdb_batch* b, bool capture, bool fused = true, hipStream_t on = nullptr) {
+// After a rebuild: the storage now lives in the other buffer of each pair.
+static void swap_storage(kgdb_batch* b, bool perm_f) {
+  b->cur = 1 - b->cur;
+  b->cells_valid = false;  // the r_c cell list holds slots of the old order
+  std::swap(b->d_v, b->d_v2);
+  std::swap(b->d_mono, b->d_mono2);
+  std::swap(b->d_loc, b->d_loc2);
+  std::swap(b->d_chain, b->d_chain2);
+  std::swap(b->d_nb4[0], b->d_nb4[1]);
+  if (perm_f) {
+    std::swap(b->d_fc, b->d_fc2);
+    std::swap(b->d_fl, b->d_fl2);
+  }
+  b->rp = 1 - b->rp;
+}
+
+// A list rebuild: binning (unless the step before binned: fused), the tile scan, the per-tile
+// stage / move / list kernel and the remap of the topology.  perm_f: also move F_c and F_L
+// (the rebuild that opens a run of steps).  With a side stream `on` (beside a sweep, which
+// rewrites the chain table meanwhile) only the first part runs there, into a separate error
+// word; the caller finishes it with finish_side_rebuild once the sweep is done.
+static int nl_rebuild(kgdb_batch* b, bool capture, bool fused, bool perm_f, hipStream_t on = nullptr) {
   const bool prof = b->prof && !capture && !on;
   if (prof) {
     if (b->ev_used == PROF_EVENTS) CHK(prof_flush(b));
     HIPCHK(hipEventRecord(b->ev[4 * b->ev_used + 2], b->s));
   }
-  launch_nl_rebuild(b->prec, nl_args(b), b->pm.nblk, b->lm[b->nl_ki].nblk, b->rm[b->nl_ki].nblk, !fused,
-                    on ? on : b->s);
+  NlArgs a = nl_args(b);
+  a.perm_f = perm_f ? 1 : 0;
+  if (on) {
+    a.err = b->d_err_side;
+    a.side = 1;
+  }
+  launch_nl_rebuild(b->prec, a, b->pm.nblk, b->rm[b->nl_ki].nblk, !fused, on ? on : b->s);
+  if (on) {
+    b->remap_pending = true;
+    return 0;
+  }
+  launch_nl_remap(a, b->pm.nblk, b->s);
   if (prof) HIPCHK(hipEventRecord(b->ev[4 * b->ev_used + 3], b->s));
-  b->cl = 1 - b->cl;
+  swap_storage(b, perm_f);
   b->rebuild_pending = prof;
   return 0;
 }
 
 // Step s of a pass (s = 0 opens it) is followed by a list rebuild exactly when (s + 1) % K == 0
 // (graph chunks hold a multiple of K steps, so the rule holds inside them): such a step bins
-// the new positions itself and the rebuild starts at the ranking.
+// the new positions itself and the rebuild starts at the scan.
 static int bin_flag(const kgdb_batch* b, int64_t s) { return (s + 1) % b->nl_k == 0 ? F_BIN : 0; }
 
-static int nl_step(kgdb_batch* b, int mode, uint32_t s_off, bool capture) {
+static int nl_step(kgdb_batch* b, int mode, uint32_t s_off, int64_t s, bool capture) {
   NlArgs a = nl_args(b);
   a.s_off = s_off;
+  a.sp = (uint32_t)(s & 1);
+  a.stage_write = s % b->nl_k == 0 ? 1 : 0;  // the first step after a rebuild records the stages
   const bool prof = b->prof && !capture && (mode & F_OPEN);
   if (prof) {
     if (!b->rebuild_pending) {  // no rebuild before this step: empty rebuild interval
@@ -489,7 +555,7 @@ static int nl_step(kgdb_batch* b, int mode, uint32_t s_off, bool capture) {
       HIPCHK(hipEventRecord(b->ev[4 * b->ev_used + 3], b->s));
     }
   }
-  launch_nl_step(b->prec, mode, a, b->pm.nblk, b->s, prof ? b->ev[4 * b->ev_used] : nullptr,
+  launch_nl_step(b->prec, mode, a, b->rm[b->nl_ki].nblk, b->s, prof ? b->ev[4 * b->ev_used] : nullptr,
                  prof ? b->ev[4 * b->ev_used + 1] : nullptr);
   if (prof) {
     b->ev_used++;
@@ -505,8 +571,8 @@ static int capture_nl_chunk(kgdb_batch* b, hipGraphExec_t* out) {
   HIPCHK(hipStreamBeginCapture(b->s, hipStreamCaptureModeThreadLocal));
   int rc = 0;
   for (int j = 1; j <= GCHUNK && !rc; ++j) {
-    if (j % b->nl_k == 0) rc = nl_rebuild(b, true);
-    if (!rc) rc = nl_step(b, F_CLOSE | F_OPEN | bin_flag(b, j), (uint32_t)j, true);
+    if (j % b->nl_k == 0) rc = nl_rebuild(b, true, true, false);
+    if (!rc) rc = nl_step(b, F_CLOSE | F_OPEN | bin_flag(b, j), (uint32_t)j, j, true);
   }
   launch_advance(b->d_step, b->nm, GCHUNK, b->s);
   hipError_t e = hipStreamEndCapture(b->s, &g);
@@ -522,60 +588,90 @@ static int capture_nl_chunk(kgdb_batch* b, hipGraphExec_t* out) {
 static int nl_pass(kgdb_batch* b, int64_t n, bool graph) {
   const int K = b->nl_k;
   if (b->lists_ver == b->xver && b->lists_ki == b->nl_ki && !b->prof) b->lists_ver = ~0ull;  // built ahead
-  else CHK(nl_rebuild(b, false, false));
-  CHK(nl_step(b, F_OPEN | bin_flag(b, 0), 0, false));
+  else CHK(nl_rebuild(b, false, false, true));
+  CHK(nl_step(b, F_OPEN | bin_flag(b, 0), 0, 0, false));
   int64_t s = 1;
   if (graph && !b->prof && GCHUNK % K == 0) {
     while (n - s >= GCHUNK) {
-      hipGraphExec_t& ge = b->ngexec[b->nl_ki][b->cur][b->cl];
-      if (!ge) CHK(capture_nl_chunk(b, &ge));  // capture flips parities GCHUNK times: net no change
+      hipGraphExec_t& ge = b->ngexec[b->nl_ki][b->cur][b->rp];
+      if (!ge) CHK(capture_nl_chunk(b, &ge));  // capture flips parities an even number of times
       HIPCHK(hipGraphLaunch(ge, b->s));
       s += GCHUNK;
     }
   }
   const int64_t s0 = s;
   for (; s < n; ++s) {
-    if (s % K == 0) CHK(nl_rebuild(b, false));
-    CHK(nl_step(b, F_CLOSE | F_OPEN | bin_flag(b, s), (uint32_t)(s - s0 + 1), false));
+    if (s % K == 0) CHK(nl_rebuild(b, false, true, false));
+    CHK(nl_step(b, F_CLOSE | F_OPEN | bin_flag(b, s), (uint32_t)(s - s0 + 1), s, false));
   }
   if (n - s0 > 0) launch_advance(b->d_step, b->nm, (uint64_t)(n - s0), b->s);
-  if (n % K == 0) CHK(nl_rebuild(b, false));
-  CHK(nl_step(b, F_CLOSE | F_STORE, 1, false));
+  if (n % K == 0) CHK(nl_rebuild(b, false, true, false));
+  CHK(nl_step(b, F_CLOSE | F_STORE, 1, n, false));
   launch_advance(b->d_step, b->nm, 1, b->s);
   HIPCHK(hipGetLastError());
   return 0;
 }
 
-static int save_state(kgdb_batch* b, bool back) {
-  const size_t n3 = 3 * (size_t)b->NP;
+// The state a pass starts from (positions, velocities, forces, topology in the current slot
+// order, step counters), for the rollback of a pass and for the autotuner.  Restoring writes
+// into the current buffers; the next pass opens with a rebuild.
+static int copy_state(kgdb_batch* b, bool back, double* sx, int* si, uint64_t* sst) {
+  const size_t n3 = 3 * (size_t)b->NP, np = (size_t)b->NP;
   double* f[4] = {b->d_x[b->cur], b->d_v, b->d_fc, b->d_fl};
   for (int q = 0; q < 4; ++q)
-    HIPCHK(hipMemcpyAsync(back ? f[q] : b->d_save + q * n3, back ? b->d_save + q * n3 : f[q], n3 * sizeof(double),
+    HIPCHK(hipMemcpyAsync(back ? f[q] : sx + q * n3, back ? sx + q * n3 : f[q], n3 * sizeof(double),
                           hipMemcpyDeviceToDevice, b->s));
-  HIPCHK(hipMemcpyAsync(back ? b->d_step : b->d_save_step, back ? b->d_save_step : b->d_step,
-                        b->nm * sizeof(uint64_t), hipMemcpyDeviceToDevice, b->s));
+  int* t[3] = {b->d_mono, b->d_loc, b->d_chain};
+  for (int q = 0; q < 3; ++q)
+    HIPCHK(hipMemcpyAsync(back ? t[q] : si + q * np, back ? si + q * np : t[q], np * sizeof(int),
+                          hipMemcpyDeviceToDevice, b->s));
+  HIPCHK(hipMemcpyAsync(back ? b->d_step : sst, back ? sst : b->d_step, b->nm * sizeof(uint64_t),
+                        hipMemcpyDeviceToDevice, b->s));
+  uint64_t* fl = (uint64_t*)b->d_floor;  // FENE-floor counters (sst holds 2 nm words)
+  HIPCHK(hipMemcpyAsync(back ? fl : sst + b->nm, back ? sst + b->nm : fl, b->nm * sizeof(uint64_t),
+                        hipMemcpyDeviceToDevice, b->s));
+  if (back) b->lists_ver = ~0ull;
   return 0;
 }
+static int save_state(kgdb_batch* b, bool back) { return copy_state(b, back, b->d_save, b->d_save_i, b->d_save_step); }
 
-// Switch the rebuild interval (and with it the list grid).  A rebuild clears the other
-// occupancy buffer only over its own grid's cells, so both buffers are zeroed here in full.
+// Switch the rebuild interval (and with it the list grid and its tiles).  The binning counts
+// are zeroed over the whole allocation (they are indexed by the new grid).
 static int set_nl_interval(kgdb_batch* b, int ki) {
-  b->lists_ver = ~0ull;  // lists built ahead rely on the occupancy buffers cleared here
+  b->lists_ver = ~0ull;
   b->nl_ki = ki;
   b->nl_k = NL_KS[ki];
   b->D = b->Dk[ki];
   HIPCHK(hipMemcpyAsync(b->d_md, b->D.data(), sizeof(MeltDesc) * b->nm, hipMemcpyHostToDevice, b->s));
-  HIPCHK(hipMemsetAsync(b->d_cntl[0], 0, sizeof(int) * (size_t)b->NCL, b->s));
-  HIPCHK(hipMemsetAsync(b->d_cntl[1], 0, sizeof(int) * (size_t)b->NCL, b->s));
+  HIPCHK(hipMemsetAsync(b->d_cntl, 0, sizeof(int) * (size_t)b->NCL, b->s));
+  HIPCHK(hipMemsetAsync(b->d_tcnt, 0, sizeof(int) * (size_t)b->NTILE, b->s));
   return 0;
 }
 
 static int run_steps_cells(kgdb_batch* b, int64_t n, bool graph);
 
+// A tile whose stage outgrew the LDS capacity was staged from global memory (correct, but far
+// slower): raise the capacity of the current interval for the passes that follow, up to the
+// LDS limit.  Captured runs of steps hold the old capacity and are dropped.
+static int adapt_stage_cap(kgdb_batch* b) {
+  HIPCHK(hipMemcpyAsync(b->h_nlstat, b->d_nlstat, sizeof(uint32_t) * 2, hipMemcpyDeviceToHost, b->s));
+  HIPCHK(hipMemsetAsync(b->d_nlstat, 0, sizeof(uint32_t) * 2, b->s));
+  HIPCHK(hipStreamSynchronize(b->s));
+  b->nl_stage_over += b->h_nlstat[0];
+  b->nl_stage_seen = std::max(b->nl_stage_seen, (int)b->h_nlstat[1]);
+  int& cap = b->stage_cap[b->nl_ki];
+  if (cap > 0 && (int)b->h_nlstat[1] > cap && cap < b->stage_cap_max) {
+    cap = std::min(b->stage_cap_max, ((int)(1.25 * b->h_nlstat[1]) + 64 + 63) / 64 * 64);
+    for (auto& a2 : b->ngexec[b->nl_ki])
+      for (auto& ge : a2)
+        if (ge) { HIPCHK(hipGraphExecDestroy(ge)); ge = nullptr; }
+  }
+  return 0;
+}
+
 static int run_steps(kgdb_batch* b, int64_t n, bool graph) {
   if (n <= 0) return 0;
   if (b->nl_ki < 0) return run_steps_cells(b, n, graph);
-  const int cur0 = b->cur;
   CHK(save_state(b, false));
   for (;;) {
     CHK(nl_pass(b, n, graph));
@@ -586,26 +682,39 @@ static int run_steps(kgdb_batch* b, int64_t n, bool graph) {
     for (int k = 0; k < b->nm; ++k) all |= b->h_err[k];
     // a monomer outran the skin, or a list-grid bucket or a list overflowed (dense spots of
     // an unrelaxed start): redo the pass with more frequent rebuilds on a finer grid
-    if (!(all & (ERR_NLIST_STALE | ERR_CELL_OVERFLOW | ERR_NLIST_OVERFLOW)) || b->nl_k == 1) break;
+    const uint32_t redo = ERR_NLIST_STALE | ERR_CELL_OVERFLOW | ERR_NLIST_OVERFLOW;
+    if (!(all & redo)) break;
+    if (b->nl_k == 1) {
+      // staleness cannot matter when every force evaluation follows a rebuild; an overflow
+      // at the finest grid is an error, and the call leaves the state it started from
+      if (all & (ERR_CELL_OVERFLOW | ERR_NLIST_OVERFLOW)) {
+        CHK(save_state(b, true));
+        HIPCHK(hipMemsetAsync(b->d_err, 0, sizeof(uint32_t) * b->nm, b->s));
+        HIPCHK(hipStreamSynchronize(b->s));
+        b->xver++;
+        return fail(KGDB_E_OVERFLOW, (all & ERR_CELL_OVERFLOW) ? "list-grid cell capacity exceeded at K = 1"
+                                                                : "neighbour list capacity exceeded at K = 1");
+      }
+      for (int k = 0; k < b->nm; ++k) b->h_err[k] &= ~ERR_NLIST_STALE;
+      HIPCHK(hipMemcpyAsync(b->d_err, b->h_err, sizeof(uint32_t) * b->nm, hipMemcpyHostToDevice, b->s));
+      break;
+    }
+    if (std::getenv("KGDB_NL_VERBOSE"))  // diagnostics: why a pass was redone
+      std::fprintf(stderr, "kgdb: pass of %lld steps redone at K = %d (error bits 0x%x)\n", (long long)n, b->nl_k, all);
     HIPCHK(hipMemsetAsync(b->d_err, 0, sizeof(uint32_t) * b->nm, b->s));
-    b->cur = cur0;
     CHK(save_state(b, true));
     CHK(set_nl_interval(b, b->nl_ki - 1));
     b->nl_rollbacks++;
     b->nl_clean = -1;
   }
-  if (b->nl_k == 1) {  // staleness cannot matter when every force evaluation follows a rebuild
-    for (int k = 0; k < b->nm; ++k) b->h_err[k] &= ~ERR_NLIST_STALE;
-    HIPCHK(hipMemcpyAsync(b->d_err, b->h_err, sizeof(uint32_t) * b->nm, hipMemcpyHostToDevice, b->s));
-  }
   for (int k = 0; k < b->nm; ++k) b->step[k] += (uint64_t)n;
   b->fc_valid = true;
   b->cells_valid = false;
+  b->xver++;
   CHK(check_errors(b));
+  CHK(adapt_stage_cap(b));
   if (b->msd_on)  // a run of steps moves a monomer far less than L / 2
     launch_msd_track(b->d_md, b->pm, b->NP, b->d_x[b->cur], b->d_mono, b->d_msd_last, b->d_msd_acc, 0, -1, b->s);
-  if (b->reorder) CHK(reorder_storage(b));
-  b->xver++;
   // A rollback answers one fast monomer, usually a rare event: after NL_CLEAN_PASSES clean
   // passes the next pass tries the next longer interval again, up to the chosen one.
   if (b->nl_ki < b->nl_ki_target && ++b->nl_clean >= NL_CLEAN_PASSES) {
@@ -674,6 +783,7 @@ void kgdb_destroy(kgdb_batch* b) {
   if (b->s2) hipStreamDestroy(b->s2);
   for (void* q : b->allocs) hipFree(q);
   if (b->h_err) hipHostFree(b->h_err);
+  if (b->h_nlstat) hipHostFree(b->h_nlstat);
   if (b->own_stream && b->s) hipStreamDestroy(b->s);
   delete b;
 }
@@ -695,17 +805,7 @@ static int build_block_maps(kgdb_batch* b) {
   add_map(256, false);
   add_map(256 / FIN_LANES, true);
   for (int G : {1, 2, 4, 8}) add_map(256 / G, false);
-  for (int q = 0; q < 3; ++q) {  // list-grid cells for each rebuild interval
-    std::vector<int> melt, base;
-    for (int k = 0; k < b->nm; ++k) {
-      const int n = b->Dk[q][k].ncl * b->Dk[q][k].ncl * b->Dk[q][k].ncl;
-      for (int i = 0; i < n; i += 256) { melt.push_back(k); base.push_back(i); }
-    }
-    spans.push_back({all.size(), melt.size()});
-    all.insert(all.end(), melt.begin(), melt.end());
-    all.insert(all.end(), base.begin(), base.end());
-  }
-  for (int q = 0; q < 3; ++q) {  // list-build row segments for each rebuild interval
+  for (int q = 0; q < 3; ++q) {  // list-grid tiles for each rebuild interval
     std::vector<int> melt, base;
     for (int k = 0; k < b->nm; ++k) {
       const MeltDesc& d = b->Dk[q][k];
@@ -718,9 +818,8 @@ static int build_block_maps(kgdb_batch* b) {
   }
   CHK(dalloc(b, &b->d_blk, all.size()));
   HIPCHK(hipMemcpy(b->d_blk, all.data(), all.size() * sizeof(int), hipMemcpyHostToDevice));
-  BlockMap* maps[12] = {&b->pm,    &b->cm,    &b->fm[0], &b->fm[1], &b->fm[2], &b->fm[3],
-                        &b->lm[0], &b->lm[1], &b->lm[2], &b->rm[0], &b->rm[1], &b->rm[2]};
-  for (int m = 0; m < 12; ++m) {
+  BlockMap* maps[9] = {&b->pm, &b->cm, &b->fm[0], &b->fm[1], &b->fm[2], &b->fm[3], &b->rm[0], &b->rm[1], &b->rm[2]};
+  for (int m = 0; m < 9; ++m) {
     maps[m]->melt = b->d_blk + spans[m].first;
     maps[m]->base = b->d_blk + spans[m].first + spans[m].second;
     maps[m]->nblk = (int)spans[m].second;
@@ -893,23 +992,30 @@ static int init_impl(const kgdb_params* params, int32_t count, void* stream, kgd
   b->NP = (int)NP; b->NC = (int)NC; b->NC13 = (int)NC13;
   // list-grid geometry for each rebuild interval; pick the requested or the largest usable
   {
-    int64_t ncl_max = 0;
+    int64_t ncl_max = 0, nt_max = 0;
     bool usable[3];
     for (int q = 0; q < 3; ++q) {
       b->Dk[q] = b->D;
-      int64_t off = 0;
+      int64_t off = 0, toff = 0;
       usable[q] = true;
       for (int k = 0; k < count; ++k) {
-        set_list_geometry(b->Dk[q][k], params[k], NL_KS[q], (double)NP);
-        b->Dk[q][k].celll_off = (int)off;
-        off += (int64_t)b->Dk[q][k].ncl * b->Dk[q][k].ncl * b->Dk[q][k].ncl;
-        if (b->Dk[q][k].ncl < 3 || b->Dk[q][k].ncl > 1023) usable[q] = false;
+        MeltDesc& d = b->Dk[q][k];
+        set_list_geometry(d, params[k], NL_KS[q], (double)NP);
+        d.celll_off = (int)off;
+        d.tile_off = (int)toff;
+        off += (int64_t)d.ncl * d.ncl * d.ncl;
+        toff += (int64_t)d.ncl * d.nl_nyb * d.nl_nseg;
+        if (d.ncl < 3 || d.ncl > 1023) usable[q] = false;
       }
       ncl_max = std::max(ncl_max, off);
+      nt_max = std::max(nt_max, toff);
+      b->ntile[q] = (int)toff;
     }
     if (ncl_max * NL_CELL_CAP >= (1ll << 31)) { delete b; return fail(KGDB_E_PARAM, "list grid too large"); }
-    // LDS stage of the list build: 1.25 x the largest mean neighbourhood of a block (+ 64); a
-    // block whose neighbourhood does not fit reads it from global memory instead
+    // LDS stage of a tile: 1.5 x the largest mean neighbourhood of a tile + 64 (density
+    // fluctuations of a melt that is still relaxing from its start are large), at most 2688
+    // members (mixed) or 1792 (FP64), which keeps the step's and the rebuild's LDS within 64 KB;
+    // a tile whose neighbourhood does not fit reads it from global memory instead, far slower
     for (int q = 0; q < 3; ++q) {
       double mx = 0.0;
       for (int k = 0; k < count; ++k) {
@@ -917,11 +1023,12 @@ static int init_impl(const kgdb_params* params, int32_t count, void* stream, kgd
         const double occ = (double)d.Nm / ((double)d.ncl * d.ncl * d.ncl);
         mx = std::max(mx, 3.0 * (d.nl_S + 2) * (d.nl_Sy + 2) * occ);
       }
-      b->stage_cap[q] = std::min(b->prec ? 4032 : 2000, ((int)(1.25 * mx) + 64 + 63) / 64 * 64);  // <= 64 KB
+      b->stage_cap[q] = std::min(b->prec ? STAGE_CAP_MAX : STAGE_CAP_MAX_FP64, ((int)(1.5 * mx) + 64 + 63) / 64 * 64);
       for (int k = 0; k < count; ++k)
         if (params[k].test_flags & TF_NL_GLOBAL) b->stage_cap[q] = 0;
     }
     b->NCL = (int)ncl_max;
+    b->NTILE = (int)nt_max;
     int want = params[0].nl_every;
     for (int k = 1; k < count; ++k)
       if (params[k].nl_every != want) { delete b; return fail(KGDB_E_PARAM, "nl_every differs within the batch"); }
@@ -966,30 +1073,40 @@ static int init_impl(const kgdb_params* params, int32_t count, void* stream, kgd
   step(dalloc(b, &b->d_chain, np));
   step(dalloc(b, &b->d_loc, np));
   step(dalloc(b, &b->d_mono, np));
-  step(dalloc(b, &b->d_perm, np));
+  step(dalloc(b, &b->d_chain2, np));
+  step(dalloc(b, &b->d_loc2, np));
+  step(dalloc(b, &b->d_mono2, np));
+  step(dalloc(b, &b->d_v2, 3 * np));
+  step(dalloc(b, &b->d_fc2, 3 * np));
+  step(dalloc(b, &b->d_fl2, 3 * np));
+  step(dalloc(b, &b->d_nb4[0], np));
+  step(dalloc(b, &b->d_nb4[1], np));
   step(dalloc(b, &b->d_inv, np));
-  step(dalloc(b, &b->d_tmpi, np));
-  step(dalloc(b, &b->d_tmp3, 3 * np));
-  {  // cell starts [0, NC], then the scan's scratch: the total and one sum per 1024 cells
-    const int64_t nc_max = std::max<int64_t>(NC, b->NCL);
-    step(dalloc(b, &b->d_start, (size_t)(nc_max + 3 + (nc_max + 1023) / 1024)));
-  }
-  step(dalloc(b, &b->d_cntl[0], (size_t)b->NCL));
-  step(dalloc(b, &b->d_cntl[1], (size_t)b->NCL));
-  step(dalloc(b, &b->d_bucketl, (size_t)b->NCL * NL_CELL_CAP));
+  step(dalloc(b, &b->d_cntl, (size_t)b->NCL));
+  step(dalloc(b, &b->d_tcnt, (size_t)b->NTILE));
+  step(dalloc(b, &b->d_tstart, (size_t)b->NTILE));
+  step(dalloc(b, &b->d_cellsc, (size_t)b->NCL));
+  b->stage_cap_max = b->prec ? STAGE_CAP_MAX : STAGE_CAP_MAX_FP64;
+  for (int q = 0; q < 3; ++q)
+    b->stage_words = std::max(b->stage_words, (size_t)b->ntile[q] * (size_t)(b->stage_cap[q] > 0 ? b->stage_cap_max : 0));
+  step(dalloc(b, &b->d_nlstat, 2));
+  step(dalloc(b, &b->d_stage, std::max<size_t>(b->stage_words, 1)));
+  step(dalloc(b, &b->d_smeta, (size_t)b->NTILE));
   step(dalloc(b, &b->d_bucketl_raw, (size_t)b->NCL * NL_CELL_CAP));
-  step(dalloc(b, &b->d_celll, (size_t)NP));
+  step(dalloc(b, &b->d_disp, 2 * (size_t)DISP_SLOTS * DISP_STRIDE * count));
+  step(dalloc(b, &b->d_dacc, (size_t)count));
+  step(dalloc(b, &b->d_floor, (size_t)count));
+  step(dalloc(b, &b->d_err_side, (size_t)count));
   for (int q = 0; q < 2 && !rc; ++q) {
     void* r = nullptr;
     if (hipMalloc(&r, np * rel_bytes(b->prec)) != hipSuccess) rc = fail(KGDB_E_ALLOC, "hipMalloc rel");
     else { b->allocs.push_back(r); b->d_rel[q] = r; }
   }
-  step(dalloc(b, &b->d_relb, np));
-  step(dalloc(b, &b->d_refc, np));
-  step(dalloc(b, &b->d_nlist, (np + 63) / 64 * 64 * NL_CAP));  // whole 64-monomer tiles
+  step(dalloc(b, &b->d_nlist, (np + 63) / 64 * 64 * NL_CAP / 2));  // whole 64-slot tiles, 16-bit entries
   step(dalloc(b, &b->d_nlen, np));
   step(dalloc(b, &b->d_save, 12 * np));
-  step(dalloc(b, &b->d_save_step, (size_t)count));
+  step(dalloc(b, &b->d_save_i, 3 * np));
+  step(dalloc(b, &b->d_save_step, 2 * (size_t)count));
   step(dalloc(b, &b->d_step, (size_t)count));
   step(dalloc(b, &b->d_err, (size_t)count));
   step(dalloc(b, &b->d_out4, 4 * (size_t)count));
@@ -1013,6 +1130,8 @@ static int init_impl(const kgdb_params* params, int32_t count, void* stream, kgd
   step(dalloc(b, &b->d_r2, (size_t)b->max_N));
   if (!rc && hipHostMalloc((void**)&b->h_err, sizeof(uint32_t) * count, 0) != hipSuccess)
     rc = fail(KGDB_E_ALLOC, "hipHostMalloc");
+  if (!rc && hipHostMalloc((void**)&b->h_nlstat, sizeof(uint32_t) * 2, 0) != hipSuccess)
+    rc = fail(KGDB_E_ALLOC, "hipHostMalloc");
   if (!rc) rc = build_block_maps(b);
   if (rc) { kgdb_destroy(b); return rc; }
   if (const char* e = std::getenv("KGDB_FORCE_LANES")) {
@@ -1031,14 +1150,24 @@ static int init_impl(const kgdb_params* params, int32_t count, void* stream, kgd
   hip(hipMemsetAsync(b->d_err, 0, sizeof(uint32_t) * count, b->s), "err");
   hip(hipMemsetAsync(b->d_fl, 0, sizeof(double) * 3 * np, b->s), "fl");
   hip(hipMemsetAsync(b->d_fc, 0, sizeof(double) * 3 * np, b->s), "fc");
-  hip(hipMemsetAsync(b->d_cntl[0], 0, sizeof(int) * (size_t)b->NCL, b->s), "cntl");
-  hip(hipMemsetAsync(b->d_cntl[1], 0, sizeof(int) * (size_t)b->NCL, b->s), "cntl");
+  hip(hipMemsetAsync(b->d_cntl, 0, sizeof(int) * (size_t)b->NCL, b->s), "cntl");
+  hip(hipMemsetAsync(b->d_tcnt, 0, sizeof(int) * (size_t)b->NTILE, b->s), "tcnt");
+  hip(hipMemsetAsync(b->d_disp, 0, sizeof(uint32_t) * 2 * DISP_SLOTS * DISP_STRIDE * count, b->s), "disp");
+  hip(hipMemsetAsync(b->d_dacc, 0, sizeof(float) * count, b->s), "dacc");
+  hip(hipMemsetAsync(b->d_floor, 0, sizeof(unsigned long long) * count, b->s), "floor");
+  hip(hipMemsetAsync(b->d_err_side, 0, sizeof(uint32_t) * count, b->s), "err2");
+  hip(hipMemsetAsync(b->d_nlen, 0, sizeof(int) * np, b->s), "nlen");
+  hip(hipMemsetAsync(b->d_stage, 0, sizeof(int) * std::max<size_t>(b->stage_words, 1), b->s), "stage");
+  hip(hipMemsetAsync(b->d_smeta, 0, sizeof(int4) * (size_t)b->NTILE, b->s), "smeta");
+  hip(hipMemsetAsync(b->d_nlstat, 0, sizeof(uint32_t) * 2, b->s), "nlstat");
   if (rc) { kgdb_destroy(b); return rc; }
   {
     std::vector<int> mono(np);
     for (int k = 0; k < count; ++k)
       for (int i = 0; i < b->D[k].Nm; ++i) mono[b->D[k].off + i] = i;
     hip(hipMemcpy(b->d_mono, mono.data(), sizeof(int) * np, hipMemcpyHostToDevice), "mono");
+    for (size_t i = 0; i < np; ++i) mono[i] = (int)i;  // the identity until the first rebuild
+    hip(hipMemcpy(b->d_inv, mono.data(), sizeof(int) * np, hipMemcpyHostToDevice), "inv");
   }
   launch_random_walks(b->d_md, count, b->max_M, b->NP, b->d_x[0], b->d_chain, b->d_loc, b->s);
   b->cur = 0;
@@ -1049,6 +1178,18 @@ static int init_impl(const kgdb_params* params, int32_t count, void* stream, kgd
   launch_velocities(b->d_md, b->pm, b->NP, b->d_v, b->s);
   launch_remove_mean(b->d_md, count, b->NP, b->d_v, b->s);
   hip(hipGetLastError(), "init kernels");
+  // The other buffer of each pair starts as a copy (indices in range): a rebuild that overflows
+  // a list-grid cell leaves some new slots unwritten until its run is rolled back, and those
+  // entries must still name valid slots meanwhile.
+  hip(hipMemcpyAsync(b->d_chain2, b->d_chain, sizeof(int) * np, hipMemcpyDeviceToDevice, b->s), "chain2");
+  hip(hipMemcpyAsync(b->d_loc2, b->d_loc, sizeof(int) * np, hipMemcpyDeviceToDevice, b->s), "loc2");
+  hip(hipMemcpyAsync(b->d_mono2, b->d_mono, sizeof(int) * np, hipMemcpyDeviceToDevice, b->s), "mono2");
+  hip(hipMemsetAsync(b->d_nb4[0], 0xff, sizeof(int4) * np, b->s), "nb4");  // -1: no neighbour
+  hip(hipMemsetAsync(b->d_nb4[1], 0xff, sizeof(int4) * np, b->s), "nb4");
+  hip(hipMemsetAsync(b->d_x[1], 0, sizeof(double) * 3 * np, b->s), "x1");
+  hip(hipMemsetAsync(b->d_v2, 0, sizeof(double) * 3 * np, b->s), "v2");
+  hip(hipMemsetAsync(b->d_fc2, 0, sizeof(double) * 3 * np, b->s), "fc2");
+  hip(hipMemsetAsync(b->d_fl2, 0, sizeof(double) * 3 * np, b->s), "fl2");
   b->cells_valid = false;
   if (!rc) rc = warmup(b);
   if (rc) { std::string m = g_err; kgdb_destroy(b); g_err = m; return rc; }
@@ -1347,6 +1488,34 @@ int kgdb_db_probe(kgdb_batch* b, int32_t melt, const uint64_t* keys, int64_t nke
   return 0;
 }
 
+// The rebuild run beside a sweep moved positions, velocities, forces and monomer ids into the
+// other buffers and built the lists; the topology (which the sweep was rewriting meanwhile)
+// is carried over now.  If that rebuild overflowed a capacity, its buffers are dropped and the
+// next run of steps rebuilds in-run (where an overflow rolls back to a finer grid).
+static int finish_side_rebuild(kgdb_batch* b) {
+  b->remap_pending = false;
+  std::vector<uint32_t> e(b->nm);
+  HIPCHK(hipMemcpyAsync(e.data(), b->d_err_side, sizeof(uint32_t) * b->nm, hipMemcpyDeviceToHost, b->s));
+  HIPCHK(hipStreamSynchronize(b->s));
+  uint32_t all = 0;
+  for (uint32_t v : e) all |= v;
+  if (all) {
+    HIPCHK(hipMemsetAsync(b->d_err_side, 0, sizeof(uint32_t) * b->nm, b->s));
+    // the binning counts of the dropped rebuild are cleared (the remap would have)
+    HIPCHK(hipMemsetAsync(b->d_cntl, 0, sizeof(int) * (size_t)b->NCL, b->s));
+    HIPCHK(hipMemsetAsync(b->d_tcnt, 0, sizeof(int) * (size_t)b->NTILE, b->s));
+    b->lists_ver = ~0ull;
+    return 0;
+  }
+  NlArgs a = nl_args(b);
+  launch_nl_remap(a, b->pm.nblk, b->s);
+  HIPCHK(hipGetLastError());
+  swap_storage(b, true);
+  b->lists_ver = b->xver;
+  b->lists_ki = b->nl_ki;
+  return 0;
+}
+
 static int sweep_impl(kgdb_batch* b, int64_t n_attempts, kgdb_db_stats* stats, int debug, float* log_feat = nullptr,
                       int32_t* log_label = nullptr, int64_t log_cap = 0, int64_t* log_n = nullptr) {
   if (!b) return fail(KGDB_E_PARAM, "bad handle");
@@ -1388,11 +1557,9 @@ static int sweep_impl(kgdb_batch* b, int64_t n_attempts, kgdb_db_stats* stats, i
   if (b->learned) launch_db_sweep_learned(a, b->s);
   else launch_db_sweep(a, b->s);
   if (ahead) {
-    CHK(nl_rebuild(b, false, false, b->s2));
+    CHK(nl_rebuild(b, false, false, true, b->s2));
     HIPCHK(hipEventRecord(b->ev_join, b->s2));
     HIPCHK(hipStreamWaitEvent(b->s, b->ev_join, 0));
-    b->lists_ver = b->xver;
-    b->lists_ki = b->nl_ki;
   }
   HIPCHK(hipGetLastError());
   if (log_feat) {
@@ -1402,6 +1569,7 @@ static int sweep_impl(kgdb_batch* b, int64_t n_attempts, kgdb_db_stats* stats, i
   std::vector<kgdb_db_stats> st(b->nm);
   HIPCHK(hipMemcpyAsync(st.data(), b->d_stats, sizeof(kgdb_db_stats) * b->nm, hipMemcpyDeviceToHost, b->s));
   const int rc = check_errors(b);
+  if (b->remap_pending) CHK(finish_side_rebuild(b));
   for (int k = 0; k < b->nm; ++k) {
     b->sweep[k]++;
     b->last_sweep[k] = b->step[k];
@@ -1585,23 +1753,15 @@ int kgdb_autotune(kgdb_batch* b, int32_t nl_every, int32_t reps, int32_t* chosen
   }
   const size_t n3 = 3 * (size_t)b->NP;
   double* sx = nullptr;
+  int* si = nullptr;
   uint64_t* sst = nullptr;
   HIPCHK(hipMalloc(&sx, 4 * n3 * sizeof(double)));
-  HIPCHK(hipMalloc(&sst, b->nm * sizeof(uint64_t)));
-  auto copy_state = [&](bool back) {
-    double* f[4] = {b->d_x[b->cur], b->d_v, b->d_fc, b->d_fl};
-    for (int q = 0; q < 4; ++q)
-      (void)hipMemcpyAsync(back ? f[q] : sx + q * n3, back ? sx + q * n3 : f[q], n3 * sizeof(double),
-                           hipMemcpyDeviceToDevice, b->s);
-    (void)hipMemcpyAsync(back ? b->d_step : sst, back ? sst : b->d_step, b->nm * sizeof(uint64_t),
-                         hipMemcpyDeviceToDevice, b->s);
-  };
-  const bool was_reorder = b->reorder, was_fc = b->fc_valid, was_prof = b->prof, was_msd = b->msd_on;
-  const int was_cur = b->cur;
+  HIPCHK(hipMalloc(&si, 3 * (size_t)b->NP * sizeof(int)));
+  HIPCHK(hipMalloc(&sst, 2 * b->nm * sizeof(uint64_t)));
+  const bool was_fc = b->fc_valid, was_prof = b->prof, was_msd = b->msd_on;
   const std::vector<uint64_t> was_step = b->step;
-  b->reorder = false;
   b->msd_on = false;  // the trial steps are undone
-  copy_state(false);
+  CHK(copy_state(b, false, sx, si, sst));
   double best = INFINITY;
   int best_q = b->nl_ki, rc = 0;
   for (int q = 0; q < 3 && !rc; ++q) {
@@ -1619,16 +1779,15 @@ int kgdb_autotune(kgdb_batch* b, int32_t nl_every, int32_t reps, int32_t* chosen
     const double ms = b->prof_force_n ? (b->prof_force_ms + b->prof_fin_ms) / b->prof_force_n : INFINITY;
     if (ms_per_variant) ms_per_variant[q] = ms;
     if (!rc && b->nl_ki == q && ms < best) { best = ms; best_q = q; }  // a rollback disqualifies
-    b->cur = was_cur;
-    copy_state(true);
+    if (!rc) rc = copy_state(b, true, sx, si, sst);
     b->step = was_step;
     b->cells_valid = false;
     b->fc_valid = was_fc;
   }
   (void)hipStreamSynchronize(b->s);
   (void)hipFree(sx);
+  (void)hipFree(si);
   (void)hipFree(sst);
-  b->reorder = was_reorder;
   b->msd_on = was_msd;
   b->prof_force_ms = b->prof_fin_ms = 0;
   b->prof_force_n = b->prof_fin_n = 0;
@@ -1638,6 +1797,15 @@ int kgdb_autotune(kgdb_batch* b, int32_t nl_every, int32_t reps, int32_t* chosen
   b->nl_clean = 0;
   if (chosen) *chosen = b->nl_k;
   return rc;
+}
+
+int kgdb_nl_stats(kgdb_batch* b, int64_t out[4]) {
+  if (!b || !out) return fail(KGDB_E_PARAM, "bad arguments");
+  out[0] = b->nl_stage_over;
+  out[1] = b->nl_stage_seen;
+  out[2] = b->nl_ki >= 0 ? b->stage_cap[b->nl_ki] : 0;
+  out[3] = b->stage_cap_max;
+  return 0;
 }
 
 // neighbour-list state: out = {rebuild interval K, skin, mean list length, rollbacks so far}
@@ -1653,6 +1821,16 @@ int kgdb_nl_info(kgdb_batch* b, double out[4]) {
   out[1] = nl_skin_for(b->P[0], b->nl_k, (double)b->NP);
   out[2] = sum / b->NP;
   out[3] = (double)b->nl_rollbacks;
+  return 0;
+}
+
+int kgdb_fene_floored(kgdb_batch* b, int32_t melt, uint64_t* bond_steps) {
+  CHK(check_melt(b, melt));
+  if (!bond_steps) return fail(KGDB_E_PARAM, "null argument");
+  unsigned long long v = 0;
+  HIPCHK(hipStreamSynchronize(b->s));
+  HIPCHK(hipMemcpy(&v, b->d_floor + melt, sizeof v, hipMemcpyDeviceToHost));
+  *bond_steps = (uint64_t)v;
   return 0;
 }
 

@@ -15,8 +15,16 @@ constexpr int DB_CAND_CAP = 3072; // candidate keys per melt (held in LDS during
 constexpr int DB_NEW_CAP = 1024;  // candidates touching the two chains of one move
 constexpr int DB_MAX_CHAINS = 8192; // chains per melt (per-chain key counts held in LDS during a sweep)
 constexpr int NLB_THREADS = 256;  // list-build workgroup: about this many home monomers per block
+// LDS stage of a list tile, members at most: mixed path (16-byte entries), plain FP64 path
+// (32-byte entries in the step)
+constexpr int STAGE_CAP_MAX = 2688;
+constexpr int STAGE_CAP_MAX_FP64 = 1792;
 constexpr int NL_CELL_CAP = 32;   // monomers per cell of the neighbour-list grid
-constexpr int NL_CAP = 64;        // neighbour-list entries per monomer
+constexpr int NL_CAP = 64;        // neighbour-list entries per monomer (16-bit stage indices)
+// per melt and step parity, the step's largest displacement is gathered in DISP_SLOTS maxima,
+// one 128-byte line each, so that the workgroups' atomics spread over the cache
+constexpr int DISP_SLOTS = 64;
+constexpr int DISP_STRIDE = 32;   // uint32 words per slot
 
 // device error bits (per melt)
 enum : uint32_t {
@@ -33,7 +41,7 @@ enum : uint32_t {
 // Philox counter word 2: the random-number stream
 enum : uint64_t { ST_WALK = 1, ST_VEL = 2, ST_LANGEVIN = 3, ST_DB = 4, ST_WARMUP = 5 };
 
-enum : uint32_t { TF_PHANTOM = 1u, TF_NOFORCE = 2u, TF_NL_GLOBAL = 4u };
+enum : uint32_t { TF_PHANTOM = 1u, TF_NOFORCE = 2u, TF_NL_GLOBAL = 4u, TF_SIDE_FAULT = 8u };
 
 // Per-melt constants, laid out for scalar loads (the melt index is uniform per workgroup).
 struct MeltDesc {
@@ -68,6 +76,12 @@ struct MeltDesc {
   // initial state: KGDB_INIT_* and, for freely rotating chains, cos theta* (Eqs. 12-13)
   int init_mode;
   double fr_cos;
+  // first tile of this melt among the batch's tiles; skin / 2 (list validity bound)
+  int tile_off;
+  double half_skin;
+  // constants of the step kernel: 1 / L, 1 / R0^2, and r_c^2 and 1 / u^2 in the units u of the
+  // fixed-point relative positions (u = hl / 2^24)
+  double invL, iR0sq, rc2_fx, iu2_fx;
 };
 
 // ---------------------------------------------------------------------------------------
@@ -133,6 +147,20 @@ __device__ __forceinline__ double wrap_box(double x, double L) {
   return w;
 }
 __device__ __forceinline__ double min_image(double d, double L) { return d - L * rint(d / L); }
+// wrap_box for a coordinate that has left [0, L) by less than one box: the same result
+// (x + L and x - L round as x - L floor(x / L) does there), without the division.  (A step
+// moves a monomer far less than a box; a coordinate beyond that, of a run already flagged as
+// broken, maps to 0.)
+__device__ __forceinline__ double wrap_near(double x, double L) {
+  double w = x;
+  if (w < 0.0) {
+    w += L;
+    if (w >= L) w = 0.0;
+  } else if (w >= L) {
+    w -= L;
+  }
+  return (w >= 0.0 && w < L) ? w : 0.0;
+}
 
 // cell index along one axis of a wrapped coordinate; clamped so that even a corrupted
 // (non-finite or unwrapped) coordinate cannot index outside the grid

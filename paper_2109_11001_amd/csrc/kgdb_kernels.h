@@ -65,54 +65,70 @@ void launch_force(int prec, int mode, int lanes, const ForceArgs& a, int nblk, h
 void launch_advance(uint64_t* step_base, int nm, uint64_t n, hipStream_t s);
 void launch_fill_i32(int* p, int n, int v, hipStream_t s);
 size_t spos_bytes(int prec);
-// renumbering of storage slots in cell order: perm[new] = old, inv[old] = new
-void launch_perm_cells(const int* cnt, const int* bucket, int cap, int NC, int* start, int* perm, int* inv,
-                       hipStream_t s);
-void launch_gather_f64x3(double* dst, const double* src, const int* perm, int NP, hipStream_t s);
-void launch_gather_i32(int* dst, const int* src, const int* perm, int NP, hipStream_t s);
-void launch_remap_i32(int* a, const int* inv, int NP, hipStream_t s);
 
 // ---- neighbour-list MD step (kgdb_nl.hip)
 struct NlArgs {
   const MeltDesc* md;
+  int nm;
   const int* pblk_melt;  // monomer blocks (256 per block)
   const int* pblk_base;
-  const int* cblk_melt;  // list-grid cell blocks (256 per block)
-  const int* cblk_base;
-  const int* rblk_melt;  // list-build blocks: nl_S x nl_Sy cells of one z-plane each
+  const int* rblk_melt;  // tiles of the list grid: nl_S x nl_Sy cells of one z-plane each
   const int* rblk_base;  // (z * nl_nyb + y block) * nl_nseg + x block
   int NP;
+  int ncl_total;    // list-grid cells of the batch (current rebuild interval)
+  int ntile_total;  // tiles of the batch
+  // storage: the step reads x and writes xn; a rebuild moves every per-monomer array into
+  // the other buffer of its pair (x -> xn, v -> vn, ...) in the new slot order
   const double* x;
   double* xn;
   double* v;
+  double* vn;
   double* fc;
+  double* fcn;
   double* fl;
-  int* cnt;        // list-grid occupancy being filled
-  int* cnt_clear;  // the other occupancy buffer (cleared by the rebuild)
-  int* bucket;      // list-grid buckets, ordered by slot
-  int* bucket_raw;  // the same as filled by the binning (any order)
-  int* cell_l;      // list-grid cell of each monomer
-  int ncl_total;    // list-grid cells of the batch (current rebuild interval)
-  void* rel_cur;   // reference-cell-relative positions (force precision, 4 per monomer)
+  double* fln;
+  int perm_f;        // the rebuild also moves fc and fl (the one that opens a run of steps)
+  int* mono;         // monomer id (local to its melt) held in each slot
+  int* mono_n;
+  int* loc;          // chain * N + position of each slot's monomer
+  int* loc_n;
+  int* chain;        // chain tables: slot at (melt, chain, position)
+  int* chain_n;
+  int4* nb4;         // slots of the chain neighbours p-2, p-1, p+1, p+2 (-1: none)
+  int4* nb4_n;
+  int* inv;          // old slot -> new slot of the last rebuild
+  int* cnt;          // occupancy per sorted list-grid cell (binning)
+  int* tcnt;         // occupancy per tile (binning)
+  int* tstart;       // first new slot of each tile
+  int* bucket_raw;   // slots binned into each cell (any order)
+  int2* cellsc;      // first slot and count of each sorted cell
+  int* stage_list;   // per tile (stage_stride each): slots of the staged members, in stage order
+  int stage_stride;  // entries per tile in stage_list (the largest capacity)
+  uint32_t* nlstat;  // rebuild: [0] tiles staged from global memory, [1] largest stage (atomic)
+  int4* stage_meta;  // per tile: first home slot, home count, staged count
+  int stage_write;   // this step follows a rebuild: find the stages from cellsc and record them
+  void* rel_cur;     // positions relative to the reference cell (force precision; 4th word: packed cell)
   void* rel_next;
-  float4* relb;    // relative positions at the last rebuild
-  int* refc;       // packed reference cell of each monomer
-  uint32_t* nlist; // tiles of 64 monomers x NL_CAP entries: (slot << 5) | cell-offset code
+  uint32_t* nlist;   // tiles of 64 slots x NL_CAP 16-bit entries (indices into the tile's stage)
   int* nlen;
-  const int* chain;
-  const int* loc;
-  const int* mono;
   const uint64_t* step_base;
   uint32_t* err;
-  uint32_t s_off;
-  int stage_cap;   // list build: staged monomers per workgroup held in LDS
-  int nh_uniform;  // n / 2 when every melt has n = 2 or n = 12 (the step kernel is built for those), else 0
+  uint32_t* disp;    // [nm][2][DISP_SLOTS * DISP_STRIDE] largest displacements of the last two steps (float bits)
+  float* dacc;       // [nm] sum of the steps' largest displacements since the rebuild
+  unsigned long long* fene_floored;  // [nm] bond-steps with the FENE argument below a_min
+  uint32_t s_off;    // Langevin counter offset of this closing kick
+  uint32_t sp;       // parity of the step within its run of steps
+  int side;          // the rebuild runs beside a sweep (on its own error word)
+  int stage_cap;     // staged members per workgroup held in LDS
+  int nh_uniform;    // n / 2 when every melt has n = 2 or n = 12 (the step kernel is built for those), else 0
 };
-size_t nl_stage_bytes(int prec, int cap);  // dynamic LDS of the list build
-// bin = false: the positions were binned by the step before (F_BIN)
-void launch_nl_rebuild(int prec, const NlArgs& a, int pblk, int cblk, int rblk, bool bin, hipStream_t s);
+size_t nl_stage_bytes(int prec, int cap);  // dynamic LDS of the rebuild
+// binning (unless the step before binned), tile scan and per-tile rebuild; then, once the
+// chain table is final, launch_nl_remap
+void launch_nl_rebuild(int prec, const NlArgs& a, int pblk, int ntile, bool bin, hipStream_t s);
+void launch_nl_remap(const NlArgs& a, int pblk, hipStream_t s);
 // ev0/ev1 (optional): events stamped at the kernel's own start and end
-void launch_nl_step(int prec, int mode, const NlArgs& a, int pblk, hipStream_t s, hipEvent_t ev0 = nullptr,
+void launch_nl_step(int prec, int mode, const NlArgs& a, int ntile, hipStream_t s, hipEvent_t ev0 = nullptr,
                     hipEvent_t ev1 = nullptr);
 size_t rel_bytes(int prec);
 

@@ -408,126 +408,6 @@ __global__ __launch_bounds__(256) void k_force(ForceArgs a) {
   if (errbits) atomicOr(&a.err[k], errbits);
 }
 
-// ---------------------------------------------------------------------------------------
-// Spatial reordering of the per-monomer storage: slots are renumbered in cell order
-// (row-major cells, ascending old slot within a cell), so that consecutive threads and each
-// XCD's share of the grid touch a compact region of the box.
-// ---------------------------------------------------------------------------------------
-// exclusive scan of the bucket occupancies over all cells (one workgroup; once per reorder)
-// Exclusive scan of the (capped) cell occupancies into start[0..NC], in three coalesced
-// passes: per-block sums over runs of SCAN_RUN cells, a scan of the block sums, then each
-// block's local scan plus its offset.
-constexpr int SCAN_RUN = 1024;  // cells per block: 256 threads x 4
-
-__device__ __forceinline__ int block_excl_scan_256(int v, int* s_w, int* total) {
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  int incl = v;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const int t = __shfl_up(incl, o, 64);
-    if (lane >= o) incl += t;
-  }
-  if (lane == 63) s_w[wv] = incl;
-  __syncthreads();
-  int off = 0, tot = 0;
-#pragma unroll
-  for (int q = 0; q < 4; ++q) { off += q < wv ? s_w[q] : 0; tot += s_w[q]; }
-  *total = tot;
-  return off + incl - v;
-}
-
-__global__ __launch_bounds__(256) void k_scan_part(const int* __restrict__ cnt, int cap, int NC,
-                                                   int* __restrict__ part) {
-  __shared__ int s_w[4];
-  const int c0 = blockIdx.x * SCAN_RUN + 4 * threadIdx.x;
-  int sum = 0;
-#pragma unroll
-  for (int q = 0; q < 4; ++q) sum += (c0 + q < NC) ? min(cnt[c0 + q], cap) : 0;
-  int tot;
-  block_excl_scan_256(sum, s_w, &tot);
-  if (threadIdx.x == 0) part[blockIdx.x] = tot;
-}
-
-// one workgroup: exclusive scan of the nb block sums in place (runs of 1024 with a carry)
-__global__ __launch_bounds__(1024) void k_scan_top(int* __restrict__ part, int nb, int* __restrict__ total) {
-  __shared__ int s_w[16];
-  __shared__ int s_carry;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  if (threadIdx.x == 0) s_carry = 0;
-  __syncthreads();
-  for (int b0 = 0; b0 < nb; b0 += 1024) {
-    const int i = b0 + (int)threadIdx.x;
-    const int v = i < nb ? part[i] : 0;
-    int incl = v;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-      const int t = __shfl_up(incl, o, 64);
-      if (lane >= o) incl += t;
-    }
-    if (lane == 63) s_w[wv] = incl;
-    __syncthreads();
-    int off = s_carry, tot = 0;
-    for (int q = 0; q < 16; ++q) { off += q < wv ? s_w[q] : 0; tot += s_w[q]; }
-    if (i < nb) part[i] = off + incl - v;
-    __syncthreads();
-    if (threadIdx.x == 0) s_carry += tot;
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) *total = s_carry;
-}
-
-__global__ __launch_bounds__(256) void k_scan_final(const int* __restrict__ cnt, int cap, int NC,
-                                                    const int* __restrict__ part, const int* __restrict__ total,
-                                                    int* __restrict__ start) {
-  __shared__ int s_w[4];
-  const int c0 = blockIdx.x * SCAN_RUN + 4 * threadIdx.x;
-  int v[4], sum = 0;
-#pragma unroll
-  for (int q = 0; q < 4; ++q) { v[q] = (c0 + q < NC) ? min(cnt[c0 + q], cap) : 0; sum += v[q]; }
-  int tot;
-  int run = part[blockIdx.x] + block_excl_scan_256(sum, s_w, &tot);
-#pragma unroll
-  for (int q = 0; q < 4; ++q)
-    if (c0 + q < NC) { start[c0 + q] = run; run += v[q]; }
-  if (blockIdx.x == 0 && threadIdx.x == 0) start[NC] = *total;
-}
-
-// perm[new slot] = old slot, inv[old slot] = new slot
-__global__ __launch_bounds__(256) void k_perm_cells(const int* __restrict__ cnt, const int* __restrict__ bucket,
-                                                    int cap, const int* __restrict__ start, int NC,
-                                                    int* __restrict__ perm, int* __restrict__ inv) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= NC) return;
-  const int n = min(cnt[c], cap), s0 = start[c];
-  for (int j = 0; j < n; ++j) {
-    const int old = bucket[c * cap + j];
-    perm[s0 + j] = old;
-    inv[old] = s0 + j;
-  }
-}
-
-__global__ __launch_bounds__(256) void k_gather_f64x3(double* __restrict__ dst, const double* __restrict__ src,
-                                                      const int* __restrict__ perm, int NP) {
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= NP) return;
-  const int o = perm[s];
-  dst[s] = src[o];
-  dst[NP + s] = src[NP + o];
-  dst[2 * NP + s] = src[2 * NP + o];
-}
-
-__global__ __launch_bounds__(256) void k_gather_i32(int* __restrict__ dst, const int* __restrict__ src,
-                                                    const int* __restrict__ perm, int NP) {
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s < NP) dst[s] = src[perm[s]];
-}
-
-// chain tables hold slots: map them through inv
-__global__ __launch_bounds__(256) void k_remap_i32(int* __restrict__ a, const int* __restrict__ inv, int NP) {
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s < NP) a[s] = inv[a[s]];
-}
-
 // per-melt step counters advance after a run of closing kicks
 __global__ void k_advance(uint64_t* step_base, int nm, uint64_t n) {
   int k = blockIdx.x * blockDim.x + threadIdx.x;
@@ -596,26 +476,6 @@ void launch_advance(uint64_t* step_base, int nm, uint64_t n, hipStream_t s) {
 
 void launch_fill_i32(int* p, int n, int v, hipStream_t s) {
   if (n > 0) hipLaunchKernelGGL(k_fill_i32, dim3((n + 255) / 256), dim3(256), 0, s, p, n, v);
-}
-
-void launch_perm_cells(const int* cnt, const int* bucket, int cap, int NC, int* start, int* perm, int* inv,
-                       hipStream_t s) {
-  // start[NC + 1 ..] serves as scratch: block sums, then the total
-  const int nb = (NC + SCAN_RUN - 1) / SCAN_RUN;
-  int* part = start + NC + 2;
-  hipLaunchKernelGGL(k_scan_part, dim3(nb), dim3(256), 0, s, cnt, cap, NC, part);
-  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, part, nb, start + NC + 1);
-  hipLaunchKernelGGL(k_scan_final, dim3(nb), dim3(256), 0, s, cnt, cap, NC, part, start + NC + 1, start);
-  hipLaunchKernelGGL(k_perm_cells, dim3((NC + 255) / 256), dim3(256), 0, s, cnt, bucket, cap, start, NC, perm, inv);
-}
-void launch_gather_f64x3(double* dst, const double* src, const int* perm, int NP, hipStream_t s) {
-  hipLaunchKernelGGL(k_gather_f64x3, dim3((NP + 255) / 256), dim3(256), 0, s, dst, src, perm, NP);
-}
-void launch_gather_i32(int* dst, const int* src, const int* perm, int NP, hipStream_t s) {
-  hipLaunchKernelGGL(k_gather_i32, dim3((NP + 255) / 256), dim3(256), 0, s, dst, src, perm, NP);
-}
-void launch_remap_i32(int* a, const int* inv, int NP, hipStream_t s) {
-  hipLaunchKernelGGL(k_remap_i32, dim3((NP + 255) / 256), dim3(256), 0, s, a, inv, NP);
 }
 
 size_t spos_bytes(int prec) { return prec ? sizeof(SPos<float>) : sizeof(SPos<double>); }

@@ -1,19 +1,31 @@
-// Production MD step on gfx950: Verlet neighbour lists rebuilt every K steps.
+// Production MD step on gfx950: Verlet neighbour lists over a tile-sorted storage order,
+// with every workgroup's neighbourhood staged in LDS.
 //
-// Rebuild (every K steps): bin the monomers into a grid of cells of edge >= r_list = r_c + skin
-// (counting sort with id-ordered buckets), record for each monomer its reference cell and its
-// position relative to that cell's origin, and list the monomers within r_list in the 27
-// neighbouring cells together with the cell offset (a 5-bit code), from neighbourhoods staged
-// in LDS one row segment at a time.  Lists are stored in tiles of 64 monomers: entries
-// 4q .. 4q + 3 of monomer i form one 16-byte word at ((i / 64) * NL_CAP / 4 + q) * 64 + i % 64,
-// so a wavefront of consecutive monomers reads (and the build writes) 1 KB runs.
+// Geometry.  The list grid has cells of edge >= r_list = r_c + skin.  Its cells are grouped
+// into tiles of nl_S x nl_Sy cells of one z-plane; a tile's cells are numbered row by row, and
+// the tiles of a plane, then the planes, follow one another ("sorted cell index").
 //
-// Step: one kernel per step; one thread per monomer runs the truncated MLJ^n pair force over
-// its list (displacements from reference-cell-relative coordinates, so FP32 keeps full
-// relative precision), the FENE and angle forces along its chain, and the Langevin
-// velocity-Verlet update.  It writes the new relative coordinates to the other buffer and
-// flags the run stale when a monomer has moved more than skin/2 since the rebuild (the host
-// then reruns the chunk with more frequent rebuilds).
+// Rebuild (every K steps).  (1) Binning: each monomer's list cell, counted per cell and per
+// tile (wave-aggregated atomics) with its storage slot appended to the cell's bucket; the
+// step before a rebuild bins the positions it has just written.  (2) A scan of the tile
+// counts gives each tile's first storage slot.  (3) One workgroup per tile stages the members
+// of the 3 (nl_S + 2)(nl_Sy + 2) cells around the tile in LDS, ordered by cell and by monomer
+// id within a cell, at their positions relative to the tile (so that periodic images need no
+// offsets); it moves its own members to their new storage slots (cell order, monomer id
+// within a cell: a canonical order that does not depend on the history of the run), records
+// each one's position relative to its cell (its reference cell until the next rebuild), and
+// lists for each one the staged members within r_list as 16-bit indices into the stage.
+// (4) The chain table, chain positions and bonded-neighbour slots are carried over to the new
+// slots.
+//
+// Step.  One workgroup per tile stages the current positions of the same neighbourhood (the
+// storage of a cell is contiguous, so the stage is a set of contiguous runs), then each thread
+// takes one home monomer: the truncated MLJ^n pair force over its list (LDS reads), the FENE
+// and angle forces from its four chain neighbours' relative positions and cells, the Langevin
+// noise, and the velocity-Verlet update.  List validity: each step records the largest
+// displacement of its monomers (per melt); a list is valid while the sum of those maxima since
+// its rebuild is at most skin/2, which bounds every monomer's displacement.  A run that exceeds
+// it is redone by the host with more frequent rebuilds.
 #include <hip/hip_ext.h>
 
 #include "kgdb_dev.h"
@@ -21,44 +33,173 @@
 
 namespace kgdb {
 
-template <typename R> struct Rel4;
-template <> struct Rel4<float> { float x, y, z, w; };
-template <> struct Rel4<double> { double x, y, z, w; };
-
 __device__ __forceinline__ int pack_cell(int cx, int cy, int cz) { return cx | (cy << 10) | (cz << 20); }
 
-// ---------------------------------------------------------------------------------------
-// rebuild 1: binning into the list grid
-// ---------------------------------------------------------------------------------------
-// Monomers are stored in cell order from the previous rebuild, so a wavefront's lanes mostly
-// fall into a few cells: each run of lanes with the same cell takes its bucket slots with one
-// atomic (the order within a bucket is fixed by the finalisation).  Inactive lanes end runs,
-// so the step kernel (whose last wavefront of a melt may have left lanes) bins the same way.
-__device__ __forceinline__ void nl_bin_wave(const NlArgs& a, int k, int g, int c) {
-  const int lane = threadIdx.x & 63;
-  const int prev = __shfl_up(c, 1, 64);
-  const uint64_t active = __ballot(1);
-  const bool prev_on = lane > 0 && ((active >> (lane - 1)) & 1ull);
-  const uint64_t heads = __ballot(!prev_on || prev != c);  // first lane of each run
-  const uint64_t upto = (2ull << lane) - 1ull;             // lanes 0 .. lane (all 64 for lane 63)
-  const int hl = 63 - __builtin_clzll(heads & upto);
-  int base = 0;
-  if (hl == lane && c >= 0) {
-    const uint64_t after = (heads | ~active) & ~upto;
-    const int next = after ? __builtin_ctzll(after) : 64;
-    base = atomicAdd(&a.cnt[c], next - lane);
+// Position of a monomer relative to its reference cell (the list-grid cell it was sorted into
+// at the last rebuild), and relative to a tile's frame once staged.  With FP32 forces it is
+// kept in fixed point, 2^24 units per cell edge (about 1e-7 sigma per unit): displacements
+// between two monomers are then exact integer differences, however far the frame extends
+// (a tile and its halo span up to ~66 cells), and only the displacement itself is rounded to
+// FP32.  With FP64 forces it is kept in FP64.  The fourth word holds the packed reference cell.
+template <typename R> struct Rel;
+template <> struct Rel<float> {
+  using T = int4;
+  static constexpr double UNITS = 16777216.0;  // per cell edge
+  __device__ static T make(double dx, double dy, double dz, int pc, double hl) {
+    const double s = UNITS / hl;
+    return make_int4((int)rint(dx * s), (int)rint(dy * s), (int)rint(dz * s), pc);
   }
-  base = __shfl(base, hl, 64);
-  if (c < 0) return;
-  const int s = base + (lane - hl);
-  if (s < NL_CELL_CAP) a.bucket_raw[c * NL_CELL_CAP + s] = g;
-  else atomicOr(&a.err[k], ERR_CELL_OVERFLOW);
+  __device__ static T shift(T p, int ox, int oy, int oz) {
+    p.x += ox << 24;
+    p.y += oy << 24;
+    p.z += oz << 24;
+    return p;
+  }
+  // a - b in units of the fixed point (the caller scales by the unit length)
+  __device__ static void diff(const T& a, const T& b, float& dx, float& dy, float& dz) {
+    dx = (float)(a.x - b.x);
+    dy = (float)(a.y - b.y);
+    dz = (float)(a.z - b.z);
+  }
+  __device__ static int cell(const T& p) { return p.w; }
+  __host__ __device__ static double unit(double hl) { return hl / UNITS; }
+  // a - b for a monomer a whose reference cell lies (ox, oy, oz) cells from b's (each in
+  // (-nc/2, nc/2]), as the nearest periodic image, in units
+  __device__ static void image_diff(const T& a, const T& b, int ox, int oy, int oz, int nc, double, float& dx,
+                                    float& dy, float& dz) {
+    int d[3] = {a.x - b.x + (ox << 24), a.y - b.y + (oy << 24), a.z - b.z + (oz << 24)};
+    if (nc < 128) {  // boxes of fewer than 128 cells: the displacement may be nearer through the other image
+      const int Lu = nc << 24, hLu = Lu >> 1;
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        d[q] -= d[q] > hLu ? Lu : 0;
+        d[q] += d[q] < -hLu ? Lu : 0;
+      }
+    }
+    dx = (float)d[0];
+    dy = (float)d[1];
+    dz = (float)d[2];
+  }
+};
+template <> struct Rel<double> {
+  struct alignas(32) T { double x, y, z, w; };
+  __device__ static T make(double dx, double dy, double dz, int pc, double) { return T{dx, dy, dz, (double)pc}; }
+  __device__ static T shift(T p, int ox, int oy, int oz, double hl) {
+    p.x += ox * hl;
+    p.y += oy * hl;
+    p.z += oz * hl;
+    return p;
+  }
+  __device__ static void diff(const T& a, const T& b, double& dx, double& dy, double& dz) {
+    dx = a.x - b.x;
+    dy = a.y - b.y;
+    dz = a.z - b.z;
+  }
+  __device__ static int cell(const T& p) { return (int)p.w; }
+  __host__ __device__ static double unit(double) { return 1.0; }
+  __device__ static void image_diff(const T& a, const T& b, int ox, int oy, int oz, int nc, double hl, double& dx,
+                                    double& dy, double& dz) {
+    const double L = nc * hl, iL = 1.0 / L;
+    dx = a.x - b.x + ox * hl;
+    dy = a.y - b.y + oy * hl;
+    dz = a.z - b.z + oz * hl;
+    dx -= L * rint(dx * iL);
+    dy -= L * rint(dy * iL);
+    dz -= L * rint(dz * iL);
+  }
+};
+template <typename R>
+__device__ __forceinline__ typename Rel<R>::T rel_shift(const typename Rel<R>::T& p, int ox, int oy, int oz, double hl) {
+  if constexpr (sizeof(R) == 4) {
+    (void)hl;
+    return Rel<float>::shift(p, ox, oy, oz);
+  } else {
+    return Rel<double>::shift(p, ox, oy, oz, hl);
+  }
 }
 
-// the list-grid cell of a position
-__device__ __forceinline__ int nl_cell(const MeltDesc& d, double x, double y, double z) {
+// ---------------------------------------------------------------------------------------
+// tile geometry
+// ---------------------------------------------------------------------------------------
+struct TileGeo {
+  int x0, y0, cz, nh, nhy;
+};
+__device__ __forceinline__ TileGeo tile_geo(const MeltDesc& d, int t) {
+  const int seg = t % d.nl_nseg;
+  t /= d.nl_nseg;
+  const int yb = t % d.nl_nyb;
+  TileGeo g;
+  g.cz = t / d.nl_nyb;
+  g.x0 = seg * d.nl_S;
+  g.y0 = yb * d.nl_Sy;
+  g.nh = min(d.nl_S, d.ncl - g.x0);
+  g.nhy = min(d.nl_Sy, d.ncl - g.y0);
+  return g;
+}
+// sorted index of list-grid cell (cx, cy, cz) of melt d (global over the batch) and its tile
+__device__ __forceinline__ int sorted_cell(const MeltDesc& d, int cx, int cy, int cz, int* tile) {
   const int nc = d.ncl;
-  return d.celll_off + (cell_coord(z, d.cinvl, nc) * nc + cell_coord(y, d.cinvl, nc)) * nc + cell_coord(x, d.cinvl, nc);
+  const int xb = cx / d.nl_S, yb = cy / d.nl_Sy;
+  const int x0 = xb * d.nl_S, y0 = yb * d.nl_Sy;
+  const int nh = min(d.nl_S, nc - x0), nhy = min(d.nl_Sy, nc - y0);
+  if (tile) *tile = d.tile_off + (cz * d.nl_nyb + yb) * d.nl_nseg + xb;
+  return d.celll_off + cz * nc * nc + y0 * nc + x0 * nhy + (cy - y0) * nh + (cx - x0);
+}
+__device__ __forceinline__ int wrapc(int c, int nc) { return c < 0 ? c + nc : (c >= nc ? c - nc : c); }
+
+// staged cell t of a tile: (x index i, y index yy, z index zz) in a frame of W x WY x 3 cells
+// whose cell (1, 1, 1) is the tile's first home cell; its grid cell and sorted index
+struct StagedCell {
+  int i, yy, zz, ax, ay, az;
+};
+__device__ __forceinline__ StagedCell staged_cell(const MeltDesc& d, const TileGeo& tg, int W, int WY, int t) {
+  StagedCell s;
+  const int row = t / W;
+  s.i = t - row * W;
+  s.zz = row / WY;
+  s.yy = row - s.zz * WY;
+  const int nc = d.ncl;
+  s.ax = wrapc(tg.x0 - 1 + s.i, nc);
+  s.ay = wrapc(tg.y0 - 1 + s.yy, nc);
+  s.az = wrapc(tg.cz - 1 + s.zz, nc);
+  return s;
+}
+
+// ---------------------------------------------------------------------------------------
+// binning: runs of lanes with the same cell (resp. tile) take their slots with one atomic
+// ---------------------------------------------------------------------------------------
+// first lane of the run of equal keys that this lane belongs to, its length, and the base
+// returned by one atomicAdd per run; inactive lanes (and key < 0) end runs
+__device__ __forceinline__ int run_add(int* ctr, int key) {
+  const int lane = threadIdx.x & 63;
+  const int prev = __shfl_up(key, 1, 64);
+  const uint64_t active = __ballot(1);
+  const bool prev_on = lane > 0 && ((active >> (lane - 1)) & 1ull);
+  const uint64_t heads = __ballot(!prev_on || prev != key);
+  const uint64_t upto = (2ull << lane) - 1ull;  // lanes 0 .. lane
+  const int hl = 63 - __builtin_clzll(heads & upto);
+  int base = 0;
+  if (hl == lane && key >= 0) {
+    const uint64_t after = (heads | ~active) & ~upto;
+    const int next = after ? __builtin_ctzll(after) : 64;
+    base = atomicAdd(&ctr[key], next - lane);
+  }
+  base = __shfl(base, hl, 64);
+  return base + (lane - hl);
+}
+
+__device__ __forceinline__ void nl_bin_one(const NlArgs& a, int k, const MeltDesc& d, int g, double x, double y,
+                                           double z, bool valid) {
+  int sc = -1, tile = -1;
+  if (valid) {
+    const int nc = d.ncl;
+    sc = sorted_cell(d, cell_coord(x, d.cinvl, nc), cell_coord(y, d.cinvl, nc), cell_coord(z, d.cinvl, nc), &tile);
+  }
+  const int s = run_add(a.cnt, sc);
+  (void)run_add(a.tcnt, tile);
+  if (!valid) return;
+  if (s < NL_CELL_CAP) a.bucket_raw[sc * NL_CELL_CAP + s] = g;
+  else atomicOr(&a.err[k], ERR_CELL_OVERFLOW);
 }
 
 __global__ __launch_bounds__(256) void k_nl_bin(NlArgs a) {
@@ -68,117 +209,108 @@ __global__ __launch_bounds__(256) void k_nl_bin(NlArgs a) {
   const int li = a.pblk_base[lb] + (int)threadIdx.x;
   const bool valid = li < d.Nm;
   const int g = d.off + (valid ? li : 0);
-  int c = -1;
-  if (valid) {
-    c = nl_cell(d, a.x[g], a.x[a.NP + g], a.x[2 * a.NP + g]);
-    a.cell_l[g] = c;
-  }
-  nl_bin_wave(a, k, g, c);
+  double x = 0, y = 0, z = 0;
+  if (valid) { x = a.x[g]; y = a.x[a.NP + g]; z = a.x[2 * a.NP + g]; }
+  nl_bin_one(a, k, d, g, x, y, z, valid);
 }
 
-// ---------------------------------------------------------------------------------------
-// rebuild 2: one thread per monomer: its rank by slot within its cell's bucket (buckets end up
-// ordered by slot), its reference cell and reference-relative position; the other occupancy
-// buffer is cleared over the current grid
-// ---------------------------------------------------------------------------------------
-template <typename R>
-__global__ __launch_bounds__(256) void k_nl_finalize(NlArgs a) {
-  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < a.ncl_total; t += gridDim.x * blockDim.x)
-    a.cnt_clear[t] = 0;
-  const int lb = xcd_remap(blockIdx.x, gridDim.x);
-  const int k = __builtin_amdgcn_readfirstlane(a.pblk_melt[lb]);
-  const MeltDesc& d = a.md[k];
-  const int li = a.pblk_base[lb] + (int)threadIdx.x;
-  if (li >= d.Nm) return;
-  const int g = d.off + li;
-  const int c = a.cell_l[g];
-  const int n = min(a.cnt[c], NL_CELL_CAP);
-  const int base = c * NL_CELL_CAP;
-  int r = 0;
-  for (int j0 = 0; j0 < n; j0 += 4) {
-    const int4 q = *(const int4*)(a.bucket_raw + base + j0);
-    r += (q.x < g) + (j0 + 1 < n && q.y < g) + (j0 + 2 < n && q.z < g) + (j0 + 3 < n && q.w < g);
-  }
-  if (r < NL_CELL_CAP) a.bucket[base + r] = g;
-  const int nc = d.ncl, lc = c - d.celll_off;
-  const int cx = lc % nc, cy = (lc / nc) % nc, cz = lc / (nc * nc);
-  Rel4<R> p;
-  p.x = (R)(a.x[g] - cx * d.hl);
-  p.y = (R)(a.x[a.NP + g] - cy * d.hl);
-  p.z = (R)(a.x[2 * a.NP + g] - cz * d.hl);
-  p.w = (R)0;
-  ((Rel4<R>*)a.rel_cur)[g] = p;
-  a.relb[g] = make_float4((float)p.x, (float)p.y, (float)p.z, 0.f);
-  a.refc[g] = pack_cell(cx, cy, cz);
-}
-
-// ---------------------------------------------------------------------------------------
-// rebuild 3: neighbour lists (all monomers within r_list, bonded ones included: every pair
-// feels MLJ^n once).  One workgroup per block of nl_S x nl_Sy home cells in one z-plane of
-// the list grid: it stages the members of the (nl_S + 2) x (nl_Sy + 2) x 3 cells around the
-// block in LDS, then each thread lists one home monomer.  Candidates are visited row by row
-// (oz, then oy), the row's three cells in x order, each bucket in slot order.
-// ---------------------------------------------------------------------------------------
-constexpr int NLB_CELLS = 594;   // staged cells: 3 (nl_S + 2)(nl_Sy + 2) <= 594
-
-// A staged monomer: position in the block frame (origin at the corner of the first home cell,
-// so displacements need no per-cell offsets) and tag = (slot << 8) | (9 zz + 3 yy + i + 1) for
-// staged cell (x index i, y index yy, z index zz).  For a pair, the tag difference plus 13
-// is the 27-cell offset code of the list entry.
-template <typename R> struct alignas(16) Staged { R x, y, z; uint32_t tag; };
-
-// 16-byte word q of monomer i's list
-__device__ __forceinline__ size_t nl_word(int i, int q) {
-  return ((size_t)(i >> 6) * (NL_CAP / 4) + (size_t)q) * 64 + (size_t)(i & 63);
-}
-
-// The list of one home monomer (staged index tme, staged x index ih, y index yy); at(t, tmax)
-// gives staged member t, or any valid member when t > tmax.
-//
-// The neighbourhood is the 3 x 3 rows (z index zz, y offset dy) of three cells along x.  A row,
-// or a side cell of it, whose nearest point is farther than r_list plus a margin (far above
-// the rounding of frame coordinates) holds no member within r_list and is skipped: the list is
-// the same.  Hits of a run of up to 32 members are collected as a bit mask first (the home
-// monomer's own bit cleared), then appended in order, four entries per 16-byte store.
-template <typename R, typename At>
-__device__ __forceinline__ void nl_list_one(const NlArgs& a, int k, const Staged<R>& me, int tme, int ih, int yy,
-                                            int W, int WY, R hl, R rl2, R rskip2, const int* s_off, At at) {
-  uint4* __restrict__ out = (uint4*)a.nlist;
-  const int g = (int)(me.tag >> 8);
-  const uint32_t hv = (me.tag & 255u) - 13u;
-  uint4 acc = make_uint4(0, 0, 0, 0);  // the entries of the word being filled
-  int cnt = 0;
-  auto put = [&](uint32_t tag) {  // entry = (slot << 5) | (9 (oz + 1) + 3 (oy + 1) + ox + 1)
-    const uint32_t en = ((tag >> 3) & ~31u) | ((tag & 255u) - hv);
-    const int sl = cnt & 3;
-    acc.x = sl == 0 ? en : acc.x;
-    acc.y = sl == 1 ? en : acc.y;
-    acc.z = sl == 2 ? en : acc.z;
-    acc.w = sl == 3 ? en : acc.w;
-    if (sl == 3 && cnt < NL_CAP) out[nl_word(g, cnt >> 2)] = acc;
-    ++cnt;
-  };
-  auto hits = [&](int r0, int re) {  // hit mask of members r0 .. re - 1 (re - r0 <= 32)
-    uint32_t m = 0;
-    for (int t0 = r0; t0 < re; t0 += 4) {
-      // at() may read up to three entries past the run (masked below)
-      Staged<R> p[4];
+// exclusive scan of the tile counts (one workgroup, runs of 1024 with a carry)
+__global__ __launch_bounds__(1024) void k_tile_scan(const int* __restrict__ tcnt, int nt, int* __restrict__ tstart) {
+  __shared__ int s_w[16];
+  __shared__ int s_carry;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (threadIdx.x == 0) s_carry = 0;
+  __syncthreads();
+  for (int b0 = 0; b0 < nt; b0 += 1024) {
+    const int i = b0 + (int)threadIdx.x;
+    const int v = i < nt ? tcnt[i] : 0;
+    int incl = v;
 #pragma unroll
-      for (int u = 0; u < 4; ++u) p[u] = at(t0 + u, re - 1);
-      uint32_t nib = 0;  // straight-line: no branches per candidate
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const R dx = p[u].x - me.x, dy = p[u].y - me.y, dz = p[u].z - me.z;
-        nib |= (uint32_t)(dx * dx + dy * dy + dz * dz < rl2) << u;
-      }
-      const int rem = re - t0;
-      nib &= rem >= 4 ? 15u : ((1u << rem) - 1u);
-      m |= nib << (t0 - r0);
+    for (int o = 1; o < 64; o <<= 1) {
+      const int t = __shfl_up(incl, o, 64);
+      if (lane >= o) incl += t;
     }
-    return m;
-  };
-  // distances from the home monomer to the faces of its cell (frame origin: low corner of the
-  // first home cell, which has x index 1)
+    if (lane == 63) s_w[wv] = incl;
+    __syncthreads();
+    int off = s_carry, tot = 0;
+    for (int q = 0; q < 16; ++q) { off += q < wv ? s_w[q] : 0; tot += s_w[q]; }
+    if (i < nt) tstart[i] = off + incl - v;
+    __syncthreads();
+    if (threadIdx.x == 0) s_carry += tot;
+    __syncthreads();
+  }
+}
+
+// inclusive prefix of s[1..n] in place (s[0] = 0), one wavefront
+__device__ __forceinline__ void wave_prefix(int* s, int n) {
+  const int lane = threadIdx.x & 63;
+  const int per = (n + 63) >> 6;
+  int sum = 0;
+  for (int q = 0; q < per; ++q) {
+    const int t = lane * per + q;
+    if (t < n) sum += s[t + 1];
+  }
+  int incl = sum;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int v = __shfl_up(incl, o, 64);
+    if (lane >= o) incl += v;
+  }
+  int acc = incl - sum;
+  for (int q = 0; q < per; ++q) {
+    const int t = lane * per + q;
+    if (t < n) { acc += s[t + 1]; s[t + 1] = acc; }
+  }
+  if (lane == 0) s[0] = 0;
+}
+
+// first index t in [lo, hi) with s[t + 1] > v (s ascending; s[lo] <= v)
+__device__ __forceinline__ int find_cell(const int* s, int lo, int hi, int v) {
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (s[mid] <= v) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+constexpr int NLB_CELLS = 594;  // staged cells: 3 (nl_S + 2)(nl_Sy + 2) <= 594
+constexpr int STAGE_PER_THREAD = (STAGE_CAP_MAX + NLB_THREADS - 1) / NLB_THREADS;
+
+// a staged member: position relative to the tile frame, and (rebuild only) its old slot
+template <typename R> struct alignas(16) Staged { R x, y, z; int tag; };
+
+// 16-byte word q (eight 16-bit entries) of the list of the monomer in slot i
+__device__ __forceinline__ size_t nl_word(int i, int q) {
+  return ((size_t)(i >> 6) * (NL_CAP / 8) + (size_t)q) * 64 + (size_t)(i & 63);
+}
+
+// ---------------------------------------------------------------------------------------
+// rebuild 3: per tile, stage, move the home members to their new slots, list
+// ---------------------------------------------------------------------------------------
+// The members of staged cell t sorted by monomer id: slot of the member of rank r.
+__device__ __forceinline__ int member_slot(const NlArgs& a, int sc, int n, int r) {
+  const int* b = a.bucket_raw + (size_t)sc * NL_CELL_CAP;
+  for (int j = 0; j < n; ++j) {
+    const int sj = b[j], mj = a.mono[sj];
+    int rank = 0;
+    for (int m = 0; m < n; ++m) rank += a.mono[b[m]] < mj;
+    if (rank == r) return sj;
+  }
+  return b[0];
+}
+
+// The list of one home monomer (staged position me, staged index tme, home cell (ih, yy) of
+// the frame): staged members within r_list in the 3 x 3 rows of three cells around it.  A
+// row, or a side cell of it, whose nearest point is beyond r_list plus a margin (far above the
+// rounding of frame coordinates) holds no member within r_list and is skipped.  at(t) gives
+// staged member t.  Each entry is stored as it is found (16 bits; entry j of slot g lies in
+// word nl_word(g, j / 8) at place j % 8), so that taking a candidate costs no branch.
+template <typename R, typename At>
+__device__ __forceinline__ int nl_list_one(const NlArgs& a, int g, const Staged<R>& me, int tme, int ih, int yy,
+                                           int W, int WY, R hl, R rl2, R rskip2, const int* s_off, At at) {
+  uint16_t* __restrict__ out = (uint16_t*)a.nlist + nl_word(g, 0) * 8;
+  int cnt = 0;
   const R cx0 = (R)(ih - 1) * hl, cy0 = (R)(yy - 1) * hl;
   const R dxl = me.x - cx0, dxr = cx0 + hl - me.x;
   const R dyl = me.y - cy0, dyr = cy0 + hl - me.y;
@@ -196,143 +328,208 @@ __device__ __forceinline__ void nl_list_one(const NlArgs& a, int k, const Staged
         if (dxl * dxl + e2 > rskip2) b = s_off[c0 + 1];
         if (dxr * dxr + e2 > rskip2) e = s_off[c0 + 2];
       }
-      const int re = min(e, b + 32);
-      uint32_t m = hits(b, re);
-      const int sb = tme - b;  // the home monomer itself
-      if (sb >= 0 && sb < 32) m &= ~(1u << sb);
-      while (m) {
-        const int bit = __builtin_ctz(m);
-        m &= m - 1;
-        put(at(b + bit, b + bit).tag);
-      }
-      for (int r0 = re; r0 < e; r0 += 32) {  // members past the first 32 of a run
-        uint32_t m2 = hits(r0, min(e, r0 + 32));
-        while (m2) {
-          const int bit = __builtin_ctz(m2);
-          m2 &= m2 - 1;
-          const uint32_t tag = at(r0 + bit, r0 + bit).tag;
-          if (tag != me.tag) put(tag);
+      for (int t0 = b; t0 < e; t0 += 4) {
+        Staged<R> p[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) p[u] = at(min(t0 + u, e - 1));
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const R dx = p[u].x - me.x, dy2 = p[u].y - me.y, dz = p[u].z - me.z;
+          if (t0 + u < e && t0 + u != tme && dx * dx + dy2 * dy2 + dz * dz < rl2) {
+            if (cnt < NL_CAP) out[(cnt >> 3) * 512 + (cnt & 7)] = (uint16_t)(t0 + u);
+            ++cnt;
+          }
         }
       }
     }
   }
-  if ((cnt & 3) && cnt < NL_CAP) out[nl_word(g, cnt >> 2)] = acc;  // the partial last word
-  if (cnt > NL_CAP) { atomicOr(&a.err[k], ERR_NLIST_OVERFLOW); cnt = NL_CAP; }
-  a.nlen[g] = cnt;
+  return cnt;
 }
 
 template <typename R>
-__global__ __launch_bounds__(NLB_THREADS) void k_nl_build(NlArgs a) {
-  // a.stage_cap staged members (+ 4 of padding for reads past a run) in dynamic LDS
+__global__ __launch_bounds__(NLB_THREADS) void k_nl_rebuild(NlArgs a) {
+  // the stage holds FP32 frame positions in both precisions: they only decide list membership,
+  // whose cutoff carries a margin far above their rounding
   extern __shared__ __align__(16) unsigned char s_dyn[];
-  Staged<R>* s_pos = (Staged<R>*)s_dyn;
-  __shared__ int s_off[NLB_CELLS + 1];  // staged cell -> first staged member
+  Staged<float>* s_pos = (Staged<float>*)s_dyn;
+  // monomer ids of the staged members in binning order: they share the stage's memory and are
+  // consumed before it is written
+  int* s_mono = (int*)s_dyn;
+  __shared__ int s_off[NLB_CELLS + 1];
+  __shared__ int s_sc[NLB_CELLS];
+  __shared__ int s_home[NLB_CELLS + 1];  // prefix of the home cells' counts, sorted order
+  __shared__ uint8_t s_wrap[NLB_CELLS];  // per staged cell and axis: periodic wrap -1, 0, +1 (2 bits each, +1)
   const int lb = xcd_remap(blockIdx.x, gridDim.x);
   const int k = __builtin_amdgcn_readfirstlane(a.rblk_melt[lb]);
+  const int lt = a.rblk_base[lb];
   const MeltDesc& d = a.md[k];
-  const int nc = d.ncl, nseg = d.nl_nseg, nyb = d.nl_nyb, S = d.nl_S, Sy = d.nl_Sy;
-  const int W = S + 2, WY = Sy + 2;
-  int rb = a.rblk_base[lb];
-  const int seg = rb % nseg;
-  rb /= nseg;
-  const int yb = rb % nyb, cz = rb / nyb;
-  const int x0 = seg * S, nh = min(S, nc - x0);   // home cells x0 .. x0 + nh - 1
-  const int y0 = yb * Sy, nhy = min(Sy, nc - y0); // and rows y0 .. y0 + nhy - 1
-  const int ncell = 3 * WY * W;
-  const R hl = (R)d.hl;
-  const Rel4<R>* __restrict__ rel = (const Rel4<R>*)a.rel_cur;
+  const TileGeo tg = tile_geo(d, lt);
+  const int W = tg.nh + 2, WY = tg.nhy + 2, ncell = 3 * WY * W;
+  const double hl = d.hl;
+  const int nc = d.ncl;
 
-  // staged cell t = (zz WY + yy) W + i sits at x = x0 - 1 + i, y = y0 - 1 + yy, z = cz - 1 + zz
-  auto cell_of = [&](int t) {
-    const int row = t / W, i = t - row * W;
-    const int zz = row / WY, yy = row - zz * WY;
-    const int nz = (cz - 1 + zz + nc) % nc, ny = (y0 - 1 + yy + nc) % nc, nx = (x0 - 1 + i + nc) % nc;
-    return d.celll_off + (nz * nc + ny) * nc + nx;
-  };
-  for (int t = threadIdx.x; t < ncell; t += NLB_THREADS) s_off[t + 1] = min(a.cnt[cell_of(t)], NL_CELL_CAP);
-  __syncthreads();
-  if (threadIdx.x < 64) {  // inclusive scan of the counts by one wavefront
-    const int lane = threadIdx.x;
-    const int per = (ncell + 63) >> 6;
-    int sum = 0;
-    for (int q = 0; q < per; ++q) { const int t = lane * per + q; if (t < ncell) sum += s_off[t + 1]; }
-    int incl = sum;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) { const int v = __shfl_up(incl, o, 64); if (lane >= o) incl += v; }
-    int acc = incl - sum;
-    for (int q = 0; q < per; ++q) {
-      const int t = lane * per + q;
-      if (t < ncell) { acc += s_off[t + 1]; s_off[t + 1] = acc; }
-    }
-    if (lane == 0) s_off[0] = 0;
+  for (int t = threadIdx.x; t < ncell; t += NLB_THREADS) {
+    const StagedCell s = staged_cell(d, tg, W, WY, t);
+    const int sc = sorted_cell(d, s.ax, s.ay, s.az, nullptr);
+    s_sc[t] = sc;
+    s_off[t + 1] = min(a.cnt[sc], NL_CELL_CAP);
+    const int wx = s.ax - (tg.x0 - 1 + s.i), wy = s.ay - (tg.y0 - 1 + s.yy), wz = s.az - (tg.cz - 1 + s.zz);
+    s_wrap[t] = (uint8_t)((wx > 0) - (wx < 0) + 1 + (((wy > 0) - (wy < 0) + 1) << 2) + (((wz > 0) - (wz < 0) + 1) << 4));
   }
+  __syncthreads();
+  if (threadIdx.x < 64) wave_prefix(s_off, ncell);
   __syncthreads();
   const int total = s_off[ncell];
-  const bool staged = total <= a.stage_cap;
-  // member t of the stage (or of the neighbourhood when it does not fit): its cell by
-  // bisection of s_off, then its slot, frame position and tag
-  auto member = [&](int t) -> Staged<R> {
-    int lo = 0, hi = ncell;
-    while (hi - lo > 1) { const int mid = (lo + hi) >> 1; if (s_off[mid] <= t) lo = mid; else hi = mid; }
-    const int id = a.bucket[cell_of(lo) * NL_CELL_CAP + (t - s_off[lo])];
-    const Rel4<R> p = rel[id];
-    const int row = lo / W, i = lo - row * W;
-    const int zz = row / WY, yy = row - zz * WY;
-    Staged<R> m;
-    m.x = p.x + (R)(i - 1) * hl;
-    m.y = p.y + (R)(yy - 1) * hl;
-    m.z = p.z + (R)(zz - 1) * hl;
-    m.tag = ((uint32_t)id << 8) | (uint32_t)(9 * zz + 3 * yy + i + 1);
+  const bool staged = total <= a.stage_cap && !(d.test_flags & TF_NL_GLOBAL);
+  if (threadIdx.x == 0 && !(d.test_flags & TF_NL_GLOBAL) && a.nlstat) {
+    atomicMax(&a.nlstat[1], (uint32_t)total);
+    if (!staged) atomicAdd(&a.nlstat[0], 1u);
+  }
+  // staged member of cell t with rank r: its frame position (from the FP64 position relative
+  // to its grid cell, plus the staged cell's place in the frame) and its old slot
+  // (the frame's cell (i, yy, zz) is grid cell (x0 - 1 + i, y0 - 1 + yy, cz - 1 + zz) up to the
+  // recorded periodic wrap, so that the frame origin of a member is (x0, y0, cz) + wrap nc)
+  auto make = [&](int t, int slot) {
+    const int f = s_wrap[t];
+    Staged<float> m;
+    m.x = (float)(a.x[slot] - (double)(tg.x0 + ((f & 3) - 1) * nc) * hl);
+    m.y = (float)(a.x[a.NP + slot] - (double)(tg.y0 + (((f >> 2) & 3) - 1) * nc) * hl);
+    m.z = (float)(a.x[2 * a.NP + slot] - (double)(tg.cz + ((f >> 4) - 1) * nc) * hl);
+    m.tag = slot;
     return m;
   };
+  // binned member u (cell q, place j in the cell's bucket): its old slot
+  auto raw_slot = [&](int q, int u) { return a.bucket_raw[(size_t)s_sc[q] * NL_CELL_CAP + (u - s_off[q])]; };
   if (staged) {
-    for (int t0 = threadIdx.x; t0 < total; t0 += 2 * NLB_THREADS) {
-      Staged<R> m[2];
+    // (1) the monomer ids of the binned members
+#pragma unroll 4
+    for (int u = threadIdx.x; u < total; u += NLB_THREADS) s_mono[u] = a.mono[raw_slot(find_cell(s_off, 0, ncell, u), u)];
+    __syncthreads();
+    // (2) each member's rank by id within its cell gives its place in the stage (held in
+    // registers until every id has been read: cell q and place packed, and the old slot)
+    int pl[STAGE_PER_THREAD], sl[STAGE_PER_THREAD];
 #pragma unroll
-      for (int u = 0; u < 2; ++u) {
-        const int t = t0 + u * NLB_THREADS;
-        if (t < total) m[u] = member(t);
-      }
-#pragma unroll
-      for (int u = 0; u < 2; ++u) {
-        const int t = t0 + u * NLB_THREADS;
-        if (t < total) s_pos[t] = m[u];
+    for (int i = 0; i < STAGE_PER_THREAD; ++i) {
+      const int u = (int)threadIdx.x + i * NLB_THREADS;
+      pl[i] = -1;
+      sl[i] = 0;
+      if (u < total) {
+        const int q = find_cell(s_off, 0, ncell, u);
+        const int b = s_off[q], e = s_off[q + 1], m = s_mono[u];
+        int r = 0;
+        for (int w = b; w < e; ++w) r += s_mono[w] < m;
+        pl[i] = ((b + r) << 10) | q;
+        sl[i] = raw_slot(q, u);
       }
     }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < STAGE_PER_THREAD; ++i)
+      if (pl[i] >= 0) s_pos[pl[i] >> 10] = make(pl[i] & 1023, sl[i]);
+  }
+  // home cells (frame z index 1, rows 1 .. nhy, x 1 .. nh) in sorted order: their counts
+  const int nhc = tg.nh * tg.nhy;
+  for (int c = threadIdx.x; c < nhc; c += NLB_THREADS) {
+    const int ly = c / tg.nh, lx = c - ly * tg.nh;
+    const int t = (WY + ly + 1) * W + lx + 1;
+    s_home[c + 1] = s_off[t + 1] - s_off[t];
   }
   __syncthreads();
-
-  // home members: rows yy = 1 .. nhy of z index 1, cells i = 1 .. nh of each
-  int nhome = 0;
-  for (int yy = 1; yy <= nhy; ++yy) {
-    const int c = (WY + yy) * W + 1;
-    nhome += s_off[c + nh] - s_off[c];
+  if (threadIdx.x < 64) wave_prefix(s_home, nhc);
+  __syncthreads();
+  const int tile = d.tile_off + lt;
+  const int first = a.tstart[tile];
+  for (int c = threadIdx.x; c < nhc; c += NLB_THREADS) {
+    const int ly = c / tg.nh, lx = c - ly * tg.nh;
+    const int t = (WY + ly + 1) * W + lx + 1;
+    a.cellsc[s_sc[t]] = make_int2(first + s_home[c], s_home[c + 1] - s_home[c]);
   }
-  // the bound carries a 1e-4 relative margin for the rounding of frame coordinates; rows and
-  // cells are skipped only beyond r_list + 1e-3
-  const R rl2 = (R)(d.rlist2 * 1.0002);
+  const int nhome = s_home[nhc];
+  const float hlr = (float)hl;
+  const float rl2 = (float)(d.rlist2 * 1.0002);
   const double rsk = sqrt(d.rlist2) + 1e-3;
-  const R rskip2 = (R)(rsk * rsk);
+  const float rskip2 = (float)(rsk * rsk);
+  const int NP = a.NP;
   for (int h = threadIdx.x; h < nhome; h += NLB_THREADS) {
-    int yy = 1, q = h;
-    for (;; ++yy) {
-      const int c = (WY + yy) * W + 1;
-      const int n = s_off[c + nh] - s_off[c];
-      if (q < n || yy == nhy) break;
-      q -= n;
+    const int c = find_cell(s_home, 0, nhc, h);
+    const int ly = c / tg.nh, lx = c - ly * tg.nh;
+    const int t = (WY + ly + 1) * W + lx + 1;
+    const int r = h - s_home[c];
+    const int si = s_off[t] + r;
+    const int g = first + h;
+    Staged<float> me;
+    if (staged) me = s_pos[si];
+    else me = make(t, member_slot(a, s_sc[t], s_off[t + 1] - s_off[t], r));
+    const int old = me.tag;
+    // the new slot takes the monomer's state
+    const int cx = wrapc(tg.x0 + lx, nc), cy = wrapc(tg.y0 + ly, nc), cz = tg.cz;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      a.xn[(size_t)q * NP + g] = a.x[(size_t)q * NP + old];
+      a.vn[(size_t)q * NP + g] = a.v[(size_t)q * NP + old];
     }
-    const int c1 = (WY + yy) * W + 1;
-    const int t = s_off[c1] + q;
-    int lo = c1, hi = c1 + nh;
-    while (hi - lo > 1) { const int mid = (lo + hi) >> 1; if (s_off[mid] <= t) lo = mid; else hi = mid; }
-    const int ih = lo - (WY + yy) * W;
+    if (a.perm_f) {
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        a.fcn[(size_t)q * NP + g] = a.fc[(size_t)q * NP + old];
+        a.fln[(size_t)q * NP + g] = a.fl[(size_t)q * NP + old];
+      }
+    }
+    a.mono_n[g] = a.mono[old];
+    a.inv[old] = g;
+    ((typename Rel<R>::T*)a.rel_next)[g] =
+        Rel<R>::make(a.x[old] - cx * hl, a.x[NP + old] - cy * hl, a.x[2 * NP + old] - cz * hl, pack_cell(cx, cy, cz), hl);
+    int n;
     if (staged)
-      nl_list_one(a, k, s_pos[t], t, ih, yy, W, WY, hl, rl2, rskip2, s_off,
-                  [&](int u, int) { return s_pos[u]; });
+      n = nl_list_one(a, g, me, si, lx + 1, ly + 1, W, WY, hlr, rl2, rskip2, s_off, [&](int u) { return s_pos[u]; });
     else
-      nl_list_one(a, k, member(t), t, ih, yy, W, WY, hl, rl2, rskip2, s_off,
-                  [&](int u, int umax) { return member(min(u, umax)); });
+      n = nl_list_one(a, g, me, si, lx + 1, ly + 1, W, WY, hlr, rl2, rskip2, s_off, [&](int u) {
+        const int q = find_cell(s_off, 0, ncell, u);
+        return make(q, member_slot(a, s_sc[q], s_off[q + 1] - s_off[q], u - s_off[q]));
+      });
+    if (n > NL_CAP) { atomicOr(&a.err[k], ERR_NLIST_OVERFLOW); n = NL_CAP; }
+    if (a.side && (d.test_flags & TF_SIDE_FAULT)) {  // test hook: a failed rebuild beside a sweep
+      atomicOr(&a.err[k], ERR_NLIST_OVERFLOW);
+      n = 0;
+    }
+    a.nlen[g] = n;
   }
+}
+
+// ---------------------------------------------------------------------------------------
+// rebuild 4: per old slot, carry the chain position over to the new slot, rewrite the chain
+// table entry it owns, and record the new slots of its chain neighbours p-2, p-1, p+1, p+2
+// (-1 past a chain end); clear the counts for the next binning and the displacement bounds
+// ---------------------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_nl_remap(NlArgs a) {
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < a.ncl_total; t += gridDim.x * blockDim.x) a.cnt[t] = 0;
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < a.ntile_total; t += gridDim.x * blockDim.x) a.tcnt[t] = 0;
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < a.nm * 2 * DISP_SLOTS; t += gridDim.x * blockDim.x)
+    a.disp[(size_t)t * DISP_STRIDE] = 0u;
+  if (blockIdx.x == 0)
+    for (int m = threadIdx.x; m < a.nm; m += blockDim.x) a.dacc[m] = 0.0f;
+  const int lb = xcd_remap(blockIdx.x, gridDim.x);
+  const int k = __builtin_amdgcn_readfirstlane(a.pblk_melt[lb]);
+  const MeltDesc& d = a.md[k];
+  const int li = a.pblk_base[lb] + (int)threadIdx.x;
+  if (li >= d.Nm) return;
+  const int o = d.off + li;
+  // (after a rebuild that overflowed a cell, entries may be stale until the run is rolled
+  // back: indices are kept inside the melt)
+  const int g = min(max(a.inv[o], d.off), d.off + d.Nm - 1);
+  const int lc = min(max(a.loc[o], 0), d.Nm - 1);
+  const int N = d.N;
+  const int c = lc / N, p = lc - c * N;
+  const int* row = a.chain + d.off + c * N;
+  int nb[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int pp = p + (q < 2 ? q - 2 : q - 1);
+    nb[q] = (pp >= 0 && pp < N) ? a.inv[min(max(row[pp], d.off), d.off + d.Nm - 1)] : -1;
+  }
+  a.loc_n[g] = lc;
+  a.chain_n[d.off + lc] = g;
+  a.nb4_n[g] = make_int4(nb[0], nb[1], nb[2], nb[3]);
 }
 
 template <typename R> struct W3 { R x, y, z; };
@@ -347,280 +544,406 @@ __device__ __forceinline__ double fsqrt(double x) { return sqrt(x); }
 // the step: forces from the lists + chain, Langevin velocity Verlet
 // ---------------------------------------------------------------------------------------
 // NH > 0: the exponent n = 2 NH is fixed at compile time (the soft and the standard
-// potential); NH = 0 reads it from the melt.  At most 128 registers, so that four
-// wavefronts fit per SIMD: a 200k-monomer melt needs a little over three per SIMD, and a
-// second round of workgroups would double the kernel's duration.
+// potential); NH = 0 reads it from the melt.
 template <typename R, int MODE, int NH>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_nl_step(NlArgs a) {
+__global__ __launch_bounds__(NLB_THREADS) void k_nl_step(NlArgs a) {
+  using P = typename Rel<R>::T;
+  extern __shared__ __align__(16) unsigned char s_dyn[];
+  P* s_pos = (P*)s_dyn;
+  __shared__ int s_off[NLB_CELLS + 1];
+  __shared__ int s_start[NLB_CELLS];
   const int lb = xcd_remap(blockIdx.x, gridDim.x);
-  const int k = __builtin_amdgcn_readfirstlane(a.pblk_melt[lb]);
+  const int k = __builtin_amdgcn_readfirstlane(a.rblk_melt[lb]);
+  const int lt = a.rblk_base[lb];
   const MeltDesc& d = a.md[k];
-  const int li = a.pblk_base[lb] + (int)threadIdx.x;
-  // displacement of each of the 27 neighbouring reference cells (list entries carry its code)
-  __shared__ Rel4<R> s_cell[27];
-  if (threadIdx.x < 27) {
-    const int code = (int)threadIdx.x;
-    const R hl = (R)d.hl;
-    s_cell[code].x = (R)(code % 3 - 1) * hl;
-    s_cell[code].y = (R)((code / 3) % 3 - 1) * hl;
-    s_cell[code].z = (R)(code / 9 - 1) * hl;
-    s_cell[code].w = (R)0;
-  }
-  __syncthreads();
-  if (li >= d.Nm) return;
+  const TileGeo tg = tile_geo(d, lt);
+  const int W = tg.nh + 2, WY = tg.nhy + 2, ncell = 3 * WY * W;
   const int NP = a.NP;
-  const int g = d.off + li;
-  const double L = d.L, invL = 1.0 / d.L;
-  const Rel4<R>* __restrict__ rel = (const Rel4<R>*)a.rel_cur;
-  const bool forces_on = !(d.test_flags & TF_NOFORCE);
-  const bool pairs_on = forces_on && !(d.test_flags & TF_PHANTOM);
-  uint32_t errbits = 0;
+  const double L = d.L, invL = d.invL, hl = d.hl;
+  const P* __restrict__ rel = (const P*)a.rel_cur;
+  // length of one unit of the relative coordinates (fixed point: cell edge / 2^24)
+  const R u = (R)Rel<R>::unit(hl);
 
-  // independent loads first: the wavefront's memory requests overlap one another and the
-  // noise arithmetic below
-  const int lcp = a.loc[g];
-  const int n = pairs_on ? a.nlen[g] : 0;
-  const Rel4<R> ri = rel[g];
-  const double xg = a.x[g], yg = a.x[NP + g], zg = a.x[2 * NP + g];
-  double vx = a.v[g], vy = a.v[NP + g], vz = a.v[2 * NP + g];
-  const uint64_t mono = (MODE & F_CLOSE) ? (uint64_t)a.mono[g] : 0ull;
+  // list validity: the first tile of each melt adds the previous step's largest displacement
+  // to the bound accumulated since the rebuild
+  const int sp = (int)(a.sp & 1u);
+  uint32_t* const disp_now = a.disp + ((size_t)k * 2 + sp) * DISP_SLOTS * DISP_STRIDE;
+  if (lt == 0 && threadIdx.x < 64) {  // one wavefront: the previous step's slots (then cleared)
+    uint32_t* const prev = a.disp + ((size_t)k * 2 + (1 - sp)) * DISP_SLOTS * DISP_STRIDE;
+    float m = threadIdx.x < DISP_SLOTS ? __uint_as_float(prev[threadIdx.x * DISP_STRIDE]) : 0.0f;
+    if (threadIdx.x < DISP_SLOTS) prev[threadIdx.x * DISP_STRIDE] = 0u;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
+    if (threadIdx.x == 0) {
+      const float acc = a.dacc[k] + m;
+      a.dacc[k] = acc;
+      if (acc > (float)d.half_skin) atomicOr(&a.err[k], ERR_NLIST_STALE);
+    }
+  }
+
+  // The stage (the members of the 3 x (nh + 2) x (nhy + 2) cells around the tile) keeps its
+  // slots from one rebuild to the next.  The first step after a rebuild finds them from the cell
+  // table and records them with the tile's home range; later steps read that record.  (When the
+  // frame wraps onto itself in a small box, a slot does not fix its frame cell: such melts always
+  // take the cell table.)
+  const int tile = d.tile_off + lt;
+  const int nc = d.ncl;
+  const bool frame_ok = W <= nc && WY <= nc && !(d.test_flags & TF_NL_GLOBAL);
+  int* const slist = a.stage_list + (size_t)tile * a.stage_stride;
+  int4 meta = make_int4(0, 0, 0, 0);
+  bool fast = false;
+  if (!a.stage_write && frame_ok) {
+    meta = a.stage_meta[tile];
+    fast = meta.z <= a.stage_cap;
+  }
+  // the tile's home monomers occupy slots h0 .. h0 + nhome - 1
+  int h0, nhome;
+  if (fast) {
+    h0 = meta.x;
+    nhome = meta.y;
+  } else {
+    h0 = a.cellsc[sorted_cell(d, tg.x0, tg.y0, tg.cz, nullptr)].x;
+    const int2 lastc = a.cellsc[sorted_cell(d, tg.x0 + tg.nh - 1, tg.y0 + tg.nhy - 1, tg.cz, nullptr)];
+    nhome = lastc.x + lastc.y - h0;
+  }
+  const bool pairs_on = !(d.test_flags & (TF_NOFORCE | TF_PHANTOM));
+  // a home monomer's own data (independent loads; the first one's are issued before the stage
+  // is built, so that they arrive meanwhile)
+  struct Home {
+    P ri;
+    int4 nb;
+    int n;
+    double x, y, z, vx, vy, vz;
+    double z0, z1, z2;  // Langevin noise of this closing kick
+    uint4 w0;
+  };
+  // the noise depends only on the monomer id and the step
+  const uint64_t noise_idx = (MODE & F_CLOSE) ? a.step_base[k] + (uint64_t)a.s_off : 0ull;
+  auto noise = [&](Home& o, int mono) {
+    o.z0 = o.z1 = o.z2 = 0.0;
+    if (MODE & F_CLOSE) {
+      const U64x4 w = rng_draw(d, (uint64_t)mono, noise_idx, ST_LANGEVIN);
+      double z3;
+      gauss2_r<R>(w.w[0], w.w[1], o.z0, o.z1);
+      gauss2_r<R>(w.w[2], w.w[3], o.z2, z3);
+    }
+  };
   const uint4* __restrict__ words = (const uint4*)a.nlist;
-  // first chunk of the list: CH0 entries (CH0 / 4 16-byte words) and their gathers, all
-  // requested before the noise arithmetic; later chunks have CH entries.  FP64 coordinates
-  // take twice the registers, so their chunks are half as long.
-  constexpr int CH0 = sizeof(R) == 4 ? 8 : 4, CW0 = CH0 / 4;
-  constexpr int CH = sizeof(R) == 4 ? 8 : 4, CW = CH / 4;
-  uint4 wd0[CW0];
-#pragma unroll
-  for (int q = 0; q < CW0; ++q) wd0[q] = words[nl_word(g, q)];
-
-  // chain neighbours p-2, p-1, p+1, p+2 (FP64 minimum image, then the force precision)
-  const int N = d.N;
-  const int c = (int)((double)lcp * d.invN), p0 = lcp - c * N;
-  const int cch = (p0 < 0) ? c - 1 : (p0 >= N ? c + 1 : c);  // guard the reciprocal's rounding
-  const int p = lcp - cch * N;
-  bool has[5];
-  int pj[5];
-#pragma unroll
-  for (int q = 0; q < 5; ++q) {  // unconditional loads of clamped positions: no branches between them
-    const int pp = p + q - 2;
-    has[q] = (q == 2) || (forces_on && pp >= 0 && pp < N);
-    const int j = a.chain[d.off + cch * N + min(max(pp, 0), N - 1)];
-    pj[q] = (q != 2 && has[q]) ? j : g;
-  }
-  double bx[5], by[5], bz[5];
-#pragma unroll
-  for (int q = 0; q < 5; ++q) { bx[q] = a.x[pj[q]]; by[q] = a.x[NP + pj[q]]; bz[q] = a.x[2 * NP + pj[q]]; }
-
-  uint32_t e0[CH0];
-  Rel4<R> rj0[CH0];
-#pragma unroll
-  for (int q = 0; q < CW0; ++q) {
-    e0[4 * q] = wd0[q].x; e0[4 * q + 1] = wd0[q].y; e0[4 * q + 2] = wd0[q].z; e0[4 * q + 3] = wd0[q].w;
-  }
-#pragma unroll
-  for (int u = 0; u < CH0; ++u) rj0[u] = rel[(u < n) ? (e0[u] >> 5) : g];
-
-  // Langevin noise of this closing kick (depends only on the monomer id and the step),
-  // computed while the gathers above are in flight: the empty asm pins the arithmetic here
-  // and the scheduling barriers keep the loads issued before it
-  double z0 = 0.0, z1 = 0.0, z2 = 0.0;
-  if (MODE & F_CLOSE) {
-    const uint64_t idx = a.step_base[k] + (uint64_t)a.s_off;
-    __builtin_amdgcn_sched_barrier(0);
-    const U64x4 w = rng_draw(d, mono, idx, ST_LANGEVIN);
-    double z3;
-    gauss2_r<R>(w.w[0], w.w[1], z0, z1);
-    gauss2_r<R>(w.w[2], w.w[3], z2, z3);
-    asm volatile("" : "+v"(z0), "+v"(z1), "+v"(z2));  // materialise the noise here
-    __builtin_amdgcn_sched_barrier(0);
-  }
-
-  W3<R> F = {(R)0, (R)0, (R)0};
-  const R pa = (R)d.pa, pb = (R)d.pb, rc2 = (R)d.rc2, n_half = (R)(0.5 * d.n_exp);
-  const int nh = NH > 0 ? NH : d.n_half_int;
-  auto pair_add = [&](R dx, R dy, R dz) {  // (dx, dy, dz) = x_j - x_i
-    const R r2 = dx * dx + dy * dy + dz * dz;
-    if (r2 < rc2) {
-      const R s2 = frcp(r2);
-      const R s6 = s2 * s2 * s2;
-      const R sn = pow_half<R>(s2, nh, n_half);
-      const R coef = (pa * sn - pb * s6) * s2;
-      F.x -= coef * dx; F.y -= coef * dy; F.z -= coef * dz;
-    }
+  auto load_home = [&](int g) {
+    Home o;
+    o.ri = rel[g];
+    o.n = pairs_on ? a.nlen[g] : 0;
+    o.nb = a.nb4[g];
+    o.x = a.x[g]; o.y = a.x[NP + g]; o.z = a.x[2 * NP + g];
+    o.vx = a.v[g]; o.vy = a.v[NP + g]; o.vz = a.v[2 * NP + g];
+    o.w0 = words[nl_word(g, 0)];
+    noise(o, (MODE & F_CLOSE) ? a.mono[g] : 0);
+    return o;
   };
-  // list entries: the same force without a branch (lanes of a wavefront rarely agree on the
-  // cutoff test); r2 is clamped away from 0 for entries outside it, whose force is masked
-  auto pair_add_nb = [&](R dx, R dy, R dz) {
-    const R r2 = dx * dx + dy * dy + dz * dz;
-    const bool in = r2 < rc2;
-    const R s2 = frcp(in ? r2 : rc2);
-    const R s6 = s2 * s2 * s2;
-    const R sn = pow_half<R>(s2, nh, n_half);
-    const R coef = in ? (pa * sn - pb * s6) * s2 : (R)0;
-    F.x -= coef * dx; F.y -= coef * dy; F.z -= coef * dz;
+  // (the first home's noise is drawn while its stage loads arrive)
+  Home pre;
+  if ((int)threadIdx.x < nhome) pre = load_home(h0 + (int)threadIdx.x);
+
+  int total;
+  bool staged;
+  // staged member t: current position relative to its reference cell, moved into the frame
+  auto member = [&](int t) -> P {
+    const int q = find_cell(s_off, 0, ncell, t);
+    const int row = q / W, i = q - row * W;
+    const int zz = row / WY, yy = row - zz * WY;
+    return rel_shift<R>(rel[s_start[q] + (t - s_off[q])], i - 1, yy - 1, zz - 1, hl);
   };
-  auto entry = [&](uint32_t en, const Rel4<R>& r) {
-    const Rel4<R> o = s_cell[en & 31u];
-    pair_add_nb(r.x + o.x - ri.x, r.y + o.y - ri.y, r.z + o.z - ri.z);
-  };
-
-  // list: the first chunk, then chunks t .. t + CH - 1 whose words are requested before the
-  // previous chunk is evaluated
-  uint4 wd[CW];
-  uint32_t e[CH];
-  Rel4<R> rj[CH];
-  bool more = CH0 < n;
-#pragma unroll
-  for (int q = 0; q < CW; ++q) wd[q] = more ? words[nl_word(g, CW0 + q)] : make_uint4(0, 0, 0, 0);
-#pragma unroll
-  for (int u = 0; u < CH0; ++u)
-    if (u < n) entry(e0[u], rj0[u]);
-  for (int t = CH0; t < n; t += CH) {
-#pragma unroll
-    for (int q = 0; q < CW; ++q) {
-      e[4 * q] = wd[q].x; e[4 * q + 1] = wd[q].y; e[4 * q + 2] = wd[q].z; e[4 * q + 3] = wd[q].w;
+  if (fast) {
+    total = meta.z;
+    staged = true;
+    // the frame cell of a member follows from its reference cell (the frame is no wider than
+    // the box, so the periodic difference is unique)
+    const int fx = tg.x0 - 1, fy = tg.y0 - 1, fz = tg.cz - 1;
+#pragma unroll 4
+    for (int u = threadIdx.x; u < total; u += NLB_THREADS) {
+      const P p = rel[min(max(slist[u], 0), NP - 1)];  // (kept inside the storage whatever the record holds)
+      const int c = Rel<R>::cell(p);
+      int i = (c & 1023) - fx, yy = ((c >> 10) & 1023) - fy, zz = (c >> 20) - fz;
+      i += i < 0 ? nc : 0;
+      i -= i >= nc ? nc : 0;
+      yy += yy < 0 ? nc : 0;
+      yy -= yy >= nc ? nc : 0;
+      zz += zz < 0 ? nc : 0;
+      zz -= zz >= nc ? nc : 0;
+      s_pos[u] = rel_shift<R>(p, i - 1, yy - 1, zz - 1, hl);
     }
-#pragma unroll
-    for (int u = 0; u < CH; ++u) rj[u] = rel[(t + u < n) ? (e[u] >> 5) : g];
-    more = t + CH < n;
-#pragma unroll
-    for (int q = 0; q < CW; ++q) wd[q] = more ? words[nl_word(g, ((t + CH) >> 2) + q)] : make_uint4(0, 0, 0, 0);
-#pragma unroll
-    for (int u = 0; u < CH; ++u)
-      if (t + u < n) entry(e[u], rj[u]);
-  }
-
-  W3<R> P[5];
-#pragma unroll
-  for (int q = 0; q < 5; ++q) {
-    P[q].x = P[q].y = P[q].z = (R)0;
-    if (q != 2 && has[q]) {
-      double dx = bx[q] - xg, dy = by[q] - yg, dz = bz[q] - zg;
-      dx -= L * rint(dx * invL); dy -= L * rint(dy * invL); dz -= L * rint(dz * invL);
-      P[q].x = (R)dx; P[q].y = (R)dy; P[q].z = (R)dz;
+  } else {
+    for (int t = threadIdx.x; t < ncell; t += NLB_THREADS) {
+      const StagedCell s = staged_cell(d, tg, W, WY, t);
+      const int2 cs = a.cellsc[sorted_cell(d, s.ax, s.ay, s.az, nullptr)];
+      s_start[t] = cs.x;
+      s_off[t + 1] = cs.y;
     }
-  }
-
-  if (forces_on) {
-    const R kf = (R)d.kfene, R0sq = (R)d.R0sq, amin = (R)d.amin, iR0sq = (R)(1.0 / d.R0sq);
-#pragma unroll
-    for (int q = 1; q <= 3; q += 2) {
-      if (!has[q]) continue;
-      const W3<R> b = P[q];
-      const R r2 = b.x * b.x + b.y * b.y + b.z * b.z;
-      const bool broken = (amin > (R)0) ? !(r2 < (R)4 * R0sq) : !(r2 < R0sq);
-      if (broken) errbits |= ERR_FENE;
-      const R am = (R)1 - r2 * iR0sq;
-      const R cb = kf * frcp((amin > (R)0 && am < amin) ? amin : am);  // F_i = k (x_j - x_i) / a
-      F.x += cb * b.x; F.y += cb * b.y; F.z += cb * b.z;
-      if (d.test_flags & TF_PHANTOM) pair_add(b.x, b.y, b.z);
-    }
-    const R kap = (R)d.kappa;
-    if (d.kappa != 0.0) {
-#pragma unroll
-      for (int dv = -1; dv <= 1; ++dv) {
-        const int iv = 2 + dv;
-        if (!(has[iv - 1] && has[iv] && has[iv + 1])) continue;
-        const W3<R> b1 = {P[iv].x - P[iv - 1].x, P[iv].y - P[iv - 1].y, P[iv].z - P[iv - 1].z};
-        const W3<R> b2 = {P[iv + 1].x - P[iv].x, P[iv + 1].y - P[iv].y, P[iv + 1].z - P[iv].z};
-        const R l1s = b1.x * b1.x + b1.y * b1.y + b1.z * b1.z;
-        const R l2s = b2.x * b2.x + b2.y * b2.y + b2.z * b2.z;
-        const R i1 = frcp(l1s), i2 = frcp(l2s);
-        const R inv12 = fsqrt(i1 * i2);
-        const R cs = (b1.x * b2.x + b1.y * b2.y + b1.z * b2.z) * inv12;
-        const R c1 = cs * i1, c2 = cs * i2;
-        const W3<R> g1 = {b2.x * inv12 - c1 * b1.x, b2.y * inv12 - c1 * b1.y, b2.z * inv12 - c1 * b1.z};
-        const W3<R> g2 = {b1.x * inv12 - c2 * b2.x, b1.y * inv12 - c2 * b2.y, b1.z * inv12 - c2 * b2.z};
-        if (dv == 1) { F.x -= kap * g1.x; F.y -= kap * g1.y; F.z -= kap * g1.z; }  // first bead
-        else if (dv == 0) { F.x += kap * (g1.x - g2.x); F.y += kap * (g1.y - g2.y); F.z += kap * (g1.z - g2.z); }
-        else { F.x += kap * g2.x; F.y += kap * g2.y; F.z += kap * g2.z; }  // last bead
+    __syncthreads();
+    if (threadIdx.x < 64) wave_prefix(s_off, ncell);
+    __syncthreads();
+    total = s_off[ncell];
+    staged = total <= a.stage_cap && !(d.test_flags & TF_NL_GLOBAL);
+    const bool record = a.stage_write && staged && frame_ok;
+    if (staged) {
+#pragma unroll 4
+      for (int u = threadIdx.x; u < total; u += NLB_THREADS) {
+        const int q = find_cell(s_off, 0, ncell, u);
+        const int row = q / W, i = q - row * W;
+        const int zz = row / WY, yy = row - zz * WY;
+        const int slot = s_start[q] + (u - s_off[q]);
+        if (record) slist[u] = slot;
+        s_pos[u] = rel_shift<R>(rel[slot], i - 1, yy - 1, zz - 1, hl);
       }
     }
+    if (a.stage_write && threadIdx.x == 0) a.stage_meta[tile] = make_int4(h0, nhome, total, 0);
   }
+  __syncthreads();
 
-  const double Fx = (double)F.x, Fy = (double)F.y, Fz = (double)F.z;
-  if (!(isfinite(Fx) && isfinite(Fy) && isfinite(Fz))) errbits |= ERR_NONFINITE;
-  double fx, fy, fz;
-  const double dt = d.dt;
-  if (MODE & F_CLOSE) {
-    const double amp = d.lang_amp;  // sqrt(2 gamma T / dt)
-    fx = -d.gamma * vx + amp * z0;
-    fy = -d.gamma * vy + amp * z1;
-    fz = -d.gamma * vz + amp * z2;
-    vx = vx + 0.5 * dt * (Fx + fx);
-    vy = vy + 0.5 * dt * (Fy + fy);
-    vz = vz + 0.5 * dt * (Fz + fz);
-  } else {
-    fx = a.fl[g]; fy = a.fl[NP + g]; fz = a.fl[2 * NP + g];
-  }
-  if (MODE & F_STORE) {
-    a.fc[g] = Fx; a.fc[NP + g] = Fy; a.fc[2 * NP + g] = Fz;
-    a.fl[g] = fx; a.fl[NP + g] = fy; a.fl[2 * NP + g] = fz;
-    a.v[g] = vx; a.v[NP + g] = vy; a.v[2 * NP + g] = vz;
-    if (!(isfinite(vx) && isfinite(vy) && isfinite(vz))) errbits |= ERR_NONFINITE;
+  const bool forces_on = !(d.test_flags & TF_NOFORCE);
+  uint32_t errbits = 0;
+  float dmax = 0.0f;
+  int nfloor = 0;
+  const R pa = (R)d.pa, pb = (R)d.pb, n_half = (R)(0.5 * d.n_exp);
+  // the cutoff in units of the relative coordinates, and 1 / unit^2
+  const R rc2u = sizeof(R) == 4 ? (R)d.rc2_fx : (R)d.rc2, iu2 = sizeof(R) == 4 ? (R)d.iu2_fx : (R)1;
+  const int nh = NH > 0 ? NH : d.n_half_int;
+
+  for (int h = threadIdx.x; h < nhome; h += NLB_THREADS) {
+    const int g = h0 + h;
+    const Home hm = h == (int)threadIdx.x ? pre : load_home(g);
+    const P ri = hm.ri;
+    const int n = hm.n;
+    const int4 nb = hm.nb;
+    const double xg = hm.x, yg = hm.y, zg = hm.z;
+    double vx = hm.vx, vy = hm.vy, vz = hm.vz;
+    uint4 wd = hm.w0;
+    const int pc = Rel<R>::cell(ri);
+    const int ix = pc & 1023, iy = (pc >> 10) & 1023, iz = pc >> 20;
+    // chain neighbours p-2, p-1, p+1, p+2 (slots, or -1)
+    int nbq[4] = {nb.x, nb.y, nb.z, nb.w};
+    P rb[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      if (nbq[q] >= NP) nbq[q] = -1;  // (only a rebuild that overflowed, whose run is redone, leaves such an entry)
+      rb[q] = rel[(forces_on && nbq[q] >= 0) ? nbq[q] : g];
+    }
+
+    const double z0 = hm.z0, z1 = hm.z1, z2 = hm.z2;
+
+    W3<R> F = {(R)0, (R)0, (R)0};
+    // pair force from a displacement in units (x_j - x_i); F accumulates in units too and is
+    // scaled by the unit at the end
+    auto pair_add = [&](R dx, R dy, R dz) {
+      const R r2 = dx * dx + dy * dy + dz * dz;
+      if (r2 < rc2u) {
+        const R s2 = frcp(r2) * iu2;
+        const R s6 = s2 * s2 * s2;
+        const R sn = pow_half<R>(s2, nh, n_half);
+        const R coef = (pa * sn - pb * s6) * s2;
+        F.x -= coef * dx; F.y -= coef * dy; F.z -= coef * dz;
+      }
+    };
+    // list entries: the same force without a branch; r2 is clamped away from 0 for entries
+    // outside the cutoff, whose force is masked
+    auto pair_add_nb = [&](R dx, R dy, R dz) {
+      const R r2 = dx * dx + dy * dy + dz * dz;
+      const bool in = r2 < rc2u;
+      const R s2 = frcp(in ? r2 : rc2u) * iu2;
+      const R s6 = s2 * s2 * s2;
+      const R sn = pow_half<R>(s2, nh, n_half);
+      const R coef = in ? (pa * sn - pb * s6) * s2 : (R)0;
+      F.x -= coef * dx; F.y -= coef * dy; F.z -= coef * dz;
+    };
+    // own position in the tile frame (the reference cell is a home cell of this tile)
+    const P me = rel_shift<R>(ri, ix - tg.x0, iy - tg.y0, 0, hl);
+    for (int t = 0; t < n; t += 8) {
+      const uint4 cw = wd;
+      if (t + 8 < n) wd = words[nl_word(g, (t >> 3) + 1)];
+      const uint32_t e2[4] = {cw.x, cw.y, cw.z, cw.w};
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        if (t + q < n) {
+          // (an index past the stage can only come from a list left by a failed rebuild,
+          // whose run is redone: it is kept inside the stage)
+          const int e = min((int)((e2[q >> 1] >> ((q & 1) * 16)) & 0xffffu), total - 1);
+          const P p = staged ? s_pos[e] : member(e);
+          R dx, dy, dz;
+          Rel<R>::diff(p, me, dx, dy, dz);
+          pair_add_nb(dx, dy, dz);
+        }
+      }
+    }
+    F.x *= u; F.y *= u; F.z *= u;  // coef * (x_j - x_i): units -> sigma
+
+    // bonded partners: displacement from the relative positions and the reference cells
+    W3<R> Pd[5];
+    bool has[5];
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+      Pd[q].x = Pd[q].y = Pd[q].z = (R)0;
+      has[q] = q == 2;
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int sl = q < 2 ? q : q + 1;
+      if (!(forces_on && nbq[q] >= 0)) continue;
+      has[sl] = true;
+      const int pj = Rel<R>::cell(rb[q]);
+      int dx = (pj & 1023) - ix, dy = ((pj >> 10) & 1023) - iy, dz = (pj >> 20) - iz;
+      // nearest periodic image of the cell difference
+      dx -= nc * (dx > nc / 2) - nc * (dx < -(nc - 1) / 2);
+      dy -= nc * (dy > nc / 2) - nc * (dy < -(nc - 1) / 2);
+      dz -= nc * (dz > nc / 2) - nc * (dz < -(nc - 1) / 2);
+      R bx, by, bz;
+      Rel<R>::image_diff(rb[q], ri, dx, dy, dz, nc, hl, bx, by, bz);
+      Pd[sl].x = bx * u;
+      Pd[sl].y = by * u;
+      Pd[sl].z = bz * u;
+    }
+
+    if (forces_on) {
+      const R kf = (R)d.kfene, R0sq = (R)d.R0sq, amin = (R)d.amin, iR0sq = (R)d.iR0sq;
+#pragma unroll
+      for (int q = 1; q <= 3; q += 2) {
+        if (!has[q]) continue;
+        const W3<R> b = Pd[q];
+        const R r2 = b.x * b.x + b.y * b.y + b.z * b.z;
+        const bool broken = (amin > (R)0) ? !(r2 < (R)4 * R0sq) : !(r2 < R0sq);
+        if (broken) errbits |= ERR_FENE;
+        const R am = (R)1 - r2 * iR0sq;
+        const bool floored = amin > (R)0 && am < amin;
+        if ((MODE & F_CLOSE) && q == 3 && floored) ++nfloor;  // each bond once per step, by its first bead
+        const R cb = kf * frcp(floored ? amin : am);  // F_i = k (x_j - x_i) / a
+        F.x += cb * b.x; F.y += cb * b.y; F.z += cb * b.z;
+        if (d.test_flags & TF_PHANTOM) {  // the bonded pair's MLJ^n, from the displacement in units
+          const R ui = (R)1 / u;
+          const W3<R> Fs = F;
+          F.x = F.y = F.z = (R)0;
+          pair_add(b.x * ui, b.y * ui, b.z * ui);
+          F.x = Fs.x + F.x * u; F.y = Fs.y + F.y * u; F.z = Fs.z + F.z * u;
+        }
+      }
+      const R kap = (R)d.kappa;
+      if (d.kappa != 0.0) {
+#pragma unroll
+        for (int dv = -1; dv <= 1; ++dv) {
+          const int iv = 2 + dv;
+          if (!(has[iv - 1] && has[iv] && has[iv + 1])) continue;
+          const W3<R> b1 = {Pd[iv].x - Pd[iv - 1].x, Pd[iv].y - Pd[iv - 1].y, Pd[iv].z - Pd[iv - 1].z};
+          const W3<R> b2 = {Pd[iv + 1].x - Pd[iv].x, Pd[iv + 1].y - Pd[iv].y, Pd[iv + 1].z - Pd[iv].z};
+          const R l1s = b1.x * b1.x + b1.y * b1.y + b1.z * b1.z;
+          const R l2s = b2.x * b2.x + b2.y * b2.y + b2.z * b2.z;
+          const R i1 = frcp(l1s), i2 = frcp(l2s);
+          const R inv12 = fsqrt(i1 * i2);
+          const R cs = (b1.x * b2.x + b1.y * b2.y + b1.z * b2.z) * inv12;
+          const R c1 = cs * i1, c2 = cs * i2;
+          const W3<R> g1 = {b2.x * inv12 - c1 * b1.x, b2.y * inv12 - c1 * b1.y, b2.z * inv12 - c1 * b1.z};
+          const W3<R> g2 = {b1.x * inv12 - c2 * b2.x, b1.y * inv12 - c2 * b2.y, b1.z * inv12 - c2 * b2.z};
+          if (dv == 1) { F.x -= kap * g1.x; F.y -= kap * g1.y; F.z -= kap * g1.z; }  // first bead
+          else if (dv == 0) { F.x += kap * (g1.x - g2.x); F.y += kap * (g1.y - g2.y); F.z += kap * (g1.z - g2.z); }
+          else { F.x += kap * g2.x; F.y += kap * g2.y; F.z += kap * g2.z; }  // last bead
+        }
+      }
+    }
+
+    const double Fx = (double)F.x, Fy = (double)F.y, Fz = (double)F.z;
+    if (!(isfinite(Fx) && isfinite(Fy) && isfinite(Fz))) errbits |= ERR_NONFINITE;
+    double fx, fy, fz;
+    const double dt = d.dt;
+    if (MODE & F_CLOSE) {
+      const double amp = d.lang_amp;  // sqrt(2 gamma T / dt)
+      fx = -d.gamma * vx + amp * z0;
+      fy = -d.gamma * vy + amp * z1;
+      fz = -d.gamma * vz + amp * z2;
+      vx = vx + 0.5 * dt * (Fx + fx);
+      vy = vy + 0.5 * dt * (Fy + fy);
+      vz = vz + 0.5 * dt * (Fz + fz);
+    } else {
+      fx = a.fl[g]; fy = a.fl[NP + g]; fz = a.fl[2 * NP + g];
+    }
+    if (MODE & F_STORE) {
+      a.fc[g] = Fx; a.fc[NP + g] = Fy; a.fc[2 * NP + g] = Fz;
+      a.fl[g] = fx; a.fl[NP + g] = fy; a.fl[2 * NP + g] = fz;
+      a.v[g] = vx; a.v[NP + g] = vy; a.v[2 * NP + g] = vz;
+      if (!(isfinite(vx) && isfinite(vy) && isfinite(vz))) errbits |= ERR_NONFINITE;
+    }
+    if (MODE & F_OPEN) {
+      const double hx = vx + 0.5 * dt * (Fx + fx);
+      const double hy = vy + 0.5 * dt * (Fy + fy);
+      const double hz = vz + 0.5 * dt * (Fz + fz);
+      const double nxp = wrap_near(xg + dt * hx, L);
+      const double nyp = wrap_near(yg + dt * hy, L);
+      const double nzp = wrap_near(zg + dt * hz, L);
+      if (!(isfinite(nxp) && isfinite(nyp) && isfinite(nzp) && isfinite(hx) && isfinite(hy) && isfinite(hz)))
+        errbits |= ERR_NONFINITE;
+      a.v[g] = hx; a.v[NP + g] = hy; a.v[2 * NP + g] = hz;
+      a.xn[g] = nxp; a.xn[NP + g] = nyp; a.xn[2 * NP + g] = nzp;
+      // (FP32, rounded up by a relative 1e-6: a bound, not a value)
+      dmax = fmaxf(dmax, (float)dt * __builtin_amdgcn_sqrtf((float)(hx * hx + hy * hy + hz * hz)) * 1.000001f);
+      if (MODE & F_BIN) nl_bin_one(a, k, d, g, nxp, nyp, nzp, true);
+      // position relative to the reference cell (periodic image nearest to it)
+      double rx = nxp - ix * hl, ry = nyp - iy * hl, rz = nzp - iz * hl;
+      rx -= L * rint(rx * invL); ry -= L * rint(ry * invL); rz -= L * rint(rz * invL);
+      ((P*)a.rel_next)[g] = Rel<R>::make(rx, ry, rz, pc, hl);
+    }
   }
   if (MODE & F_OPEN) {
-    const double hx = vx + 0.5 * dt * (Fx + fx);
-    const double hy = vy + 0.5 * dt * (Fy + fy);
-    const double hz = vz + 0.5 * dt * (Fz + fz);
-    const double nxp = wrap_box(xg + dt * hx, L);
-    const double nyp = wrap_box(yg + dt * hy, L);
-    const double nzp = wrap_box(zg + dt * hz, L);
-    if (!(isfinite(nxp) && isfinite(nyp) && isfinite(nzp) && isfinite(hx) && isfinite(hy) && isfinite(hz)))
-      errbits |= ERR_NONFINITE;
-    a.v[g] = hx; a.v[NP + g] = hy; a.v[2 * NP + g] = hz;
-    a.xn[g] = nxp; a.xn[NP + g] = nyp; a.xn[2 * NP + g] = nzp;
-    if (MODE & F_BIN) {  // the list rebuild that follows takes the new positions binned here
-      const int cl = nl_cell(d, nxp, nyp, nzp);
-      a.cell_l[g] = cl;
-      nl_bin_wave(a, k, g, cl);
+    // the step's largest displacement: per workgroup, then one atomic into one of the melt's
+    // slots (non-negative floats order as their bit patterns)
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) dmax = fmaxf(dmax, __shfl_xor(dmax, o, 64));
+    __shared__ float s_dmax[NLB_THREADS / 64];
+    if ((threadIdx.x & 63) == 0) s_dmax[threadIdx.x >> 6] = dmax;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      float m = s_dmax[0];
+      for (int w = 1; w < NLB_THREADS / 64; ++w) m = fmaxf(m, s_dmax[w]);
+      if (m > 0.0f) atomicMax(&disp_now[(lt % DISP_SLOTS) * DISP_STRIDE], __float_as_uint(m));
     }
-    // position relative to the reference cell (periodic image nearest to it)
-    const int pc = a.refc[g];
-    double rx = nxp - (pc & 1023) * d.hl, ry = nyp - ((pc >> 10) & 1023) * d.hl, rz = nzp - (pc >> 20) * d.hl;
-    rx -= L * rint(rx * invL); ry -= L * rint(ry * invL); rz -= L * rint(rz * invL);
-    Rel4<R> r;
-    r.x = (R)rx; r.y = (R)ry; r.z = (R)rz; r.w = (R)0;
-    ((Rel4<R>*)a.rel_next)[g] = r;
-    const float4 b = a.relb[g];
-    const float ex = (float)rx - b.x, ey = (float)ry - b.y, ez = (float)rz - b.z;
-    if (ex * ex + ey * ey + ez * ez > (float)d.half_skin2) errbits |= ERR_NLIST_STALE;
+  }
+  if (__ballot(nfloor > 0)) {
+    int c = nfloor;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
+    if ((threadIdx.x & 63) == 0) atomicAdd(&a.fene_floored[k], (unsigned long long)c);
   }
   if (errbits) atomicOr(&a.err[k], errbits);
 }
 
 // ---------------------------------------------------------------------------------------
-size_t nl_stage_bytes(int prec, int cap) {
-  return (size_t)(cap + 4) * (prec ? sizeof(Staged<float>) : sizeof(Staged<double>));
+size_t nl_stage_bytes(int, int cap) { return (size_t)(cap + 4) * sizeof(Staged<float>); }
+size_t rel_bytes(int prec) { return prec ? sizeof(Rel<float>::T) : sizeof(Rel<double>::T); }
+
+void launch_nl_rebuild(int prec, const NlArgs& a, int pblk, int ntile, bool bin, hipStream_t s) {
+  if (bin) hipLaunchKernelGGL(k_nl_bin, dim3(pblk), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(1024), 0, s, a.tcnt, a.ntile_total, a.tstart);
+  if (prec)
+    hipLaunchKernelGGL(k_nl_rebuild<float>, dim3(ntile), dim3(NLB_THREADS), nl_stage_bytes(1, a.stage_cap), s, a);
+  else
+    hipLaunchKernelGGL(k_nl_rebuild<double>, dim3(ntile), dim3(NLB_THREADS), nl_stage_bytes(0, a.stage_cap), s, a);
 }
 
-void launch_nl_rebuild(int prec, const NlArgs& a, int pblk, int cblk, int rblk, bool bin, hipStream_t s) {
-  if (bin) hipLaunchKernelGGL(k_nl_bin, dim3(pblk), dim3(256), 0, s, a);
-  if (prec) {
-    hipLaunchKernelGGL(k_nl_finalize<float>, dim3(pblk), dim3(256), 0, s, a);
-    hipLaunchKernelGGL(k_nl_build<float>, dim3(rblk), dim3(NLB_THREADS), nl_stage_bytes(1, a.stage_cap), s, a);
-  } else {
-    hipLaunchKernelGGL(k_nl_finalize<double>, dim3(pblk), dim3(256), 0, s, a);
-    hipLaunchKernelGGL(k_nl_build<double>, dim3(rblk), dim3(NLB_THREADS), nl_stage_bytes(0, a.stage_cap), s, a);
-  }
+void launch_nl_remap(const NlArgs& a, int pblk, hipStream_t s) {
+  hipLaunchKernelGGL(k_nl_remap, dim3(pblk), dim3(256), 0, s, a);
 }
 
 template <typename R, int M>
-static void launch_step_nh(const NlArgs& a, int pblk, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+static void launch_step_nh(const NlArgs& a, int ntile, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+  const size_t lds = (size_t)(a.stage_cap + 4) * sizeof(typename Rel<R>::T);
   // with events: hipExtLaunchKernelGGL stamps them at the dispatch's own start and end
   auto go = [&](auto kern) {
-    if (ev0) hipExtLaunchKernelGGL(kern, dim3(pblk), dim3(256), 0, s, ev0, ev1, 0, a);
-    else hipLaunchKernelGGL(kern, dim3(pblk), dim3(256), 0, s, a);
+    if (ev0) hipExtLaunchKernelGGL(kern, dim3(ntile), dim3(NLB_THREADS), lds, s, ev0, ev1, 0, a);
+    else hipLaunchKernelGGL(kern, dim3(ntile), dim3(NLB_THREADS), lds, s, a);
   };
   if (a.nh_uniform == 1) go(k_nl_step<R, M, 1>);
   else if (a.nh_uniform == 6) go(k_nl_step<R, M, 6>);
   else go(k_nl_step<R, M, 0>);
 }
 
-void launch_nl_step(int prec, int mode, const NlArgs& a, int pblk, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+void launch_nl_step(int prec, int mode, const NlArgs& a, int ntile, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
 #define KG_CASE(R, M) \
-  case M: launch_step_nh<R, M>(a, pblk, s, ev0, ev1); break;
+  case M: launch_step_nh<R, M>(a, ntile, s, ev0, ev1); break;
   if (prec) {
     switch (mode) {
       KG_CASE(float, F_OPEN)
@@ -642,7 +965,5 @@ void launch_nl_step(int prec, int mode, const NlArgs& a, int pblk, hipStream_t s
   }
 #undef KG_CASE
 }
-
-size_t rel_bytes(int prec) { return prec ? sizeof(Rel4<float>) : sizeof(Rel4<double>); }
 
 }  // namespace kgdb

@@ -194,6 +194,24 @@ def test_stale_lists_roll_back():
     assert np.max(np.abs(d)) < 1e-11
 
 
+def test_list_cell_overflow_rolls_back():
+    # A raw random-walk start (no warm-up) packs 42 monomers into one cell of the K = 5 list
+    # grid, beyond its capacity of 32: that rebuild cannot place every monomer, so the run is
+    # redone from its start on the finer K = 2 grid.  Phantom chains (bonded forces only) keep
+    # the forces of the unrelaxed start finite; the trajectory must match the oracle.
+    kw = dict(M=20, N=50, seed=21, test_flags=kg.TF_PHANTOM, kappa=1.5)
+    om = o.Melt(warmup_steps=0, **kw)
+    gm = kg.Melt(warmup_steps=0, nl_every=5, **kw)
+    transfer(om, gm)
+    om.md_steps(20)
+    gm.md_steps(20)
+    info = gm.nl_info()
+    assert info["rollbacks"] >= 1 and info["K"] < 5
+    so, sg = om.get_state(), gm.get_state()
+    assert np.max(np.abs(mi_diff(so["x"], sg["x"], om.L))) < 1e-11
+    assert np.array_equal(so["chains"], sg["chains"])
+
+
 def test_lowered_interval_is_retried():
     # with the same too-thin skin, K = 1 is clean: after four clean passes the runtime tries a
     # longer interval again, which rolls back again; the trajectory still matches the oracle
@@ -405,6 +423,74 @@ def test_lists_built_beside_the_sweep():
     sa, sb = a.get_state(), b.get_state()
     for f in ("x", "v", "fl", "chains"):
         assert np.array_equal(sa[f], sb[f]), f
+
+
+def test_failed_rebuild_beside_the_sweep_is_dropped():
+    # a rebuild beside a sweep that overflows (forced by a test flag: it reports an overflow on
+    # its own error word and leaves empty lists) must not affect the sweep nor be used by the
+    # next run of steps: the trajectory equals that of a run without rebuilds beside sweeps
+    kw = dict(M=20, N=50, seed=8, warmup_steps=100, kappa=1.5, test_flags=kg.TF_SIDE_FAULT)
+    a, b = kg.Melt(**kw), kg.Melt(**kw)
+    b.profile(True)  # rebuilds at the start of each run instead of beside the sweep
+    for m in (a, b):
+        m.md_steps(20, graph=False)
+        st = m.db_sweep(50)[0]
+        m.md_steps(20, graph=False)
+        m.db_sweep(50)
+        m.md_steps(7, graph=False)
+    b.profile(False)
+    sa, sb = a.get_state(), b.get_state()
+    for f in ("x", "v", "fl", "chains"):
+        assert np.array_equal(sa[f], sb[f]), f
+    assert st["attempts"] == 50
+
+
+def test_fene_floor_count():
+    # bond-steps on the floored FENE continuation: after one step the count equals the bonds
+    # of the new positions whose argument 1 - r^2/R0^2 lies below the floor (FP64 path)
+    om = o.Melt(M=20, N=50, seed=21, warmup_steps=200)
+    gm = kg.Melt(M=20, N=50, seed=21, warmup_steps=0)
+    st = om.get_state()
+    x = st["x"].copy()
+    ch = st["chains"]
+    # stretch a few bonds into the floored region (r > 1.485; here 1.6) by moving chain ends outward
+    for c in range(0, 20, 4):
+        i, j = ch[c, -2], ch[c, -1]
+        d = x[:, j] - x[:, i]
+        d -= om.L * np.rint(d / om.L)
+        x[:, j] = (x[:, i] + d / np.linalg.norm(d) * 1.6) % om.L
+    gm.set_state(0, x=x, v=np.zeros_like(x), fl=np.zeros_like(x), chains=ch)
+    assert gm.fene_floored() == 0
+    gm.md_steps(1)
+    xs = gm.get_state()["x"]
+    b = xs[:, ch[:, 1:]] - xs[:, ch[:, :-1]]
+    b -= om.L * np.rint(b / om.L)
+    a_arg = 1.0 - (b ** 2).sum(0) / 1.5 ** 2
+    expect = int(np.sum(a_arg < 0.02))
+    assert expect >= 1 and gm.fene_floored() == expect
+
+
+def test_resume_from_state_is_bitwise():
+    # get_state, a new handle, set_state and continuing equals the uninterrupted run: the
+    # storage order after a rebuild (list cell, then monomer id) does not depend on the history
+    kw = dict(M=40, N=50, seed=4, warmup_steps=100, kappa=2.0)
+    a = kg.Melt(**kw)
+    a.md_steps(130)
+    a.db_sweep(40)
+    a.md_steps(30)
+    st = a.get_state()
+    b = kg.Melt(**dict(kw, warmup_steps=0))
+    b.set_state(0, x=st["x"], v=st["v"], fl=st["fl"], chains=st["chains"], counters=st["counters"])
+    for m in (a, b):  # the same rebuild interval on both (a may run a lowered one after a rollback)
+        m.autotune(5)
+    for m in (a, b):
+        m.md_steps(120)
+        m.db_sweep(40)
+        m.md_steps(60)
+    sa, sb = a.get_state(), b.get_state()
+    for f in ("x", "v", "fl", "fc", "chains", "counters"):
+        assert np.array_equal(sa[f], sb[f]), f
+    assert a.nl_info()["K"] == b.nl_info()["K"]
 
 
 def test_sweeps_with_rolled_back_lists_match_oracle():
