@@ -48,25 +48,26 @@ def algorithmic_bytes(mixed):
     return 168.0 if mixed else 196.0
 
 
-def implementation_bytes(mixed, mean_list, K):
+def implementation_bytes(mixed, mean_list, K, staged_per_monomer):
     """Bytes per monomer one launch of this implementation's step kernel moves in its own
     layout, averaged over the K steps of a rebuild interval.
 
     reads: position x (24), velocity v_half (24), own relative position (16: fixed point with
-    FP32 forces; 32 FP64), monomer id (4), chain neighbours' slots (16), list length (4) and
-    list entries (2 each, 16-bit indices into the workgroup's LDS stage).
+    FP32 forces; 32 FP64), monomer id (4), chain neighbours' slots (16), list length (4), list
+    entries (2 each, 16-bit indices into the workgroup's LDS stage) and the recorded slots of
+    the tile's stage (4 per staged member: staged_per_monomer of them per home monomer).
     writes: new x (24), new v_half (24), new relative position (16 / 32); on the step before a
-    rebuild also the bucket entry (4, 4/K per launch on average).  The stage (the tile and its
-    halo: every cell's positions are re-read by ~5 tiles) and the chain neighbours' positions
-    are re-reads served from cache.
+    rebuild also the bucket entry (4, 4/K per launch on average).  The staged positions (the
+    tile and its halo: every cell's are re-read by ~5 tiles) and the chain neighbours'
+    positions are re-reads served from cache.
     """
     rel = 16 if mixed else 32
-    reads = 24 + 24 + rel + 4 + 16 + 4 + 2 * mean_list
+    reads = 24 + 24 + rel + 4 + 16 + 4 + 2 * mean_list + 4 * staged_per_monomer
     writes = 24 + 24 + rel + 4.0 / K
     return reads + writes
 
 
-def run_gpu(kg, precision, steps, warmup, stream, profile_steps):
+def run_gpu(kg, precision, steps, warmup, stream, profile_steps, keep_state=False):
     params = dict(WORKLOAD, precision=precision)
     t0 = time.perf_counter()
     b = kg.Batch([params], stream=stream)
@@ -114,10 +115,13 @@ def run_gpu(kg, precision, steps, warmup, stream, profile_steps):
     M_, N_ = WORKLOAD["M"], WORKLOAD["N"]
     out["fene_floored_frac"] = b.fene_floored() / max(1, b.counters()[0] * M_ * (N_ - 1))
     out["nl"] = b.nl_info()
+    out["lds_stage"] = b.nl_stats()
     out["tune_ms"] = {str(k_): round(v_, 5) for k_, v_ in tune_ms.items()}
     out["ell_K"] = lk
     out["mean_bond"] = mb
     out["monomers"] = nm
+    if keep_state:
+        out["state"] = b.get_state()
     b.close()
     return out
 
@@ -156,11 +160,12 @@ def run_size(kg, monomers, md_steps, stream, precision):
     prof = b.profile_read()
     b.profile(False)
     nl = b.nl_info()
+    st = b.nl_stats()
     b.close()
     ms = prof["force_ms"] / max(prof["force_n"], 1)
     mixed = precision == kg.PREC_MIXED
     bpm = algorithmic_bytes(mixed)
-    ibpm = implementation_bytes(mixed, nl["mean_list"], nl["K"])
+    ibpm = implementation_bytes(mixed, nl["mean_list"], nl["K"], st["staged_per_monomer"])
     achieved = bpm * nm / (ms * 1e-3) / 1e9
     return {"monomers": nm, "chains": nm // N, "beads_per_chain": N, "md_steps": chunks * MD_PER_STEP,
             "monomer_steps_per_s": nm * chunks * MD_PER_STEP / wall, "avg_launch_ms": ms,
@@ -171,7 +176,7 @@ def run_size(kg, monomers, md_steps, stream, precision):
             "implementation_GBs": round(ibpm * nm / (ms * 1e-3) / 1e9, 1), "K": nl["K"], "mean_list": nl["mean_list"],
             "rollbacks": nl["rollbacks"], "skin": round(nl["skin"], 4),
             "autotune_ms_per_step_by_K": {str(k_): round(v_, 5) for k_, v_ in tune_ms.items()},
-            "init_s": round(t_init, 2)}
+            "lds_stage": st, "init_s": round(t_init, 2)}
 
 
 def train_proposal(kg, b, stream, log_sweeps, log_attempts, train_steps):
@@ -408,6 +413,116 @@ def kg_kuhn(kappa):
     return flory + 0.77 * (math.tanh(-0.03 * kappa ** 2 - 0.41 * kappa + 0.16) + 1.0)
 
 
+XI = (2.0, 3.0, 4.0, 5.0, 5.75, 6.5, 7.0, 8.0, 9.0, 10.0, 11.0, 12.0)  # the exponents of Eq. 11
+
+
+def success_fits(kappa, n):
+    """The paper's two fits of the swap success rate: Eq. 15, a exp(-b kappa - d n), and the
+    Fig. 3 caption's a' exp(-b' kappa - d' n - e' n^2)."""
+    return (1.6 * math.exp(-0.77 * kappa - 0.35 * n),
+            1.24 * math.exp(-0.77 * kappa - 0.24 * n - 0.015 * n * n))
+
+
+def wlc_r2_over_n(n, ell_k, l0):
+    """<R^2(n)> / n of the worm-like chain (Eq. 14) for Kuhn length ell_k and bond length l0."""
+    x = 2.0 * n * l0 / ell_k
+    return l0 * ell_k * (1.0 - (1.0 - math.exp(-x)) / x)
+
+
+def run_config2(kg, stream, steps_per_n=20000, sweep_every=50):
+    """The stiff system near nematic onset: 100 chains x 2000 beads (200k monomers), kappa = 3,
+    seeded random-walk start, mixed precision; the exponent stepped through every n of Eq. 11 in
+    turn, `steps_per_n` MD steps at each with one double-bridging sweep every `sweep_every` steps
+    at the paper's attempt rate (Sec. II.B: 100 attempts per sweep here).  Per n: the sweeps'
+    acceptance beside Eq. 15 and the Fig. 3 fit, and R^2(n)/n at the end of the stage beside the
+    worm-like chain of Eq. 14 with the Kuhn length of Eq. 12."""
+    import torch
+    kappa = 3.0
+    params = dict(WORKLOAD, M=100, N=2000, kappa=kappa, n_exp=XI[0], precision=kg.PREC_MIXED)
+    t0 = time.perf_counter()
+    b = kg.Batch([params], stream=stream)
+    torch.cuda.synchronize()
+    setup = time.perf_counter() - t0
+    N = params["N"]
+    sample = [1, 2, 5, 10, 20, 50, 100, 200, 500, 1000, N - 1]
+    rows = []
+    t_all = time.perf_counter()
+    for n in XI:
+        t1 = time.perf_counter()
+        st = b.run_protocol([n], [steps_per_n], sweep_every=sweep_every)[0]
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t1
+        r2n, lk, mb = b.observables()
+        eq15, fig3 = success_fits(kappa, n)
+        tried = st["attempts"] - st["no_candidate"]
+        rows.append({"n": n, "md_steps": st["steps"], "attempts": st["attempts"], "no_candidate": st["no_candidate"],
+                     "accepted": st["accepted"], "acceptance": st["accepted"] / max(st["attempts"], 1),
+                     "acceptance_of_tried": st["accepted"] / max(tried, 1),
+                     "eq15_fit": round(eq15, 5), "fig3_fit": round(fig3, 5),
+                     "r2_over_n": {str(k_): round(float(r2n[k_ - 1]), 4) for k_ in sample},
+                     "ell_K_fit": round(lk, 4), "mean_bond": round(mb, 5), "wall_s": round(wall, 3)})
+    total = time.perf_counter() - t_all
+    lk_pred = kg_kuhn(kappa)
+    mb_end = rows[-1]["mean_bond"]
+    b.close()
+    return {"system": "100 chains x 2000 beads (200k monomers), rho 0.85, kappa 3, mixed precision, "
+                      "seeded random-walk start with the workload's warm-up",
+            "steps_per_n": steps_per_n, "sweep_every": sweep_every, "n_values": list(XI), "setup_s": round(setup, 2),
+            "wall_s": round(total, 2), "stages": rows,
+            "ell_K_eq12_over_l0": round(lk_pred, 4),
+            "wlc_r2_over_n_eq14": {str(k_): round(wlc_r2_over_n(k_, lk_pred * mb_end, mb_end), 4) for k_ in sample}}
+
+
+def run_config1_checks(kg, stream, state, drift_steps=10000, chunk=1000, sweeps=10, attempts=200):
+    """Config 1 (200 x 1000, kappa = 2) from the mixed bench run's final state: (1) energy drift of
+    each precision form over `drift_steps` steps at gamma = 0 (velocity Verlet without the
+    thermostat, Langevin force cleared) on a copy of the state, total energy read every `chunk`
+    steps; (2) the double-bridging decisions of the two forms from the same snapshots: a mixed
+    run (gamma = 1) is stopped every 100 steps, and the FP64 and the mixed batch each run one
+    sweep of `attempts` attempts from that snapshot, `sweeps` times."""
+    nm = state["x"].shape[1]
+    base = dict(WORKLOAD, warmup_steps=0)
+    drift = {}
+    for name, prec in (("fp64", kg.PREC_FP64), ("mixed", kg.PREC_MIXED)):
+        b = kg.Batch([dict(base, precision=prec, gamma=0.0)], stream=stream)
+        b.set_state(0, x=state["x"], v=state["v"], fl=np.zeros_like(state["fl"]), chains=state["chains"],
+                     counters=state["counters"])
+        e = [float(np.sum(b.energy()))]
+        for _ in range(drift_steps // chunk):
+            b.md_steps(chunk)
+            e.append(float(np.sum(b.energy())))
+        b.close()
+        e = np.array(e)
+        drift[name] = {"E0_per_monomer": round(e[0] / nm, 8), "E_end_per_monomer": round(e[-1] / nm, 8),
+                       "drift_rel": float((e[-1] - e[0]) / abs(e[0])),
+                       "max_dev_rel": float(np.max(np.abs(e - e[0])) / abs(e[0])),
+                       "per_monomer_every_chunk": [round(v_ / nm, 8) for v_ in e]}
+    src = kg.Batch([dict(base, precision=kg.PREC_MIXED)], stream=stream)
+    src.set_state(0, x=state["x"], v=state["v"], fl=state["fl"], chains=state["chains"], counters=state["counters"])
+    fb = kg.Batch([dict(base, precision=kg.PREC_FP64)], stream=stream)
+    mb_ = kg.Batch([dict(base, precision=kg.PREC_MIXED)], stream=stream)
+    same_topo, acc = 0, {"fp64": 0, "mixed": 0}
+    same_counts = True
+    for _ in range(sweeps):
+        src.md_steps(MD_PER_STEP)
+        st = src.get_state()
+        res = {}
+        for name, bb in (("fp64", fb), ("mixed", mb_)):
+            bb.set_state(0, x=st["x"], v=st["v"], fl=st["fl"], chains=st["chains"], counters=st["counters"])
+            s = bb.db_sweep(attempts)[0]
+            acc[name] += s["accepted"]
+            res[name] = (s["accepted"], s["no_candidate"], bb.get_state()["chains"])
+        same_counts &= res["fp64"][:2] == res["mixed"][:2]
+        same_topo += int(np.array_equal(res["fp64"][2], res["mixed"][2]))
+    for bb in (src, fb, mb_):
+        bb.close()
+    return {"energy_drift": dict(drift, steps=drift_steps, gamma=0.0, dt=WORKLOAD["dt"]),
+            "db_decision_match": {"sweeps": sweeps, "attempts_per_sweep": attempts,
+                                  "accepted_fp64": acc["fp64"], "accepted_mixed": acc["mixed"],
+                                  "accept_counts_identical": bool(same_counts),
+                                  "sweeps_with_identical_topology": same_topo}}
+
+
 def run_protocol_bench(kg, stream, kappa, steps_per_stage, sweep_every=100):
     """The n-ramp protocol (Sec. II.B) on the paper's own melt size at stiffness kappa: every
     stage of the plan (Eqs. 11, 16-20) runs `steps_per_stage` steps with a sweep at the paper's
@@ -515,7 +630,7 @@ def roofline(run, mixed):
     nm = run["monomers"]
     ms = run["force_kernel_ms"]
     bpm = algorithmic_bytes(mixed)
-    ibpm = implementation_bytes(mixed, run["nl"]["mean_list"], run["nl"]["K"])
+    ibpm = implementation_bytes(mixed, run["nl"]["mean_list"], run["nl"]["K"], run["lds_stage"]["staged_per_monomer"])
     achieved = bpm * nm / (ms * 1e-3) / 1e9
     impl = ibpm * nm / (ms * 1e-3) / 1e9
     return {"bound": "hbm", "kernel": f"k_nl_step<{'float' if mixed else 'double'}, close|open> "
@@ -527,7 +642,7 @@ def roofline(run, mixed):
             "implementation_frac": round(impl / HBM_PEAK_GBS, 4),
             "avg_launch_ms": ms, "launches": run["force_launches_timed"], "neighbour_lists": run["nl"],
             "autotune_ms_per_step_by_K": run["tune_ms"], "rebuild_ms_per_step": run.get("finalize_kernel_ms"),
-            "fene_floored_per_bond_step": run.get("fene_floored_frac")}
+            "fene_floored_per_bond_step": run.get("fene_floored_frac"), "lds_stage": run["lds_stage"]}
 
 
 def step_kernel_hash():
@@ -675,6 +790,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--no-config2", action="store_true",
+                    help="skip the stiff-system run (100 x 2000, kappa 3, every n of Eq. 11)")
+    ap.add_argument("--no-checks", action="store_true",
+                    help="skip the workload's energy drift and FP64/mixed decision match")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run plain copies of known size (for PMC byte counters)")
     ap.add_argument("--size-sweep", default="",
@@ -738,8 +857,22 @@ def main():
         print(json.dumps({"size_sweep": sweep, "equilibration": eq, "protocol": prot, "batch": bat}), flush=True)
         return
     print(f"[bench] mixed path: {args.warmup} warm-up + {args.steps} timed steps", file=sys.stderr, flush=True)
-    mixed = run_gpu(kg, kg.PREC_MIXED, args.steps, args.warmup, stream, args.profile_steps)
+    mixed = run_gpu(kg, kg.PREC_MIXED, args.steps, args.warmup, stream, args.profile_steps,
+                    keep_state=not args.no_checks)
     print(f"[bench] mixed done: {mixed['monomer_steps_per_s']:.3e} monomer-steps/s", file=sys.stderr, flush=True)
+    checks = None
+    if not args.no_checks:
+        print("[bench] workload checks: energy drift (both forms) and decision match", file=sys.stderr, flush=True)
+        checks = run_config1_checks(kg, stream, mixed.pop("state"))
+        print(f"[bench] checks done: drift {checks['energy_drift']['fp64']['drift_rel']:.2e} (fp64), "
+              f"{checks['energy_drift']['mixed']['drift_rel']:.2e} (mixed); identical topology after "
+              f"{checks['db_decision_match']['sweeps_with_identical_topology']} of "
+              f"{checks['db_decision_match']['sweeps']} sweeps", file=sys.stderr, flush=True)
+    conf2 = None
+    if not args.no_config2:
+        print("[bench] stiff system: 100 x 2000, kappa 3, n over Eq. 11", file=sys.stderr, flush=True)
+        conf2 = run_config2(kg, stream)
+        print(f"[bench] stiff system done in {conf2['wall_s']} s", file=sys.stderr, flush=True)
     fp64 = None
     if not args.no_fp64:
         fp64 = run_gpu(kg, kg.PREC_FP64, args.steps, args.warmup, stream, args.profile_steps)
@@ -793,6 +926,10 @@ def main():
                              "neighbour_lists": fp64["nl"], "autotune_ms_per_step_by_K": fp64["tune_ms"],
                              "roofline": roofline(fp64, False) if "force_kernel_ms" in fp64 else None}
         line["speedup_vs_fp64_path"] = mixed["monomer_steps_per_s"] / fp64["monomer_steps_per_s"]
+    if checks:
+        line["workload_checks"] = checks
+    if conf2:
+        line["stiff_system"] = conf2
     if learned:
         line["learned_form"] = learned
     if sweep:

@@ -228,8 +228,9 @@ int kgdb_nl_info(kgdb_batch* b, double out[4]);
 /* LDS stages of the list tiles (a performance diagnostic; no effect on results): out =
    {rebuild tiles whose neighbourhood exceeded the LDS stage and was read from global memory,
    so far; the largest neighbourhood (members) seen; the stage capacity at the current K; its
-   upper limit}.  After a pass in which a tile overflowed, the capacity grows (up to the limit). */
-int kgdb_nl_stats(kgdb_batch* b, int64_t out[4]);
+   upper limit; staged members summed over the tiles at the last stage record; tiles at the
+   current K}.  After a pass in which a tile overflowed, the capacity grows (up to the limit). */
+int kgdb_nl_stats(kgdb_batch* b, int64_t out[6]);
 /* Bond-steps of melt `melt` (since init; each bond counted once per closing kick of an MD
    step on the neighbour-list path) whose FENE argument a = 1 - r^2/R0^2 fell below
    fene_floor, i.e. where the floored continuation of Eqs. 3/10 replaced the log. */

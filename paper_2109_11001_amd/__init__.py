@@ -187,10 +187,11 @@ class Batch:
     def nl_stats(self):
         """LDS stages of the list tiles: tiles read from global memory so far, largest stage,
         current capacity, capacity limit."""
-        out = np.zeros(4, np.int64)
+        out = np.zeros(6, np.int64)
         check(load().kgdb_nl_stats(self._h, ptr(out)))
+        nm, _ = self.sizes()
         return dict(stage_overflows=int(out[0]), largest_stage=int(out[1]), stage_cap=int(out[2]),
-                    stage_cap_max=int(out[3]))
+                    stage_cap_max=int(out[3]), staged_per_monomer=float(out[4]) / max(nm, 1), tiles=int(out[5]))
 
     def fene_floored(self, melt=0):
         """Bond-steps of melt `melt` on the floored FENE continuation (argument below fene_floor)."""

@@ -1799,12 +1799,21 @@ int kgdb_autotune(kgdb_batch* b, int32_t nl_every, int32_t reps, int32_t* chosen
   return rc;
 }
 
-int kgdb_nl_stats(kgdb_batch* b, int64_t out[4]) {
+int kgdb_nl_stats(kgdb_batch* b, int64_t out[6]) {
   if (!b || !out) return fail(KGDB_E_PARAM, "bad arguments");
   out[0] = b->nl_stage_over;
   out[1] = b->nl_stage_seen;
   out[2] = b->nl_ki >= 0 ? b->stage_cap[b->nl_ki] : 0;
   out[3] = b->stage_cap_max;
+  out[4] = out[5] = 0;
+  if (b->nl_ki >= 0) {
+    const int nt = b->ntile[b->nl_ki];
+    std::vector<int4> meta((size_t)nt);
+    HIPCHK(hipStreamSynchronize(b->s));
+    HIPCHK(hipMemcpy(meta.data(), b->d_smeta, sizeof(int4) * (size_t)nt, hipMemcpyDeviceToHost));
+    for (const int4& m : meta) out[4] += m.z;
+    out[5] = nt;
+  }
   return 0;
 }
 

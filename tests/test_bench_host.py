@@ -27,12 +27,28 @@ def test_step_kernel_bytes():
     # integrator 112 (mixed), 56 + 20 + 120 (plain FP64)
     assert B.algorithmic_bytes(True) == 36 + 20 + 112
     assert B.algorithmic_bytes(False) == 56 + 20 + 120
-    # the implementation's own layout: 24 + 24 + 16 + 4 + 16 + 4 + 2 L reads; 24 + 24 + 16 + 4 / K writes
-    L, K = 19.0, 5
-    assert B.implementation_bytes(True, L, K) == pytest.approx(88 + 2 * L + 64 + 4 / K)
-    assert B.implementation_bytes(False, L, K) - B.implementation_bytes(True, L, K) == pytest.approx(32)
+    # the implementation's own layout: 24 + 24 + 16 + 4 + 16 + 4 + 2 L + 4 S reads (S staged
+    # members per monomer); 24 + 24 + 16 + 4 / K writes
+    L, K, S = 19.0, 5, 5.1
+    assert B.implementation_bytes(True, L, K, S) == pytest.approx(88 + 2 * L + 4 * S + 64 + 4 / K)
+    assert B.implementation_bytes(False, L, K, S) - B.implementation_bytes(True, L, K, S) == pytest.approx(32)
 
 
 @pytest.mark.parametrize("kappa", [0.0, 1.0, 2.5, 5.5])
 def test_report_kuhn_equals_oracle(kappa):
     assert B.kg_kuhn(kappa) == pytest.approx(op.kuhn_over_l0(kappa), rel=1e-14)
+
+
+def test_success_fits_are_the_papers_laws():
+    # Eq. 15 and the Fig. 3 caption's fit at kappa = 3, n = 2
+    e15, f3 = B.success_fits(3.0, 2.0)
+    assert e15 == pytest.approx(1.6 * np.exp(-2.31 - 0.70), rel=1e-12)
+    assert f3 == pytest.approx(1.24 * np.exp(-2.31 - 0.48 - 0.06), rel=1e-12)
+
+
+def test_wlc_limits():
+    # Eq. 14: a rod at n l0 << l_K (R^2 = n^2 l0^2), a random walk of Kuhn steps at n l0 >> l_K
+    l0, lk = 0.97, 5.0
+    assert B.wlc_r2_over_n(1e-4, lk, l0) == pytest.approx(1e-4 * l0 * l0, rel=1e-4)
+    assert B.wlc_r2_over_n(1e7, lk, l0) == pytest.approx(l0 * lk, rel=1e-6)
+    assert B.XI == (2.0, 3.0, 4.0, 5.0, 5.75, 6.5, 7.0, 8.0, 9.0, 10.0, 11.0, 12.0)
