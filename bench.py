@@ -131,8 +131,9 @@ def run_size(kg, monomers, md_steps, stream, precision):
     that would exceed the 8192 chains a melt may hold; rho = 0.85, the workload's potentials):
     `md_steps` MD steps timed end to end, then as many again with the step kernel timed by
     events.  From 1M monomers up the per-step state no longer fits the 256 MB last-level cache,
-    so the roofline figure is then set by HBM.  MD only: the sweep's candidate list (at most
-    3072 keys per melt) does not hold the ~2.6 keys per chain of melts this large."""
+    so the roofline figure is then set by HBM.  Then the same number of bench steps with a
+    double-bridging sweep after every 100 MD steps at the paper's attempt rate (lists beyond
+    3072 keys are swept from global memory)."""
     import torch
     N = WORKLOAD["N"]
     while monomers // N > 8192:
@@ -161,6 +162,20 @@ def run_size(kg, monomers, md_steps, stream, precision):
     b.profile(False)
     nl = b.nl_info()
     st = b.nl_stats()
+    att = acc = 0
+    t_db = 0.0
+    t0 = time.perf_counter()
+    for _ in range(chunks):
+        b.md_steps(MD_PER_STEP)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        s_ = b.db_sweep(-1)[0]
+        torch.cuda.synchronize()
+        t_db += time.perf_counter() - t1
+        att += s_["attempts"]
+        acc += s_["accepted"]
+    wall_sw = time.perf_counter() - t0
+    ncand = s_["ncand_end"]
     b.close()
     ms = prof["force_ms"] / max(prof["force_n"], 1)
     mixed = precision == kg.PREC_MIXED
@@ -176,7 +191,10 @@ def run_size(kg, monomers, md_steps, stream, precision):
             "implementation_GBs": round(ibpm * nm / (ms * 1e-3) / 1e9, 1), "K": nl["K"], "mean_list": nl["mean_list"],
             "rollbacks": nl["rollbacks"], "skin": round(nl["skin"], 4),
             "autotune_ms_per_step_by_K": {str(k_): round(v_, 5) for k_, v_ in tune_ms.items()},
-            "lds_stage": st, "init_s": round(t_init, 2)}
+            "lds_stage": st, "init_s": round(t_init, 2),
+            "with_sweeps": {"monomer_steps_per_s": nm * chunks * MD_PER_STEP / wall_sw,
+                            "sweep_ms": round(1e3 * t_db / chunks, 3), "attempts": att, "accepted": acc,
+                            "candidates": ncand}}
 
 
 def train_proposal(kg, b, stream, log_sweeps, log_attempts, train_steps):
@@ -798,7 +816,8 @@ def main():
                     help="also run plain copies of known size (for PMC byte counters)")
     ap.add_argument("--size-sweep", default="",
                     help="comma-separated monomer counts (e.g. 1000000,4000000,16000000): also time the "
-                         "step kernel on single melts of these sizes (N = 1000), mixed path, MD only")
+                         "step kernel on single melts of these sizes (N = 1000), mixed path, then the "
+                         "same bench steps with sweeps")
     ap.add_argument("--size-sweep-steps", type=int, default=500)
     ap.add_argument("--no-main", action="store_true", help="skip the workload runs (with --size-sweep or --equilibration)")
     ap.add_argument("--batch", action="store_true",

@@ -49,6 +49,8 @@ enum kgdb_err {
                                 (the path taken when one does not fit the LDS stage); results unchanged */
 #define KGDB_TF_SIDE_FAULT 8u /* the list rebuild run beside a sweep reports an overflow and leaves
                                  empty lists (tests that such a rebuild is dropped); results unchanged */
+#define KGDB_TF_DB_GLOBAL 16u /* the double-bridging sweep keeps its list in global memory at any
+                                 length (the path of lists above 3072 keys); results unchanged */
 
 /* One melt: M chains of N beads in a cubic periodic box of side (M N / rho)^(1/3).
    Field order is part of the ABI. */
@@ -131,7 +133,10 @@ int kgdb_md_steps(kgdb_batch* b, int64_t nsteps, int32_t use_graph);
 
 /* One double-bridging sweep per melt (Fig. 1, Sec. II.B): n_attempts sequential attempts
    (< 0: round(db_rate * N_mono * time since the last sweep)).  Positions and velocities are
-   untouched; the chain tables change.  stats[k] receives melt k's statistics (may be NULL). */
+   untouched; the chain tables change.  stats[k] receives melt k's statistics (may be NULL).
+   A melt holds up to max(3072, 8 M + 1024) candidates (rounded up to a power of two beyond
+   3072); lists above 3072 keys are swept from global memory (same decisions), and the learned
+   proposal reports them as a candidate overflow. */
 int kgdb_db_sweep(kgdb_batch* b, int64_t n_attempts, kgdb_db_stats* stats);
 
 /* ---- the n-ramp protocol (Sec. II.B) ---- */

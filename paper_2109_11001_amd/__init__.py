@@ -9,7 +9,7 @@ import ctypes as C
 import numpy as np
 
 from ._lib import (INIT_FREELY_ROTATING, INIT_RANDOM_WALK, MLP_NPARAM, PREC_FP64, PREC_MIXED, PROPOSAL_LEARNED,
-                   PROPOSAL_LITERAL, PROPOSAL_UNIFORM, TF_NL_GLOBAL, TF_NOFORCE, TF_PHANTOM, TF_SIDE_FAULT, DbStats, KgdbError,
+                   PROPOSAL_LITERAL, PROPOSAL_UNIFORM, TF_DB_GLOBAL, TF_NL_GLOBAL, TF_NOFORCE, TF_PHANTOM, TF_SIDE_FAULT, DbStats, KgdbError,
                    Params, StageStats, check, load, ptr)
 
 NN_IN = 25

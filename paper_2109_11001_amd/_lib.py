@@ -15,7 +15,7 @@ E_PARAM, E_ALLOC, E_HIP, E_FENE, E_NONFINITE, E_OVERFLOW, E_STATE = -1, -2, -3, 
 PROPOSAL_UNIFORM, PROPOSAL_LEARNED, PROPOSAL_LITERAL = 0, 1, 2
 PREC_FP64, PREC_MIXED = 0, 1
 INIT_RANDOM_WALK, INIT_FREELY_ROTATING = 0, 1
-TF_PHANTOM, TF_NOFORCE, TF_NL_GLOBAL, TF_SIDE_FAULT = 1, 2, 4, 8
+TF_PHANTOM, TF_NOFORCE, TF_NL_GLOBAL, TF_SIDE_FAULT, TF_DB_GLOBAL = 1, 2, 4, 8, 16
 
 
 class KgdbError(RuntimeError):

@@ -126,6 +126,11 @@ struct kgdb_batch {
   double* d_out4 = nullptr;
   int *d_cnt13 = nullptr, *d_bucket13 = nullptr, *d_nnb = nullptr, *d_nbr = nullptr, *d_ncand = nullptr;
   uint64_t *d_cand = nullptr, *d_sweep = nullptr, *d_probe_keys = nullptr;
+  int cand_cap = DB_CAND_CAP;      // candidate keys per melt
+  uint64_t* d_gkeys = nullptr;     // the sweep's working lists beyond the LDS (cand_cap > DB_CAND_CAP)
+  uint32_t* d_gpair = nullptr;
+  double* d_gdE = nullptr;
+  uint8_t* d_grev = nullptr;
   int64_t *d_natt = nullptr, *d_probe_n = nullptr;
   double* d_probe_dE = nullptr;
   kgdb_db_stats* d_stats = nullptr;
@@ -1115,7 +1120,29 @@ static int init_impl(const kgdb_params* params, int32_t count, void* stream, kgd
   step(dalloc(b, &b->d_nnb, np));
   step(dalloc(b, &b->d_nbr, np * DB_NBR_CAP));
   step(dalloc(b, &b->d_ncand, (size_t)count));
-  step(dalloc(b, &b->d_cand, (size_t)count * DB_CAND_CAP));
+  {
+    // room for 8 keys per chain + 1024 (random-walk and equilibrated melts hold about 2.6 per
+    // chain); beyond what the sweep holds in LDS, a power of two and the lists in global memory
+    int mmax = 0;
+    bool force = false;
+    for (int k = 0; k < count; ++k) {
+      mmax = std::max(mmax, params[k].M);
+      force = force || (params[k].test_flags & TF_DB_GLOBAL);
+    }
+    const int want = 8 * mmax + 1024;
+    if (want > DB_CAND_CAP || force) {
+      b->cand_cap = 4096;
+      while (b->cand_cap < want) b->cand_cap <<= 1;
+    }
+  }
+  step(dalloc(b, &b->d_cand, (size_t)count * b->cand_cap));
+  if (b->cand_cap > DB_CAND_CAP) {
+    const size_t g = (size_t)count * 2 * b->cand_cap;
+    step(dalloc(b, &b->d_gkeys, g));
+    step(dalloc(b, &b->d_gpair, g));
+    step(dalloc(b, &b->d_gdE, g));
+    step(dalloc(b, &b->d_grev, g));
+  }
   step(dalloc(b, &b->d_sweep, (size_t)count));
   step(dalloc(b, &b->d_natt, (size_t)count));
   step(dalloc(b, &b->d_stats, (size_t)count));
@@ -1427,6 +1454,11 @@ static DbArgs db_args(kgdb_batch* b) {
   a.nnb = b->d_nnb;
   a.nbr = b->d_nbr;
   a.cand = b->d_cand;
+  a.cand_cap = b->cand_cap;
+  a.gkeys = b->d_gkeys;
+  a.gpair = b->d_gpair;
+  a.gdE = b->d_gdE;
+  a.grev = b->d_grev;
   a.ncand = b->d_ncand;
   a.err = b->d_err;
   a.sweep_ctr = b->d_sweep;
@@ -1457,7 +1489,7 @@ int kgdb_candidates(kgdb_batch* b, int32_t melt, uint64_t* keys, int64_t cap, in
   if (n) *n = nk;
   if (keys) {
     if (cap < nk) return fail(KGDB_E_PARAM, "key buffer too small");
-    HIPCHK(hipMemcpy(keys, b->d_cand + (size_t)melt * DB_CAND_CAP, sizeof(uint64_t) * nk, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(keys, b->d_cand + (size_t)melt * b->cand_cap, sizeof(uint64_t) * nk, hipMemcpyDeviceToHost));
     std::sort(keys, keys + nk);
   }
   return 0;

@@ -271,7 +271,7 @@ __global__ __launch_bounds__(256) void k_db_cands(const MeltDesc* __restrict__ m
     if (Cu >= Cw) continue;
     first_bond_candidates(T, a.x, a.NP, d.L, d.rmax2, d.M, u, Cu, pu, w, Cw, pw, [&](uint64_t key) {
       const int s = atomicAdd(&a.ncand[k], 1);
-      if (s < DB_CAND_CAP) a.cand[(size_t)k * DB_CAND_CAP + s] = key;
+      if (s < a.cand_cap) a.cand[(size_t)k * a.cand_cap + s] = key;
       else atomicOr(&a.err[k], ERR_CAND_OVERFLOW);
     });
   }
@@ -527,16 +527,20 @@ __device__ __forceinline__ bool touches(uint64_t key, const MeltDesc& d, int A, 
   return pair_touches(key_pair(key, d), A, B);
 }
 
-// number of keys < v in the sorted s_keys[0, n), n <= 64 * 64, by one wavefront: a coarse pass
-// over every S-th key, then the S - 1 keys of the bracket it found
-__device__ __forceinline__ int wave_lower_bound(const uint64_t* s_keys, int n, uint64_t v, int lane) {
-  const int S = (n + 63) >> 6;
-  const int pc = lane * S;
-  const int c = __popcll(__ballot(pc < n && s_keys[pc] < v));
-  if (c == 0) return 0;
-  const int b0 = (c - 1) * S + 1, b1 = min(c * S, n);
-  const int pf = b0 + lane;
-  return b0 + __popcll(__ballot(lane < S - 1 && pf < b1 && s_keys[pf] < v));
+// number of keys < v in the sorted keys[0, n), by one wavefront: passes over every S-th key of
+// the open range narrow it to the bracket between two samples, until 64 keys remain (one pass
+// for n <= 64 * 64, two for n <= 64^3)
+__device__ __forceinline__ int wave_lower_bound(const uint64_t* keys, int n, uint64_t v, int lane) {
+  int lo = 0, len = n;  // keys before lo are < v; the answer lies in [lo, lo + len]
+  while (len > 64) {
+    const int S = (len + 63) >> 6;
+    const int c = __popcll(__ballot(lane * S < len && keys[lo + lane * S] < v));
+    if (c == 0) return lo;
+    const int nlo = lo + (c - 1) * S + 1;
+    len = lo + min(c * S, len) - nlo;
+    lo = nlo;
+  }
+  return lo + __popcll(__ballot(lane < len && keys[lo + lane] < v));
 }
 
 // Delta E and reverse-move validity of keys[0, n) in the current topology, four threads per
@@ -618,6 +622,8 @@ __global__ __launch_bounds__(DB_BLOCK) void k_db_sweep(DbArgs a) {
     sum_dE = 0.0;
   }
   int n = a.ncand[k];
+  // a long list (or any, under the test flag): k_db_sweep_big's melt
+  if ((n > DB_CAND_CAP || (a.md[k].test_flags & TF_DB_GLOBAL)) && a.gkeys && a.err[k] == 0) return;
   if (n > DB_CAND_CAP || a.err[k] != 0) {  // a build overflow was latched: no attempts
     if (threadIdx.x == 0) {
       st->attempts = st->no_candidate = st->accepted = st->reverse_impossible = st->sum_ncand = 0;
@@ -630,7 +636,7 @@ __global__ __launch_bounds__(DB_BLOCK) void k_db_sweep(DbArgs a) {
   // sort the list (bitonic over the next power of two, padded with the largest key)
   int P = 1;
   while (P < n) P <<= 1;
-  for (int t = threadIdx.x; t < P; t += blockDim.x) s_keys[t] = t < n ? a.cand[(size_t)k * DB_CAND_CAP + t] : ~0ull;
+  for (int t = threadIdx.x; t < P; t += blockDim.x) s_keys[t] = t < n ? a.cand[(size_t)k * a.cand_cap + t] : ~0ull;
   for (int t = threadIdx.x; t < M; t += blockDim.x) s_cc[t] = 0;
   __syncthreads();
   for (int size = 2; size <= P; size <<= 1)
@@ -879,7 +885,284 @@ __global__ __launch_bounds__(DB_BLOCK) void k_db_sweep(DbArgs a) {
     a.ncand[k] = n;
     if (a.log_n) a.log_n[k] = s_logn;
   }
-  for (int t = threadIdx.x; t < n; t += blockDim.x) a.cand[(size_t)k * DB_CAND_CAP + t] = s_keys[t];
+  for (int t = threadIdx.x; t < n; t += blockDim.x) a.cand[(size_t)k * a.cand_cap + t] = s_keys[t];
+}
+
+// ---------------------------------------------------------------------------------------
+// The sweep for lists longer than the LDS holds (more than DB_CAND_CAP keys, melts of more
+// than about 1,100 chains): the same attempts, decisions and list updates as k_db_sweep, with
+// the sorted list and its attributes in global memory.  Each accepted move writes the merged
+// list into the melt's other buffer (no update in place).  The per-chain key counts, the new
+// and the leaving keys of a move stay in LDS.  One workgroup per melt.
+// ---------------------------------------------------------------------------------------
+template <bool DBG>
+__global__ __launch_bounds__(DB_BLOCK) void k_db_sweep_big(DbArgs a) {
+  __shared__ uint64_t s_new[DB_NEW_CAP];
+  __shared__ uint64_t s_ns[DB_NEW_CAP];   // the new keys, sorted
+  __shared__ uint64_t s_rm[DB_NEW_CAP];   // the leaving keys (any order)
+  __shared__ int s_cc[DB_MAX_CHAINS];     // keys touching each chain
+  __shared__ double s_ndE[DB_NEW_CAP];
+  __shared__ uint8_t s_nrev[DB_NEW_CAP];
+  __shared__ int s_dst[DB_NEW_CAP];
+  __shared__ AttemptEval s_ev[DB_WAVES];
+  __shared__ uint64_t s_rw[DB_BLOCK];
+  __shared__ double s_ru[DB_BLOCK];
+  __shared__ int s_tmp[DB_BLOCK / 64];
+  __shared__ int s_cnt[4];
+  __shared__ int s_total, s_nrm;
+  __shared__ uint32_t s_err;
+  __shared__ int s_accept;
+  __shared__ int64_t s_logn, s_logat;
+  __shared__ int64_t n_att, n_nocand, n_acc, n_norev, sum_nc;
+  __shared__ double sum_dE;
+
+  const int k = blockIdx.x;
+  int n = a.ncand[k];
+  const MeltDesc& d = a.md[k];
+  if ((n <= DB_CAND_CAP && !(d.test_flags & TF_DB_GLOBAL)) || a.err[k] != 0) return;  // k_db_sweep's melt
+  const int M = d.M, N = d.N;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int cap = a.cand_cap;  // a power of two >= n
+  kgdb_db_stats* st = (kgdb_db_stats*)a.stats + k;
+  if (threadIdx.x == 0) {
+    s_err = 0;
+    s_logn = 0;
+    n_att = n_nocand = n_acc = n_norev = sum_nc = 0;
+    sum_dE = 0.0;
+  }
+  const size_t base = (size_t)k * 2 * cap;
+  uint64_t* keys = a.gkeys + base;
+  uint64_t* keys2 = keys + cap;
+  uint32_t* pair = a.gpair + base;
+  uint32_t* pair2 = pair + cap;
+  double* dEv = a.gdE + base;
+  double* dE2 = dEv + cap;
+  uint8_t* rev = a.grev + base;
+  uint8_t* rev2 = rev + cap;
+  // sort the list (bitonic over the next power of two, padded with the largest key)
+  int P = 1;
+  while (P < n) P <<= 1;
+  for (int t = threadIdx.x; t < P; t += blockDim.x) keys[t] = t < n ? a.cand[(size_t)k * cap + t] : ~0ull;
+  for (int t = threadIdx.x; t < M; t += blockDim.x) s_cc[t] = 0;
+  __syncthreads();
+  for (int size = 2; size <= P; size <<= 1)
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int t = threadIdx.x; t < P; t += blockDim.x) {
+        const int o = t ^ stride;
+        if (o > t) {
+          const bool up = (t & size) == 0;
+          const uint64_t x0 = keys[t], x1 = keys[o];
+          if ((x0 > x1) == up) { keys[t] = x1; keys[o] = x0; }
+        }
+      }
+      __syncthreads();
+    }
+  for (int t = threadIdx.x; t < n; t += blockDim.x) {
+    const uint32_t pr = key_pair(keys[t], d);
+    pair[t] = pr;
+    atomicAdd(&s_cc[pr >> 16], 1);
+    atomicAdd(&s_cc[pr & 0xffffu], 1);
+  }
+  key_attributes(d, a, keys, n, dEv, rev);
+  __syncthreads();
+
+  const int64_t K = a.nattempt[k];
+  const uint64_t sweep = a.sweep_ctr[k];
+  const uint64_t kstride = (uint64_t)(N - 1) * (uint64_t)M * (uint64_t)(N - 1) * 2u;
+  const double T = d.T;
+  const int literal = d.proposal == KGDB_PROPOSAL_LITERAL;
+  int64_t att = 0, c0 = -(int64_t)DB_BLOCK;
+  while (att < K) {
+    if (att + DB_WAVES > c0 + DB_BLOCK) {
+      c0 = att;
+      const U64x4 r = rng_draw(d, (uint64_t)(c0 + threadIdx.x), sweep, ST_DB);
+      s_rw[threadIdx.x] = r.w[0];
+      s_ru[threadIdx.x] = u01(r.w[1]);
+      __syncthreads();
+    }
+    if (n == 0) {
+      if (threadIdx.x == 0) {
+        n_att += K - att;
+        n_nocand += K - att;
+      }
+      break;
+    }
+    // ---- evaluate attempts att .. att + DB_WAVES - 1, wavefront wv taking att + wv
+    if (threadIdx.x == 0) s_cnt[0] = s_cnt[1] = s_cnt[2] = s_cnt[3] = 0;
+    if (att + wv < K) {
+      const int ci = (int)(att - c0) + wv;
+      const int idx = (int)rng_choice(s_rw[ci], (uint64_t)n);
+      const Move mv = decode_key(keys[idx], d);
+      const int lo = wave_lower_bound(keys, n, (uint64_t)mv.A * kstride, lane);
+      const int hi = wave_lower_bound(keys, n, (uint64_t)(mv.A + 1) * kstride, lane);
+      const uint32_t want = ((uint32_t)mv.A << 16) | (uint32_t)mv.B;
+      int both = 0;
+      for (int t = lo; t < hi; t += 64) both += __popcll(__ballot(t + lane < hi && pair[t + lane] == want));
+      if (lane == 0) {
+        const double dE = dEv[idx];
+        const double u = s_ru[ci];
+        const int rv = rev[idx];
+        const int old_ab = s_cc[mv.A] + s_cc[mv.B] - both;
+        int phase = 1;
+        if (literal) phase = (u < exp(-dE / T)) ? 2 : 0;
+        else if (!rv) phase = 0;
+        else if (!(u < exp(-dE / T) * (double)n / (double)(n - old_ab + 1))) phase = 0;
+        AttemptEval& ev = s_ev[wv];
+        ev.mv = mv; ev.old_ab = old_ab; ev.phase = phase; ev.rev = rv; ev.dE = dE; ev.u = u;
+      }
+    }
+    __syncthreads();
+    // ---- walk the evaluated attempts in order
+    const int nev = (int)min((int64_t)DB_WAVES, K - att);
+    int used = nev;
+    for (int w = 0; w < nev; ++w) {
+      const Move mv = s_ev[w].mv;
+      const int phase = s_ev[w].phase, old_ab = s_ev[w].old_ab;
+      if constexpr (DBG) {
+        Topo To{a.chain, a.loc, d.off, N, {mv.A, mv.i, mv.B, mv.j, -1}};
+        count_touching(d, To, a, mv.A, mv.B, s_cnt + 3, nullptr, &s_err);
+        __syncthreads();
+        if (threadIdx.x == 0) {
+          if (s_cnt[3] != old_ab) s_err |= ERR_DB_MISMATCH;
+          s_cnt[3] = 0;
+        }
+        __syncthreads();
+      }
+      if (threadIdx.x == 0) {
+        n_att++;
+        sum_nc += n;
+        if (!literal && !s_ev[w].rev) n_norev++;
+        s_logat = -1;
+        if (a.log_feat && s_logn < a.log_cap) {
+          s_logat = s_logn++;
+          const Topo To{a.chain, a.loc, d.off, N, {mv.A, mv.i, mv.B, mv.j, -1}};
+          float f[NN_IN];
+          move_features(d, To, a.x, a.NP, mv, f);
+          const size_t r = (size_t)k * a.log_cap + s_logat;
+          for (int q = 0; q < NN_IN; ++q) a.log_feat[r * NN_IN + q] = f[q];
+          a.log_label[r] = 0;
+        }
+      }
+      if (phase == 0) continue;
+      touching_after(d, a, mv, keys, pair, n, s_cnt, s_new, &s_err, DB_NEW_CAP);
+      if constexpr (DBG) {
+        Topo Tn{a.chain, a.loc, d.off, N, mv};
+        count_touching(d, Tn, a, mv.A, mv.B, s_cnt + 2, nullptr, &s_err);
+      }
+      __syncthreads();
+      if (DBG && threadIdx.x == 0) {
+        if (s_cnt[2] != s_cnt[0]) s_err |= ERR_DB_MISMATCH;
+        s_cnt[2] = 0;
+      }
+      if (threadIdx.x == 0) {
+        const int new_ab = s_cnt[0];
+        const int n_new = n - old_ab + new_ab;
+        const double dE = s_ev[w].dE, u = s_ev[w].u;
+        const double ratio = (phase == 2) ? 2.0 : exp(-dE / T) * (double)n / (double)n_new;
+        const int acc = (u < ratio) && (s_cnt[1] <= DB_NEW_CAP) && (n_new <= cap) && (old_ab <= DB_NEW_CAP);
+        if ((u < ratio) && !acc) s_err |= ERR_CAND_OVERFLOW;
+        if (acc) { n_acc++; sum_dE += dE; }
+        if (acc && s_logat >= 0) a.log_label[(size_t)k * a.log_cap + s_logat] = 1;
+        s_accept = acc;
+        s_nrm = 0;
+      }
+      __syncthreads();
+      if (!s_accept) {
+        if (threadIdx.x == 0) s_cnt[0] = s_cnt[1] = 0;
+        __syncthreads();
+        continue;
+      }
+
+      // ---- commit, then the merged list into the other buffers
+      commit_move(d.off, N, a.chain, a.loc, mv);
+      {
+        const int nn = s_cnt[1];
+        const int per = (n + DB_BLOCK - 1) / DB_BLOCK;
+        const int t0 = min(n, (int)threadIdx.x * per), t1 = min(n, t0 + per);
+        int keep = 0;
+        for (int t = t0; t < t1; ++t) {
+          const uint32_t p = pair[t];
+          if (!pair_touches(p, mv.A, mv.B)) {
+            ++keep;
+          } else {
+            const int slot = atomicAdd(&s_nrm, 1);  // < old_ab <= DB_NEW_CAP
+            if (slot < DB_NEW_CAP) s_rm[slot] = keys[t];
+            atomicSub(&s_cc[p >> 16], 1);
+            atomicSub(&s_cc[p & 0xffffu], 1);
+          }
+        }
+        const int pos0 = block_exclusive_scan(keep, s_tmp, &s_total);  // synchronises
+        const int nk = s_total, nrm = min(s_nrm, DB_NEW_CAP);
+        key_attributes(d, a, s_new, nn, s_ndE, s_nrev);
+        // a new key's destination: its rank r among the new keys + #(kept keys below it)
+        for (int t = wv; t < nn; t += DB_WAVES) {
+          const uint64_t key = s_new[t];
+          int r = 0, brm = 0;
+          for (int q0 = 0; q0 < nn; q0 += 64) r += __popcll(__ballot(q0 + lane < nn && s_new[q0 + lane] < key));
+          for (int q0 = 0; q0 < nrm; q0 += 64) brm += __popcll(__ballot(q0 + lane < nrm && s_rm[q0 + lane] < key));
+          const int lo = wave_lower_bound(keys, n, key, lane);
+          if (lane == 0) {
+            s_ns[r] = key;
+            s_dst[t] = r + lo - brm;
+            const uint32_t pr = key_pair(key, d);
+            atomicAdd(&s_cc[pr >> 16], 1);
+            atomicAdd(&s_cc[pr & 0xffffu], 1);
+          }
+        }
+        __syncthreads();
+        // a kept key's destination: its kept rank + #(new keys below it)
+        int pos = pos0;
+        for (int t = t0; t < t1; ++t) {
+          const uint32_t p = pair[t];
+          if (pair_touches(p, mv.A, mv.B)) continue;
+          const uint64_t key = keys[t];
+          int lo = 0, hi = nn;
+          while (lo < hi) { const int mid = (lo + hi) >> 1; if (s_ns[mid] < key) lo = mid + 1; else hi = mid; }
+          const int dd = pos++ + lo;
+          keys2[dd] = key; pair2[dd] = p; dE2[dd] = dEv[t]; rev2[dd] = rev[t];
+        }
+        for (int t = threadIdx.x; t < nn; t += blockDim.x) {
+          const int dd = s_dst[t];
+          const uint64_t key = s_new[t];
+          keys2[dd] = key;
+          pair2[dd] = key_pair(key, d);
+          dE2[dd] = s_ndE[t];
+          rev2[dd] = s_nrev[t];
+        }
+        uint64_t* tk = keys; keys = keys2; keys2 = tk;
+        uint32_t* tp = pair; pair = pair2; pair2 = tp;
+        double* td = dEv; dEv = dE2; dE2 = td;
+        uint8_t* tr = rev; rev = rev2; rev2 = tr;
+        n = nk + nn;
+        __syncthreads();
+      }
+      if constexpr (DBG) {  // the carried attributes equal a full evaluation in the new topology
+        key_attributes(d, a, keys, n, dE2, rev2);
+        __syncthreads();
+        for (int t = threadIdx.x; t < n; t += blockDim.x)
+          if (dE2[t] != dEv[t] || rev2[t] != rev[t]) atomicOr(&s_err, ERR_DB_MISMATCH);
+        __syncthreads();
+      }
+      used = w + 1;
+      break;
+    }
+    att += used;
+    __syncthreads();
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    st->attempts = n_att;
+    st->no_candidate = n_nocand;
+    st->accepted = n_acc;
+    st->reverse_impossible = n_norev;
+    st->sum_ncand = sum_nc;
+    st->sum_dE_accepted = sum_dE;
+    st->ncand_end = n;
+    if (s_err) atomicOr(&a.err[k], s_err);
+    a.ncand[k] = n;
+    if (a.log_n) a.log_n[k] = s_logn;
+  }
+  for (int t = threadIdx.x; t < n; t += blockDim.x) a.cand[(size_t)k * cap + t] = keys[t];
 }
 
 // test hook: Delta E and |C(x')| for given keys, without committing (one block per key)
@@ -891,10 +1174,10 @@ __global__ __launch_bounds__(DB_BLOCK) void k_db_probe(DbArgs a, int k, const ui
   const Move mv = decode_key(keys[blockIdx.x], d);
   if (threadIdx.x == 0) { s_cnt[0] = s_cnt[1] = s_cnt[2] = s_cnt[3] = 0; s_err = 0; }
   __syncthreads();
-  const int n = a.ncand[k] < DB_CAND_CAP ? a.ncand[k] : DB_CAND_CAP;
+  const int n = a.ncand[k] < a.cand_cap ? a.ncand[k] : a.cand_cap;
   int mine = 0;
   for (int t = threadIdx.x; t < n; t += blockDim.x)
-    mine += touches(a.cand[(size_t)k * DB_CAND_CAP + t], d, mv.A, mv.B) ? 1 : 0;
+    mine += touches(a.cand[(size_t)k * a.cand_cap + t], d, mv.A, mv.B) ? 1 : 0;
   if (mine) atomicAdd(&s_cnt[2], mine);
   Topo Tn{a.chain, a.loc, d.off, d.N, mv};
   count_touching(d, Tn, a, mv.A, mv.B, s_cnt, nullptr, &s_err);
@@ -1068,6 +1351,8 @@ __global__ __launch_bounds__(DB_BLOCK) void k_db_sweep_learned(DbArgs a) {
   int n = a.ncand[k];
   if (n > DB_CAND_CAP || a.err[k] != 0) {
     if (threadIdx.x == 0) {
+      // (the learned sweep holds its list in LDS: a longer one is an overflow here)
+      if (n > DB_CAND_CAP && a.err[k] == 0) atomicOr(&a.err[k], ERR_CAND_OVERFLOW);
       st->attempts = st->no_candidate = st->accepted = st->reverse_impossible = st->sum_ncand = 0;
       st->sum_dE_accepted = 0.0;
       st->ncand_end = n;
@@ -1076,7 +1361,7 @@ __global__ __launch_bounds__(DB_BLOCK) void k_db_sweep_learned(DbArgs a) {
   }
   int P = 1;
   while (P < n) P <<= 1;
-  for (int t = threadIdx.x; t < P; t += blockDim.x) s_keys[t] = t < n ? a.cand[(size_t)k * DB_CAND_CAP + t] : ~0ull;
+  for (int t = threadIdx.x; t < P; t += blockDim.x) s_keys[t] = t < n ? a.cand[(size_t)k * a.cand_cap + t] : ~0ull;
   __syncthreads();
   for (int size = 2; size <= P; size <<= 1)
     for (int stride = size >> 1; stride > 0; stride >>= 1) {
@@ -1320,7 +1605,7 @@ __global__ __launch_bounds__(DB_BLOCK) void k_db_sweep_learned(DbArgs a) {
     if (s_err) atomicOr(&a.err[k], s_err);
     a.ncand[k] = n;
   }
-  for (int t = threadIdx.x; t < n; t += blockDim.x) a.cand[(size_t)k * DB_CAND_CAP + t] = s_keys[t];
+  for (int t = threadIdx.x; t < n; t += blockDim.x) a.cand[(size_t)k * a.cand_cap + t] = s_keys[t];
 }
 
 // test hook: inputs of the learned proposal for given keys at the current topology
@@ -1346,6 +1631,10 @@ void launch_db_build(const DbArgs& a, const BlockMap& pm, const BlockMap& cm13, 
 void launch_db_sweep(const DbArgs& a, hipStream_t s) {
   if (a.debug) hipLaunchKernelGGL(k_db_sweep<true>, dim3(a.nm), dim3(DB_BLOCK), 0, s, a);
   else hipLaunchKernelGGL(k_db_sweep<false>, dim3(a.nm), dim3(DB_BLOCK), 0, s, a);
+  if (a.gkeys) {  // melts whose list is longer than the LDS holds (the kernel above skips them)
+    if (a.debug) hipLaunchKernelGGL(k_db_sweep_big<true>, dim3(a.nm), dim3(DB_BLOCK), 0, s, a);
+    else hipLaunchKernelGGL(k_db_sweep_big<false>, dim3(a.nm), dim3(DB_BLOCK), 0, s, a);
+  }
 }
 
 void launch_db_probe(const DbArgs& a, int melt, const uint64_t* keys, int nkeys, double* dE, int64_t* nafter,

@@ -41,7 +41,7 @@ enum : uint32_t {
 // Philox counter word 2: the random-number stream
 enum : uint64_t { ST_WALK = 1, ST_VEL = 2, ST_LANGEVIN = 3, ST_DB = 4, ST_WARMUP = 5 };
 
-enum : uint32_t { TF_PHANTOM = 1u, TF_NOFORCE = 2u, TF_NL_GLOBAL = 4u, TF_SIDE_FAULT = 8u };
+enum : uint32_t { TF_PHANTOM = 1u, TF_NOFORCE = 2u, TF_NL_GLOBAL = 4u, TF_SIDE_FAULT = 8u, TF_DB_GLOBAL = 16u };
 
 // Per-melt constants, laid out for scalar loads (the melt index is uniform per workgroup).
 struct MeltDesc {

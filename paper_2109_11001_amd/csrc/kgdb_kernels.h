@@ -166,7 +166,14 @@ struct DbArgs {
   int* bucket13;   // [NC13 * DB_CELL_CAP]
   int* nnb;        // [NP] close-neighbour counts
   int* nbr;        // [NP * DB_NBR_CAP] close neighbours (global ids)
-  uint64_t* cand;  // [nm * DB_CAND_CAP] candidate keys per melt
+  uint64_t* cand;  // [nm * cand_cap] candidate keys per melt
+  int cand_cap;    // candidate keys a melt may hold (DB_CAND_CAP, or a power of two above it)
+  // lists longer than the LDS holds (more than DB_CAND_CAP keys): the sweep's working list in
+  // global memory, two buffers of cand_cap entries per melt (null when cand_cap = DB_CAND_CAP)
+  uint64_t* gkeys;
+  uint32_t* gpair;
+  double* gdE;
+  uint8_t* grev;
   int* ncand;      // [nm]
   uint32_t* err;
   const uint64_t* sweep_ctr;  // per melt sweep index (Philox counter word 1)

@@ -406,6 +406,58 @@ def test_db_sweep_full_size_c1():
     assert np.array_equal(om.get_state()["chains"], gm.get_state()["chains"])
 
 
+@pytest.mark.parametrize("kw,proposal", [(dict(M=20, N=50, seed=8, kappa=1.5), 0),
+                                         (dict(M=25, N=31, seed=8, kappa=3.0, n_exp=12.0), 0),
+                                         (dict(M=40, N=60, seed=3, kappa=0.5), 2)])
+def test_db_sweep_global_list_equals_oracle(kw, proposal):
+    # the sweep with its list in global memory (the path of lists above 3,072 keys, forced here
+    # on small melts) against the oracle: decisions, statistics and topology bit for bit, with the
+    # on-device checks of the incremental list on and off
+    om, gm = pair(proposal=proposal, test_flags=kg.TF_DB_GLOBAL, **kw)
+    for sweep, checked in enumerate((True, False, True)):
+        so = om.db_sweep(150)
+        sg = gm.db_sweep(150, checked=checked)[0]
+        for f in ("attempts", "no_candidate", "accepted", "reverse_impossible", "sum_ncand", "ncand_end"):
+            assert so[f] == sg[f], (sweep, f, so, sg)
+        assert sg["sum_dE_accepted"] == pytest.approx(so["sum_dE_accepted"], rel=1e-11, abs=1e-11)
+        assert np.array_equal(om.get_state()["chains"], gm.get_state()["chains"]), sweep
+
+
+def test_db_sweep_beyond_the_lds_list():
+    # 6,000 chains of 100 beads (600,000 monomers, a short warm-up to clear the random walks'
+    # overlaps): more candidates than the 3,072 keys the sweep holds in LDS.  The oracle's
+    # attempts each cost a pass over the melt, so the sweeps are short.
+    print("building the 600k-monomer oracle melt", flush=True)
+    om, gm = pair(M=6000, N=100, seed=4, kappa=1.5, warmup_steps=30)
+    n_o = om.candidates().size
+    assert n_o > 3072, n_o
+    for sweep, checked in enumerate((True, False)):
+        print(f"sweep {sweep}", flush=True)
+        so = om.db_sweep(25)
+        sg = gm.db_sweep(25, checked=checked)[0]
+        for f in ("attempts", "no_candidate", "accepted", "reverse_impossible", "sum_ncand", "ncand_end"):
+            assert so[f] == sg[f], (sweep, f, so, sg)
+        assert np.array_equal(om.get_state()["chains"], gm.get_state()["chains"]), sweep
+    assert so["ncand_end"] > 3072
+
+
+def test_db_sweep_long_and_short_lists_in_one_batch():
+    # a batch whose first melt is swept from global memory (test flag) and whose second from
+    # LDS: each by its kernel, both equal to the oracle
+    kws = [dict(M=20, N=50, seed=8, kappa=1.5, test_flags=kg.TF_DB_GLOBAL), dict(M=30, N=40, seed=9, kappa=1.0)]
+    b = kg.Batch([dict(k_, warmup_steps=0) for k_ in kws])
+    oms = [o.Melt(warmup_steps=100, **k_) for k_ in kws]
+    for i, om in enumerate(oms):
+        transfer(om, b, melt=i)
+    for _ in range(2):
+        sg = b.db_sweep(100)
+        for i, om in enumerate(oms):
+            so = om.db_sweep(100)
+            for f in ("attempts", "accepted", "ncand_end"):
+                assert so[f] == sg[i][f], (i, f)
+            assert np.array_equal(om.get_state()["chains"], b.get_state(i)["chains"]), i
+
+
 def test_lists_built_beside_the_sweep():
     # after a sweep the next run of steps starts from lists rebuilt beside the sweep (second
     # stream); with profiling on they are rebuilt at the start of the run instead.  The lists
