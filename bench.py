@@ -934,6 +934,9 @@ def main():
         "md_only_monomer_steps_per_s": mixed["md_only_monomer_steps_per_s"],
         "time_split_s": {"md": round(mixed["md_s"], 4), "db": round(mixed["db_s"], 4)},
         "rebuild_ms_per_md_step": mixed.get("finalize_kernel_ms"),
+        "autotuner": {"K": mixed["nl"]["K"], "tile_shape": mixed["lds_stage"]["tile_shape"],
+                      "ms_per_step_by_K_with_its_best_shape": mixed["tune_ms"],
+                      "tried": "K in {1, 2, 5} x up to 3 tile shapes per K"},
     }
     if fp64:
         line["fp64_path"] = {"value": fp64["monomer_steps_per_s"], "ms_per_step": fp64["ms_per_step"],

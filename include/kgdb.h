@@ -222,11 +222,13 @@ int kgdb_db_sweep_checked(kgdb_batch* b, int64_t n_attempts, kgdb_db_stats* stat
 int kgdb_profile(kgdb_batch* b, int32_t enable);
 int kgdb_profile_read(kgdb_batch* b, double* force_ms, int64_t* force_n, double* fin_ms, int64_t* fin_n);
 /* Autotuner of the production step: the neighbour-list rebuild interval K (1, 2 or 5 steps;
-   the skin follows K).  nl_every > 0 sets it; nl_every == 0 times each usable K over `reps`
-   steps (<= 0: 20) on the current state with HIP events, keeps the fastest, and restores the
-   state.  *chosen (may be NULL) receives K (0: the box is too small for lists and steps run
-   on the r_c cell grid); ms_per_variant (may be NULL, 3 entries) the mean time per step of
-   K = 1, 2, 5 (0 when unusable). */
+   the skin, and with it the list-grid cell size, follows K) and the list tiles' shape (up to
+   three candidates per K, kgdb_tile_shapes).  nl_every > 0 sets K; nl_every == 0 times every
+   usable K with each of its shapes over `reps` steps (<= 0: 20) on the current state with HIP
+   events, keeps the fastest shape for each K and the fastest K, and restores the state.
+   *chosen (may be NULL) receives K (0: the box is too small for lists and steps run on the r_c
+   cell grid); ms_per_variant (may be NULL, 3 entries) the mean time per step of K = 1, 2, 5
+   with its best shape (0 when unusable). */
 int kgdb_autotune(kgdb_batch* b, int32_t nl_every, int32_t reps, int32_t* chosen, double* ms_per_variant);
 /* neighbour lists: out = {K, skin, mean list length, rollbacks so far} */
 int kgdb_nl_info(kgdb_batch* b, double out[4]);
@@ -234,8 +236,18 @@ int kgdb_nl_info(kgdb_batch* b, double out[4]);
    {rebuild tiles whose neighbourhood exceeded the LDS stage and was read from global memory,
    so far; the largest neighbourhood (members) seen; the stage capacity at the current K; its
    upper limit; staged members summed over the tiles at the last stage record; tiles at the
-   current K}.  After a pass in which a tile overflowed, the capacity grows (up to the limit). */
-int kgdb_nl_stats(kgdb_batch* b, int64_t out[6]);
+   current K; nl_S and nl_Sy of melt 0's tiles}.  After a pass in which a tile overflowed, the
+   capacity grows (up to the limit). */
+int kgdb_nl_stats(kgdb_batch* b, int64_t out[8]);
+/* List tiles (the workgroups of the MD step and the list rebuild): nl_S x nl_Sy cells of one
+   z-plane of the list grid.  kgdb_tile_shapes: out = the (S, Sy) pairs that the autotuner tries
+   for melt 0 at the current rebuild interval, cheapest first by a cost model (0 where fewer).
+   kgdb_set_tiles: give every melt tiles of S x Sy cells at the current interval (an error if
+   that is not a shape of some melt's grid: S and Sy must tile it with a remainder tile, and the
+   stage must fit the LDS).  The next run of steps starts with a rebuild.  Results do not depend
+   on the shape (each monomer's list holds its neighbours in the same order), only speed does. */
+int kgdb_tile_shapes(const kgdb_batch* b, int32_t out[6]);
+int kgdb_set_tiles(kgdb_batch* b, int32_t S, int32_t Sy);
 /* Bond-steps of melt `melt` (since init; each bond counted once per closing kick of an MD
    step on the neighbour-list path) whose FENE argument a = 1 - r^2/R0^2 fell below
    fene_floor, i.e. where the floored continuation of Eqs. 3/10 replaced the log. */

@@ -187,11 +187,22 @@ class Batch:
     def nl_stats(self):
         """LDS stages of the list tiles: tiles read from global memory so far, largest stage,
         current capacity, capacity limit."""
-        out = np.zeros(6, np.int64)
+        out = np.zeros(8, np.int64)
         check(load().kgdb_nl_stats(self._h, ptr(out)))
         nm, _ = self.sizes()
         return dict(stage_overflows=int(out[0]), largest_stage=int(out[1]), stage_cap=int(out[2]),
-                    stage_cap_max=int(out[3]), staged_per_monomer=float(out[4]) / max(nm, 1), tiles=int(out[5]))
+                    stage_cap_max=int(out[3]), staged_per_monomer=float(out[4]) / max(nm, 1), tiles=int(out[5]),
+                    tile_shape=(int(out[6]), int(out[7])))
+
+    def tile_shapes(self):
+        """Candidate (S, Sy) list-tile shapes of melt 0 at the current rebuild interval."""
+        out = np.zeros(6, np.int32)
+        check(load().kgdb_tile_shapes(self._h, ptr(out)))
+        return [(int(out[2 * c]), int(out[2 * c + 1])) for c in range(3) if out[2 * c] > 0]
+
+    def set_tiles(self, S, Sy):
+        """List tiles of S x Sy cells at the current rebuild interval (results unchanged)."""
+        check(load().kgdb_set_tiles(self._h, int(S), int(Sy)))
 
     def fene_floored(self, melt=0):
         """Bond-steps of melt `melt` on the floored FENE continuation (argument below fene_floor)."""

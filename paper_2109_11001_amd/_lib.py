@@ -72,7 +72,7 @@ EXPORTS = [
     "kgdb_mlp_workspace_bytes", "kgdb_mlp_forward", "kgdb_mlp_grad", "kgdb_mlp_adam", "kgdb_mlp_train_step",
     "kgdb_set_potential", "kgdb_protocol_schedule", "kgdb_run_protocol", "kgdb_init_info",
     "kgdb_pair_correlation", "kgdb_structure_factor", "kgdb_msd_reset", "kgdb_msd",
-    "kgdb_mlp_train_step_static", "kgdb_fene_floored", "kgdb_nl_stats",
+    "kgdb_mlp_train_step_static", "kgdb_fene_floored", "kgdb_nl_stats", "kgdb_tile_shapes", "kgdb_set_tiles",
 ]
 MLP_STATIC_ROWS = 4096
 MLP_NPARAM = 36481
@@ -118,6 +118,8 @@ def load():
     L.kgdb_nl_info.argtypes = [P, P]
     L.kgdb_fene_floored.argtypes = [P, i32, P]
     L.kgdb_nl_stats.argtypes = [P, P]
+    L.kgdb_tile_shapes.argtypes = [P, P]
+    L.kgdb_set_tiles.argtypes = [P, i32, i32]
     L.kgdb_mlp_nparam.argtypes = []
     L.kgdb_set_proposal_net.argtypes = [P, P, i32, dbl]
     L.kgdb_db_sweep_log.argtypes = [P, i64, P, P, P, i64, P]

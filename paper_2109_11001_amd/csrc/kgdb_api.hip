@@ -38,6 +38,8 @@ constexpr int GCHUNK = 100;      // steps per captured graph (even: the buffer p
 constexpr int PROF_EVENTS = 256; // event pairs per profiling batch
 }  // namespace
 
+struct TileShape { int S, Sy; };  // list-grid tile: nl_S x nl_Sy cells
+
 struct kgdb_batch {
   int nm = 0;
   std::vector<kgdb_params> P;
@@ -84,6 +86,10 @@ struct kgdb_batch {
   int nl_ki = 2;                   // its index in NL_KS
   std::vector<MeltDesc> Dk[3];     // descriptors for each rebuild interval of NL_KS
   BlockMap rm[3];                  // list-grid tiles for each K
+  int* d_rmap[3] = {nullptr, nullptr, nullptr};  // their (melt, local tile) arrays, room for any candidate shape
+  int rmap_cap[3] = {0, 0, 0};
+  static constexpr int NSHAPE = 3;  // tile shapes the autotuner tries for each K
+  std::vector<std::vector<TileShape>> shapes[3];  // [K][melt]: candidate shapes, cheapest first
   int stage_cap[3] = {0, 0, 0};    // LDS-staged members per tile for each K
   int* d_cntl = nullptr;           // binning: count per sorted list-grid cell
   int* d_tcnt = nullptr;           // binning: count per tile
@@ -228,6 +234,51 @@ static double nl_skin_for(const kgdb_params& p, int K, double nm_total) {
   return p.nl_skin > 0 ? p.nl_skin : 2.0 * nl_skin_sigmas(nm_total) * K * p.dt * std::sqrt(p.T > 0 ? p.T : 1.0);
 }
 
+// Tiles of nl_S x nl_Sy cells, ranked by a model of their cost per home monomer.  A workgroup
+// stages 3 (nl_S + 2)(nl_Sy + 2) cells and updates its home monomers in rounds of NLB_THREADS
+// lanes (a round costs the same whether or not every lane holds a monomer); the last tile of a
+// row (column) takes the remainder, and no tile is empty.  The stage must fit the LDS cap with
+// room for fluctuations.  out receives up to nmax shapes, cheapest first.
+static void tile_shapes(const MeltDesc& d, int precision, int nmax, std::vector<TileShape>& out) {
+  const double occ = (double)d.Nm / ((double)d.ncl * d.ncl * d.ncl);
+  const int cap = precision == KGDB_PREC_MIXED ? STAGE_CAP_MAX : STAGE_CAP_MAX_FP64;
+  std::vector<std::pair<double, TileShape>> all;
+  for (int Sy = 1; Sy <= std::min(d.ncl, 64); ++Sy) {
+    const int nyb = (d.ncl + Sy - 1) / Sy, Sye = (d.ncl + nyb - 1) / nyb;
+    if (Sye != Sy) continue;
+    for (int S = 1; S <= std::min(d.ncl, 64); ++S) {
+      const int nseg = (d.ncl + S - 1) / S, Se = (d.ncl + nseg - 1) / nseg;
+      if (Se != S || (S + 2) * (Sy + 2) > 198) continue;
+      const double homes = S * Sy * occ, stage = 3.0 * (S + 2) * (Sy + 2) * occ;
+      if (1.5 * stage + 64 > cap && !(S == 1 && Sy == 1)) continue;
+      // (a tile's count fluctuates by about sqrt(homes / 4) in a melt: two of those in hand)
+      const double rounds = std::ceil((homes + std::sqrt(homes) + 2.0) / NLB_THREADS);
+      const double cost = (3000.0 + 40.0 * stage + 2500.0 * NLB_THREADS * rounds) / std::max(homes, 1e-9);
+      all.push_back({cost, TileShape{S, Sy}});
+    }
+  }
+  std::stable_sort(all.begin(), all.end(), [](const auto& x, const auto& y) { return x.first < y.first; });
+  out.clear();
+  for (size_t i = 0; i < all.size() && (int)out.size() < nmax; ++i) out.push_back(all[i].second);
+  if (out.empty()) out.push_back(TileShape{1, 1});
+}
+static void set_tile_shape(MeltDesc& d, TileShape t) {
+  d.nl_S = t.S;
+  d.nl_nseg = (d.ncl + t.S - 1) / t.S;
+  d.nl_Sy = t.Sy;
+  d.nl_nyb = (d.ncl + t.Sy - 1) / t.Sy;
+}
+// whether (S, Sy) is a tile shape of melt d's list grid whose stage fits the LDS
+static bool tile_shape_ok(const MeltDesc& d, int precision, TileShape t) {
+  if (t.S < 1 || t.Sy < 1 || t.S > std::min(d.ncl, 64) || t.Sy > std::min(d.ncl, 64)) return false;
+  if ((t.S + 2) * (t.Sy + 2) > 198) return false;
+  const int nseg = (d.ncl + t.S - 1) / t.S, nyb = (d.ncl + t.Sy - 1) / t.Sy;
+  if ((d.ncl + nseg - 1) / nseg != t.S || (d.ncl + nyb - 1) / nyb != t.Sy) return false;
+  const double occ = (double)d.Nm / ((double)d.ncl * d.ncl * d.ncl);
+  const int cap = precision == KGDB_PREC_MIXED ? STAGE_CAP_MAX : STAGE_CAP_MAX_FP64;
+  return 1.5 * 3.0 * (t.S + 2) * (t.Sy + 2) * occ + 64 <= cap;
+}
+
 static void set_list_geometry(MeltDesc& d, const kgdb_params& p, int K, double nm_total) {
   const double rc = std::pow(2.0, 1.0 / 6.0);
   const double skin = nl_skin_for(p, K, nm_total);
@@ -241,33 +292,9 @@ static void set_list_geometry(MeltDesc& d, const kgdb_params& p, int K, double n
   d.rlist2 = rl * rl;
   d.half_skin2 = 0.25 * skin * skin;
   d.half_skin = 0.5 * skin;
-  // Tiles of nl_S x nl_Sy cells: the shape with the least modelled cost per home monomer.  A
-  // workgroup stages 3 (nl_S + 2)(nl_Sy + 2) cells and updates its home monomers in rounds of
-  // NLB_THREADS lanes (a round costs the same whether or not every lane holds a monomer); the
-  // last tile of a row (column) takes the remainder, and no tile is empty.  The stage must
-  // fit the LDS cap with room for fluctuations.
-  const double occ = (double)d.Nm / ((double)d.ncl * d.ncl * d.ncl);
-  const int cap = p.precision == KGDB_PREC_MIXED ? STAGE_CAP_MAX : STAGE_CAP_MAX_FP64;
-  double best = 1e300;
-  int bS = 1, bSy = 1;
-  for (int Sy = 1; Sy <= std::min(d.ncl, 64); ++Sy) {
-    const int nyb = (d.ncl + Sy - 1) / Sy, Sye = (d.ncl + nyb - 1) / nyb;
-    if (Sye != Sy) continue;
-    for (int S = 1; S <= std::min(d.ncl, 64); ++S) {
-      const int nseg = (d.ncl + S - 1) / S, Se = (d.ncl + nseg - 1) / nseg;
-      if (Se != S || (S + 2) * (Sy + 2) > 198) continue;
-      const double homes = S * Sy * occ, stage = 3.0 * (S + 2) * (Sy + 2) * occ;
-      if (1.5 * stage + 64 > cap && !(S == 1 && Sy == 1)) continue;
-      // (a tile's count fluctuates by about sqrt(homes / 4) in a melt: two of those in hand)
-      const double rounds = std::ceil((homes + std::sqrt(homes) + 2.0) / NLB_THREADS);
-      const double cost = (3000.0 + 40.0 * stage + 2500.0 * NLB_THREADS * rounds) / std::max(homes, 1e-9);
-      if (cost < best) { best = cost; bS = S; bSy = Sy; }
-    }
-  }
-  d.nl_S = bS;
-  d.nl_nseg = (d.ncl + bS - 1) / bS;
-  d.nl_Sy = bSy;
-  d.nl_nyb = (d.ncl + bSy - 1) / bSy;
+  std::vector<TileShape> sh;
+  tile_shapes(d, p.precision, 1, sh);
+  set_tile_shape(d, sh[0]);
 }
 
 static MeltDesc make_desc(const kgdb_params& p) {
@@ -653,7 +680,38 @@ static int set_nl_interval(kgdb_batch* b, int ki) {
   return 0;
 }
 
+static int stage_cap_for(const kgdb_batch* b, int q);
+static int write_tile_map(kgdb_batch* b, int q);
 static int run_steps_cells(kgdb_batch* b, int64_t n, bool graph);
+
+// Give interval q's tiles the shapes t[k] (one per melt): tile offsets, the tile map and the
+// stage capacity follow; captured runs of steps of q are dropped, and when q is in use the next
+// run of steps starts with a rebuild.  The slot order (cells grouped by tile) changes with the
+// shape, the results do not: lists hold each monomer's neighbours in the same order (by cell
+// offset, then monomer id) whatever the tile.
+static int apply_tiles(kgdb_batch* b, int q, const std::vector<TileShape>& t) {
+  int64_t toff = 0;
+  for (int k = 0; k < b->nm; ++k) {
+    MeltDesc& d = b->Dk[q][k];
+    set_tile_shape(d, t[k]);
+    d.tile_off = (int)toff;
+    toff += (int64_t)d.ncl * d.nl_nyb * d.nl_nseg;
+  }
+  if (toff > b->rmap_cap[q] || toff > b->NTILE) return fail(KGDB_E_PARAM, "tile shape needs more tiles than allocated");
+  b->ntile[q] = (int)toff;
+  b->stage_cap[q] = stage_cap_for(b, q);
+  CHK(write_tile_map(b, q));
+  for (auto& a2 : b->ngexec[q])
+    for (auto& ge : a2)
+      if (ge) { HIPCHK(hipGraphExecDestroy(ge)); ge = nullptr; }
+  if (q == b->nl_ki) CHK(set_nl_interval(b, q));
+  return 0;
+}
+static std::vector<TileShape> current_tiles(const kgdb_batch* b, int q) {
+  std::vector<TileShape> t;
+  for (const MeltDesc& d : b->Dk[q]) t.push_back(TileShape{d.nl_S, d.nl_Sy});
+  return t;
+}
 
 // A tile whose stage outgrew the LDS capacity was staged from global memory (correct, but far
 // slower): raise the capacity of the current interval for the passes that follow, up to the
@@ -793,6 +851,42 @@ void kgdb_destroy(kgdb_batch* b) {
   delete b;
 }
 
+// LDS stage of a tile: 1.5 x the largest mean neighbourhood of a tile + 64 (density
+// fluctuations of a melt that is still relaxing from its start are large), at most 2688
+// members (mixed) or 1792 (FP64), which keeps the step's and the rebuild's LDS within 64 KB;
+// a tile whose neighbourhood does not fit reads it from global memory instead, far slower
+static int stage_cap_for(const kgdb_batch* b, int q) {
+  double mx = 0.0;
+  for (int k = 0; k < b->nm; ++k) {
+    const MeltDesc& d = b->Dk[q][k];
+    const double occ = (double)d.Nm / ((double)d.ncl * d.ncl * d.ncl);
+    mx = std::max(mx, 3.0 * (d.nl_S + 2) * (d.nl_Sy + 2) * occ);
+    if (d.test_flags & TF_NL_GLOBAL) return 0;
+  }
+  return std::min(b->prec ? STAGE_CAP_MAX : STAGE_CAP_MAX_FP64, ((int)(1.5 * mx) + 64 + 63) / 64 * 64);
+}
+
+// (melt, local tile) of every list-grid tile of interval q, in the current shapes
+static int write_tile_map(kgdb_batch* b, int q) {
+  std::vector<int> melt, base;
+  for (int k = 0; k < b->nm; ++k) {
+    const MeltDesc& d = b->Dk[q][k];
+    const int n = d.ncl * d.nl_nyb * d.nl_nseg;
+    for (int i = 0; i < n; ++i) { melt.push_back(k); base.push_back(i); }
+  }
+  const int nt = (int)melt.size();
+  if (nt > b->rmap_cap[q]) return fail(KGDB_E_PARAM, "tile map too small");
+  std::vector<int> all(melt);
+  all.resize((size_t)b->rmap_cap[q], 0);
+  all.insert(all.end(), base.begin(), base.end());
+  HIPCHK(hipMemcpyAsync(b->d_rmap[q], all.data(), all.size() * sizeof(int), hipMemcpyHostToDevice, b->s));
+  HIPCHK(hipStreamSynchronize(b->s));
+  b->rm[q].melt = b->d_rmap[q];
+  b->rm[q].base = b->d_rmap[q] + b->rmap_cap[q];
+  b->rm[q].nblk = nt;
+  return 0;
+}
+
 static int build_block_maps(kgdb_batch* b) {
   // per melt: blocks of `per` items; each map is (melt index, first local item) per block
   std::vector<int> all;
@@ -810,24 +904,17 @@ static int build_block_maps(kgdb_batch* b) {
   add_map(256, false);
   add_map(256 / FIN_LANES, true);
   for (int G : {1, 2, 4, 8}) add_map(256 / G, false);
-  for (int q = 0; q < 3; ++q) {  // list-grid tiles for each rebuild interval
-    std::vector<int> melt, base;
-    for (int k = 0; k < b->nm; ++k) {
-      const MeltDesc& d = b->Dk[q][k];
-      const int n = d.ncl * d.nl_nyb * d.nl_nseg;
-      for (int i = 0; i < n; ++i) { melt.push_back(k); base.push_back(i); }
-    }
-    spans.push_back({all.size(), melt.size()});
-    all.insert(all.end(), melt.begin(), melt.end());
-    all.insert(all.end(), base.begin(), base.end());
-  }
   CHK(dalloc(b, &b->d_blk, all.size()));
   HIPCHK(hipMemcpy(b->d_blk, all.data(), all.size() * sizeof(int), hipMemcpyHostToDevice));
-  BlockMap* maps[9] = {&b->pm, &b->cm, &b->fm[0], &b->fm[1], &b->fm[2], &b->fm[3], &b->rm[0], &b->rm[1], &b->rm[2]};
-  for (int m = 0; m < 9; ++m) {
+  BlockMap* maps[6] = {&b->pm, &b->cm, &b->fm[0], &b->fm[1], &b->fm[2], &b->fm[3]};
+  for (int m = 0; m < 6; ++m) {
     maps[m]->melt = b->d_blk + spans[m].first;
     maps[m]->base = b->d_blk + spans[m].first + spans[m].second;
     maps[m]->nblk = (int)spans[m].second;
+  }
+  for (int q = 0; q < 3; ++q) {  // list-grid tiles for each rebuild interval
+    CHK(dalloc(b, &b->d_rmap[q], 2 * (size_t)std::max(b->rmap_cap[q], 1)));
+    CHK(write_tile_map(b, q));
   }
   return 0;
 }
@@ -1003,17 +1090,26 @@ static int init_impl(const kgdb_params* params, int32_t count, void* stream, kgd
       b->Dk[q] = b->D;
       int64_t off = 0, toff = 0;
       usable[q] = true;
+      b->shapes[q].assign(count, {});
+      std::vector<int64_t> tiles_c(kgdb_batch::NSHAPE, 0);
       for (int k = 0; k < count; ++k) {
         MeltDesc& d = b->Dk[q][k];
         set_list_geometry(d, params[k], NL_KS[q], (double)NP);
+        tile_shapes(d, params[k].precision, kgdb_batch::NSHAPE, b->shapes[q][k]);
         d.celll_off = (int)off;
         d.tile_off = (int)toff;
         off += (int64_t)d.ncl * d.ncl * d.ncl;
         toff += (int64_t)d.ncl * d.nl_nyb * d.nl_nseg;
+        for (int c = 0; c < kgdb_batch::NSHAPE; ++c) {
+          const TileShape t = b->shapes[q][k][std::min<size_t>(c, b->shapes[q][k].size() - 1)];
+          tiles_c[c] += (int64_t)d.ncl * ((d.ncl + t.Sy - 1) / t.Sy) * ((d.ncl + t.S - 1) / t.S);
+        }
         if (d.ncl < 3 || d.ncl > 1023) usable[q] = false;
       }
       ncl_max = std::max(ncl_max, off);
       nt_max = std::max(nt_max, toff);
+      for (int64_t t : tiles_c) nt_max = std::max(nt_max, t);
+      b->rmap_cap[q] = (int)*std::max_element(tiles_c.begin(), tiles_c.end());
       b->ntile[q] = (int)toff;
     }
     if (ncl_max * NL_CELL_CAP >= (1ll << 31)) { delete b; return fail(KGDB_E_PARAM, "list grid too large"); }
@@ -1021,17 +1117,7 @@ static int init_impl(const kgdb_params* params, int32_t count, void* stream, kgd
     // fluctuations of a melt that is still relaxing from its start are large), at most 2688
     // members (mixed) or 1792 (FP64), which keeps the step's and the rebuild's LDS within 64 KB;
     // a tile whose neighbourhood does not fit reads it from global memory instead, far slower
-    for (int q = 0; q < 3; ++q) {
-      double mx = 0.0;
-      for (int k = 0; k < count; ++k) {
-        const MeltDesc& d = b->Dk[q][k];
-        const double occ = (double)d.Nm / ((double)d.ncl * d.ncl * d.ncl);
-        mx = std::max(mx, 3.0 * (d.nl_S + 2) * (d.nl_Sy + 2) * occ);
-      }
-      b->stage_cap[q] = std::min(b->prec ? STAGE_CAP_MAX : STAGE_CAP_MAX_FP64, ((int)(1.5 * mx) + 64 + 63) / 64 * 64);
-      for (int k = 0; k < count; ++k)
-        if (params[k].test_flags & TF_NL_GLOBAL) b->stage_cap[q] = 0;
-    }
+    for (int q = 0; q < 3; ++q) b->stage_cap[q] = stage_cap_for(b, q);
     b->NCL = (int)ncl_max;
     b->NTILE = (int)nt_max;
     int want = params[0].nl_every;
@@ -1093,7 +1179,7 @@ static int init_impl(const kgdb_params* params, int32_t count, void* stream, kgd
   step(dalloc(b, &b->d_cellsc, (size_t)b->NCL));
   b->stage_cap_max = b->prec ? STAGE_CAP_MAX : STAGE_CAP_MAX_FP64;
   for (int q = 0; q < 3; ++q)
-    b->stage_words = std::max(b->stage_words, (size_t)b->ntile[q] * (size_t)(b->stage_cap[q] > 0 ? b->stage_cap_max : 0));
+    b->stage_words = std::max(b->stage_words, (size_t)b->rmap_cap[q] * (size_t)(b->stage_cap[q] > 0 ? b->stage_cap_max : 0));
   step(dalloc(b, &b->d_nlstat, 2));
   step(dalloc(b, &b->d_stage, std::max<size_t>(b->stage_words, 1)));
   step(dalloc(b, &b->d_smeta, (size_t)b->NTILE));
@@ -1796,25 +1882,43 @@ int kgdb_autotune(kgdb_batch* b, int32_t nl_every, int32_t reps, int32_t* chosen
   CHK(copy_state(b, false, sx, si, sst));
   double best = INFINITY;
   int best_q = b->nl_ki, rc = 0;
+  // every usable interval K with each of its candidate tile shapes; per K the fastest shape
+  // stays, then the fastest K is kept
   for (int q = 0; q < 3 && !rc; ++q) {
     if (ms_per_variant) ms_per_variant[q] = 0;
     if (!usable(q)) continue;
-    rc = set_nl_interval(b, q);
-    if (rc) break;
-    b->nl_ki_target = q;
-    b->nl_clean = 0;
-    b->prof = true;
-    b->prof_force_ms = b->prof_fin_ms = 0;
-    b->prof_force_n = b->prof_fin_n = 0;
-    rc = run_steps(b, reps, false);
-    b->prof = was_prof;
-    const double ms = b->prof_force_n ? (b->prof_force_ms + b->prof_fin_ms) / b->prof_force_n : INFINITY;
-    if (ms_per_variant) ms_per_variant[q] = ms;
-    if (!rc && b->nl_ki == q && ms < best) { best = ms; best_q = q; }  // a rollback disqualifies
-    if (!rc) rc = copy_state(b, true, sx, si, sst);
-    b->step = was_step;
-    b->cells_valid = false;
-    b->fc_valid = was_fc;
+    double best_c = INFINITY;
+    std::vector<TileShape> keep = current_tiles(b, q);
+    for (int c = 0; c < kgdb_batch::NSHAPE && !rc; ++c) {
+      std::vector<TileShape> t;
+      bool fresh = true;
+      for (int k = 0; k < b->nm; ++k) {
+        const auto& v = b->shapes[q][k];
+        if ((size_t)c >= v.size()) fresh = false;
+        else t.push_back(v[c]);
+      }
+      if (!fresh) continue;
+      rc = apply_tiles(b, q, t);
+      if (!rc) rc = set_nl_interval(b, q);
+      if (rc) break;
+      b->nl_ki_target = q;
+      b->nl_clean = 0;
+      b->prof = true;
+      b->prof_force_ms = b->prof_fin_ms = 0;
+      b->prof_force_n = b->prof_fin_n = 0;
+      rc = run_steps(b, reps, false);
+      b->prof = was_prof;
+      const double ms = b->prof_force_n ? (b->prof_force_ms + b->prof_fin_ms) / b->prof_force_n : INFINITY;
+      const bool clean = !rc && b->nl_ki == q;  // a rollback disqualifies
+      if (clean && ms < best_c) { best_c = ms; keep = t; }
+      if (!rc) rc = copy_state(b, true, sx, si, sst);
+      b->step = was_step;
+      b->cells_valid = false;
+      b->fc_valid = was_fc;
+    }
+    if (!rc) rc = apply_tiles(b, q, keep);
+    if (ms_per_variant) ms_per_variant[q] = best_c;
+    if (!rc && best_c < best) { best = best_c; best_q = q; }
   }
   (void)hipStreamSynchronize(b->s);
   (void)hipFree(sx);
@@ -1831,13 +1935,48 @@ int kgdb_autotune(kgdb_batch* b, int32_t nl_every, int32_t reps, int32_t* chosen
   return rc;
 }
 
-int kgdb_nl_stats(kgdb_batch* b, int64_t out[6]) {
+int kgdb_tile_shapes(const kgdb_batch* b, int32_t out[6]) {
+  if (!b || !out) return fail(KGDB_E_PARAM, "bad arguments");
+  for (int i = 0; i < 6; ++i) out[i] = 0;
+  if (b->nl_ki < 0) return 0;
+  const auto& v = b->shapes[b->nl_ki][0];
+  for (size_t c = 0; c < v.size() && c < 3; ++c) { out[2 * c] = v[c].S; out[2 * c + 1] = v[c].Sy; }
+  return 0;
+}
+
+int kgdb_set_tiles(kgdb_batch* b, int32_t S, int32_t Sy) {
+  if (!b) return fail(KGDB_E_PARAM, "bad handle");
+  if (b->nl_ki < 0) return fail(KGDB_E_PARAM, "the box is too small for list tiles");
+  std::vector<TileShape> t;
+  for (int k = 0; k < b->nm; ++k) {
+    const TileShape s{S, Sy};
+    if (!tile_shape_ok(b->Dk[b->nl_ki][k], b->P[k].precision, s))
+      return fail(KGDB_E_PARAM, "not a tile shape of this list grid (or its stage exceeds the LDS)");
+    t.push_back(s);
+  }
+  const int nt = [&] {
+    int64_t n = 0;
+    for (int k = 0; k < b->nm; ++k) {
+      const MeltDesc& d = b->Dk[b->nl_ki][k];
+      n += (int64_t)d.ncl * ((d.ncl + Sy - 1) / Sy) * ((d.ncl + S - 1) / S);
+    }
+    return (int)std::min<int64_t>(n, 1ll << 30);
+  }();
+  if (nt > b->rmap_cap[b->nl_ki]) return fail(KGDB_E_PARAM, "tile shape needs more tiles than allocated");
+  CHK(apply_tiles(b, b->nl_ki, t));
+  b->xver++;
+  return 0;
+}
+
+int kgdb_nl_stats(kgdb_batch* b, int64_t out[8]) {
   if (!b || !out) return fail(KGDB_E_PARAM, "bad arguments");
   out[0] = b->nl_stage_over;
   out[1] = b->nl_stage_seen;
   out[2] = b->nl_ki >= 0 ? b->stage_cap[b->nl_ki] : 0;
   out[3] = b->stage_cap_max;
   out[4] = out[5] = 0;
+  out[6] = b->nl_ki >= 0 ? b->Dk[b->nl_ki][0].nl_S : 0;
+  out[7] = b->nl_ki >= 0 ? b->Dk[b->nl_ki][0].nl_Sy : 0;
   if (b->nl_ki >= 0) {
     const int nt = b->ntile[b->nl_ki];
     std::vector<int4> meta((size_t)nt);

@@ -458,6 +458,46 @@ def test_db_sweep_long_and_short_lists_in_one_batch():
             assert np.array_equal(om.get_state()["chains"], b.get_state(i)["chains"]), i
 
 
+@pytest.mark.parametrize("prec", [1, 0])
+def test_tile_shape_leaves_the_trajectory_unchanged(prec):
+    # The autotuner's candidate tile shapes regroup the slots but keep each monomer's list in
+    # the same order (by cell offset, then monomer id).  Mixed path: a staged position is its
+    # fixed-point offset from its reference cell plus whole cells, so every pair displacement is
+    # the same integer whatever the tile, and runs of steps with a sweep between them end in the
+    # same positions, velocities and topology bit for bit.  Plain FP64 path: the frame shift is
+    # a rounded FP64 addition, so shapes agree to rounding only.
+    kw = dict(M=100, N=200, seed=5, kappa=2.0, warmup_steps=200, nl_every=5, precision=prec)
+    ref = kg.Melt(**kw)
+    shapes = ref.tile_shapes()
+    assert len(shapes) >= 2, shapes
+    assert ref.nl_stats()["tile_shape"] == shapes[0]
+    runs = []
+    for S, Sy in shapes[1:]:
+        m = kg.Melt(**kw)
+        m.set_tiles(S, Sy)
+        assert m.nl_stats()["tile_shape"] == (S, Sy)
+        runs.append(m)
+    for m in [ref] + runs:
+        m.md_steps(150)
+        m.db_sweep(60)
+        m.md_steps(55)
+    s0 = ref.get_state()
+    L = ref.geom[0]["L"]
+    for m in runs:
+        s1 = m.get_state()
+        if prec == 1:
+            for f in ("x", "v", "fl", "fc", "chains"):
+                assert np.array_equal(s0[f], s1[f]), (m.nl_stats()["tile_shape"], f)
+        else:
+            assert np.array_equal(s0["chains"], s1["chains"])
+            d = s0["x"] - s1["x"]
+            d -= np.rint(d / L) * L
+            assert np.max(np.abs(d)) < 1e-8
+            assert np.max(np.abs(s0["v"] - s1["v"])) < 1e-7
+    with pytest.raises(kg.KgdbError):
+        ref.set_tiles(1000, 1)
+
+
 def test_lists_built_beside_the_sweep():
     # after a sweep the next run of steps starts from lists rebuilt beside the sweep (second
     # stream); with profiling on they are rebuilt at the start of the run instead.  The lists
