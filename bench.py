@@ -379,8 +379,11 @@ def run_equilibration(kg, stream, steps, ref_steps, every=1000, tol=0.02, batch_
             samples.append(np.mean([b.observables(i)[0] for i in range(melts)], axis=0))
             times.append(s)
             walls.append(time.perf_counter() - t0)
+        floored = sum(b.fene_floored(i) for i in range(melts))
+        bond_steps = sum(b.counters(i)[0] for i in range(melts)) * EQ_SYSTEM["M"] * (EQ_SYSTEM["N"] - 1)
         b.close()
-        return dict(times=times, walls=walls, samples=samples, accepted=acc, attempts=att, melts=melts)
+        return dict(times=times, walls=walls, samples=samples, accepted=acc, attempts=att, melts=melts,
+                    floored=floored / max(bond_steps, 1))
 
     out = {"system": f"{EQ_SYSTEM['M']} chains x {EQ_SYSTEM['N']} beads, kappa {EQ_SYSTEM['kappa']}, n 2, "
                      "rho 0.85, dt 0.01, gamma 1", "tolerance": tol, "reading_every_steps": every,
@@ -411,7 +414,8 @@ def run_equilibration(kg, stream, steps, ref_steps, every=1000, tol=0.02, batch_
             "tau_to_tol": r["times"][k] * WORKLOAD["dt"] if k is not None else None,
             "wall_s_to_tol": round(r["walls"][k], 3) if k is not None else None,
             "max_dev_end": round(dev[-1], 5), "max_dev_start": round(dev[0], 4),
-            "accepted": r["accepted"], "accept_rate": r["accepted"] / max(r["attempts"], 1)}
+            "accepted": r["accepted"], "accept_rate": r["accepted"] / max(r["attempts"], 1),
+            "fene_floored_per_bond_step": r["floored"]}
     return out
 
 
@@ -652,6 +656,7 @@ def run_protocol_bench(kg, stream, kappa, steps_per_stage, sweep_every=100):
     tail = b.run_protocol([plan["n"][-1]], [10 * (steps_per_stage if not full else 1000)], sweep_every=sweep_every)[0]
     s12 = tail["accepted"] / max(tail["attempts"] - tail["no_candidate"], 1)
     nm, _ = b.sizes()
+    floored = b.fene_floored() / max(1, b.counters()[0] * PAPER_SYSTEM["M"] * (PAPER_SYSTEM["N"] - 1))
     b.close()
     stages, proj = [], 0.0
     for i, s_ in enumerate(st):
@@ -682,6 +687,7 @@ def run_protocol_bench(kg, stream, kappa, steps_per_stage, sweep_every=100):
             "plan": {"steps_total": int(sum(plan["steps"])), "tau_eq": plan["tau_eq"], "scheme": plan["scheme"]},
             "steps_per_stage_timed": steps_per_stage, "sweep_every": sweep_every, "setup_s": round(setup_s, 2),
             "stages": stages, "projected_full_protocol_s": round(proj, 1), "structure": structure,
+            "fene_floored_per_bond_step": floored,
             "q_vectors": int(len(qv)), "g_r_ms": round(1e3 * float(np.median([t[0] for t in t_obs])), 2),
             "S_q_ms": round(1e3 * float(np.median([t[1] for t in t_obs])), 2)}
 
