@@ -69,6 +69,25 @@ void kgdbref_philox(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4
   out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
 }
 
+/* Philox4x32-10 (same paper): ten rounds of two 32x32->64 multiplies, the same word
+   permutation and key XOR, the key bumped by the 32-bit Weyl constants between rounds. */
+void kgdbref_philox4x32(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) {
+  const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+  const uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+  uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+  uint32_t k0 = key[0], k1 = key[1];
+  for (int r = 0; r < 10; r++) {
+    if (r > 0) { k0 += W0; k1 += W1; }
+    uint64_t p0 = (uint64_t)M0 * c0;
+    uint64_t p1 = (uint64_t)M1 * c2;
+    uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+    uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+    uint32_t n0 = hi1 ^ c1 ^ k0, n1 = lo1, n2 = hi0 ^ c3 ^ k1, n3 = lo0;
+    c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+  }
+  out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
 static void draw(uint64_t seed, uint64_t melt, uint64_t i_lo, uint64_t i_hi, uint64_t stream,
                  uint64_t out[4]) {
   uint64_t ctr[4] = {i_lo, i_hi, stream, 0};
@@ -95,6 +114,24 @@ void kgdbref_normals(uint64_t seed, uint64_t melt, uint64_t i_lo, uint64_t i_hi,
   draw(seed, melt, i_lo, i_hi, stream, w);
   box_muller(w[0], w[1], &z[0], &z[1]);
   box_muller(w[2], w[3], &z[2], &z[3]);
+}
+/* The noise of the MD kicks (the Langevin random force, and the warm-up's): one Philox4x32-10
+   draw per monomer i and step t, counter (i, t mod 2^32, t / 2^32, stream), key (seed mod 2^32,
+   seed / 2^32 xor (melt 0x9E3779B9 mod 2^32)); Box-Muller pairs from the 32-bit uniforms
+   u = (w + 1) 2^-32 in (0, 1] and v = w 2^-32 in [0, 1). */
+static void box_muller32(uint32_t a, uint32_t b, double *z0, double *z1) {
+  double rad = sqrt(-2.0 * log(((double)a + 1.0) * 0x1.0p-32));
+  double ph = 2.0 * M_PI * ((double)b * 0x1.0p-32);
+  *z0 = rad * cos(ph);
+  *z1 = rad * sin(ph);
+}
+void kgdbref_md_normals(uint64_t seed, uint64_t melt, uint64_t i, uint64_t t, uint64_t stream, double z[4]) {
+  const uint32_t ctr[4] = {(uint32_t)i, (uint32_t)t, (uint32_t)(t >> 32), (uint32_t)stream};
+  const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32) ^ ((uint32_t)melt * 0x9E3779B9u)};
+  uint32_t w[4];
+  kgdbref_philox4x32(ctr, key, w);
+  box_muller32(w[0], w[1], &z[0], &z[1]);
+  box_muller32(w[2], w[3], &z[2], &z[3]);
 }
 
 /* ------------------------------------------------------------------------------------ */
@@ -450,7 +487,7 @@ static int vv_step(melt_t *m, double dt, double cap, uint64_t noise_index, uint6
   double amp = sqrt(2.0 * m->p.gamma * m->p.T / dt);
   for (int i = 0; i < Nm; i++) {
     double z[4];
-    kgdbref_normals(m->p.seed, (uint64_t)m->p.melt_id, (uint64_t)i, noise_index, stream, z);
+    kgdbref_md_normals(m->p.seed, (uint64_t)m->p.melt_id, (uint64_t)i, noise_index, stream, z);
     for (int k = 0; k < 3; k++) {
       double vh = m->v[k * Nm + i];
       double fl = -m->p.gamma * vh + amp * z[k];

@@ -76,6 +76,9 @@ def lib():
         L.kgdbref_last_error.restype = C.c_char_p
         L.kgdbref_philox.argtypes = [up, up, up]
         L.kgdbref_normals.argtypes = [C.c_uint64] * 5 + [dp]
+        u32p = np.ctypeslib.ndpointer(np.uint32, flags="C")
+        L.kgdbref_philox4x32.argtypes = [u32p, u32p, u32p]
+        L.kgdbref_md_normals.argtypes = [C.c_uint64] * 5 + [dp]
         for f in ("kgdbref_mie",):
             getattr(L, f).restype = C.c_double
             getattr(L, f).argtypes = [C.c_double] * 3
@@ -152,6 +155,19 @@ def philox(ctr, key):
 def normals(seed, melt, i_lo, i_hi, stream):
     z = np.zeros(4)
     lib().kgdbref_normals(seed, melt, i_lo, i_hi, stream, z)
+    return z
+
+
+def philox4x32(ctr, key):
+    out = np.zeros(4, np.uint32)
+    lib().kgdbref_philox4x32(np.asarray(ctr, np.uint32), np.asarray(key, np.uint32), out)
+    return out
+
+
+def md_normals(seed, melt, i, t, stream):
+    """The four normals of the MD kick of monomer i at step t (Philox4x32-10)."""
+    z = np.zeros(4)
+    lib().kgdbref_md_normals(seed, melt, i, t, stream, z)
     return z
 
 

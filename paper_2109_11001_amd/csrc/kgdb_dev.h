@@ -120,21 +120,51 @@ __device__ __forceinline__ void gauss2(uint64_t a, uint64_t b, double& z0, doubl
   z0 = rad * cs;
   z1 = rad * sn;
 }
-// The same transform in FP32 for the mixed-precision path (FP32 forces): the hardware log2 and
-// sine / cosine (argument in revolutions, so 2 pi u needs no range reduction) on the same
-// 53-bit uniforms; |error| of a normal is a few 1e-7, far below the FP32 force rounding.
-__device__ __forceinline__ void gauss2_f32(uint64_t a, uint64_t b, double& z0, double& z1) {
-  const float u = (float)u01_open0(a);  // (0, 1]: log2 u >= -53
+// Philox4x32-10 (same paper) for the MD kicks' noise, which needs only four 32-bit words per
+// monomer and step: 32x32 multiplies are single instructions where the 64-bit rounds take
+// several.  Counter (monomer, step low, step high, stream), key (seed low, seed high xor
+// melt 0x9E3779B9).
+struct U32x4 { uint32_t w[4]; };
+
+__device__ __forceinline__ U32x4 philox4x32(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                            uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r) { k0 += 0x9E3779B9u; k1 += 0xBB67AE85u; }
+    const uint32_t hi0 = __umulhi(0xD2511F53u, c0), lo0 = 0xD2511F53u * c0;
+    const uint32_t hi1 = __umulhi(0xCD9E8D57u, c2), lo1 = 0xCD9E8D57u * c2;
+    const uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+    c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
+  }
+  U32x4 o; o.w[0] = c0; o.w[1] = c1; o.w[2] = c2; o.w[3] = c3;
+  return o;
+}
+
+__device__ __forceinline__ U32x4 md_noise_draw(const MeltDesc& d, uint64_t mono, uint64_t step, uint64_t stream) {
+  return philox4x32((uint32_t)mono, (uint32_t)step, (uint32_t)(step >> 32), (uint32_t)stream,
+                    (uint32_t)d.seed, (uint32_t)(d.seed >> 32) ^ ((uint32_t)d.melt_id * 0x9E3779B9u));
+}
+// Box-Muller on 32-bit words: u = (a + 1) 2^-32 in (0, 1], angle 2 pi b 2^-32
+__device__ __forceinline__ void gauss2_md(uint32_t a, uint32_t b, double& z0, double& z1) {
+  const double rad = sqrt(-2.0 * log(((double)a + 1.0) * 0x1.0p-32));
+  double sn, cs;
+  sincospi((double)b * 0x1.0p-31, &sn, &cs);
+  z0 = rad * cs;
+  z1 = rad * sn;
+}
+// the same in FP32 for the mixed path: u rounded to 24 bits (relative error 2^-24; log2 u >=
+// -32), hardware log2 and revolutions-argument sine / cosine
+__device__ __forceinline__ void gauss2_md_f32(uint32_t a, uint32_t b, double& z0, double& z1) {
+  const float u = __builtin_fmaf((float)a, 0x1.0p-32f, 0x1.0p-32f);
   const float rad = __builtin_amdgcn_sqrtf(-1.38629436f * __builtin_amdgcn_logf(u));  // -2 ln u
-  const float t = (float)u01(b);        // [0, 1)
+  const float t = (float)b * 0x1.0p-32f;
   z0 = (double)(rad * __builtin_amdgcn_cosf(t));
   z1 = (double)(rad * __builtin_amdgcn_sinf(t));
 }
-// Langevin noise at the force precision R
 template <typename R>
-__device__ __forceinline__ void gauss2_r(uint64_t a, uint64_t b, double& z0, double& z1) {
-  if constexpr (sizeof(R) == 4) gauss2_f32(a, b, z0, z1);
-  else gauss2(a, b, z0, z1);
+__device__ __forceinline__ void gauss2_md_r(uint32_t a, uint32_t b, double& z0, double& z1) {
+  if constexpr (sizeof(R) == 4) gauss2_md_f32(a, b, z0, z1);
+  else gauss2_md(a, b, z0, z1);
 }
 // exact integer in [0,K): high word of r*K
 __device__ __forceinline__ uint64_t rng_choice(uint64_t r, uint64_t K) { return __umul64hi(r, K); }

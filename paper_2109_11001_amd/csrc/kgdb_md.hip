@@ -357,10 +357,10 @@ __global__ __launch_bounds__(256) void k_force(ForceArgs a) {
       // Langevin force of this step, then the closing half kick
       const uint64_t idx = (MODE & F_WARM) ? (uint64_t)a.s_off : a.step_base[k] + (uint64_t)a.s_off;
       // the noise is keyed by the monomer id, not by the storage slot
-      const U64x4 w = rng_draw(d, (uint64_t)a.mono[g], idx, (MODE & F_WARM) ? ST_WARMUP : ST_LANGEVIN);
+      const U32x4 w = md_noise_draw(d, (uint64_t)a.mono[g], idx, (MODE & F_WARM) ? ST_WARMUP : ST_LANGEVIN);
       double z0, z1, z2, z3;
-      gauss2_r<R>(w.w[0], w.w[1], z0, z1);
-      gauss2_r<R>(w.w[2], w.w[3], z2, z3);
+      gauss2_md_r<R>(w.w[0], w.w[1], z0, z1);
+      gauss2_md_r<R>(w.w[2], w.w[3], z2, z3);
       const double amp = sqrt(2.0 * d.gamma * d.T / dt_close);
       fx = -d.gamma * vx + amp * z0;
       fy = -d.gamma * vy + amp * z1;

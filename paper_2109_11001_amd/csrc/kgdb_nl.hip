@@ -622,10 +622,10 @@ __global__ __launch_bounds__(NLB_THREADS) void k_nl_step(NlArgs a) {
   auto noise = [&](Home& o, int mono) {
     o.z0 = o.z1 = o.z2 = 0.0;
     if (MODE & F_CLOSE) {
-      const U64x4 w = rng_draw(d, (uint64_t)mono, noise_idx, ST_LANGEVIN);
+      const U32x4 w = md_noise_draw(d, (uint64_t)mono, noise_idx, ST_LANGEVIN);
       double z3;
-      gauss2_r<R>(w.w[0], w.w[1], o.z0, o.z1);
-      gauss2_r<R>(w.w[2], w.w[3], o.z2, z3);
+      gauss2_md_r<R>(w.w[0], w.w[1], o.z0, o.z1);
+      gauss2_md_r<R>(w.w[2], w.w[3], o.z2, z3);
     }
   };
   const uint4* __restrict__ words = (const uint4*)a.nlist;
