@@ -461,24 +461,23 @@ __global__ __launch_bounds__(NLB_THREADS) void k_nl_rebuild(NlArgs a) {
     if (staged) me = s_pos[si];
     else me = make(t, member_slot(a, s_sc[t], s_off[t + 1] - s_off[t], r));
     const int old = me.tag;
-    // the new slot takes the monomer's state
+    // the new slot takes the monomer's state: its loads are issued here and stored after the
+    // list is built, so that they arrive while the list is built
     const int cx = wrapc(tg.x0 + lx, nc), cy = wrapc(tg.y0 + ly, nc), cz = tg.cz;
+    double xo[3], vo[3], fco[3] = {0.0, 0.0, 0.0}, flo[3] = {0.0, 0.0, 0.0};
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
-      a.xn[(size_t)q * NP + g] = a.x[(size_t)q * NP + old];
-      a.vn[(size_t)q * NP + g] = a.v[(size_t)q * NP + old];
+      xo[q] = a.x[(size_t)q * NP + old];
+      vo[q] = a.v[(size_t)q * NP + old];
     }
     if (a.perm_f) {
 #pragma unroll
       for (int q = 0; q < 3; ++q) {
-        a.fcn[(size_t)q * NP + g] = a.fc[(size_t)q * NP + old];
-        a.fln[(size_t)q * NP + g] = a.fl[(size_t)q * NP + old];
+        fco[q] = a.fc[(size_t)q * NP + old];
+        flo[q] = a.fl[(size_t)q * NP + old];
       }
     }
-    a.mono_n[g] = a.mono[old];
-    a.inv[old] = g;
-    ((typename Rel<R>::T*)a.rel_next)[g] =
-        Rel<R>::make(a.x[old] - cx * hl, a.x[NP + old] - cy * hl, a.x[2 * NP + old] - cz * hl, pack_cell(cx, cy, cz), hl);
+    const int mo = a.mono[old];
     int n;
     if (staged)
       n = nl_list_one(a, g, me, si, lx + 1, ly + 1, W, WY, hlr, rl2, rskip2, s_off, [&](int u) { return s_pos[u]; });
@@ -487,6 +486,22 @@ __global__ __launch_bounds__(NLB_THREADS) void k_nl_rebuild(NlArgs a) {
         const int q = find_cell(s_off, 0, ncell, u);
         return make(q, member_slot(a, s_sc[q], s_off[q + 1] - s_off[q], u - s_off[q]));
       });
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      a.xn[(size_t)q * NP + g] = xo[q];
+      a.vn[(size_t)q * NP + g] = vo[q];
+    }
+    if (a.perm_f) {
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        a.fcn[(size_t)q * NP + g] = fco[q];
+        a.fln[(size_t)q * NP + g] = flo[q];
+      }
+    }
+    a.mono_n[g] = mo;
+    a.inv[old] = g;
+    ((typename Rel<R>::T*)a.rel_next)[g] =
+        Rel<R>::make(xo[0] - cx * hl, xo[1] - cy * hl, xo[2] - cz * hl, pack_cell(cx, cy, cz), hl);
     if (n > NL_CAP) { atomicOr(&a.err[k], ERR_NLIST_OVERFLOW); n = NL_CAP; }
     if (a.side && (d.test_flags & TF_SIDE_FAULT)) {  // test hook: a failed rebuild beside a sweep
       atomicOr(&a.err[k], ERR_NLIST_OVERFLOW);
@@ -614,18 +629,19 @@ __global__ __launch_bounds__(NLB_THREADS) void k_nl_step(NlArgs a) {
     int4 nb;
     int n;
     double x, y, z, vx, vy, vz;
-    double z0, z1, z2;  // Langevin noise of this closing kick
+    R z0, z1, z2;  // Langevin noise of this closing kick (drawn at the force precision)
     uint4 w0;
   };
   // the noise depends only on the monomer id and the step
   const uint64_t noise_idx = (MODE & F_CLOSE) ? a.step_base[k] + (uint64_t)a.s_off : 0ull;
   auto noise = [&](Home& o, int mono) {
-    o.z0 = o.z1 = o.z2 = 0.0;
+    o.z0 = o.z1 = o.z2 = (R)0;
     if (MODE & F_CLOSE) {
       const U32x4 w = md_noise_draw(d, (uint64_t)mono, noise_idx, ST_LANGEVIN);
-      double z3;
-      gauss2_md_r<R>(w.w[0], w.w[1], o.z0, o.z1);
-      gauss2_md_r<R>(w.w[2], w.w[3], o.z2, z3);
+      double n0, n1, n2, n3;
+      gauss2_md_r<R>(w.w[0], w.w[1], n0, n1);
+      gauss2_md_r<R>(w.w[2], w.w[3], n2, n3);
+      o.z0 = (R)n0; o.z1 = (R)n1; o.z2 = (R)n2;  // (exact: the normals are of precision R)
     }
   };
   const uint4* __restrict__ words = (const uint4*)a.nlist;
@@ -721,12 +737,15 @@ __global__ __launch_bounds__(NLB_THREADS) void k_nl_step(NlArgs a) {
     const int pc = Rel<R>::cell(ri);
     const int ix = pc & 1023, iy = (pc >> 10) & 1023, iz = pc >> 20;
     // chain neighbours p-2, p-1, p+1, p+2 (slots, or -1)
-    int nbq[4] = {nb.x, nb.y, nb.z, nb.w};
+    const int nbq[4] = {nb.x, nb.y, nb.z, nb.w};
     P rb[4];
+    uint32_t nbmask = 0;  // bit q: partner q exists (and forces are on)
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      if (nbq[q] >= NP) nbq[q] = -1;  // (only a rebuild that overflowed, whose run is redone, leaves such an entry)
-      rb[q] = rel[(forces_on && nbq[q] >= 0) ? nbq[q] : g];
+      // (a slot past the storage can only come from a rebuild that overflowed, whose run is redone)
+      const bool on = forces_on && nbq[q] >= 0 && nbq[q] < NP;
+      nbmask |= on ? 1u << q : 0u;
+      rb[q] = rel[on ? nbq[q] : g];
     }
 
     const double z0 = hm.z0, z1 = hm.z1, z2 = hm.z2;
@@ -787,7 +806,7 @@ __global__ __launch_bounds__(NLB_THREADS) void k_nl_step(NlArgs a) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int sl = q < 2 ? q : q + 1;
-      if (!(forces_on && nbq[q] >= 0)) continue;
+      if (!((nbmask >> q) & 1u)) continue;
       has[sl] = true;
       const int pj = Rel<R>::cell(rb[q]);
       int dx = (pj & 1023) - ix, dy = ((pj >> 10) & 1023) - iy, dz = (pj >> 20) - iz;
@@ -881,11 +900,11 @@ __global__ __launch_bounds__(NLB_THREADS) void k_nl_step(NlArgs a) {
       a.xn[g] = nxp; a.xn[NP + g] = nyp; a.xn[2 * NP + g] = nzp;
       // (FP32, rounded up by a relative 1e-6: a bound, not a value)
       dmax = fmaxf(dmax, (float)dt * __builtin_amdgcn_sqrtf((float)(hx * hx + hy * hy + hz * hz)) * 1.000001f);
-      if (MODE & F_BIN) nl_bin_one(a, k, d, g, nxp, nyp, nzp, true);
       // position relative to the reference cell (periodic image nearest to it)
       double rx = nxp - ix * hl, ry = nyp - iy * hl, rz = nzp - iz * hl;
       rx -= L * rint(rx * invL); ry -= L * rint(ry * invL); rz -= L * rint(rz * invL);
       ((P*)a.rel_next)[g] = Rel<R>::make(rx, ry, rz, pc, hl);
+      if (MODE & F_BIN) nl_bin_one(a, k, d, g, nxp, nyp, nzp, true);
     }
   }
   if (MODE & F_OPEN) {
