@@ -95,6 +95,7 @@ struct kgdb_batch {
   int* d_tcnt = nullptr;           // binning: count per tile
   int* d_tstart = nullptr;         // first slot of each tile
   int* d_bucketl_raw = nullptr;    // slots binned into each cell
+  int* d_bucketl_mono = nullptr;   // and their monomer ids
   int2* d_cellsc = nullptr;        // first slot and count of each sorted cell
   int* d_stage = nullptr;          // per tile: slots of its staged members (stage_cap_max each)
   int stage_cap_max = 0;           // LDS limit of a stage (members)
@@ -507,6 +508,7 @@ static NlArgs nl_args(kgdb_batch* b) {
   a.tcnt = b->d_tcnt;
   a.tstart = b->d_tstart;
   a.bucket_raw = b->d_bucketl_raw;
+  a.bucket_mono = b->d_bucketl_mono;
   a.cellsc = b->d_cellsc;
   a.stage_list = b->d_stage;
   a.stage_stride = b->stage_cap_max;
@@ -1184,6 +1186,7 @@ static int init_impl(const kgdb_params* params, int32_t count, void* stream, kgd
   step(dalloc(b, &b->d_stage, std::max<size_t>(b->stage_words, 1)));
   step(dalloc(b, &b->d_smeta, (size_t)b->NTILE));
   step(dalloc(b, &b->d_bucketl_raw, (size_t)b->NCL * NL_CELL_CAP));
+  step(dalloc(b, &b->d_bucketl_mono, (size_t)b->NCL * NL_CELL_CAP));
   step(dalloc(b, &b->d_disp, 2 * (size_t)DISP_SLOTS * DISP_STRIDE * count));
   step(dalloc(b, &b->d_dacc, (size_t)count));
   step(dalloc(b, &b->d_floor, (size_t)count));

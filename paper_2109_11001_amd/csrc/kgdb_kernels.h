@@ -101,6 +101,7 @@ struct NlArgs {
   int* tcnt;         // occupancy per tile (binning)
   int* tstart;       // first new slot of each tile
   int* bucket_raw;   // slots binned into each cell (any order)
+  int* bucket_mono;  // the monomer id of each binned slot (same places)
   int2* cellsc;      // first slot and count of each sorted cell
   int* stage_list;   // per tile (stage_stride each): slots of the staged members, in stage order
   int stage_stride;  // entries per tile in stage_list (the largest capacity)

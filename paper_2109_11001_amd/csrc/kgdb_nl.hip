@@ -188,8 +188,8 @@ __device__ __forceinline__ int run_add(int* ctr, int key) {
   return base + (lane - hl);
 }
 
-__device__ __forceinline__ void nl_bin_one(const NlArgs& a, int k, const MeltDesc& d, int g, double x, double y,
-                                           double z, bool valid) {
+__device__ __forceinline__ void nl_bin_one(const NlArgs& a, int k, const MeltDesc& d, int g, int mono, double x,
+                                           double y, double z, bool valid) {
   int sc = -1, tile = -1;
   if (valid) {
     const int nc = d.ncl;
@@ -198,8 +198,12 @@ __device__ __forceinline__ void nl_bin_one(const NlArgs& a, int k, const MeltDes
   const int s = run_add(a.cnt, sc);
   (void)run_add(a.tcnt, tile);
   if (!valid) return;
-  if (s < NL_CELL_CAP) a.bucket_raw[sc * NL_CELL_CAP + s] = g;
-  else atomicOr(&a.err[k], ERR_CELL_OVERFLOW);
+  if (s < NL_CELL_CAP) {
+    a.bucket_raw[sc * NL_CELL_CAP + s] = g;
+    a.bucket_mono[sc * NL_CELL_CAP + s] = mono;
+  } else {
+    atomicOr(&a.err[k], ERR_CELL_OVERFLOW);
+  }
 }
 
 __global__ __launch_bounds__(256) void k_nl_bin(NlArgs a) {
@@ -211,7 +215,7 @@ __global__ __launch_bounds__(256) void k_nl_bin(NlArgs a) {
   const int g = d.off + (valid ? li : 0);
   double x = 0, y = 0, z = 0;
   if (valid) { x = a.x[g]; y = a.x[a.NP + g]; z = a.x[2 * a.NP + g]; }
-  nl_bin_one(a, k, d, g, x, y, z, valid);
+  nl_bin_one(a, k, d, g, valid ? a.mono[g] : 0, x, y, z, valid);
 }
 
 // exclusive scan of the tile counts (one workgroup, runs of 1024 with a carry)
@@ -352,8 +356,8 @@ __global__ __launch_bounds__(NLB_THREADS) void k_nl_rebuild(NlArgs a) {
   // whose cutoff carries a margin far above their rounding
   extern __shared__ __align__(16) unsigned char s_dyn[];
   Staged<float>* s_pos = (Staged<float>*)s_dyn;
-  // monomer ids of the staged members in binning order: they share the stage's memory and are
-  // consumed before it is written
+  // monomer ids (then old slots and staged cells) of the staged members in binning order: they
+  // share the stage's memory and are consumed before it is written
   int* s_mono = (int*)s_dyn;
   __shared__ int s_off[NLB_CELLS + 1];
   __shared__ int s_sc[NLB_CELLS];
@@ -398,12 +402,23 @@ __global__ __launch_bounds__(NLB_THREADS) void k_nl_rebuild(NlArgs a) {
     m.tag = slot;
     return m;
   };
-  // binned member u (cell q, place j in the cell's bucket): its old slot
-  auto raw_slot = [&](int q, int u) { return a.bucket_raw[(size_t)s_sc[q] * NL_CELL_CAP + (u - s_off[q])]; };
   if (staged) {
-    // (1) the monomer ids of the binned members
+    // (1) the binned members' monomer ids (binned with them), old slots and staged cells, a
+    // staged cell per thread (three int arrays of `total` in the stage's memory, 12 of its 16
+    // bytes per member)
+    int* const s_slot = s_mono + total;
+    int* const s_cq = s_mono + 2 * total;
+    for (int t = threadIdx.x; t < ncell; t += NLB_THREADS) {
+      const int b0 = s_off[t], n = s_off[t + 1] - b0;
+      const int* __restrict__ bm = a.bucket_mono + (size_t)s_sc[t] * NL_CELL_CAP;
+      const int* __restrict__ br = a.bucket_raw + (size_t)s_sc[t] * NL_CELL_CAP;
 #pragma unroll 4
-    for (int u = threadIdx.x; u < total; u += NLB_THREADS) s_mono[u] = a.mono[raw_slot(find_cell(s_off, 0, ncell, u), u)];
+      for (int j = 0; j < n; ++j) {
+        s_mono[b0 + j] = bm[j];
+        s_slot[b0 + j] = br[j];
+        s_cq[b0 + j] = t;
+      }
+    }
     __syncthreads();
     // (2) each member's rank by id within its cell gives its place in the stage (held in
     // registers until every id has been read: cell q and place packed, and the old slot)
@@ -414,12 +429,12 @@ __global__ __launch_bounds__(NLB_THREADS) void k_nl_rebuild(NlArgs a) {
       pl[i] = -1;
       sl[i] = 0;
       if (u < total) {
-        const int q = find_cell(s_off, 0, ncell, u);
+        const int q = s_cq[u];
         const int b = s_off[q], e = s_off[q + 1], m = s_mono[u];
         int r = 0;
         for (int w = b; w < e; ++w) r += s_mono[w] < m;
         pl[i] = ((b + r) << 10) | q;
-        sl[i] = raw_slot(q, u);
+        sl[i] = s_slot[u];
       }
     }
     __syncthreads();
@@ -628,6 +643,7 @@ __global__ __launch_bounds__(NLB_THREADS) void k_nl_step(NlArgs a) {
     P ri;
     int4 nb;
     int n;
+    int mono;  // (read for the noise and for the binning only)
     double x, y, z, vx, vy, vz;
     R z0, z1, z2;  // Langevin noise of this closing kick (drawn at the force precision)
     uint4 w0;
@@ -653,7 +669,8 @@ __global__ __launch_bounds__(NLB_THREADS) void k_nl_step(NlArgs a) {
     o.x = a.x[g]; o.y = a.x[NP + g]; o.z = a.x[2 * NP + g];
     o.vx = a.v[g]; o.vy = a.v[NP + g]; o.vz = a.v[2 * NP + g];
     o.w0 = words[nl_word(g, 0)];
-    noise(o, (MODE & F_CLOSE) ? a.mono[g] : 0);
+    o.mono = (MODE & (F_CLOSE | F_BIN)) ? a.mono[g] : 0;
+    noise(o, o.mono);
     return o;
   };
   // (the first home's noise is drawn while its stage loads arrive)
@@ -904,7 +921,7 @@ __global__ __launch_bounds__(NLB_THREADS) void k_nl_step(NlArgs a) {
       double rx = nxp - ix * hl, ry = nyp - iy * hl, rz = nzp - iz * hl;
       rx -= L * rint(rx * invL); ry -= L * rint(ry * invL); rz -= L * rint(rz * invL);
       ((P*)a.rel_next)[g] = Rel<R>::make(rx, ry, rz, pc, hl);
-      if (MODE & F_BIN) nl_bin_one(a, k, d, g, nxp, nyp, nzp, true);
+      if (MODE & F_BIN) nl_bin_one(a, k, d, g, hm.mono, nxp, nyp, nzp, true);
     }
   }
   if (MODE & F_OPEN) {
