@@ -372,11 +372,22 @@ __global__ __launch_bounds__(NLB_THREADS) void k_nl_rebuild(NlArgs a) {
   const double hl = d.hl;
   const int nc = d.ncl;
 
+  // the first PF bucket entries (ids and slots) of a thread's first staged cell are read with the
+  // cell's count, so that they arrive meanwhile (entries past the count are read and not used)
+  constexpr int PF = 8;
+  int pf_mono[PF], pf_slot[PF];
   for (int t = threadIdx.x; t < ncell; t += NLB_THREADS) {
     const StagedCell s = staged_cell(d, tg, W, WY, t);
     const int sc = sorted_cell(d, s.ax, s.ay, s.az, nullptr);
     s_sc[t] = sc;
     s_off[t + 1] = min(a.cnt[sc], NL_CELL_CAP);
+    if (t == (int)threadIdx.x) {
+#pragma unroll
+      for (int j = 0; j < PF; ++j) {
+        pf_mono[j] = a.bucket_mono[(size_t)sc * NL_CELL_CAP + j];
+        pf_slot[j] = a.bucket_raw[(size_t)sc * NL_CELL_CAP + j];
+      }
+    }
     const int wx = s.ax - (tg.x0 - 1 + s.i), wy = s.ay - (tg.y0 - 1 + s.yy), wz = s.az - (tg.cz - 1 + s.zz);
     s_wrap[t] = (uint8_t)((wx > 0) - (wx < 0) + 1 + (((wy > 0) - (wy < 0) + 1) << 2) + (((wz > 0) - (wz < 0) + 1) << 4));
   }
@@ -410,10 +421,21 @@ __global__ __launch_bounds__(NLB_THREADS) void k_nl_rebuild(NlArgs a) {
     int* const s_cq = s_mono + 2 * total;
     for (int t = threadIdx.x; t < ncell; t += NLB_THREADS) {
       const int b0 = s_off[t], n = s_off[t + 1] - b0;
+      int j0 = 0;
+      if (t == (int)threadIdx.x) {
+#pragma unroll
+        for (int j = 0; j < PF; ++j)
+          if (j < n) {
+            s_mono[b0 + j] = pf_mono[j];
+            s_slot[b0 + j] = pf_slot[j];
+            s_cq[b0 + j] = t;
+          }
+        j0 = PF;
+      }
       const int* __restrict__ bm = a.bucket_mono + (size_t)s_sc[t] * NL_CELL_CAP;
       const int* __restrict__ br = a.bucket_raw + (size_t)s_sc[t] * NL_CELL_CAP;
 #pragma unroll 4
-      for (int j = 0; j < n; ++j) {
+      for (int j = j0; j < n; ++j) {
         s_mono[b0 + j] = bm[j];
         s_slot[b0 + j] = br[j];
         s_cq[b0 + j] = t;
@@ -643,7 +665,6 @@ __global__ __launch_bounds__(NLB_THREADS) void k_nl_step(NlArgs a) {
     P ri;
     int4 nb;
     int n;
-    int mono;  // (read for the noise and for the binning only)
     double x, y, z, vx, vy, vz;
     R z0, z1, z2;  // Langevin noise of this closing kick (drawn at the force precision)
     uint4 w0;
@@ -669,8 +690,7 @@ __global__ __launch_bounds__(NLB_THREADS) void k_nl_step(NlArgs a) {
     o.x = a.x[g]; o.y = a.x[NP + g]; o.z = a.x[2 * NP + g];
     o.vx = a.v[g]; o.vy = a.v[NP + g]; o.vz = a.v[2 * NP + g];
     o.w0 = words[nl_word(g, 0)];
-    o.mono = (MODE & (F_CLOSE | F_BIN)) ? a.mono[g] : 0;
-    noise(o, o.mono);
+    noise(o, (MODE & F_CLOSE) ? a.mono[g] : 0);
     return o;
   };
   // (the first home's noise is drawn while its stage loads arrive)
@@ -921,7 +941,15 @@ __global__ __launch_bounds__(NLB_THREADS) void k_nl_step(NlArgs a) {
       double rx = nxp - ix * hl, ry = nyp - iy * hl, rz = nzp - iz * hl;
       rx -= L * rint(rx * invL); ry -= L * rint(ry * invL); rz -= L * rint(rz * invL);
       ((P*)a.rel_next)[g] = Rel<R>::make(rx, ry, rz, pc, hl);
-      if (MODE & F_BIN) nl_bin_one(a, k, d, g, hm.mono, nxp, nyp, nzp, true);
+    }
+  }
+  // the step before a rebuild bins the new positions into the list grid, in a loop of its own that
+  // reads back what the lane has just written (outside the force loop, whose registers it would
+  // otherwise raise past four wavefronts per SIMD)
+  if (MODE & F_BIN) {
+    for (int h = threadIdx.x; h < nhome; h += NLB_THREADS) {
+      const int g = h0 + h;
+      nl_bin_one(a, k, d, g, a.mono[g], a.xn[g], a.xn[NP + g], a.xn[2 * NP + g], true);
     }
   }
   if (MODE & F_OPEN) {
