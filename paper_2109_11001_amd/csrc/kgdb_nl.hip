@@ -279,6 +279,8 @@ __device__ __forceinline__ int find_cell(const int* s, int lo, int hi, int v) {
 }
 
 constexpr int NLB_CELLS = 594;  // staged cells: 3 (nl_S + 2)(nl_Sy + 2) <= 594
+// batches of at most this many list tiles find a tile's first slot inside the rebuild kernel
+constexpr int TILE_SUM_MAX = 4096;
 constexpr int STAGE_PER_THREAD = (STAGE_CAP_MAX + NLB_THREADS - 1) / NLB_THREADS;
 
 // a staged member: position relative to the tile frame, and (rebuild only) its old slot
@@ -376,6 +378,18 @@ __global__ __launch_bounds__(NLB_THREADS) void k_nl_rebuild(NlArgs a) {
   // cell's count, so that they arrive meanwhile (entries past the count are read and not used)
   constexpr int PF = 8;
   int pf_mono[PF], pf_slot[PF];
+  // the first slot of this tile: with few tiles in the batch, the sum of the counts of the tiles
+  // before it, read here with the cells' counts (no scan kernel); else the scan's result
+  const int tile = d.tile_off + lt;
+  __shared__ int s_tsum[NLB_THREADS / 64];
+  const bool tile_sum = a.ntile_total <= TILE_SUM_MAX;
+  if (tile_sum) {
+    int part = 0;
+    for (int t = threadIdx.x; t < tile; t += NLB_THREADS) part += a.tcnt[t];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o, 64);
+    if ((threadIdx.x & 63) == 0) s_tsum[threadIdx.x >> 6] = part;
+  }
   for (int t = threadIdx.x; t < ncell; t += NLB_THREADS) {
     const StagedCell s = staged_cell(d, tg, W, WY, t);
     const int sc = sorted_cell(d, s.ax, s.ay, s.az, nullptr);
@@ -474,8 +488,13 @@ __global__ __launch_bounds__(NLB_THREADS) void k_nl_rebuild(NlArgs a) {
   __syncthreads();
   if (threadIdx.x < 64) wave_prefix(s_home, nhc);
   __syncthreads();
-  const int tile = d.tile_off + lt;
-  const int first = a.tstart[tile];
+  int first = 0;
+  if (tile_sum) {
+#pragma unroll
+    for (int w = 0; w < NLB_THREADS / 64; ++w) first += s_tsum[w];
+  } else {
+    first = a.tstart[tile];
+  }
   for (int c = threadIdx.x; c < nhc; c += NLB_THREADS) {
     const int ly = c / tg.nh, lx = c - ly * tg.nh;
     const int t = (WY + ly + 1) * W + lx + 1;
@@ -981,7 +1000,8 @@ size_t rel_bytes(int prec) { return prec ? sizeof(Rel<float>::T) : sizeof(Rel<do
 
 void launch_nl_rebuild(int prec, const NlArgs& a, int pblk, int ntile, bool bin, hipStream_t s) {
   if (bin) hipLaunchKernelGGL(k_nl_bin, dim3(pblk), dim3(256), 0, s, a);
-  hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(1024), 0, s, a.tcnt, a.ntile_total, a.tstart);
+  if (a.ntile_total > TILE_SUM_MAX)  // (fewer tiles: each tile sums its predecessors' counts)
+    hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(1024), 0, s, a.tcnt, a.ntile_total, a.tstart);
   if (prec)
     hipLaunchKernelGGL(k_nl_rebuild<float>, dim3(ntile), dim3(NLB_THREADS), nl_stage_bytes(1, a.stage_cap), s, a);
   else
