@@ -97,6 +97,33 @@ def test_run_protocol_matches_oracle():
     gm.close()
 
 
+def test_run_protocol_stiff_long_chains_matches_oracle():
+    # the stiff system's regime (kappa = 3, 2000-bead chains, exponents of Eq. 11 at the hard
+    # end) on 5 chains: two stages with sweeps every 10 steps, decisions and trajectory against
+    # the oracle
+    kw = dict(M=5, N=2000, kappa=3.0, n_exp=12.0, seed=7, db_rate=0.05)
+    om = o.Melt(warmup_steps=200, **kw)
+    gm = kg.Melt(warmup_steps=0, **kw)
+    transfer(om, gm)
+    n_values, steps, every = [12.0, 11.0], [20, 20], 10
+    stats = gm.run_protocol(n_values, steps, sweep_every=every)
+    for n, s, st in zip(n_values, steps, stats):
+        om.set_potential(n)
+        acc = att = 0
+        for _ in range(s // every):
+            om.md_steps(every)
+            r = om.db_sweep(-1)
+            acc += r["accepted"]
+            att += r["attempts"]
+        assert (st["accepted"], st["attempts"]) == (acc, att), n
+        assert att > 0
+    so, sg = om.get_state(), gm.get_state()
+    assert np.array_equal(so["chains"], sg["chains"])
+    assert np.max(np.abs(mi_diff(so["x"], sg["x"], om.L))) < 1e-10
+    assert sum(st["accepted"] for st in stats) > 0
+    gm.close()
+
+
 def test_run_protocol_without_sweeps_is_plain_md():
     kw = dict(M=20, N=50, kappa=1.5, n_exp=12.0, seed=6)
     a = kg.Melt(warmup_steps=100, **kw)
