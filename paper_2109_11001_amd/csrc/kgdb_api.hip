@@ -101,6 +101,8 @@ struct kgdb_batch {
   int stage_cap_max = 0;           // LDS limit of a stage (members)
   uint32_t* d_nlstat = nullptr;    // rebuild tiles staged from global memory; largest stage (since last read)
   uint32_t* h_nlstat = nullptr;
+  kgdb_db_stats* h_stats = nullptr;  // pinned: a sweep's statistics
+  uint32_t* h_err_side = nullptr;    // pinned: the error words of a rebuild beside a sweep
   int64_t nl_stage_over = 0;       // rebuild tiles staged from global memory, all passes
   int nl_stage_seen = 0;           // largest stage seen
   int4* d_smeta = nullptr;         // per tile: first home slot, home count, staged count
@@ -651,19 +653,23 @@ static int nl_pass(kgdb_batch* b, int64_t n, bool graph) {
 // into the current buffers; the next pass opens with a rebuild.
 static int copy_state(kgdb_batch* b, bool back, double* sx, int* si, uint64_t* sst) {
   const size_t n3 = 3 * (size_t)b->NP, np = (size_t)b->NP;
+  // nine buffers in one copy kernel (nine separate copies cost a host round trip each)
+  CopyJobs c;
+  c.n = 0;
+  auto job = [&](void* live, void* saved, size_t bytes) {
+    c.src[c.n] = back ? saved : live;
+    c.dst[c.n] = back ? live : saved;
+    c.bytes[c.n] = bytes;
+    ++c.n;
+  };
   double* f[4] = {b->d_x[b->cur], b->d_v, b->d_fc, b->d_fl};
-  for (int q = 0; q < 4; ++q)
-    HIPCHK(hipMemcpyAsync(back ? f[q] : sx + q * n3, back ? sx + q * n3 : f[q], n3 * sizeof(double),
-                          hipMemcpyDeviceToDevice, b->s));
+  for (int q = 0; q < 4; ++q) job(f[q], sx + q * n3, n3 * sizeof(double));
   int* t[3] = {b->d_mono, b->d_loc, b->d_chain};
-  for (int q = 0; q < 3; ++q)
-    HIPCHK(hipMemcpyAsync(back ? t[q] : si + q * np, back ? si + q * np : t[q], np * sizeof(int),
-                          hipMemcpyDeviceToDevice, b->s));
-  HIPCHK(hipMemcpyAsync(back ? b->d_step : sst, back ? sst : b->d_step, b->nm * sizeof(uint64_t),
-                        hipMemcpyDeviceToDevice, b->s));
-  uint64_t* fl = (uint64_t*)b->d_floor;  // FENE-floor counters (sst holds 2 nm words)
-  HIPCHK(hipMemcpyAsync(back ? fl : sst + b->nm, back ? sst + b->nm : fl, b->nm * sizeof(uint64_t),
-                        hipMemcpyDeviceToDevice, b->s));
+  for (int q = 0; q < 3; ++q) job(t[q], si + q * np, np * sizeof(int));
+  job(b->d_step, sst, b->nm * sizeof(uint64_t));
+  job(b->d_floor, sst + b->nm, b->nm * sizeof(uint64_t));  // FENE-floor counters (sst holds 2 nm words)
+  launch_copy_jobs(c, b->s);
+  HIPCHK(hipGetLastError());
   if (back) b->lists_ver = ~0ull;
   return 0;
 }
@@ -718,10 +724,9 @@ static std::vector<TileShape> current_tiles(const kgdb_batch* b, int q) {
 // A tile whose stage outgrew the LDS capacity was staged from global memory (correct, but far
 // slower): raise the capacity of the current interval for the passes that follow, up to the
 // LDS limit.  Captured runs of steps hold the old capacity and are dropped.
+// h_nlstat holds the pass's stage statistics, read with its error words
 static int adapt_stage_cap(kgdb_batch* b) {
-  HIPCHK(hipMemcpyAsync(b->h_nlstat, b->d_nlstat, sizeof(uint32_t) * 2, hipMemcpyDeviceToHost, b->s));
   HIPCHK(hipMemsetAsync(b->d_nlstat, 0, sizeof(uint32_t) * 2, b->s));
-  HIPCHK(hipStreamSynchronize(b->s));
   b->nl_stage_over += b->h_nlstat[0];
   b->nl_stage_seen = std::max(b->nl_stage_seen, (int)b->h_nlstat[1]);
   int& cap = b->stage_cap[b->nl_ki];
@@ -741,7 +746,9 @@ static int run_steps(kgdb_batch* b, int64_t n, bool graph) {
   for (;;) {
     CHK(nl_pass(b, n, graph));
     if (b->prof) CHK(prof_flush(b));
+    // the pass's error words and stage statistics, one wait for both
     HIPCHK(hipMemcpyAsync(b->h_err, b->d_err, sizeof(uint32_t) * b->nm, hipMemcpyDeviceToHost, b->s));
+    HIPCHK(hipMemcpyAsync(b->h_nlstat, b->d_nlstat, sizeof(uint32_t) * 2, hipMemcpyDeviceToHost, b->s));
     HIPCHK(hipStreamSynchronize(b->s));
     uint32_t all = 0;
     for (int k = 0; k < b->nm; ++k) all |= b->h_err[k];
@@ -776,7 +783,11 @@ static int run_steps(kgdb_batch* b, int64_t n, bool graph) {
   b->fc_valid = true;
   b->cells_valid = false;
   b->xver++;
-  CHK(check_errors(b));
+  // (the error words were read after the pass, and nothing has run since but a restore of the
+  // K = 1 staleness bits: read again only when some bit is set)
+  uint32_t any = 0;
+  for (int k = 0; k < b->nm; ++k) any |= b->h_err[k];
+  if (any) CHK(check_errors(b));
   CHK(adapt_stage_cap(b));
   if (b->msd_on)  // a run of steps moves a monomer far less than L / 2
     launch_msd_track(b->d_md, b->pm, b->NP, b->d_x[b->cur], b->d_mono, b->d_msd_last, b->d_msd_acc, 0, -1, b->s);
@@ -849,6 +860,8 @@ void kgdb_destroy(kgdb_batch* b) {
   for (void* q : b->allocs) hipFree(q);
   if (b->h_err) hipHostFree(b->h_err);
   if (b->h_nlstat) hipHostFree(b->h_nlstat);
+  if (b->h_stats) hipHostFree(b->h_stats);
+  if (b->h_err_side) hipHostFree(b->h_err_side);
   if (b->own_stream && b->s) hipStreamDestroy(b->s);
   delete b;
 }
@@ -1248,6 +1261,10 @@ static int init_impl(const kgdb_params* params, int32_t count, void* stream, kgd
     rc = fail(KGDB_E_ALLOC, "hipHostMalloc");
   if (!rc && hipHostMalloc((void**)&b->h_nlstat, sizeof(uint32_t) * 2, 0) != hipSuccess)
     rc = fail(KGDB_E_ALLOC, "hipHostMalloc");
+  if (!rc && hipHostMalloc((void**)&b->h_stats, sizeof(kgdb_db_stats) * count, 0) != hipSuccess)
+    rc = fail(KGDB_E_ALLOC, "hipHostMalloc");
+  if (!rc && hipHostMalloc((void**)&b->h_err_side, sizeof(uint32_t) * count, 0) != hipSuccess)
+    rc = fail(KGDB_E_ALLOC, "hipHostMalloc");
   if (!rc) rc = build_block_maps(b);
   if (rc) { kgdb_destroy(b); return rc; }
   if (const char* e = std::getenv("KGDB_FORCE_LANES")) {
@@ -1613,13 +1630,11 @@ int kgdb_db_probe(kgdb_batch* b, int32_t melt, const uint64_t* keys, int64_t nke
 // other buffers and built the lists; the topology (which the sweep was rewriting meanwhile)
 // is carried over now.  If that rebuild overflowed a capacity, its buffers are dropped and the
 // next run of steps rebuilds in-run (where an overflow rolls back to a finer grid).
+// (h_err_side holds the side rebuild's error words, read after the sweep with its statistics)
 static int finish_side_rebuild(kgdb_batch* b) {
   b->remap_pending = false;
-  std::vector<uint32_t> e(b->nm);
-  HIPCHK(hipMemcpyAsync(e.data(), b->d_err_side, sizeof(uint32_t) * b->nm, hipMemcpyDeviceToHost, b->s));
-  HIPCHK(hipStreamSynchronize(b->s));
   uint32_t all = 0;
-  for (uint32_t v : e) all |= v;
+  for (int k = 0; k < b->nm; ++k) all |= b->h_err_side[k];
   if (all) {
     HIPCHK(hipMemsetAsync(b->d_err_side, 0, sizeof(uint32_t) * b->nm, b->s));
     // the binning counts of the dropped rebuild are cleared (the remap would have)
@@ -1687,17 +1702,21 @@ static int sweep_impl(kgdb_batch* b, int64_t n_attempts, kgdb_db_stats* stats, i
     HIPCHK(hipMemcpyAsync(log_n, d_logn, sizeof(int64_t) * b->nm, hipMemcpyDeviceToHost, b->s));
     HIPCHK(hipFreeAsync(d_logn, b->s));
   }
-  std::vector<kgdb_db_stats> st(b->nm);
-  HIPCHK(hipMemcpyAsync(st.data(), b->d_stats, sizeof(kgdb_db_stats) * b->nm, hipMemcpyDeviceToHost, b->s));
+  // the statistics and the side rebuild's error words into pinned memory: check_errors' wait
+  // covers them
+  HIPCHK(hipMemcpyAsync(b->h_stats, b->d_stats, sizeof(kgdb_db_stats) * b->nm, hipMemcpyDeviceToHost, b->s));
+  if (b->remap_pending)
+    HIPCHK(hipMemcpyAsync(b->h_err_side, b->d_err_side, sizeof(uint32_t) * b->nm, hipMemcpyDeviceToHost, b->s));
   const int rc = check_errors(b);
   if (b->remap_pending) CHK(finish_side_rebuild(b));
   for (int k = 0; k < b->nm; ++k) {
     b->sweep[k]++;
     b->last_sweep[k] = b->step[k];
   }
-  HIPCHK(hipMemcpy(b->d_sweep, b->sweep.data(), sizeof(uint64_t) * b->nm, hipMemcpyHostToDevice));
+  launch_advance(b->d_sweep, b->nm, 1, b->s);  // the device's sweep counters follow the host's
+  HIPCHK(hipGetLastError());
   b->fc_valid = false;
-  if (stats) std::memcpy(stats, st.data(), sizeof(kgdb_db_stats) * b->nm);
+  if (stats) std::memcpy(stats, b->h_stats, sizeof(kgdb_db_stats) * b->nm);
   return rc;
 }
 

@@ -419,6 +419,25 @@ __global__ void k_fill_i32(int* p, int n, int v) {
   if (i < n) p[i] = v;
 }
 
+// several device-to-device copies in one launch (the state saved at the start of a pass and
+// restored on a rollback), grid-stride; a job whose addresses and size are multiples of 16
+// bytes moves 16-byte words, any other 4-byte words (every buffer here is a whole number of them)
+__global__ void k_copy_jobs(CopyJobs c) {
+  const size_t tid = (size_t)blockIdx.x * blockDim.x + threadIdx.x, nt = (size_t)gridDim.x * blockDim.x;
+  for (int q = 0; q < c.n; ++q) {
+    const size_t bytes = c.bytes[q];
+    if ((((uintptr_t)c.src[q] | (uintptr_t)c.dst[q] | bytes) & 15) == 0) {
+      const uint4* __restrict__ s = (const uint4*)c.src[q];
+      uint4* __restrict__ d = (uint4*)c.dst[q];
+      for (size_t i = tid; i < bytes / 16; i += nt) d[i] = s[i];
+    } else {
+      const uint32_t* __restrict__ s = (const uint32_t*)c.src[q];
+      uint32_t* __restrict__ d = (uint32_t*)c.dst[q];
+      for (size_t i = tid; i < bytes / 4; i += nt) d[i] = s[i];
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------------------
 // host launchers
 // ---------------------------------------------------------------------------------------
@@ -476,6 +495,14 @@ void launch_advance(uint64_t* step_base, int nm, uint64_t n, hipStream_t s) {
 
 void launch_fill_i32(int* p, int n, int v, hipStream_t s) {
   if (n > 0) hipLaunchKernelGGL(k_fill_i32, dim3((n + 255) / 256), dim3(256), 0, s, p, n, v);
+}
+
+void launch_copy_jobs(const CopyJobs& c, hipStream_t s) {
+  size_t most = 0;
+  for (int q = 0; q < c.n; ++q) most = c.bytes[q] > most ? c.bytes[q] : most;
+  const size_t blocks = (most / 16 + 255) / 256;
+  if (c.n > 0 && most > 0)
+    hipLaunchKernelGGL(k_copy_jobs, dim3((unsigned)(blocks < 2048 ? (blocks > 0 ? blocks : 1) : 2048)), dim3(256), 0, s, c);
 }
 
 size_t spos_bytes(int prec) { return prec ? sizeof(SPos<float>) : sizeof(SPos<double>); }
