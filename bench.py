@@ -779,6 +779,7 @@ def cpu_baseline(md_steps=15, db_attempts=8, stream=None):
            "sample": f"200k-monomer workload melt: {md_steps} MD steps ({t_step:.3f} s each) and "
                      f"{db_attempts} DB attempts ({t_att:.3f} s each), scaled to one bench step of "
                      f"{MD_PER_STEP} MD steps + {K} attempts; single-threaded FP64 C oracle"}
+    out["all_cores"] = cpu_baseline_all_cores(md_steps, db_attempts)
     out["gpu_error_vs_oracle"] = oracle_errors(m, stream)
     # the small workload (20 chains x 50 beads) in full on both sides
     import torch
@@ -793,6 +794,40 @@ def cpu_baseline(md_steps=15, db_attempts=8, stream=None):
                                               "2000 MD steps, 20 sweeps of 1 attempt",
                                   "oracle_s": round(t_or, 3), "gpu_fp64_s": round(t_gpu, 4)}
     return out
+
+
+def cpu_baseline_all_cores(md_steps, db_attempts, max_threads=16):
+    """The same oracle sample on every host core at once: one independent workload melt per
+    thread (seeds 1, 2, ...), each stepped by its own thread (the oracle's C calls release the
+    interpreter lock, and its melts share no state).  The aggregate is the sum of the melts'
+    rates over the slowest thread's time: the oracle's throughput for a batch of melts."""
+    from concurrent.futures import ThreadPoolExecutor
+    import threading
+    from oracle import oracle as o
+    P = max(1, min(os.cpu_count() or 1, max_threads))
+    start = threading.Barrier(P)
+
+    def one(i):
+        m = o.Melt(**dict(WORKLOAD, warmup_steps=60, seed=1 + i))  # untimed setup
+        start.wait(timeout=600)
+        t0 = time.perf_counter()
+        m.md_steps(md_steps)
+        t1 = time.perf_counter()
+        m.db_sweep(db_attempts)
+        t2 = time.perf_counter()
+        return t1 - t0, t2 - t1
+
+    with ThreadPoolExecutor(max_workers=P) as ex:
+        times = list(ex.map(one, range(P)))
+    t_step = max(t[0] for t in times) / md_steps
+    t_att = max(t[1] for t in times) / db_attempts
+    nm = WORKLOAD["M"] * WORKLOAD["N"]
+    K = round(1e-3 * nm * MD_PER_STEP * WORKLOAD["dt"])
+    chunk = MD_PER_STEP * t_step + K * t_att
+    return {"value": P * nm * MD_PER_STEP / chunk, "unit": "monomer-timesteps/s", "cores": P,
+            "sample": f"{P} workload melts (seeds 1-{P}), one per thread at once: {md_steps} MD steps "
+                      f"(slowest {t_step:.3f} s each) and {db_attempts} DB attempts (slowest {t_att:.3f} s "
+                      f"each), scaled to one bench step per melt"}
 
 
 SMALL_WORKLOAD = dict(M=20, N=50, kappa=1.5, n_exp=2.0, seed=1)  # 1000 monomers, L = 10.56 sigma
