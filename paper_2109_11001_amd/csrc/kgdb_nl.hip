@@ -605,6 +605,25 @@ __global__ __launch_bounds__(256) void k_nl_remap(NlArgs a) {
 
 template <typename R> struct W3 { R x, y, z; };
 
+// The step kernel's LDS stage: a fixed-point int4 per member in the mixed path; in the FP64
+// path three arrays of coordinates (24 bytes per member where the relative-position record takes
+// 32: three workgroups of the workload's tiles then fit a CU's LDS instead of two)
+template <typename R> struct StageLds;
+template <> struct StageLds<float> {
+  int4* p;
+  __device__ StageLds(unsigned char* base, int) : p((int4*)base) {}
+  __device__ void put(int u, const int4& v) { p[u] = v; }
+  __device__ int4 get(int u) const { return p[u]; }
+  __host__ __device__ static size_t bytes(int cap) { return (size_t)(cap + 4) * sizeof(int4); }
+};
+template <> struct StageLds<double> {
+  double *x, *y, *z;
+  __device__ StageLds(unsigned char* base, int cap) : x((double*)base), y(x + cap + 4), z(y + cap + 4) {}
+  __device__ void put(int u, const Rel<double>::T& v) { x[u] = v.x; y[u] = v.y; z[u] = v.z; }
+  __device__ Rel<double>::T get(int u) const { return Rel<double>::T{x[u], y[u], z[u], 0.0}; }
+  __host__ __device__ static size_t bytes(int cap) { return (size_t)(cap + 4) * 3 * sizeof(double); }
+};
+
 // fast FP32 reciprocal and square root (about 1 ulp); exact IEEE forms in FP64
 __device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ double frcp(double x) { return 1.0 / x; }
@@ -620,7 +639,7 @@ template <typename R, int MODE, int NH>
 __global__ __launch_bounds__(NLB_THREADS) void k_nl_step(NlArgs a) {
   using P = typename Rel<R>::T;
   extern __shared__ __align__(16) unsigned char s_dyn[];
-  P* s_pos = (P*)s_dyn;
+  StageLds<R> s_pos(s_dyn, a.stage_cap);
   __shared__ int s_off[NLB_CELLS + 1];
   __shared__ int s_start[NLB_CELLS];
   const int lb = xcd_remap(blockIdx.x, gridDim.x);
@@ -742,7 +761,7 @@ __global__ __launch_bounds__(NLB_THREADS) void k_nl_step(NlArgs a) {
       yy -= yy >= nc ? nc : 0;
       zz += zz < 0 ? nc : 0;
       zz -= zz >= nc ? nc : 0;
-      s_pos[u] = rel_shift<R>(p, i - 1, yy - 1, zz - 1, hl);
+      s_pos.put(u, rel_shift<R>(p, i - 1, yy - 1, zz - 1, hl));
     }
   } else {
     for (int t = threadIdx.x; t < ncell; t += NLB_THREADS) {
@@ -765,7 +784,7 @@ __global__ __launch_bounds__(NLB_THREADS) void k_nl_step(NlArgs a) {
         const int zz = row / WY, yy = row - zz * WY;
         const int slot = s_start[q] + (u - s_off[q]);
         if (record) slist[u] = slot;
-        s_pos[u] = rel_shift<R>(rel[slot], i - 1, yy - 1, zz - 1, hl);
+        s_pos.put(u, rel_shift<R>(rel[slot], i - 1, yy - 1, zz - 1, hl));
       }
     }
     if (a.stage_write && threadIdx.x == 0) a.stage_meta[tile] = make_int4(h0, nhome, total, 0);
@@ -783,7 +802,9 @@ __global__ __launch_bounds__(NLB_THREADS) void k_nl_step(NlArgs a) {
 
   for (int h = threadIdx.x; h < nhome; h += NLB_THREADS) {
     const int g = h0 + h;
-    const Home hm = h == (int)threadIdx.x ? pre : load_home(g);
+    // (a lane's next home, in a tile of more than 256, is loaded at the end of this one: one
+    // home's data live at a time)
+    const Home hm = pre;
     const P ri = hm.ri;
     const int n = hm.n;
     const int4 nb = hm.nb;
@@ -794,7 +815,9 @@ __global__ __launch_bounds__(NLB_THREADS) void k_nl_step(NlArgs a) {
     const int ix = pc & 1023, iy = (pc >> 10) & 1023, iz = pc >> 20;
     // chain neighbours p-2, p-1, p+1, p+2 (slots, or -1)
     const int nbq[4] = {nb.x, nb.y, nb.z, nb.w};
+    // (the FP64 record's packed cell is taken as an int where the partner is loaded)
     P rb[4];
+    int rbc[4];
     uint32_t nbmask = 0;  // bit q: partner q exists (and forces are on)
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
@@ -802,6 +825,7 @@ __global__ __launch_bounds__(NLB_THREADS) void k_nl_step(NlArgs a) {
       const bool on = forces_on && nbq[q] >= 0 && nbq[q] < NP;
       nbmask |= on ? 1u << q : 0u;
       rb[q] = rel[on ? nbq[q] : g];
+      rbc[q] = Rel<R>::cell(rb[q]);
     }
 
     const double z0 = hm.z0, z1 = hm.z1, z2 = hm.z2;
@@ -842,7 +866,7 @@ __global__ __launch_bounds__(NLB_THREADS) void k_nl_step(NlArgs a) {
           // (an index past the stage can only come from a list left by a failed rebuild,
           // whose run is redone: it is kept inside the stage)
           const int e = min((int)((e2[q >> 1] >> ((q & 1) * 16)) & 0xffffu), total - 1);
-          const P p = staged ? s_pos[e] : member(e);
+          const P p = staged ? s_pos.get(e) : member(e);
           R dx, dy, dz;
           Rel<R>::diff(p, me, dx, dy, dz);
           pair_add_nb(dx, dy, dz);
@@ -864,7 +888,7 @@ __global__ __launch_bounds__(NLB_THREADS) void k_nl_step(NlArgs a) {
       const int sl = q < 2 ? q : q + 1;
       if (!((nbmask >> q) & 1u)) continue;
       has[sl] = true;
-      const int pj = Rel<R>::cell(rb[q]);
+      const int pj = rbc[q];
       int dx = (pj & 1023) - ix, dy = ((pj >> 10) & 1023) - iy, dz = (pj >> 20) - iz;
       // nearest periodic image of the cell difference
       dx -= nc * (dx > nc / 2) - nc * (dx < -(nc - 1) / 2);
@@ -961,6 +985,7 @@ __global__ __launch_bounds__(NLB_THREADS) void k_nl_step(NlArgs a) {
       rx -= L * rint(rx * invL); ry -= L * rint(ry * invL); rz -= L * rint(rz * invL);
       ((P*)a.rel_next)[g] = Rel<R>::make(rx, ry, rz, pc, hl);
     }
+    if (h + NLB_THREADS < nhome) pre = load_home(g + NLB_THREADS);
   }
   // the step before a rebuild bins the new positions into the list grid, in a loop of its own that
   // reads back what the lane has just written (outside the force loop, whose registers it would
@@ -1014,7 +1039,7 @@ void launch_nl_remap(const NlArgs& a, int pblk, hipStream_t s) {
 
 template <typename R, int M>
 static void launch_step_nh(const NlArgs& a, int ntile, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
-  const size_t lds = (size_t)(a.stage_cap + 4) * sizeof(typename Rel<R>::T);
+  const size_t lds = StageLds<R>::bytes(a.stage_cap);
   // with events: hipExtLaunchKernelGGL stamps them at the dispatch's own start and end
   auto go = [&](auto kern) {
     if (ev0) hipExtLaunchKernelGGL(kern, dim3(ntile), dim3(NLB_THREADS), lds, s, ev0, ev1, 0, a);
