@@ -108,6 +108,13 @@ template <> struct Rel<double> {
     dz -= L * rint(dz * iL);
   }
 };
+// a staged position no home monomer's cutoff reaches: 2^30 units (64 cell edges) above the
+// frame's z planes in the mixed path, 10^6 sigma in FP64 (every home lies within a cell of z = 0)
+template <typename R>
+__device__ __forceinline__ typename Rel<R>::T stage_sentinel() {
+  if constexpr (sizeof(R) == 4) return make_int4(0, 0, 1 << 30, 0);
+  else return typename Rel<double>::T{0.0, 0.0, 1.0e6, 0.0};
+}
 template <typename R>
 __device__ __forceinline__ typename Rel<R>::T rel_shift(const typename Rel<R>::T& p, int ox, int oy, int oz, double hl) {
   if constexpr (sizeof(R) == 4) {
@@ -311,10 +318,12 @@ __device__ __forceinline__ int member_slot(const NlArgs& a, int sc, int n, int r
 // row, or a side cell of it, whose nearest point is beyond r_list plus a margin (far above the
 // rounding of frame coordinates) holds no member within r_list and is skipped.  at(t) gives
 // staged member t.  Each entry is stored as it is found (16 bits; entry j of slot g lies in
-// word nl_word(g, j / 8) at place j % 8), so that taking a candidate costs no branch.
+// word nl_word(g, j / 8) at place j % 8), so that taking a candidate costs no branch.  The last
+// word is filled up with `pad`, the index one past the stage, where the step keeps a position
+// outside every cutoff: the step reads whole words without testing the list's end.
 template <typename R, typename At>
 __device__ __forceinline__ int nl_list_one(const NlArgs& a, int g, const Staged<R>& me, int tme, int ih, int yy,
-                                           int W, int WY, R hl, R rl2, R rskip2, const int* s_off, At at) {
+                                           int W, int WY, R hl, R rl2, R rskip2, const int* s_off, int pad, At at) {
   uint16_t* __restrict__ out = (uint16_t*)a.nlist + nl_word(g, 0) * 8;
   int cnt = 0;
   const R cx0 = (R)(ih - 1) * hl, cy0 = (R)(yy - 1) * hl;
@@ -349,6 +358,7 @@ __device__ __forceinline__ int nl_list_one(const NlArgs& a, int g, const Staged<
       }
     }
   }
+  for (int c = cnt; c < NL_CAP && (c & 7); ++c) out[(c >> 3) * 512 + (c & 7)] = (uint16_t)pad;
   return cnt;
 }
 
@@ -536,9 +546,9 @@ __global__ __launch_bounds__(NLB_THREADS) void k_nl_rebuild(NlArgs a) {
     const int mo = a.mono[old];
     int n;
     if (staged)
-      n = nl_list_one(a, g, me, si, lx + 1, ly + 1, W, WY, hlr, rl2, rskip2, s_off, [&](int u) { return s_pos[u]; });
+      n = nl_list_one(a, g, me, si, lx + 1, ly + 1, W, WY, hlr, rl2, rskip2, s_off, total, [&](int u) { return s_pos[u]; });
     else
-      n = nl_list_one(a, g, me, si, lx + 1, ly + 1, W, WY, hlr, rl2, rskip2, s_off, [&](int u) {
+      n = nl_list_one(a, g, me, si, lx + 1, ly + 1, W, WY, hlr, rl2, rskip2, s_off, total, [&](int u) {
         const int q = find_cell(s_off, 0, ncell, u);
         return make(q, member_slot(a, s_sc[q], s_off[q + 1] - s_off[q], u - s_off[q]));
       });
@@ -789,6 +799,8 @@ __global__ __launch_bounds__(NLB_THREADS) void k_nl_step(NlArgs a) {
     }
     if (a.stage_write && threadIdx.x == 0) a.stage_meta[tile] = make_int4(h0, nhome, total, 0);
   }
+  // one place past the stage: the position that the padding of a list's last word reads
+  if (staged && threadIdx.x == 0) s_pos.put(total, stage_sentinel<R>());
   __syncthreads();
 
   const bool forces_on = !(d.test_flags & TF_NOFORCE);
@@ -856,20 +868,42 @@ __global__ __launch_bounds__(NLB_THREADS) void k_nl_step(NlArgs a) {
     };
     // own position in the tile frame (the reference cell is a home cell of this tile)
     const P me = rel_shift<R>(ri, ix - tg.x0, iy - tg.y0, 0, hl);
-    for (int t = 0; t < n; t += 8) {
-      const uint4 cw = wd;
-      if (t + 8 < n) wd = words[nl_word(g, (t >> 3) + 1)];
-      const uint32_t e2[4] = {cw.x, cw.y, cw.z, cw.w};
+    // (mixed path, integer n / 2: the FP64 and general-exponent variants would need more
+    // registers than fit four wavefronts per SIMD, and keep the guarded loop)
+    constexpr bool whole_words = sizeof(R) == 4 && NH > 0;
+    if (whole_words && staged) {
+      // whole words without a branch: the rebuild fills a list's last word up with the
+      // sentinel's index, so that the LDS reads of a word can be issued together
+      for (int t = 0; t < n; t += 8) {
+        const uint4 cw = wd;
+        if (t + 8 < n) wd = words[nl_word(g, (t >> 3) + 1)];
+        const uint32_t e2[4] = {cw.x, cw.y, cw.z, cw.w};
 #pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        if (t + q < n) {
-          // (an index past the stage can only come from a list left by a failed rebuild,
-          // whose run is redone: it is kept inside the stage)
-          const int e = min((int)((e2[q >> 1] >> ((q & 1) * 16)) & 0xffffu), total - 1);
-          const P p = staged ? s_pos.get(e) : member(e);
+        for (int q = 0; q < 8; ++q) {
+          // (an index past the stage can only come from a list left by a failed rebuild, whose
+          // run is redone: it reads the sentinel)
+          const P p = s_pos.get(min((int)((e2[q >> 1] >> ((q & 1) * 16)) & 0xffffu), total));
           R dx, dy, dz;
           Rel<R>::diff(p, me, dx, dy, dz);
           pair_add_nb(dx, dy, dz);
+        }
+      }
+    } else {
+      for (int t = 0; t < n; t += 8) {
+        const uint4 cw = wd;
+        if (t + 8 < n) wd = words[nl_word(g, (t >> 3) + 1)];
+        const uint32_t e2[4] = {cw.x, cw.y, cw.z, cw.w};
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          if (t + q < n) {
+            // (an index past the stage can only come from a list left by a failed rebuild,
+            // whose run is redone: it is kept inside the stage)
+            const int e = min((int)((e2[q >> 1] >> ((q & 1) * 16)) & 0xffffu), total - 1);
+            const P p = staged ? s_pos.get(e) : member(e);
+            R dx, dy, dz;
+            Rel<R>::diff(p, me, dx, dy, dz);
+            pair_add_nb(dx, dy, dz);
+          }
         }
       }
     }
