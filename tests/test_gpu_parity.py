@@ -499,6 +499,24 @@ def test_tile_shape_leaves_the_trajectory_unchanged(prec):
         ref.set_tiles(1000, 1)
 
 
+def test_tiles_of_more_homes_than_lanes():
+    # 8 x 8-cell tiles hold about 310 home monomers: a lane steps a second home, loaded after its
+    # first one is done; the trajectory is that of the default tiles, bit for bit (mixed path; the
+    # FP64 stage's capacity admits no tile shape of more than 256 homes at this density)
+    kw = dict(M=100, N=200, seed=9, kappa=1.5, warmup_steps=200, nl_every=5, precision=1)
+    ref = kg.Melt(**kw)
+    big = kg.Melt(**kw)
+    big.set_tiles(8, 8)
+    assert big.nl_stats()["tile_shape"] == (8, 8)
+    for m in (ref, big):
+        m.md_steps(120)
+        m.db_sweep(40)
+        m.md_steps(35)
+    s0, s1 = ref.get_state(), big.get_state()
+    for f in ("x", "v", "fl", "fc", "chains"):
+        assert np.array_equal(s0[f], s1[f]), f
+
+
 def test_lists_built_beside_the_sweep():
     # after a sweep the next run of steps starts from lists rebuilt beside the sweep (second
     # stream); with profiling on they are rebuilt at the start of the run instead.  The lists
