@@ -328,39 +328,53 @@ def _steps_to_within(times, samples, ref, tol):
     return (None if first >= len(t) else first), dev
 
 
-def run_equilibration(kg, stream, steps, ref_steps, every=1000, tol=0.02, batch_melts=4):
-    """Time to equilibrium of R^2(n)/n for each form, from one shared warmed-up start.
+EQ_FORMS = ("fp64", "mixed", "batched", "learned", "mixed_fr")
+# the default line's time-to-equilibrium check: one seed, shorter runs than the study above
+EQ_CHECK = dict(steps=200_000, ref_steps=500_000, forms=("fp64", "mixed", "learned"))
 
-    The reference is the plain FP64 path with the uniform proposal, its R^2(n)/n averaged over
-    the second half of a run of `ref_steps` steps.  Each form (plain FP64, mixed precision, a
-    batch of `batch_melts` melts with their own random streams, the learned proposal) then runs
-    `steps` steps from the start, one sweep at the paper's rate every 100 steps, R^2(n)/n read
-    every `every` steps; a form has equilibrated once the mean over the second half of its run
-    so far stays within `tol` of the reference for every n (the reference run itself counts as
-    the FP64 form).  Wall-clock times include the sweeps and the readings.  One more form,
+
+def run_equilibration(kg, stream, steps, ref_steps, every=1000, tol=0.02, batch_melts=4, seeds=(1,),
+                      forms=EQ_FORMS, ref_seed=101):
+    """Time to equilibrium of R^2(n)/n for each form, from warmed-up starts of several seeds.
+
+    The reference is the plain FP64 path with the uniform proposal, started from a random-walk
+    start of its own (seed `ref_seed`, so its start and random stream are shared with no form),
+    its R^2(n)/n averaged over the second half of a run of `ref_steps` steps.  For every seed,
+    each form (plain FP64, mixed precision, a batch of `batch_melts` melts with their own random
+    streams, the learned proposal) runs `steps` steps from that seed's warmed-up start, one sweep
+    at the paper's rate every 100 steps, R^2(n)/n read every `every` steps; a form has
+    equilibrated once the mean over the second half of its run so far stays within `tol` of the
+    reference for every n.  Wall-clock times include the sweeps and the readings.  One more form,
     mixed precision from freely rotating chains (Sec. II.B) instead of the shared random-walk
-    start, measures what the better initial state saves."""
+    start, measures what the better initial state saves.  The learned proposal's network is
+    trained on uniform sweeps logged from a copy of the reference's start."""
     import numpy as np
     import torch
-    base = dict(WORKLOAD, **EQ_SYSTEM)
-    g = kg.Batch([dict(base, precision=kg.PREC_FP64)], stream=stream)
-    S0 = g.get_state()
-    g.close()
 
-    def start(form):
+    def base_of(seed):
+        return dict(WORKLOAD, **EQ_SYSTEM, seed=seed)
+
+    def warm_start(seed):
+        g = kg.Batch([dict(base_of(seed), precision=kg.PREC_FP64)], stream=stream)
+        S = g.get_state()
+        g.close()
+        return S
+
+    def start(form, seed, S0):
         melts = batch_melts if form == "batched" else 1
         prec = kg.PREC_FP64 if form == "fp64" else kg.PREC_MIXED
         prop = kg.PROPOSAL_LEARNED if form == "learned" else kg.PROPOSAL_UNIFORM
         if form == "mixed_fr":  # its own start: freely rotating chains (Sec. II.B), then the warm-up
-            return kg.Batch([dict(base, precision=prec, init_mode=kg.INIT_FREELY_ROTATING)], stream=stream), 1
-        b = kg.Batch([dict(base, warmup_steps=0, precision=prec, proposal=prop, melt_id=i) for i in range(melts)],
-                     stream=stream)
+            return kg.Batch([dict(base_of(seed), precision=prec, init_mode=kg.INIT_FREELY_ROTATING)],
+                            stream=stream), 1
+        b = kg.Batch([dict(base_of(seed), warmup_steps=0, precision=prec, proposal=prop, melt_id=i)
+                      for i in range(melts)], stream=stream)
         for i in range(melts):
             b.set_state(i, x=S0["x"], v=S0["v"], fl=S0["fl"], chains=S0["chains"], counters=S0["counters"])
         return b, melts
 
-    def run(form, nsteps, net=None):
-        b, melts = start(form)
+    def run(form, seed, S0, nsteps, net=None):
+        b, melts = start(form, seed, S0)
         if net is not None:
             b.set_proposal_net(net, 0.1)
         b.autotune(0, reps=20)
@@ -382,40 +396,56 @@ def run_equilibration(kg, stream, steps, ref_steps, every=1000, tol=0.02, batch_
         floored = sum(b.fene_floored(i) for i in range(melts))
         bond_steps = sum(b.counters(i)[0] for i in range(melts)) * EQ_SYSTEM["M"] * (EQ_SYSTEM["N"] - 1)
         b.close()
+        print(f"[bench] equilibration: {form}, seed {seed}, {nsteps} steps in {walls[-1]:.1f} s",
+              file=sys.stderr, flush=True)
         return dict(times=times, walls=walls, samples=samples, accepted=acc, attempts=att, melts=melts,
                     floored=floored / max(bond_steps, 1))
 
     out = {"system": f"{EQ_SYSTEM['M']} chains x {EQ_SYSTEM['N']} beads, kappa {EQ_SYSTEM['kappa']}, n 2, "
                      "rho 0.85, dt 0.01, gamma 1", "tolerance": tol, "reading_every_steps": every,
-           "forms": {}}
-    runs = {"fp64": run("fp64", ref_steps)}
-    r = runs["fp64"]
+           "seeds": list(seeds), "forms": {}}
+    S_ref = warm_start(ref_seed)
+    r = run("fp64", ref_seed, S_ref, ref_steps)
     half = np.asarray(r["times"]) > ref_steps / 2
     ref = np.asarray(r["samples"])[half].mean(0)
-    out["reference"] = {"steps": ref_steps, "r2n_first": float(ref[0]), "r2n_last": float(ref[-1]),
-                        "r2n_max": float(ref.max())}
-    # learned proposal: a network trained on logged uniform sweeps of a copy of the start
-    b, _ = start("fp64")
-    t0 = time.perf_counter()
-    tr, first, last, y = train_proposal(kg, b, stream, 10, 2000, 300)
-    out["learned_training"] = {"records": int(len(y)), "loss_first": first, "loss_last": last,
-                               "setup_s": round(time.perf_counter() - t0, 2)}
-    b.close()
-    runs["mixed"] = run("mixed", steps)
-    runs["batched"] = run("batched", steps)
-    runs["learned"] = run("learned", steps, net=tr.params)
-    runs["mixed_fr"] = run("mixed_fr", steps)
-    for form, r in runs.items():
-        k, dev = _steps_to_within(r["times"], r["samples"], ref, tol)
+    out["reference"] = {"seed": ref_seed, "steps": ref_steps, "r2n_first": float(ref[0]),
+                        "r2n_last": float(ref[-1]), "r2n_max": float(ref.max()),
+                        "wall_s": round(r["walls"][-1], 3)}
+    net = None
+    if "learned" in forms:  # a network trained on logged uniform sweeps of a copy of the reference's start
+        b, _ = start("fp64", ref_seed, S_ref)
+        t0 = time.perf_counter()
+        tr, first, last, y = train_proposal(kg, b, stream, 10, 2000, 300)
+        out["learned_training"] = {"records": int(len(y)), "loss_first": first, "loss_last": last,
+                                   "setup_s": round(time.perf_counter() - t0, 2)}
+        b.close()
+        net = tr.params
+    per = {f: [] for f in forms}
+    for seed in seeds:
+        S0 = warm_start(seed)
+        for form in forms:
+            r = run(form, seed, S0, steps, net=net if form == "learned" else None)
+            k, dev = _steps_to_within(r["times"], r["samples"], ref, tol)
+            per[form].append({
+                "seed": seed, "melts": r["melts"], "steps": r["times"][-1], "wall_s": round(r["walls"][-1], 3),
+                "us_per_md_step": round(1e6 * r["walls"][-1] / r["times"][-1], 2),
+                "steps_to_tol": r["times"][k] if k is not None else None,
+                "tau_to_tol": r["times"][k] * WORKLOAD["dt"] if k is not None else None,
+                "wall_s_to_tol": round(r["walls"][k], 3) if k is not None else None,
+                "max_dev_end": round(dev[-1], 5), "max_dev_start": round(dev[0], 4),
+                "accepted": r["accepted"], "accept_rate": r["accepted"] / max(r["attempts"], 1),
+                "fene_floored_per_bond_step": r["floored"]})
+    for form, rs in per.items():
+        reached = [x for x in rs if x["steps_to_tol"] is not None]
+        mean = lambda key, xs: (float(np.mean([x[key] for x in xs])) if xs else None)
         out["forms"][form] = {
-            "melts": r["melts"], "steps": r["times"][-1], "wall_s": round(r["walls"][-1], 3),
-            "us_per_md_step": round(1e6 * r["walls"][-1] / r["times"][-1], 2),
-            "steps_to_tol": r["times"][k] if k is not None else None,
-            "tau_to_tol": r["times"][k] * WORKLOAD["dt"] if k is not None else None,
-            "wall_s_to_tol": round(r["walls"][k], 3) if k is not None else None,
-            "max_dev_end": round(dev[-1], 5), "max_dev_start": round(dev[0], 4),
-            "accepted": r["accepted"], "accept_rate": r["accepted"] / max(r["attempts"], 1),
-            "fene_floored_per_bond_step": r["floored"]}
+            "reached": f"{len(reached)} of {len(rs)}",
+            "steps_to_tol_mean": mean("steps_to_tol", reached),
+            "wall_s_to_tol_mean": mean("wall_s_to_tol", reached),
+            "us_per_md_step_mean": mean("us_per_md_step", rs),
+            "accept_rate_mean": mean("accept_rate", rs),
+            "max_dev_end_max": max(x["max_dev_end"] for x in rs),
+            "per_seed": rs}
     return out
 
 
@@ -896,7 +926,11 @@ def main():
     ap.add_argument("--no-config2", action="store_true",
                     help="skip the stiff-system run (100 x 2000, kappa 3, every n of Eq. 11)")
     ap.add_argument("--no-checks", action="store_true",
-                    help="skip the workload's energy drift and FP64/mixed decision match")
+                    help="skip the workload's energy drift, FP64/mixed decision match and the "
+                         "time-to-equilibrium check")
+    ap.add_argument("--no-equilibration-check", action="store_true",
+                    help="skip the short time-to-equilibrium check (2000 x 25 melt; FP64, mixed and "
+                         "learned forms against an FP64 reference run)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run plain copies of known size (for PMC byte counters)")
     ap.add_argument("--size-sweep", default="",
@@ -917,7 +951,14 @@ def main():
                     help="time to equilibrium of R^2(n)/n for each form on a 2000 x 25 melt, STEPS steps each")
     ap.add_argument("--equilibration-ref", type=int, default=0, metavar="STEPS",
                     help="length of the plain FP64 reference run (default: 2 x --equilibration)")
+    ap.add_argument("--equilibration-seeds", default="1", metavar="S1,S2,...",
+                    help="seeds of the warmed-up starts every form runs from (default: 1)")
+    ap.add_argument("--equilibration-forms", default=",".join(EQ_FORMS), metavar="F1,F2,...",
+                    help="forms to time (fp64, mixed, batched, learned, mixed_fr; default: all)")
     args = ap.parse_args()
+    bad = set(v.strip() for v in args.equilibration_forms.split(",") if v.strip()) - set(EQ_FORMS)
+    if bad:
+        sys.exit(f"bench.py: unknown --equilibration-forms {sorted(bad)}; known: {', '.join(EQ_FORMS)}")
     if args.profile_steps < 0:
         args.profile_steps = args.steps
     if args.gpus != 1:
@@ -940,7 +981,9 @@ def main():
     eq = None
     if args.equilibration > 0:
         print(f"[bench] equilibration: {args.equilibration} steps per form", file=sys.stderr, flush=True)
-        eq = run_equilibration(kg, stream, args.equilibration, args.equilibration_ref or 2 * args.equilibration)
+        eq = run_equilibration(kg, stream, args.equilibration, args.equilibration_ref or 2 * args.equilibration,
+                               seeds=[int(v) for v in args.equilibration_seeds.split(",") if v.strip()],
+                               forms=[v.strip() for v in args.equilibration_forms.split(",") if v.strip()])
         print("[bench] equilibration done", file=sys.stderr, flush=True)
     prot = []
     for kap in [float(v) for v in args.protocol_kappa.split(",") if v.strip()] if args.protocol > 0 else []:
@@ -987,6 +1030,15 @@ def main():
         learned = run_learned(kg, args.steps, args.warmup, stream)
         print(f"[bench] learned done: accept rate {learned['learned']['accept_rate']:.3f} vs "
               f"{learned['uniform']['accept_rate']:.3f}", file=sys.stderr, flush=True)
+    eq_check = None
+    if not (args.no_equilibration_check or args.no_checks) and args.equilibration == 0:
+        print(f"[bench] time to equilibrium: {EQ_CHECK['steps']} steps per form, reference "
+              f"{EQ_CHECK['ref_steps']}", file=sys.stderr, flush=True)
+        eq_check = run_equilibration(kg, stream, EQ_CHECK["steps"], EQ_CHECK["ref_steps"], seeds=(1,),
+                                     forms=EQ_CHECK["forms"])
+        print("[bench] time to equilibrium: " + ", ".join(
+            f"{f} {v['steps_to_tol_mean']} steps / {v['wall_s_to_tol_mean']} s" for f, v in eq_check["forms"].items()),
+            file=sys.stderr, flush=True)
     cpu = None
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
@@ -1043,6 +1095,8 @@ def main():
         line["size_sweep"] = sweep
     if eq:
         line["equilibration"] = eq
+    if eq_check:
+        line["equilibration_check"] = eq_check
     if prot:
         line["protocol"] = prot
     if bat:
