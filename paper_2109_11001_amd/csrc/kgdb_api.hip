@@ -668,7 +668,7 @@ static int copy_state(kgdb_batch* b, bool back, double* sx, int* si, uint64_t* s
   for (int q = 0; q < 3; ++q) job(t[q], si + q * np, np * sizeof(int));
   job(b->d_step, sst, b->nm * sizeof(uint64_t));
   job(b->d_floor, sst + b->nm, b->nm * sizeof(uint64_t));  // FENE-floor counters (sst holds 2 nm words)
-  launch_copy_jobs(c, b->s);
+  if (!launch_copy_jobs(c, b->s)) return fail(KGDB_E_STATE, "state copy: a buffer is not 4-byte aligned");
   HIPCHK(hipGetLastError());
   if (back) b->lists_ver = ~0ull;
   return 0;

@@ -64,7 +64,8 @@ void launch_finalize(int prec, const MeltDesc* md, const BlockMap& cm, int NP, c
 void launch_force(int prec, int mode, int lanes, const ForceArgs& a, int nblk, hipStream_t s);
 void launch_advance(uint64_t* step_base, int nm, uint64_t n, hipStream_t s);
 void launch_fill_i32(int* p, int n, int v, hipStream_t s);
-// up to COPY_JOBS_MAX device-to-device copies (sizes in bytes, multiples of 4) in one launch
+// up to COPY_JOBS_MAX device-to-device copies in one launch; each job's addresses and size (in
+// bytes) must be multiples of 4, else nothing is launched and false is returned
 constexpr int COPY_JOBS_MAX = 12;
 struct CopyJobs {
   const void* src[COPY_JOBS_MAX];
@@ -72,7 +73,7 @@ struct CopyJobs {
   size_t bytes[COPY_JOBS_MAX];
   int n;
 };
-void launch_copy_jobs(const CopyJobs& c, hipStream_t s);
+bool launch_copy_jobs(const CopyJobs& c, hipStream_t s);
 size_t spos_bytes(int prec);
 
 // ---- neighbour-list MD step (kgdb_nl.hip)

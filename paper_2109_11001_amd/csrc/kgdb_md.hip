@@ -497,12 +497,18 @@ void launch_fill_i32(int* p, int n, int v, hipStream_t s) {
   if (n > 0) hipLaunchKernelGGL(k_fill_i32, dim3((n + 255) / 256), dim3(256), 0, s, p, n, v);
 }
 
-void launch_copy_jobs(const CopyJobs& c, hipStream_t s) {
+bool launch_copy_jobs(const CopyJobs& c, hipStream_t s) {
+  if (c.n < 0 || c.n > COPY_JOBS_MAX) return false;
   size_t most = 0;
-  for (int q = 0; q < c.n; ++q) most = c.bytes[q] > most ? c.bytes[q] : most;
+  for (int q = 0; q < c.n; ++q) {
+    // the kernel moves whole 4-byte words: a job it cannot copy exactly is refused
+    if ((((uintptr_t)c.src[q] | (uintptr_t)c.dst[q] | c.bytes[q]) & 3) != 0) return false;
+    most = c.bytes[q] > most ? c.bytes[q] : most;
+  }
   const size_t blocks = (most / 16 + 255) / 256;
   if (c.n > 0 && most > 0)
     hipLaunchKernelGGL(k_copy_jobs, dim3((unsigned)(blocks < 2048 ? (blocks > 0 ? blocks : 1) : 2048)), dim3(256), 0, s, c);
+  return true;
 }
 
 size_t spos_bytes(int prec) { return prec ? sizeof(SPos<float>) : sizeof(SPos<double>); }
