@@ -495,11 +495,23 @@ def run_batch(kg, stream, steps, warmup, single_steps=10):
         torch.cuda.synchronize()
         seq += (time.perf_counter() - a0) / single_steps
         g.close()
-    return {"melts": len(melts), "monomers": nm, "rebuild_interval": K, "setup_s": round(setup_s, 2),
+    return {"workload": "24 melts, kappa in {0, 0.5, 1, 1.5, 2, 2.5} x (chains, beads) in {(225, 100), "
+                        "(125, 200), (75, 400), (50, 800)}, rho 0.85, n 2, mixed precision; bench step = 100 MD "
+                        "steps (hipGraph chunks) + one sweep per melt at the attempt rate",
+            "melts": len(melts), "monomers": nm, "rebuild_interval": K, "setup_s": round(setup_s, 2),
             "ms_per_bench_step": round(1e3 * wall / steps, 3), "monomer_steps_per_s": nm * MD_PER_STEP * steps / wall,
             "db_accepted_per_s": acc / wall,
             "one_at_a_time_ms_per_bench_step": round(1e3 * seq, 3),
             "batching_gain": round(seq / (wall / steps), 2)}
+
+
+def batch_form(kg, stream, steps, warmup):
+    """run_batch with progress lines."""
+    print("[bench] batched form: 24 uneven melts in one batch, then one at a time", file=sys.stderr, flush=True)
+    bat = run_batch(kg, stream, steps, warmup)
+    print(f"[bench] batch: {bat['monomer_steps_per_s']:.3e} monomer-steps/s, gain {bat['batching_gain']}",
+          file=sys.stderr, flush=True)
+    return bat
 
 
 def kg_kuhn(kappa):
@@ -940,7 +952,9 @@ def main():
     ap.add_argument("--size-sweep-steps", type=int, default=500)
     ap.add_argument("--no-main", action="store_true", help="skip the workload runs (with --size-sweep or --equilibration)")
     ap.add_argument("--batch", action="store_true",
-                    help="24 uneven melts (kappa 0-2.5, N 100-800, 705k monomers) as one batch vs one at a time")
+                    help="with --no-main: run the batched form (24 uneven melts, kappa 0-2.5, N 100-800, 705k "
+                         "monomers, as one batch vs one at a time); the default line runs it anyway")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched form in the default line")
     ap.add_argument("--protocol", type=int, default=0, metavar="STEPS",
                     help="time every stage of the n-ramp protocol for STEPS steps on the paper's 1000 x 400 "
                          "melt and project the full run")
@@ -992,11 +1006,8 @@ def main():
         print(f"[bench] protocol kappa {kap}: projected {prot[-1]['projected_full_protocol_s']} s for "
               f"{prot[-1]['plan']['steps_total']} steps", file=sys.stderr, flush=True)
     bat = None
-    if args.batch:
-        print("[bench] batch of 24 melts", file=sys.stderr, flush=True)
-        bat = run_batch(kg, stream, args.steps, args.warmup)
-        print(f"[bench] batch: {bat['monomer_steps_per_s']:.3e} monomer-steps/s, gain {bat['batching_gain']}",
-              file=sys.stderr, flush=True)
+    if args.batch and args.no_main:
+        bat = batch_form(kg, stream, args.steps, args.warmup)
     if args.protocol_full is not None:
         print(f"[bench] full protocol run: kappa {args.protocol_full}", file=sys.stderr, flush=True)
         prot.append(run_protocol_bench(kg, stream, args.protocol_full, 0))
@@ -1030,6 +1041,8 @@ def main():
         learned = run_learned(kg, args.steps, args.warmup, stream)
         print(f"[bench] learned done: accept rate {learned['learned']['accept_rate']:.3f} vs "
               f"{learned['uniform']['accept_rate']:.3f}", file=sys.stderr, flush=True)
+    if not args.no_batch:
+        bat = batch_form(kg, stream, args.steps, args.warmup)
     eq_check = None
     if not (args.no_equilibration_check or args.no_checks) and args.equilibration == 0:
         print(f"[bench] time to equilibrium: {EQ_CHECK['steps']} steps per form, reference "
