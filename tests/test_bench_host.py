@@ -52,3 +52,13 @@ def test_wlc_limits():
     assert B.wlc_r2_over_n(1e-4, lk, l0) == pytest.approx(1e-4 * l0 * l0, rel=1e-4)
     assert B.wlc_r2_over_n(1e7, lk, l0) == pytest.approx(l0 * lk, rel=1e-6)
     assert B.XI == (2.0, 3.0, 4.0, 5.0, 5.75, 6.5, 7.0, 8.0, 9.0, 10.0, 11.0, 12.0)
+
+
+def test_batched_form_melts():
+    # 24 melts: six stiffnesses x four chain lengths, M = ceil(20000 / N) (1 + N / 800) chains
+    assert B.BATCH_KAPPAS == (0.0, 0.5, 1.0, 1.5, 2.0, 2.5)
+    assert [N for _, N in B.BATCH_SHAPES] == [100, 200, 400, 800]
+    for M, N in B.BATCH_SHAPES:
+        assert M == int(np.ceil(20000 / N) * (1 + N / 800))
+    total = len(B.BATCH_KAPPAS) * sum(M * N for M, N in B.BATCH_SHAPES)
+    assert total == 705000
