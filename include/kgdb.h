@@ -136,7 +136,11 @@ int kgdb_md_steps(kgdb_batch* b, int64_t nsteps, int32_t use_graph);
    untouched; the chain tables change.  stats[k] receives melt k's statistics (may be NULL).
    A melt holds up to max(3072, 8 M + 1024) candidates (rounded up to a power of two beyond
    3072); lists above 3072 keys are swept from global memory (same decisions), and the learned
-   proposal reports them as a candidate overflow. */
+   proposal reports them as a candidate overflow.  Which of the two holds a melt's list is
+   decided when its sweep starts: an accepted move that would take a list held in LDS past
+   3072 keys or any list past its melt's capacity, or whose two chains hold more than 1024
+   keys, is not made, and the call returns KGDB_E_OVERFLOW after the sweep (the other moves
+   of the sweep stay; the topology is valid). */
 int kgdb_db_sweep(kgdb_batch* b, int64_t n_attempts, kgdb_db_stats* stats);
 
 /* ---- the n-ramp protocol (Sec. II.B) ---- */
