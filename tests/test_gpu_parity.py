@@ -668,6 +668,34 @@ def test_batch_equals_single_melts():
             assert np.array_equal(sb[f], ss[f]), (k, f)
 
 
+def test_batched_form_equals_its_melts_alone():
+    # the 24 uneven melts of the batched form (kappa 0-2.5 x (chains, beads) (225, 100),
+    # (125, 200), (75, 400), (50, 800): 705,000 monomers), mixed precision: each melt of the
+    # batch follows the trajectory and topology it follows alone, bit for bit.  The skin and the
+    # rebuild interval are fixed (the default skin grows with the batch's monomer count, which
+    # would give the batch other list-grid cells than a melt alone).
+    shapes = [(225, 100), (125, 200), (75, 400), (50, 800)]
+    melts = [dict(M=M, N=N, kappa=kap, seed=1, melt_id=i, precision=kg.PREC_MIXED, warmup_steps=1000,
+                  nl_skin=0.85, nl_every=5)
+             for i, (kap, (M, N)) in enumerate((k_, s_) for k_ in (0.0, 0.5, 1.0, 1.5, 2.0, 2.5) for s_ in shapes)]
+    b = kg.Batch(melts)
+    assert b.sizes()[0] == 705000
+    b.md_steps(200)
+    acc = [st["accepted"] for st in b.db_sweep(-1)]
+    b.md_steps(100)
+    rb = b.nl_info()["rollbacks"]
+    for k, m in enumerate(melts):
+        s = kg.Batch([m])
+        s.md_steps(200)
+        assert s.db_sweep(-1)[0]["accepted"] == acc[k], k
+        s.md_steps(100)
+        sb, ss = b.get_state(k), s.get_state()
+        for f in ("x", "v", "fl", "chains"):
+            assert np.array_equal(sb[f], ss[f]), (k, f, rb, s.nl_info()["rollbacks"])
+        s.close()
+    b.close()
+
+
 # ---------------------------------------------------------------------------- errors
 def test_invalid_params():
     with pytest.raises(kg.KgdbError) as e:
