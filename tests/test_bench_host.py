@@ -5,6 +5,7 @@ import pytest
 
 import bench as B
 from oracle import protocol as op
+from tests.paper_values import PAPER
 
 
 def test_steps_to_within_uses_second_half_windows():
@@ -42,8 +43,10 @@ def test_report_kuhn_equals_oracle(kappa):
 def test_success_fits_are_the_papers_laws():
     # Eq. 15 and the Fig. 3 caption's fit at kappa = 3, n = 2
     e15, f3 = B.success_fits(3.0, 2.0)
-    assert e15 == pytest.approx(1.6 * np.exp(-2.31 - 0.70), rel=1e-12)
-    assert f3 == pytest.approx(1.24 * np.exp(-2.31 - 0.48 - 0.06), rel=1e-12)
+    a, b, d = PAPER["eq15_fit"]
+    a_, b_, d_, e_ = PAPER["fig3_fit"]
+    assert e15 == pytest.approx(a * np.exp(-3.0 * b - 2.0 * d), rel=1e-12)
+    assert f3 == pytest.approx(a_ * np.exp(-3.0 * b_ - 2.0 * d_ - 4.0 * e_), rel=1e-12)
 
 
 def test_wlc_limits():
@@ -51,7 +54,7 @@ def test_wlc_limits():
     l0, lk = 0.97, 5.0
     assert B.wlc_r2_over_n(1e-4, lk, l0) == pytest.approx(1e-4 * l0 * l0, rel=1e-4)
     assert B.wlc_r2_over_n(1e7, lk, l0) == pytest.approx(l0 * lk, rel=1e-6)
-    assert B.XI == (2.0, 3.0, 4.0, 5.0, 5.75, 6.5, 7.0, 8.0, 9.0, 10.0, 11.0, 12.0)
+    assert B.XI == PAPER["xi"]
 
 
 def test_batched_form_melts():

@@ -6,8 +6,9 @@ import pytest
 
 from oracle import oracle as o
 from oracle import protocol as op
+from tests.paper_values import value
 
-L0 = 0.960897
+L0 = value("l0")
 
 
 def bonds(m, N):

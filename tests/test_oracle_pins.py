@@ -12,9 +12,11 @@ from scipy import integrate
 
 from oracle import oracle as o
 from tests import inputs
+from tests.paper_values import PAPER, value
 
 RC = 2.0 ** (1.0 / 6.0)
-XI = [2, 3, 4, 5, 5.75, 6.5, 7, 8, 9, 10, 11, 12]  # Eq. (11)
+XI = list(PAPER["xi"])  # Eq. (11)
+L0 = value("l0")
 
 
 # ----------------------------------------------------------------------------- RNG
@@ -152,13 +154,13 @@ def test_soft_pair_is_softer():
 def test_kn_standard_value():
     # Eqs. (7)-(9): k = 30 eps/sigma^2 makes l0 = 0.960897 stationary in the standard
     # model, so Eq. (9) at n = 12 returns 30 up to the 6 printed digits of l0
-    assert o.kn(12) == pytest.approx(30.0, rel=1e-5)
+    assert o.kn(12) == pytest.approx(value("k_standard"), rel=1e-5)
 
 
 @pytest.mark.parametrize("n", XI)
 def test_kn_makes_l0_stationary(n):
     # Eq. (8): d/dr [MLJ^n + FENE(k_n)] = 0 at l0, via finite differences of the energies
-    k, l0, h = o.kn(n), 0.960897, 1e-6
+    k, l0, h = o.kn(n), L0, 1e-6
     U = lambda r: o.pair_u(n, r) + o.fene_u(k, 1.5, r)
     assert abs((U(l0 + h) - U(l0 - h)) / (2 * h)) < 1e-7
     assert o.pair_f(n, l0) + o.fene_f(k, 1.5, l0) == pytest.approx(0.0, abs=1e-10)

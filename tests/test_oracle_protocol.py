@@ -5,6 +5,10 @@ import math
 import pytest
 
 from oracle import protocol as op
+from tests.paper_values import PAPER, value
+
+N_PAPER = int(value("chain_length"))
+DT = value("dt")
 
 KAPPAS = [0.0, 0.5, 1.0, 1.5, 2.0, 2.5, 3.0, 3.5, 4.0, 4.5, 5.0, 5.5]
 
@@ -22,28 +26,36 @@ def test_flory_term_limit_at_zero():
     assert op.flory_term(1e-3) == pytest.approx(1 + 2e-3 / 3, rel=1e-6)
 
 
+def test_plan_constants_are_the_papers():
+    assert op.F0 == value("f0")
+    assert tuple(op.XI) == PAPER["xi"]
+    assert (op.FIT_A, op.FIT_B, op.FIT_D) == PAPER["eq15_fit"]
+
+
 def test_f0_gives_1e8_steps_at_kappa_5p5():
     # the paper fixes f0 so that kappa = 5.5, N = 400 runs take 10^8 steps of dt = tau / 125
-    assert op.tau_fix(5.5, 400) / 0.008 == pytest.approx(1e8, rel=1e-5)
-    assert op.tau_eq(5.5, 400) == op.tau_fix(5.5, 400)
-    assert sum(op.schedule(5.5, 400, 0.008)[1]) == pytest.approx(1e8, rel=1e-5)
+    budget = value("steps_kappa_5p5")
+    assert op.tau_fix(5.5, N_PAPER) / DT == pytest.approx(budget, rel=1e-5)
+    assert op.tau_eq(5.5, N_PAPER) == op.tau_fix(5.5, N_PAPER)
+    assert sum(op.schedule(5.5, N_PAPER, DT)[1]) == pytest.approx(budget, rel=1e-5)
 
 
 @pytest.mark.parametrize("kappa", [0.0, 0.5, 1.0, 1.5, 2.0])
 def test_1e7_steps_for_kappa_below_2p5(kappa):
     # 200 N tau = 80,000 tau for N = 400: 10^7 steps of 0.008 tau (figure of the run times)
-    assert op.tau_eq(kappa, 400) == 80000.0
-    assert abs(sum(op.schedule(kappa, 400, 0.008)[1]) - 10 ** 7) <= 12
+    assert op.tau_eq(kappa, N_PAPER) == 200.0 * N_PAPER
+    assert abs(sum(op.schedule(kappa, N_PAPER, DT)[1]) - value("steps_kappa_le_2p5")) <= 12
 
 
 def test_n2_stage_lengths_of_the_paper():
     # the n = 2 stages of the 2 <= kappa <= 4 runs (read as kappa = 2, 3, 4: at kappa = 2.5 the
     # stage would end at 1.13e4 tau) end between 1.15e4 and 3.56e4 tau
-    t2 = op.stage_times(2.0, 400)[0][0]
-    t4 = op.stage_times(4.0, 400)[0][0]
-    assert abs(t2 - 1.15e4) < 50 and abs(t4 - 3.56e4) < 50
+    lo, hi = PAPER["n2_stage_end_range"]
+    t2 = op.stage_times(2.0, N_PAPER)[0][0]
+    t4 = op.stage_times(4.0, N_PAPER)[0][0]
+    assert abs(t2 - lo) < 50 and abs(t4 - hi) < 50  # (the paper prints three digits)
     for k in (2.0, 3.0, 4.0):
-        assert 1.145e4 <= op.stage_times(k, 400)[0][0] <= 3.565e4
+        assert lo - 50 <= op.stage_times(k, N_PAPER)[0][0] <= hi + 50
 
 
 @pytest.mark.parametrize("kappa", KAPPAS)
